@@ -1,0 +1,307 @@
+"""FP64 CPU oracle of the Granule-In-Cell granule step -- TEST INFRASTRUCTURE.
+
+Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  The product path (the HIP library and its binding) never
+imports it.
+
+Thin ctypes wrapper over oracle.c: numpy arrays in, numpy arrays out.  Each
+wrapper names the passage of the paper its C function follows.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+
+class OrcParams(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32 * 3), ("dx", C.c_double), ("nc", C.c_int32 * 3), ("cell", C.c_double),
+        ("kn", C.c_double), ("restitution", C.c_double), ("kt_ratio", C.c_double), ("mu", C.c_double),
+        ("rho_s", C.c_double), ("eta_f", C.c_double), ("c_drag", C.c_double), ("alpha_max", C.c_double),
+        ("g", C.c_double * 3), ("dt", C.c_double), ("walls", C.c_uint32), ("pad", C.c_int32),
+    ]
+
+
+def params(cfg: dict) -> OrcParams:
+    """Oracle parameter block from a workload parameter dict."""
+    p = OrcParams()
+    p.n = (C.c_int32 * 3)(*cfg["n"])
+    p.dx = cfg["dx"]
+    p.nc = (C.c_int32 * 3)(*cfg["nc"])
+    p.cell = cfg["cell"]
+    for k in ("kn", "restitution", "kt_ratio", "mu", "rho_s", "eta_f", "c_drag", "alpha_max", "dt"):
+        setattr(p, k, float(cfg[k]))
+    p.g = (C.c_double * 3)(*cfg["g"])
+    p.walls = int(cfg["walls"])
+    return p
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(_HERE, "liboracle.so")
+        if not os.path.exists(path):
+            _build.build()
+        _LIB = C.CDLL(path)
+        _declare(_LIB)
+    return _LIB
+
+
+_P = C.POINTER
+_d = _P(C.c_double)
+_i64 = _P(C.c_int64)
+_i32 = _P(C.c_int32)
+_u32 = _P(C.c_uint32)
+_pp = _P(OrcParams)
+
+
+def _declare(L):
+    sig = {
+        "orc_key_space": (C.c_int64, [_pp]),
+        "orc_cell_keys": (None, [_pp, C.c_int64, _d, _u32]),
+        "orc_stable_sort": (None, [C.c_int64, _u32, _i32]),
+        "orc_cell_ranges": (None, [_pp, C.c_int64, _u32, _i32, _i32, _i32]),
+        "orc_pairs_brute": (C.c_int64, [C.c_int64, _d, _d, C.c_int64, _i32, _i32]),
+        "orc_pairs_cells": (C.c_int64, [_pp, C.c_int64, _d, _d, C.c_int64, _i32, _i32]),
+        "orc_contact_forces": (None, [_pp, C.c_int64, _d, _d, _d, _d, _d, _i32, _i32]),
+        "orc_contact_forces_sample": (None, [_pp, C.c_int64, _d, _d, _d, C.c_int64, _i64, _d, _d]),
+        "orc_pair": (C.c_int, [_pp, _d, _d, _d, _d, C.c_double, C.c_double, _d, _i32]),
+        "orc_stencil27": (None, [_pp, _d, _d, _i64, _d]),
+        "orc_p2g_fixed": (None, [_pp, C.c_int64, _d, _d, _d, _i64, _i64]),
+        "orc_p2g_real": (None, [_pp, C.c_int64, _d, _d, _d, _d, _d]),
+        "orc_g2p": (None, [_pp, C.c_int64, _d, _d, _i64, _d, _d, _d]),
+        "orc_drag": (None, [_pp, C.c_int64, _d, _d, _d, _d, _d]),
+        "orc_integrate": (None, [_pp, C.c_int64, _d, _d, _d, _d, _d]),
+        "orc_step": (None, [_pp, C.c_int64, _d, _d, _d, _d, _i64, _i64, _d, _d, _d, _d]),
+        "orc_num_threads": (C.c_int, []),
+        "orc_set_num_threads": (None, [C.c_int]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+
+
+def _ptr(a, ctype):
+    if a is None:
+        return None
+    return a.ctypes.data_as(_P(ctype))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def nodes(cfg):
+    n = cfg["n"]
+    return int(n[0]) * int(n[1]) * int(n[2])
+
+
+def key_space(cfg):
+    p = params(cfg)
+    return int(lib().orc_key_space(C.byref(p)))
+
+
+def num_threads():
+    return int(lib().orc_num_threads())
+
+
+def set_num_threads(t):
+    lib().orc_set_num_threads(int(t))
+
+
+# ---- binning / neighbour search (support of Sec. 3.1's contact test) --------
+
+def cell_keys(cfg, x):
+    """Brick-major neighbour-cell key per granule (uint32)."""
+    x = _f64(x)
+    n = x.shape[1]
+    key = np.zeros(n, np.uint32)
+    p = params(cfg)
+    lib().orc_cell_keys(C.byref(p), n, _ptr(x, C.c_double), _ptr(key, C.c_uint32))
+    return key
+
+
+def stable_sort(key):
+    key = np.ascontiguousarray(key, np.uint32)
+    order = np.zeros(key.shape[0], np.int32)
+    lib().orc_stable_sort(key.shape[0], _ptr(key, C.c_uint32), _ptr(order, C.c_int32))
+    return order
+
+
+def cell_ranges(cfg, key, order):
+    key = np.ascontiguousarray(key, np.uint32)
+    order = np.ascontiguousarray(order, np.int32)
+    K = key_space(cfg)
+    begin = np.zeros(K, np.int32)
+    end = np.zeros(K, np.int32)
+    p = params(cfg)
+    lib().orc_cell_ranges(C.byref(p), key.shape[0], _ptr(key, C.c_uint32), _ptr(order, C.c_int32),
+                          _ptr(begin, C.c_int32), _ptr(end, C.c_int32))
+    return begin, end
+
+
+def _pairs(fn, args, n_guess):
+    cap = max(16, n_guess)
+    while True:
+        pi = np.zeros(cap, np.int32)
+        pj = np.zeros(cap, np.int32)
+        cnt = fn(*args, cap, _ptr(pi, C.c_int32), _ptr(pj, C.c_int32))
+        if cnt <= cap:
+            return np.stack([pi[:cnt], pj[:cnt]], 1)
+        cap = int(cnt)
+
+
+def pairs_brute(x, r):
+    """Touching pairs (i < j) by the O(N^2) definition d_ij < r_i + r_j (Sec. 3.1)."""
+    x = _f64(x)
+    r = _f64(r)
+    return _pairs(lib().orc_pairs_brute, (x.shape[1], _ptr(x, C.c_double), _ptr(r, C.c_double)), 8 * x.shape[1])
+
+
+def pairs_cells(cfg, x, r):
+    """The same pair set found through the cell list."""
+    x = _f64(x)
+    r = _f64(r)
+    p = params(cfg)
+    return _pairs(lib().orc_pairs_cells,
+                  (C.byref(p), x.shape[1], _ptr(x, C.c_double), _ptr(r, C.c_double)), 8 * x.shape[1])
+
+
+# ---- contact force, Eq. (1a)-(1c) --------------------------------------------
+
+def contact_forces(cfg, x, v, r):
+    """Returns (F (3,n), fabs (n), ncontacts (n), nsliding (n))."""
+    x, v, r = _f64(x), _f64(v), _f64(r)
+    n = x.shape[1]
+    F = np.zeros((3, n))
+    fa = np.zeros(n)
+    nc = np.zeros(n, np.int32)
+    ns = np.zeros(n, np.int32)
+    p = params(cfg)
+    lib().orc_contact_forces(C.byref(p), n, _ptr(x, C.c_double), _ptr(v, C.c_double), _ptr(r, C.c_double),
+                             _ptr(F, C.c_double), _ptr(fa, C.c_double), _ptr(nc, C.c_int32), _ptr(ns, C.c_int32))
+    return F, fa, nc, ns
+
+
+def contact_forces_sample(cfg, x, v, r, idx):
+    x, v, r = _f64(x), _f64(v), _f64(r)
+    idx = np.ascontiguousarray(idx, np.int64)
+    m = idx.shape[0]
+    F = np.zeros((3, m))
+    fa = np.zeros(m)
+    p = params(cfg)
+    lib().orc_contact_forces_sample(C.byref(p), x.shape[1], _ptr(x, C.c_double), _ptr(v, C.c_double),
+                                    _ptr(r, C.c_double), m, _ptr(idx, C.c_int64), _ptr(F, C.c_double),
+                                    _ptr(fa, C.c_double))
+    return F, fa
+
+
+def pair_force(cfg, xi, xj, vi, vj, ri, rj):
+    """Force on i from j; returns (F (3,), touching, sliding)."""
+    p = params(cfg)
+    F = np.zeros(3)
+    s = np.zeros(1, np.int32)
+    a = [_f64(t) for t in (xi, xj, vi, vj)]
+    hit = lib().orc_pair(C.byref(p), *[_ptr(t, C.c_double) for t in a], float(ri), float(rj),
+                         _ptr(F, C.c_double), _ptr(s, C.c_int32))
+    return F, bool(hit), bool(s[0])
+
+
+# ---- transfers, Eq. (7a) and the G2P of Sec. 5.2 -----------------------------
+
+def stencil27(cfg, xa):
+    p = params(cfg)
+    xa = _f64(xa)
+    w = np.zeros(27)
+    node = np.zeros(27, np.int64)
+    w1 = np.zeros(9)
+    lib().orc_stencil27(C.byref(p), _ptr(xa, C.c_double), _ptr(w, C.c_double), _ptr(node, C.c_int64),
+                        _ptr(w1, C.c_double))
+    return w, node, w1.reshape(3, 3)
+
+
+def p2g_fixed(cfg, x, v, r):
+    """(alpha (G,) int64, mom (3,G) int64) in 2^-32 units."""
+    x, v, r = _f64(x), _f64(v), _f64(r)
+    G = nodes(cfg)
+    alpha = np.zeros(G, np.int64)
+    mom = np.zeros((3, G), np.int64)
+    p = params(cfg)
+    lib().orc_p2g_fixed(C.byref(p), x.shape[1], _ptr(x, C.c_double), _ptr(v, C.c_double), _ptr(r, C.c_double),
+                        _ptr(alpha, C.c_int64), _ptr(mom, C.c_int64))
+    return alpha, mom
+
+
+def p2g_real(cfg, x, v, r):
+    """(alpha (G,) cell volumes, mom (3,G) kg m/s), unquantised."""
+    x, v, r = _f64(x), _f64(v), _f64(r)
+    G = nodes(cfg)
+    alpha = np.zeros(G)
+    mom = np.zeros((3, G))
+    p = params(cfg)
+    lib().orc_p2g_real(C.byref(p), x.shape[1], _ptr(x, C.c_double), _ptr(v, C.c_double), _ptr(r, C.c_double),
+                       _ptr(alpha, C.c_double), _ptr(mom, C.c_double))
+    return alpha, mom
+
+
+def g2p(cfg, x, u, alpha_fx=None, alpha_real=None):
+    """(u_at (3,n), alpha_f (n,))."""
+    assert (alpha_fx is None) != (alpha_real is None)
+    x, u = _f64(x), _f64(u)
+    n = x.shape[1]
+    uat = np.zeros((3, n))
+    af = np.zeros(n)
+    afx = None if alpha_fx is None else np.ascontiguousarray(alpha_fx, np.int64)
+    are = None if alpha_real is None else _f64(alpha_real)
+    p = params(cfg)
+    lib().orc_g2p(C.byref(p), n, _ptr(x, C.c_double), _ptr(u, C.c_double), _ptr(afx, C.c_int64),
+                  _ptr(are, C.c_double), _ptr(uat, C.c_double), _ptr(af, C.c_double))
+    return uat, af
+
+
+def drag(cfg, r, v, u_at, alpha_f):
+    r, v, u_at, alpha_f = _f64(r), _f64(v), _f64(u_at), _f64(alpha_f)
+    n = r.shape[0]
+    Fd = np.zeros((3, n))
+    p = params(cfg)
+    lib().orc_drag(C.byref(p), n, _ptr(r, C.c_double), _ptr(v, C.c_double), _ptr(u_at, C.c_double),
+                   _ptr(alpha_f, C.c_double), _ptr(Fd, C.c_double))
+    return Fd
+
+
+def integrate(cfg, r, Fc, Fd, x, v):
+    """Returns new (x, v); inputs are not modified."""
+    r, Fc, Fd = _f64(r), _f64(Fc), _f64(Fd)
+    x = _f64(x).copy()
+    v = _f64(v).copy()
+    p = params(cfg)
+    lib().orc_integrate(C.byref(p), r.shape[0], _ptr(r, C.c_double), _ptr(Fc, C.c_double), _ptr(Fd, C.c_double),
+                        _ptr(x, C.c_double), _ptr(v, C.c_double))
+    return x, v
+
+
+def step(cfg, x, v, r, u, alpha_fx):
+    """One granule step (Alg. 2, one sub-step).  Returns a dict with the new
+    x, v, the new alpha / momentum grids and the intermediates."""
+    x = _f64(x).copy()
+    v = _f64(v).copy()
+    r, u = _f64(r), _f64(u)
+    n = x.shape[1]
+    G = nodes(cfg)
+    alpha = np.ascontiguousarray(alpha_fx, np.int64).copy()
+    mom = np.zeros((3, G), np.int64)
+    Fc = np.zeros((3, n))
+    Fd = np.zeros((3, n))
+    uat = np.zeros((3, n))
+    af = np.zeros(n)
+    p = params(cfg)
+    lib().orc_step(C.byref(p), n, _ptr(x, C.c_double), _ptr(v, C.c_double), _ptr(r, C.c_double),
+                   _ptr(u, C.c_double), _ptr(alpha, C.c_int64), _ptr(mom, C.c_int64), _ptr(Fc, C.c_double),
+                   _ptr(Fd, C.c_double), _ptr(uat, C.c_double), _ptr(af, C.c_double))
+    return dict(x=x, v=v, alpha=alpha, mom=mom, Fc=Fc, Fd=Fd, u_at=uat, alpha_f=af)

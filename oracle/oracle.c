@@ -1,0 +1,721 @@
+/*
+ * Granule-In-Cell granule step: plain FP64 CPU oracle.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously-correct
+ * reference that the GPU path is checked against.  Only the test-suite, the
+ * smoke check and the CPU-baseline leg of the benchmark load it; the product
+ * library never links, includes or calls it, and it includes nothing from the
+ * product library.
+ *
+ * Paper: Tang, Zhu, Ni, Chen, "The Granule-In-Cell Method for Simulating
+ * Sand-Water Mixtures", ACM TOG 44(6) 2025 (arXiv 2504.00745).
+ *
+ * Passages followed:
+ *   contact force .......... Sec. 3.1, Eq. (1a)-(1c)
+ *   interphase drag ........ Sec. 3.3, Eq. (5b) and App. A (linear relaxation
+ *                            drag M_s = a_s rho_s (v_f - v_s) / tau_s)
+ *   sub-step loop .......... Alg. 2 (SandSubstep): coupling force, collision,
+ *                            move
+ *   integrator ............. Sec. 4 ("similar to the symplectic Euler method")
+ *   volume fraction P2G .... Sec. 5.1, Eq. (7a), at cell centres
+ *   alpha_s limit 0.740 .... Sec. 5.1 (densest sphere packing, 3D)
+ *   fluid velocity G2P ..... Sec. 5.2 ("interpolating the fluid velocity at the
+ *                            position x_s from the grid")
+ *
+ * Readings where the paper is silent (all recorded in the design notes):
+ *   - normal dashpot from a restitution coefficient (Eq. 1a has none);
+ *     gamma_n = 2 zeta sqrt(m_eff k_n), zeta = -ln e / sqrt(pi^2 + ln^2 e);
+ *     no tensile clamp;
+ *   - k_t = kt_ratio * gamma_n (k_t multiplies a velocity in Eq. 1c);
+ *   - Coulomb cap = tan(phi) * k_n * delta, i.e. the norm of Eq. 1a's spring
+ *     force; mu = tan(phi);
+ *   - polydisperse: 2r -> r_i + r_j, strict "<";
+ *   - six planar box walls, infinite-mass partners, same law;
+ *   - drag F_d = C_d 6 pi eta_f r alpha_f (u - v) (Stokes form of App. A's
+ *     relaxation drag, scaled by the local fluid fraction);
+ *   - grid nodes at cell centres (i + 1/2) dx, quadratic B-spline kernel,
+ *     out-of-range nodes folded onto the edge node;
+ *   - alpha_s clamped at the nodes, then interpolated; alpha_f = 1 - alpha_s;
+ *   - int64 fixed point, 2^-32 units, round half to even, the per-granule
+ *     remainder goes to the centre node so each granule deposits exactly
+ *     rint(frac * 2^32);
+ *   - coincident centres (d == 0) exert no force.
+ *
+ * Arrays are structure-of-arrays: x[0..n) = x-coordinates, x[n..2n) = y,
+ * x[2n..3n) = z; the same for v and for every 3-vector per granule.  Grid
+ * arrays are x-fastest: node (i,j,k) sits at i + nx (j + ny k); 3-vector grid
+ * fields are three consecutive G-sized planes.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared (see build.py).
+ * No fused multiply-add is allowed anywhere: every product and sum below is
+ * rounded on its own, in the order written.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_PI 3.14159265358979323846
+#define ORC_C43PI (4.0 * ORC_PI / 3.0)
+#define ORC_C6PI (6.0 * ORC_PI)
+#define ORC_TWO32 4294967296.0
+#define ORC_TWOM32 (1.0 / 4294967296.0)
+#define ORC_BRICK 4 /* neighbour cells per brick edge in the cell key */
+
+typedef struct {
+    int32_t n[3];       /* grid nodes per axis; node i sits at (i + 1/2) dx */
+    double dx;          /* grid spacing [m]                                */
+    int32_t nc[3];      /* neighbour cells per axis                         */
+    double cell;        /* neighbour cell edge [m], >= 2 r_max              */
+    double kn;          /* normal stiffness [N/m]                           */
+    double restitution; /* normal coefficient of restitution e in (0,1]     */
+    double kt_ratio;    /* k_t = kt_ratio * gamma_n                         */
+    double mu;          /* Coulomb coefficient tan(phi)                     */
+    double rho_s;       /* granule density [kg/m^3]                         */
+    double eta_f;       /* fluid viscosity [Pa s]                           */
+    double c_drag;      /* drag coefficient C_d (dimensionless)             */
+    double alpha_max;   /* node clamp of alpha_s (0.740)                    */
+    double g[3];        /* gravity [m/s^2]                                  */
+    double dt;          /* step [s]                                         */
+    uint32_t walls;     /* bit 2a: low face of axis a, bit 2a+1: high face  */
+    int32_t pad;
+} orc_params;
+
+/* ------------------------------------------------------------------------ */
+/* Small helpers                                                            */
+/* ------------------------------------------------------------------------ */
+
+static double orc_mass(const orc_params *p, double r)
+{
+    /* m = rho_s * (4/3) pi r^3 */
+    return p->rho_s * (((ORC_C43PI * r) * r) * r);
+}
+
+static double orc_volume(double r)
+{
+    return ((ORC_C43PI * r) * r) * r;
+}
+
+/* Damping ratio of the linear spring-dashpot that gives restitution e. */
+static double orc_zeta(double e)
+{
+    double le = log(e);
+    return -le / sqrt(ORC_PI * ORC_PI + le * le);
+}
+
+static int64_t orc_nodes(const orc_params *p)
+{
+    return (int64_t)p->n[0] * p->n[1] * p->n[2];
+}
+
+/* Neighbour-cell coordinate along one axis: clamp(floor(x / cell), 0, nc-1).
+ * NaN maps to 0. */
+static int32_t orc_cell_coord(double x, double inv_cell, int32_t nc)
+{
+    double t = floor(x * inv_cell);
+    if (!(t >= 0.0)) return 0;
+    if (t > (double)(nc - 1)) return nc - 1;
+    return (int32_t)t;
+}
+
+/* Key of a neighbour cell: bricks of 4x4x4 cells in x-fastest brick order,
+ * cells x-fastest inside a brick. */
+static uint32_t orc_key_of_cell(const orc_params *p, int32_t cx, int32_t cy, int32_t cz)
+{
+    int32_t nbx = (p->nc[0] + ORC_BRICK - 1) / ORC_BRICK;
+    int32_t nby = (p->nc[1] + ORC_BRICK - 1) / ORC_BRICK;
+    uint32_t brick = (uint32_t)(((cz / ORC_BRICK) * nby + (cy / ORC_BRICK)) * nbx + (cx / ORC_BRICK));
+    uint32_t local = (uint32_t)(((cz % ORC_BRICK) * ORC_BRICK + (cy % ORC_BRICK)) * ORC_BRICK + (cx % ORC_BRICK));
+    return brick * (uint32_t)(ORC_BRICK * ORC_BRICK * ORC_BRICK) + local;
+}
+
+int64_t orc_key_space(const orc_params *p)
+{
+    int64_t nbx = (p->nc[0] + ORC_BRICK - 1) / ORC_BRICK;
+    int64_t nby = (p->nc[1] + ORC_BRICK - 1) / ORC_BRICK;
+    int64_t nbz = (p->nc[2] + ORC_BRICK - 1) / ORC_BRICK;
+    return nbx * nby * nbz * ORC_BRICK * ORC_BRICK * ORC_BRICK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Binning and stable sort (neighbour search support)                        */
+/* ------------------------------------------------------------------------ */
+
+void orc_cell_keys(const orc_params *p, int64_t n, const double *x, uint32_t *key)
+{
+    double inv_cell = 1.0 / p->cell;
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t cx = orc_cell_coord(x[i], inv_cell, p->nc[0]);
+        int32_t cy = orc_cell_coord(x[n + i], inv_cell, p->nc[1]);
+        int32_t cz = orc_cell_coord(x[2 * n + i], inv_cell, p->nc[2]);
+        key[i] = orc_key_of_cell(p, cx, cy, cz);
+    }
+}
+
+typedef struct {
+    uint32_t key;
+    int32_t idx;
+} orc_kv;
+
+static int orc_kv_cmp(const void *a, const void *b)
+{
+    const orc_kv *u = (const orc_kv *)a, *w = (const orc_kv *)b;
+    if (u->key != w->key) return u->key < w->key ? -1 : 1;
+    /* ties keep input order: the sort is stable */
+    return (u->idx > w->idx) - (u->idx < w->idx);
+}
+
+/* order[p] = index of the granule at sorted position p; ties in input order. */
+void orc_stable_sort(int64_t n, const uint32_t *key, int32_t *order)
+{
+    orc_kv *kv = (orc_kv *)malloc(sizeof(orc_kv) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        kv[i].key = key[i];
+        kv[i].idx = (int32_t)i;
+    }
+    qsort(kv, (size_t)n, sizeof(orc_kv), orc_kv_cmp);
+    for (int64_t i = 0; i < n; ++i) order[i] = kv[i].idx;
+    free(kv);
+}
+
+/* begin[c], end[c]: sorted positions of the granules in cell key c, for every
+ * key c of the key space; an empty cell has begin = end = 0. */
+void orc_cell_ranges(const orc_params *p, int64_t n, const uint32_t *key, const int32_t *order,
+                     int32_t *begin, int32_t *end)
+{
+    int64_t K = orc_key_space(p);
+    memset(begin, 0, sizeof(int32_t) * (size_t)K);
+    memset(end, 0, sizeof(int32_t) * (size_t)K);
+    for (int64_t q = 0; q < n; ++q) {
+        uint32_t k = key[order[q]];
+        if (q == 0 || key[order[q - 1]] != k) begin[k] = (int32_t)q;
+        end[k] = (int32_t)(q + 1);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Contact test and pair list                                                */
+/* ------------------------------------------------------------------------ */
+
+/* Sec. 3.1: granules i, j touch iff d_ij < r_i + r_j; the test is done on
+ * squared distances with d^2 = (dx*dx + dy*dy) + dz*dz. */
+static int orc_touch(int64_t n, const double *x, const double *r, int64_t i, int64_t j, double dv[3],
+                     double *d2)
+{
+    dv[0] = x[i] - x[j];
+    dv[1] = x[n + i] - x[n + j];
+    dv[2] = x[2 * n + i] - x[2 * n + j];
+    *d2 = (dv[0] * dv[0] + dv[1] * dv[1]) + dv[2] * dv[2];
+    double R = r[i] + r[j];
+    return *d2 < R * R;
+}
+
+/* All touching pairs i < j by the plain O(N^2) definition.  Returns the pair
+ * count; writes at most cap pairs. */
+int64_t orc_pairs_brute(int64_t n, const double *x, const double *r, int64_t cap, int32_t *pi,
+                        int32_t *pj)
+{
+    int64_t cnt = 0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = i + 1; j < n; ++j) {
+            double dv[3], d2;
+            if (orc_touch(n, x, r, i, j, dv, &d2)) {
+                if (cnt < cap) {
+                    pi[cnt] = (int32_t)i;
+                    pj[cnt] = (int32_t)j;
+                }
+                ++cnt;
+            }
+        }
+    return cnt;
+}
+
+/* Cell list built from the keys, for the cell-based search below. */
+typedef struct {
+    uint32_t *key;
+    int32_t *order;
+    int32_t *begin;
+    int32_t *end;
+} orc_cells;
+
+static void orc_cells_build(const orc_params *p, int64_t n, const double *x, orc_cells *c)
+{
+    int64_t K = orc_key_space(p);
+    c->key = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+    c->order = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    c->begin = (int32_t *)malloc(sizeof(int32_t) * (size_t)K);
+    c->end = (int32_t *)malloc(sizeof(int32_t) * (size_t)K);
+    orc_cell_keys(p, n, x, c->key);
+    orc_stable_sort(n, c->key, c->order);
+    orc_cell_ranges(p, n, c->key, c->order, c->begin, c->end);
+}
+
+static void orc_cells_free(orc_cells *c)
+{
+    free(c->key);
+    free(c->order);
+    free(c->begin);
+    free(c->end);
+}
+
+/* Largest number of granules in one cell. */
+static int64_t orc_cells_maxocc(const orc_params *p, const orc_cells *c)
+{
+    int64_t K = orc_key_space(p), m = 0;
+    for (int64_t k = 0; k < K; ++k)
+        if (c->end[k] - c->begin[k] > m) m = c->end[k] - c->begin[k];
+    return m;
+}
+
+/* Candidates of granule i: every j != i in the 27 cells around i's cell (the
+ * cell edge is at least the largest diameter, so every touching partner is
+ * among them).  Writes them to out and returns their number. */
+static int64_t orc_candidates(const orc_params *p, int64_t n, const double *x, const orc_cells *cl, int64_t i,
+                              int64_t *out)
+{
+    double inv_cell = 1.0 / p->cell;
+    int32_t ci[3];
+    for (int a = 0; a < 3; ++a) ci[a] = orc_cell_coord(x[a * n + i], inv_cell, p->nc[a]);
+    int64_t cnt = 0;
+    for (int32_t cz = ci[2] - 1; cz <= ci[2] + 1; ++cz)
+        for (int32_t cy = ci[1] - 1; cy <= ci[1] + 1; ++cy)
+            for (int32_t cx = ci[0] - 1; cx <= ci[0] + 1; ++cx) {
+                if (cx < 0 || cy < 0 || cz < 0 || cx >= p->nc[0] || cy >= p->nc[1] || cz >= p->nc[2]) continue;
+                uint32_t k = orc_key_of_cell(p, cx, cy, cz);
+                for (int32_t q = cl->begin[k]; q < cl->end[k]; ++q)
+                    if (cl->order[q] != i) out[cnt++] = cl->order[q];
+            }
+    return cnt;
+}
+
+/* Same pair set as orc_pairs_brute, found through the cell list. */
+int64_t orc_pairs_cells(const orc_params *p, int64_t n, const double *x, const double *r, int64_t cap,
+                        int32_t *pi, int32_t *pj)
+{
+    orc_cells cl;
+    orc_cells_build(p, n, x, &cl);
+    int64_t cnt = 0;
+    int64_t *cand = (int64_t *)malloc(sizeof(int64_t) * (size_t)(27 * orc_cells_maxocc(p, &cl) + 1));
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t nc_ = orc_candidates(p, n, x, &cl, i, cand);
+        for (int64_t s = 0; s < nc_; ++s) {
+            int64_t j = cand[s];
+            double dv[3], d2;
+            if (j > i && orc_touch(n, x, r, i, j, dv, &d2)) {
+                if (cnt < cap) {
+                    pi[cnt] = (int32_t)i;
+                    pj[cnt] = (int32_t)j;
+                }
+                ++cnt;
+            }
+        }
+    }
+    free(cand);
+    orc_cells_free(&cl);
+    return cnt;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pair force, Eq. (1a)-(1c) with the dashpot reading                        */
+/* ------------------------------------------------------------------------ */
+
+/* Force on the first partner of a touching pair.
+ *   nh     : unit normal x_ij / d (from the partner to this granule)
+ *   delta  : overlap (r_i + r_j) - d  (> 0)
+ *   w      : relative velocity v_i - v_j
+ *   meff   : effective mass m_i m_j / (m_i + m_j) (m_i for a wall)
+ * Writes the force; returns 1 if the tangential force was capped (sliding). */
+static int orc_pair_force(const orc_params *p, double zeta, const double nh[3], double delta,
+                          const double w[3], double meff, double F[3])
+{
+    double gam = 2.0 * zeta * sqrt(meff * p->kn);
+    double kt = p->kt_ratio * gam;
+    double vn = (w[0] * nh[0] + w[1] * nh[1]) + w[2] * nh[2];
+    double fn = p->kn * delta - gam * vn; /* Eq. (1a) + dashpot */
+    double ft[3];
+    for (int a = 0; a < 3; ++a) ft[a] = -kt * (w[a] - vn * nh[a]); /* Eq. (1c) */
+    double fts = sqrt((ft[0] * ft[0] + ft[1] * ft[1]) + ft[2] * ft[2]);
+    double cap = p->mu * (p->kn * delta); /* Eq. (1b): ||F_n|| tan(phi) */
+    int slide = fts > cap;
+    double s = slide ? cap / fts : 1.0;
+    for (int a = 0; a < 3; ++a) F[a] = fn * nh[a] + (slide ? ft[a] * s : ft[a]);
+    return slide;
+}
+
+/* Contact force of granule i with every touching granule (cell list) and
+ * every enabled wall.  Fabs[i] (optional) = sum of the norms of the pair and
+ * wall forces, the scale of the sum's rounding error. */
+static void orc_contact_one(const orc_params *p, double zeta, int64_t n, const double *x, const double *v,
+                            const double *r, const orc_cells *cl, int64_t i, int64_t *cand, double Fi[3],
+                            double *fabs_i, int32_t *ncont, int32_t *nslide)
+{
+    double mi = orc_mass(p, r[i]);
+    double acc[3] = {0.0, 0.0, 0.0};
+    double sabs = 0.0;
+    int32_t nc_ = 0, ns_ = 0;
+    int64_t ncand = orc_candidates(p, n, x, cl, i, cand);
+    for (int64_t s = 0; s < ncand; ++s) {
+        int64_t j = cand[s];
+        double dv[3], d2;
+        if (!orc_touch(n, x, r, i, j, dv, &d2)) continue;
+        if (d2 == 0.0) continue; /* coincident centres: no normal, no force */
+        double d = sqrt(d2);
+        double nh[3] = {dv[0] / d, dv[1] / d, dv[2] / d};
+        double delta = (r[i] + r[j]) - d;
+        double w[3] = {v[i] - v[j], v[n + i] - v[n + j], v[2 * n + i] - v[2 * n + j]};
+        double mj = orc_mass(p, r[j]);
+        double meff = (mi * mj) / (mi + mj);
+        double F[3];
+        ns_ += orc_pair_force(p, zeta, nh, delta, w, meff, F);
+        ++nc_;
+        for (int a = 0; a < 3; ++a) acc[a] += F[a];
+        sabs += sqrt((F[0] * F[0] + F[1] * F[1]) + F[2] * F[2]);
+    }
+    for (int a = 0; a < 3; ++a) {
+        double L = (double)p->n[a] * p->dx;
+        for (int side = 0; side < 2; ++side) {
+            if (!(p->walls & (1u << (2 * a + side)))) continue;
+            double xa = x[a * n + i];
+            double dist = side == 0 ? xa : L - xa;
+            double delta = r[i] - dist;
+            if (!(delta > 0.0)) continue;
+            double nh[3] = {0.0, 0.0, 0.0};
+            nh[a] = side == 0 ? 1.0 : -1.0;
+            double w[3] = {v[i], v[n + i], v[2 * n + i]};
+            double F[3];
+            ns_ += orc_pair_force(p, zeta, nh, delta, w, mi, F);
+            ++nc_;
+            for (int b = 0; b < 3; ++b) acc[b] += F[b];
+            sabs += sqrt((F[0] * F[0] + F[1] * F[1]) + F[2] * F[2]);
+        }
+    }
+    for (int a = 0; a < 3; ++a) Fi[a] = acc[a];
+    if (fabs_i) *fabs_i = sabs;
+    if (ncont) *ncont = nc_;
+    if (nslide) *nslide = ns_;
+}
+
+/* F (3n, SoA) = contact force per granule; fabs, ncont, nslide optional. */
+void orc_contact_forces(const orc_params *p, int64_t n, const double *x, const double *v, const double *r,
+                        double *F, double *fabs_out, int32_t *ncont, int32_t *nslide)
+{
+    orc_cells cl;
+    orc_cells_build(p, n, x, &cl);
+    double zeta = orc_zeta(p->restitution);
+    int64_t cap = 27 * orc_cells_maxocc(p, &cl) + 1;
+#pragma omp parallel
+    {
+        int64_t *cand = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap);
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            double Fi[3], fa;
+            int32_t c1, c2;
+            orc_contact_one(p, zeta, n, x, v, r, &cl, i, cand, Fi, &fa, &c1, &c2);
+            for (int a = 0; a < 3; ++a) F[a * n + i] = Fi[a];
+            if (fabs_out) fabs_out[i] = fa;
+            if (ncont) ncont[i] = c1;
+            if (nslide) nslide[i] = c2;
+        }
+        free(cand);
+    }
+    orc_cells_free(&cl);
+}
+
+/* Contact force on the granules listed in idx[0..m) only (sampled parity at
+ * sizes where the full oracle would be slow). */
+void orc_contact_forces_sample(const orc_params *p, int64_t n, const double *x, const double *v,
+                               const double *r, int64_t m, const int64_t *idx, double *F, double *fabs_out)
+{
+    orc_cells cl;
+    orc_cells_build(p, n, x, &cl);
+    double zeta = orc_zeta(p->restitution);
+    int64_t cap = 27 * orc_cells_maxocc(p, &cl) + 1;
+#pragma omp parallel
+    {
+        int64_t *cand = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap);
+#pragma omp for schedule(static)
+        for (int64_t s = 0; s < m; ++s) {
+            double Fi[3], fa;
+            orc_contact_one(p, zeta, n, x, v, r, &cl, idx[s], cand, Fi, &fa, NULL, NULL);
+            for (int a = 0; a < 3; ++a) F[a * m + s] = Fi[a];
+            if (fabs_out) fabs_out[s] = fa;
+        }
+        free(cand);
+    }
+    orc_cells_free(&cl);
+}
+
+/* Force of one pair, exposed for the closed-form and antisymmetry pins.
+ * xi, xj, vi, vj: 3-vectors; returns 0 if the pair does not touch. */
+int orc_pair(const orc_params *p, const double *xi, const double *xj, const double *vi, const double *vj,
+             double ri, double rj, double *F, int32_t *slide)
+{
+    double X[6] = {xi[0], xj[0], xi[1], xj[1], xi[2], xj[2]};
+    double R2[2] = {ri, rj};
+    double dv[3], d2;
+    if (!orc_touch(2, X, R2, 0, 1, dv, &d2) || d2 == 0.0) {
+        F[0] = F[1] = F[2] = 0.0;
+        if (slide) *slide = 0;
+        return 0;
+    }
+    double d = sqrt(d2);
+    double nh[3] = {dv[0] / d, dv[1] / d, dv[2] / d};
+    double w[3] = {vi[0] - vj[0], vi[1] - vj[1], vi[2] - vj[2]};
+    double mi = orc_mass(p, ri), mj = orc_mass(p, rj);
+    int s = orc_pair_force(p, orc_zeta(p->restitution), nh, (ri + rj) - d, w, (mi * mj) / (mi + mj), F);
+    if (slide) *slide = s;
+    return 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Quadratic B-spline stencil on cell-centred nodes (Sec. 5.1, Eq. 7a)        */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t node[3][3]; /* node index per axis and stencil slot, folded into range */
+    double w[3][3];     /* 1-D weights */
+    double dw[3][3];    /* d w / d x (per metre) */
+} orc_stencil;
+
+/* Node i sits at (i + 1/2) dx.  t = x/dx; base = floor(t - 1); f = t - base -
+ * 1/2 in [1/2, 3/2) is the distance from the first node.  Weights of the
+ * quadratic B-spline at distances f, |f-1|, 2-f. */
+static void orc_stencil_of(const orc_params *p, double inv_dx, const double xa[3], orc_stencil *s)
+{
+    for (int a = 0; a < 3; ++a) {
+        double t = xa[a] * inv_dx;
+        double fb = floor(t - 1.0);
+        double f = (t - fb) - 0.5;
+        double c0 = 1.5 - f, c1 = f - 1.0, c2 = f - 0.5;
+        s->w[a][0] = 0.5 * (c0 * c0);
+        s->w[a][1] = 0.75 - c1 * c1;
+        s->w[a][2] = 0.5 * (c2 * c2);
+        s->dw[a][0] = -c0 * inv_dx;
+        s->dw[a][1] = (-2.0 * c1) * inv_dx;
+        s->dw[a][2] = c2 * inv_dx;
+        /* fold out-of-range nodes onto the edge node */
+        double lo = -2.0, hi = (double)p->n[a];
+        if (!(fb >= lo)) fb = lo; /* also catches NaN */
+        if (fb > hi) fb = hi;
+        int32_t b = (int32_t)fb;
+        for (int k = 0; k < 3; ++k) {
+            int32_t id = b + k;
+            if (id < 0) id = 0;
+            if (id > p->n[a] - 1) id = p->n[a] - 1;
+            s->node[a][k] = id;
+        }
+    }
+}
+
+static int64_t orc_node_index(const orc_params *p, const orc_stencil *s, int a, int b, int c)
+{
+    return (int64_t)s->node[0][a] + (int64_t)p->n[0] * ((int64_t)s->node[1][b] + (int64_t)p->n[1] * s->node[2][c]);
+}
+
+static void orc_pos(int64_t n, const double *x, int64_t i, double xa[3])
+{
+    xa[0] = x[i];
+    xa[1] = x[n + i];
+    xa[2] = x[2 * n + i];
+}
+
+/* Weights of one granule's stencil, exposed for the B-spline pins:
+ * w27[(c*3+b)*3+a] = (wx[a] wy[b]) wz[c], node27 the flat node index. */
+void orc_stencil27(const orc_params *p, const double *xa, double *w27, int64_t *node27, double *w1d)
+{
+    orc_stencil s;
+    orc_stencil_of(p, 1.0 / p->dx, xa, &s);
+    for (int c = 0; c < 3; ++c)
+        for (int b = 0; b < 3; ++b)
+            for (int a = 0; a < 3; ++a) {
+                int k = (c * 3 + b) * 3 + a;
+                w27[k] = (s.w[0][a] * s.w[1][b]) * s.w[2][c];
+                node27[k] = orc_node_index(p, &s, a, b, c);
+            }
+    if (w1d)
+        for (int a = 0; a < 3; ++a)
+            for (int k = 0; k < 3; ++k) w1d[a * 3 + k] = s.w[a][k];
+}
+
+/* ------------------------------------------------------------------------ */
+/* P2G: Eq. (7a) volume fraction and granule momentum                        */
+/* ------------------------------------------------------------------------ */
+
+/* Fixed point.  alpha in units of 2^-32 cell volumes; momentum in units of
+ * 2^-32 rho_s dx^3 (1 m/s).  Per granule and channel the target total is
+ * Q = rint(S) with S = frac * 2^32 (alpha) or (frac * v_c) * 2^32 (momentum),
+ * frac = V_i / dx^3.  The 26 outer nodes take rint(w * S); the centre node
+ * takes Q minus their sum.  Adds into alpha (G) and mom (3G). */
+void orc_p2g_fixed(const orc_params *p, int64_t n, const double *x, const double *v, const double *r,
+                   int64_t *alpha, int64_t *mom)
+{
+    double inv_dx = 1.0 / p->dx;
+    double inv_vcell = 1.0 / ((p->dx * p->dx) * p->dx);
+    int64_t G = orc_nodes(p);
+    for (int64_t i = 0; i < n; ++i) {
+        double xa[3];
+        orc_pos(n, x, i, xa);
+        orc_stencil s;
+        orc_stencil_of(p, inv_dx, xa, &s);
+        double frac = orc_volume(r[i]) * inv_vcell;
+        double S[4] = {frac * ORC_TWO32, (frac * v[i]) * ORC_TWO32, (frac * v[n + i]) * ORC_TWO32,
+                       (frac * v[2 * n + i]) * ORC_TWO32};
+        for (int ch = 0; ch < 4; ++ch) {
+            int64_t Q = llrint(S[ch]);
+            int64_t rest = Q;
+            int64_t *dst = ch == 0 ? alpha : mom + (int64_t)(ch - 1) * G;
+            for (int c = 0; c < 3; ++c)
+                for (int b = 0; b < 3; ++b)
+                    for (int a = 0; a < 3; ++a) {
+                        if (a == 1 && b == 1 && c == 1) continue;
+                        double w = (s.w[0][a] * s.w[1][b]) * s.w[2][c];
+                        int64_t q = llrint(w * S[ch]);
+                        rest -= q;
+                        dst[orc_node_index(p, &s, a, b, c)] += q;
+                    }
+            dst[orc_node_index(p, &s, 1, 1, 1)] += rest;
+        }
+    }
+}
+
+/* Unquantised P2G for the differentiable form: alpha in cell volumes
+ * (sum_i w frac_i), momentum in kg m/s (sum_i w m_i v_i). */
+void orc_p2g_real(const orc_params *p, int64_t n, const double *x, const double *v, const double *r,
+                  double *alpha, double *mom)
+{
+    double inv_dx = 1.0 / p->dx;
+    double inv_vcell = 1.0 / ((p->dx * p->dx) * p->dx);
+    int64_t G = orc_nodes(p);
+    for (int64_t i = 0; i < n; ++i) {
+        double xa[3];
+        orc_pos(n, x, i, xa);
+        orc_stencil s;
+        orc_stencil_of(p, inv_dx, xa, &s);
+        double frac = orc_volume(r[i]) * inv_vcell;
+        double m = orc_mass(p, r[i]);
+        for (int c = 0; c < 3; ++c)
+            for (int b = 0; b < 3; ++b)
+                for (int a = 0; a < 3; ++a) {
+                    double w = (s.w[0][a] * s.w[1][b]) * s.w[2][c];
+                    int64_t k = orc_node_index(p, &s, a, b, c);
+                    if (alpha) alpha[k] += w * frac;
+                    if (mom)
+                        for (int d = 0; d < 3; ++d) mom[d * G + k] += w * (m * v[d * n + i]);
+                }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* G2P of fluid velocity and volume fraction (Sec. 5.2; Sec. 5.1 clamp)       */
+/* ------------------------------------------------------------------------ */
+
+/* u_at (3n) = sum_k w u_k; alpha_f (n) = 1 - sum_k w min(alpha_k, alpha_max).
+ * The alpha grid is either fixed point (alpha_fx, 2^-32 units) or real
+ * (alpha_real, cell volumes); exactly one is non-NULL. */
+void orc_g2p(const orc_params *p, int64_t n, const double *x, const double *u, const int64_t *alpha_fx,
+             const double *alpha_real, double *u_at, double *alpha_f)
+{
+    double inv_dx = 1.0 / p->dx;
+    int64_t G = orc_nodes(p);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double xa[3];
+        orc_pos(n, x, i, xa);
+        orc_stencil s;
+        orc_stencil_of(p, inv_dx, xa, &s);
+        double acc[3] = {0.0, 0.0, 0.0}, as = 0.0;
+        for (int c = 0; c < 3; ++c)
+            for (int b = 0; b < 3; ++b)
+                for (int a = 0; a < 3; ++a) {
+                    double w = (s.w[0][a] * s.w[1][b]) * s.w[2][c];
+                    int64_t k = orc_node_index(p, &s, a, b, c);
+                    for (int d = 0; d < 3; ++d) acc[d] += w * u[d * G + k];
+                    double al = alpha_fx ? (double)alpha_fx[k] * ORC_TWOM32 : alpha_real[k];
+                    if (al > p->alpha_max) al = p->alpha_max;
+                    as += w * al;
+                }
+        for (int d = 0; d < 3; ++d) u_at[d * n + i] = acc[d];
+        alpha_f[i] = 1.0 - as;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Drag (Eq. 5b / App. A, Stokes form scaled by alpha_f) and integration      */
+/* ------------------------------------------------------------------------ */
+
+void orc_drag(const orc_params *p, int64_t n, const double *r, const double *v, const double *u_at,
+              const double *alpha_f, double *Fd)
+{
+    double cdrag = (p->c_drag * ORC_C6PI) * p->eta_f;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double beta = (cdrag * r[i]) * alpha_f[i];
+        for (int d = 0; d < 3; ++d) Fd[d * n + i] = beta * (u_at[d * n + i] - v[d * n + i]);
+    }
+}
+
+/* Semi-implicit (symplectic) Euler: v += dt ((Fc + Fd)/m + g); x += dt v. */
+void orc_integrate(const orc_params *p, int64_t n, const double *r, const double *Fc, const double *Fd,
+                   double *x, double *v)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double m = orc_mass(p, r[i]);
+        for (int d = 0; d < 3; ++d) {
+            double a = (Fc[d * n + i] + Fd[d * n + i]) / m + p->g[d];
+            v[d * n + i] = v[d * n + i] + p->dt * a;
+            x[d * n + i] = x[d * n + i] + p->dt * v[d * n + i];
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* One step of the granule path (Alg. 2, one sub-step)                       */
+/* ------------------------------------------------------------------------ */
+
+/* In: x, v (x^n, v^n), r, u grid (3G), alpha_fx = P2G(x^n) (G, fixed point).
+ * Out: x, v = x^{n+1}, v^{n+1}; alpha_fx, mom_fx = P2G(x^{n+1}, v^{n+1});
+ * Fc, Fd, u_at, alpha_f (optional, may be NULL) the intermediates. */
+void orc_step(const orc_params *p, int64_t n, double *x, double *v, const double *r, const double *u,
+              int64_t *alpha_fx, int64_t *mom_fx, double *Fc_out, double *Fd_out, double *uat_out,
+              double *af_out)
+{
+    int64_t G = orc_nodes(p);
+    double *Fc = Fc_out ? Fc_out : (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    double *Fd = Fd_out ? Fd_out : (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    double *uat = uat_out ? uat_out : (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    double *af = af_out ? af_out : (double *)malloc(sizeof(double) * (size_t)n);
+    orc_g2p(p, n, x, u, alpha_fx, NULL, uat, af);
+    orc_drag(p, n, r, v, uat, af, Fd);
+    orc_contact_forces(p, n, x, v, r, Fc, NULL, NULL, NULL);
+    orc_integrate(p, n, r, Fc, Fd, x, v);
+    memset(alpha_fx, 0, sizeof(int64_t) * (size_t)G);
+    memset(mom_fx, 0, sizeof(int64_t) * 3 * (size_t)G);
+    orc_p2g_fixed(p, n, x, v, r, alpha_fx, mom_fx);
+    if (!Fc_out) free(Fc);
+    if (!Fd_out) free(Fd);
+    if (!uat_out) free(uat);
+    if (!af_out) free(af);
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_set_num_threads(int t)
+{
+#ifdef _OPENMP
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}
