@@ -1,0 +1,208 @@
+"""Throughput of the granule hot path on one MI355X.
+
+One step = one sand sub-step (Alg. 2) through the C ABI: cell sort, reorder,
+G2P, drag, contact, integration and P2G, on the c3 workload (dam-break
+column, 4,194,304 granules, 256x128x128 grid), FP32 form; the plain FP64 GPU
+path is timed the same way.  Inputs are resident in HBM before timing.
+
+Prints ONE JSON line (rank 0, N=1):
+  value         granule-steps/s of the FP32 form (whole step)
+  fp64_value    granule-steps/s of the plain FP64 path
+  roofline      dominant kernel: algorithmic bytes per launch / its average
+                duration from HIP events on its own stream, vs 8 TB/s
+  cpu_baseline  the FP64 CPU oracle on this host's cores, bounded sample
+
+    python bench.py [--steps K] [--warmup W] [--workload c3] [--no-cpu]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# Algorithmic bytes per granule (and per touched grid node) of each stage in
+# the FP32 form: the arrays the method itself must read and write once,
+# neighbour re-reads and scratch excluded.  B = size of the real type.
+def stage_bytes(stage, n, nodes, real_bytes):
+    B = real_bytes
+    per = {
+        "sort": 24 + 4 + 4,                  # read x, write key, write order
+        "reorder": 4 + 2 * (24 + 24 + 8 + 4),  # read order, gather + write x, v, r, id
+        "g2p": 24 + 3 * B + B,               # read x, write u_at, alpha_f (+ grid below)
+        "drag": 8 + 24 + 3 * B + B + 3 * B,  # read r, v, u_at, alpha_f; write F_d
+        "contact": 24 + 24 + 8 + 3 * B,      # read x, v, r; write F_c
+        "integrate": 8 + 3 * B + 3 * B + 2 * (24 + 24),  # read r, F_c, F_d; read+write x, v
+        "p2g": 24 + 24 + 8,                  # read x, v, r (+ grid writes below)
+    }[stage]
+    grid = {"g2p": 3 * B + 8, "p2g": 8 + 24}.get(stage, 0)
+    return per * n + grid * nodes
+
+
+def time_steps(sim, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        sim.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record()
+    sim.step(steps)
+    end.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return start.elapsed_time(end) / 1e3, t1 - t0
+
+
+def time_stages(sim, steps):
+    """Per-stage times from HIP events recorded on the stream the stages are
+    launched on (torch's current stream), between separate C-ABI calls."""
+    import torch
+    from paper_2504_00745_amd import gic
+    ctx, s = sim.ctx, sim.scratch
+    names = ["sort", "reorder", "g2p", "drag", "contact", "integrate", "p2g"]
+    acc = {k: 0.0 for k in names}
+    for _ in range(steps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
+        cur, nxt = sim.cur, sim.nxt
+        ev[0].record()
+        gic.gic_sort_cells(ctx, cur["x"], s["key"], s["order"], s["cell_begin"], s["cell_end"])
+        ev[1].record()
+        gic.gic_reorder(ctx, s["order"], cur["x"], cur["v"], cur["r"], cur["id"], nxt["x"], nxt["v"], nxt["r"],
+                        nxt["id"])
+        ev[2].record()
+        gic.gic_g2p(ctx, nxt["x"], sim.u, sim.alpha, None, s["u_at"], s["alpha_f"])
+        ev[3].record()
+        gic.gic_drag(ctx, nxt["r"], nxt["v"], s["u_at"], s["alpha_f"], s["f_drag"])
+        ev[4].record()
+        gic.gic_contact_forces(ctx, nxt["x"], nxt["v"], nxt["r"], s["cell_begin"], s["cell_end"], s["f_contact"])
+        ev[5].record()
+        gic.gic_integrate(ctx, nxt["r"], s["f_contact"], s["f_drag"], nxt["x"], nxt["v"])
+        ev[6].record()
+        gic.gic_p2g(ctx, nxt["x"], nxt["v"], nxt["r"], s["cell_begin"], s["cell_end"], sim.alpha, sim.mom)
+        ev[7].record()
+        sim.cur, sim.nxt = nxt, cur
+        torch.cuda.synchronize()
+        for i, k in enumerate(names):
+            acc[k] += ev[i].elapsed_time(ev[i + 1]) / 1e3
+    return {k: v / steps for k, v in acc.items()}
+
+
+def touched_nodes(sim):
+    import torch
+    return int((sim.alpha != 0).sum().item())
+
+
+def cpu_baseline(d, steps):
+    """The FP64 oracle as it stands, on this host's cores, for a bounded
+    number of steps of the same workload."""
+    import oracle
+    cfg = d["params"]
+    x, v, r, u = d["x"], d["v"], d["r"], d["u"]
+    a0, _ = oracle.p2g_fixed(cfg, x, v, r)
+    t0 = time.perf_counter()
+    st = None
+    for _ in range(steps):
+        st = oracle.step(cfg, x, v, r, u, a0)
+        x, v, a0 = st["x"], st["v"], st["alpha"]
+    dt = time.perf_counter() - t0
+    n = x.shape[1]
+    return dict(value=n * steps / dt, unit="granule-steps/s", cores=oracle.num_threads(), kind="oracle",
+                sample=f"{steps} full steps of the {d['name']} workload ({n} granules), FP64 C oracle with OpenMP",
+                seconds=round(dt, 3))
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported by this build "
+              "(multi-GPU sharding is a design note, not code).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2504_00745_amd import gic, workloads as wl
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    log(f"[bench] generating {a.workload}")
+    d = wl.make(a.workload)
+    n = d["x"].shape[1]
+    G = int(np.prod(d["params"]["n"]))
+    rmax = float(d["r"].max())
+    out = {}
+    for prec in (["fp32"] if a.no_fp64 else ["fp32", "fp64"]):
+        log(f"[bench] {prec}: building state")
+        sim = gic.Simulator(d["params"], d["x"], d["v"], d["r"], d["u"], prec, r_max=rmax)
+        log(f"[bench] {prec}: timing {a.steps} steps after {a.warmup} warmup")
+        t_ev, t_wall = time_steps(sim, a.steps, a.warmup)
+        code, idx = sim.ctx.error()
+        if code:
+            log(f"[bench] {prec}: kernel error latched: code {code} index {idx}")
+        stages = time_stages(sim, max(3, min(a.steps, 10)))
+        nodes = touched_nodes(sim)
+        out[prec] = dict(t=t_ev, wall=t_wall, stages=stages, nodes=nodes, err=code)
+        log(f"[bench] {prec}: {t_ev / a.steps * 1e3:.3f} ms/step  stages(ms) " +
+            " ".join(f"{k}={v * 1e3:.3f}" for k, v in stages.items()))
+        del sim
+        torch.cuda.empty_cache()
+    r32 = out["fp32"]
+    value = n * a.steps / r32["t"]
+    # dominant kernel of the FP32 step
+    st = r32["stages"]
+    dom = max(st, key=st.get)
+    abytes = stage_bytes(dom, n, r32["nodes"], 4)
+    achieved = abytes / st[dom] / 1e9
+    line = {
+        "metric": "granule-steps/s FP32 vs plain FP64 GPU path at 4M granules; bwd/fwd time",
+        "value": value,
+        "unit": "granule-steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": r32["t"] / a.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 forces / f64 state / i64 grids",
+        "data": "synthetic",
+        "config": {"workload": f"{a.workload}: dam-break column, {n} granules r=1 mm, {d['params']['n']} grid "
+                               f"dx={d['params']['dx']}, dt={d['params']['dt']}", "granules": n, "grid_nodes": G,
+                   "parallelism": "single GPU"},
+        "stages_ms": {k: round(v * 1e3, 4) for k, v in st.items()},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes": abytes},
+    }
+    if "fp64" in out:
+        r64 = out["fp64"]
+        line["fp64_value"] = n * a.steps / r64["t"]
+        line["fp32_over_fp64"] = line["value"] / line["fp64_value"]
+        line["fp64_stages_ms"] = {k: round(v * 1e3, 4) for k, v in r64["stages"].items()}
+    line["bwd_fwd"] = None
+    if not a.no_cpu:
+        log(f"[bench] cpu baseline: {a.cpu_steps} oracle steps")
+        line["cpu_baseline"] = cpu_baseline(d, a.cpu_steps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,233 @@
+/*
+ * gic.h -- C ABI of the Granule-In-Cell granule hot path for AMD MI355X
+ * (gfx950).
+ *
+ * Paper: Tang, Zhu, Ni, Chen, "The Granule-In-Cell Method for Simulating
+ * Sand-Water Mixtures", ACM TOG 44(6) 2025 (arXiv 2504.00745).
+ *
+ * One call of each stage below, in the order
+ *     gic_sort_cells -> gic_reorder -> gic_g2p -> gic_drag ->
+ *     gic_contact_forces -> gic_integrate -> gic_p2g
+ * is one sand sub-step of Alg. 2 (SandSubstep): coupling force from the grid
+ * (Sec. 5.2), collision handling (Sec. 3.1, Eq. 1), move (Sec. 4, symplectic
+ * ordering), and the transfer of the granules' volume fraction (Sec. 5.1,
+ * Eq. 7a) and momentum to the grid.  gic_step runs the same sub-step through
+ * the same kernels in one call.
+ *
+ * Conventions
+ *   Memory.   Every array argument is a DEVICE pointer owned by the caller.
+ *             The library never frees or keeps it beyond the work the call
+ *             enqueues.  The context owns only its scratch (sort buffers,
+ *             error word), allocated by gic_create for n_max granules; no
+ *             stage call allocates.
+ *   Streams.  `stream` is a hipStream_t passed as void* (NULL = the null
+ *             stream).  Stage calls only enqueue work on it and never
+ *             synchronise; gic_get_error and gic_destroy do.
+ *   Layout.   Per-granule 3-vectors are structure of arrays: a[0..n) holds x
+ *             components, a[n..2n) y, a[2n..3n) z.  Grid fields are
+ *             x-fastest: node (i,j,k) at i + nx (j + ny k), node centre at
+ *             ((i+1/2) dx, (j+1/2) dx, (k+1/2) dx); a 3-vector grid field is
+ *             three consecutive G-node planes (G = nx ny nz).  The box is
+ *             [0, n_a dx) per axis.
+ *   Types.    Positions, velocities and radii are always double.  "real"
+ *             arrays (forces, fluid velocity, sampled velocity and fraction)
+ *             are float in the FP32 form (precision GIC_FP32) and double in
+ *             the plain form (GIC_FP64).  Fixed-point grids are int64.
+ *   Sorted order.  gic_contact_forces and gic_p2g take granules in the order
+ *             produced by gic_reorder from the `order` of gic_sort_cells on
+ *             those same positions, with the cell tables of that sort.
+ *             Granules that moved after the sort (gic_p2g after
+ *             gic_integrate) are still handled exactly; only speed depends on
+ *             the order.
+ *   Errors.   Calls return gic_status and never print, throw or abort.
+ *             Argument errors (NULL, n < 0 or n > n_max, bad parameters) are
+ *             detected on the host and return GIC_E_ARG before anything is
+ *             enqueued.  A failed launch returns GIC_E_HIP.  Conditions found
+ *             by the kernels (a non-finite position or velocity, a granule
+ *             centre outside the box, a radius above r_max, a fixed-point
+ *             value out of range) latch the first code and granule index in
+ *             the context; gic_get_error reads them.
+ *   Threads.  A context is used by one host thread and one stream at a time.
+ */
+#ifndef GIC_H
+#define GIC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GIC_OK = 0,
+    GIC_E_ARG = 1,       /* invalid argument, nothing enqueued            */
+    GIC_E_HIP = 2,       /* HIP runtime or launch failure                 */
+    GIC_E_ALLOC = 3,     /* device allocation failed in gic_create        */
+    GIC_E_DOMAIN = 4,    /* latched: granule centre outside the box       */
+    GIC_E_NONFINITE = 5, /* latched: non-finite position or velocity      */
+    GIC_E_RANGE = 6      /* latched: radius > r_max, or a fixed-point
+                            contribution of magnitude >= 2^51 units      */
+} gic_status;
+
+typedef enum { GIC_FP64 = 0, GIC_FP32 = 1 } gic_precision;
+
+/* Parameters of the granule step.
+ *   n[3], dx      grid nodes per axis and spacing [m]; nodes at cell centres
+ *                 (Sec. 5.1: fractions "computed at the grid cell centers").
+ *   nc[3], cell   neighbour-search cells per axis and their edge [m];
+ *                 cell >= 2 r_max and nc[a] cell <= n[a] dx; the last cell
+ *                 of an axis extends to the box face.
+ *   kn            normal stiffness k_n of Eq. (1a) [N/m].
+ *   restitution   e in (0,1]: the normal dashpot gamma_n = 2 zeta
+ *                 sqrt(m_eff k_n), zeta = -ln e / sqrt(pi^2 + ln^2 e).
+ *   kt_ratio      k_t of Eq. (1c) = kt_ratio * gamma_n [N s/m].
+ *   mu            tan(phi) of Eq. (1b); the cap is mu k_n delta.
+ *   rho_s         granule density [kg/m^3] (Sec. 6: 2.5e3).
+ *   eta_f, c_drag drag F_d = c_drag 6 pi eta_f r alpha_f (u - v) (Eq. 5b,
+ *                 App. A relaxation drag in Stokes form).
+ *   alpha_max     node clamp of alpha_s (Sec. 5.1: 0.740 in 3D).
+ *   g[3], dt      gravity [m/s^2] and step [s].
+ *   r_max         largest granule radius that will be passed [m].
+ *   walls         bit 2a: wall on the low face of axis a; bit 2a+1: high.
+ *   precision     gic_precision. */
+typedef struct gic_params {
+    int32_t n[3];
+    int32_t pad0;
+    double dx;
+    int32_t nc[3];
+    int32_t pad1;
+    double cell;
+    double kn, restitution, kt_ratio, mu;
+    double rho_s, eta_f, c_drag, alpha_max;
+    double g[3];
+    double dt;
+    double r_max;
+    uint32_t walls;
+    int32_t precision;
+} gic_params;
+
+typedef struct gic_ctx gic_ctx;
+
+/* Number of neighbour-cell keys K: the length of cell_begin / cell_end.
+ * Keys order cells in bricks of 4x4x4, bricks x-fastest, cells x-fastest
+ * inside a brick.  Returns -1 for invalid parameters. */
+int64_t gic_key_space(const gic_params *p);
+
+/* Create a context on the current HIP device for up to n_max granules;
+ * allocates the sort scratch and the error word.  *out is set on success. */
+gic_status gic_create(const gic_params *p, int64_t n_max, gic_ctx **out);
+
+/* Replace the parameters (same grid, cells and precision; e.g. mu, c_drag,
+ * dt).  Returns GIC_E_ARG if the grid, cells or precision change. */
+gic_status gic_set_params(gic_ctx *ctx, const gic_params *p);
+
+/* Synchronise the device and free the context's scratch. */
+gic_status gic_destroy(gic_ctx *ctx);
+
+/* Synchronise `stream` and read the latched error: *code = 0 or a
+ * gic_status, *index = the first granule index that raised it (-1 if none).
+ * clear != 0 resets the latch. */
+gic_status gic_get_error(gic_ctx *ctx, void *stream, int32_t *code, int64_t *index, int32_t clear);
+
+/* ---- a1: binning and stable radix sort -----------------------------------
+ * Neighbour search support for the contact test of Sec. 3.1.
+ *   x           3n positions (any order).
+ *   key         out, n: cell key of granule i, cell coordinate per axis
+ *               clamp(floor(x / cell), 0, nc - 1).
+ *   order       out, n: order[q] = index of the granule at sorted position q;
+ *               a stable sort by key (ties in input order).
+ *   cell_begin, cell_end   out, K each: sorted positions [begin, end) of the
+ *               granules of each key; empty cells hold begin = end = 0. */
+gic_status gic_sort_cells(gic_ctx *ctx, int64_t n, const double *x, uint32_t *key, int32_t *order,
+                          int32_t *cell_begin, int32_t *cell_end, void *stream);
+
+/* Gather granule arrays into sorted order: out[q] = in[order[q]] for x, v
+ * (3n each) and r, id (n each).  id / id_out may both be NULL.  Outputs must
+ * not alias inputs. */
+gic_status gic_reorder(gic_ctx *ctx, int64_t n, const int32_t *order, const double *x, const double *v,
+                       const double *r, const int32_t *id, double *x_out, double *v_out, double *r_out,
+                       int32_t *id_out, void *stream);
+
+/* ---- a2 + a3: contact forces (Sec. 3.1, Eq. 1a-c) -------------------------
+ * Granules i, j touch iff d^2 < (r_i + r_j)^2 in double with d^2 =
+ * (dx*dx + dy*dy) + dz*dz.  Per pair: n = x_ij / d, delta = r_i + r_j - d,
+ * v_n = v_ij . n, F_n = (k_n delta - gamma_n v_n) n, f_t = -k_t (v_ij - v_n
+ * n), F_t = f_t capped to mu k_n delta along f_t.  Enabled box walls act as
+ * infinite-mass partners with the same law.  Positions, overlaps and the
+ * contact test are double in both forms; the pair force arithmetic and the
+ * per-granule sum are in the form's real type.
+ *   x, v, r     sorted order (see Conventions).
+ *   f_contact   out, 3n real: force per granule [N].
+ *   n_contacts  out (optional, NULL = skip), n: touching partners + walls. */
+gic_status gic_contact_forces(gic_ctx *ctx, int64_t n, const double *x, const double *v, const double *r,
+                              const int32_t *cell_begin, const int32_t *cell_end, void *f_contact,
+                              int32_t *n_contacts, void *stream);
+
+/* Touching pairs (q, j) with q < j in sorted positions, for checks of the
+ * neighbour search.  Writes up to cap pairs to pairs[2*k], pairs[2*k+1];
+ * *count (device int64, zeroed by the call) receives the total number. */
+gic_status gic_contact_pairs(gic_ctx *ctx, int64_t n, const double *x, const double *r,
+                             const int32_t *cell_begin, const int32_t *cell_end, int32_t *pairs, int64_t cap,
+                             int64_t *count, void *stream);
+
+/* ---- a5: G2P of fluid velocity and fraction (Sec. 5.2; Sec. 5.1 clamp) ----
+ * Quadratic B-spline on cell-centred nodes, out-of-range nodes folded onto
+ * the edge node.  u_at = sum_k w_k u_k; alpha_f = 1 - sum_k w_k min(alpha_k,
+ * alpha_max) with alpha_k = alpha_fx[k] 2^-32 (fixed point) or alpha_real[k]
+ * (cell volumes); exactly one of alpha_fx, alpha_real is non-NULL.
+ *   u           3G real fluid velocity at the nodes [m/s].
+ *   u_at        out, 3n real;  alpha_f  out, n real. */
+gic_status gic_g2p(gic_ctx *ctx, int64_t n, const double *x, const void *u, const int64_t *alpha_fx,
+                   const double *alpha_real, void *u_at, void *alpha_f, void *stream);
+
+/* ---- a6: drag (Eq. 5b, App. A) ---------------------------------------------
+ * f_drag = c_drag 6 pi eta_f r alpha_f (u_at - v), all real, 3n out. */
+gic_status gic_drag(gic_ctx *ctx, int64_t n, const double *r, const double *v, const void *u_at,
+                    const void *alpha_f, void *f_drag, void *stream);
+
+/* ---- a7: integration (Sec. 4, semi-implicit Euler, double) ----------------
+ * v += dt ((f_contact + f_drag) / m + g); x += dt v, with m = rho_s 4/3 pi
+ * r^3.  x and v are updated in place.  f_drag may be NULL (no drag). */
+gic_status gic_integrate(gic_ctx *ctx, int64_t n, const double *r, const void *f_contact, const void *f_drag,
+                         double *x, double *v, void *stream);
+
+/* ---- a4: P2G of volume fraction and momentum (Sec. 5.1, Eq. 7a) ------------
+ * Fixed point: alpha in 2^-32 cell volumes, momentum in 2^-32 rho_s dx^3
+ * (1 m/s) units.  Per granule and channel the total is Q = rint(S) with
+ * S = frac 2^32 (alpha) or (frac v_c) 2^32 (momentum), frac = (4/3 pi r^3)
+ * / dx^3; each of the 26 outer stencil nodes takes rint(w S) (round half to
+ * even) and the centre node takes Q minus their sum, so every granule
+ * deposits exactly Q.  Integer sums make the grid independent of the order
+ * of accumulation.
+ *   alpha_fx    G int64, mom_fx 3G int64 (mom_fx may be NULL).
+ *   accumulate  0: the grids are cleared first; 1: added to. */
+gic_status gic_p2g(gic_ctx *ctx, int64_t n, const double *x, const double *v, const double *r,
+                   const int32_t *cell_begin, const int32_t *cell_end, int64_t *alpha_fx, int64_t *mom_fx,
+                   int32_t accumulate, void *stream);
+
+/* Unquantised P2G for the differentiable form: alpha in cell volumes
+ * (sum w frac), momentum in kg m/s (sum w m v), double; accumulation order is
+ * not fixed, so results agree with a sequential sum to rounding only. */
+gic_status gic_p2g_real(gic_ctx *ctx, int64_t n, const double *x, const double *v, const double *r,
+                        const int32_t *cell_begin, const int32_t *cell_end, double *alpha, double *mom,
+                        int32_t accumulate, void *stream);
+
+/* ---- one full sub-step -------------------------------------------------------
+ * Sort, reorder, G2P (alpha_fx at the current positions, as left by the
+ * previous step's P2G), drag, contact, integrate, P2G.  The granule state
+ * is double-buffered: x, v, r, id are read from the `cur` arrays and written,
+ * advanced and in the new sorted order, to the `nxt` arrays (same sizes);
+ * the caller swaps them.  alpha_fx is read, then overwritten with the
+ * fraction at the new positions; mom_fx receives the new momentum.
+ * Scratch arrays (caller-owned): key, order (n int32), cell_begin, cell_end
+ * (K int32), f_contact, f_drag, u_at (3n real), alpha_f (n real). */
+gic_status gic_step(gic_ctx *ctx, int64_t n, const double *x_cur, const double *v_cur, const double *r_cur,
+                    const int32_t *id_cur, double *x_nxt, double *v_nxt, double *r_nxt, int32_t *id_nxt,
+                    const void *u, int64_t *alpha_fx, int64_t *mom_fx, uint32_t *key, int32_t *order,
+                    int32_t *cell_begin, int32_t *cell_end, void *f_contact, void *f_drag, void *u_at,
+                    void *alpha_f, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GIC_H */

@@ -1,0 +1,329 @@
+// C ABI of the granule path (include/gic.h): argument checks, context and
+// scratch management, and the launch sequence of one sub-step (Alg. 2).
+#include <math.h>
+#include <string.h>
+
+#include "../../include/gic.h"
+#include "gic_launch.hpp"
+
+using namespace gic;
+
+struct gic_ctx {
+    gic_params p;
+    DevParams dp;
+    int64_t n_max;
+    int64_t K;
+    SortScratch sort;
+    int64_t *err;  // device: [code, index]
+    int device;
+};
+
+namespace {
+
+int64_t key_space_of(const gic_params *p)
+{
+    int64_t nb[3];
+    for (int a = 0; a < 3; ++a) nb[a] = (p->nc[a] + kBrick - 1) / kBrick;
+    return nb[0] * nb[1] * nb[2] * kBrickCells;
+}
+
+bool params_valid(const gic_params *p)
+{
+    if (!p) return false;
+    for (int a = 0; a < 3; ++a) {
+        if (p->n[a] < 1 || p->nc[a] < 1) return false;
+        if ((double)p->nc[a] * p->cell > (double)p->n[a] * p->dx * (1.0 + 1e-12)) return false;
+    }
+    if (!(p->dx > 0.0) || !(p->cell > 0.0) || !isfinite(p->dx) || !isfinite(p->cell)) return false;
+    if (!(p->r_max > 0.0) || p->cell < 2.0 * p->r_max) return false;
+    if (!(p->kn > 0.0) || !(p->restitution > 0.0) || !(p->restitution <= 1.0)) return false;
+    if (!(p->kt_ratio >= 0.0) || !(p->mu >= 0.0) || !(p->rho_s > 0.0)) return false;
+    if (!(p->eta_f >= 0.0) || !(p->c_drag >= 0.0) || !(p->alpha_max > 0.0) || !(p->dt > 0.0)) return false;
+    for (int a = 0; a < 3; ++a)
+        if (!isfinite(p->g[a])) return false;
+    if (p->precision != GIC_FP64 && p->precision != GIC_FP32) return false;
+    if (p->walls > 0x3Fu) return false;
+    const int64_t K = key_space_of(p);
+    if (K > ((int64_t)1 << 32) || (int64_t)p->n[0] * p->n[1] * p->n[2] > ((int64_t)1 << 40)) return false;
+    return true;
+}
+
+// Edge of the P2G LDS tile: the nodes touched by a brick's granules plus one
+// node of slack on each side.
+int tile_edge(const gic_params *p)
+{
+    return (int)ceil((double)kBrick * p->cell / p->dx - 1e-9) + 3;
+}
+
+DevParams derive(const gic_params *p)
+{
+    DevParams d;
+    memset(&d, 0, sizeof(d));
+    for (int a = 0; a < 3; ++a) {
+        d.n[a] = p->n[a];
+        d.nc[a] = p->nc[a];
+        d.nb[a] = (p->nc[a] + kBrick - 1) / kBrick;
+        d.L[a] = (double)p->n[a] * p->dx;
+        d.g[a] = p->g[a];
+    }
+    d.tile = tile_edge(p);
+    d.G = (int64_t)p->n[0] * p->n[1] * p->n[2];
+    d.dx = p->dx;
+    d.inv_dx = 1.0 / p->dx;
+    d.inv_vcell = 1.0 / ((p->dx * p->dx) * p->dx);
+    d.cell = p->cell;
+    d.inv_cell = 1.0 / p->cell;
+    d.kn = p->kn;
+    const double le = log(p->restitution);
+    d.zeta = -le / sqrt(GIC_PI * GIC_PI + le * le);
+    d.kt_ratio = p->kt_ratio;
+    d.mu = p->mu;
+    d.rho_s = p->rho_s;
+    d.cdrag = (p->c_drag * (6.0 * GIC_PI)) * p->eta_f;
+    d.alpha_max = p->alpha_max;
+    d.dt = p->dt;
+    d.r_max = p->r_max;
+    d.search_scale = 1.0 + 1.0 / 1073741824.0;  // 1 + 2^-30: slack for rounding
+    d.walls = p->walls;
+    return d;
+}
+
+int sort_passes(int64_t K)
+{
+    int bits = 1;
+    while (bits < 32 && ((int64_t)1 << bits) < K) ++bits;
+    return (bits + 7) / 8;
+}
+
+gic_status hip_status(hipError_t e) { return e == hipSuccess ? GIC_OK : GIC_E_HIP; }
+
+bool fp32(const gic_ctx *c) { return c->p.precision == GIC_FP32; }
+
+bool n_ok(const gic_ctx *c, int64_t n) { return c && n >= 0 && n <= c->n_max; }
+
+}  // namespace
+
+extern "C" {
+
+int64_t gic_key_space(const gic_params *p) { return params_valid(p) ? key_space_of(p) : -1; }
+
+gic_status gic_create(const gic_params *p, int64_t n_max, gic_ctx **out)
+{
+    if (!out || !params_valid(p) || n_max < 0 || n_max > ((int64_t)1 << 31) - 1) return GIC_E_ARG;
+    *out = nullptr;
+    const int E = tile_edge(p);
+    if ((size_t)E * E * E * 4 * sizeof(double) > 65536) return GIC_E_ARG;  // P2G tile must fit in LDS
+    gic_ctx *c = new gic_ctx;
+    memset(c, 0, sizeof(*c));
+    c->p = *p;
+    c->dp = derive(p);
+    c->n_max = n_max;
+    c->K = key_space_of(p);
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return GIC_E_HIP;
+    }
+    const int64_t nn = n_max > 0 ? n_max : 1;
+    const int64_t tiles = (nn + kSortTile - 1) / kSortTile;
+    c->sort.tiles_max = tiles;
+    c->sort.passes = sort_passes(c->K);
+    bool ok = true;
+    ok &= hipMalloc(&c->sort.kA, sizeof(uint32_t) * nn) == hipSuccess;
+    ok &= hipMalloc(&c->sort.kB, sizeof(uint32_t) * nn) == hipSuccess;
+    ok &= hipMalloc(&c->sort.skeys, sizeof(uint32_t) * nn) == hipSuccess;
+    ok &= hipMalloc(&c->sort.vA, sizeof(int32_t) * nn) == hipSuccess;
+    ok &= hipMalloc(&c->sort.vB, sizeof(int32_t) * nn) == hipSuccess;
+    ok &= hipMalloc(&c->sort.hist, sizeof(uint32_t) * 256 * tiles) == hipSuccess;
+    ok &= hipMalloc(&c->err, sizeof(int64_t) * 2) == hipSuccess;
+    if (ok) ok = hipMemset(c->err, 0, sizeof(int64_t) * 2) == hipSuccess;
+    if (!ok) {
+        gic_destroy(c);
+        return GIC_E_ALLOC;
+    }
+    *out = c;
+    return GIC_OK;
+}
+
+gic_status gic_set_params(gic_ctx *c, const gic_params *p)
+{
+    if (!c || !params_valid(p)) return GIC_E_ARG;
+    for (int a = 0; a < 3; ++a)
+        if (p->n[a] != c->p.n[a] || p->nc[a] != c->p.nc[a]) return GIC_E_ARG;
+    if (p->dx != c->p.dx || p->cell != c->p.cell || p->precision != c->p.precision) return GIC_E_ARG;
+    c->p = *p;
+    c->dp = derive(p);
+    return GIC_OK;
+}
+
+gic_status gic_destroy(gic_ctx *c)
+{
+    if (!c) return GIC_E_ARG;
+    hipError_t e = hipDeviceSynchronize();
+    (void)hipFree(c->sort.kA);
+    (void)hipFree(c->sort.kB);
+    (void)hipFree(c->sort.skeys);
+    (void)hipFree(c->sort.vA);
+    (void)hipFree(c->sort.vB);
+    (void)hipFree(c->sort.hist);
+    (void)hipFree(c->err);
+    delete c;
+    return hip_status(e);
+}
+
+gic_status gic_get_error(gic_ctx *c, void *stream, int32_t *code, int64_t *index, int32_t clear)
+{
+    if (!c || !code || !index) return GIC_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    int64_t h[2] = {0, -1};
+    hipError_t e = hipMemcpyAsync(h, c->err, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return GIC_E_HIP;
+    *code = (int32_t)h[0];
+    *index = h[0] ? h[1] : -1;
+    if (clear) {
+        e = hipMemsetAsync(c->err, 0, sizeof(int64_t) * 2, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
+    return hip_status(e);
+}
+
+gic_status gic_sort_cells(gic_ctx *c, int64_t n, const double *x, uint32_t *key, int32_t *order,
+                          int32_t *cell_begin, int32_t *cell_end, void *stream)
+{
+    if (!n_ok(c, n) || !cell_begin || !cell_end || (n > 0 && (!x || !key || !order))) return GIC_E_ARG;
+    return hip_status(launch_sort_cells(c->dp, n, x, key, order, cell_begin, cell_end, c->K, c->sort, c->err,
+                                        (hipStream_t)stream));
+}
+
+gic_status gic_reorder(gic_ctx *c, int64_t n, const int32_t *order, const double *x, const double *v,
+                       const double *r, const int32_t *id, double *x_out, double *v_out, double *r_out,
+                       int32_t *id_out, void *stream)
+{
+    if (!n_ok(c, n)) return GIC_E_ARG;
+    if (n > 0 && (!order || !x || !v || !r || !x_out || !v_out || !r_out)) return GIC_E_ARG;
+    if ((id == nullptr) != (id_out == nullptr)) return GIC_E_ARG;
+    if (n > 0 && (x_out == x || v_out == v || r_out == r || (id && id_out == id))) return GIC_E_ARG;
+    return hip_status(launch_reorder(n, order, x, v, r, id, x_out, v_out, r_out, id_out, (hipStream_t)stream));
+}
+
+gic_status gic_contact_forces(gic_ctx *c, int64_t n, const double *x, const double *v, const double *r,
+                              const int32_t *cell_begin, const int32_t *cell_end, void *f_contact,
+                              int32_t *n_contacts, void *stream)
+{
+    if (!n_ok(c, n)) return GIC_E_ARG;
+    if (n > 0 && (!x || !v || !r || !cell_begin || !cell_end || !f_contact)) return GIC_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (fp32(c))
+        return hip_status(launch_contact<float>(c->dp, n, x, v, r, cell_begin, cell_end, (float *)f_contact,
+                                                n_contacts, c->err, s));
+    return hip_status(launch_contact<double>(c->dp, n, x, v, r, cell_begin, cell_end, (double *)f_contact,
+                                             n_contacts, c->err, s));
+}
+
+gic_status gic_contact_pairs(gic_ctx *c, int64_t n, const double *x, const double *r, const int32_t *cell_begin,
+                             const int32_t *cell_end, int32_t *pairs, int64_t cap, int64_t *count, void *stream)
+{
+    if (!n_ok(c, n) || !count || cap < 0 || (cap > 0 && !pairs)) return GIC_E_ARG;
+    if (n > 0 && (!x || !r || !cell_begin || !cell_end)) return GIC_E_ARG;
+    return hip_status(
+        launch_contact_pairs(c->dp, n, x, r, cell_begin, cell_end, pairs, cap, count, (hipStream_t)stream));
+}
+
+gic_status gic_g2p(gic_ctx *c, int64_t n, const double *x, const void *u, const int64_t *alpha_fx,
+                   const double *alpha_real, void *u_at, void *alpha_f, void *stream)
+{
+    if (!n_ok(c, n) || ((alpha_fx == nullptr) == (alpha_real == nullptr))) return GIC_E_ARG;
+    if (n > 0 && (!x || !u || !u_at || !alpha_f)) return GIC_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (fp32(c))
+        return hip_status(launch_g2p<float>(c->dp, n, x, (const float *)u, alpha_fx, alpha_real, (float *)u_at,
+                                            (float *)alpha_f, s));
+    return hip_status(launch_g2p<double>(c->dp, n, x, (const double *)u, alpha_fx, alpha_real, (double *)u_at,
+                                         (double *)alpha_f, s));
+}
+
+gic_status gic_drag(gic_ctx *c, int64_t n, const double *r, const double *v, const void *u_at, const void *alpha_f,
+                    void *f_drag, void *stream)
+{
+    if (!n_ok(c, n)) return GIC_E_ARG;
+    if (n > 0 && (!r || !v || !u_at || !alpha_f || !f_drag)) return GIC_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (fp32(c))
+        return hip_status(launch_drag<float>(c->dp, n, r, v, (const float *)u_at, (const float *)alpha_f,
+                                             (float *)f_drag, s));
+    return hip_status(launch_drag<double>(c->dp, n, r, v, (const double *)u_at, (const double *)alpha_f,
+                                          (double *)f_drag, s));
+}
+
+gic_status gic_integrate(gic_ctx *c, int64_t n, const double *r, const void *f_contact, const void *f_drag,
+                         double *x, double *v, void *stream)
+{
+    if (!n_ok(c, n)) return GIC_E_ARG;
+    if (n > 0 && (!r || !f_contact || !x || !v)) return GIC_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (fp32(c))
+        return hip_status(launch_integrate<float>(c->dp, n, r, (const float *)f_contact, (const float *)f_drag, x,
+                                                  v, s));
+    return hip_status(
+        launch_integrate<double>(c->dp, n, r, (const double *)f_contact, (const double *)f_drag, x, v, s));
+}
+
+gic_status gic_p2g(gic_ctx *c, int64_t n, const double *x, const double *v, const double *r,
+                   const int32_t *cell_begin, const int32_t *cell_end, int64_t *alpha_fx, int64_t *mom_fx,
+                   int32_t accumulate, void *stream)
+{
+    if (!n_ok(c, n) || !alpha_fx) return GIC_E_ARG;
+    if (n > 0 && (!x || !r || !cell_begin || !cell_end || (mom_fx && !v))) return GIC_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t G = c->dp.G;
+    if (!accumulate) {
+        hipError_t e = launch_fill_i64(alpha_fx, G, s);
+        if (e == hipSuccess && mom_fx) e = launch_fill_i64(mom_fx, 3 * G, s);
+        if (e != hipSuccess) return GIC_E_HIP;
+    }
+    return hip_status(launch_p2g_fixed(c->dp, n, c->K, x, v, r, cell_begin, cell_end, alpha_fx, mom_fx, c->err, s));
+}
+
+gic_status gic_p2g_real(gic_ctx *c, int64_t n, const double *x, const double *v, const double *r,
+                        const int32_t *cell_begin, const int32_t *cell_end, double *alpha, double *mom,
+                        int32_t accumulate, void *stream)
+{
+    if (!n_ok(c, n) || (!alpha && !mom)) return GIC_E_ARG;
+    if (n > 0 && (!x || !r || !cell_begin || !cell_end || (mom && !v))) return GIC_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t G = c->dp.G;
+    if (!accumulate) {
+        hipError_t e = alpha ? launch_fill_f64(alpha, G, s) : hipSuccess;
+        if (e == hipSuccess && mom) e = launch_fill_f64(mom, 3 * G, s);
+        if (e != hipSuccess) return GIC_E_HIP;
+    }
+    return hip_status(launch_p2g_real(c->dp, n, c->K, x, v, r, cell_begin, cell_end, alpha, mom, s));
+}
+
+gic_status gic_step(gic_ctx *c, int64_t n, const double *x_cur, const double *v_cur, const double *r_cur,
+                    const int32_t *id_cur, double *x_nxt, double *v_nxt, double *r_nxt, int32_t *id_nxt,
+                    const void *u, int64_t *alpha_fx, int64_t *mom_fx, uint32_t *key, int32_t *order,
+                    int32_t *cell_begin, int32_t *cell_end, void *f_contact, void *f_drag, void *u_at,
+                    void *alpha_f, void *stream)
+{
+    if (!n_ok(c, n) || !alpha_fx || !mom_fx || !cell_begin || !cell_end) return GIC_E_ARG;
+    if (n > 0 && (!x_cur || !v_cur || !r_cur || !x_nxt || !v_nxt || !r_nxt || !u || !key || !order ||
+                  !f_contact || !f_drag || !u_at || !alpha_f))
+        return GIC_E_ARG;
+    if ((id_cur == nullptr) != (id_nxt == nullptr)) return GIC_E_ARG;
+    gic_status st;
+    if ((st = gic_sort_cells(c, n, x_cur, key, order, cell_begin, cell_end, stream)) != GIC_OK) return st;
+    if ((st = gic_reorder(c, n, order, x_cur, v_cur, r_cur, id_cur, x_nxt, v_nxt, r_nxt, id_nxt, stream)) != GIC_OK)
+        return st;
+    // alpha_fx was deposited at the current positions; G2P reads it by node,
+    // so the reorder does not change it.
+    if ((st = gic_g2p(c, n, x_nxt, u, alpha_fx, nullptr, u_at, alpha_f, stream)) != GIC_OK) return st;
+    if ((st = gic_drag(c, n, r_nxt, v_nxt, u_at, alpha_f, f_drag, stream)) != GIC_OK) return st;
+    if ((st = gic_contact_forces(c, n, x_nxt, v_nxt, r_nxt, cell_begin, cell_end, f_contact, nullptr, stream)) !=
+        GIC_OK)
+        return st;
+    if ((st = gic_integrate(c, n, r_nxt, f_contact, f_drag, x_nxt, v_nxt, stream)) != GIC_OK) return st;
+    return gic_p2g(c, n, x_nxt, v_nxt, r_nxt, cell_begin, cell_end, alpha_fx, mom_fx, 0, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,165 @@
+// Device-side definitions shared by the gfx950 kernels of the granule path.
+//
+// Paper: Tang, Zhu, Ni, Chen, "The Granule-In-Cell Method for Simulating
+// Sand-Water Mixtures", ACM TOG 44(6) 2025 (arXiv 2504.00745).
+//
+// Everything that decides an integer (cell keys, the contact test, B-spline
+// weights that feed fixed-point rounding) is written with FMA contraction off,
+// one rounding per operation in the order written, so that these decisions
+// are reproducible operation by operation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gic {
+
+#define GIC_PI 3.14159265358979323846
+#define GIC_C43PI (4.0 * GIC_PI / 3.0)
+#define GIC_TWO32 4294967296.0
+#define GIC_TWOM32 (1.0 / 4294967296.0)
+constexpr int kBrick = 4;                 // cells per brick edge in the key
+constexpr int kBrickCells = kBrick * kBrick * kBrick;
+
+// Latched error codes (same values as gic_status).
+constexpr int kErrDomain = 4;
+constexpr int kErrNonFinite = 5;
+constexpr int kErrRange = 6;
+
+// Parameters as the kernels use them: derived constants precomputed on the
+// host once per context.
+struct DevParams {
+    int32_t n[3];       // grid nodes per axis
+    int32_t nc[3];      // neighbour cells per axis
+    int32_t nb[3];      // bricks per axis
+    int32_t tile;       // P2G LDS tile edge (nodes)
+    int64_t G;          // nodes
+    double dx, inv_dx, inv_vcell;
+    double cell, inv_cell;
+    double L[3];        // box edges n_a dx
+    double kn, zeta, kt_ratio, mu;
+    double rho_s, cdrag;  // cdrag = c_drag 6 pi eta_f
+    double alpha_max;
+    double g[3], dt;
+    double r_max, search_scale;
+    uint32_t walls;
+};
+
+// Latch the first error: code and granule index.
+__device__ inline void raise_error(int64_t *err, int code, int64_t idx)
+{
+    unsigned long long *e = reinterpret_cast<unsigned long long *>(err);
+    if (atomicCAS(e, 0ull, (unsigned long long)code) == 0ull) atomicExch(e + 1, (unsigned long long)idx);
+}
+
+__device__ inline double volume_of(double r)
+{
+#pragma clang fp contract(off)
+    return ((GIC_C43PI * r) * r) * r;
+}
+
+__device__ inline double mass_of(const DevParams &P, double r) { return P.rho_s * volume_of(r); }
+
+// clamp(floor(x / cell), 0, nc - 1); NaN -> 0.
+__device__ inline int32_t cell_coord(double x, double inv_cell, int32_t nc)
+{
+#pragma clang fp contract(off)
+    double t = floor(x * inv_cell);
+    if (!(t >= 0.0)) return 0;
+    if (t > (double)(nc - 1)) return nc - 1;
+    return (int32_t)t;
+}
+
+__device__ inline uint32_t key_of_cell(const DevParams &P, int32_t cx, int32_t cy, int32_t cz)
+{
+    uint32_t brick = (uint32_t)(((cz / kBrick) * P.nb[1] + (cy / kBrick)) * P.nb[0] + (cx / kBrick));
+    uint32_t local = (uint32_t)(((cz % kBrick) * kBrick + (cy % kBrick)) * kBrick + (cx % kBrick));
+    return brick * (uint32_t)kBrickCells + local;
+}
+
+// Quadratic B-spline stencil on cell-centred nodes.  base = floor(t - 1),
+// f = (t - base) - 1/2 in [1/2, 3/2) is the distance to the first node;
+// weights N(f), N(f-1), N(2-f).  Node indices are folded into [0, n-1].
+struct Stencil {
+    int32_t node[3][3];
+    double w[3][3];
+};
+
+__device__ inline void stencil_of(const DevParams &P, const double xa[3], Stencil &s)
+{
+#pragma clang fp contract(off)
+    for (int a = 0; a < 3; ++a) {
+        double t = xa[a] * P.inv_dx;
+        double fb = floor(t - 1.0);
+        double f = (t - fb) - 0.5;
+        double c0 = 1.5 - f, c1 = f - 1.0, c2 = f - 0.5;
+        s.w[a][0] = 0.5 * (c0 * c0);
+        s.w[a][1] = 0.75 - c1 * c1;
+        s.w[a][2] = 0.5 * (c2 * c2);
+        double hi = (double)P.n[a];
+        if (!(fb >= -2.0)) fb = -2.0;
+        if (fb > hi) fb = hi;
+        int32_t b = (int32_t)fb;
+        for (int k = 0; k < 3; ++k) {
+            int32_t id = b + k;
+            id = id < 0 ? 0 : id;
+            id = id > P.n[a] - 1 ? P.n[a] - 1 : id;
+            s.node[a][k] = id;
+        }
+    }
+}
+
+// Derivative of the 1-D weights with respect to x (per metre).
+__device__ inline void stencil_dw(const DevParams &P, const double xa[3], double dw[3][3])
+{
+    for (int a = 0; a < 3; ++a) {
+        double t = xa[a] * P.inv_dx;
+        double fb = floor(t - 1.0);
+        double f = (t - fb) - 0.5;
+        dw[a][0] = -(1.5 - f) * P.inv_dx;
+        dw[a][1] = (-2.0 * (f - 1.0)) * P.inv_dx;
+        dw[a][2] = (f - 0.5) * P.inv_dx;
+    }
+}
+
+__device__ inline int64_t node_index(const DevParams &P, int32_t i, int32_t j, int32_t k)
+{
+    return (int64_t)i + (int64_t)P.n[0] * ((int64_t)j + (int64_t)P.n[1] * k);
+}
+
+// rint (round half to even) to int64 for |v| < 2^51: adding 1.5 * 2^52 puts
+// the value in [2^52, 2^53) where the unit in the last place is 1, so the
+// add itself rounds to an integer; the integer is then the difference of the
+// bit patterns.
+__device__ inline int64_t rint_i64(double v)
+{
+#pragma clang fp contract(off)
+    const double M = 6755399441055744.0;
+    double y = v + M;
+    return __double_as_longlong(y) - __double_as_longlong(M);
+}
+
+constexpr double kFixLimit = 2251799813685248.0;  // 2^51
+
+// Pair (or wall) force of Eq. (1a)-(1c) with the dashpot reading, in real
+// type T.  nh: unit normal from the partner to this granule; delta: overlap;
+// w: relative velocity; meff: effective mass.  Returns 1 if capped.
+template <typename T>
+__device__ inline int pair_force(const DevParams &P, const T nh[3], T delta, const T w[3], T meff, T F[3])
+{
+    const T kn = (T)P.kn;
+    T gam = (T)2 * (T)P.zeta * sqrt(meff * kn);
+    T kt = (T)P.kt_ratio * gam;
+    T vn = (w[0] * nh[0] + w[1] * nh[1]) + w[2] * nh[2];
+    T fn = kn * delta - gam * vn;
+    T ft[3];
+    for (int a = 0; a < 3; ++a) ft[a] = -kt * (w[a] - vn * nh[a]);
+    T fts = sqrt((ft[0] * ft[0] + ft[1] * ft[1]) + ft[2] * ft[2]);
+    T cap = (T)P.mu * (kn * delta);
+    int slide = fts > cap;
+    T s = slide ? cap / fts : (T)1;
+    for (int a = 0; a < 3; ++a) F[a] = fn * nh[a] + ft[a] * s;
+    return slide;
+}
+
+}  // namespace gic

@@ -1,0 +1,64 @@
+// Host-side launchers of the gfx950 kernels (one translation unit per stage
+// family); the C ABI in gic_api.hip validates arguments and calls these.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gic_device.hpp"
+
+namespace gic {
+
+// Sort scratch owned by a context.
+struct SortScratch {
+    uint32_t *kA, *kB, *skeys;
+    int32_t *vA, *vB;
+    uint32_t *hist;     // RADIX x tiles
+    int64_t tiles_max;
+    int passes;         // 8-bit digit passes over the key bits
+};
+
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 8;
+constexpr int kSortTile = kSortThreads * kSortItems;
+
+hipError_t launch_sort_cells(const DevParams &P, int64_t n, const double *x, uint32_t *key, int32_t *order,
+                             int32_t *cell_begin, int32_t *cell_end, int64_t K, SortScratch &S, int64_t *err,
+                             hipStream_t s);
+hipError_t launch_reorder(int64_t n, const int32_t *order, const double *x, const double *v, const double *r,
+                          const int32_t *id, double *xo, double *vo, double *ro, int32_t *ido, hipStream_t s);
+
+template <typename T>
+hipError_t launch_contact(const DevParams &P, int64_t n, const double *x, const double *v, const double *r,
+                          const int32_t *cb, const int32_t *ce, T *F, int32_t *ncont, int64_t *err,
+                          hipStream_t s);
+hipError_t launch_contact_pairs(const DevParams &P, int64_t n, const double *x, const double *r,
+                                const int32_t *cb, const int32_t *ce, int32_t *pairs, int64_t cap,
+                                int64_t *count, hipStream_t s);
+
+template <typename T>
+hipError_t launch_g2p(const DevParams &P, int64_t n, const double *x, const T *u, const int64_t *afx,
+                      const double *are, T *uat, T *af, hipStream_t s);
+template <typename T>
+hipError_t launch_drag(const DevParams &P, int64_t n, const double *r, const double *v, const T *uat, const T *af,
+                       T *Fd, hipStream_t s);
+template <typename T>
+hipError_t launch_integrate(const DevParams &P, int64_t n, const double *r, const T *Fc, const T *Fd, double *x,
+                            double *v, hipStream_t s);
+
+hipError_t launch_fill_i64(int64_t *a, int64_t len, hipStream_t s);
+hipError_t launch_fill_f64(double *a, int64_t len, hipStream_t s);
+hipError_t launch_p2g_fixed(const DevParams &P, int64_t n, int64_t K, const double *x, const double *v,
+                            const double *r, const int32_t *cb, const int32_t *ce, int64_t *alpha, int64_t *mom,
+                            int64_t *err, hipStream_t s);
+hipError_t launch_p2g_real(const DevParams &P, int64_t n, int64_t K, const double *x, const double *v,
+                           const double *r, const int32_t *cb, const int32_t *ce, double *alpha, double *mom,
+                           hipStream_t s);
+
+inline unsigned grid_for(int64_t n, int threads)
+{
+    int64_t b = (n + threads - 1) / threads;
+    return (unsigned)(b < 1 ? 1 : b);
+}
+
+}  // namespace gic

@@ -1,0 +1,321 @@
+// a4 + a5: granule <-> grid transfers with the quadratic B-spline on
+// cell-centred nodes (Sec. 5.1 Eq. 7a; Sec. 5.2 G2P) on gfx950.
+//
+// P2G: one workgroup per brick of 4x4x4 neighbour cells.  Granules of a brick
+// are contiguous in sorted order and their stencils cover a small box of
+// nodes, so their 27-node x 4-channel contributions are first summed in an
+// LDS tile with 64-bit LDS atomics and then added to the grid with one global
+// atomic per touched node and channel.  A contribution whose node falls
+// outside the tile (a granule that moved after the sort) goes straight to a
+// global atomic, so the result never depends on the order.  Fixed-point
+// contributions are integers, so every accumulation order gives the same
+// bits.
+//
+// G2P: one thread per granule, 27 node reads from L1/L2 (sorted granules
+// read overlapping stencils).
+#include "gic_launch.hpp"
+
+namespace gic {
+
+namespace {
+
+constexpr int kP2GThreads = 256;
+
+__global__ void __launch_bounds__(256) k_fill_i64(int64_t *a, int64_t len)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = 0;
+}
+
+__global__ void __launch_bounds__(256) k_fill_f64(double *a, int64_t len)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = 0.0;
+}
+
+// [begin, end) of brick b in sorted order, from the 64 cell ranges of the
+// brick; returned through LDS to the whole workgroup.
+__device__ inline void brick_range(int64_t b, const int32_t *__restrict__ cb, const int32_t *__restrict__ ce,
+                                   int32_t *s_range)
+{
+    if (threadIdx.x < 64) {
+        const int64_t key = b * kBrickCells + threadIdx.x;
+        const int32_t bb = cb[key], ee = ce[key];
+        int32_t lo = ee > bb ? bb : 0x7fffffff;
+        int32_t hi = ee > bb ? ee : 0;
+        for (int off = 32; off > 0; off >>= 1) {
+            int32_t olo = __shfl_xor(lo, off);
+            int32_t ohi = __shfl_xor(hi, off);
+            lo = olo < lo ? olo : lo;
+            hi = ohi > hi ? ohi : hi;
+        }
+        if (threadIdx.x == 0) {
+            s_range[0] = lo;
+            s_range[1] = hi;
+        }
+    }
+}
+
+// Origin of the LDS node tile of brick b: one node below the brick's first
+// node per axis.
+__device__ inline void tile_origin(const DevParams &P, int64_t b, int32_t o[3])
+{
+    const int64_t bx = b % P.nb[0];
+    const int64_t by = (b / P.nb[0]) % P.nb[1];
+    const int64_t bz = b / ((int64_t)P.nb[0] * P.nb[1]);
+    const int64_t bc[3] = {bx, by, bz};
+    for (int a = 0; a < 3; ++a) o[a] = (int32_t)floor((double)(bc[a] * kBrick) * P.cell * P.inv_dx) - 1;
+}
+
+__global__ void __launch_bounds__(kP2GThreads) k_p2g_fixed(DevParams P, int64_t n, const double *__restrict__ x,
+                                                           const double *__restrict__ v,
+                                                           const double *__restrict__ r,
+                                                           const int32_t *__restrict__ cb,
+                                                           const int32_t *__restrict__ ce,
+                                                           unsigned long long *__restrict__ alpha,
+                                                           unsigned long long *__restrict__ mom, int64_t *err)
+{
+#pragma clang fp contract(off)
+    extern __shared__ unsigned long long tile[];
+    __shared__ int32_t s_range[2];
+    const int64_t b = blockIdx.x;
+    brick_range(b, cb, ce, s_range);
+    __syncthreads();
+    const int32_t beg = s_range[0], end = s_range[1];
+    if (end <= beg) return;
+    const int E = P.tile;
+    const int E3 = E * E * E;
+    const int nch = mom ? 4 : 1;
+    for (int k = threadIdx.x; k < nch * E3; k += kP2GThreads) tile[k] = 0ull;
+    int32_t o[3];
+    tile_origin(P, b, o);
+    __syncthreads();
+    const int64_t G = P.G;
+    for (int64_t q = beg + (int64_t)threadIdx.x; q < end; q += kP2GThreads) {
+        const double xa[3] = {x[q], x[n + q], x[2 * n + q]};
+        Stencil s;
+        stencil_of(P, xa, s);
+        const double frac = volume_of(r[q]) * P.inv_vcell;
+        double S[4];
+        S[0] = frac * GIC_TWO32;
+        for (int c = 0; c < 3; ++c) S[c + 1] = mom ? (frac * v[c * n + q]) * GIC_TWO32 : 0.0;
+        bool ok = true;
+        for (int c = 0; c < nch; ++c) ok &= fabs(S[c]) < kFixLimit;
+        if (!ok) {
+            raise_error(err, isfinite(S[0] + S[1] + S[2] + S[3]) ? kErrRange : kErrNonFinite, q);
+            continue;
+        }
+        int64_t rest[4];
+        for (int c = 0; c < nch; ++c) rest[c] = rint_i64(S[c]);
+        for (int cz = 0; cz < 3; ++cz)
+            for (int cy = 0; cy < 3; ++cy)
+                for (int cx = 0; cx < 3; ++cx) {
+                    const bool centre = cx == 1 && cy == 1 && cz == 1;
+                    const double w = (s.w[0][cx] * s.w[1][cy]) * s.w[2][cz];
+                    const int32_t ni = s.node[0][cx], nj = s.node[1][cy], nk = s.node[2][cz];
+                    const int32_t li = ni - o[0], lj = nj - o[1], lk = nk - o[2];
+                    const bool in = li >= 0 && lj >= 0 && lk >= 0 && li < E && lj < E && lk < E;
+                    const int lidx = (lk * E + lj) * E + li;
+                    const int64_t gidx = node_index(P, ni, nj, nk);
+                    for (int c = 0; c < nch; ++c) {
+                        int64_t val;
+                        if (centre) {
+                            continue;
+                        } else {
+                            val = rint_i64(w * S[c]);
+                            rest[c] -= val;
+                        }
+                        if (val == 0) continue;
+                        if (in)
+                            atomicAdd(&tile[c * E3 + lidx], (unsigned long long)val);
+                        else
+                            atomicAdd(c == 0 ? &alpha[gidx] : &mom[(c - 1) * G + gidx], (unsigned long long)val);
+                    }
+                }
+        {
+            const int32_t ni = s.node[0][1], nj = s.node[1][1], nk = s.node[2][1];
+            const int32_t li = ni - o[0], lj = nj - o[1], lk = nk - o[2];
+            const bool in = li >= 0 && lj >= 0 && lk >= 0 && li < E && lj < E && lk < E;
+            const int lidx = (lk * E + lj) * E + li;
+            const int64_t gidx = node_index(P, ni, nj, nk);
+            for (int c = 0; c < nch; ++c) {
+                if (rest[c] == 0) continue;
+                if (in)
+                    atomicAdd(&tile[c * E3 + lidx], (unsigned long long)rest[c]);
+                else
+                    atomicAdd(c == 0 ? &alpha[gidx] : &mom[(c - 1) * G + gidx], (unsigned long long)rest[c]);
+            }
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < nch * E3; k += kP2GThreads) {
+        const unsigned long long val = tile[k];
+        if (val == 0ull) continue;
+        const int c = k / E3;
+        const int l = k - c * E3;
+        const int32_t ni = o[0] + l % E, nj = o[1] + (l / E) % E, nk = o[2] + l / (E * E);
+        const int64_t gidx = node_index(P, ni, nj, nk);
+        atomicAdd(c == 0 ? &alpha[gidx] : &mom[(c - 1) * G + gidx], val);
+    }
+}
+
+__global__ void __launch_bounds__(kP2GThreads) k_p2g_real(DevParams P, int64_t n, const double *__restrict__ x,
+                                                          const double *__restrict__ v,
+                                                          const double *__restrict__ r,
+                                                          const int32_t *__restrict__ cb,
+                                                          const int32_t *__restrict__ ce, double *__restrict__ alpha,
+                                                          double *__restrict__ mom)
+{
+    extern __shared__ double dtile[];
+    __shared__ int32_t s_range[2];
+    const int64_t b = blockIdx.x;
+    brick_range(b, cb, ce, s_range);
+    __syncthreads();
+    const int32_t beg = s_range[0], end = s_range[1];
+    if (end <= beg) return;
+    const int E = P.tile;
+    const int E3 = E * E * E;
+    const bool wa = alpha != nullptr, wm = mom != nullptr;
+    for (int k = threadIdx.x; k < 4 * E3; k += kP2GThreads) dtile[k] = 0.0;
+    int32_t o[3];
+    tile_origin(P, b, o);
+    __syncthreads();
+    const int64_t G = P.G;
+    for (int64_t q = beg + (int64_t)threadIdx.x; q < end; q += kP2GThreads) {
+        const double xa[3] = {x[q], x[n + q], x[2 * n + q]};
+        Stencil s;
+        stencil_of(P, xa, s);
+        const double frac = volume_of(r[q]) * P.inv_vcell;
+        const double m = mass_of(P, r[q]);
+        double S[4] = {frac, 0.0, 0.0, 0.0};
+        if (wm)
+            for (int c = 0; c < 3; ++c) S[c + 1] = m * v[c * n + q];
+        for (int cz = 0; cz < 3; ++cz)
+            for (int cy = 0; cy < 3; ++cy)
+                for (int cx = 0; cx < 3; ++cx) {
+                    const double w = (s.w[0][cx] * s.w[1][cy]) * s.w[2][cz];
+                    const int32_t ni = s.node[0][cx], nj = s.node[1][cy], nk = s.node[2][cz];
+                    const int32_t li = ni - o[0], lj = nj - o[1], lk = nk - o[2];
+                    const bool in = li >= 0 && lj >= 0 && lk >= 0 && li < E && lj < E && lk < E;
+                    const int lidx = (lk * E + lj) * E + li;
+                    const int64_t gidx = node_index(P, ni, nj, nk);
+                    for (int c = wa ? 0 : 1; c < (wm ? 4 : 1); ++c) {
+                        const double val = w * S[c];
+                        if (in)
+                            atomicAdd(&dtile[c * E3 + lidx], val);
+                        else
+                            unsafeAtomicAdd(c == 0 ? &alpha[gidx] : &mom[(c - 1) * G + gidx], val);
+                    }
+                }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < 4 * E3; k += kP2GThreads) {
+        const double val = dtile[k];
+        if (val == 0.0) continue;
+        const int c = k / E3;
+        const int l = k - c * E3;
+        const int32_t ni = o[0] + l % E, nj = o[1] + (l / E) % E, nk = o[2] + l / (E * E);
+        const int64_t gidx = node_index(P, ni, nj, nk);
+        unsafeAtomicAdd(c == 0 ? &alpha[gidx] : &mom[(c - 1) * G + gidx], val);
+    }
+}
+
+template <typename T, bool FIXED>
+__global__ void __launch_bounds__(256) k_g2p(DevParams P, int64_t n, const double *__restrict__ x,
+                                             const T *__restrict__ u, const int64_t *__restrict__ afx,
+                                             const double *__restrict__ are, T *__restrict__ uat,
+                                             T *__restrict__ af)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const double xa[3] = {x[q], x[n + q], x[2 * n + q]};
+    Stencil s;
+    stencil_of(P, xa, s);
+    const int64_t G = P.G;
+    T acc[3] = {(T)0, (T)0, (T)0};
+    T as = (T)0;
+    for (int cz = 0; cz < 3; ++cz)
+        for (int cy = 0; cy < 3; ++cy) {
+            const double wyz = s.w[1][cy] * s.w[2][cz];
+            const int64_t row = (int64_t)P.n[0] * ((int64_t)s.node[1][cy] + (int64_t)P.n[1] * s.node[2][cz]);
+            for (int cx = 0; cx < 3; ++cx) {
+                const T w = (T)(s.w[0][cx] * wyz);
+                const int64_t k = row + s.node[0][cx];
+                acc[0] += w * u[k];
+                acc[1] += w * u[G + k];
+                acc[2] += w * u[2 * G + k];
+                double al = FIXED ? (double)afx[k] * GIC_TWOM32 : are[k];
+                al = al > P.alpha_max ? P.alpha_max : al;
+                as += w * (T)al;
+            }
+        }
+    uat[q] = acc[0];
+    uat[n + q] = acc[1];
+    uat[2 * n + q] = acc[2];
+    af[q] = (T)1 - as;
+}
+
+}  // namespace
+
+hipError_t launch_fill_i64(int64_t *a, int64_t len, hipStream_t s)
+{
+    if (len <= 0) return hipSuccess;
+    unsigned g = grid_for(len, 256);
+    if (g > 65536) g = 65536;
+    k_fill_i64<<<g, 256, 0, s>>>(a, len);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double *a, int64_t len, hipStream_t s)
+{
+    if (len <= 0) return hipSuccess;
+    unsigned g = grid_for(len, 256);
+    if (g > 65536) g = 65536;
+    k_fill_f64<<<g, 256, 0, s>>>(a, len);
+    return hipGetLastError();
+}
+
+hipError_t launch_p2g_fixed(const DevParams &P, int64_t n, int64_t K, const double *x, const double *v,
+                            const double *r, const int32_t *cb, const int32_t *ce, int64_t *alpha, int64_t *mom,
+                            int64_t *err, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const int64_t bricks = K / kBrickCells;
+    const int E3 = P.tile * P.tile * P.tile;
+    const size_t lds = sizeof(unsigned long long) * (size_t)(mom ? 4 : 1) * E3;
+    k_p2g_fixed<<<(unsigned)bricks, kP2GThreads, lds, s>>>(P, n, x, v, r, cb, ce,
+                                                           reinterpret_cast<unsigned long long *>(alpha),
+                                                           reinterpret_cast<unsigned long long *>(mom), err);
+    return hipGetLastError();
+}
+
+hipError_t launch_p2g_real(const DevParams &P, int64_t n, int64_t K, const double *x, const double *v,
+                           const double *r, const int32_t *cb, const int32_t *ce, double *alpha, double *mom,
+                           hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const int64_t bricks = K / kBrickCells;
+    const int E3 = P.tile * P.tile * P.tile;
+    const size_t lds = sizeof(double) * 4 * (size_t)E3;
+    k_p2g_real<<<(unsigned)bricks, kP2GThreads, lds, s>>>(P, n, x, v, r, cb, ce, alpha, mom);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_g2p(const DevParams &P, int64_t n, const double *x, const T *u, const int64_t *afx,
+                      const double *are, T *uat, T *af, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    if (afx)
+        k_g2p<T, true><<<grid_for(n, 256), 256, 0, s>>>(P, n, x, u, afx, nullptr, uat, af);
+    else
+        k_g2p<T, false><<<grid_for(n, 256), 256, 0, s>>>(P, n, x, u, nullptr, are, uat, af);
+    return hipGetLastError();
+}
+
+template hipError_t launch_g2p<float>(const DevParams &, int64_t, const double *, const float *, const int64_t *,
+                                      const double *, float *, float *, hipStream_t);
+template hipError_t launch_g2p<double>(const DevParams &, int64_t, const double *, const double *,
+                                       const int64_t *, const double *, double *, double *, hipStream_t);
+
+}  // namespace gic

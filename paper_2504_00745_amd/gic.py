@@ -1,0 +1,309 @@
+"""Thin Python binding of the gfx950 C ABI (include/gic.h).
+
+Argument marshalling only: torch tensors on the GPU provide device memory
+and torch's current stream is passed to every call; every step of the path
+runs in the HIP kernels of libgic.so.  Functions keep the C names.  A missing
+library raises immediately: there is no fallback.
+"""
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgic.so")
+_LIB = None
+
+GIC_FP64 = 0
+GIC_FP32 = 1
+STATUS = {0: "GIC_OK", 1: "GIC_E_ARG", 2: "GIC_E_HIP", 3: "GIC_E_ALLOC", 4: "GIC_E_DOMAIN", 5: "GIC_E_NONFINITE",
+          6: "GIC_E_RANGE"}
+
+
+class GicError(RuntimeError):
+    def __init__(self, status, where):
+        super().__init__(f"{where}: {STATUS.get(status, status)}")
+        self.status = status
+
+
+class gic_params(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32 * 3), ("pad0", C.c_int32), ("dx", C.c_double),
+        ("nc", C.c_int32 * 3), ("pad1", C.c_int32), ("cell", C.c_double),
+        ("kn", C.c_double), ("restitution", C.c_double), ("kt_ratio", C.c_double), ("mu", C.c_double),
+        ("rho_s", C.c_double), ("eta_f", C.c_double), ("c_drag", C.c_double), ("alpha_max", C.c_double),
+        ("g", C.c_double * 3), ("dt", C.c_double), ("r_max", C.c_double),
+        ("walls", C.c_uint32), ("precision", C.c_int32),
+    ]
+
+
+_V = C.c_void_p
+_I64 = C.c_int64
+_I32 = C.c_int32
+_PP = C.POINTER(gic_params)
+
+
+def lib():
+    """The loaded libgic.so; raises if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2504_00745_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        sig = {
+            "gic_key_space": (_I64, [_PP]),
+            "gic_create": (C.c_int, [_PP, _I64, C.POINTER(_V)]),
+            "gic_set_params": (C.c_int, [_V, _PP]),
+            "gic_destroy": (C.c_int, [_V]),
+            "gic_get_error": (C.c_int, [_V, _V, C.POINTER(_I32), C.POINTER(_I64), _I32]),
+            "gic_sort_cells": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V]),
+            "gic_reorder": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V, _V, _V, _V]),
+            "gic_contact_forces": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V, _V]),
+            "gic_contact_pairs": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _I64, _V, _V]),
+            "gic_g2p": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V]),
+            "gic_drag": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V]),
+            "gic_integrate": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V]),
+            "gic_p2g": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V, _I32, _V]),
+            "gic_p2g_real": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V, _I32, _V]),
+            "gic_step": (C.c_int, [_V, _I64] + [_V] * 19),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def make_params(cfg: dict, precision: str = "fp32", r_max: float = None) -> gic_params:
+    """C parameter block from a workload parameter dict (workloads.spec)."""
+    p = gic_params()
+    p.n = (C.c_int32 * 3)(*cfg["n"])
+    p.dx = float(cfg["dx"])
+    p.nc = (C.c_int32 * 3)(*cfg["nc"])
+    p.cell = float(cfg["cell"])
+    for k in ("kn", "restitution", "kt_ratio", "mu", "rho_s", "eta_f", "c_drag", "alpha_max", "dt"):
+        setattr(p, k, float(cfg[k]))
+    p.g = (C.c_double * 3)(*cfg["g"])
+    p.r_max = float(cfg["cell"] / 2.0 if r_max is None else r_max)
+    p.walls = int(cfg["walls"])
+    p.precision = GIC_FP32 if precision == "fp32" else GIC_FP64
+    return p
+
+
+def _stream():
+    return _V(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, dtype=None, numel=None, name="array"):
+    """Device pointer of a contiguous CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name} holds {t.numel()} elements, needs {numel}")
+    return _V(t.data_ptr())
+
+
+def _check(status, where):
+    if status != 0:
+        raise GicError(status, where)
+
+
+class Context:
+    """A gic_ctx: parameters, sort scratch and the latched error word."""
+
+    def __init__(self, cfg: dict, n_max: int, precision: str = "fp32", r_max: float = None):
+        self.cfg = dict(cfg)
+        self.precision = precision
+        self.params = make_params(cfg, precision, r_max)
+        self.n_max = int(n_max)
+        self.real = torch.float32 if precision == "fp32" else torch.float64
+        L = lib()
+        self.K = int(L.gic_key_space(C.byref(self.params)))
+        if self.K < 0:
+            raise GicError(1, "gic_key_space")
+        self.G = int(cfg["n"][0]) * int(cfg["n"][1]) * int(cfg["n"][2])
+        h = _V()
+        _check(L.gic_create(C.byref(self.params), self.n_max, C.byref(h)), "gic_create")
+        self.handle = h
+
+    def set_params(self, **over):
+        for k, val in over.items():
+            if k == "g":
+                self.params.g = (C.c_double * 3)(*val)
+            else:
+                setattr(self.params, k, float(val))
+            self.cfg[k] = val
+        _check(lib().gic_set_params(self.handle, C.byref(self.params)), "gic_set_params")
+
+    def error(self, clear=True):
+        code = _I32()
+        idx = _I64()
+        _check(lib().gic_get_error(self.handle, _stream(), C.byref(code), C.byref(idx), int(clear)),
+               "gic_get_error")
+        return int(code.value), int(idx.value)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().gic_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gic_sort_cells(ctx, x, key, order, cell_begin, cell_end):
+    n = x.shape[-1]
+    _check(lib().gic_sort_cells(ctx.handle, n, _ptr(x, torch.float64, 3 * n, "x"), _ptr(key, torch.int32, n, "key"),
+                                _ptr(order, torch.int32, n, "order"), _ptr(cell_begin, torch.int32, ctx.K, "cell_begin"),
+                                _ptr(cell_end, torch.int32, ctx.K, "cell_end"), _stream()), "gic_sort_cells")
+
+
+def gic_reorder(ctx, order, x, v, r, id_, x_out, v_out, r_out, id_out):
+    n = x.shape[-1]
+    f64 = torch.float64
+    _check(lib().gic_reorder(ctx.handle, n, _ptr(order, torch.int32, n), _ptr(x, f64, 3 * n), _ptr(v, f64, 3 * n),
+                             _ptr(r, f64, n), _ptr(id_, torch.int32, n), _ptr(x_out, f64, 3 * n),
+                             _ptr(v_out, f64, 3 * n), _ptr(r_out, f64, n), _ptr(id_out, torch.int32, n), _stream()),
+           "gic_reorder")
+
+
+def gic_contact_forces(ctx, x, v, r, cell_begin, cell_end, f_contact, n_contacts=None):
+    n = x.shape[-1]
+    f64 = torch.float64
+    _check(lib().gic_contact_forces(ctx.handle, n, _ptr(x, f64, 3 * n), _ptr(v, f64, 3 * n), _ptr(r, f64, n),
+                                    _ptr(cell_begin, torch.int32, ctx.K), _ptr(cell_end, torch.int32, ctx.K),
+                                    _ptr(f_contact, ctx.real, 3 * n, "f_contact"),
+                                    _ptr(n_contacts, torch.int32, n), _stream()), "gic_contact_forces")
+
+
+def gic_contact_pairs(ctx, x, r, cell_begin, cell_end, pairs, count):
+    n = x.shape[-1]
+    cap = pairs.numel() // 2
+    _check(lib().gic_contact_pairs(ctx.handle, n, _ptr(x, torch.float64, 3 * n), _ptr(r, torch.float64, n),
+                                   _ptr(cell_begin, torch.int32, ctx.K), _ptr(cell_end, torch.int32, ctx.K),
+                                   _ptr(pairs, torch.int32), cap, _ptr(count, torch.int64, 1), _stream()),
+           "gic_contact_pairs")
+
+
+def gic_g2p(ctx, x, u, alpha_fx, alpha_real, u_at, alpha_f):
+    n = x.shape[-1]
+    _check(lib().gic_g2p(ctx.handle, n, _ptr(x, torch.float64, 3 * n), _ptr(u, ctx.real, 3 * ctx.G, "u"),
+                         _ptr(alpha_fx, torch.int64, ctx.G), _ptr(alpha_real, torch.float64, ctx.G),
+                         _ptr(u_at, ctx.real, 3 * n, "u_at"), _ptr(alpha_f, ctx.real, n, "alpha_f"), _stream()),
+           "gic_g2p")
+
+
+def gic_drag(ctx, r, v, u_at, alpha_f, f_drag):
+    n = r.shape[-1]
+    _check(lib().gic_drag(ctx.handle, n, _ptr(r, torch.float64, n), _ptr(v, torch.float64, 3 * n),
+                          _ptr(u_at, ctx.real, 3 * n), _ptr(alpha_f, ctx.real, n), _ptr(f_drag, ctx.real, 3 * n),
+                          _stream()), "gic_drag")
+
+
+def gic_integrate(ctx, r, f_contact, f_drag, x, v):
+    n = r.shape[-1]
+    _check(lib().gic_integrate(ctx.handle, n, _ptr(r, torch.float64, n), _ptr(f_contact, ctx.real, 3 * n),
+                               _ptr(f_drag, ctx.real, 3 * n), _ptr(x, torch.float64, 3 * n),
+                               _ptr(v, torch.float64, 3 * n), _stream()), "gic_integrate")
+
+
+def gic_p2g(ctx, x, v, r, cell_begin, cell_end, alpha_fx, mom_fx, accumulate=False):
+    n = x.shape[-1]
+    _check(lib().gic_p2g(ctx.handle, n, _ptr(x, torch.float64, 3 * n), _ptr(v, torch.float64, 3 * n),
+                         _ptr(r, torch.float64, n), _ptr(cell_begin, torch.int32, ctx.K),
+                         _ptr(cell_end, torch.int32, ctx.K), _ptr(alpha_fx, torch.int64, ctx.G),
+                         _ptr(mom_fx, torch.int64, 3 * ctx.G), int(bool(accumulate)), _stream()), "gic_p2g")
+
+
+def gic_p2g_real(ctx, x, v, r, cell_begin, cell_end, alpha, mom, accumulate=False):
+    n = x.shape[-1]
+    _check(lib().gic_p2g_real(ctx.handle, n, _ptr(x, torch.float64, 3 * n), _ptr(v, torch.float64, 3 * n),
+                              _ptr(r, torch.float64, n), _ptr(cell_begin, torch.int32, ctx.K),
+                              _ptr(cell_end, torch.int32, ctx.K), _ptr(alpha, torch.float64, ctx.G),
+                              _ptr(mom, torch.float64, 3 * ctx.G), int(bool(accumulate)), _stream()),
+           "gic_p2g_real")
+
+
+def gic_step(ctx, cur, nxt, u, alpha_fx, mom_fx, scratch):
+    """One sub-step; cur/nxt: dicts of x, v, r, id tensors; scratch: dict of
+    key, order, cell_begin, cell_end, f_contact, f_drag, u_at, alpha_f."""
+    n = cur["x"].shape[-1]
+    f64 = torch.float64
+    s = scratch
+    _check(lib().gic_step(ctx.handle, n, _ptr(cur["x"], f64, 3 * n), _ptr(cur["v"], f64, 3 * n),
+                          _ptr(cur["r"], f64, n), _ptr(cur.get("id"), torch.int32, n), _ptr(nxt["x"], f64, 3 * n),
+                          _ptr(nxt["v"], f64, 3 * n), _ptr(nxt["r"], f64, n), _ptr(nxt.get("id"), torch.int32, n),
+                          _ptr(u, ctx.real, 3 * ctx.G), _ptr(alpha_fx, torch.int64, ctx.G),
+                          _ptr(mom_fx, torch.int64, 3 * ctx.G), _ptr(s["key"], torch.int32, n),
+                          _ptr(s["order"], torch.int32, n), _ptr(s["cell_begin"], torch.int32, ctx.K),
+                          _ptr(s["cell_end"], torch.int32, ctx.K), _ptr(s["f_contact"], ctx.real, 3 * n),
+                          _ptr(s["f_drag"], ctx.real, 3 * n), _ptr(s["u_at"], ctx.real, 3 * n),
+                          _ptr(s["alpha_f"], ctx.real, n), _stream()), "gic_step")
+
+
+class Simulator:
+    """Granule state on the GPU plus the buffers of one sub-step.
+
+    The state (x, v, r, id) is double-buffered: each step reads `cur` and
+    writes the advanced state, in the new sorted order, to `nxt`, then swaps.
+    id[q] is the input index of the granule now at position q."""
+
+    def __init__(self, cfg, x, v, r, u, precision="fp32", r_max=None, device="cuda"):
+        n = x.shape[-1]
+        self.n = n
+        self.ctx = Context(cfg, n, precision, r_max)
+        dev = torch.device(device)
+        f64 = torch.float64
+        real = self.ctx.real
+        self.cur = dict(x=torch.as_tensor(x, dtype=f64).to(dev).contiguous(),
+                        v=torch.as_tensor(v, dtype=f64).to(dev).contiguous(),
+                        r=torch.as_tensor(r, dtype=f64).to(dev).contiguous(),
+                        id=torch.arange(n, dtype=torch.int32, device=dev))
+        self.nxt = {k: torch.empty_like(t) for k, t in self.cur.items()}
+        self.u = torch.as_tensor(u).to(dev, real).contiguous()
+        G, K = self.ctx.G, self.ctx.K
+        self.alpha = torch.zeros(G, dtype=torch.int64, device=dev)
+        self.mom = torch.zeros(3 * G, dtype=torch.int64, device=dev)
+        self.scratch = dict(key=torch.empty(n, dtype=torch.int32, device=dev),
+                            order=torch.empty(n, dtype=torch.int32, device=dev),
+                            cell_begin=torch.empty(K, dtype=torch.int32, device=dev),
+                            cell_end=torch.empty(K, dtype=torch.int32, device=dev),
+                            f_contact=torch.empty(3 * n, dtype=real, device=dev),
+                            f_drag=torch.empty(3 * n, dtype=real, device=dev),
+                            u_at=torch.empty(3 * n, dtype=real, device=dev),
+                            alpha_f=torch.empty(n, dtype=real, device=dev))
+        self.init_grid()
+
+    def init_grid(self):
+        """alpha, momentum = P2G of the current state (Alg. 1 initial state)."""
+        s = self.scratch
+        gic_sort_cells(self.ctx, self.cur["x"], s["key"], s["order"], s["cell_begin"], s["cell_end"])
+        gic_reorder(self.ctx, s["order"], self.cur["x"], self.cur["v"], self.cur["r"], self.cur["id"],
+                    self.nxt["x"], self.nxt["v"], self.nxt["r"], self.nxt["id"])
+        self.cur, self.nxt = self.nxt, self.cur
+        gic_p2g(self.ctx, self.cur["x"], self.cur["v"], self.cur["r"], s["cell_begin"], s["cell_end"], self.alpha,
+                self.mom)
+
+    def step(self, k=1):
+        for _ in range(k):
+            gic_step(self.ctx, self.cur, self.nxt, self.u, self.alpha, self.mom, self.scratch)
+            self.cur, self.nxt = self.nxt, self.cur
+
+    def state_in_input_order(self):
+        """(x, v) as (3, n) float64 CPU arrays indexed by input granule."""
+        idx = self.cur["id"].long()
+        x = torch.empty_like(self.cur["x"]).view(3, -1)
+        v = torch.empty_like(self.cur["v"]).view(3, -1)
+        x[:, idx] = self.cur["x"].view(3, -1)
+        v[:, idx] = self.cur["v"].view(3, -1)
+        return x.cpu().numpy(), v.cpu().numpy()

@@ -1,0 +1,212 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Bars: bit-exact keys, order, cell ranges, touching pairs and int64 P2G grids
+on identical inputs; forces, velocities and positions within 1e-5 (FP32
+form) or 1e-12 (plain FP64 form) of the scale of the terms that sum into
+them, per granule and per step from an identical state:
+    |F - F_or| <= tol S,  S = sum_j |F_ij| + |F_wall| (oracle)
+    |v - v_or| <= tol (|v_or| + dt (S + |F_d| + m |g|) / m)
+because a dense bed's net force cancels to far below its terms.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2504_00745_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-5, "fp64": 1e-12}
+
+
+@pytest.fixture(scope="module")
+def G():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2504_00745_amd import gic
+    gic.lib()
+    import gpu_util
+    return gpu_util
+
+
+def _cases():
+    return ["c1", "c1b", "c4s", "c2s"]
+
+
+def _make(name):
+    if name == "c4s":
+        d = wl.make("c4", n_override=12289)   # ragged: 6 sort tiles + a tail
+    elif name == "c2s":
+        d = wl.make("c2", n_override=30001)
+    else:
+        d = wl.make(name)
+    return d
+
+
+def _rmax(name, r):
+    return float(r.max())
+
+
+def _check_sort(orc, d, out):
+    cfg = d["params"]
+    key = orc.cell_keys(cfg, d["x"])
+    assert np.array_equal(out["key"], key)
+    order = orc.stable_sort(key)
+    assert np.array_equal(out["order"], order)
+    assert np.array_equal(out["ids"], order)
+    b, e = orc.cell_ranges(cfg, key, order)
+    assert np.array_equal(out["cell_begin"], b)
+    assert np.array_equal(out["cell_end"], e)
+
+
+def _force_scale(orc, d, Fd=None):
+    cfg = d["params"]
+    F, fa, nc, ns = orc.contact_forces(cfg, d["x"], d["v"], d["r"])
+    return F, fa, nc, ns
+
+
+def _check_step(orc, d, out, prec, name):
+    cfg = d["params"]
+    tol = TOL[prec]
+    x, v, r, u = d["x"], d["v"], d["r"], d["u"]
+    # identical alpha grid on both sides (the GPU's own initial P2G, itself
+    # checked bit-exact against the oracle below)
+    a0_or, _ = orc.p2g_fixed(cfg, x, v, r)
+    assert np.array_equal(out["alpha0"], a0_or), "initial P2G alpha differs"
+    st = orc.step(cfg, x, v, r, u, a0_or)
+    Fc, fa, nc, ns = orc.contact_forces(cfg, x, v, r)
+    assert np.array_equal(out["ncont"], nc), "contact counts differ"
+    # G2P, drag
+    ures = np.abs(u).max() + 1e-300
+    assert np.abs(out["u_at"] - st["u_at"]).max() <= 10 * tol * ures
+    assert np.abs(out["alpha_f"] - st["alpha_f"]).max() <= 10 * tol
+    m = cfg["rho_s"] * (((4.0 * math.pi / 3.0) * r) * r) * r
+    fdn = np.linalg.norm(st["Fd"], axis=0)
+    beta = cfg["c_drag"] * 6 * math.pi * cfg["eta_f"] * r
+    dscale = beta * (np.linalg.norm(st["u_at"], axis=0) + np.linalg.norm(v, axis=0))
+    assert np.all(np.linalg.norm(out["Fd"] - st["Fd"], axis=0) <= 10 * tol * dscale + 1e-300)
+    # contact force
+    err = np.linalg.norm(out["Fc"] - Fc, axis=0)
+    assert np.all(err <= tol * fa + 1e-300), f"{name}: max contact err/scale {np.max(err / (fa + 1e-300))}"
+    # velocities and positions
+    g = np.linalg.norm(cfg["g"])
+    S = fa + fdn + 10 * tol * dscale + m * g
+    vscale = np.linalg.norm(st["v"], axis=0) + cfg["dt"] * S / m
+    verr = np.linalg.norm(out["v1"] - st["v"], axis=0)
+    assert np.all(verr <= tol * vscale), f"{name}: max v err/scale {np.max(verr / vscale)}"
+    xerr = np.linalg.norm(out["x1"] - st["x"], axis=0)
+    ulp = 4 * np.spacing(np.abs(st["x"]).max(axis=0))
+    assert np.all(xerr <= cfg["dt"] * tol * vscale + ulp)
+    # P2G of the GPU's own new state: bit-exact
+    a1, m1 = orc.p2g_fixed(cfg, out["x1"], out["v1"], r)
+    assert np.array_equal(out["alpha1"], a1)
+    assert np.array_equal(out["mom1"], m1)
+    return nc.sum(), ns.sum()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", _cases())
+def test_stage_parity(G, orc, name, prec):
+    G.say(f"[parity] {name} {prec}")
+    d = _make(name)
+    out = G.run_stages(d["params"], d["x"], d["v"], d["r"], d["u"], prec, r_max=_rmax(name, d["r"]))
+    _check_sort(orc, d, out)
+    nct, nsl = _check_step(orc, d, out, prec, name)
+    assert out["err"] == (0, -1)
+    if name in ("c1b", "c4s", "c2s"):
+        assert nct > 0
+    G.say(f"[parity] {name} {prec} ok: contacts {nct} sliding {nsl}")
+
+
+def test_contact_pairs_bit_exact(G, orc):
+    import torch
+    from paper_2504_00745_amd import gic
+    for name in ("c1b", "c4s", "c2s"):
+        G.say(f"[pairs] {name}")
+        d = _make(name)
+        x, r = d["x"], d["r"]
+        n = x.shape[1]
+        out = G.run_stages(d["params"], x, d["v"], r, d["u"], "fp32", r_max=float(r.max()))
+        ctx = out["ctx"]
+        ids = out["ids"]
+        Xs = G.dev(x[:, ids].reshape(-1))
+        Rs = G.dev(r[ids])
+        cb, ce = G.dev(out["cell_begin"], torch.int32), G.dev(out["cell_end"], torch.int32)
+        cap = 20 * n
+        pairs = torch.empty(2 * cap, dtype=torch.int32, device="cuda")
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+        gic.gic_contact_pairs(ctx, Xs.view(3, n), Rs, cb, ce, pairs, cnt)
+        k = int(cnt.item())
+        assert k <= cap
+        P = pairs[:2 * k].view(k, 2).cpu().numpy()
+        got = set(map(tuple, np.sort(ids[P], 1).tolist()))
+        ref = set(map(tuple, np.sort(orc.pairs_cells(d["params"], x, r), 1).tolist()))
+        assert got == ref and len(ref) > 0
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 2047, 2048, 2049])
+def test_sort_edge_sizes(G, orc, n):
+    G.say(f"[sort] n={n}")
+    d = wl.make("c2", n_override=max(n, 1))
+    x, v, r = d["x"][:, :n], d["v"][:, :n], d["r"][:n]
+    out = G.run_stages(d["params"], x, v, r, d["u"], "fp32", r_max=0.01)
+    if n:
+        _check_sort(orc, dict(d, x=x), out)
+    else:
+        assert not out["cell_begin"].any() and not out["cell_end"].any()
+    assert out["err"] == (0, -1)
+
+
+def test_sort_many_equal_keys_stable(G, orc):
+    """All granules in a handful of cells: long runs of equal keys keep input
+    order across tiles and passes."""
+    G.say("[sort] equal keys")
+    d = wl.make("c2", n_override=20000)
+    rng = np.random.Generator(np.random.PCG64(1))
+    cells = rng.integers(0, 5, 20000)
+    x = np.stack([0.005 + cells * 0.02, np.full(20000, 0.005), np.full(20000, 0.5)])
+    out = G.run_stages(d["params"], x, d["v"], np.full(20000, 0.004), d["u"], "fp32", r_max=0.01)
+    _check_sort(orc, dict(d, x=x), out)
+
+
+def test_latched_errors(G, orc):
+    """Non-finite and out-of-box positions and oversized radii latch the
+    documented code and the first offending index."""
+    G.say("[errors]")
+    d = wl.make("c1")
+    x = d["x"].copy()
+    x[1, 17] = np.nan
+    out = G.run_stages(d["params"], x, d["v"], d["r"], d["u"], "fp64", r_max=0.01)
+    assert out["err"][0] == 5
+    x = d["x"].copy()
+    x[2, 33] = -0.01
+    out = G.run_stages(d["params"], x, d["v"], d["r"], d["u"], "fp64", r_max=0.01)
+    assert out["err"] == (4, 33)
+    r = d["r"].copy()
+    r[5] = 0.011
+    out = G.run_stages(d["params"], d["x"], d["v"], r, d["u"], "fp64", r_max=0.01)
+    assert out["err"][0] == 6
+
+
+def test_whole_step_matches_stages(G):
+    """gic_step runs the same kernels as the staged sequence: bit-identical
+    state, grids and order."""
+    import torch
+    from paper_2504_00745_amd import gic
+    G.say("[step] c4s fp32")
+    d = _make("c4s")
+    n = d["x"].shape[1]
+    out = G.run_stages(d["params"], d["x"], d["v"], d["r"], d["u"], "fp32", r_max=0.006)
+    sim = gic.Simulator(d["params"], d["x"].reshape(3, n), d["v"].reshape(3, n), d["r"], d["u"].reshape(-1),
+                        "fp32", r_max=0.006)
+    # the Simulator starts from its own sorted copy; feed the stage run the same
+    # alpha grid and compare state by input index
+    assert np.array_equal(sim.alpha.cpu().numpy(), out["alpha0"])
+    sim.step()
+    x1, v1 = sim.state_in_input_order()
+    assert np.array_equal(x1, out["x1"])
+    assert np.array_equal(v1, out["v1"])
+    assert np.array_equal(sim.alpha.cpu().numpy(), out["alpha1"])
+    assert np.array_equal(sim.mom.cpu().numpy().reshape(3, -1), out["mom1"])
