@@ -78,6 +78,12 @@ def _declare(L):
         "orc_drag": (None, [_pp, C.c_int64, _d, _d, _d, _d, _d]),
         "orc_integrate": (None, [_pp, C.c_int64, _d, _d, _d, _d, _d]),
         "orc_step": (None, [_pp, C.c_int64, _d, _d, _d, _d, _i64, _i64, _d, _d, _d, _d]),
+        "orc_contact_vjp": (None, [_pp, C.c_int64, _d, _d, _d, _d, _d, _d, _d]),
+        "orc_drag_vjp": (None, [_pp, C.c_int64, _d, _d, _d, _d, _d, _d, _d, _d, _d]),
+        "orc_g2p_vjp": (None, [_pp, C.c_int64, _d, _d, _d, _d, _d, _d, _d]),
+        "orc_p2g_vjp": (None, [_pp, C.c_int64, _d, _d, _d, _d, _d, _d, _d]),
+        "orc_rollout": (C.c_double, [_pp, C.c_int64, _d, _d, _d, _d, C.c_int32, _d, _P(C.c_uint64)]),
+        "orc_rollout_vjp": (C.c_double, [_pp, C.c_int64, _d, _d, _d, _d, C.c_int32, _d, _d, _d]),
         "orc_num_threads": (C.c_int, []),
         "orc_set_num_threads": (None, [C.c_int]),
     }
@@ -305,3 +311,79 @@ def step(cfg, x, v, r, u, alpha_fx):
                    _ptr(u, C.c_double), _ptr(alpha, C.c_int64), _ptr(mom, C.c_int64), _ptr(Fc, C.c_double),
                    _ptr(Fd, C.c_double), _ptr(uat, C.c_double), _ptr(af, C.c_double))
     return dict(x=x, v=v, alpha=alpha, mom=mom, Fc=Fc, Fd=Fd, u_at=uat, alpha_f=af)
+
+
+# ---- differentiable form (unquantised transfers) and its reverse pass -------
+
+def contact_vjp(cfg, x, v, r, gF):
+    """(gx, gv, gmu) = (dL/dx, dL/dv, dL/dmu) for dL/dF_c = gF."""
+    x, v, r, gF = _f64(x), _f64(v), _f64(r), _f64(gF)
+    gx = np.zeros_like(x)
+    gv = np.zeros_like(v)
+    gmu = np.zeros(1)
+    p = params(cfg)
+    lib().orc_contact_vjp(C.byref(p), x.shape[1], _ptr(x, C.c_double), _ptr(v, C.c_double), _ptr(r, C.c_double),
+                          _ptr(gF, C.c_double), _ptr(gx, C.c_double), _ptr(gv, C.c_double), _ptr(gmu, C.c_double))
+    return gx, gv, float(gmu[0])
+
+
+def drag_vjp(cfg, r, v, u_at, alpha_f, gF):
+    """(gv, gu_at, galpha_f, gcd) for dL/dF_d = gF."""
+    r, v, u_at, alpha_f, gF = _f64(r), _f64(v), _f64(u_at), _f64(alpha_f), _f64(gF)
+    gv = np.zeros_like(v)
+    guat = np.zeros_like(u_at)
+    gaf = np.zeros_like(alpha_f)
+    gcd = np.zeros(1)
+    p = params(cfg)
+    lib().orc_drag_vjp(C.byref(p), r.shape[0], _ptr(r, C.c_double), _ptr(v, C.c_double), _ptr(u_at, C.c_double),
+                       _ptr(alpha_f, C.c_double), _ptr(gF, C.c_double), _ptr(gv, C.c_double),
+                       _ptr(guat, C.c_double), _ptr(gaf, C.c_double), _ptr(gcd, C.c_double))
+    return gv, guat, gaf, float(gcd[0])
+
+
+def g2p_vjp(cfg, x, u, alpha_real, guat, gaf):
+    """(gx, galpha) for cotangents of u_at and alpha_f."""
+    x, u, alpha_real, guat, gaf = _f64(x), _f64(u), _f64(alpha_real), _f64(guat), _f64(gaf)
+    gx = np.zeros_like(x)
+    galpha = np.zeros(nodes(cfg))
+    p = params(cfg)
+    lib().orc_g2p_vjp(C.byref(p), x.shape[1], _ptr(x, C.c_double), _ptr(u, C.c_double), _ptr(alpha_real, C.c_double),
+                      _ptr(guat, C.c_double), _ptr(gaf, C.c_double), _ptr(gx, C.c_double), _ptr(galpha, C.c_double))
+    return gx, galpha
+
+
+def p2g_vjp(cfg, x, v, r, galpha=None, gmom=None):
+    """(gx, gv) for cotangents of the real alpha grid and momentum grid."""
+    x, v, r = _f64(x), _f64(v), _f64(r)
+    ga = None if galpha is None else _f64(galpha)
+    gm = None if gmom is None else _f64(gmom)
+    gx = np.zeros_like(x)
+    gv = np.zeros_like(v)
+    p = params(cfg)
+    lib().orc_p2g_vjp(C.byref(p), x.shape[1], _ptr(x, C.c_double), _ptr(v, C.c_double), _ptr(r, C.c_double),
+                      _ptr(ga, C.c_double), _ptr(gm, C.c_double), _ptr(gx, C.c_double), _ptr(gv, C.c_double))
+    return gx, gv
+
+
+def rollout(cfg, x0, v0, r, u, steps, want_mom=False):
+    """Real-mode rollout.  Returns (L, signature[, mom])."""
+    x0, v0, r, u = _f64(x0), _f64(v0), _f64(r), _f64(u)
+    mom = np.zeros((3, nodes(cfg))) if want_mom else None
+    sig = (C.c_uint64 * 1)()
+    p = params(cfg)
+    L = lib().orc_rollout(C.byref(p), x0.shape[1], _ptr(x0, C.c_double), _ptr(v0, C.c_double), _ptr(r, C.c_double),
+                          _ptr(u, C.c_double), int(steps), _ptr(mom, C.c_double), sig)
+    return (L, int(sig[0]), mom) if want_mom else (L, int(sig[0]))
+
+
+def rollout_vjp(cfg, x0, v0, r, u, steps):
+    """Reverse pass: (L, dL/dv0 (3,n), dL/dmu, dL/dC_d)."""
+    x0, v0, r, u = _f64(x0), _f64(v0), _f64(r), _f64(u)
+    gv0 = np.zeros_like(v0)
+    gmu = np.zeros(1)
+    gcd = np.zeros(1)
+    p = params(cfg)
+    L = lib().orc_rollout_vjp(C.byref(p), x0.shape[1], _ptr(x0, C.c_double), _ptr(v0, C.c_double),
+                              _ptr(r, C.c_double), _ptr(u, C.c_double), int(steps), _ptr(gv0, C.c_double),
+                              _ptr(gmu, C.c_double), _ptr(gcd, C.c_double))
+    return L, gv0, float(gmu[0]), float(gcd[0])

@@ -182,19 +182,23 @@ void orc_stable_sort(int64_t n, const uint32_t *key, int32_t *order)
     free(kv);
 }
 
-/* begin[c], end[c]: sorted positions of the granules in cell key c, for every
- * key c of the key space; an empty cell has begin = end = 0. */
+/* begin[c], end[c] for every key c of the key space: the sorted positions
+ * [begin, end) of the granules in cell c, i.e. begin[c] = number of granules
+ * with a smaller key and end[c] = number with a key not larger (an empty cell
+ * has begin = end, so consecutive cells have contiguous ranges). */
 void orc_cell_ranges(const orc_params *p, int64_t n, const uint32_t *key, const int32_t *order,
                      int32_t *begin, int32_t *end)
 {
     int64_t K = orc_key_space(p);
-    memset(begin, 0, sizeof(int32_t) * (size_t)K);
-    memset(end, 0, sizeof(int32_t) * (size_t)K);
-    for (int64_t q = 0; q < n; ++q) {
-        uint32_t k = key[order[q]];
-        if (q == 0 || key[order[q - 1]] != k) begin[k] = (int32_t)q;
-        end[k] = (int32_t)(q + 1);
+    int64_t *count = (int64_t *)calloc((size_t)K, sizeof(int64_t));
+    for (int64_t q = 0; q < n; ++q) count[key[order[q]]] += 1;
+    int64_t below = 0;
+    for (int64_t k = 0; k < K; ++k) {
+        begin[k] = (int32_t)below;
+        below += count[k];
+        end[k] = (int32_t)below;
     }
+    free(count);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -718,4 +722,364 @@ void orc_set_num_threads(int t)
 #else
     (void)t;
 #endif
+}
+
+/* ======================================================================== */
+/* Differentiable form: unquantised rollout and its reverse pass             */
+/* ======================================================================== */
+/*
+ * Forward (one step, x^n -> x^{n+1}):
+ *   A^n = P2G_alpha(x^n) (real);  (u_at, alpha_f) = G2P(x^n; u, A^n);
+ *   F_d = C_d 6 pi eta r alpha_f (u_at - v^n);  F_c = contact(x^n, v^n; mu);
+ *   v^{n+1} = v^n + dt ((F_c + F_d)/m + g);  x^{n+1} = x^n + dt v^{n+1}.
+ * Loss L = sum_k |P_k|^2 with P = P2G_momentum(x^T, v^T) in kg m/s.
+ * The reverse pass below is written by hand, step by step, from these
+ * definitions; the alpha clamp and the Coulomb cap take the derivative of the
+ * branch taken (the clamp's derivative is 0 at and above alpha_max).
+ */
+
+/* Reverse of orc_pair_force.  gbar: cotangent of the force on the first
+ * partner; gmu: cotangent used for the mu derivative.  Adds to nbar[3],
+ * *dbar (overlap), wbar[3] (relative velocity) and *mubar. */
+static void orc_pair_force_vjp(const orc_params *p, double zeta, const double nh[3], double delta,
+                               const double w[3], double meff, const double gbar[3], const double gmu[3],
+                               double nbar[3], double *dbar, double wbar[3], double *mubar)
+{
+    double gam = 2.0 * zeta * sqrt(meff * p->kn);
+    double kt = p->kt_ratio * gam;
+    double vn = (w[0] * nh[0] + w[1] * nh[1]) + w[2] * nh[2];
+    double fn = p->kn * delta - gam * vn;
+    double t[3], ft[3];
+    for (int a = 0; a < 3; ++a) {
+        t[a] = w[a] - vn * nh[a];
+        ft[a] = -kt * t[a];
+    }
+    double s = sqrt((ft[0] * ft[0] + ft[1] * ft[1]) + ft[2] * ft[2]);
+    double cap = p->mu * (p->kn * delta);
+    int slide = s > cap;
+    /* F = fn n + F_t */
+    double fnbar = (gbar[0] * nh[0] + gbar[1] * nh[1]) + gbar[2] * nh[2];
+    for (int a = 0; a < 3; ++a) nbar[a] += fn * gbar[a];
+    double ftbar[3];
+    if (slide) {
+        /* F_t = cap ft / s */
+        double fh[3] = {ft[0] / s, ft[1] / s, ft[2] / s};
+        double gdotf = (gbar[0] * fh[0] + gbar[1] * fh[1]) + gbar[2] * fh[2];
+        double capbar = gdotf;
+        for (int a = 0; a < 3; ++a) ftbar[a] = (cap / s) * (gbar[a] - gdotf * fh[a]);
+        *dbar += capbar * p->mu * p->kn;
+        double gmudotf = (gmu[0] * fh[0] + gmu[1] * fh[1]) + gmu[2] * fh[2];
+        *mubar += gmudotf * p->kn * delta;
+    } else {
+        for (int a = 0; a < 3; ++a) ftbar[a] = gbar[a];
+    }
+    /* ft = -kt t, t = w - vn n */
+    double tbar[3];
+    for (int a = 0; a < 3; ++a) tbar[a] = -kt * ftbar[a];
+    double vnbar = -((tbar[0] * nh[0] + tbar[1] * nh[1]) + tbar[2] * nh[2]);
+    for (int a = 0; a < 3; ++a) {
+        wbar[a] += tbar[a];
+        nbar[a] += -vn * tbar[a];
+    }
+    /* fn = kn delta - gam vn */
+    *dbar += p->kn * fnbar;
+    vnbar += -gam * fnbar;
+    /* vn = w . n */
+    for (int a = 0; a < 3; ++a) {
+        wbar[a] += vnbar * nh[a];
+        nbar[a] += vnbar * w[a];
+    }
+}
+
+/* VJP of the contact forces: given gF (3n) = dL/dF_c, adds dL/dx (gx),
+ * dL/dv (gv) and dL/dmu (*gmu).  Gather form: granule i collects, for every
+ * touching partner j, the pair term with cotangent gF_i - gF_j. */
+void orc_contact_vjp(const orc_params *p, int64_t n, const double *x, const double *v, const double *r,
+                     const double *gF, double *gx, double *gv, double *gmu)
+{
+    orc_cells cl;
+    orc_cells_build(p, n, x, &cl);
+    double zeta = orc_zeta(p->restitution);
+    int64_t cap = 27 * orc_cells_maxocc(p, &cl) + 1;
+    double mu_acc = 0.0;
+#pragma omp parallel reduction(+ : mu_acc)
+    {
+        int64_t *cand = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap);
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            double mi = orc_mass(p, r[i]);
+            double gxi[3] = {0, 0, 0}, gvi[3] = {0, 0, 0};
+            double gFi[3] = {gF[i], gF[n + i], gF[2 * n + i]};
+            int64_t nc_ = orc_candidates(p, n, x, &cl, i, cand);
+            for (int64_t s = 0; s < nc_; ++s) {
+                int64_t j = cand[s];
+                double dv[3], d2;
+                if (!orc_touch(n, x, r, i, j, dv, &d2) || d2 == 0.0) continue;
+                double d = sqrt(d2);
+                double nh[3] = {dv[0] / d, dv[1] / d, dv[2] / d};
+                double delta = (r[i] + r[j]) - d;
+                double w[3] = {v[i] - v[j], v[n + i] - v[n + j], v[2 * n + i] - v[2 * n + j]};
+                double mj = orc_mass(p, r[j]);
+                double meff = (mi * mj) / (mi + mj);
+                double gbar[3] = {gFi[0] - gF[j], gFi[1] - gF[n + j], gFi[2] - gF[2 * n + j]};
+                double nbar[3] = {0, 0, 0}, wbar[3] = {0, 0, 0}, dbar = 0.0, mubar = 0.0;
+                orc_pair_force_vjp(p, zeta, nh, delta, w, meff, gbar, gFi, nbar, &dbar, wbar, &mubar);
+                /* n = dv / d, delta = R - d, d = |dv| */
+                double ndotn = (nbar[0] * nh[0] + nbar[1] * nh[1]) + nbar[2] * nh[2];
+                for (int a = 0; a < 3; ++a) {
+                    gxi[a] += (nbar[a] - ndotn * nh[a]) / d - dbar * nh[a];
+                    gvi[a] += wbar[a];
+                }
+                mu_acc += mubar;
+            }
+            for (int a = 0; a < 3; ++a) {
+                double L = (double)p->n[a] * p->dx;
+                for (int side = 0; side < 2; ++side) {
+                    if (!(p->walls & (1u << (2 * a + side)))) continue;
+                    double xa = x[a * n + i];
+                    double dist = side == 0 ? xa : L - xa;
+                    double delta = r[i] - dist;
+                    if (!(delta > 0.0)) continue;
+                    double nh[3] = {0.0, 0.0, 0.0};
+                    nh[a] = side == 0 ? 1.0 : -1.0;
+                    double w[3] = {v[i], v[n + i], v[2 * n + i]};
+                    double nbar[3] = {0, 0, 0}, wbar[3] = {0, 0, 0}, dbar = 0.0, mubar = 0.0;
+                    orc_pair_force_vjp(p, zeta, nh, delta, w, mi, gFi, gFi, nbar, &dbar, wbar, &mubar);
+                    /* delta = r - x_a (low face) or r - (L - x_a) (high face) */
+                    gxi[a] += side == 0 ? -dbar : dbar;
+                    for (int b = 0; b < 3; ++b) gvi[b] += wbar[b];
+                    mu_acc += mubar;
+                }
+            }
+            for (int a = 0; a < 3; ++a) {
+                gx[a * n + i] += gxi[a];
+                gv[a * n + i] += gvi[a];
+            }
+        }
+        free(cand);
+    }
+    *gmu += mu_acc;
+    orc_cells_free(&cl);
+}
+
+/* VJP of the drag F_d = beta alpha_f (u_at - v), beta = C_d 6 pi eta r:
+ * gv += -beta alpha_f gF; guat = beta alpha_f gF; gaf = beta (u_at - v).gF;
+ * *gcd += (F_d / C_d) . gF. */
+void orc_drag_vjp(const orc_params *p, int64_t n, const double *r, const double *v, const double *uat,
+                  const double *af, const double *gF, double *gv, double *guat, double *gaf, double *gcd)
+{
+    double c = ORC_C6PI * p->eta_f;
+    double acc = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double beta = (p->c_drag * c) * r[i];
+        double s = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            double g = gF[d * n + i];
+            double slip = uat[d * n + i] - v[d * n + i];
+            gv[d * n + i] += -beta * af[i] * g;
+            guat[d * n + i] = beta * af[i] * g;
+            s += slip * g;
+        }
+        gaf[i] = beta * s;
+        acc += (c * r[i]) * af[i] * s;
+    }
+    *gcd += acc;
+}
+
+/* VJP of G2P with a real alpha grid: given guat (3n) and gaf (n), adds
+ * dL/dx to gx and dL/dA to galpha (G). */
+void orc_g2p_vjp(const orc_params *p, int64_t n, const double *x, const double *u, const double *alpha,
+                 const double *guat, const double *gaf, double *gx, double *galpha)
+{
+    double inv_dx = 1.0 / p->dx;
+    int64_t G = orc_nodes(p);
+    for (int64_t i = 0; i < n; ++i) {
+        double xa[3];
+        orc_pos(n, x, i, xa);
+        orc_stencil s;
+        orc_stencil_of(p, inv_dx, xa, &s);
+        for (int c = 0; c < 3; ++c)
+            for (int b = 0; b < 3; ++b)
+                for (int a = 0; a < 3; ++a) {
+                    int64_t k = orc_node_index(p, &s, a, b, c);
+                    double w = (s.w[0][a] * s.w[1][b]) * s.w[2][c];
+                    double gw[3] = {(s.dw[0][a] * s.w[1][b]) * s.w[2][c], (s.w[0][a] * s.dw[1][b]) * s.w[2][c],
+                                    (s.w[0][a] * s.w[1][b]) * s.dw[2][c]};
+                    double ul = (u[k] * guat[i] + u[G + k] * guat[n + i]) + u[2 * G + k] * guat[2 * n + i];
+                    int clamped = !(alpha[k] < p->alpha_max);
+                    double al = clamped ? p->alpha_max : alpha[k];
+                    /* alpha_f = 1 - sum w al */
+                    double coef = ul - al * gaf[i];
+                    for (int d = 0; d < 3; ++d) gx[d * n + i] += gw[d] * coef;
+                    if (!clamped) galpha[k] += -w * gaf[i];
+                }
+    }
+}
+
+/* VJP of the real P2G: alpha_k = sum_i w_ik frac_i, P_k = sum_i w_ik m_i v_i.
+ * Given galpha (G, may be NULL) and gmom (3G, may be NULL), adds to gx, gv. */
+void orc_p2g_vjp(const orc_params *p, int64_t n, const double *x, const double *v, const double *r,
+                 const double *galpha, const double *gmom, double *gx, double *gv)
+{
+    double inv_dx = 1.0 / p->dx;
+    double inv_vcell = 1.0 / ((p->dx * p->dx) * p->dx);
+    int64_t G = orc_nodes(p);
+    for (int64_t i = 0; i < n; ++i) {
+        double xa[3];
+        orc_pos(n, x, i, xa);
+        orc_stencil s;
+        orc_stencil_of(p, inv_dx, xa, &s);
+        double frac = orc_volume(r[i]) * inv_vcell;
+        double m = orc_mass(p, r[i]);
+        for (int c = 0; c < 3; ++c)
+            for (int b = 0; b < 3; ++b)
+                for (int a = 0; a < 3; ++a) {
+                    int64_t k = orc_node_index(p, &s, a, b, c);
+                    double w = (s.w[0][a] * s.w[1][b]) * s.w[2][c];
+                    double gw[3] = {(s.dw[0][a] * s.w[1][b]) * s.w[2][c], (s.w[0][a] * s.dw[1][b]) * s.w[2][c],
+                                    (s.w[0][a] * s.w[1][b]) * s.dw[2][c]};
+                    double coef = 0.0;
+                    if (galpha) coef += galpha[k] * frac;
+                    if (gmom) {
+                        double pv = (gmom[k] * v[i] + gmom[G + k] * v[n + i]) + gmom[2 * G + k] * v[2 * n + i];
+                        coef += m * pv;
+                        for (int d = 0; d < 3; ++d) gv[d * n + i] += m * w * gmom[d * G + k];
+                    }
+                    for (int d = 0; d < 3; ++d) gx[d * n + i] += gw[d] * coef;
+                }
+    }
+}
+
+static uint64_t orc_fnv(uint64_t h, const int32_t *a, int64_t m)
+{
+    for (int64_t i = 0; i < m; ++i) {
+        h ^= (uint64_t)(uint32_t)a[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+/* Nodes read by G2P of granule i at or above the clamp, per granule. */
+static void orc_clamp_counts(const orc_params *p, int64_t n, const double *x, const double *alpha, int32_t *cnt)
+{
+    double inv_dx = 1.0 / p->dx;
+    for (int64_t i = 0; i < n; ++i) {
+        double xa[3];
+        orc_pos(n, x, i, xa);
+        orc_stencil s;
+        orc_stencil_of(p, inv_dx, xa, &s);
+        int32_t c_ = 0;
+        for (int c = 0; c < 3; ++c)
+            for (int b = 0; b < 3; ++b)
+                for (int a = 0; a < 3; ++a) c_ += !(alpha[orc_node_index(p, &s, a, b, c)] < p->alpha_max);
+        cnt[i] = c_;
+    }
+}
+
+/* One real-mode step in place; intermediates to the given buffers; the
+ * signature (if non-NULL) hashes the contact, sliding and clamp counts. */
+static void orc_step_real(const orc_params *p, int64_t n, double *x, double *v, const double *r, const double *u,
+                          double *A, double *uat, double *af, double *Fd, double *Fc, int32_t *i1, int32_t *i2,
+                          uint64_t *sig)
+{
+    int64_t G = orc_nodes(p);
+    memset(A, 0, sizeof(double) * (size_t)G);
+    orc_p2g_real(p, n, x, v, r, A, NULL);
+    orc_g2p(p, n, x, u, NULL, A, uat, af);
+    orc_drag(p, n, r, v, uat, af, Fd);
+    orc_contact_forces(p, n, x, v, r, Fc, NULL, i1, i2);
+    if (sig) {
+        *sig = orc_fnv(*sig, i1, n);
+        *sig = orc_fnv(*sig, i2, n);
+        orc_clamp_counts(p, n, x, A, i1);
+        *sig = orc_fnv(*sig, i1, n);
+    }
+    orc_integrate(p, n, r, Fc, Fd, x, v);
+}
+
+/* Real-mode rollout of `steps` steps from (x0, v0); returns L = sum |P|^2 of
+ * the final momentum grid (written to mom_out, 3G, if non-NULL); *sig (if
+ * non-NULL) receives a hash of the contact, sliding and clamp sets. */
+double orc_rollout(const orc_params *p, int64_t n, const double *x0, const double *v0, const double *r,
+                   const double *u, int32_t steps, double *mom_out, uint64_t *sig)
+{
+    int64_t G = orc_nodes(p);
+    size_t n3 = sizeof(double) * 3 * (size_t)n;
+    double *x = (double *)malloc(n3), *v = (double *)malloc(n3);
+    memcpy(x, x0, n3);
+    memcpy(v, v0, n3);
+    double *A = (double *)malloc(sizeof(double) * (size_t)G);
+    double *uat = (double *)malloc(n3), *Fd = (double *)malloc(n3), *Fc = (double *)malloc(n3);
+    double *af = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    int32_t *i1 = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *i2 = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (sig) *sig = 1469598103934665603ull;
+    for (int32_t s = 0; s < steps; ++s) orc_step_real(p, n, x, v, r, u, A, uat, af, Fd, Fc, i1, i2, sig);
+    double *P = (double *)calloc((size_t)(3 * G), sizeof(double));
+    orc_p2g_real(p, n, x, v, r, NULL, P);
+    double L = 0.0;
+    for (int64_t k = 0; k < 3 * G; ++k) L += P[k] * P[k];
+    if (mom_out) memcpy(mom_out, P, sizeof(double) * 3 * (size_t)G);
+    free(x); free(v); free(A); free(uat); free(Fd); free(Fc); free(af); free(i1); free(i2); free(P);
+    return L;
+}
+
+/* Reverse pass of orc_rollout: returns L and writes dL/dv0 (3n), adds
+ * dL/dmu and dL/dC_d.  The whole trajectory is stored (no checkpoints). */
+double orc_rollout_vjp(const orc_params *p, int64_t n, const double *x0, const double *v0, const double *r,
+                       const double *u, int32_t steps, double *gv0, double *gmu, double *gcd)
+{
+    int64_t G = orc_nodes(p);
+    size_t n3 = sizeof(double) * 3 * (size_t)n;
+    size_t n1 = sizeof(double) * (size_t)(n > 0 ? n : 1);
+    double *X = (double *)malloc(n3 * (size_t)(steps + 1)), *V = (double *)malloc(n3 * (size_t)(steps + 1));
+    memcpy(X, x0, n3);
+    memcpy(V, v0, n3);
+    double *A = (double *)malloc(sizeof(double) * (size_t)G);
+    double *uat = (double *)malloc(n3), *Fd = (double *)malloc(n3), *Fc = (double *)malloc(n3);
+    double *af = (double *)malloc(n1);
+    int32_t *i1 = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *i2 = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    for (int32_t s = 0; s < steps; ++s) {
+        memcpy(X + (size_t)(s + 1) * 3 * n, X + (size_t)s * 3 * n, n3);
+        memcpy(V + (size_t)(s + 1) * 3 * n, V + (size_t)s * 3 * n, n3);
+        orc_step_real(p, n, X + (size_t)(s + 1) * 3 * n, V + (size_t)(s + 1) * 3 * n, r, u, A, uat, af, Fd, Fc, i1,
+                      i2, NULL);
+    }
+    double *xT = X + (size_t)steps * 3 * n, *vT = V + (size_t)steps * 3 * n;
+    double *P = (double *)calloc((size_t)(3 * G), sizeof(double));
+    orc_p2g_real(p, n, xT, vT, r, NULL, P);
+    double L = 0.0;
+    for (int64_t k = 0; k < 3 * G; ++k) {
+        L += P[k] * P[k];
+        P[k] *= 2.0; /* dL/dP */
+    }
+    double *gx = (double *)calloc((size_t)(3 * n), sizeof(double));
+    double *gv = (double *)calloc((size_t)(3 * n), sizeof(double));
+    orc_p2g_vjp(p, n, xT, vT, r, NULL, P, gx, gv);
+    double *gF = (double *)malloc(n3), *guat = (double *)malloc(n3), *gaf = (double *)malloc(n1);
+    double *galpha = (double *)malloc(sizeof(double) * (size_t)G);
+    for (int32_t s = steps - 1; s >= 0; --s) {
+        double *x = X + (size_t)s * 3 * n, *v = V + (size_t)s * 3 * n;
+        memset(A, 0, sizeof(double) * (size_t)G);
+        orc_p2g_real(p, n, x, v, r, A, NULL);
+        orc_g2p(p, n, x, u, NULL, A, uat, af);
+        /* x^{s+1} = x^s + dt v^{s+1};  v^{s+1} = v^s + dt (F/m + g) */
+        for (int64_t i = 0; i < n; ++i) {
+            double m = orc_mass(p, r[i]);
+            for (int d = 0; d < 3; ++d) {
+                gv[d * n + i] += p->dt * gx[d * n + i];
+                gF[d * n + i] = (p->dt / m) * gv[d * n + i];
+            }
+        }
+        orc_contact_vjp(p, n, x, v, r, gF, gx, gv, gmu);
+        orc_drag_vjp(p, n, r, v, uat, af, gF, gv, guat, gaf, gcd);
+        memset(galpha, 0, sizeof(double) * (size_t)G);
+        orc_g2p_vjp(p, n, x, u, A, guat, gaf, gx, galpha);
+        orc_p2g_vjp(p, n, x, v, r, galpha, NULL, gx, gv);
+    }
+    memcpy(gv0, gv, n3);
+    free(X); free(V); free(A); free(uat); free(Fd); free(Fc); free(af); free(i1); free(i2); free(P);
+    free(gx); free(gv); free(gF); free(guat); free(gaf); free(galpha);
+    return L;
 }

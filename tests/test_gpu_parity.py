@@ -210,3 +210,39 @@ def test_whole_step_matches_stages(G):
     assert np.array_equal(v1, out["v1"])
     assert np.array_equal(sim.alpha.cpu().numpy(), out["alpha1"])
     assert np.array_equal(sim.mom.cpu().numpy().reshape(3, -1), out["mom1"])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_contact_dense_brick_and_many_partners(G, orc, prec):
+    """Rare paths of the contact kernel: a brick whose one-cell shell holds
+    more granules than fit in LDS (global candidate path), and granules with
+    more touching partners than the per-granule list (second candidate
+    walk).  Forces and contact counts still match the oracle."""
+    G.say(f"[contact rare paths] {prec}")
+    d = wl.make("c2", n_override=1000)
+    cfg = d["params"]
+    rng = np.random.Generator(np.random.PCG64(21))
+    # 3000 small granules packed in one 0.08 m brick (cell 0.02): shell overflow
+    xs = rng.uniform(0.405, 0.475, (3, 3000))
+    rs = np.full(3000, 0.0012)
+    # big granules each ringed by 30 small touching ones: long partner lists
+    big = []
+    for c in ([0.9, 0.9, 0.9], [0.3, 1.0, 0.6]):
+        c = np.array(c)
+        u = rng.normal(size=(30, 3))
+        u /= np.linalg.norm(u, axis=1)[:, None]
+        big.append(np.concatenate([c[None, :], c + u * (0.0099 + 0.0029)], 0))
+    xb = np.concatenate(big, 0).T
+    rb = np.tile(np.concatenate([[0.0099], np.full(30, 0.003)]), 2)
+    x = np.concatenate([xs, xb], 1)
+    r = np.concatenate([rs, rb])
+    v = rng.normal(0, 0.05, x.shape)
+    n = x.shape[1]
+    u = np.zeros((3, int(np.prod(cfg["n"]))))
+    out = G.run_stages(cfg, x, v, r, u, prec, r_max=0.0099)
+    Fc, fa, nc, ns = orc.contact_forces(cfg, x, v, r)
+    assert nc.max() >= 20 and nc[:3000].sum() > 3000
+    assert np.array_equal(out["ncont"], nc)
+    err = np.linalg.norm(out["Fc"] - Fc, axis=0)
+    assert np.all(err <= TOL[prec] * fa + 1e-300), np.max(err / (fa + 1e-300))
+    assert out["err"] == (0, -1)
