@@ -137,7 +137,10 @@ gic_status gic_get_error(gic_ctx *ctx, void *stream, int32_t *code, int64_t *ind
  *   order       out, n: order[q] = index of the granule at sorted position q;
  *               a stable sort by key (ties in input order).
  *   cell_begin, cell_end   out, K each: sorted positions [begin, end) of the
- *               granules of each key; empty cells hold begin = end = 0. */
+ *               granules of each key: begin[c] = number of granules with a
+ *               smaller key, end[c] = number with a key not larger.  Empty
+ *               cells have begin = end, so consecutive keys have contiguous
+ *               ranges. */
 gic_status gic_sort_cells(gic_ctx *ctx, int64_t n, const double *x, uint32_t *key, int32_t *order,
                           int32_t *cell_begin, int32_t *cell_end, void *stream);
 
@@ -226,6 +229,63 @@ gic_status gic_step(gic_ctx *ctx, int64_t n, const double *x_cur, const double *
                     const void *u, int64_t *alpha_fx, int64_t *mom_fx, uint32_t *key, int32_t *order,
                     int32_t *cell_begin, int32_t *cell_end, void *f_contact, void *f_drag, void *u_at,
                     void *alpha_f, void *stream);
+
+/* ---- a9: adjoint form ------------------------------------------------------
+ * Vector-Jacobian products of the stages of the differentiable step (all
+ * double; the context must be GIC_FP64).  The forward of the differentiable
+ * step uses unquantised transfers (gic_p2g_real):
+ *   A = P2G_alpha(x);  (u_at, alpha_f) = G2P(x; u, A);
+ *   F_d = c_drag 6 pi eta_f r alpha_f (u_at - v);  F_c = contact(x, v; mu);
+ *   v' = v + dt ((F_c + F_d)/m + g);  x' = x + dt v'.
+ * Cotangents named g_*; "+=" outputs accumulate, "=" outputs are written.
+ * The alpha clamp and the Coulomb cap take the derivative of the branch in
+ * effect (the clamp passes no gradient at or above alpha_max).  Per-granule
+ * parameter contributions (g_mu, g_cdrag) are written per granule; gic_sum
+ * adds them in a fixed order, so results are reproducible run to run. */
+
+/* Contact pullback (Sec. 3.1, Eq. 1a-c) in gather form: granule i collects,
+ * for every touching partner j, the pair term with cotangent g_f[i] - g_f[j].
+ *   g_f 3n;  g_x, g_v 3n (+=);  g_mu n (=, dL/dmu per granule). */
+gic_status gic_contact_forces_vjp(gic_ctx *ctx, int64_t n, const double *x, const double *v, const double *r,
+                                  const int32_t *cell_begin, const int32_t *cell_end, const double *g_f, double *g_x,
+                                  double *g_v, double *g_mu, void *stream);
+
+/* Drag pullback (Eq. 5b, App. A):  g_v += -beta alpha_f g_f;  g_u_at =
+ * beta alpha_f g_f;  g_alpha_f = beta (u_at - v).g_f;  g_cdrag[i] =
+ * 6 pi eta_f r alpha_f (u_at - v).g_f  (beta = c_drag 6 pi eta_f r). */
+gic_status gic_drag_vjp(gic_ctx *ctx, int64_t n, const double *r, const double *v, const double *u_at,
+                        const double *alpha_f, const double *g_f, double *g_v, double *g_u_at, double *g_alpha_f,
+                        double *g_cdrag, void *stream);
+
+/* Integration pullback (Sec. 4): on entry g_x, g_v are dL/dx', dL/dv'; on
+ * return g_v = g_v + dt g_x (the adjoint of v through the identity term)
+ * and g_f = dt/m times it (dL/d(F_c + F_d)); g_x is unchanged (= its
+ * identity part for x). */
+gic_status gic_integrate_vjp(gic_ctx *ctx, int64_t n, const double *r, const double *g_x, double *g_v, double *g_f,
+                             void *stream);
+
+/* G2P pullback (Sec. 5.2) with a real alpha grid:  g_x += sum_k grad w_k
+ * (u_k . g_u_at - min(A_k, alpha_max) g_alpha_f);  g_alpha (G, =, optional)
+ * = -sum_i w_ik g_alpha_f[i] on nodes below the clamp, 0 elsewhere.  The grid part needs
+ * the sorted order and cell tables of x (as gic_p2g). */
+gic_status gic_g2p_vjp(gic_ctx *ctx, int64_t n, const double *x, const double *u, const double *alpha_real,
+                       const double *g_u_at, const double *g_alpha_f, const int32_t *cell_begin,
+                       const int32_t *cell_end, double *g_x, double *g_alpha, void *stream);
+
+/* P2G pullback (Sec. 5.1, Eq. 7a) of the real transfers: g_alpha (G) and/or
+ * g_mom (3G) given;  g_x += ..., g_v += m sum_k w_k g_mom_k. */
+gic_status gic_p2g_vjp(gic_ctx *ctx, int64_t n, const double *x, const double *v, const double *r,
+                       const double *g_alpha, const double *g_mom, double *g_x, double *g_v, void *stream);
+
+/* *out (device double) = (accumulate ? *out : 0) + sum of a[i] (b == NULL)
+ * or of a[i] b[i], i < n, summed in a fixed order (reproducible). */
+gic_status gic_sum(gic_ctx *ctx, int64_t n, const double *a, const double *b, double *out, int32_t accumulate,
+                   void *stream);
+
+/* Permute comps (1..3) planes of n doubles: scatter = 0: out[c n + q] =
+ * in[c n + order[q]];  scatter = 1: out[c n + order[q]] = in[c n + q]. */
+gic_status gic_permute(gic_ctx *ctx, int64_t n, int32_t comps, const int32_t *order, const double *in, double *out,
+                       int32_t scatter, void *stream);
 
 #ifdef __cplusplus
 }

@@ -35,14 +35,109 @@ __device__ inline bool touching(double dx0, double dx1, double dx2, double R, do
     return d2 < R * R;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_contact(DevParams P, int64_t n, const double *__restrict__ x,
-                                                 const double *__restrict__ v, const double *__restrict__ r,
-                                                 const int32_t *__restrict__ cb, const int32_t *__restrict__ ce,
-                                                 T *__restrict__ F, int32_t *__restrict__ ncont, int64_t *err)
+// Visit the candidate ranges of granule q: for each row (cy, cz) of the
+// search box the cells [lo_x, hi_x] split into at most two runs of
+// consecutive keys (a run ends at a brick face), and consecutive keys have
+// contiguous granule ranges, so each run is one range [begin, end).
+template <typename F>
+__device__ inline void for_each_run(const DevParams &P, const int32_t lo[3], const int32_t hi[3],
+                                    const int32_t *__restrict__ cb, const int32_t *__restrict__ ce, F &&f)
 {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n) return;
+    for (int32_t cz = lo[2]; cz <= hi[2]; ++cz)
+        for (int32_t cy = lo[1]; cy <= hi[1]; ++cy) {
+            int32_t cx = lo[0];
+            while (cx <= hi[0]) {
+                const int32_t brick_end = (cx & ~(kBrick - 1)) + (kBrick - 1);
+                const int32_t cend = hi[0] < brick_end ? hi[0] : brick_end;
+                const uint32_t k0 = key_of_cell(P, cx, cy, cz);
+                f(cb[k0], ce[k0 + (uint32_t)(cend - cx)]);
+                cx = cend + 1;
+            }
+        }
+}
+
+constexpr int kUnroll = 4;
+constexpr int kMaxPartners = 12;  // partners listed per granule before forces are evaluated
+
+// Force that partner j exerts on granule q (both in sorted positions): the
+// overlap, its normal and the relative velocity come from double positions
+// and velocities; the pair law of Eq. (1a)-(1c) runs in T.
+template <typename T>
+__device__ inline void add_pair(const DevParams &P, int64_t n, const double *__restrict__ x,
+                                const double *__restrict__ v, const double *__restrict__ r, const double xi[3],
+                                const double vi[3], double ri, double mi, int32_t j, T acc[3])
+{
+    const double d0 = xi[0] - x[j], d1 = xi[1] - x[n + j], d2c = xi[2] - x[2 * n + j];
+    const double rj = r[j];
+    double d2;
+    {
+#pragma clang fp contract(off)
+        d2 = (d0 * d0 + d1 * d1) + d2c * d2c;
+    }
+    const double R = ri + rj;
+    const double d = sqrt(d2);
+    T nh[3];
+    if constexpr (sizeof(T) == sizeof(float)) {
+        const float inv_d = __builtin_amdgcn_rcpf((float)d);
+        nh[0] = (float)d0 * inv_d;
+        nh[1] = (float)d1 * inv_d;
+        nh[2] = (float)d2c * inv_d;
+    } else {
+        const double inv_d = 1.0 / d;
+        nh[0] = d0 * inv_d;
+        nh[1] = d1 * inv_d;
+        nh[2] = d2c * inv_d;
+    }
+    const T delta = (T)(R - d);
+    const T w[3] = {(T)(vi[0] - v[j]), (T)(vi[1] - v[n + j]), (T)(vi[2] - v[2 * n + j])};
+    const T mj = (T)mass_of(P, rj);
+    const T mit = (T)mi;
+    const T meff = law_div(mit * mj, mit + mj);
+    T Fp[3];
+    pair_force<T>(P, nh, delta, w, meff, Fp);
+    acc[0] += Fp[0];
+    acc[1] += Fp[1];
+    acc[2] += Fp[2];
+}
+
+// Wall forces of Eq. (1a)-(1c) with the box faces as infinite-mass partners.
+template <typename T>
+__device__ inline void add_walls(const DevParams &P, const double xi[3], const double vi[3], double ri, double mi,
+                                 T acc[3], int32_t &cnt)
+{
+    if (!P.walls) return;
+    const T wv[3] = {(T)vi[0], (T)vi[1], (T)vi[2]};
+    for (int a = 0; a < 3; ++a)
+        for (int side = 0; side < 2; ++side) {
+            if (!(P.walls & (1u << (2 * a + side)))) continue;
+            const double dist = side == 0 ? xi[a] : P.L[a] - xi[a];
+            const double delta = ri - dist;
+            if (!(delta > 0.0)) continue;
+            T nh[3] = {(T)0, (T)0, (T)0};
+            nh[a] = side == 0 ? (T)1 : (T)-1;
+            T Fp[3];
+            pair_force<T>(P, nh, (T)delta, wv, (T)mi, Fp);
+            acc[0] += Fp[0];
+            acc[1] += Fp[1];
+            acc[2] += Fp[2];
+            ++cnt;
+        }
+}
+
+// Contact force on granule q reading its candidates from global memory, in
+// two passes: the candidate pass runs only the double contact test and lists
+// touching partners in `plist` (kMaxPartners x 256 ints in LDS, column tid);
+// the force pass then evaluates the pair law for the listed partners.  Lanes
+// of a wave touch partners at different candidate positions, so evaluating
+// forces inside the candidate loop would run the expensive branch for almost
+// every candidate.
+template <typename T>
+__device__ inline void contact_global(const DevParams &P, int64_t n, const double *__restrict__ x,
+                                      const double *__restrict__ v, const double *__restrict__ r,
+                                      const int32_t *__restrict__ cb, const int32_t *__restrict__ ce, int64_t q,
+                                      int32_t *plist, int tid, T *__restrict__ F, int32_t *__restrict__ ncont,
+                                      int64_t *err)
+{
     const double xi[3] = {x[q], x[n + q], x[2 * n + q]};
     const double vi[3] = {v[q], v[n + q], v[2 * n + q]};
     const double ri = r[q];
@@ -53,55 +148,203 @@ __global__ void __launch_bounds__(256) k_contact(DevParams P, int64_t n, const d
     for (int a = 0; a < 3; ++a) search_range(P, xi[a], Rs, P.nc[a], lo[a], hi[a]);
     T acc[3] = {(T)0, (T)0, (T)0};
     int32_t cnt = 0;
-    for (int32_t cz = lo[2]; cz <= hi[2]; ++cz)
-        for (int32_t cy = lo[1]; cy <= hi[1]; ++cy)
-            for (int32_t cx = lo[0]; cx <= hi[0]; ++cx) {
-                const uint32_t key = key_of_cell(P, cx, cy, cz);
-                const int32_t e = ce[key];
-                for (int32_t j = cb[key]; j < e; ++j) {
-                    if (j == q) continue;
-                    const double d0 = xi[0] - x[j], d1 = xi[1] - x[n + j], d2c = xi[2] - x[2 * n + j];
-                    const double rj = r[j];
-                    const double R = ri + rj;
-                    double d2;
-                    if (!touching(d0, d1, d2c, R, d2) || d2 == 0.0) continue;
-                    const double d = sqrt(d2);
-                    const double inv_d = 1.0 / d;
-                    const T nh[3] = {(T)(d0 * inv_d), (T)(d1 * inv_d), (T)(d2c * inv_d)};
-                    const T delta = (T)(R - d);
-                    const T w[3] = {(T)(vi[0] - v[j]), (T)(vi[1] - v[n + j]), (T)(vi[2] - v[2 * n + j])};
-                    const double mj = mass_of(P, rj);
-                    const T meff = (T)((mi * mj) / (mi + mj));
-                    T Fp[3];
-                    pair_force<T>(P, nh, delta, w, meff, Fp);
-                    acc[0] += Fp[0];
-                    acc[1] += Fp[1];
-                    acc[2] += Fp[2];
-                    ++cnt;
-                }
+    for_each_run(P, lo, hi, cb, ce, [&](int32_t jb, int32_t je) {
+        for (int32_t j0 = jb; j0 < je; j0 += kUnroll) {
+            double cx[kUnroll], cy[kUnroll], cz[kUnroll], cr[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int32_t j = j0 + u < je ? j0 + u : je - 1;  // in range; duplicates skipped below
+                cx[u] = x[j];
+                cy[u] = x[n + j];
+                cz[u] = x[2 * n + j];
+                cr[u] = r[j];
             }
-    if (P.walls) {
-        const T wv[3] = {(T)vi[0], (T)vi[1], (T)vi[2]};
-        for (int a = 0; a < 3; ++a)
-            for (int side = 0; side < 2; ++side) {
-                if (!(P.walls & (1u << (2 * a + side)))) continue;
-                const double dist = side == 0 ? xi[a] : P.L[a] - xi[a];
-                const double delta = ri - dist;
-                if (!(delta > 0.0)) continue;
-                T nh[3] = {(T)0, (T)0, (T)0};
-                nh[a] = side == 0 ? (T)1 : (T)-1;
-                T Fp[3];
-                pair_force<T>(P, nh, (T)delta, wv, (T)mi, Fp);
-                acc[0] += Fp[0];
-                acc[1] += Fp[1];
-                acc[2] += Fp[2];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int32_t j = j0 + u;
+                if (j >= je || j == q) continue;
+                double d2;
+                if (!touching(xi[0] - cx[u], xi[1] - cy[u], xi[2] - cz[u], ri + cr[u], d2) || d2 == 0.0) continue;
+                if (cnt < kMaxPartners)
+                    plist[cnt * 256 + tid] = j;
+                else
+                    add_pair<T>(P, n, x, v, r, xi, vi, ri, mi, j, acc);  // rare: long partner list
                 ++cnt;
             }
-    }
+        }
+    });
+    const int listed = cnt < kMaxPartners ? cnt : kMaxPartners;
+    for (int k = 0; k < listed; ++k) add_pair<T>(P, n, x, v, r, xi, vi, ri, mi, plist[k * 256 + tid], acc);
+    add_walls<T>(P, xi, vi, ri, mi, acc, cnt);
     F[q] = acc[0];
     F[n + q] = acc[1];
     F[2 * n + q] = acc[2];
     if (ncont) ncont[q] = cnt;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_contact(DevParams P, int64_t n, int64_t nblk, const double *__restrict__ x,
+                                                 const double *__restrict__ v, const double *__restrict__ r,
+                                                 const int32_t *__restrict__ cb, const int32_t *__restrict__ ce,
+                                                 T *__restrict__ F, int32_t *__restrict__ ncont, int64_t *err)
+{
+    __shared__ int32_t plist[kMaxPartners * 256];
+    const int64_t lb = xcd_block(nblk);
+    if (lb < 0) return;
+    const int64_t q = lb * 256 + threadIdx.x;
+    if (q >= n) return;
+    contact_global<T>(P, n, x, v, r, cb, ce, q, plist, threadIdx.x, F, ncont, err);
+}
+
+// ---------------------------------------------------------------------------
+// LDS-staged contact: one workgroup per brick of 4x4x4 cells.  The 6x6x6
+// cells around the brick (the brick and a one-cell shell) are copied once
+// into LDS, cell after cell in (z, y, x) order with one empty slot (NaN
+// position, never touching) after each cell: when cells hold equal numbers
+// of granules, the slot keeps lanes that read different cells at the same
+// step on different LDS banks.  Consecutive cells of a row stay one
+// contiguous range of slots.  Each granule of the brick then tests its
+// candidates from LDS.  A brick whose shell does not fit takes the global
+// path.
+constexpr int kHaloCells = 216;
+constexpr int kLdsPartners = 12;
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_contact_lds(DevParams P, int64_t n, int64_t nbricks, int cap,
+                                                     const double *__restrict__ x, const double *__restrict__ v,
+                                                     const double *__restrict__ r, const int32_t *__restrict__ cb,
+                                                     const int32_t *__restrict__ ce, T *__restrict__ F,
+                                                     int32_t *__restrict__ ncont, int64_t *err)
+{
+    extern __shared__ double smem[];
+    double2 *sxy = reinterpret_cast<double2 *>(smem);            // [cap] (x, y)
+    double2 *szr = sxy + cap;                                      // [cap] (z, r)
+    int32_t *sg = reinterpret_cast<int32_t *>(szr + cap);         // [cap] global index of each slot
+    uint16_t *plist = reinterpret_cast<uint16_t *>(sg + cap);     // [kLdsPartners][256] partner slots
+    int32_t *clo = reinterpret_cast<int32_t *>(plist + kLdsPartners * 256);  // [216] first slot of each cell
+    int32_t *cnum = clo + kHaloCells;                              // [216] granules of each shell cell
+    int32_t *cgb = cnum + kHaloCells;                              // [216] global begin of each shell cell
+    __shared__ int32_t s_wave[4];
+    const int tid = threadIdx.x;
+    const int64_t b = xcd_block(nbricks);
+    if (b < 0) return;
+    const int32_t bc[3] = {(int32_t)(b % P.nb[0]), (int32_t)((b / P.nb[0]) % P.nb[1]),
+                           (int32_t)(b / ((int64_t)P.nb[0] * P.nb[1]))};
+    const int32_t c0[3] = {bc[0] * kBrick - 1, bc[1] * kBrick - 1, bc[2] * kBrick - 1};  // shell origin cell
+    const int32_t gb = cb[b * kBrickCells], ge = ce[b * kBrickCells + kBrickCells - 1];
+    if (ge <= gb) return;
+    // ---- shell cells: counts, then slots (count + 1 pad each) by a scan
+    int32_t num = 0, gbeg = 0;
+    if (tid < kHaloCells) {
+        const int hx = tid % 6, hy = (tid / 6) % 6, hz = tid / 36;
+        const int32_t cx = c0[0] + hx, cy = c0[1] + hy, cz = c0[2] + hz;
+        if (cx >= 0 && cy >= 0 && cz >= 0 && cx < P.nc[0] && cy < P.nc[1] && cz < P.nc[2]) {
+            const uint32_t k = key_of_cell(P, cx, cy, cz);
+            gbeg = cb[k];
+            num = ce[k] - gbeg;
+        }
+    }
+    const int32_t slots = tid < kHaloCells ? num + 1 : 0;
+    {
+        const int lane = tid & 63, wave = tid >> 6;
+        int32_t incl = slots;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int32_t t = __shfl_up(incl, off);
+            if (lane >= off) incl += t;
+        }
+        if (lane == 63) s_wave[wave] = incl;
+        __syncthreads();
+        int32_t before = 0;
+        for (int w = 0; w < wave; ++w) before += s_wave[w];
+        if (tid < kHaloCells) {
+            clo[tid] = before + incl - slots;
+            cnum[tid] = num;
+            cgb[tid] = gbeg;
+        }
+        __syncthreads();
+    }
+    const int32_t H = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+    if (H > cap) {  // shell too large for LDS: global candidate path for this brick
+        int32_t *glist = reinterpret_cast<int32_t *>(smem);  // the slot arrays are unused on this path
+        for (int64_t q = gb + tid; q < ge; q += 256) contact_global<T>(P, n, x, v, r, cb, ce, q, glist, tid, F, ncont, err);
+        return;
+    }
+    // ---- copy the shell's granules (and a NaN pad after each cell)
+    for (int k = tid; k < H; k += 256) {
+        int lo = 0, hi = kHaloCells;  // largest cell with clo <= k
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (clo[mid] <= k) lo = mid; else hi = mid;
+        }
+        const int off = k - clo[lo];
+        if (off < cnum[lo]) {
+            const int64_t g = cgb[lo] + off;
+            sxy[k] = make_double2(x[g], x[n + g]);
+            szr[k] = make_double2(x[2 * n + g], r[g]);
+            sg[k] = (int32_t)g;
+        } else {
+            const double nan = __builtin_nan("");
+            sxy[k] = make_double2(nan, nan);
+            szr[k] = make_double2(nan, 0.0);
+            sg[k] = -1;
+        }
+    }
+    __syncthreads();
+    // ---- granules of the brick
+    for (int64_t q = gb + tid; q < ge; q += 256) {
+        const double xi[3] = {x[q], x[n + q], x[2 * n + q]};
+        const double vi[3] = {v[q], v[n + q], v[2 * n + q]};
+        const double ri = r[q];
+        if (ri > P.r_max) raise_error(err, kErrRange, q);
+        const double mi = mass_of(P, ri);
+        const double Rs = (ri + P.r_max) * P.search_scale;
+        int32_t lo[3], hi[3];
+        for (int a = 0; a < 3; ++a) {
+            search_range(P, xi[a], Rs, P.nc[a], lo[a], hi[a]);
+            lo[a] -= c0[a];
+            hi[a] -= c0[a];
+        }
+        T acc[3] = {(T)0, (T)0, (T)0};
+        int32_t cnt = 0;
+        for (int hz = lo[2]; hz <= hi[2]; ++hz)
+            for (int hy = lo[1]; hy <= hi[1]; ++hy) {
+                const int c = (hz * 6 + hy) * 6;
+                // cells lo..hi of this row: one contiguous run of slots
+                const int k0 = clo[c + lo[0]];
+                const int k1 = clo[c + hi[0]] + cnum[c + hi[0]];
+                for (int k = k0; k < k1; ++k) {
+                    const double2 pxy = sxy[k], pzr = szr[k];
+                    double d2;
+                    if (!touching(xi[0] - pxy.x, xi[1] - pxy.y, xi[2] - pzr.x, ri + pzr.y, d2) || d2 == 0.0) continue;
+                    if (cnt < kLdsPartners) plist[cnt * 256 + tid] = (uint16_t)k;
+                    ++cnt;
+                }
+            }
+        const int listed = cnt < kLdsPartners ? cnt : kLdsPartners;
+        for (int i = 0; i < listed; ++i) add_pair<T>(P, n, x, v, r, xi, vi, ri, mi, sg[plist[i * 256 + tid]], acc);
+        if (cnt > kLdsPartners) {
+            // more partners than listed: walk the candidates again for the rest
+            int32_t seen = 0;
+            for (int hz = lo[2]; hz <= hi[2]; ++hz)
+                for (int hy = lo[1]; hy <= hi[1]; ++hy) {
+                    const int c = (hz * 6 + hy) * 6;
+                    const int k1 = clo[c + hi[0]] + cnum[c + hi[0]];
+                    for (int k = clo[c + lo[0]]; k < k1; ++k) {
+                        const double2 pxy = sxy[k], pzr = szr[k];
+                        double d2;
+                        if (!touching(xi[0] - pxy.x, xi[1] - pxy.y, xi[2] - pzr.x, ri + pzr.y, d2) || d2 == 0.0)
+                            continue;
+                        if (seen++ < kLdsPartners) continue;
+                        add_pair<T>(P, n, x, v, r, xi, vi, ri, mi, sg[k], acc);
+                    }
+                }
+        }
+        add_walls<T>(P, xi, vi, ri, mi, acc, cnt);
+        F[q] = acc[0];
+        F[n + q] = acc[1];
+        F[2 * n + q] = acc[2];
+        if (ncont) ncont[q] = cnt;
+    }
 }
 
 __global__ void __launch_bounds__(256) k_contact_pairs(DevParams P, int64_t n, const double *__restrict__ x,
@@ -117,34 +360,41 @@ __global__ void __launch_bounds__(256) k_contact_pairs(DevParams P, int64_t n, c
     const double Rs = (ri + P.r_max) * P.search_scale;
     int32_t lo[3], hi[3];
     for (int a = 0; a < 3; ++a) search_range(P, xi[a], Rs, P.nc[a], lo[a], hi[a]);
-    for (int32_t cz = lo[2]; cz <= hi[2]; ++cz)
-        for (int32_t cy = lo[1]; cy <= hi[1]; ++cy)
-            for (int32_t cx = lo[0]; cx <= hi[0]; ++cx) {
-                const uint32_t key = key_of_cell(P, cx, cy, cz);
-                const int32_t e = ce[key];
-                for (int32_t j = cb[key]; j < e; ++j) {
-                    if (j <= q) continue;
-                    double d2;
-                    if (!touching(xi[0] - x[j], xi[1] - x[n + j], xi[2] - x[2 * n + j], ri + r[j], d2)) continue;
-                    unsigned long long k = atomicAdd(count, 1ull);
-                    if ((int64_t)k < cap) {
-                        pairs[2 * k] = (int32_t)q;
-                        pairs[2 * k + 1] = j;
-                    }
-                }
+    for_each_run(P, lo, hi, cb, ce, [&](int32_t jb, int32_t je) {
+        for (int32_t j = jb; j < je; ++j) {
+            if (j <= q) continue;
+            double d2;
+            if (!touching(xi[0] - x[j], xi[1] - x[n + j], xi[2] - x[2 * n + j], ri + r[j], d2)) continue;
+            unsigned long long k = atomicAdd(count, 1ull);
+            if ((int64_t)k < cap) {
+                pairs[2 * k] = (int32_t)q;
+                pairs[2 * k + 1] = j;
             }
+        }
+    });
 }
 
 __global__ void k_zero_count(unsigned long long *c) { *c = 0ull; }
 
 }  // namespace
 
+// LDS bytes of the staged contact kernel for a shell capacity of cap granules.
+static size_t contact_lds_bytes(int cap)
+{
+    size_t b = (size_t)cap * 36 + sizeof(uint16_t) * kLdsPartners * 256 + sizeof(int32_t) * kHaloCells * 3;
+    const size_t fallback = sizeof(int32_t) * kMaxPartners * 256;  // list of the global path, aliasing the slots
+    return b > fallback ? b : fallback;
+}
+
 template <typename T>
 hipError_t launch_contact(const DevParams &P, int64_t n, const double *x, const double *v, const double *r,
                           const int32_t *cb, const int32_t *ce, T *F, int32_t *ncont, int64_t *err, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    k_contact<T><<<grid_for(n, 256), 256, 0, s>>>(P, n, x, v, r, cb, ce, F, ncont, err);
+    const int64_t nbricks = (int64_t)P.nb[0] * P.nb[1] * P.nb[2];
+    const int cap = 1960;  // shell slots held in LDS (< 65536 for 16-bit lists; two workgroups fit per CU)
+    k_contact_lds<T><<<xcd_grid(nbricks), 256, contact_lds_bytes(cap), s>>>(P, n, nbricks, cap, x, v, r, cb, ce, F,
+                                                                            ncont, err);
     return hipGetLastError();
 }
 

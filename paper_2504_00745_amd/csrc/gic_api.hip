@@ -15,6 +15,7 @@ struct gic_ctx {
     int64_t K;
     SortScratch sort;
     int64_t *err;  // device: [code, index]
+    double *part;  // device: partial sums of gic_sum
     int device;
 };
 
@@ -80,6 +81,8 @@ DevParams derive(const gic_params *p)
     d.mu = p->mu;
     d.rho_s = p->rho_s;
     d.cdrag = (p->c_drag * (6.0 * GIC_PI)) * p->eta_f;
+    d.c_drag = p->c_drag;
+    d.cdrag_unit = (6.0 * GIC_PI) * p->eta_f;
     d.alpha_max = p->alpha_max;
     d.dt = p->dt;
     d.r_max = p->r_max;
@@ -100,6 +103,8 @@ gic_status hip_status(hipError_t e) { return e == hipSuccess ? GIC_OK : GIC_E_HI
 bool fp32(const gic_ctx *c) { return c->p.precision == GIC_FP32; }
 
 bool n_ok(const gic_ctx *c, int64_t n) { return c && n >= 0 && n <= c->n_max; }
+
+constexpr int kSumParts = 1024;
 
 }  // namespace
 
@@ -134,7 +139,9 @@ gic_status gic_create(const gic_params *p, int64_t n_max, gic_ctx **out)
     ok &= hipMalloc(&c->sort.vA, sizeof(int32_t) * nn) == hipSuccess;
     ok &= hipMalloc(&c->sort.vB, sizeof(int32_t) * nn) == hipSuccess;
     ok &= hipMalloc(&c->sort.hist, sizeof(uint32_t) * 256 * tiles) == hipSuccess;
+    ok &= hipMalloc(&c->sort.sums, sizeof(uint32_t) * 1024) == hipSuccess;
     ok &= hipMalloc(&c->err, sizeof(int64_t) * 2) == hipSuccess;
+    ok &= hipMalloc(&c->part, sizeof(double) * kSumParts) == hipSuccess;
     if (ok) ok = hipMemset(c->err, 0, sizeof(int64_t) * 2) == hipSuccess;
     if (!ok) {
         gic_destroy(c);
@@ -165,7 +172,9 @@ gic_status gic_destroy(gic_ctx *c)
     (void)hipFree(c->sort.vA);
     (void)hipFree(c->sort.vB);
     (void)hipFree(c->sort.hist);
+    (void)hipFree(c->sort.sums);
     (void)hipFree(c->err);
+    (void)hipFree(c->part);
     delete c;
     return hip_status(e);
 }
@@ -324,6 +333,71 @@ gic_status gic_step(gic_ctx *c, int64_t n, const double *x_cur, const double *v_
         return st;
     if ((st = gic_integrate(c, n, r_nxt, f_contact, f_drag, x_nxt, v_nxt, stream)) != GIC_OK) return st;
     return gic_p2g(c, n, x_nxt, v_nxt, r_nxt, cell_begin, cell_end, alpha_fx, mom_fx, 0, stream);
+}
+
+/* ---- adjoint form (double) ---------------------------------------------- */
+
+gic_status gic_contact_forces_vjp(gic_ctx *c, int64_t n, const double *x, const double *v, const double *r,
+                                  const int32_t *cell_begin, const int32_t *cell_end, const double *g_f, double *g_x,
+                                  double *g_v, double *g_mu, void *stream)
+{
+    if (!n_ok(c, n) || fp32(c)) return GIC_E_ARG;
+    if (n > 0 && (!x || !v || !r || !cell_begin || !cell_end || !g_f || !g_x || !g_v || !g_mu)) return GIC_E_ARG;
+    return hip_status(launch_contact_vjp(c->dp, n, x, v, r, cell_begin, cell_end, g_f, g_x, g_v, g_mu,
+                                         (hipStream_t)stream));
+}
+
+gic_status gic_drag_vjp(gic_ctx *c, int64_t n, const double *r, const double *v, const double *u_at,
+                        const double *alpha_f, const double *g_f, double *g_v, double *g_u_at, double *g_alpha_f,
+                        double *g_cdrag, void *stream)
+{
+    if (!n_ok(c, n) || fp32(c)) return GIC_E_ARG;
+    if (n > 0 && (!r || !v || !u_at || !alpha_f || !g_f || !g_v || !g_u_at || !g_alpha_f || !g_cdrag))
+        return GIC_E_ARG;
+    return hip_status(
+        launch_drag_vjp(c->dp, n, r, v, u_at, alpha_f, g_f, g_v, g_u_at, g_alpha_f, g_cdrag, (hipStream_t)stream));
+}
+
+gic_status gic_integrate_vjp(gic_ctx *c, int64_t n, const double *r, const double *g_x, double *g_v, double *g_f,
+                             void *stream)
+{
+    if (!n_ok(c, n) || fp32(c)) return GIC_E_ARG;
+    if (n > 0 && (!r || !g_x || !g_v || !g_f)) return GIC_E_ARG;
+    return hip_status(launch_integrate_vjp(c->dp, n, r, g_x, g_v, g_f, (hipStream_t)stream));
+}
+
+gic_status gic_g2p_vjp(gic_ctx *c, int64_t n, const double *x, const double *u, const double *alpha_real,
+                       const double *g_u_at, const double *g_alpha_f, const int32_t *cell_begin,
+                       const int32_t *cell_end, double *g_x, double *g_alpha, void *stream)
+{
+    if (!n_ok(c, n) || fp32(c)) return GIC_E_ARG;
+    if (n > 0 && (!x || !u || !alpha_real || !g_u_at || !g_alpha_f || !g_x)) return GIC_E_ARG;
+    if (n > 0 && g_alpha && (!cell_begin || !cell_end)) return GIC_E_ARG;
+    return hip_status(launch_g2p_vjp(c->dp, n, c->K, x, u, alpha_real, g_u_at, g_alpha_f, cell_begin, cell_end, g_x,
+                                     g_alpha, (hipStream_t)stream));
+}
+
+gic_status gic_p2g_vjp(gic_ctx *c, int64_t n, const double *x, const double *v, const double *r,
+                       const double *g_alpha, const double *g_mom, double *g_x, double *g_v, void *stream)
+{
+    if (!n_ok(c, n)) return GIC_E_ARG;
+    if (n > 0 && (!x || !r || !g_x || (g_mom && (!v || !g_v)) || (!g_alpha && !g_mom))) return GIC_E_ARG;
+    return hip_status(launch_p2g_vjp(c->dp, n, x, v, r, g_alpha, g_mom, g_x, g_v, (hipStream_t)stream));
+}
+
+gic_status gic_sum(gic_ctx *c, int64_t n, const double *a, const double *b, double *out, int32_t accumulate,
+                   void *stream)
+{
+    if (!c || n < 0 || !out || (n > 0 && !a)) return GIC_E_ARG;
+    return hip_status(launch_sum(a, b, n, c->part, kSumParts, out, accumulate ? 1 : 0, (hipStream_t)stream));
+}
+
+gic_status gic_permute(gic_ctx *c, int64_t n, int32_t comps, const int32_t *order, const double *in, double *out,
+                       int32_t scatter, void *stream)
+{
+    if (!n_ok(c, n) || comps < 1 || comps > 3) return GIC_E_ARG;
+    if (n > 0 && (!order || !in || !out || in == out)) return GIC_E_ARG;
+    return hip_status(launch_permute(n, comps, order, in, out, scatter ? 1 : 0, (hipStream_t)stream));
 }
 
 }  // extern "C"

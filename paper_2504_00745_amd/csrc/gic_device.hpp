@@ -21,6 +21,27 @@ namespace gic {
 constexpr int kBrick = 4;                 // cells per brick edge in the key
 constexpr int kBrickCells = kBrick * kBrick * kBrick;
 
+// Workgroups are handed to the 8 XCDs round robin (workgroup b runs on XCD
+// b mod 8), and each XCD has its own L2.  Kernels whose neighbouring
+// workgroups read overlapping data remap their workgroup index so that each
+// XCD runs one contiguous eighth of the logical workgroups.  Launch with
+// xcd_grid(nlogical) workgroups; xcd_block returns the logical index or -1.
+constexpr int kXcds = 8;
+
+inline unsigned xcd_grid(int64_t nlogical)
+{
+    const int64_t per = (nlogical + kXcds - 1) / kXcds;
+    return (unsigned)(per * kXcds > 0 ? per * kXcds : kXcds);
+}
+
+__device__ inline int64_t xcd_block(int64_t nlogical)
+{
+    const int64_t per = (nlogical + kXcds - 1) / kXcds;
+    const int64_t b = blockIdx.x;
+    const int64_t l = (b % kXcds) * per + b / kXcds;
+    return l < nlogical ? l : -1;
+}
+
 // Latched error codes (same values as gic_status).
 constexpr int kErrDomain = 4;
 constexpr int kErrNonFinite = 5;
@@ -39,6 +60,7 @@ struct DevParams {
     double L[3];        // box edges n_a dx
     double kn, zeta, kt_ratio, mu;
     double rho_s, cdrag;  // cdrag = c_drag 6 pi eta_f
+    double c_drag, cdrag_unit;  // C_d and 6 pi eta_f separately (adjoint)
     double alpha_max;
     double g[3], dt;
     double r_max, search_scale;
@@ -144,20 +166,28 @@ constexpr double kFixLimit = 2251799813685248.0;  // 2^51
 // Pair (or wall) force of Eq. (1a)-(1c) with the dashpot reading, in real
 // type T.  nh: unit normal from the partner to this granule; delta: overlap;
 // w: relative velocity; meff: effective mass.  Returns 1 if capped.
+// Square root and quotient of the pair law: correctly rounded in double; in
+// float the hardware square root and reciprocal (about 1 ulp), far inside
+// the FP32 form's 1e-5 tolerance.
+__device__ inline double law_sqrt(double a) { return sqrt(a); }
+__device__ inline float law_sqrt(float a) { return __builtin_amdgcn_sqrtf(a); }
+__device__ inline double law_div(double a, double b) { return a / b; }
+__device__ inline float law_div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+
 template <typename T>
 __device__ inline int pair_force(const DevParams &P, const T nh[3], T delta, const T w[3], T meff, T F[3])
 {
     const T kn = (T)P.kn;
-    T gam = (T)2 * (T)P.zeta * sqrt(meff * kn);
+    T gam = (T)2 * (T)P.zeta * law_sqrt(meff * kn);
     T kt = (T)P.kt_ratio * gam;
     T vn = (w[0] * nh[0] + w[1] * nh[1]) + w[2] * nh[2];
     T fn = kn * delta - gam * vn;
     T ft[3];
     for (int a = 0; a < 3; ++a) ft[a] = -kt * (w[a] - vn * nh[a]);
-    T fts = sqrt((ft[0] * ft[0] + ft[1] * ft[1]) + ft[2] * ft[2]);
+    T fts = law_sqrt((ft[0] * ft[0] + ft[1] * ft[1]) + ft[2] * ft[2]);
     T cap = (T)P.mu * (kn * delta);
     int slide = fts > cap;
-    T s = slide ? cap / fts : (T)1;
+    T s = slide ? law_div(cap, fts) : (T)1;
     for (int a = 0; a < 3; ++a) F[a] = fn * nh[a] + ft[a] * s;
     return slide;
 }

@@ -14,6 +14,7 @@ struct SortScratch {
     uint32_t *kA, *kB, *skeys;
     int32_t *vA, *vB;
     uint32_t *hist;     // RADIX x tiles
+    uint32_t *sums;     // 1024 chunk totals of the digit-offset scan
     int64_t tiles_max;
     int passes;         // 8-bit digit passes over the key bits
 };
@@ -54,6 +55,24 @@ hipError_t launch_p2g_fixed(const DevParams &P, int64_t n, int64_t K, const doub
 hipError_t launch_p2g_real(const DevParams &P, int64_t n, int64_t K, const double *x, const double *v,
                            const double *r, const int32_t *cb, const int32_t *ce, double *alpha, double *mom,
                            hipStream_t s);
+
+hipError_t launch_contact_vjp(const DevParams &P, int64_t n, const double *x, const double *v, const double *r,
+                              const int32_t *cb, const int32_t *ce, const double *gF, double *gx, double *gv,
+                              double *gmu, hipStream_t s);
+hipError_t launch_drag_vjp(const DevParams &P, int64_t n, const double *r, const double *v, const double *uat,
+                           const double *af, const double *gF, double *gv, double *guat, double *gaf, double *gcd,
+                           hipStream_t s);
+hipError_t launch_integrate_vjp(const DevParams &P, int64_t n, const double *r, const double *gx, double *gv,
+                                double *gF, hipStream_t s);
+hipError_t launch_g2p_vjp(const DevParams &P, int64_t n, int64_t K, const double *x, const double *u,
+                          const double *A, const double *guat, const double *gaf, const int32_t *cb,
+                          const int32_t *ce, double *gx, double *gA, hipStream_t s);
+hipError_t launch_p2g_vjp(const DevParams &P, int64_t n, const double *x, const double *v, const double *r,
+                          const double *gA, const double *gP, double *gx, double *gv, hipStream_t s);
+hipError_t launch_sum(const double *a, const double *b, int64_t n, double *part, int nparts, double *out, int acc,
+                      hipStream_t s);
+hipError_t launch_permute(int64_t n, int comps, const int32_t *order, const double *in, double *out, int scatter,
+                          hipStream_t s);
 
 inline unsigned grid_for(int64_t n, int threads)
 {

@@ -50,31 +50,87 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint32_t *__r
     hist[(int64_t)tid * tiles + blockIdx.x] = h[tid];
 }
 
-// Exclusive prefix sum of len entries in place, one workgroup of 1024
-// threads: each thread sums a contiguous chunk, the chunk sums are scanned in
-// LDS, then each chunk is rewritten with its running prefix.
-__global__ void __launch_bounds__(1024) k_scan_exclusive(uint32_t *a, int64_t len)
+// Exclusive prefix sum in place, in three coalesced phases: each workgroup
+// reduces one contiguous chunk, one workgroup scans the chunk totals, then
+// each workgroup rescans its chunk 1024 entries at a time from its offset.
+constexpr int kScanThreads = 1024;
+
+__device__ inline uint32_t block_reduce_sum(uint32_t v, uint32_t *lds)
 {
-    __shared__ uint32_t part[1024];
-    const int tid = threadIdx.x;
-    const int64_t chunk = (len + 1023) / 1024;
-    const int64_t lo = tid * chunk;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) lds[wave] = v;
+    __syncthreads();
+    uint32_t t = 0;
+    if (threadIdx.x < 64) {
+        t = threadIdx.x < (blockDim.x >> 6) ? lds[threadIdx.x] : 0u;
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+    }
+    __syncthreads();
+    return t;  // valid in wave 0
+}
+
+// Inclusive scan over the workgroup (thread order); *total = sum of all.
+__device__ inline uint32_t block_scan_inclusive(uint32_t v, uint32_t *lds, uint32_t *total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t t = __shfl_up(v, off);
+        if (lane >= off) v += t;
+    }
+    if (lane == 63) lds[wave] = v;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int nw = blockDim.x >> 6;
+        uint32_t w = threadIdx.x < nw ? lds[threadIdx.x] : 0u;
+        for (int off = 1; off < 64; off <<= 1) {
+            uint32_t t = __shfl_up(w, off);
+            if (lane >= off) w += t;
+        }
+        if (threadIdx.x < nw) lds[threadIdx.x] = w;  // inclusive prefix of wave totals
+    }
+    __syncthreads();
+    const uint32_t before = wave > 0 ? lds[wave - 1] : 0u;
+    *total = lds[(blockDim.x >> 6) - 1];
+    __syncthreads();
+    return v + before;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const uint32_t *__restrict__ a, int64_t len,
+                                                              int64_t chunk, uint32_t *__restrict__ sums)
+{
+    __shared__ uint32_t lds[kScanThreads / 64];
+    const int64_t lo = (int64_t)blockIdx.x * chunk;
     const int64_t hi = lo + chunk < len ? lo + chunk : len;
     uint32_t s = 0;
-    for (int64_t k = lo; k < hi; ++k) s += a[k];
-    part[tid] = s;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        uint32_t t = tid >= off ? part[tid - off] : 0u;
-        __syncthreads();
-        part[tid] += t;
-        __syncthreads();
-    }
-    uint32_t run = part[tid] - s;
-    for (int64_t k = lo; k < hi; ++k) {
-        uint32_t t = a[k];
-        a[k] = run;
-        run += t;
+    for (int64_t k = lo + threadIdx.x; k < hi; k += kScanThreads) s += a[k];
+    s = block_reduce_sum(s, lds);
+    if (threadIdx.x == 0) sums[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_spine(uint32_t *sums, int nb)
+{
+    __shared__ uint32_t lds[kScanThreads / 64];
+    const uint32_t v = threadIdx.x < nb ? sums[threadIdx.x] : 0u;
+    uint32_t total;
+    const uint32_t inc = block_scan_inclusive(v, lds, &total);
+    if (threadIdx.x < nb) sums[threadIdx.x] = inc - v;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_down(uint32_t *__restrict__ a, int64_t len, int64_t chunk,
+                                                            const uint32_t *__restrict__ sums)
+{
+    __shared__ uint32_t lds[kScanThreads / 64];
+    const int64_t lo = (int64_t)blockIdx.x * chunk;
+    const int64_t hi = lo + chunk < len ? lo + chunk : len;
+    uint32_t carry = sums[blockIdx.x];
+    for (int64_t base = lo; base < hi; base += kScanThreads) {
+        const int64_t k = base + threadIdx.x;
+        const uint32_t v = k < hi ? a[k] : 0u;
+        uint32_t total;
+        const uint32_t inc = block_scan_inclusive(v, lds, &total);
+        if (k < hi) a[k] = carry + inc - v;
+        carry += total;
     }
 }
 
@@ -139,15 +195,45 @@ __global__ void __launch_bounds__(256) k_fill_i32(int32_t *a, int64_t len, int32
         a[i] = v;
 }
 
-// begin/end of each occupied cell from the sorted keys.
-__global__ void __launch_bounds__(256) k_cell_ranges(const uint32_t *__restrict__ sk, int64_t n,
-                                                     int32_t *__restrict__ cb, int32_t *__restrict__ ce)
+// Number of granules per cell key, from the sorted keys: the first lane of
+// each run of equal keys inside a wave adds the run's length.
+__global__ void __launch_bounds__(256) k_cell_count(const uint32_t *__restrict__ sk, int64_t n,
+                                                    uint32_t *__restrict__ cnt)
 {
-    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n) return;
-    uint32_t k = sk[q];
-    if (q == 0 || sk[q - 1] != k) cb[k] = (int32_t)q;
-    if (q == n - 1 || sk[q + 1] != k) ce[k] = (int32_t)(q + 1);
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const bool valid = q < n;
+    const uint32_t k = valid ? sk[q] : 0u;
+    const bool start = valid && (lane == 0 || sk[q - 1] != k);
+    const uint64_t starts = __ballot(start) | (~__ballot(valid));  // invalid lanes end the last run
+    if (start) {
+        const uint64_t above = lane == 63 ? 0ull : (starts >> (lane + 1)) << (lane + 1);
+        const int next = above ? __ffsll((unsigned long long)above) - 1 : 64;
+        atomicAdd(&cnt[k], (uint32_t)(next - lane));
+    }
+}
+
+// Last phase of the scan of the per-cell counts: begin = exclusive prefix,
+// end = inclusive prefix (end overwrites the counts in place).
+__global__ void __launch_bounds__(kScanThreads) k_scan_down_ranges(uint32_t *__restrict__ cnt_end,
+                                                                   uint32_t *__restrict__ begin, int64_t len,
+                                                                   int64_t chunk, const uint32_t *__restrict__ sums)
+{
+    __shared__ uint32_t lds[kScanThreads / 64];
+    const int64_t lo = (int64_t)blockIdx.x * chunk;
+    const int64_t hi = lo + chunk < len ? lo + chunk : len;
+    uint32_t carry = sums[blockIdx.x];
+    for (int64_t base = lo; base < hi; base += kScanThreads) {
+        const int64_t k = base + threadIdx.x;
+        const uint32_t v = k < hi ? cnt_end[k] : 0u;
+        uint32_t total;
+        const uint32_t inc = block_scan_inclusive(v, lds, &total);
+        if (k < hi) {
+            begin[k] = carry + inc - v;
+            cnt_end[k] = carry + inc;
+        }
+        carry += total;
+    }
 }
 
 __global__ void __launch_bounds__(256) k_reorder(int64_t n, const int32_t *__restrict__ order,
@@ -169,33 +255,54 @@ __global__ void __launch_bounds__(256) k_reorder(int64_t n, const int32_t *__res
 
 }  // namespace
 
+namespace {
+
+int64_t scan_chunk(int64_t len)
+{
+    int64_t chunk = (len + kScanThreads - 1) / kScanThreads;
+    return ((chunk + kScanThreads - 1) / kScanThreads) * kScanThreads;
+}
+
+}  // namespace
+
 hipError_t launch_sort_cells(const DevParams &P, int64_t n, const double *x, uint32_t *key, int32_t *order,
                              int32_t *cell_begin, int32_t *cell_end, int64_t K, SortScratch &S, int64_t *err,
                              hipStream_t s)
 {
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(cell_end);
     {
         unsigned g = grid_for(K, 256);
         if (g > 65536) g = 65536;
-        k_fill_i32<<<g, 256, 0, s>>>(cell_begin, K, 0);
         k_fill_i32<<<g, 256, 0, s>>>(cell_end, K, 0);
     }
-    if (n == 0) return hipGetLastError();
-    k_cell_keys<<<grid_for(n, 256), 256, 0, s>>>(P, n, x, key, err);
-    const int64_t tiles = (n + kSortTile - 1) / kSortTile;
-    const uint32_t *kin = key;
-    const int32_t *vin = nullptr;
-    for (int pass = 0; pass < S.passes; ++pass) {
-        const bool last = pass == S.passes - 1;
-        uint32_t *kout = last ? S.skeys : ((pass & 1) ? S.kB : S.kA);
-        int32_t *vout = last ? order : ((pass & 1) ? S.vB : S.vA);
-        const int shift = 8 * pass;
-        k_radix_hist<<<(unsigned)tiles, kSortThreads, 0, s>>>(kin, n, shift, S.hist, tiles);
-        k_scan_exclusive<<<1, 1024, 0, s>>>(S.hist, tiles * kRadix);
-        k_radix_scatter<<<(unsigned)tiles, kSortThreads, 0, s>>>(kin, vin, kout, vout, n, shift, S.hist, tiles);
-        kin = kout;
-        vin = vout;
+    if (n > 0) {
+        k_cell_keys<<<grid_for(n, 256), 256, 0, s>>>(P, n, x, key, err);
+        const int64_t tiles = (n + kSortTile - 1) / kSortTile;
+        const uint32_t *kin = key;
+        const int32_t *vin = nullptr;
+        for (int pass = 0; pass < S.passes; ++pass) {
+            const bool last = pass == S.passes - 1;
+            uint32_t *kout = last ? S.skeys : ((pass & 1) ? S.kB : S.kA);
+            int32_t *vout = last ? order : ((pass & 1) ? S.vB : S.vA);
+            const int shift = 8 * pass;
+            k_radix_hist<<<(unsigned)tiles, kSortThreads, 0, s>>>(kin, n, shift, S.hist, tiles);
+            const int64_t len = tiles * kRadix;
+            const int64_t chunk = scan_chunk(len);
+            const int nb = (int)((len + chunk - 1) / chunk);
+            k_scan_reduce<<<nb, kScanThreads, 0, s>>>(S.hist, len, chunk, S.sums);
+            k_scan_spine<<<1, kScanThreads, 0, s>>>(S.sums, nb);
+            k_scan_down<<<nb, kScanThreads, 0, s>>>(S.hist, len, chunk, S.sums);
+            k_radix_scatter<<<(unsigned)tiles, kSortThreads, 0, s>>>(kin, vin, kout, vout, n, shift, S.hist, tiles);
+            kin = kout;
+            vin = vout;
+        }
+        k_cell_count<<<grid_for(n, 256), 256, 0, s>>>(S.skeys, n, cnt);
     }
-    k_cell_ranges<<<grid_for(n, 256), 256, 0, s>>>(S.skeys, n, cell_begin, cell_end);
+    const int64_t chunk = scan_chunk(K);
+    const int nb = (int)((K + chunk - 1) / chunk);
+    k_scan_reduce<<<nb, kScanThreads, 0, s>>>(cnt, K, chunk, S.sums);
+    k_scan_spine<<<1, kScanThreads, 0, s>>>(S.sums, nb);
+    k_scan_down_ranges<<<nb, kScanThreads, 0, s>>>(cnt, reinterpret_cast<uint32_t *>(cell_begin), K, chunk, S.sums);
     return hipGetLastError();
 }
 

@@ -67,7 +67,36 @@ __device__ inline void tile_origin(const DevParams &P, int64_t b, int32_t o[3])
     for (int a = 0; a < 3; ++a) o[a] = (int32_t)floor((double)(bc[a] * kBrick) * P.cell * P.inv_dx) - 1;
 }
 
-__global__ void __launch_bounds__(kP2GThreads) k_p2g_fixed(DevParams P, int64_t n, const double *__restrict__ x,
+// Flat stencil slot (0..26, x fastest; 13 is the centre) -> 1-D offsets.
+__device__ inline void slot_offsets(int slot, int &cx, int &cy, int &cz)
+{
+    cz = slot / 9;
+    cy = (slot / 3) % 3;
+    cx = slot % 3;
+}
+
+__device__ inline void tile_add(unsigned long long *tile, unsigned long long *glob, bool in, int lidx,
+                                int64_t gidx, int64_t val)
+{
+    if (val == 0) return;
+    if (in)
+        atomicAdd(&tile[lidx], (unsigned long long)val);
+    else
+        atomicAdd(&glob[gidx], (unsigned long long)val);
+}
+
+// One workgroup per brick, granules taken in batches.  Phase 1 (a thread per
+// granule) computes the 1-D weights, the scaled totals S and the centre
+// remainder Q - sum of the 26 outer contributions, into LDS.  Consecutive
+// sorted granules with the same stencil base form a run; they share all 27
+// nodes.  Phase 2 (a thread per run and slot) sums the run's integer
+// contributions rint(w S) in registers and issues one LDS atomic per
+// channel, instead of one per granule; the 27 slots of a run sit on
+// neighbouring lanes, so their LDS reads of the run's granule data are
+// broadcasts and their atomics go to distinct nodes.
+template <bool MOM>
+__global__ void __launch_bounds__(kP2GThreads) k_p2g_fixed(DevParams P, int64_t n, int64_t nbricks, int batch,
+                                                           const double *__restrict__ x,
                                                            const double *__restrict__ v,
                                                            const double *__restrict__ r,
                                                            const int32_t *__restrict__ cb,
@@ -76,90 +105,156 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g_fixed(DevParams P, int64_t 
                                                            unsigned long long *__restrict__ mom, int64_t *err)
 {
 #pragma clang fp contract(off)
+    constexpr int NCH = MOM ? 4 : 1;
     extern __shared__ unsigned long long tile[];
     __shared__ int32_t s_range[2];
-    const int64_t b = blockIdx.x;
+    __shared__ int32_t s_wave[kP2GThreads / 64];
+    const int64_t b = xcd_block(nbricks);
+    if (b < 0) return;
     brick_range(b, cb, ce, s_range);
     __syncthreads();
     const int32_t beg = s_range[0], end = s_range[1];
     if (end <= beg) return;
     const int E = P.tile;
     const int E3 = E * E * E;
-    const int nch = mom ? 4 : 1;
-    for (int k = threadIdx.x; k < nch * E3; k += kP2GThreads) tile[k] = 0ull;
+    double *sw = reinterpret_cast<double *>(tile + NCH * E3);          // [9][batch]
+    double *sS = sw + 9 * batch;                                        // [NCH][batch]
+    int64_t *srest = reinterpret_cast<int64_t *>(sS + NCH * batch);    // [NCH][batch]
+    int32_t *sbase = reinterpret_cast<int32_t *>(srest + NCH * batch);  // [3][batch]
+    int32_t *srun = sbase + 3 * batch;                                  // [batch + 1]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int k = tid; k < NCH * E3; k += kP2GThreads) tile[k] = 0ull;
     int32_t o[3];
     tile_origin(P, b, o);
-    __syncthreads();
-    const int64_t G = P.G;
-    for (int64_t q = beg + (int64_t)threadIdx.x; q < end; q += kP2GThreads) {
-        const double xa[3] = {x[q], x[n + q], x[2 * n + q]};
-        Stencil s;
-        stencil_of(P, xa, s);
-        const double frac = volume_of(r[q]) * P.inv_vcell;
-        double S[4];
-        S[0] = frac * GIC_TWO32;
-        for (int c = 0; c < 3; ++c) S[c + 1] = mom ? (frac * v[c * n + q]) * GIC_TWO32 : 0.0;
-        bool ok = true;
-        for (int c = 0; c < nch; ++c) ok &= fabs(S[c]) < kFixLimit;
-        if (!ok) {
-            raise_error(err, isfinite(S[0] + S[1] + S[2] + S[3]) ? kErrRange : kErrNonFinite, q);
-            continue;
-        }
-        int64_t rest[4];
-        for (int c = 0; c < nch; ++c) rest[c] = rint_i64(S[c]);
-        for (int cz = 0; cz < 3; ++cz)
-            for (int cy = 0; cy < 3; ++cy)
-                for (int cx = 0; cx < 3; ++cx) {
-                    const bool centre = cx == 1 && cy == 1 && cz == 1;
-                    const double w = (s.w[0][cx] * s.w[1][cy]) * s.w[2][cz];
-                    const int32_t ni = s.node[0][cx], nj = s.node[1][cy], nk = s.node[2][cz];
-                    const int32_t li = ni - o[0], lj = nj - o[1], lk = nk - o[2];
-                    const bool in = li >= 0 && lj >= 0 && lk >= 0 && li < E && lj < E && lk < E;
-                    const int lidx = (lk * E + lj) * E + li;
-                    const int64_t gidx = node_index(P, ni, nj, nk);
-                    for (int c = 0; c < nch; ++c) {
-                        int64_t val;
-                        if (centre) {
-                            continue;
-                        } else {
-                            val = rint_i64(w * S[c]);
-                            rest[c] -= val;
-                        }
-                        if (val == 0) continue;
-                        if (in)
-                            atomicAdd(&tile[c * E3 + lidx], (unsigned long long)val);
-                        else
-                            atomicAdd(c == 0 ? &alpha[gidx] : &mom[(c - 1) * G + gidx], (unsigned long long)val);
+    unsigned long long *glob[4] = {alpha, mom, mom ? mom + P.G : nullptr, mom ? mom + 2 * P.G : nullptr};
+    for (int64_t b0 = beg; b0 < end; b0 += batch) {
+        const int m = (int)(end - b0 < batch ? end - b0 : batch);
+        // ---- phase 1: per granule
+        int32_t base[3] = {0, 0, 0};
+        if (tid < m) {
+            const int64_t q = b0 + tid;
+            const double xa[3] = {x[q], x[n + q], x[2 * n + q]};
+            double w[3][3];
+            for (int a = 0; a < 3; ++a) {
+                const double t = xa[a] * P.inv_dx;
+                double fb = floor(t - 1.0);
+                const double f = (t - fb) - 0.5;
+                const double c0 = 1.5 - f, c1 = f - 1.0, c2 = f - 0.5;
+                w[a][0] = 0.5 * (c0 * c0);
+                w[a][1] = 0.75 - c1 * c1;
+                w[a][2] = 0.5 * (c2 * c2);
+                if (!(fb >= -2.0)) fb = -2.0;
+                if (fb > (double)P.n[a]) fb = (double)P.n[a];
+                base[a] = (int32_t)fb;
+                for (int k = 0; k < 3; ++k) sw[(a * 3 + k) * batch + tid] = w[a][k];
+                sbase[a * batch + tid] = base[a];
+            }
+            const double frac = volume_of(r[q]) * P.inv_vcell;
+            double S[NCH];
+            S[0] = frac * GIC_TWO32;
+            if (MOM)
+#pragma unroll
+                for (int c = 1; c < NCH; ++c) S[c] = (frac * v[(c - 1) * n + q]) * GIC_TWO32;
+            bool ok = true;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) ok &= fabs(S[c]) < kFixLimit;
+            if (!ok) {
+                double sum = 0.0;
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) sum += S[c];
+                raise_error(err, isfinite(sum) ? kErrRange : kErrNonFinite, q);
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) S[c] = 0.0;
+            }
+            int64_t rest[NCH];
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) rest[c] = rint_i64(S[c]);
+            for (int cz = 0; cz < 3; ++cz)
+                for (int cy = 0; cy < 3; ++cy)
+                    for (int cx = 0; cx < 3; ++cx) {
+                        if (cx == 1 && cy == 1 && cz == 1) continue;
+                        const double ww = (w[0][cx] * w[1][cy]) * w[2][cz];
+#pragma unroll
+                        for (int c = 0; c < NCH; ++c) rest[c] -= rint_i64(ww * S[c]);
                     }
-                }
-        {
-            const int32_t ni = s.node[0][1], nj = s.node[1][1], nk = s.node[2][1];
-            const int32_t li = ni - o[0], lj = nj - o[1], lk = nk - o[2];
-            const bool in = li >= 0 && lj >= 0 && lk >= 0 && li < E && lj < E && lk < E;
-            const int lidx = (lk * E + lj) * E + li;
-            const int64_t gidx = node_index(P, ni, nj, nk);
-            for (int c = 0; c < nch; ++c) {
-                if (rest[c] == 0) continue;
-                if (in)
-                    atomicAdd(&tile[c * E3 + lidx], (unsigned long long)rest[c]);
-                else
-                    atomicAdd(c == 0 ? &alpha[gidx] : &mom[(c - 1) * G + gidx], (unsigned long long)rest[c]);
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                sS[c * batch + tid] = S[c];
+                srest[c * batch + tid] = rest[c];
             }
         }
+        __syncthreads();
+        // ---- runs of equal stencil base
+        bool start = false;
+        if (tid < m) {
+            start = tid == 0;
+            if (!start)
+                for (int a = 0; a < 3; ++a) start |= sbase[a * batch + tid - 1] != base[a];
+        }
+        const uint64_t smask = __ballot(start);
+        if (lane == 0) s_wave[wave] = (int32_t)__popcll(smask);
+        __syncthreads();
+        int off = 0, nruns = 0;
+        for (int w = 0; w < kP2GThreads / 64; ++w) {
+            off += w < wave ? s_wave[w] : 0;
+            nruns += s_wave[w];
+        }
+        if (start) {
+            const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+            srun[off + __popcll(smask & lt)] = tid;
+        }
+        if (tid == 0) srun[nruns] = m;
+        __syncthreads();
+        // ---- phase 2: per run and slot
+        for (int task = tid; task < nruns * 27; task += kP2GThreads) {
+            const int rr = task / 27;
+            const int slot = task - rr * 27;
+            const int g0 = srun[rr], g1 = srun[rr + 1];
+            int cx, cy, cz;
+            slot_offsets(slot, cx, cy, cz);
+            int64_t acc[NCH];
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) acc[c] = 0;
+            if (slot == 13) {
+                for (int g = g0; g < g1; ++g)
+#pragma unroll
+                    for (int c = 0; c < NCH; ++c) acc[c] += srest[c * batch + g];
+            } else {
+                for (int g = g0; g < g1; ++g) {
+                    const double ww = (sw[cx * batch + g] * sw[(3 + cy) * batch + g]) * sw[(6 + cz) * batch + g];
+#pragma unroll
+                    for (int c = 0; c < NCH; ++c) acc[c] += rint_i64(ww * sS[c * batch + g]);
+                }
+            }
+            const int off3[3] = {cx, cy, cz};
+            int32_t nd[3];
+            for (int a = 0; a < 3; ++a) {
+                int32_t id = sbase[a * batch + g0] + off3[a];
+                id = id < 0 ? 0 : id;
+                id = id > P.n[a] - 1 ? P.n[a] - 1 : id;
+                nd[a] = id;
+            }
+            const int32_t li = nd[0] - o[0], lj = nd[1] - o[1], lk = nd[2] - o[2];
+            const bool in = li >= 0 && lj >= 0 && lk >= 0 && li < E && lj < E && lk < E;
+            const int lidx = (lk * E + lj) * E + li;
+            const int64_t gidx = node_index(P, nd[0], nd[1], nd[2]);
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) tile_add(tile + c * E3, glob[c], in, lidx, gidx, acc[c]);
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    for (int k = threadIdx.x; k < nch * E3; k += kP2GThreads) {
+    for (int k = tid; k < NCH * E3; k += kP2GThreads) {
         const unsigned long long val = tile[k];
         if (val == 0ull) continue;
         const int c = k / E3;
         const int l = k - c * E3;
         const int32_t ni = o[0] + l % E, nj = o[1] + (l / E) % E, nk = o[2] + l / (E * E);
-        const int64_t gidx = node_index(P, ni, nj, nk);
-        atomicAdd(c == 0 ? &alpha[gidx] : &mom[(c - 1) * G + gidx], val);
+        atomicAdd(&glob[c][node_index(P, ni, nj, nk)], val);
     }
 }
 
-__global__ void __launch_bounds__(kP2GThreads) k_p2g_real(DevParams P, int64_t n, const double *__restrict__ x,
+__global__ void __launch_bounds__(kP2GThreads) k_p2g_real(DevParams P, int64_t n, int64_t nbricks,
+                                                          const double *__restrict__ x,
                                                           const double *__restrict__ v,
                                                           const double *__restrict__ r,
                                                           const int32_t *__restrict__ cb,
@@ -168,7 +263,8 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g_real(DevParams P, int64_t n
 {
     extern __shared__ double dtile[];
     __shared__ int32_t s_range[2];
-    const int64_t b = blockIdx.x;
+    const int64_t b = xcd_block(nbricks);
+    if (b < 0) return;
     brick_range(b, cb, ce, s_range);
     __syncthreads();
     const int32_t beg = s_range[0], end = s_range[1];
@@ -221,12 +317,14 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g_real(DevParams P, int64_t n
 }
 
 template <typename T, bool FIXED>
-__global__ void __launch_bounds__(256) k_g2p(DevParams P, int64_t n, const double *__restrict__ x,
+__global__ void __launch_bounds__(256) k_g2p(DevParams P, int64_t n, int64_t nblk, const double *__restrict__ x,
                                              const T *__restrict__ u, const int64_t *__restrict__ afx,
                                              const double *__restrict__ are, T *__restrict__ uat,
                                              T *__restrict__ af)
 {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t lb = xcd_block(nblk);
+    if (lb < 0) return;
+    const int64_t q = lb * 256 + threadIdx.x;
     if (q >= n) return;
     const double xa[3] = {x[q], x[n + q], x[2 * n + q]};
     Stencil s;
@@ -275,6 +373,12 @@ hipError_t launch_fill_f64(double *a, int64_t len, hipStream_t s)
     return hipGetLastError();
 }
 
+// LDS bytes of the fixed-point P2G: node tile plus per-granule batch data.
+static size_t p2g_lds(int nch, int E3, int batch)
+{
+    return sizeof(unsigned long long) * (size_t)nch * E3 + (size_t)batch * (9 * 8 + nch * 16 + 3 * 4 + 4) + 4;
+}
+
 hipError_t launch_p2g_fixed(const DevParams &P, int64_t n, int64_t K, const double *x, const double *v,
                             const double *r, const int32_t *cb, const int32_t *ce, int64_t *alpha, int64_t *mom,
                             int64_t *err, hipStream_t s)
@@ -282,10 +386,17 @@ hipError_t launch_p2g_fixed(const DevParams &P, int64_t n, int64_t K, const doub
     if (n == 0) return hipSuccess;
     const int64_t bricks = K / kBrickCells;
     const int E3 = P.tile * P.tile * P.tile;
-    const size_t lds = sizeof(unsigned long long) * (size_t)(mom ? 4 : 1) * E3;
-    k_p2g_fixed<<<(unsigned)bricks, kP2GThreads, lds, s>>>(P, n, x, v, r, cb, ce,
-                                                           reinterpret_cast<unsigned long long *>(alpha),
-                                                           reinterpret_cast<unsigned long long *>(mom), err);
+    const int nch = mom ? 4 : 1;
+    int batch = 256;
+    while (batch > 32 && p2g_lds(nch, E3, batch) > 65536) batch /= 2;
+    const size_t lds = p2g_lds(nch, E3, batch);
+    if (mom)
+        k_p2g_fixed<true><<<xcd_grid(bricks), kP2GThreads, lds, s>>>(
+            P, n, bricks, batch, x, v, r, cb, ce, reinterpret_cast<unsigned long long *>(alpha),
+            reinterpret_cast<unsigned long long *>(mom), err);
+    else
+        k_p2g_fixed<false><<<xcd_grid(bricks), kP2GThreads, lds, s>>>(
+            P, n, bricks, batch, x, v, r, cb, ce, reinterpret_cast<unsigned long long *>(alpha), nullptr, err);
     return hipGetLastError();
 }
 
@@ -297,7 +408,7 @@ hipError_t launch_p2g_real(const DevParams &P, int64_t n, int64_t K, const doubl
     const int64_t bricks = K / kBrickCells;
     const int E3 = P.tile * P.tile * P.tile;
     const size_t lds = sizeof(double) * 4 * (size_t)E3;
-    k_p2g_real<<<(unsigned)bricks, kP2GThreads, lds, s>>>(P, n, x, v, r, cb, ce, alpha, mom);
+    k_p2g_real<<<xcd_grid(bricks), kP2GThreads, lds, s>>>(P, n, bricks, x, v, r, cb, ce, alpha, mom);
     return hipGetLastError();
 }
 
@@ -306,10 +417,11 @@ hipError_t launch_g2p(const DevParams &P, int64_t n, const double *x, const T *u
                       const double *are, T *uat, T *af, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
+    const int64_t nblk = (n + 255) / 256;
     if (afx)
-        k_g2p<T, true><<<grid_for(n, 256), 256, 0, s>>>(P, n, x, u, afx, nullptr, uat, af);
+        k_g2p<T, true><<<xcd_grid(nblk), 256, 0, s>>>(P, n, nblk, x, u, afx, nullptr, uat, af);
     else
-        k_g2p<T, false><<<grid_for(n, 256), 256, 0, s>>>(P, n, x, u, nullptr, are, uat, af);
+        k_g2p<T, false><<<xcd_grid(nblk), 256, 0, s>>>(P, n, nblk, x, u, nullptr, are, uat, af);
     return hipGetLastError();
 }
 

@@ -66,6 +66,13 @@ def lib():
             "gic_p2g": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V, _I32, _V]),
             "gic_p2g_real": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V, _I32, _V]),
             "gic_step": (C.c_int, [_V, _I64] + [_V] * 19),
+            "gic_contact_forces_vjp": (C.c_int, [_V, _I64] + [_V] * 10),
+            "gic_drag_vjp": (C.c_int, [_V, _I64] + [_V] * 10),
+            "gic_integrate_vjp": (C.c_int, [_V, _I64] + [_V] * 5),
+            "gic_g2p_vjp": (C.c_int, [_V, _I64] + [_V] * 10),
+            "gic_p2g_vjp": (C.c_int, [_V, _I64] + [_V] * 8),
+            "gic_sum": (C.c_int, [_V, _I64, _V, _V, _V, _I32, _V]),
+            "gic_permute": (C.c_int, [_V, _I64, _I32, _V, _V, _V, _I32, _V]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -249,6 +256,62 @@ def gic_step(ctx, cur, nxt, u, alpha_fx, mom_fx, scratch):
                           _ptr(s["cell_end"], torch.int32, ctx.K), _ptr(s["f_contact"], ctx.real, 3 * n),
                           _ptr(s["f_drag"], ctx.real, 3 * n), _ptr(s["u_at"], ctx.real, 3 * n),
                           _ptr(s["alpha_f"], ctx.real, n), _stream()), "gic_step")
+
+
+# ---- adjoint form (double) ----------------------------------------------------
+
+def gic_contact_forces_vjp(ctx, x, v, r, cell_begin, cell_end, g_f, g_x, g_v, g_mu):
+    n = x.shape[-1]
+    f64 = torch.float64
+    _check(lib().gic_contact_forces_vjp(ctx.handle, n, _ptr(x, f64, 3 * n), _ptr(v, f64, 3 * n), _ptr(r, f64, n),
+                                        _ptr(cell_begin, torch.int32, ctx.K), _ptr(cell_end, torch.int32, ctx.K),
+                                        _ptr(g_f, f64, 3 * n), _ptr(g_x, f64, 3 * n), _ptr(g_v, f64, 3 * n),
+                                        _ptr(g_mu, f64, n), _stream()), "gic_contact_forces_vjp")
+
+
+def gic_drag_vjp(ctx, r, v, u_at, alpha_f, g_f, g_v, g_u_at, g_alpha_f, g_cdrag):
+    n = r.shape[-1]
+    f64 = torch.float64
+    _check(lib().gic_drag_vjp(ctx.handle, n, _ptr(r, f64, n), _ptr(v, f64, 3 * n), _ptr(u_at, f64, 3 * n),
+                              _ptr(alpha_f, f64, n), _ptr(g_f, f64, 3 * n), _ptr(g_v, f64, 3 * n),
+                              _ptr(g_u_at, f64, 3 * n), _ptr(g_alpha_f, f64, n), _ptr(g_cdrag, f64, n), _stream()),
+           "gic_drag_vjp")
+
+
+def gic_integrate_vjp(ctx, r, g_x, g_v, g_f):
+    n = r.shape[-1]
+    f64 = torch.float64
+    _check(lib().gic_integrate_vjp(ctx.handle, n, _ptr(r, f64, n), _ptr(g_x, f64, 3 * n), _ptr(g_v, f64, 3 * n),
+                                   _ptr(g_f, f64, 3 * n), _stream()), "gic_integrate_vjp")
+
+
+def gic_g2p_vjp(ctx, x, u, alpha_real, g_u_at, g_alpha_f, cell_begin, cell_end, g_x, g_alpha):
+    n = x.shape[-1]
+    f64 = torch.float64
+    _check(lib().gic_g2p_vjp(ctx.handle, n, _ptr(x, f64, 3 * n), _ptr(u, f64, 3 * ctx.G),
+                             _ptr(alpha_real, f64, ctx.G), _ptr(g_u_at, f64, 3 * n), _ptr(g_alpha_f, f64, n),
+                             _ptr(cell_begin, torch.int32, ctx.K), _ptr(cell_end, torch.int32, ctx.K),
+                             _ptr(g_x, f64, 3 * n), _ptr(g_alpha, f64, ctx.G), _stream()), "gic_g2p_vjp")
+
+
+def gic_p2g_vjp(ctx, x, v, r, g_alpha, g_mom, g_x, g_v):
+    n = x.shape[-1]
+    f64 = torch.float64
+    _check(lib().gic_p2g_vjp(ctx.handle, n, _ptr(x, f64, 3 * n), _ptr(v, f64, 3 * n), _ptr(r, f64, n),
+                             _ptr(g_alpha, f64, ctx.G), _ptr(g_mom, f64, 3 * ctx.G), _ptr(g_x, f64, 3 * n),
+                             _ptr(g_v, f64, 3 * n), _stream()), "gic_p2g_vjp")
+
+
+def gic_sum(ctx, a, out, b=None, accumulate=False):
+    _check(lib().gic_sum(ctx.handle, a.numel(), _ptr(a, torch.float64), _ptr(b, torch.float64, a.numel()),
+                         _ptr(out, torch.float64, 1), int(bool(accumulate)), _stream()), "gic_sum")
+
+
+def gic_permute(ctx, order, src, dst, comps, scatter):
+    n = order.numel()
+    _check(lib().gic_permute(ctx.handle, n, int(comps), _ptr(order, torch.int32, n),
+                             _ptr(src, torch.float64, comps * n), _ptr(dst, torch.float64, comps * n),
+                             int(bool(scatter)), _stream()), "gic_permute")
 
 
 class Simulator:

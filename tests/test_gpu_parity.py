@@ -224,7 +224,7 @@ def test_contact_dense_brick_and_many_partners(G, orc, prec):
     rng = np.random.Generator(np.random.PCG64(21))
     # 3000 small granules packed in one 0.08 m brick (cell 0.02): shell overflow
     xs = rng.uniform(0.405, 0.475, (3, 3000))
-    rs = np.full(3000, 0.0012)
+    rs = np.full(3000, 0.0018)
     # big granules each ringed by 30 small touching ones: long partner lists
     big = []
     for c in ([0.9, 0.9, 0.9], [0.3, 1.0, 0.6]):
@@ -241,7 +241,7 @@ def test_contact_dense_brick_and_many_partners(G, orc, prec):
     u = np.zeros((3, int(np.prod(cfg["n"]))))
     out = G.run_stages(cfg, x, v, r, u, prec, r_max=0.0099)
     Fc, fa, nc, ns = orc.contact_forces(cfg, x, v, r)
-    assert nc.max() >= 20 and nc[:3000].sum() > 3000
+    assert nc.max() >= 20 and nc[:3000].sum() > 3000  # shell overflow and long lists both occur
     assert np.array_equal(out["ncont"], nc)
     err = np.linalg.norm(out["Fc"] - Fc, axis=0)
     assert np.all(err <= TOL[prec] * fa + 1e-300), np.max(err / (fa + 1e-300))
