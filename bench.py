@@ -109,6 +109,38 @@ def time_stages(sim, steps):
     return {k: v / steps for k, v in acc.items()}
 
 
+def time_adjoint(reps=3):
+    """Forward and backward of the differentiable rollout on the c4 workload
+    (65,536 bidisperse granules, 20 steps, checkpoint every 5), FP64."""
+    import torch
+    from paper_2504_00745_amd import workloads as wl
+    from paper_2504_00745_amd.rollout import GICRollout, Rollout
+    d = wl.make("c4")
+    cfg = d["params"]
+    sim = Rollout(cfg, d["r"], d["u"], 20, ckpt=5, r_max=float(d["r"].max()))
+    x0 = torch.as_tensor(d["x"]).cuda()
+    v0d = torch.as_tensor(d["v"]).cuda()
+    fw, bw = [], []
+    for it in range(reps + 1):
+        v0 = v0d.clone().requires_grad_(True)
+        mu = torch.tensor(cfg["mu"], dtype=torch.float64, requires_grad=True)
+        cd = torch.tensor(cfg["c_drag"], dtype=torch.float64, requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L = GICRollout.apply(x0, v0, mu, cd, sim)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        L.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if it:
+            fw.append(t1 - t0)
+            bw.append(t2 - t1)
+    f, b = float(np.median(fw)), float(np.median(bw))
+    return {"workload": "c4: 65,536 bidisperse granules, 64^3 grid, 20 steps, checkpoint every 5, FP64",
+            "forward_ms": f * 1e3, "backward_ms": b * 1e3, "ratio": b / f, "reps": reps}
+
+
 def touched_nodes(sim):
     import torch
     return int((sim.alpha != 0).sum().item())
@@ -197,7 +229,8 @@ def main():
         line["fp64_value"] = n * a.steps / r64["t"]
         line["fp32_over_fp64"] = line["value"] / line["fp64_value"]
         line["fp64_stages_ms"] = {k: round(v * 1e3, 4) for k, v in r64["stages"].items()}
-    line["bwd_fwd"] = None
+    log("[bench] adjoint: forward and backward of the c4 rollout")
+    line["bwd_fwd"] = time_adjoint()
     if not a.no_cpu:
         log(f"[bench] cpu baseline: {a.cpu_steps} oracle steps")
         line["cpu_baseline"] = cpu_baseline(d, a.cpu_steps)

@@ -1,0 +1,165 @@
+"""Adjoint form on the GPU: each pullback kernel against the oracle's
+hand-written reverse pass on identical inputs, and the checkpointed rollout
+gradient (dL/dv0, dL/dmu, dL/dC_d) against the oracle's reverse pass and
+against FP64 central differences of the GPU forward.
+
+Both sides are double; they differ only in summation order, so per-stage
+results agree to ~1e-12 of their scale.  Whole-rollout gradients are held
+to the 1e-4 relative bar."""
+import numpy as np
+import pytest
+
+from paper_2504_00745_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2504_00745_amd import gic
+    gic.lib()
+    import gpu_util
+    return gpu_util
+
+
+def _close(a, b, rel):
+    scale = np.abs(b).max() + 1e-300
+    return np.abs(a - b).max() <= rel * scale
+
+
+def test_stage_pullbacks_match_oracle(T, orc):
+    import torch
+    from paper_2504_00745_amd import gic
+    T.say("[adjoint stages] c4 12289 granules")
+    d = wl.make("c4", n_override=12289)
+    cfg, x, v, r, u = d["params"], d["x"], d["v"], d["r"], d["u"]
+    n = x.shape[1]
+    ctx = gic.Context(cfg, n, "fp64", float(r.max()))
+    X, V, R = T.dev(x.reshape(-1)), T.dev(v.reshape(-1)), T.dev(r)
+    key = torch.empty(n, dtype=torch.int32, device="cuda")
+    order = torch.empty(n, dtype=torch.int32, device="cuda")
+    cb = torch.empty(ctx.K, dtype=torch.int32, device="cuda")
+    ce = torch.empty(ctx.K, dtype=torch.int32, device="cuda")
+    gic.gic_sort_cells(ctx, X.view(3, n), key, order, cb, ce)
+    Xs, Vs, Rs = torch.empty_like(X), torch.empty_like(V), torch.empty_like(R)
+    gic.gic_permute(ctx, order, X, Xs, 3, False)
+    gic.gic_permute(ctx, order, V, Vs, 3, False)
+    gic.gic_permute(ctx, order, R, Rs, 1, False)
+    ids = order.cpu().numpy()
+    rng = np.random.Generator(np.random.PCG64(5))
+
+    def unsort(t, comps):
+        a = t.cpu().numpy().reshape(comps, n)
+        o = np.empty_like(a)
+        o[:, ids] = a
+        return o if comps > 1 else o[0]
+
+    def sort3(a):
+        return T.dev(np.ascontiguousarray(a[:, ids]).reshape(-1))
+
+    # contact
+    gF = rng.normal(0, 1, (3, n))
+    gx = torch.zeros(3 * n, dtype=torch.float64, device="cuda")
+    gv = torch.zeros_like(gx)
+    gmu = torch.empty(n, dtype=torch.float64, device="cuda")
+    gic.gic_contact_forces_vjp(ctx, Xs.view(3, n), Vs, Rs, cb, ce, sort3(gF), gx, gv, gmu)
+    ox, ov, omu = orc.contact_vjp(cfg, x, v, r, gF)
+    assert _close(unsort(gx, 3), ox, 1e-11)
+    assert _close(unsort(gv, 3), ov, 1e-11)
+    assert gmu.sum().item() == pytest.approx(omu, rel=1e-10)
+    # integrate
+    gx1, gv1 = rng.normal(0, 1, (3, n)), rng.normal(0, 1, (3, n))
+    Gx, Gv = sort3(gx1), sort3(gv1)
+    gf = torch.empty(3 * n, dtype=torch.float64, device="cuda")
+    gic.gic_integrate_vjp(ctx, Rs, Gx, Gv, gf)
+    m = cfg["rho_s"] * 4.0 / 3.0 * np.pi * r ** 3
+    tot = gv1 + cfg["dt"] * gx1
+    assert _close(unsort(Gv, 3), tot, 1e-14)
+    assert _close(unsort(gf, 3), cfg["dt"] / m * tot, 1e-14)
+    # drag and G2P with a real alpha grid (some nodes above the clamp)
+    A, _ = orc.p2g_real(cfg, x, v, r)
+    A = A * 3.0
+    uat, af = orc.g2p(cfg, x, u, alpha_real=A)
+    gv2 = torch.zeros(3 * n, dtype=torch.float64, device="cuda")
+    guat = torch.empty(3 * n, dtype=torch.float64, device="cuda")
+    gaf = torch.empty(n, dtype=torch.float64, device="cuda")
+    gcd = torch.empty(n, dtype=torch.float64, device="cuda")
+    gic.gic_drag_vjp(ctx, Rs, Vs, sort3(uat), T.dev(af[ids]), sort3(gF), gv2, guat, gaf, gcd)
+    ov2, ouat, oaf, ocd = orc.drag_vjp(cfg, r, v, uat, af, gF)
+    assert _close(unsort(gv2, 3), ov2, 1e-13)
+    assert _close(unsort(guat, 3), ouat, 1e-13)
+    assert _close(unsort(gaf, 1), oaf, 1e-13)
+    assert gcd.sum().item() == pytest.approx(ocd, rel=1e-11)
+    gx3 = torch.zeros(3 * n, dtype=torch.float64, device="cuda")
+    gA = torch.empty(ctx.G, dtype=torch.float64, device="cuda")
+    rg = rng.normal(0, 1, (3, n))
+    ra = rng.normal(0, 1, n)
+    gic.gic_g2p_vjp(ctx, Xs.view(3, n), T.dev(u.reshape(-1)), T.dev(A), sort3(rg), T.dev(ra[ids]), cb, ce, gx3, gA)
+    ox3, oA = orc.g2p_vjp(cfg, x, u, A, rg, ra)
+    assert _close(unsort(gx3, 3), ox3, 1e-11)
+    assert _close(gA.cpu().numpy(), oA, 1e-12)
+    assert (A >= cfg["alpha_max"]).any()
+    # P2G
+    gAin, gPin = rng.normal(0, 1, ctx.G), rng.normal(0, 1, 3 * ctx.G)
+    gx4 = torch.zeros(3 * n, dtype=torch.float64, device="cuda")
+    gv4 = torch.zeros_like(gx4)
+    gic.gic_p2g_vjp(ctx, Xs.view(3, n), Vs, Rs, T.dev(gAin), T.dev(gPin), gx4, gv4)
+    ox4, ov4 = orc.p2g_vjp(cfg, x, v, r, gAin, gPin.reshape(3, -1))
+    assert _close(unsort(gx4, 3), ox4, 1e-12)
+    assert _close(unsort(gv4, 3), ov4, 1e-12)
+
+
+@pytest.mark.parametrize("n_gran,steps", [(12289, 20), (65536, 20)])
+def test_rollout_gradient(T, orc, n_gran, steps):
+    """Checkpointed GPU rollout (checkpoint every 5 steps): loss and
+    gradients against the oracle's stored-trajectory reverse pass, and
+    dL/dmu, dL/dC_d and a v0 direction against central differences of the
+    GPU forward (h = 1e-6 max(|theta|, 1)), all to 1e-4."""
+    import torch
+    from paper_2504_00745_amd.rollout import GICRollout, Rollout
+    T.say(f"[adjoint rollout] c4 {n_gran} granules, {steps} steps")
+    d = wl.make("c4", n_override=None if n_gran == 65536 else n_gran)
+    cfg, x, v, r, u = d["params"], d["x"], d["v"], d["r"], d["u"]
+    sim = Rollout(cfg, r, u, steps, ckpt=5, r_max=float(r.max()))
+    x0 = T.dev(x.reshape(3, -1))
+    v0 = T.dev(v.reshape(3, -1)).requires_grad_(True)
+    mu = torch.tensor(cfg["mu"], dtype=torch.float64, requires_grad=True)
+    cd = torch.tensor(cfg["c_drag"], dtype=torch.float64, requires_grad=True)
+    L = GICRollout.apply(x0, v0, mu, cd, sim)
+    L.backward()
+    Lg = L.item()
+    g_v0 = v0.grad.cpu().numpy()
+    g_mu, g_cd = mu.grad.item(), cd.grad.item()
+    T.say(f"[adjoint rollout] L={Lg:.6e} dL/dmu={g_mu:.6e} dL/dCd={g_cd:.6e}")
+    Lo, ogv, omu, ocd = orc.rollout_vjp(cfg, x, v, r, u, steps)
+    assert Lg == pytest.approx(Lo, rel=1e-9)
+    assert g_mu == pytest.approx(omu, rel=1e-4)
+    assert g_cd == pytest.approx(ocd, rel=1e-4)
+    rng = np.random.Generator(np.random.PCG64(2))
+    dv = rng.normal(0, 1, v.shape)
+    dv /= np.linalg.norm(dv)
+    assert np.sum(g_v0 * dv) == pytest.approx(np.sum(ogv * dv), rel=1e-4)
+    assert np.abs(g_v0 - ogv).max() <= 1e-4 * np.abs(ogv).max()
+
+    def L_gpu(mu_=cfg["mu"], cd_=cfg["c_drag"], vv=v):
+        sim.set_params(mu_, cd_)
+        Lt, _, _ = sim.forward(x0, T.dev(vv.reshape(3, -1)))
+        return Lt.item()
+
+    eps_floor = lambda h: 50 * np.finfo(float).eps * Lg / h
+    h = 1e-6 * max(cfg["mu"], 1)
+    fd = (L_gpu(mu_=cfg["mu"] + h) - L_gpu(mu_=cfg["mu"] - h)) / (2 * h)
+    assert fd == pytest.approx(g_mu, rel=1e-4, abs=eps_floor(h))
+    h = 1e-6 * max(cfg["c_drag"], 1)
+    fd = (L_gpu(cd_=cfg["c_drag"] + h) - L_gpu(cd_=cfg["c_drag"] - h)) / (2 * h)
+    assert fd == pytest.approx(g_cd, rel=1e-4, abs=eps_floor(h))
+    h = 1e-6 * max(np.linalg.norm(v), 1)
+    fd = (L_gpu(vv=v + h * dv) - L_gpu(vv=v - h * dv)) / (2 * h)
+    assert fd == pytest.approx(np.sum(g_v0 * dv), rel=1e-4, abs=eps_floor(h))
+    # non-vacuity on the full bed: the parameters move the loss well above the
+    # FD floor (the thinned bed has too few sliding contacts for mu to matter)
+    if n_gran == 65536:
+        assert abs(g_mu * cfg["mu"]) > 1e-5 * Lg and abs(g_cd * cfg["c_drag"]) > 1e-5 * Lg
