@@ -199,15 +199,47 @@ __global__ void __launch_bounds__(256) k_contact(DevParams P, int64_t n, int64_t
 // ---------------------------------------------------------------------------
 // LDS-staged contact: one workgroup per brick of 4x4x4 cells.  The 6x6x6
 // cells around the brick (the brick and a one-cell shell) are copied once
-// into LDS, cell after cell in (z, y, x) order with one empty slot (NaN
-// position, never touching) after each cell: when cells hold equal numbers
-// of granules, the slot keeps lanes that read different cells at the same
+// into LDS, cell after cell in (z, y, x) order with one empty slot (NaN,
+// never a candidate) after each cell: when cells hold equal numbers of
+// granules the empty slot puts lanes that read different cells at the same
 // step on different LDS banks.  Consecutive cells of a row stay one
-// contiguous range of slots.  Each granule of the brick then tests its
-// candidates from LDS.  A brick whose shell does not fit takes the global
-// path.
+// contiguous range of slots.
+//
+// A slot holds the granule's position relative to the shell's corner and
+// its radius in single precision (16 bytes, one LDS read per candidate).
+// The candidate pass tests d^2 < (r_i + r_j + m)^2 on these with a margin m
+// well above their rounding error, so it keeps every pair the exact test
+// keeps; the force pass then runs the exact double test of Sec. 3.1 on the
+// listed partners (from global memory, as the force needs their double
+// state anyway) and evaluates Eq. (1) for those that touch.
+//
+// Margin: relative coordinates lie within 6 cells of the corner, so each is
+// rounded by at most 6 cell 2^-24; a difference of two adds its own rounding
+// (at most 2^-24 of it), the squared distance a few ulps and each radius
+// 2^-24 of itself.  Altogether the single-precision distance is within
+// 2^-18 cell of the exact one; the margin is 2^-16 cell.  (For positions
+// outside the box, which the key kernel reports as a domain error, the
+// bound does not hold and the step's result is unspecified.)
+//
+// A brick whose shell does not fit in LDS takes the global path.
 constexpr int kHaloCells = 216;
-constexpr int kLdsPartners = 12;
+constexpr int kLdsPartners = 10;
+constexpr int kCand = 4;  // candidates read from LDS before they are tested
+
+// Exact contact test of Sec. 3.1 against partner j and, if the two touch,
+// the pair force added to acc.  Returns 1 for a contact.
+template <typename T>
+__device__ inline int exact_pair(const DevParams &P, int64_t n, const double *__restrict__ x,
+                                 const double *__restrict__ v, const double *__restrict__ r, const double xi[3],
+                                 const double vi[3], double ri, double mi, int64_t q, int32_t j, T acc[3])
+{
+    if (j == q) return 0;
+    const double d0 = xi[0] - x[j], d1 = xi[1] - x[n + j], d2c = xi[2] - x[2 * n + j];
+    double d2;
+    if (!touching(d0, d1, d2c, ri + r[j], d2) || d2 == 0.0) return 0;
+    add_pair<T>(P, n, x, v, r, xi, vi, ri, mi, j, acc);
+    return 1;
+}
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_contact_lds(DevParams P, int64_t n, int64_t nbricks, int cap,
@@ -216,15 +248,14 @@ __global__ void __launch_bounds__(256) k_contact_lds(DevParams P, int64_t n, int
                                                      const int32_t *__restrict__ ce, T *__restrict__ F,
                                                      int32_t *__restrict__ ncont, int64_t *err)
 {
-    extern __shared__ double smem[];
-    double2 *sxy = reinterpret_cast<double2 *>(smem);            // [cap] (x, y)
-    double2 *szr = sxy + cap;                                      // [cap] (z, r)
-    int32_t *sg = reinterpret_cast<int32_t *>(szr + cap);         // [cap] global index of each slot
-    uint16_t *plist = reinterpret_cast<uint16_t *>(sg + cap);     // [kLdsPartners][256] partner slots
+    extern __shared__ float4 smem4[];
+    float4 *spos = smem4;                                                  // [cap] (x, y, z, r) relative
+    uint16_t *plist = reinterpret_cast<uint16_t *>(spos + cap);           // [kLdsPartners][256] partner slots
     int32_t *clo = reinterpret_cast<int32_t *>(plist + kLdsPartners * 256);  // [216] first slot of each cell
-    int32_t *cnum = clo + kHaloCells;                              // [216] granules of each shell cell
-    int32_t *cgb = cnum + kHaloCells;                              // [216] global begin of each shell cell
-    __shared__ int32_t s_wave[4];
+    int32_t *cnum = clo + kHaloCells;                                      // [216] granules of each shell cell
+    int32_t *cgb = cnum + kHaloCells;                                      // [216] global begin of each shell cell
+    int32_t *s_wave = cgb + kHaloCells;                                    // [4]
+    uint8_t *scell = reinterpret_cast<uint8_t *>(s_wave + 4);              // [cap] shell cell of each slot
     const int tid = threadIdx.x;
     const int64_t b = xcd_block(nbricks);
     if (b < 0) return;
@@ -233,6 +264,7 @@ __global__ void __launch_bounds__(256) k_contact_lds(DevParams P, int64_t n, int
     const int32_t c0[3] = {bc[0] * kBrick - 1, bc[1] * kBrick - 1, bc[2] * kBrick - 1};  // shell origin cell
     const int32_t gb = cb[b * kBrickCells], ge = ce[b * kBrickCells + kBrickCells - 1];
     if (ge <= gb) return;
+    const double o[3] = {c0[0] * P.cell, c0[1] * P.cell, c0[2] * P.cell};  // shell corner
     // ---- shell cells: counts, then slots (count + 1 pad each) by a scan
     int32_t num = 0, gbeg = 0;
     if (tid < kHaloCells) {
@@ -245,6 +277,7 @@ __global__ void __launch_bounds__(256) k_contact_lds(DevParams P, int64_t n, int
         }
     }
     const int32_t slots = tid < kHaloCells ? num + 1 : 0;
+    int32_t first = 0;
     {
         const int lane = tid & 63, wave = tid >> 6;
         int32_t incl = slots;
@@ -256,55 +289,59 @@ __global__ void __launch_bounds__(256) k_contact_lds(DevParams P, int64_t n, int
         __syncthreads();
         int32_t before = 0;
         for (int w = 0; w < wave; ++w) before += s_wave[w];
+        first = before + incl - slots;
         if (tid < kHaloCells) {
-            clo[tid] = before + incl - slots;
+            clo[tid] = first;
             cnum[tid] = num;
             cgb[tid] = gbeg;
         }
-        __syncthreads();
     }
     const int32_t H = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
     if (H > cap) {  // shell too large for LDS: global candidate path for this brick
-        int32_t *glist = reinterpret_cast<int32_t *>(smem);  // the slot arrays are unused on this path
+        __syncthreads();  // every thread has read s_wave
+        int32_t *glist = reinterpret_cast<int32_t *>(smem4);  // the slot arrays are unused on this path
         for (int64_t q = gb + tid; q < ge; q += 256) contact_global<T>(P, n, x, v, r, cb, ce, q, glist, tid, F, ncont, err);
         return;
     }
-    // ---- copy the shell's granules (and a NaN pad after each cell)
+    // ---- slot -> shell cell map (the NaN pad takes its cell's number too)
+    if (tid < kHaloCells)
+        for (int32_t k = first; k < first + slots; ++k) scell[k] = (uint8_t)tid;
+    __syncthreads();
+    // ---- copy the shell's granules, relative to the corner, in single precision
     for (int k = tid; k < H; k += 256) {
-        int lo = 0, hi = kHaloCells;  // largest cell with clo <= k
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (clo[mid] <= k) lo = mid; else hi = mid;
-        }
-        const int off = k - clo[lo];
-        if (off < cnum[lo]) {
-            const int64_t g = cgb[lo] + off;
-            sxy[k] = make_double2(x[g], x[n + g]);
-            szr[k] = make_double2(x[2 * n + g], r[g]);
-            sg[k] = (int32_t)g;
+        const int c = scell[k];
+        const int off = k - clo[c];
+        float4 p;
+        if (off < cnum[c]) {
+            const int64_t g = cgb[c] + off;
+            p = make_float4((float)(x[g] - o[0]), (float)(x[n + g] - o[1]), (float)(x[2 * n + g] - o[2]), (float)r[g]);
         } else {
-            const double nan = __builtin_nan("");
-            sxy[k] = make_double2(nan, nan);
-            szr[k] = make_double2(nan, 0.0);
-            sg[k] = -1;
+            const float nan = __builtin_nanf("");
+            p = make_float4(nan, nan, nan, 0.0f);
         }
+        spos[k] = p;
     }
     __syncthreads();
+    const float margin = (float)(P.cell * (1.0 / 65536.0));
     // ---- granules of the brick
     for (int64_t q = gb + tid; q < ge; q += 256) {
         const double xi[3] = {x[q], x[n + q], x[2 * n + q]};
-        const double vi[3] = {v[q], v[n + q], v[2 * n + q]};
         const double ri = r[q];
         if (ri > P.r_max) raise_error(err, kErrRange, q);
-        const double mi = mass_of(P, ri);
+        const float xf = (float)(xi[0] - o[0]), yf = (float)(xi[1] - o[1]), zf = (float)(xi[2] - o[2]);
+        const float rim = (float)ri + margin;
         const double Rs = (ri + P.r_max) * P.search_scale;
-        int32_t lo[3], hi[3];
+        int32_t lo[3], hi[3], ca[3];
         for (int a = 0; a < 3; ++a) {
+            ca[a] = cell_coord(xi[a], P.inv_cell, P.nc[a]) - c0[a];  // in [1, 4]: q lies in the brick
             search_range(P, xi[a], Rs, P.nc[a], lo[a], hi[a]);
             lo[a] -= c0[a];
             hi[a] -= c0[a];
         }
-        T acc[3] = {(T)0, (T)0, (T)0};
+        // slot of q itself, skipped by the candidate pass (the exact test skips q too)
+        const int own = (ca[2] * 6 + ca[1]) * 6 + ca[0];
+        const int32_t qoff = (int32_t)(q - cgb[own]);
+        const int32_t kself = qoff >= 0 && qoff < cnum[own] ? clo[own] + qoff : -1;
         int32_t cnt = 0;
         for (int hz = lo[2]; hz <= hi[2]; ++hz)
             for (int hy = lo[1]; hy <= hi[1]; ++hy) {
@@ -312,38 +349,55 @@ __global__ void __launch_bounds__(256) k_contact_lds(DevParams P, int64_t n, int
                 // cells lo..hi of this row: one contiguous run of slots
                 const int k0 = clo[c + lo[0]];
                 const int k1 = clo[c + hi[0]] + cnum[c + hi[0]];
-                for (int k = k0; k < k1; ++k) {
-                    const double2 pxy = sxy[k], pzr = szr[k];
-                    double d2;
-                    if (!touching(xi[0] - pxy.x, xi[1] - pxy.y, xi[2] - pzr.x, ri + pzr.y, d2) || d2 == 0.0) continue;
-                    if (cnt < kLdsPartners) plist[cnt * 256 + tid] = (uint16_t)k;
-                    ++cnt;
+                for (int k = k0; k < k1; k += kCand) {
+                    float4 p[kCand];
+#pragma unroll
+                    for (int u = 0; u < kCand; ++u) p[u] = spos[k + u < k1 ? k + u : k1 - 1];
+#pragma unroll
+                    for (int u = 0; u < kCand; ++u) {
+                        const float ex = xf - p[u].x, ey = yf - p[u].y, ez = zf - p[u].z;
+                        const float R = rim + p[u].w;
+                        const float d2 = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
+                        if (k + u < k1 && k + u != kself && d2 < R * R) {
+                            if (cnt < kLdsPartners) plist[cnt * 256 + tid] = (uint16_t)(k + u);
+                            ++cnt;
+                        }
+                    }
                 }
             }
+        const double vi[3] = {v[q], v[n + q], v[2 * n + q]};
+        const double mi = mass_of(P, ri);
+        T acc[3] = {(T)0, (T)0, (T)0};
+        int32_t nc = 0;
         const int listed = cnt < kLdsPartners ? cnt : kLdsPartners;
-        for (int i = 0; i < listed; ++i) add_pair<T>(P, n, x, v, r, xi, vi, ri, mi, sg[plist[i * 256 + tid]], acc);
+        for (int i = 0; i < listed; ++i) {
+            const int k = plist[i * 256 + tid];
+            const int c = scell[k];
+            nc += exact_pair<T>(P, n, x, v, r, xi, vi, ri, mi, q, cgb[c] + (k - clo[c]), acc);
+        }
         if (cnt > kLdsPartners) {
-            // more partners than listed: walk the candidates again for the rest
+            // more candidates than listed: walk them again for the rest
             int32_t seen = 0;
             for (int hz = lo[2]; hz <= hi[2]; ++hz)
                 for (int hy = lo[1]; hy <= hi[1]; ++hy) {
                     const int c = (hz * 6 + hy) * 6;
                     const int k1 = clo[c + hi[0]] + cnum[c + hi[0]];
                     for (int k = clo[c + lo[0]]; k < k1; ++k) {
-                        const double2 pxy = sxy[k], pzr = szr[k];
-                        double d2;
-                        if (!touching(xi[0] - pxy.x, xi[1] - pxy.y, xi[2] - pzr.x, ri + pzr.y, d2) || d2 == 0.0)
-                            continue;
+                        const float4 p = spos[k];
+                        const float ex = xf - p.x, ey = yf - p.y, ez = zf - p.z;
+                        const float R = rim + p.w;
+                        if (k == kself || !(fmaf(ex, ex, fmaf(ey, ey, ez * ez)) < R * R)) continue;
                         if (seen++ < kLdsPartners) continue;
-                        add_pair<T>(P, n, x, v, r, xi, vi, ri, mi, sg[k], acc);
+                        const int cc = scell[k];
+                        nc += exact_pair<T>(P, n, x, v, r, xi, vi, ri, mi, q, cgb[cc] + (k - clo[cc]), acc);
                     }
                 }
         }
-        add_walls<T>(P, xi, vi, ri, mi, acc, cnt);
+        add_walls<T>(P, xi, vi, ri, mi, acc, nc);
         F[q] = acc[0];
         F[n + q] = acc[1];
         F[2 * n + q] = acc[2];
-        if (ncont) ncont[q] = cnt;
+        if (ncont) ncont[q] = nc;
     }
 }
 
@@ -381,7 +435,8 @@ __global__ void k_zero_count(unsigned long long *c) { *c = 0ull; }
 // LDS bytes of the staged contact kernel for a shell capacity of cap granules.
 static size_t contact_lds_bytes(int cap)
 {
-    size_t b = (size_t)cap * 36 + sizeof(uint16_t) * kLdsPartners * 256 + sizeof(int32_t) * kHaloCells * 3;
+    size_t b = (size_t)cap * (sizeof(float4) + 1) + sizeof(uint16_t) * kLdsPartners * 256 +
+               sizeof(int32_t) * (kHaloCells * 3 + 4);
     const size_t fallback = sizeof(int32_t) * kMaxPartners * 256;  // list of the global path, aliasing the slots
     return b > fallback ? b : fallback;
 }
@@ -392,7 +447,7 @@ hipError_t launch_contact(const DevParams &P, int64_t n, const double *x, const 
 {
     if (n == 0) return hipSuccess;
     const int64_t nbricks = (int64_t)P.nb[0] * P.nb[1] * P.nb[2];
-    const int cap = 1960;  // shell slots held in LDS (< 65536 for 16-bit lists; two workgroups fit per CU)
+    const int cap = 1952;  // shell slots held in LDS: 40,912 bytes, four workgroups per CU
     k_contact_lds<T><<<xcd_grid(nbricks), 256, contact_lds_bytes(cap), s>>>(P, n, nbricks, cap, x, v, r, cb, ce, F,
                                                                             ncont, err);
     return hipGetLastError();
