@@ -161,6 +161,17 @@ __device__ inline int64_t rint_i64(double v)
     return __double_as_longlong(y) - __double_as_longlong(M);
 }
 
+// Bit pattern of v + 1.5 * 2^52, i.e. rint(v) plus kRintBias, for |v| < 2^51.
+// Sums of such patterns, taken modulo 2^64 and corrected by the count times
+// kRintBias, are sums of rint values.
+constexpr uint64_t kRintBias = 0x4338000000000000ull;  // bits of 1.5 * 2^52
+__device__ inline uint64_t rint_biased(double v)
+{
+#pragma clang fp contract(off)
+    const double M = 6755399441055744.0;
+    return (uint64_t)__double_as_longlong(v + M);
+}
+
 constexpr double kFixLimit = 2251799813685248.0;  // 2^51
 
 // Pair (or wall) force of Eq. (1a)-(1c) with the dashpot reading, in real

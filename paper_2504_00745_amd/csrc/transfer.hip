@@ -3,9 +3,10 @@
 //
 // P2G: one workgroup per brick of 4x4x4 neighbour cells.  Granules of a brick
 // are contiguous in sorted order and their stencils cover a small box of
-// nodes, so their 27-node x 4-channel contributions are first summed in an
-// LDS tile with 64-bit LDS atomics and then added to the grid with one global
-// atomic per touched node and channel.  A contribution whose node falls
+// nodes, so their 27-node x 4-channel contributions are first summed in
+// registers over runs of granules that share a stencil, then in an LDS tile
+// with 64-bit LDS atomics, and then added to the grid with one global atomic
+// per touched node and channel.  A contribution whose node falls
 // outside the tile (a granule that moved after the sort) goes straight to a
 // global atomic, so the result never depends on the order.  Fixed-point
 // contributions are integers, so every accumulation order gives the same
@@ -67,33 +68,29 @@ __device__ inline void tile_origin(const DevParams &P, int64_t b, int32_t o[3])
     for (int a = 0; a < 3; ++a) o[a] = (int32_t)floor((double)(bc[a] * kBrick) * P.cell * P.inv_dx) - 1;
 }
 
-// Flat stencil slot (0..26, x fastest; 13 is the centre) -> 1-D offsets.
-__device__ inline void slot_offsets(int slot, int &cx, int &cy, int &cz)
-{
-    cz = slot / 9;
-    cy = (slot / 3) % 3;
-    cx = slot % 3;
-}
-
+// Add an integer contribution to the LDS tile, or to the grid when its node
+// lies outside the tile.  The two atomics carry different scopes so that
+// they stay an LDS atomic and a global atomic.
 __device__ inline void tile_add(unsigned long long *tile, unsigned long long *glob, bool in, int lidx,
                                 int64_t gidx, int64_t val)
 {
     if (val == 0) return;
     if (in)
-        atomicAdd(&tile[lidx], (unsigned long long)val);
+        __hip_atomic_fetch_add(&tile[lidx], (unsigned long long)val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     else
-        atomicAdd(&glob[gidx], (unsigned long long)val);
+        __hip_atomic_fetch_add(&glob[gidx], (unsigned long long)val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // One workgroup per brick, granules taken in batches.  Phase 1 (a thread per
-// granule) computes the 1-D weights, the scaled totals S and the centre
-// remainder Q - sum of the 26 outer contributions, into LDS.  Consecutive
-// sorted granules with the same stencil base form a run; they share all 27
-// nodes.  Phase 2 (a thread per run and slot) sums the run's integer
-// contributions rint(w S) in registers and issues one LDS atomic per
-// channel, instead of one per granule; the 27 slots of a run sit on
-// neighbouring lanes, so their LDS reads of the run's granule data are
-// broadcasts and their atomics go to distinct nodes.
+// granule) stores the stencil base, the offsets f of the 1-D weights and the
+// scaled totals S of each channel in LDS.  Consecutive sorted granules with
+// the same stencil base form a run; they share all 27 nodes.  Phase 2 (a
+// thread per run and channel) walks the run's granules, rounds each outer
+// contribution rint(w S) and sums it in one of 26 register accumulators; the
+// centre node gets the run's sum of Q = rint(S) minus the 26 sums, which is
+// the sum over the run's granules of each granule's centre remainder (all
+// integer, so the regrouping is exact).  A run then costs 27 LDS atomics per
+// channel, not 27 per granule.
 template <bool MOM>
 __global__ void __launch_bounds__(kP2GThreads) k_p2g_fixed(DevParams P, int64_t n, int64_t nbricks, int batch,
                                                            const double *__restrict__ x,
@@ -117,11 +114,11 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g_fixed(DevParams P, int64_t 
     if (end <= beg) return;
     const int E = P.tile;
     const int E3 = E * E * E;
-    double *sw = reinterpret_cast<double *>(tile + NCH * E3);          // [9][batch]
-    double *sS = sw + 9 * batch;                                        // [NCH][batch]
-    int64_t *srest = reinterpret_cast<int64_t *>(sS + NCH * batch);    // [NCH][batch]
-    int32_t *sbase = reinterpret_cast<int32_t *>(srest + NCH * batch);  // [3][batch]
-    int32_t *srun = sbase + 3 * batch;                                  // [batch + 1]
+    const int bs = batch + 1;  // padded stride: the arrays start on different LDS banks
+    double *sf = reinterpret_cast<double *>(tile + NCH * E3);   // [3][bs] weight offsets f
+    double *sS = sf + 3 * bs;                                    // [NCH][bs] scaled totals
+    int32_t *sbase = reinterpret_cast<int32_t *>(sS + NCH * bs);  // [3][bs] stencil base
+    int32_t *srun = sbase + 3 * bs;                              // [bs] run starts
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int k = tid; k < NCH * E3; k += kP2GThreads) tile[k] = 0ull;
     int32_t o[3];
@@ -130,24 +127,15 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g_fixed(DevParams P, int64_t 
     for (int64_t b0 = beg; b0 < end; b0 += batch) {
         const int m = (int)(end - b0 < batch ? end - b0 : batch);
         // ---- phase 1: per granule
-        int32_t base[3] = {0, 0, 0};
-        if (tid < m) {
-            const int64_t q = b0 + tid;
-            const double xa[3] = {x[q], x[n + q], x[2 * n + q]};
-            double w[3][3];
+        for (int i = tid; i < m; i += kP2GThreads) {
+            const int64_t q = b0 + i;
             for (int a = 0; a < 3; ++a) {
-                const double t = xa[a] * P.inv_dx;
+                const double t = x[a * n + q] * P.inv_dx;
                 double fb = floor(t - 1.0);
-                const double f = (t - fb) - 0.5;
-                const double c0 = 1.5 - f, c1 = f - 1.0, c2 = f - 0.5;
-                w[a][0] = 0.5 * (c0 * c0);
-                w[a][1] = 0.75 - c1 * c1;
-                w[a][2] = 0.5 * (c2 * c2);
+                sf[a * bs + i] = (t - fb) - 0.5;
                 if (!(fb >= -2.0)) fb = -2.0;
                 if (fb > (double)P.n[a]) fb = (double)P.n[a];
-                base[a] = (int32_t)fb;
-                for (int k = 0; k < 3; ++k) sw[(a * 3 + k) * batch + tid] = w[a][k];
-                sbase[a * batch + tid] = base[a];
+                sbase[a * bs + i] = (int32_t)fb;
             }
             const double frac = volume_of(r[q]) * P.inv_vcell;
             double S[NCH];
@@ -166,80 +154,104 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g_fixed(DevParams P, int64_t 
 #pragma unroll
                 for (int c = 0; c < NCH; ++c) S[c] = 0.0;
             }
-            int64_t rest[NCH];
 #pragma unroll
-            for (int c = 0; c < NCH; ++c) rest[c] = rint_i64(S[c]);
-            for (int cz = 0; cz < 3; ++cz)
-                for (int cy = 0; cy < 3; ++cy)
-                    for (int cx = 0; cx < 3; ++cx) {
-                        if (cx == 1 && cy == 1 && cz == 1) continue;
-                        const double ww = (w[0][cx] * w[1][cy]) * w[2][cz];
-#pragma unroll
-                        for (int c = 0; c < NCH; ++c) rest[c] -= rint_i64(ww * S[c]);
-                    }
-#pragma unroll
-            for (int c = 0; c < NCH; ++c) {
-                sS[c * batch + tid] = S[c];
-                srest[c * batch + tid] = rest[c];
-            }
+            for (int c = 0; c < NCH; ++c) sS[c * bs + i] = S[c];
         }
         __syncthreads();
         // ---- runs of equal stencil base
-        bool start = false;
-        if (tid < m) {
-            start = tid == 0;
-            if (!start)
-                for (int a = 0; a < 3; ++a) start |= sbase[a * batch + tid - 1] != base[a];
-        }
-        const uint64_t smask = __ballot(start);
-        if (lane == 0) s_wave[wave] = (int32_t)__popcll(smask);
-        __syncthreads();
-        int off = 0, nruns = 0;
-        for (int w = 0; w < kP2GThreads / 64; ++w) {
-            off += w < wave ? s_wave[w] : 0;
-            nruns += s_wave[w];
-        }
-        if (start) {
-            const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-            srun[off + __popcll(smask & lt)] = tid;
+        int nruns = 0;
+        for (int i0 = 0; i0 < m; i0 += kP2GThreads) {
+            const int i = i0 + tid;
+            bool start = false;
+            if (i < m) {
+                start = i == 0;
+                if (!start)
+                    for (int a = 0; a < 3; ++a) start |= sbase[a * bs + i - 1] != sbase[a * bs + i];
+            }
+            const uint64_t smask = __ballot(start);
+            if (lane == 0) s_wave[wave] = (int32_t)__popcll(smask);
+            __syncthreads();
+            int off = nruns, tot = nruns;
+            for (int w = 0; w < kP2GThreads / 64; ++w) {
+                off += w < wave ? s_wave[w] : 0;
+                tot += s_wave[w];
+            }
+            if (start) {
+                const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+                srun[off + __popcll(smask & lt)] = i;
+            }
+            nruns = tot;
+            __syncthreads();
         }
         if (tid == 0) srun[nruns] = m;
         __syncthreads();
-        // ---- phase 2: per run and slot
-        for (int task = tid; task < nruns * 27; task += kP2GThreads) {
-            const int rr = task / 27;
-            const int slot = task - rr * 27;
+        // ---- phase 2: per run and channel
+        for (int task = tid; task < nruns * NCH; task += kP2GThreads) {
+            const int rr = task / NCH;
+            const int c = task - rr * NCH;
             const int g0 = srun[rr], g1 = srun[rr + 1];
-            int cx, cy, cz;
-            slot_offsets(slot, cx, cy, cz);
-            int64_t acc[NCH];
+            uint64_t acc[27];  // sums of rint_biased patterns (mod 2^64)
 #pragma unroll
-            for (int c = 0; c < NCH; ++c) acc[c] = 0;
-            if (slot == 13) {
-                for (int g = g0; g < g1; ++g)
+            for (int k = 0; k < 27; ++k) acc[k] = 0;
+            uint64_t qsum = 0;
+            for (int g = g0; g < g1; ++g) {
+                const double S = sS[c * bs + g];
+                double w[3][3];
 #pragma unroll
-                    for (int c = 0; c < NCH; ++c) acc[c] += srest[c * batch + g];
-            } else {
-                for (int g = g0; g < g1; ++g) {
-                    const double ww = (sw[cx * batch + g] * sw[(3 + cy) * batch + g]) * sw[(6 + cz) * batch + g];
+                for (int a = 0; a < 3; ++a) {
+                    const double f = sf[a * bs + g];
+                    const double c0 = 1.5 - f, c1 = f - 1.0, c2 = f - 0.5;
+                    w[a][0] = 0.5 * (c0 * c0);
+                    w[a][1] = 0.75 - c1 * c1;
+                    w[a][2] = 0.5 * (c2 * c2);
+                }
+                qsum += rint_biased(S);
 #pragma unroll
-                    for (int c = 0; c < NCH; ++c) acc[c] += rint_i64(ww * sS[c * batch + g]);
+                for (int cz = 0; cz < 3; ++cz)
+#pragma unroll
+                    for (int cy = 0; cy < 3; ++cy)
+#pragma unroll
+                        for (int cx = 0; cx < 3; ++cx) {
+                            if (cx == 1 && cy == 1 && cz == 1) continue;
+                            const double ww = (w[0][cx] * w[1][cy]) * w[2][cz];
+                            acc[(cz * 3 + cy) * 3 + cx] += rint_biased(ww * S);
+                        }
+            }
+            const uint64_t bias = (uint64_t)(g1 - g0) * kRintBias;
+            uint64_t outer = 0;
+#pragma unroll
+            for (int k = 0; k < 27; ++k) {
+                if (k == 13) continue;
+                acc[k] -= bias;
+                outer += acc[k];
+            }
+            acc[13] = (qsum - bias) - outer;
+            // nodes of the run's stencil, folded onto the edge
+            int32_t nd[3][3];
+            bool inb[3][3];
+            for (int a = 0; a < 3; ++a) {
+                const int32_t b0a = sbase[a * bs + g0];
+                for (int k = 0; k < 3; ++k) {
+                    int32_t id = b0a + k;
+                    id = id < 0 ? 0 : id;
+                    id = id > P.n[a] - 1 ? P.n[a] - 1 : id;
+                    nd[a][k] = id;
+                    const int32_t l = id - o[a];
+                    inb[a][k] = l >= 0 && l < E;
                 }
             }
-            const int off3[3] = {cx, cy, cz};
-            int32_t nd[3];
-            for (int a = 0; a < 3; ++a) {
-                int32_t id = sbase[a * batch + g0] + off3[a];
-                id = id < 0 ? 0 : id;
-                id = id > P.n[a] - 1 ? P.n[a] - 1 : id;
-                nd[a] = id;
-            }
-            const int32_t li = nd[0] - o[0], lj = nd[1] - o[1], lk = nd[2] - o[2];
-            const bool in = li >= 0 && lj >= 0 && lk >= 0 && li < E && lj < E && lk < E;
-            const int lidx = (lk * E + lj) * E + li;
-            const int64_t gidx = node_index(P, nd[0], nd[1], nd[2]);
+            unsigned long long *tl = tile + c * E3;
 #pragma unroll
-            for (int c = 0; c < NCH; ++c) tile_add(tile + c * E3, glob[c], in, lidx, gidx, acc[c]);
+            for (int cz = 0; cz < 3; ++cz)
+#pragma unroll
+                for (int cy = 0; cy < 3; ++cy)
+#pragma unroll
+                    for (int cx = 0; cx < 3; ++cx) {
+                        const bool in = inb[0][cx] && inb[1][cy] && inb[2][cz];
+                        const int lidx = ((nd[2][cz] - o[2]) * E + (nd[1][cy] - o[1])) * E + (nd[0][cx] - o[0]);
+                        const int64_t gidx = node_index(P, nd[0][cx], nd[1][cy], nd[2][cz]);
+                        tile_add(tl, glob[c], in, lidx, gidx, (int64_t)acc[(cz * 3 + cy) * 3 + cx]);
+                    }
         }
         __syncthreads();
     }
@@ -376,7 +388,7 @@ hipError_t launch_fill_f64(double *a, int64_t len, hipStream_t s)
 // LDS bytes of the fixed-point P2G: node tile plus per-granule batch data.
 static size_t p2g_lds(int nch, int E3, int batch)
 {
-    return sizeof(unsigned long long) * (size_t)nch * E3 + (size_t)batch * (9 * 8 + nch * 16 + 3 * 4 + 4) + 4;
+    return sizeof(unsigned long long) * (size_t)nch * E3 + (size_t)(batch + 1) * (3 * 8 + nch * 8 + 3 * 4 + 4);
 }
 
 hipError_t launch_p2g_fixed(const DevParams &P, int64_t n, int64_t K, const double *x, const double *v,
@@ -387,8 +399,8 @@ hipError_t launch_p2g_fixed(const DevParams &P, int64_t n, int64_t K, const doub
     const int64_t bricks = K / kBrickCells;
     const int E3 = P.tile * P.tile * P.tile;
     const int nch = mom ? 4 : 1;
-    int batch = 256;
-    while (batch > 32 && p2g_lds(nch, E3, batch) > 65536) batch /= 2;
+    int batch = 512;  // a brick of 64 cells of 8 granules in one batch; 256 run-channel tasks
+    while (batch > 64 && p2g_lds(nch, E3, batch) > 49152) batch /= 2;
     const size_t lds = p2g_lds(nch, E3, batch);
     if (mom)
         k_p2g_fixed<true><<<xcd_grid(bricks), kP2GThreads, lds, s>>>(
