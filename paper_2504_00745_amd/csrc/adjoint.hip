@@ -246,7 +246,7 @@ __global__ void __launch_bounds__(256) k_g2p_vjp_grid(DevParams P, int64_t n, in
                                                       double *__restrict__ gA)
 {
     extern __shared__ double tile[];
-    const int64_t b = xcd_block(nbricks);
+    const int64_t b = brick_block(nbricks);
     if (b < 0) return;
     const int32_t beg = cb[b * kBrickCells], end = ce[b * kBrickCells + kBrickCells - 1];
     if (end <= beg) return;
@@ -409,7 +409,7 @@ hipError_t launch_g2p_vjp(const DevParams &P, int64_t n, int64_t K, const double
         if (e != hipSuccess) return e;
         const int64_t bricks = K / kBrickCells;
         const size_t lds = sizeof(double) * (size_t)P.tile * P.tile * P.tile;
-        k_g2p_vjp_grid<<<xcd_grid(bricks), 256, lds, s>>>(P, n, bricks, x, A, gaf, cb, ce, gA);
+        k_g2p_vjp_grid<<<brick_grid(bricks), 256, lds, s>>>(P, n, bricks, x, A, gaf, cb, ce, gA);
     }
     return hipGetLastError();
 }

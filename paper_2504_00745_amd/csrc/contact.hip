@@ -257,7 +257,7 @@ __global__ void __launch_bounds__(256) k_contact_lds(DevParams P, int64_t n, int
     int32_t *s_wave = cgb + kHaloCells;                                    // [4]
     uint8_t *scell = reinterpret_cast<uint8_t *>(s_wave + 4);              // [cap] shell cell of each slot
     const int tid = threadIdx.x;
-    const int64_t b = xcd_block(nbricks);
+    const int64_t b = brick_block(nbricks);
     if (b < 0) return;
     const int32_t bc[3] = {(int32_t)(b % P.nb[0]), (int32_t)((b / P.nb[0]) % P.nb[1]),
                            (int32_t)(b / ((int64_t)P.nb[0] * P.nb[1]))};
@@ -448,7 +448,7 @@ hipError_t launch_contact(const DevParams &P, int64_t n, const double *x, const 
     if (n == 0) return hipSuccess;
     const int64_t nbricks = (int64_t)P.nb[0] * P.nb[1] * P.nb[2];
     const int cap = 1952;  // shell slots held in LDS: 40,912 bytes, four workgroups per CU
-    k_contact_lds<T><<<xcd_grid(nbricks), 256, contact_lds_bytes(cap), s>>>(P, n, nbricks, cap, x, v, r, cb, ce, F,
+    k_contact_lds<T><<<brick_grid(nbricks), 256, contact_lds_bytes(cap), s>>>(P, n, nbricks, cap, x, v, r, cb, ce, F,
                                                                             ncont, err);
     return hipGetLastError();
 }

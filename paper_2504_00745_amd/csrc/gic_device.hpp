@@ -42,6 +42,33 @@ __device__ inline int64_t xcd_block(int64_t nlogical)
     return l < nlogical ? l : -1;
 }
 
+// Brick kernels: the occupied bricks of a bed are often one contiguous part
+// of the brick order (the lower half of the box, say), so a contiguous
+// eighth per XCD would leave XCDs idle.  Bricks are instead dealt to the XCDs
+// in chunks of kBrickChunk consecutive bricks; chunk i of super-row s (8
+// chunks) goes to XCD (i + s) mod 8, so every super-row feeds every XCD once
+// and the skew keeps a pattern that repeats every 8 chunks from landing on
+// one XCD.  Launch with brick_grid(nbricks) workgroups; brick_block returns
+// the brick or -1.
+constexpr int kBrickChunk = 4;
+
+inline unsigned brick_grid(int64_t nbricks)
+{
+    const int64_t chunks = (nbricks + kBrickChunk - 1) / kBrickChunk;
+    const int64_t rows = (chunks + kXcds - 1) / kXcds;
+    return (unsigned)(rows > 0 ? rows * kXcds * kBrickChunk : kXcds);
+}
+
+__device__ inline int64_t brick_block(int64_t nbricks)
+{
+    const int64_t b = blockIdx.x;
+    const int64_t k = b % kXcds, j = b / kXcds;  // XCD and slot on it
+    const int64_t srow = j / kBrickChunk, off = j % kBrickChunk;
+    const int64_t i = (k - srow % kXcds + kXcds) % kXcds;
+    const int64_t l = (srow * kXcds + i) * kBrickChunk + off;
+    return l < nbricks ? l : -1;
+}
+
 // Latched error codes (same values as gic_status).
 constexpr int kErrDomain = 4;
 constexpr int kErrNonFinite = 5;

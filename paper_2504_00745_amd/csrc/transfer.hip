@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g_fixed(DevParams P, int64_t 
     extern __shared__ unsigned long long tile[];
     __shared__ int32_t s_range[2];
     __shared__ int32_t s_wave[kP2GThreads / 64];
-    const int64_t b = xcd_block(nbricks);
+    const int64_t b = brick_block(nbricks);
     if (b < 0) return;
     brick_range(b, cb, ce, s_range);
     __syncthreads();
@@ -275,7 +275,7 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g_real(DevParams P, int64_t n
 {
     extern __shared__ double dtile[];
     __shared__ int32_t s_range[2];
-    const int64_t b = xcd_block(nbricks);
+    const int64_t b = brick_block(nbricks);
     if (b < 0) return;
     brick_range(b, cb, ce, s_range);
     __syncthreads();
@@ -403,11 +403,11 @@ hipError_t launch_p2g_fixed(const DevParams &P, int64_t n, int64_t K, const doub
     while (batch > 64 && p2g_lds(nch, E3, batch) > 49152) batch /= 2;
     const size_t lds = p2g_lds(nch, E3, batch);
     if (mom)
-        k_p2g_fixed<true><<<xcd_grid(bricks), kP2GThreads, lds, s>>>(
+        k_p2g_fixed<true><<<brick_grid(bricks), kP2GThreads, lds, s>>>(
             P, n, bricks, batch, x, v, r, cb, ce, reinterpret_cast<unsigned long long *>(alpha),
             reinterpret_cast<unsigned long long *>(mom), err);
     else
-        k_p2g_fixed<false><<<xcd_grid(bricks), kP2GThreads, lds, s>>>(
+        k_p2g_fixed<false><<<brick_grid(bricks), kP2GThreads, lds, s>>>(
             P, n, bricks, batch, x, v, r, cb, ce, reinterpret_cast<unsigned long long *>(alpha), nullptr, err);
     return hipGetLastError();
 }
@@ -420,7 +420,7 @@ hipError_t launch_p2g_real(const DevParams &P, int64_t n, int64_t K, const doubl
     const int64_t bricks = K / kBrickCells;
     const int E3 = P.tile * P.tile * P.tile;
     const size_t lds = sizeof(double) * 4 * (size_t)E3;
-    k_p2g_real<<<xcd_grid(bricks), kP2GThreads, lds, s>>>(P, n, bricks, x, v, r, cb, ce, alpha, mom);
+    k_p2g_real<<<brick_grid(bricks), kP2GThreads, lds, s>>>(P, n, bricks, x, v, r, cb, ce, alpha, mom);
     return hipGetLastError();
 }
 
