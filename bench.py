@@ -45,21 +45,18 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# Algorithmic bytes per granule (and per touched grid node) of each stage in
-# the FP32 form: the arrays the method itself must read and write once,
-# neighbour re-reads and scratch excluded.  B = size of the real type.
+# Algorithmic bytes per granule (and per touched grid node) of each kernel of
+# the step: the arrays the method itself must read and write once, neighbour
+# re-reads and scratch excluded.  B = size of the real type.
 def stage_bytes(stage, n, nodes, real_bytes):
     B = real_bytes
     per = {
-        "sort": 24 + 4 + 4,                  # read x, write key, write order
-        "reorder": 4 + 2 * (24 + 24 + 8 + 4),  # read order, gather + write x, v, r, id
-        "g2p": 24 + 3 * B + B,               # read x, write u_at, alpha_f (+ grid below)
-        "drag": 8 + 24 + 3 * B + B + 3 * B,  # read r, v, u_at, alpha_f; write F_d
-        "contact": 24 + 24 + 8 + 3 * B,      # read x, v, r; write F_c
-        "integrate": 8 + 3 * B + 3 * B + 2 * (24 + 24),  # read r, F_c, F_d; read+write x, v
-        "p2g": 24 + 24 + 8,                  # read x, v, r (+ grid writes below)
+        "sort": 24 + 4 + 4,                          # read x, write key, write order
+        "gather_g2p_drag": 4 + 2 * (24 + 24 + 8 + 4) + 3 * B,  # order; gather + write x, v, r, id; write F_d
+        "contact": 24 + 24 + 8 + 3 * B,              # read x, v, r; write F_c
+        "integrate_p2g": 8 + 3 * B + 3 * B + 2 * (24 + 24),  # read r, F_c, F_d; read + write x, v
     }[stage]
-    grid = {"g2p": 3 * B + 8, "p2g": 8 + 24}.get(stage, 0)
+    grid = {"gather_g2p_drag": 3 * B + 8, "integrate_p2g": 8 + 24}.get(stage, 0)  # node reads / writes
     return per * n + grid * nodes
 
 
@@ -80,12 +77,14 @@ def time_steps(sim, steps, warmup):
 
 
 def time_stages(sim, steps):
-    """Per-stage times from HIP events recorded on the stream the stages are
-    launched on (torch's current stream), between separate C-ABI calls."""
+    """Per-kernel times of the step from HIP events recorded on the stream the
+    kernels are launched on (torch's current stream), between the C-ABI calls
+    that gic_step makes; each launches one kernel of the step, the sort aside
+    (its passes), and the grid clear is issued outside the bracket."""
     import torch
     from paper_2504_00745_amd import gic
     ctx, s = sim.ctx, sim.scratch
-    names = ["sort", "reorder", "g2p", "drag", "contact", "integrate", "p2g"]
+    names = ["sort", "gather_g2p_drag", "contact", "integrate_p2g"]
     acc = {k: 0.0 for k in names}
     for _ in range(steps):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
@@ -93,19 +92,16 @@ def time_stages(sim, steps):
         ev[0].record()
         gic.gic_sort_cells(ctx, cur["x"], s["key"], s["order"], s["cell_begin"], s["cell_end"])
         ev[1].record()
-        gic.gic_reorder(ctx, s["order"], cur["x"], cur["v"], cur["r"], cur["id"], nxt["x"], nxt["v"], nxt["r"],
-                        nxt["id"])
+        gic.gic_gather_g2p_drag(ctx, s["order"], cur["x"], cur["v"], cur["r"], cur["id"], nxt["x"], nxt["v"],
+                                nxt["r"], nxt["id"], sim.u, sim.alpha, s["cell_begin"], s["cell_end"], s["f_drag"])
         ev[2].record()
-        gic.gic_g2p(ctx, nxt["x"], sim.u, sim.alpha, None, s["u_at"], s["alpha_f"])
-        ev[3].record()
-        gic.gic_drag(ctx, nxt["r"], nxt["v"], s["u_at"], s["alpha_f"], s["f_drag"])
-        ev[4].record()
         gic.gic_contact_forces(ctx, nxt["x"], nxt["v"], nxt["r"], s["cell_begin"], s["cell_end"], s["f_contact"])
-        ev[5].record()
-        gic.gic_integrate(ctx, nxt["r"], s["f_contact"], s["f_drag"], nxt["x"], nxt["v"])
-        ev[6].record()
-        gic.gic_p2g(ctx, nxt["x"], nxt["v"], nxt["r"], s["cell_begin"], s["cell_end"], sim.alpha, sim.mom)
-        ev[7].record()
+        sim.alpha.zero_()  # the grid clear, outside the timed kernel
+        sim.mom.zero_()
+        ev[3].record()
+        gic.gic_integrate_p2g(ctx, nxt["x"], nxt["v"], nxt["r"], s["f_contact"], s["f_drag"], s["cell_begin"],
+                              s["cell_end"], sim.alpha, sim.mom, accumulate=True)
+        ev[4].record()
         sim.cur, sim.nxt = nxt, cur
         torch.cuda.synchronize()
         for i, k in enumerate(names):
@@ -164,7 +160,8 @@ def copy_calibration():
 # Source files whose change invalidates a stored HBM traffic measurement.
 TRAFFIC_SOURCES = {
     "contact": ["contact.hip", "gic_device.hpp", "gic_launch.hpp"],
-    "p2g": ["transfer.hip", "gic_device.hpp", "gic_launch.hpp"],
+    "integrate_p2g": ["transfer.hip", "gic_device.hpp", "gic_launch.hpp"],
+    "gather_g2p_drag": ["step.hip", "gic_device.hpp", "gic_launch.hpp"],
 }
 
 

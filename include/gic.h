@@ -215,15 +215,39 @@ gic_status gic_p2g_real(gic_ctx *ctx, int64_t n, const double *x, const double *
                         const int32_t *cell_begin, const int32_t *cell_end, double *alpha, double *mom,
                         int32_t accumulate, void *stream);
 
+/* ---- fused stages (same results, bit for bit, as the separate calls) ------
+ * gic_gather_g2p_drag = gic_reorder, then gic_g2p with alpha_fx, then
+ * gic_drag, in one pass over the bricks of cells (Sec. 5.2; Eq. 5b, App. A):
+ * the state of granule order[q] is written to position q of the _out
+ * arrays, and its drag force to f_drag[q].  u_at and alpha_f (3n and n
+ * real) receive the sampled fluid velocity and fraction, or are skipped
+ * when NULL.  cell_begin, cell_end: ranges of the sort that gave `order`. */
+gic_status gic_gather_g2p_drag(gic_ctx *ctx, int64_t n, const int32_t *order, const double *x, const double *v,
+                               const double *r, const int32_t *id, double *x_out, double *v_out, double *r_out,
+                               int32_t *id_out, const void *u, const int64_t *alpha_fx, const int32_t *cell_begin,
+                               const int32_t *cell_end, void *f_drag, void *u_at, void *alpha_f, void *stream);
+
+/* gic_integrate_p2g = gic_integrate (x, v advanced in place with f_contact +
+ * f_drag), then gic_p2g of the new state (Sec. 4; Sec. 5.1, Eq. 7a), in one
+ * pass: each granule is moved and deposited by the same thread.  x, v, r in
+ * the sorted order of cell_begin, cell_end.  accumulate as in gic_p2g. */
+gic_status gic_integrate_p2g(gic_ctx *ctx, int64_t n, double *x, double *v, const double *r, const void *f_contact,
+                             const void *f_drag, const int32_t *cell_begin, const int32_t *cell_end,
+                             int64_t *alpha_fx, int64_t *mom_fx, int32_t accumulate, void *stream);
+
 /* ---- one full sub-step -------------------------------------------------------
  * Sort, reorder, G2P (alpha_fx at the current positions, as left by the
- * previous step's P2G), drag, contact, integrate, P2G.  The granule state
- * is double-buffered: x, v, r, id are read from the `cur` arrays and written,
- * advanced and in the new sorted order, to the `nxt` arrays (same sizes);
- * the caller swaps them.  alpha_fx is read, then overwritten with the
- * fraction at the new positions; mom_fx receives the new momentum.
- * Scratch arrays (caller-owned): key, order (n int32), cell_begin, cell_end
- * (K int32), f_contact, f_drag, u_at (3n real), alpha_f (n real). */
+ * previous step's P2G), drag, contact, integrate, P2G, run as
+ * gic_sort_cells -> gic_gather_g2p_drag -> gic_contact_forces ->
+ * gic_integrate_p2g.  The granule state is double-buffered: x, v, r, id are
+ * read from the `cur` arrays and written, advanced and in the new sorted
+ * order, to the `nxt` arrays (same sizes); the caller swaps them.  alpha_fx
+ * is read, then overwritten with the fraction at the new positions; mom_fx
+ * receives the new momentum.  Scratch arrays (caller-owned): key, order (n
+ * int32), cell_begin, cell_end (K int32), f_contact, f_drag (3n real; they
+ * hold the step's forces afterwards); u_at (3n real) and alpha_f (n real)
+ * receive the sampled fluid velocity and fraction, or are skipped when
+ * NULL. */
 gic_status gic_step(gic_ctx *ctx, int64_t n, const double *x_cur, const double *v_cur, const double *r_cur,
                     const int32_t *id_cur, double *x_nxt, double *v_nxt, double *r_nxt, int32_t *id_nxt,
                     const void *u, int64_t *alpha_fx, int64_t *mom_fx, uint32_t *key, int32_t *order,

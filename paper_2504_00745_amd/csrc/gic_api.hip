@@ -309,6 +309,46 @@ gic_status gic_p2g_real(gic_ctx *c, int64_t n, const double *x, const double *v,
     return hip_status(launch_p2g_real(c->dp, n, c->K, x, v, r, cell_begin, cell_end, alpha, mom, s));
 }
 
+gic_status gic_gather_g2p_drag(gic_ctx *c, int64_t n, const int32_t *order, const double *x, const double *v,
+                               const double *r, const int32_t *id, double *x_out, double *v_out, double *r_out,
+                               int32_t *id_out, const void *u, const int64_t *alpha_fx, const int32_t *cell_begin,
+                               const int32_t *cell_end, void *f_drag, void *u_at, void *alpha_f, void *stream)
+{
+    if (!n_ok(c, n) || !cell_begin || !cell_end) return GIC_E_ARG;
+    if (n > 0 && (!order || !x || !v || !r || !x_out || !v_out || !r_out || !u || !alpha_fx || !f_drag))
+        return GIC_E_ARG;
+    if ((id == nullptr) != (id_out == nullptr) || (u_at == nullptr) != (alpha_f == nullptr)) return GIC_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (fp32(c))
+        return hip_status(launch_gather_g2p_drag<float>(c->dp, n, c->K, order, x, v, r, id, x_out, v_out, r_out,
+                                                        id_out, (const float *)u, alpha_fx, cell_begin, cell_end,
+                                                        (float *)f_drag, (float *)u_at, (float *)alpha_f, s));
+    return hip_status(launch_gather_g2p_drag<double>(c->dp, n, c->K, order, x, v, r, id, x_out, v_out, r_out, id_out,
+                                                     (const double *)u, alpha_fx, cell_begin, cell_end,
+                                                     (double *)f_drag, (double *)u_at, (double *)alpha_f, s));
+}
+
+gic_status gic_integrate_p2g(gic_ctx *c, int64_t n, double *x, double *v, const double *r, const void *f_contact,
+                             const void *f_drag, const int32_t *cell_begin, const int32_t *cell_end,
+                             int64_t *alpha_fx, int64_t *mom_fx, int32_t accumulate, void *stream)
+{
+    if (!n_ok(c, n) || !alpha_fx || !mom_fx || !cell_begin || !cell_end) return GIC_E_ARG;
+    if (n > 0 && (!x || !v || !r || !f_contact || !f_drag)) return GIC_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (!accumulate) {
+        hipError_t e = launch_fill_i64(alpha_fx, c->dp.G, s);
+        if (e == hipSuccess) e = launch_fill_i64(mom_fx, 3 * c->dp.G, s);
+        if (e != hipSuccess) return GIC_E_HIP;
+    }
+    if (fp32(c))
+        return hip_status(launch_integrate_p2g<float>(c->dp, n, c->K, x, v, r, (const float *)f_contact,
+                                                      (const float *)f_drag, cell_begin, cell_end, alpha_fx, mom_fx,
+                                                      c->err, s));
+    return hip_status(launch_integrate_p2g<double>(c->dp, n, c->K, x, v, r, (const double *)f_contact,
+                                                   (const double *)f_drag, cell_begin, cell_end, alpha_fx, mom_fx,
+                                                   c->err, s));
+}
+
 gic_status gic_step(gic_ctx *c, int64_t n, const double *x_cur, const double *v_cur, const double *r_cur,
                     const int32_t *id_cur, double *x_nxt, double *v_nxt, double *r_nxt, int32_t *id_nxt,
                     const void *u, int64_t *alpha_fx, int64_t *mom_fx, uint32_t *key, int32_t *order,
@@ -317,22 +357,21 @@ gic_status gic_step(gic_ctx *c, int64_t n, const double *x_cur, const double *v_
 {
     if (!n_ok(c, n) || !alpha_fx || !mom_fx || !cell_begin || !cell_end) return GIC_E_ARG;
     if (n > 0 && (!x_cur || !v_cur || !r_cur || !x_nxt || !v_nxt || !r_nxt || !u || !key || !order ||
-                  !f_contact || !f_drag || !u_at || !alpha_f))
+                  !f_contact || !f_drag))
         return GIC_E_ARG;
-    if ((id_cur == nullptr) != (id_nxt == nullptr)) return GIC_E_ARG;
+    if ((id_cur == nullptr) != (id_nxt == nullptr) || (u_at == nullptr) != (alpha_f == nullptr)) return GIC_E_ARG;
     gic_status st;
     if ((st = gic_sort_cells(c, n, x_cur, key, order, cell_begin, cell_end, stream)) != GIC_OK) return st;
-    if ((st = gic_reorder(c, n, order, x_cur, v_cur, r_cur, id_cur, x_nxt, v_nxt, r_nxt, id_nxt, stream)) != GIC_OK)
+    // alpha_fx was deposited at the current positions and is read by node,
+    // so the gather into sorted order does not change it
+    if ((st = gic_gather_g2p_drag(c, n, order, x_cur, v_cur, r_cur, id_cur, x_nxt, v_nxt, r_nxt, id_nxt, u, alpha_fx,
+                                  cell_begin, cell_end, f_drag, u_at, alpha_f, stream)) != GIC_OK)
         return st;
-    // alpha_fx was deposited at the current positions; G2P reads it by node,
-    // so the reorder does not change it.
-    if ((st = gic_g2p(c, n, x_nxt, u, alpha_fx, nullptr, u_at, alpha_f, stream)) != GIC_OK) return st;
-    if ((st = gic_drag(c, n, r_nxt, v_nxt, u_at, alpha_f, f_drag, stream)) != GIC_OK) return st;
     if ((st = gic_contact_forces(c, n, x_nxt, v_nxt, r_nxt, cell_begin, cell_end, f_contact, nullptr, stream)) !=
         GIC_OK)
         return st;
-    if ((st = gic_integrate(c, n, r_nxt, f_contact, f_drag, x_nxt, v_nxt, stream)) != GIC_OK) return st;
-    return gic_p2g(c, n, x_nxt, v_nxt, r_nxt, cell_begin, cell_end, alpha_fx, mom_fx, 0, stream);
+    return gic_integrate_p2g(c, n, x_nxt, v_nxt, r_nxt, f_contact, f_drag, cell_begin, cell_end, alpha_fx, mom_fx, 0,
+                             stream);
 }
 
 /* ---- adjoint form (double) ---------------------------------------------- */

@@ -188,6 +188,78 @@ __device__ inline int64_t rint_i64(double v)
     return __double_as_longlong(y) - __double_as_longlong(M);
 }
 
+// Sampled fluid velocity and fluid fraction at a granule (Sec. 5.2; clamp of
+// Sec. 5.1): u_at = sum_k w_k u_k, alpha_f = 1 - sum_k w_k min(alpha_k,
+// alpha_max) over the 27 stencil nodes, weights and sums in T.  fetch(i, j,
+// k, u[3], al) supplies node (i, j, k)'s velocity and its clamped solid
+// fraction; the same summation order serves every caller.
+template <typename T, typename Fetch>
+__device__ inline void g2p_sample(const DevParams &P, const double xa[3], Fetch &&fetch, T uat[3], T &af)
+{
+    Stencil s;
+    stencil_of(P, xa, s);
+    T acc[3] = {(T)0, (T)0, (T)0};
+    T as = (T)0;
+    for (int cz = 0; cz < 3; ++cz)
+        for (int cy = 0; cy < 3; ++cy) {
+            const double wyz = s.w[1][cy] * s.w[2][cz];
+            for (int cx = 0; cx < 3; ++cx) {
+                const T w = (T)(s.w[0][cx] * wyz);
+                T u[3], al;
+                fetch(s.node[0][cx], s.node[1][cy], s.node[2][cz], u, al);
+                acc[0] += w * u[0];
+                acc[1] += w * u[1];
+                acc[2] += w * u[2];
+                as += w * al;
+            }
+        }
+    uat[0] = acc[0];
+    uat[1] = acc[1];
+    uat[2] = acc[2];
+    af = (T)1 - as;
+}
+
+// Solid fraction of a node for G2P: fixed point to cell volumes, clamped.
+__device__ inline double node_alpha(const DevParams &P, int64_t afx)
+{
+    const double al = (double)afx * GIC_TWOM32;
+    return al > P.alpha_max ? P.alpha_max : al;
+}
+__device__ inline double node_alpha_real(const DevParams &P, double a) { return a > P.alpha_max ? P.alpha_max : a; }
+
+// Drag of Eq. (5b) in Stokes form scaled by the fluid fraction (App. A):
+// F_d = C_d 6 pi eta_f r alpha_f (u_at - v).
+template <typename T>
+__device__ inline void drag_one(const DevParams &P, double r, const double v[3], const T uat[3], T af, T Fd[3])
+{
+    const T beta = (T)(P.cdrag * r) * af;
+    for (int a = 0; a < 3; ++a) Fd[a] = beta * (uat[a] - (T)v[a]);
+}
+
+// Semi-implicit Euler (Sec. 4): v += dt ((F_c + F_d) / m + g), then x += dt v.
+template <typename T>
+__device__ inline void integrate_one(const DevParams &P, double r, const T Fc[3], const T *Fd, double x[3],
+                                     double v[3])
+{
+    const double inv_m = 1.0 / mass_of(P, r);
+    for (int a = 0; a < 3; ++a) {
+        double f = (double)Fc[a];
+        if (Fd) f += (double)Fd[a];
+        const double vn = v[a] + P.dt * (f * inv_m + P.g[a]);
+        v[a] = vn;
+        x[a] = x[a] + P.dt * vn;
+    }
+}
+
+// Origin of a brick's node tile: one node below the brick's first node per
+// axis.  The tile (P.tile nodes per edge) holds the stencils of all granules
+// whose cell lies in the brick.
+__device__ inline void tile_origin(const DevParams &P, int64_t b, int32_t o[3])
+{
+    const int64_t bc[3] = {b % P.nb[0], (b / P.nb[0]) % P.nb[1], b / ((int64_t)P.nb[0] * P.nb[1])};
+    for (int a = 0; a < 3; ++a) o[a] = (int32_t)floor((double)(bc[a] * kBrick) * P.cell * P.inv_dx) - 1;
+}
+
 // Bit pattern of v + 1.5 * 2^52, i.e. rint(v) plus kRintBias, for |v| < 2^51.
 // Sums of such patterns, taken modulo 2^64 and corrected by the count times
 // kRintBias, are sums of rint values.

@@ -52,6 +52,15 @@ hipError_t launch_fill_f64(double *a, int64_t len, hipStream_t s);
 hipError_t launch_p2g_fixed(const DevParams &P, int64_t n, int64_t K, const double *x, const double *v,
                             const double *r, const int32_t *cb, const int32_t *ce, int64_t *alpha, int64_t *mom,
                             int64_t *err, hipStream_t s);
+template <typename T>
+hipError_t launch_integrate_p2g(const DevParams &P, int64_t n, int64_t K, double *x, double *v, const double *r,
+                                const T *Fc, const T *Fd, const int32_t *cb, const int32_t *ce, int64_t *alpha,
+                                int64_t *mom, int64_t *err, hipStream_t s);
+template <typename T>
+hipError_t launch_gather_g2p_drag(const DevParams &P, int64_t n, int64_t K, const int32_t *order, const double *x,
+                                  const double *v, const double *r, const int32_t *id, double *xo, double *vo,
+                                  double *ro, int32_t *ido, const T *u, const int64_t *afx, const int32_t *cb,
+                                  const int32_t *ce, T *Fd, T *uat, T *af, hipStream_t s);
 hipError_t launch_p2g_real(const DevParams &P, int64_t n, int64_t K, const double *x, const double *v,
                            const double *r, const int32_t *cb, const int32_t *ce, double *alpha, double *mom,
                            hipStream_t s);

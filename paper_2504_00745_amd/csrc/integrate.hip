@@ -15,8 +15,11 @@ __global__ void __launch_bounds__(256) k_drag(DevParams P, int64_t n, const doub
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n) return;
-    const T beta = (T)(P.cdrag * r[q]) * af[q];
-    for (int a = 0; a < 3; ++a) Fd[a * n + q] = beta * (uat[a * n + q] - (T)v[a * n + q]);
+    const double vq[3] = {v[q], v[n + q], v[2 * n + q]};
+    const T ua[3] = {uat[q], uat[n + q], uat[2 * n + q]};
+    T f[3];
+    drag_one<T>(P, r[q], vq, ua, af[q], f);
+    for (int a = 0; a < 3; ++a) Fd[a * n + q] = f[a];
 }
 
 template <typename T>
@@ -26,13 +29,19 @@ __global__ void __launch_bounds__(256) k_integrate(DevParams P, int64_t n, const
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n) return;
-    const double inv_m = 1.0 / mass_of(P, r[q]);
+    double xq[3] = {x[q], x[n + q], x[2 * n + q]};
+    double vq[3] = {v[q], v[n + q], v[2 * n + q]};
+    const T fc[3] = {Fc[q], Fc[n + q], Fc[2 * n + q]};
+    T fd[3] = {(T)0, (T)0, (T)0};
+    if (Fd) {
+        fd[0] = Fd[q];
+        fd[1] = Fd[n + q];
+        fd[2] = Fd[2 * n + q];
+    }
+    integrate_one<T>(P, r[q], fc, Fd ? fd : nullptr, xq, vq);
     for (int a = 0; a < 3; ++a) {
-        double f = (double)Fc[a * n + q];
-        if (Fd) f += (double)Fd[a * n + q];
-        const double vn = v[a * n + q] + P.dt * (f * inv_m + P.g[a]);
-        v[a * n + q] = vn;
-        x[a * n + q] = x[a * n + q] + P.dt * vn;
+        x[a * n + q] = xq[a];
+        v[a * n + q] = vq[a];
     }
 }
 

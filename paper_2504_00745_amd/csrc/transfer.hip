@@ -57,17 +57,6 @@ __device__ inline void brick_range(int64_t b, const int32_t *__restrict__ cb, co
     }
 }
 
-// Origin of the LDS node tile of brick b: one node below the brick's first
-// node per axis.
-__device__ inline void tile_origin(const DevParams &P, int64_t b, int32_t o[3])
-{
-    const int64_t bx = b % P.nb[0];
-    const int64_t by = (b / P.nb[0]) % P.nb[1];
-    const int64_t bz = b / ((int64_t)P.nb[0] * P.nb[1]);
-    const int64_t bc[3] = {bx, by, bz};
-    for (int a = 0; a < 3; ++a) o[a] = (int32_t)floor((double)(bc[a] * kBrick) * P.cell * P.inv_dx) - 1;
-}
-
 // Add an integer contribution to the LDS tile, or to the grid when its node
 // lies outside the tile.  The two atomics carry different scopes so that
 // they stay an LDS atomic and a global atomic.
@@ -91,11 +80,15 @@ __device__ inline void tile_add(unsigned long long *tile, unsigned long long *gl
 // the sum over the run's granules of each granule's centre remainder (all
 // integer, so the regrouping is exact).  A run then costs 27 LDS atomics per
 // channel, not 27 per granule.
-template <bool MOM>
+//
+// INTEG: the move of Sec. 4 is applied first, in place (x, v advanced with
+// the contact and drag forces Fc, Fd, as the integration kernel does), and
+// the granule is deposited at its new position; each granule is read and
+// written by one thread only.
+template <bool MOM, typename T, bool INTEG>
 __global__ void __launch_bounds__(kP2GThreads) k_p2g_fixed(DevParams P, int64_t n, int64_t nbricks, int batch,
-                                                           const double *__restrict__ x,
-                                                           const double *__restrict__ v,
-                                                           const double *__restrict__ r,
+                                                           double *x, double *v, const double *__restrict__ r,
+                                                           const T *__restrict__ Fc, const T *__restrict__ Fd,
                                                            const int32_t *__restrict__ cb,
                                                            const int32_t *__restrict__ ce,
                                                            unsigned long long *__restrict__ alpha,
@@ -129,8 +122,21 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g_fixed(DevParams P, int64_t 
         // ---- phase 1: per granule
         for (int i = tid; i < m; i += kP2GThreads) {
             const int64_t q = b0 + i;
+            double xa[3] = {x[q], x[n + q], x[2 * n + q]};
+            double va[3] = {0.0, 0.0, 0.0};
+            if (MOM || INTEG)
+                for (int a = 0; a < 3; ++a) va[a] = v[a * n + q];
+            if (INTEG) {
+                const T fc[3] = {Fc[q], Fc[n + q], Fc[2 * n + q]};
+                const T fd[3] = {Fd[q], Fd[n + q], Fd[2 * n + q]};
+                integrate_one<T>(P, r[q], fc, fd, xa, va);
+                for (int a = 0; a < 3; ++a) {
+                    x[a * n + q] = xa[a];
+                    v[a * n + q] = va[a];
+                }
+            }
             for (int a = 0; a < 3; ++a) {
-                const double t = x[a * n + q] * P.inv_dx;
+                const double t = xa[a] * P.inv_dx;
                 double fb = floor(t - 1.0);
                 sf[a * bs + i] = (t - fb) - 0.5;
                 if (!(fb >= -2.0)) fb = -2.0;
@@ -142,7 +148,7 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g_fixed(DevParams P, int64_t 
             S[0] = frac * GIC_TWO32;
             if (MOM)
 #pragma unroll
-                for (int c = 1; c < NCH; ++c) S[c] = (frac * v[(c - 1) * n + q]) * GIC_TWO32;
+                for (int c = 1; c < NCH; ++c) S[c] = (frac * va[c - 1]) * GIC_TWO32;
             bool ok = true;
 #pragma unroll
             for (int c = 0; c < NCH; ++c) ok &= fabs(S[c]) < kFixLimit;
@@ -339,30 +345,19 @@ __global__ void __launch_bounds__(256) k_g2p(DevParams P, int64_t n, int64_t nbl
     const int64_t q = lb * 256 + threadIdx.x;
     if (q >= n) return;
     const double xa[3] = {x[q], x[n + q], x[2 * n + q]};
-    Stencil s;
-    stencil_of(P, xa, s);
     const int64_t G = P.G;
-    T acc[3] = {(T)0, (T)0, (T)0};
-    T as = (T)0;
-    for (int cz = 0; cz < 3; ++cz)
-        for (int cy = 0; cy < 3; ++cy) {
-            const double wyz = s.w[1][cy] * s.w[2][cz];
-            const int64_t row = (int64_t)P.n[0] * ((int64_t)s.node[1][cy] + (int64_t)P.n[1] * s.node[2][cz]);
-            for (int cx = 0; cx < 3; ++cx) {
-                const T w = (T)(s.w[0][cx] * wyz);
-                const int64_t k = row + s.node[0][cx];
-                acc[0] += w * u[k];
-                acc[1] += w * u[G + k];
-                acc[2] += w * u[2 * G + k];
-                double al = FIXED ? (double)afx[k] * GIC_TWOM32 : are[k];
-                al = al > P.alpha_max ? P.alpha_max : al;
-                as += w * (T)al;
-            }
-        }
-    uat[q] = acc[0];
-    uat[n + q] = acc[1];
-    uat[2 * n + q] = acc[2];
-    af[q] = (T)1 - as;
+    T ua[3], a;
+    g2p_sample<T>(P, xa, [&](int32_t i, int32_t j, int32_t k, T uu[3], T &al) {
+        const int64_t idx = node_index(P, i, j, k);
+        uu[0] = u[idx];
+        uu[1] = u[G + idx];
+        uu[2] = u[2 * G + idx];
+        al = (T)(FIXED ? node_alpha(P, afx[idx]) : node_alpha_real(P, are[idx]));
+    }, ua, a);
+    uat[q] = ua[0];
+    uat[n + q] = ua[1];
+    uat[2 * n + q] = ua[2];
+    af[q] = a;
 }
 
 }  // namespace
@@ -391,9 +386,10 @@ static size_t p2g_lds(int nch, int E3, int batch)
     return sizeof(unsigned long long) * (size_t)nch * E3 + (size_t)(batch + 1) * (3 * 8 + nch * 8 + 3 * 4 + 4);
 }
 
-hipError_t launch_p2g_fixed(const DevParams &P, int64_t n, int64_t K, const double *x, const double *v,
-                            const double *r, const int32_t *cb, const int32_t *ce, int64_t *alpha, int64_t *mom,
-                            int64_t *err, hipStream_t s)
+template <typename T, bool INTEG>
+static hipError_t p2g_fixed_impl(const DevParams &P, int64_t n, int64_t K, double *x, double *v, const double *r,
+                                 const T *Fc, const T *Fd, const int32_t *cb, const int32_t *ce, int64_t *alpha,
+                                 int64_t *mom, int64_t *err, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     const int64_t bricks = K / kBrickCells;
@@ -402,15 +398,40 @@ hipError_t launch_p2g_fixed(const DevParams &P, int64_t n, int64_t K, const doub
     int batch = 512;  // a brick of 64 cells of 8 granules in one batch; 256 run-channel tasks
     while (batch > 64 && p2g_lds(nch, E3, batch) > 49152) batch /= 2;
     const size_t lds = p2g_lds(nch, E3, batch);
+    unsigned long long *A = reinterpret_cast<unsigned long long *>(alpha);
+    unsigned long long *M = reinterpret_cast<unsigned long long *>(mom);
     if (mom)
-        k_p2g_fixed<true><<<brick_grid(bricks), kP2GThreads, lds, s>>>(
-            P, n, bricks, batch, x, v, r, cb, ce, reinterpret_cast<unsigned long long *>(alpha),
-            reinterpret_cast<unsigned long long *>(mom), err);
+        k_p2g_fixed<true, T, INTEG><<<brick_grid(bricks), kP2GThreads, lds, s>>>(P, n, bricks, batch, x, v, r, Fc, Fd,
+                                                                                 cb, ce, A, M, err);
     else
-        k_p2g_fixed<false><<<brick_grid(bricks), kP2GThreads, lds, s>>>(
-            P, n, bricks, batch, x, v, r, cb, ce, reinterpret_cast<unsigned long long *>(alpha), nullptr, err);
+        k_p2g_fixed<false, T, INTEG><<<brick_grid(bricks), kP2GThreads, lds, s>>>(P, n, bricks, batch, x, v, r, Fc,
+                                                                                  Fd, cb, ce, A, nullptr, err);
     return hipGetLastError();
 }
+
+hipError_t launch_p2g_fixed(const DevParams &P, int64_t n, int64_t K, const double *x, const double *v,
+                            const double *r, const int32_t *cb, const int32_t *ce, int64_t *alpha, int64_t *mom,
+                            int64_t *err, hipStream_t s)
+{
+    // x and v are only read on this path
+    return p2g_fixed_impl<float, false>(P, n, K, const_cast<double *>(x), const_cast<double *>(v), r, nullptr,
+                                        nullptr, cb, ce, alpha, mom, err, s);
+}
+
+template <typename T>
+hipError_t launch_integrate_p2g(const DevParams &P, int64_t n, int64_t K, double *x, double *v, const double *r,
+                                const T *Fc, const T *Fd, const int32_t *cb, const int32_t *ce, int64_t *alpha,
+                                int64_t *mom, int64_t *err, hipStream_t s)
+{
+    return p2g_fixed_impl<T, true>(P, n, K, x, v, r, Fc, Fd, cb, ce, alpha, mom, err, s);
+}
+
+template hipError_t launch_integrate_p2g<float>(const DevParams &, int64_t, int64_t, double *, double *,
+                                                const double *, const float *, const float *, const int32_t *,
+                                                const int32_t *, int64_t *, int64_t *, int64_t *, hipStream_t);
+template hipError_t launch_integrate_p2g<double>(const DevParams &, int64_t, int64_t, double *, double *,
+                                                 const double *, const double *, const double *, const int32_t *,
+                                                 const int32_t *, int64_t *, int64_t *, int64_t *, hipStream_t);
 
 hipError_t launch_p2g_real(const DevParams &P, int64_t n, int64_t K, const double *x, const double *v,
                            const double *r, const int32_t *cb, const int32_t *ce, double *alpha, double *mom,

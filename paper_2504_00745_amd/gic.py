@@ -65,6 +65,8 @@ def lib():
             "gic_integrate": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V]),
             "gic_p2g": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V, _I32, _V]),
             "gic_p2g_real": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V, _I32, _V]),
+            "gic_gather_g2p_drag": (C.c_int, [_V, _I64] + [_V] * 16),
+            "gic_integrate_p2g": (C.c_int, [_V, _I64] + [_V] * 9 + [_I32, _V]),
             "gic_step": (C.c_int, [_V, _I64] + [_V] * 19),
             "gic_contact_forces_vjp": (C.c_int, [_V, _I64] + [_V] * 10),
             "gic_drag_vjp": (C.c_int, [_V, _I64] + [_V] * 10),
@@ -241,9 +243,34 @@ def gic_p2g_real(ctx, x, v, r, cell_begin, cell_end, alpha, mom, accumulate=Fals
            "gic_p2g_real")
 
 
+def gic_gather_g2p_drag(ctx, order, x, v, r, id_, x_out, v_out, r_out, id_out, u, alpha_fx, cell_begin, cell_end,
+                        f_drag, u_at=None, alpha_f=None):
+    n = x.shape[-1]
+    f64 = torch.float64
+    _check(lib().gic_gather_g2p_drag(ctx.handle, n, _ptr(order, torch.int32, n), _ptr(x, f64, 3 * n),
+                                     _ptr(v, f64, 3 * n), _ptr(r, f64, n), _ptr(id_, torch.int32, n),
+                                     _ptr(x_out, f64, 3 * n), _ptr(v_out, f64, 3 * n), _ptr(r_out, f64, n),
+                                     _ptr(id_out, torch.int32, n), _ptr(u, ctx.real, 3 * ctx.G),
+                                     _ptr(alpha_fx, torch.int64, ctx.G), _ptr(cell_begin, torch.int32, ctx.K),
+                                     _ptr(cell_end, torch.int32, ctx.K), _ptr(f_drag, ctx.real, 3 * n, "f_drag"),
+                                     _ptr(u_at, ctx.real, 3 * n), _ptr(alpha_f, ctx.real, n), _stream()),
+           "gic_gather_g2p_drag")
+
+
+def gic_integrate_p2g(ctx, x, v, r, f_contact, f_drag, cell_begin, cell_end, alpha_fx, mom_fx, accumulate=False):
+    n = x.shape[-1]
+    f64 = torch.float64
+    _check(lib().gic_integrate_p2g(ctx.handle, n, _ptr(x, f64, 3 * n), _ptr(v, f64, 3 * n), _ptr(r, f64, n),
+                                   _ptr(f_contact, ctx.real, 3 * n), _ptr(f_drag, ctx.real, 3 * n),
+                                   _ptr(cell_begin, torch.int32, ctx.K), _ptr(cell_end, torch.int32, ctx.K),
+                                   _ptr(alpha_fx, torch.int64, ctx.G), _ptr(mom_fx, torch.int64, 3 * ctx.G),
+                                   int(bool(accumulate)), _stream()), "gic_integrate_p2g")
+
+
 def gic_step(ctx, cur, nxt, u, alpha_fx, mom_fx, scratch):
     """One sub-step; cur/nxt: dicts of x, v, r, id tensors; scratch: dict of
-    key, order, cell_begin, cell_end, f_contact, f_drag, u_at, alpha_f."""
+    key, order, cell_begin, cell_end, f_contact, f_drag and, optionally,
+    u_at, alpha_f (written when present)."""
     n = cur["x"].shape[-1]
     f64 = torch.float64
     s = scratch
@@ -254,8 +281,8 @@ def gic_step(ctx, cur, nxt, u, alpha_fx, mom_fx, scratch):
                           _ptr(mom_fx, torch.int64, 3 * ctx.G), _ptr(s["key"], torch.int32, n),
                           _ptr(s["order"], torch.int32, n), _ptr(s["cell_begin"], torch.int32, ctx.K),
                           _ptr(s["cell_end"], torch.int32, ctx.K), _ptr(s["f_contact"], ctx.real, 3 * n),
-                          _ptr(s["f_drag"], ctx.real, 3 * n), _ptr(s["u_at"], ctx.real, 3 * n),
-                          _ptr(s["alpha_f"], ctx.real, n), _stream()), "gic_step")
+                          _ptr(s["f_drag"], ctx.real, 3 * n), _ptr(s.get("u_at"), ctx.real, 3 * n),
+                          _ptr(s.get("alpha_f"), ctx.real, n), _stream()), "gic_step")
 
 
 # ---- adjoint form (double) ----------------------------------------------------
@@ -345,6 +372,8 @@ class Simulator:
                             f_drag=torch.empty(3 * n, dtype=real, device=dev),
                             u_at=torch.empty(3 * n, dtype=real, device=dev),
                             alpha_f=torch.empty(n, dtype=real, device=dev))
+        # the step itself does not need the sampled fluid velocity and fraction
+        self.step_scratch = {k: t for k, t in self.scratch.items() if k not in ("u_at", "alpha_f")}
         self.init_grid()
 
     def init_grid(self):
@@ -359,7 +388,7 @@ class Simulator:
 
     def step(self, k=1):
         for _ in range(k):
-            gic_step(self.ctx, self.cur, self.nxt, self.u, self.alpha, self.mom, self.scratch)
+            gic_step(self.ctx, self.cur, self.nxt, self.u, self.alpha, self.mom, self.step_scratch)
             self.cur, self.nxt = self.nxt, self.cur
 
     def state_in_input_order(self):

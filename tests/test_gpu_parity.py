@@ -246,3 +246,62 @@ def test_contact_dense_brick_and_many_partners(G, orc, prec):
     err = np.linalg.norm(out["Fc"] - Fc, axis=0)
     assert np.all(err <= TOL[prec] * fa + 1e-300), np.max(err / (fa + 1e-300))
     assert out["err"] == (0, -1)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_fused_stages_match_separate(G, prec):
+    """gic_gather_g2p_drag = reorder + G2P + drag and gic_integrate_p2g =
+    integrate + P2G, bit for bit (state, sampled fluid values, forces, int64
+    grids), on a polydisperse bed with a ragged tail; accumulate=1 adds to
+    the grids."""
+    import torch
+    from paper_2504_00745_amd import gic
+    G.say(f"[fused stages] c2s {prec}")
+    d = _make("c2s")
+    cfg, x, v, r, u = d["params"], d["x"], d["v"], d["r"], d["u"]
+    n = x.shape[1]
+    ctx = gic.Context(cfg, n, prec, float(r.max()))
+    real = ctx.real
+    X, V, R = G.dev(x.reshape(-1)), G.dev(v.reshape(-1)), G.dev(r)
+    ID = torch.arange(n, dtype=torch.int32, device="cuda")
+    key = torch.empty(n, dtype=torch.int32, device="cuda")
+    order = torch.empty(n, dtype=torch.int32, device="cuda")
+    cb = torch.empty(ctx.K, dtype=torch.int32, device="cuda")
+    ce = torch.empty(ctx.K, dtype=torch.int32, device="cuda")
+    gic.gic_sort_cells(ctx, X.view(3, n), key, order, cb, ce)
+    e = lambda like: torch.empty_like(like)
+    Xs, Vs, Rs, IDs = e(X), e(V), e(R), e(ID)
+    gic.gic_reorder(ctx, order, X.view(3, n), V, R, ID, Xs, Vs, Rs, IDs)
+    U = G.dev(u.reshape(-1), real)
+    A0 = torch.zeros(ctx.G, dtype=torch.int64, device="cuda")
+    gic.gic_p2g(ctx, Xs.view(3, n), Vs, Rs, cb, ce, A0, None)
+    uat = torch.empty(3 * n, dtype=real, device="cuda")
+    af = torch.empty(n, dtype=real, device="cuda")
+    gic.gic_g2p(ctx, Xs.view(3, n), U, A0, None, uat, af)
+    Fd = torch.empty(3 * n, dtype=real, device="cuda")
+    gic.gic_drag(ctx, Rs, Vs, uat, af, Fd)
+    Fc = torch.empty(3 * n, dtype=real, device="cuda")
+    gic.gic_contact_forces(ctx, Xs.view(3, n), Vs, Rs, cb, ce, Fc)
+    X1, V1 = Xs.clone(), Vs.clone()
+    gic.gic_integrate(ctx, Rs, Fc, Fd, X1, V1)
+    A1 = torch.empty(ctx.G, dtype=torch.int64, device="cuda")
+    M1 = torch.empty(3 * ctx.G, dtype=torch.int64, device="cuda")
+    gic.gic_p2g(ctx, X1.view(3, n), V1, Rs, cb, ce, A1, M1)
+    # fused
+    X2, V2, R2, ID2 = e(X), e(V), e(R), e(ID)
+    Fd2, uat2, af2 = e(Fd), e(uat), e(af)
+    gic.gic_gather_g2p_drag(ctx, order, X.view(3, n), V, R, ID, X2, V2, R2, ID2, U, A0, cb, ce, Fd2, uat2, af2)
+    for a, b in ((X2, Xs), (V2, Vs), (R2, Rs), (ID2, IDs), (Fd2, Fd), (uat2, uat), (af2, af)):
+        assert torch.equal(a, b)
+    Fd3 = e(Fd)
+    gic.gic_gather_g2p_drag(ctx, order, X.view(3, n), V, R, None, X2, V2, R2, None, U, A0, cb, ce, Fd3)
+    assert torch.equal(Fd3, Fd)
+    A2 = torch.full((ctx.G,), 7, dtype=torch.int64, device="cuda")
+    M2 = torch.full((3 * ctx.G,), 7, dtype=torch.int64, device="cuda")
+    X3, V3 = X2.clone(), V2.clone()
+    gic.gic_integrate_p2g(ctx, X2.view(3, n), V2, R2, Fc, Fd2, cb, ce, A2, M2)
+    assert torch.equal(X2, X1) and torch.equal(V2, V1)
+    assert torch.equal(A2, A1) and torch.equal(M2, M1)
+    gic.gic_integrate_p2g(ctx, X3.view(3, n), V3, R2, Fc, Fd2, cb, ce, A2, M2, accumulate=True)
+    assert torch.equal(A2, 2 * A1) and torch.equal(M2, 2 * M1)
+    assert ctx.error() == (0, -1)
