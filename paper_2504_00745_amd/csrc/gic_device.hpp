@@ -200,7 +200,8 @@ __device__ inline void g2p_sample(const DevParams &P, const double xa[3], Fetch 
     stencil_of(P, xa, s);
     T acc[3] = {(T)0, (T)0, (T)0};
     T as = (T)0;
-    for (int cz = 0; cz < 3; ++cz)
+#pragma unroll 1
+    for (int cz = 0; cz < 3; ++cz)  // one node plane at a time keeps few loads in flight per lane
         for (int cy = 0; cy < 3; ++cy) {
             const double wyz = s.w[1][cy] * s.w[2][cz];
             for (int cx = 0; cx < 3; ++cx) {
