@@ -86,6 +86,9 @@ def time_stages(sim, steps):
     ctx, s = sim.ctx, sim.scratch
     names = ["sort", "gather_g2p_drag", "contact", "integrate_p2g"]
     acc = {k: 0.0 for k in names}
+    # all steps are enqueued before the first synchronisation, so the stream
+    # never runs dry and each event pair brackets its kernel(s) only
+    evs = []
     for _ in range(steps):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
         cur, nxt = sim.cur, sim.nxt
@@ -96,16 +99,21 @@ def time_stages(sim, steps):
                                 nxt["r"], nxt["id"], sim.u, sim.alpha, s["cell_begin"], s["cell_end"], s["f_drag"])
         ev[2].record()
         gic.gic_contact_forces(ctx, nxt["x"], nxt["v"], nxt["r"], s["cell_begin"], s["cell_end"], s["f_contact"])
+        ev[3].record()
         sim.alpha.zero_()  # the grid clear, outside the timed kernel
         sim.mom.zero_()
-        ev[3].record()
+        ev_p = torch.cuda.Event(enable_timing=True)
+        ev_p.record()
         gic.gic_integrate_p2g(ctx, nxt["x"], nxt["v"], nxt["r"], s["f_contact"], s["f_drag"], s["cell_begin"],
                               s["cell_end"], sim.alpha, sim.mom, accumulate=True)
         ev[4].record()
         sim.cur, sim.nxt = nxt, cur
-        torch.cuda.synchronize()
-        for i, k in enumerate(names):
+        evs.append((ev, ev_p))
+    torch.cuda.synchronize()
+    for ev, ev_p in evs:
+        for i, k in enumerate(names[:3]):
             acc[k] += ev[i].elapsed_time(ev[i + 1]) / 1e3
+        acc["integrate_p2g"] += ev_p.elapsed_time(ev[4]) / 1e3
     return {k: v / steps for k, v in acc.items()}
 
 
