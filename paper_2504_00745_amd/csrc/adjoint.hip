@@ -239,14 +239,15 @@ __global__ void __launch_bounds__(256) k_g2p_vjp_x(DevParams P, int64_t n, const
 // Grid part of the G2P pullback: gA_k += -sum_i w_ik gaf_i for nodes below
 // the clamp.  One workgroup per brick, FP64 atomics into an LDS tile, then
 // into the grid.
-__global__ void __launch_bounds__(256) k_g2p_vjp_grid(DevParams P, int64_t n, int64_t nbricks,
+__global__ void __launch_bounds__(256) k_g2p_vjp_grid(DevParams P, int64_t n, const int32_t *__restrict__ bl,
+                                                      const int32_t *__restrict__ bcnt,
                                                       const double *__restrict__ x, const double *__restrict__ A,
                                                       const double *__restrict__ gaf,
                                                       const int32_t *__restrict__ cb, const int32_t *__restrict__ ce,
                                                       double *__restrict__ gA)
 {
     extern __shared__ double tile[];
-    const int64_t b = brick_block(nbricks);
+    const int64_t b = brick_of_block(bl, bcnt);
     if (b < 0) return;
     const int32_t beg = cb[b * kBrickCells], end = ce[b * kBrickCells + kBrickCells - 1];
     if (end <= beg) return;
@@ -400,7 +401,7 @@ hipError_t launch_integrate_vjp(const DevParams &P, int64_t n, const double *r, 
 
 hipError_t launch_g2p_vjp(const DevParams &P, int64_t n, int64_t K, const double *x, const double *u,
                           const double *A, const double *guat, const double *gaf, const int32_t *cb,
-                          const int32_t *ce, double *gx, double *gA, hipStream_t s)
+                          const int32_t *ce, const BrickList &B, double *gx, double *gA, hipStream_t s)
 {
     if (n == 0) return gA ? launch_fill_f64(gA, P.G, s) : hipSuccess;
     k_g2p_vjp_x<<<grid_for(n, 256), 256, 0, s>>>(P, n, x, u, A, guat, gaf, gx);
@@ -409,7 +410,7 @@ hipError_t launch_g2p_vjp(const DevParams &P, int64_t n, int64_t K, const double
         if (e != hipSuccess) return e;
         const int64_t bricks = K / kBrickCells;
         const size_t lds = sizeof(double) * (size_t)P.tile * P.tile * P.tile;
-        k_g2p_vjp_grid<<<brick_grid(bricks), 256, lds, s>>>(P, n, bricks, x, A, gaf, cb, ce, gA);
+        k_g2p_vjp_grid<<<brick_grid(bricks), 256, lds, s>>>(P, n, B.list, B.count, x, A, gaf, cb, ce, gA);
     }
     return hipGetLastError();
 }

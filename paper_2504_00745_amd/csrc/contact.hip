@@ -75,20 +75,30 @@ __device__ inline void add_pair(const DevParams &P, int64_t n, const double *__r
         d2 = (d0 * d0 + d1 * d1) + d2c * d2c;
     }
     const double R = ri + rj;
-    const double d = sqrt(d2);
     T nh[3];
+    T delta;
     if constexpr (sizeof(T) == sizeof(float)) {
-        const float inv_d = __builtin_amdgcn_rcpf((float)d);
+        // delta = (R^2 - d^2) / (R + d): the cancellation happens in the
+        // double difference of squares; the quotient needs only float d.
+        const float df = __builtin_amdgcn_sqrtf((float)d2);
+        const float inv_d = __builtin_amdgcn_rcpf(df);
         nh[0] = (float)d0 * inv_d;
         nh[1] = (float)d1 * inv_d;
         nh[2] = (float)d2c * inv_d;
+        double dsq;
+        {
+#pragma clang fp contract(off)
+            dsq = R * R - d2;
+        }
+        delta = (float)dsq * __builtin_amdgcn_rcpf((float)R + df);
     } else {
+        const double d = sqrt(d2);
         const double inv_d = 1.0 / d;
         nh[0] = d0 * inv_d;
         nh[1] = d1 * inv_d;
         nh[2] = d2c * inv_d;
+        delta = R - d;
     }
-    const T delta = (T)(R - d);
     const T w[3] = {(T)(vi[0] - v[j]), (T)(vi[1] - v[n + j]), (T)(vi[2] - v[2 * n + j])};
     const T mj = (T)mass_of(P, rj);
     const T mit = (T)mi;
@@ -242,7 +252,8 @@ __device__ inline int exact_pair(const DevParams &P, int64_t n, const double *__
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_contact_lds(DevParams P, int64_t n, int64_t nbricks, int cap,
+__global__ void __launch_bounds__(256) k_contact_lds(DevParams P, int64_t n, const int32_t *__restrict__ bl,
+                                                     const int32_t *__restrict__ bcnt, int cap,
                                                      const double *__restrict__ x, const double *__restrict__ v,
                                                      const double *__restrict__ r, const int32_t *__restrict__ cb,
                                                      const int32_t *__restrict__ ce, T *__restrict__ F,
@@ -257,7 +268,7 @@ __global__ void __launch_bounds__(256) k_contact_lds(DevParams P, int64_t n, int
     int32_t *s_wave = cgb + kHaloCells;                                    // [4]
     uint8_t *scell = reinterpret_cast<uint8_t *>(s_wave + 4);              // [cap] shell cell of each slot
     const int tid = threadIdx.x;
-    const int64_t b = brick_block(nbricks);
+    const int64_t b = brick_of_block(bl, bcnt);
     if (b < 0) return;
     const int32_t bc[3] = {(int32_t)(b % P.nb[0]), (int32_t)((b / P.nb[0]) % P.nb[1]),
                            (int32_t)(b / ((int64_t)P.nb[0] * P.nb[1]))};
@@ -443,22 +454,23 @@ static size_t contact_lds_bytes(int cap)
 
 template <typename T>
 hipError_t launch_contact(const DevParams &P, int64_t n, const double *x, const double *v, const double *r,
-                          const int32_t *cb, const int32_t *ce, T *F, int32_t *ncont, int64_t *err, hipStream_t s)
+                          const int32_t *cb, const int32_t *ce, const BrickList &B, T *F, int32_t *ncont,
+                          int64_t *err, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     const int64_t nbricks = (int64_t)P.nb[0] * P.nb[1] * P.nb[2];
     const int cap = 1952;  // shell slots held in LDS: 40,912 bytes, four workgroups per CU
-    k_contact_lds<T><<<brick_grid(nbricks), 256, contact_lds_bytes(cap), s>>>(P, n, nbricks, cap, x, v, r, cb, ce, F,
-                                                                            ncont, err);
+    k_contact_lds<T><<<brick_grid(nbricks), 256, contact_lds_bytes(cap), s>>>(P, n, B.list, B.count, cap, x, v, r, cb,
+                                                                            ce, F, ncont, err);
     return hipGetLastError();
 }
 
 template hipError_t launch_contact<float>(const DevParams &, int64_t, const double *, const double *,
-                                          const double *, const int32_t *, const int32_t *, float *, int32_t *,
-                                          int64_t *, hipStream_t);
+                                          const double *, const int32_t *, const int32_t *, const BrickList &,
+                                          float *, int32_t *, int64_t *, hipStream_t);
 template hipError_t launch_contact<double>(const DevParams &, int64_t, const double *, const double *,
-                                           const double *, const int32_t *, const int32_t *, double *, int32_t *,
-                                           int64_t *, hipStream_t);
+                                           const double *, const int32_t *, const int32_t *, const BrickList &,
+                                           double *, int32_t *, int64_t *, hipStream_t);
 
 hipError_t launch_contact_pairs(const DevParams &P, int64_t n, const double *x, const double *r,
                                 const int32_t *cb, const int32_t *ce, int32_t *pairs, int64_t cap,

@@ -16,6 +16,8 @@ struct gic_ctx {
     SortScratch sort;
     int64_t *err;  // device: [code, index]
     double *part;  // device: partial sums of gic_sum
+    BrickList bricks;  // device: occupied bricks of the last cell ranges given
+    bool in_step;      // inside gic_step, which builds the brick list once
     int device;
 };
 
@@ -106,6 +108,14 @@ bool n_ok(const gic_ctx *c, int64_t n) { return c && n >= 0 && n <= c->n_max; }
 
 constexpr int kSumParts = 1024;
 
+// The brick schedule of the cell ranges a call is given, built on the stream
+// before its brick kernel; gic_step builds it once after its sort.
+hipError_t brick_list(gic_ctx *c, const int32_t *cb, const int32_t *ce, hipStream_t s)
+{
+    if (c->in_step) return hipSuccess;
+    return launch_brick_list(cb, ce, c->bricks, s);
+}
+
 }  // namespace
 
 extern "C" {
@@ -142,6 +152,10 @@ gic_status gic_create(const gic_params *p, int64_t n_max, gic_ctx **out)
     ok &= hipMalloc(&c->sort.sums, sizeof(uint32_t) * 1024) == hipSuccess;
     ok &= hipMalloc(&c->err, sizeof(int64_t) * 2) == hipSuccess;
     ok &= hipMalloc(&c->part, sizeof(double) * kSumParts) == hipSuccess;
+    c->bricks.nbricks = c->K / kBrickCells;
+    ok &= hipMalloc(&c->bricks.list, sizeof(int32_t) * (c->bricks.nbricks > 0 ? c->bricks.nbricks : 1)) == hipSuccess;
+    ok &= hipMalloc(&c->bricks.count, sizeof(int32_t)) == hipSuccess;
+    ok &= hipMalloc(&c->bricks.sums, sizeof(uint32_t) * 1024) == hipSuccess;
     if (ok) ok = hipMemset(c->err, 0, sizeof(int64_t) * 2) == hipSuccess;
     if (!ok) {
         gic_destroy(c);
@@ -175,6 +189,9 @@ gic_status gic_destroy(gic_ctx *c)
     (void)hipFree(c->sort.sums);
     (void)hipFree(c->err);
     (void)hipFree(c->part);
+    (void)hipFree(c->bricks.list);
+    (void)hipFree(c->bricks.count);
+    (void)hipFree(c->bricks.sums);
     delete c;
     return hip_status(e);
 }
@@ -222,11 +239,13 @@ gic_status gic_contact_forces(gic_ctx *c, int64_t n, const double *x, const doub
     if (!n_ok(c, n)) return GIC_E_ARG;
     if (n > 0 && (!x || !v || !r || !cell_begin || !cell_end || !f_contact)) return GIC_E_ARG;
     hipStream_t s = (hipStream_t)stream;
+    if (n == 0) return GIC_OK;
+    if (brick_list(c, cell_begin, cell_end, s) != hipSuccess) return GIC_E_HIP;
     if (fp32(c))
-        return hip_status(launch_contact<float>(c->dp, n, x, v, r, cell_begin, cell_end, (float *)f_contact,
-                                                n_contacts, c->err, s));
-    return hip_status(launch_contact<double>(c->dp, n, x, v, r, cell_begin, cell_end, (double *)f_contact,
-                                             n_contacts, c->err, s));
+        return hip_status(launch_contact<float>(c->dp, n, x, v, r, cell_begin, cell_end, c->bricks,
+                                                (float *)f_contact, n_contacts, c->err, s));
+    return hip_status(launch_contact<double>(c->dp, n, x, v, r, cell_begin, cell_end, c->bricks,
+                                             (double *)f_contact, n_contacts, c->err, s));
 }
 
 gic_status gic_contact_pairs(gic_ctx *c, int64_t n, const double *x, const double *r, const int32_t *cell_begin,
@@ -290,7 +309,10 @@ gic_status gic_p2g(gic_ctx *c, int64_t n, const double *x, const double *v, cons
         if (e == hipSuccess && mom_fx) e = launch_fill_i64(mom_fx, 3 * G, s);
         if (e != hipSuccess) return GIC_E_HIP;
     }
-    return hip_status(launch_p2g_fixed(c->dp, n, c->K, x, v, r, cell_begin, cell_end, alpha_fx, mom_fx, c->err, s));
+    if (n == 0) return GIC_OK;
+    if (brick_list(c, cell_begin, cell_end, s) != hipSuccess) return GIC_E_HIP;
+    return hip_status(
+        launch_p2g_fixed(c->dp, n, c->K, x, v, r, cell_begin, cell_end, c->bricks, alpha_fx, mom_fx, c->err, s));
 }
 
 gic_status gic_p2g_real(gic_ctx *c, int64_t n, const double *x, const double *v, const double *r,
@@ -306,7 +328,9 @@ gic_status gic_p2g_real(gic_ctx *c, int64_t n, const double *x, const double *v,
         if (e == hipSuccess && mom) e = launch_fill_f64(mom, 3 * G, s);
         if (e != hipSuccess) return GIC_E_HIP;
     }
-    return hip_status(launch_p2g_real(c->dp, n, c->K, x, v, r, cell_begin, cell_end, alpha, mom, s));
+    if (n == 0) return GIC_OK;
+    if (brick_list(c, cell_begin, cell_end, s) != hipSuccess) return GIC_E_HIP;
+    return hip_status(launch_p2g_real(c->dp, n, c->K, x, v, r, cell_begin, cell_end, c->bricks, alpha, mom, s));
 }
 
 gic_status gic_gather_g2p_drag(gic_ctx *c, int64_t n, const int32_t *order, const double *x, const double *v,
@@ -319,12 +343,15 @@ gic_status gic_gather_g2p_drag(gic_ctx *c, int64_t n, const int32_t *order, cons
         return GIC_E_ARG;
     if ((id == nullptr) != (id_out == nullptr) || (u_at == nullptr) != (alpha_f == nullptr)) return GIC_E_ARG;
     hipStream_t s = (hipStream_t)stream;
+    if (n == 0) return GIC_OK;
+    if (brick_list(c, cell_begin, cell_end, s) != hipSuccess) return GIC_E_HIP;
     if (fp32(c))
         return hip_status(launch_gather_g2p_drag<float>(c->dp, n, c->K, order, x, v, r, id, x_out, v_out, r_out,
                                                         id_out, (const float *)u, alpha_fx, cell_begin, cell_end,
-                                                        (float *)f_drag, (float *)u_at, (float *)alpha_f, s));
+                                                        c->bricks, (float *)f_drag, (float *)u_at, (float *)alpha_f,
+                                                        s));
     return hip_status(launch_gather_g2p_drag<double>(c->dp, n, c->K, order, x, v, r, id, x_out, v_out, r_out, id_out,
-                                                     (const double *)u, alpha_fx, cell_begin, cell_end,
+                                                     (const double *)u, alpha_fx, cell_begin, cell_end, c->bricks,
                                                      (double *)f_drag, (double *)u_at, (double *)alpha_f, s));
 }
 
@@ -340,13 +367,15 @@ gic_status gic_integrate_p2g(gic_ctx *c, int64_t n, double *x, double *v, const 
         if (e == hipSuccess) e = launch_fill_i64(mom_fx, 3 * c->dp.G, s);
         if (e != hipSuccess) return GIC_E_HIP;
     }
+    if (n == 0) return GIC_OK;
+    if (brick_list(c, cell_begin, cell_end, s) != hipSuccess) return GIC_E_HIP;
     if (fp32(c))
         return hip_status(launch_integrate_p2g<float>(c->dp, n, c->K, x, v, r, (const float *)f_contact,
-                                                      (const float *)f_drag, cell_begin, cell_end, alpha_fx, mom_fx,
-                                                      c->err, s));
+                                                      (const float *)f_drag, cell_begin, cell_end, c->bricks,
+                                                      alpha_fx, mom_fx, c->err, s));
     return hip_status(launch_integrate_p2g<double>(c->dp, n, c->K, x, v, r, (const double *)f_contact,
-                                                   (const double *)f_drag, cell_begin, cell_end, alpha_fx, mom_fx,
-                                                   c->err, s));
+                                                   (const double *)f_drag, cell_begin, cell_end, c->bricks, alpha_fx,
+                                                   mom_fx, c->err, s));
 }
 
 gic_status gic_step(gic_ctx *c, int64_t n, const double *x_cur, const double *v_cur, const double *r_cur,
@@ -362,16 +391,19 @@ gic_status gic_step(gic_ctx *c, int64_t n, const double *x_cur, const double *v_
     if ((id_cur == nullptr) != (id_nxt == nullptr) || (u_at == nullptr) != (alpha_f == nullptr)) return GIC_E_ARG;
     gic_status st;
     if ((st = gic_sort_cells(c, n, x_cur, key, order, cell_begin, cell_end, stream)) != GIC_OK) return st;
+    if (n > 0 && launch_brick_list(cell_begin, cell_end, c->bricks, (hipStream_t)stream) != hipSuccess) return GIC_E_HIP;
+    c->in_step = true;  // the three stages below share this brick list
     // alpha_fx was deposited at the current positions and is read by node,
     // so the gather into sorted order does not change it
-    if ((st = gic_gather_g2p_drag(c, n, order, x_cur, v_cur, r_cur, id_cur, x_nxt, v_nxt, r_nxt, id_nxt, u, alpha_fx,
-                                  cell_begin, cell_end, f_drag, u_at, alpha_f, stream)) != GIC_OK)
-        return st;
-    if ((st = gic_contact_forces(c, n, x_nxt, v_nxt, r_nxt, cell_begin, cell_end, f_contact, nullptr, stream)) !=
-        GIC_OK)
-        return st;
-    return gic_integrate_p2g(c, n, x_nxt, v_nxt, r_nxt, f_contact, f_drag, cell_begin, cell_end, alpha_fx, mom_fx, 0,
-                             stream);
+    st = gic_gather_g2p_drag(c, n, order, x_cur, v_cur, r_cur, id_cur, x_nxt, v_nxt, r_nxt, id_nxt, u, alpha_fx,
+                             cell_begin, cell_end, f_drag, u_at, alpha_f, stream);
+    if (st == GIC_OK)
+        st = gic_contact_forces(c, n, x_nxt, v_nxt, r_nxt, cell_begin, cell_end, f_contact, nullptr, stream);
+    if (st == GIC_OK)
+        st = gic_integrate_p2g(c, n, x_nxt, v_nxt, r_nxt, f_contact, f_drag, cell_begin, cell_end, alpha_fx, mom_fx, 0,
+                               stream);
+    c->in_step = false;
+    return st;
 }
 
 /* ---- adjoint form (double) ---------------------------------------------- */
@@ -412,8 +444,10 @@ gic_status gic_g2p_vjp(gic_ctx *c, int64_t n, const double *x, const double *u, 
     if (!n_ok(c, n) || fp32(c)) return GIC_E_ARG;
     if (n > 0 && (!x || !u || !alpha_real || !g_u_at || !g_alpha_f || !g_x)) return GIC_E_ARG;
     if (n > 0 && g_alpha && (!cell_begin || !cell_end)) return GIC_E_ARG;
-    return hip_status(launch_g2p_vjp(c->dp, n, c->K, x, u, alpha_real, g_u_at, g_alpha_f, cell_begin, cell_end, g_x,
-                                     g_alpha, (hipStream_t)stream));
+    if (n > 0 && g_alpha && brick_list(c, cell_begin, cell_end, (hipStream_t)stream) != hipSuccess)
+        return GIC_E_HIP;
+    return hip_status(launch_g2p_vjp(c->dp, n, c->K, x, u, alpha_real, g_u_at, g_alpha_f, cell_begin, cell_end,
+                                     c->bricks, g_x, g_alpha, (hipStream_t)stream));
 }
 
 gic_status gic_p2g_vjp(gic_ctx *c, int64_t n, const double *x, const double *v, const double *r,

@@ -42,31 +42,22 @@ __device__ inline int64_t xcd_block(int64_t nlogical)
     return l < nlogical ? l : -1;
 }
 
-// Brick kernels: the occupied bricks of a bed are often one contiguous part
-// of the brick order (the lower half of the box, say), so a contiguous
-// eighth per XCD would leave XCDs idle.  Bricks are instead dealt to the XCDs
-// in chunks of kBrickChunk consecutive bricks; chunk i of super-row s (8
-// chunks) goes to XCD (i + s) mod 8, so every super-row feeds every XCD once
-// and the skew keeps a pattern that repeats every 8 chunks from landing on
-// one XCD.  Launch with brick_grid(nbricks) workgroups; brick_block returns
-// the brick or -1.
-constexpr int kBrickChunk = 4;
+// Brick kernels run over the list of occupied bricks, in brick order (a bed
+// often fills only part of the box); each XCD takes one contiguous eighth
+// of the list, so the load is even and neighbouring bricks, which read
+// overlapping cells and nodes, mostly share an L2.  Launch with
+// brick_grid(nbricks) workgroups (an upper bound of the list length);
+// brick_of_block returns the brick or -1.
+inline unsigned brick_grid(int64_t nbricks) { return xcd_grid(nbricks); }
 
-inline unsigned brick_grid(int64_t nbricks)
+__device__ inline int64_t brick_of_block(const int32_t *__restrict__ list, const int32_t *__restrict__ count)
 {
-    const int64_t chunks = (nbricks + kBrickChunk - 1) / kBrickChunk;
-    const int64_t rows = (chunks + kXcds - 1) / kXcds;
-    return (unsigned)(rows > 0 ? rows * kXcds * kBrickChunk : kXcds);
-}
-
-__device__ inline int64_t brick_block(int64_t nbricks)
-{
+    const int64_t nocc = *count;
+    const int64_t per = (nocc + kXcds - 1) / kXcds;  // list entries per XCD
     const int64_t b = blockIdx.x;
-    const int64_t k = b % kXcds, j = b / kXcds;  // XCD and slot on it
-    const int64_t srow = j / kBrickChunk, off = j % kBrickChunk;
-    const int64_t i = (k - srow % kXcds + kXcds) % kXcds;
-    const int64_t l = (srow * kXcds + i) * kBrickChunk + off;
-    return l < nbricks ? l : -1;
+    const int64_t j = b / kXcds;  // slot on the XCD; the grid has slots to spare
+    const int64_t l = (b % kXcds) * per + j;
+    return j < per && l < nocc ? list[l] : -1;
 }
 
 // Latched error codes (same values as gic_status).

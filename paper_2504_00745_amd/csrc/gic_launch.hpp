@@ -19,6 +19,17 @@ struct SortScratch {
     int passes;         // 8-bit digit passes over the key bits
 };
 
+// Occupied bricks of a set of cell ranges, in brick order (see
+// brick_of_block), built by launch_brick_list before the brick kernels.
+struct BrickList {
+    int32_t *list;    // [nbricks]
+    int32_t *count;   // [1]
+    uint32_t *sums;   // [<= 1024] block totals
+    int64_t nbricks;
+};
+
+hipError_t launch_brick_list(const int32_t *cb, const int32_t *ce, BrickList &B, hipStream_t s);
+
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 8;
 constexpr int kSortTile = kSortThreads * kSortItems;
@@ -31,8 +42,8 @@ hipError_t launch_reorder(int64_t n, const int32_t *order, const double *x, cons
 
 template <typename T>
 hipError_t launch_contact(const DevParams &P, int64_t n, const double *x, const double *v, const double *r,
-                          const int32_t *cb, const int32_t *ce, T *F, int32_t *ncont, int64_t *err,
-                          hipStream_t s);
+                          const int32_t *cb, const int32_t *ce, const BrickList &B, T *F, int32_t *ncont,
+                          int64_t *err, hipStream_t s);
 hipError_t launch_contact_pairs(const DevParams &P, int64_t n, const double *x, const double *r,
                                 const int32_t *cb, const int32_t *ce, int32_t *pairs, int64_t cap,
                                 int64_t *count, hipStream_t s);
@@ -50,20 +61,20 @@ hipError_t launch_integrate(const DevParams &P, int64_t n, const double *r, cons
 hipError_t launch_fill_i64(int64_t *a, int64_t len, hipStream_t s);
 hipError_t launch_fill_f64(double *a, int64_t len, hipStream_t s);
 hipError_t launch_p2g_fixed(const DevParams &P, int64_t n, int64_t K, const double *x, const double *v,
-                            const double *r, const int32_t *cb, const int32_t *ce, int64_t *alpha, int64_t *mom,
-                            int64_t *err, hipStream_t s);
+                            const double *r, const int32_t *cb, const int32_t *ce, const BrickList &B,
+                            int64_t *alpha, int64_t *mom, int64_t *err, hipStream_t s);
 template <typename T>
 hipError_t launch_integrate_p2g(const DevParams &P, int64_t n, int64_t K, double *x, double *v, const double *r,
-                                const T *Fc, const T *Fd, const int32_t *cb, const int32_t *ce, int64_t *alpha,
-                                int64_t *mom, int64_t *err, hipStream_t s);
+                                const T *Fc, const T *Fd, const int32_t *cb, const int32_t *ce, const BrickList &B,
+                                int64_t *alpha, int64_t *mom, int64_t *err, hipStream_t s);
 template <typename T>
 hipError_t launch_gather_g2p_drag(const DevParams &P, int64_t n, int64_t K, const int32_t *order, const double *x,
                                   const double *v, const double *r, const int32_t *id, double *xo, double *vo,
                                   double *ro, int32_t *ido, const T *u, const int64_t *afx, const int32_t *cb,
-                                  const int32_t *ce, T *Fd, T *uat, T *af, hipStream_t s);
+                                  const int32_t *ce, const BrickList &B, T *Fd, T *uat, T *af, hipStream_t s);
 hipError_t launch_p2g_real(const DevParams &P, int64_t n, int64_t K, const double *x, const double *v,
-                           const double *r, const int32_t *cb, const int32_t *ce, double *alpha, double *mom,
-                           hipStream_t s);
+                           const double *r, const int32_t *cb, const int32_t *ce, const BrickList &B,
+                           double *alpha, double *mom, hipStream_t s);
 
 hipError_t launch_contact_vjp(const DevParams &P, int64_t n, const double *x, const double *v, const double *r,
                               const int32_t *cb, const int32_t *ce, const double *gF, double *gx, double *gv,
@@ -75,7 +86,7 @@ hipError_t launch_integrate_vjp(const DevParams &P, int64_t n, const double *r, 
                                 double *gF, hipStream_t s);
 hipError_t launch_g2p_vjp(const DevParams &P, int64_t n, int64_t K, const double *x, const double *u,
                           const double *A, const double *guat, const double *gaf, const int32_t *cb,
-                          const int32_t *ce, double *gx, double *gA, hipStream_t s);
+                          const int32_t *ce, const BrickList &B, double *gx, double *gA, hipStream_t s);
 hipError_t launch_p2g_vjp(const DevParams &P, int64_t n, const double *x, const double *v, const double *r,
                           const double *gA, const double *gP, double *gx, double *gv, hipStream_t s);
 hipError_t launch_sum(const double *a, const double *b, int64_t n, double *part, int nparts, double *out, int acc,

@@ -253,6 +253,54 @@ __global__ void __launch_bounds__(256) k_reorder(int64_t n, const int32_t *__res
     if (ido) ido[q] = id[i];
 }
 
+// ---- occupied bricks, in brick order (the schedule of the brick kernels) ----
+
+__device__ inline bool brick_occupied(int64_t b, const int32_t *__restrict__ cb, const int32_t *__restrict__ ce)
+{
+    return ce[b * kBrickCells + kBrickCells - 1] > cb[b * kBrickCells];
+}
+
+__global__ void __launch_bounds__(256) k_brick_count(int64_t nbricks, int64_t per_block, const int32_t *__restrict__ cb,
+                                                     const int32_t *__restrict__ ce, uint32_t *__restrict__ sums)
+{
+    __shared__ uint32_t lds[4];
+    const int64_t lo = (int64_t)blockIdx.x * per_block;
+    const int64_t hi = lo + per_block < nbricks ? lo + per_block : nbricks;
+    uint32_t c = 0;
+    for (int64_t b = lo + threadIdx.x; b < hi; b += 256) c += brick_occupied(b, cb, ce) ? 1u : 0u;
+    c = block_reduce_sum(c, lds);
+    if (threadIdx.x == 0) sums[blockIdx.x] = c;
+}
+
+// Exclusive scan of the block counts in place; the total is the list length.
+__global__ void __launch_bounds__(kScanThreads) k_brick_spine(uint32_t *sums, int nb, int32_t *count)
+{
+    __shared__ uint32_t lds[kScanThreads / 64];
+    const uint32_t v = threadIdx.x < nb ? sums[threadIdx.x] : 0u;
+    uint32_t total;
+    const uint32_t inc = block_scan_inclusive(v, lds, &total);
+    if (threadIdx.x < nb) sums[threadIdx.x] = inc - v;
+    if (threadIdx.x == 0) *count = (int32_t)total;
+}
+
+__global__ void __launch_bounds__(256) k_brick_scatter(int64_t nbricks, int64_t per_block,
+                                                       const int32_t *__restrict__ cb, const int32_t *__restrict__ ce,
+                                                       const uint32_t *__restrict__ sums, int32_t *__restrict__ list)
+{
+    __shared__ uint32_t lds[4];
+    const int64_t lo = (int64_t)blockIdx.x * per_block;
+    const int64_t hi = lo + per_block < nbricks ? lo + per_block : nbricks;
+    uint32_t base = sums[blockIdx.x];
+    for (int64_t b0 = lo; b0 < hi; b0 += 256) {  // same trip count for the whole workgroup
+        const int64_t b = b0 + threadIdx.x;
+        const uint32_t f = b < hi && brick_occupied(b, cb, ce) ? 1u : 0u;
+        uint32_t total;
+        const uint32_t inc = block_scan_inclusive(f, lds, &total);
+        if (f) list[base + inc - 1] = (int32_t)b;
+        base += total;
+    }
+}
+
 }  // namespace
 
 namespace {
@@ -303,6 +351,19 @@ hipError_t launch_sort_cells(const DevParams &P, int64_t n, const double *x, uin
     k_scan_reduce<<<nb, kScanThreads, 0, s>>>(cnt, K, chunk, S.sums);
     k_scan_spine<<<1, kScanThreads, 0, s>>>(S.sums, nb);
     k_scan_down_ranges<<<nb, kScanThreads, 0, s>>>(cnt, reinterpret_cast<uint32_t *>(cell_begin), K, chunk, S.sums);
+    return hipGetLastError();
+}
+
+hipError_t launch_brick_list(const int32_t *cb, const int32_t *ce, BrickList &B, hipStream_t s)
+{
+    const int64_t nb = B.nbricks;
+    if (nb <= 0) return hipSuccess;
+    int64_t per = 1024;
+    while ((nb + per - 1) / per > kScanThreads) per *= 2;
+    const int blocks = (int)((nb + per - 1) / per);
+    k_brick_count<<<blocks, 256, 0, s>>>(nb, per, cb, ce, B.sums);
+    k_brick_spine<<<1, kScanThreads, 0, s>>>(B.sums, blocks, B.count);
+    k_brick_scatter<<<blocks, 256, 0, s>>>(nb, per, cb, ce, B.sums, B.list);
     return hipGetLastError();
 }
 

@@ -12,7 +12,8 @@ namespace gic {
 namespace {
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_gather_g2p_drag(DevParams P, int64_t n, int64_t nbricks,
+__global__ void __launch_bounds__(256) k_gather_g2p_drag(DevParams P, int64_t n, const int32_t *__restrict__ bl,
+                                                         const int32_t *__restrict__ bcnt,
                                                          const int32_t *__restrict__ order,
                                                          const double *__restrict__ x, const double *__restrict__ v,
                                                          const double *__restrict__ r, const int32_t *__restrict__ id,
@@ -23,7 +24,7 @@ __global__ void __launch_bounds__(256) k_gather_g2p_drag(DevParams P, int64_t n,
                                                          T *__restrict__ Fd, T *__restrict__ uat, T *__restrict__ af)
 {
     extern __shared__ double smem_d[];
-    const int64_t b = brick_block(nbricks);
+    const int64_t b = brick_of_block(bl, bcnt);
     if (b < 0) return;
     const int32_t gb = cb[b * kBrickCells], ge = ce[b * kBrickCells + kBrickCells - 1];
     if (ge <= gb) return;
@@ -88,26 +89,26 @@ template <typename T>
 hipError_t launch_gather_g2p_drag(const DevParams &P, int64_t n, int64_t K, const int32_t *order, const double *x,
                                   const double *v, const double *r, const int32_t *id, double *xo, double *vo,
                                   double *ro, int32_t *ido, const T *u, const int64_t *afx, const int32_t *cb,
-                                  const int32_t *ce, T *Fd, T *uat, T *af, hipStream_t s)
+                                  const int32_t *ce, const BrickList &B, T *Fd, T *uat, T *af, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     const int64_t bricks = K / kBrickCells;
     const int E = P.tile;
     const size_t lds = sizeof(T) * 4 * (size_t)E * E * E;
-    k_gather_g2p_drag<T><<<brick_grid(bricks), 256, lds, s>>>(P, n, bricks, order, x, v, r, id, xo, vo, ro, ido, u,
-                                                              afx, cb, ce, Fd, uat, af);
+    k_gather_g2p_drag<T><<<brick_grid(bricks), 256, lds, s>>>(P, n, B.list, B.count, order, x, v, r, id, xo, vo, ro,
+                                                              ido, u, afx, cb, ce, Fd, uat, af);
     return hipGetLastError();
 }
 
 template hipError_t launch_gather_g2p_drag<float>(const DevParams &, int64_t, int64_t, const int32_t *,
                                                   const double *, const double *, const double *, const int32_t *,
                                                   double *, double *, double *, int32_t *, const float *,
-                                                  const int64_t *, const int32_t *, const int32_t *, float *, float *,
-                                                  float *, hipStream_t);
+                                                  const int64_t *, const int32_t *, const int32_t *,
+                                                  const BrickList &, float *, float *, float *, hipStream_t);
 template hipError_t launch_gather_g2p_drag<double>(const DevParams &, int64_t, int64_t, const int32_t *,
                                                    const double *, const double *, const double *, const int32_t *,
                                                    double *, double *, double *, int32_t *, const double *,
-                                                   const int64_t *, const int32_t *, const int32_t *, double *,
-                                                   double *, double *, hipStream_t);
+                                                   const int64_t *, const int32_t *, const int32_t *,
+                                                   const BrickList &, double *, double *, double *, hipStream_t);
 
 }  // namespace gic

@@ -86,7 +86,8 @@ __device__ inline void tile_add(unsigned long long *tile, unsigned long long *gl
 // the granule is deposited at its new position; each granule is read and
 // written by one thread only.
 template <bool MOM, typename T, bool INTEG>
-__global__ void __launch_bounds__(kP2GThreads) k_p2g_fixed(DevParams P, int64_t n, int64_t nbricks, int batch,
+__global__ void __launch_bounds__(kP2GThreads) k_p2g_fixed(DevParams P, int64_t n, const int32_t *__restrict__ bl,
+                                                           const int32_t *__restrict__ bcnt, int batch,
                                                            double *x, double *v, const double *__restrict__ r,
                                                            const T *__restrict__ Fc, const T *__restrict__ Fd,
                                                            const int32_t *__restrict__ cb,
@@ -99,7 +100,7 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g_fixed(DevParams P, int64_t 
     extern __shared__ unsigned long long tile[];
     __shared__ int32_t s_range[2];
     __shared__ int32_t s_wave[kP2GThreads / 64];
-    const int64_t b = brick_block(nbricks);
+    const int64_t b = brick_of_block(bl, bcnt);
     if (b < 0) return;
     brick_range(b, cb, ce, s_range);
     __syncthreads();
@@ -271,7 +272,8 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g_fixed(DevParams P, int64_t 
     }
 }
 
-__global__ void __launch_bounds__(kP2GThreads) k_p2g_real(DevParams P, int64_t n, int64_t nbricks,
+__global__ void __launch_bounds__(kP2GThreads) k_p2g_real(DevParams P, int64_t n, const int32_t *__restrict__ bl,
+                                                          const int32_t *__restrict__ bcnt,
                                                           const double *__restrict__ x,
                                                           const double *__restrict__ v,
                                                           const double *__restrict__ r,
@@ -281,7 +283,7 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g_real(DevParams P, int64_t n
 {
     extern __shared__ double dtile[];
     __shared__ int32_t s_range[2];
-    const int64_t b = brick_block(nbricks);
+    const int64_t b = brick_of_block(bl, bcnt);
     if (b < 0) return;
     brick_range(b, cb, ce, s_range);
     __syncthreads();
@@ -388,8 +390,8 @@ static size_t p2g_lds(int nch, int E3, int batch)
 
 template <typename T, bool INTEG>
 static hipError_t p2g_fixed_impl(const DevParams &P, int64_t n, int64_t K, double *x, double *v, const double *r,
-                                 const T *Fc, const T *Fd, const int32_t *cb, const int32_t *ce, int64_t *alpha,
-                                 int64_t *mom, int64_t *err, hipStream_t s)
+                                 const T *Fc, const T *Fd, const int32_t *cb, const int32_t *ce, const BrickList &B,
+                                 int64_t *alpha, int64_t *mom, int64_t *err, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     const int64_t bricks = K / kBrickCells;
@@ -401,47 +403,49 @@ static hipError_t p2g_fixed_impl(const DevParams &P, int64_t n, int64_t K, doubl
     unsigned long long *A = reinterpret_cast<unsigned long long *>(alpha);
     unsigned long long *M = reinterpret_cast<unsigned long long *>(mom);
     if (mom)
-        k_p2g_fixed<true, T, INTEG><<<brick_grid(bricks), kP2GThreads, lds, s>>>(P, n, bricks, batch, x, v, r, Fc, Fd,
-                                                                                 cb, ce, A, M, err);
+        k_p2g_fixed<true, T, INTEG><<<brick_grid(bricks), kP2GThreads, lds, s>>>(P, n, B.list, B.count, batch, x, v, r,
+                                                                                 Fc, Fd, cb, ce, A, M, err);
     else
-        k_p2g_fixed<false, T, INTEG><<<brick_grid(bricks), kP2GThreads, lds, s>>>(P, n, bricks, batch, x, v, r, Fc,
-                                                                                  Fd, cb, ce, A, nullptr, err);
+        k_p2g_fixed<false, T, INTEG><<<brick_grid(bricks), kP2GThreads, lds, s>>>(P, n, B.list, B.count, batch, x, v,
+                                                                                  r, Fc, Fd, cb, ce, A, nullptr, err);
     return hipGetLastError();
 }
 
 hipError_t launch_p2g_fixed(const DevParams &P, int64_t n, int64_t K, const double *x, const double *v,
-                            const double *r, const int32_t *cb, const int32_t *ce, int64_t *alpha, int64_t *mom,
-                            int64_t *err, hipStream_t s)
+                            const double *r, const int32_t *cb, const int32_t *ce, const BrickList &B,
+                            int64_t *alpha, int64_t *mom, int64_t *err, hipStream_t s)
 {
     // x and v are only read on this path
     return p2g_fixed_impl<float, false>(P, n, K, const_cast<double *>(x), const_cast<double *>(v), r, nullptr,
-                                        nullptr, cb, ce, alpha, mom, err, s);
+                                        nullptr, cb, ce, B, alpha, mom, err, s);
 }
 
 template <typename T>
 hipError_t launch_integrate_p2g(const DevParams &P, int64_t n, int64_t K, double *x, double *v, const double *r,
-                                const T *Fc, const T *Fd, const int32_t *cb, const int32_t *ce, int64_t *alpha,
-                                int64_t *mom, int64_t *err, hipStream_t s)
+                                const T *Fc, const T *Fd, const int32_t *cb, const int32_t *ce, const BrickList &B,
+                                int64_t *alpha, int64_t *mom, int64_t *err, hipStream_t s)
 {
-    return p2g_fixed_impl<T, true>(P, n, K, x, v, r, Fc, Fd, cb, ce, alpha, mom, err, s);
+    return p2g_fixed_impl<T, true>(P, n, K, x, v, r, Fc, Fd, cb, ce, B, alpha, mom, err, s);
 }
 
 template hipError_t launch_integrate_p2g<float>(const DevParams &, int64_t, int64_t, double *, double *,
                                                 const double *, const float *, const float *, const int32_t *,
-                                                const int32_t *, int64_t *, int64_t *, int64_t *, hipStream_t);
+                                                const int32_t *, const BrickList &, int64_t *, int64_t *, int64_t *,
+                                                hipStream_t);
 template hipError_t launch_integrate_p2g<double>(const DevParams &, int64_t, int64_t, double *, double *,
                                                  const double *, const double *, const double *, const int32_t *,
-                                                 const int32_t *, int64_t *, int64_t *, int64_t *, hipStream_t);
+                                                 const int32_t *, const BrickList &, int64_t *, int64_t *, int64_t *,
+                                                 hipStream_t);
 
 hipError_t launch_p2g_real(const DevParams &P, int64_t n, int64_t K, const double *x, const double *v,
-                           const double *r, const int32_t *cb, const int32_t *ce, double *alpha, double *mom,
-                           hipStream_t s)
+                           const double *r, const int32_t *cb, const int32_t *ce, const BrickList &B,
+                           double *alpha, double *mom, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     const int64_t bricks = K / kBrickCells;
     const int E3 = P.tile * P.tile * P.tile;
     const size_t lds = sizeof(double) * 4 * (size_t)E3;
-    k_p2g_real<<<brick_grid(bricks), kP2GThreads, lds, s>>>(P, n, bricks, x, v, r, cb, ce, alpha, mom);
+    k_p2g_real<<<brick_grid(bricks), kP2GThreads, lds, s>>>(P, n, B.list, B.count, x, v, r, cb, ce, alpha, mom);
     return hipGetLastError();
 }
 
