@@ -150,6 +150,8 @@ gic_status gic_create(const gic_params *p, int64_t n_max, gic_ctx **out)
     ok &= hipMalloc(&c->sort.vB, sizeof(int32_t) * nn) == hipSuccess;
     ok &= hipMalloc(&c->sort.hist, sizeof(uint32_t) * 256 * tiles) == hipSuccess;
     ok &= hipMalloc(&c->sort.sums, sizeof(uint32_t) * 1024) == hipSuccess;
+    ok &= hipMalloc(&c->sort.cnt, sizeof(uint32_t) * (c->K > 0 ? c->K : 1)) == hipSuccess;
+    if (ok) ok = hipMemset(c->sort.cnt, 0, sizeof(uint32_t) * (c->K > 0 ? c->K : 1)) == hipSuccess;
     ok &= hipMalloc(&c->err, sizeof(int64_t) * 2) == hipSuccess;
     ok &= hipMalloc(&c->part, sizeof(double) * kSumParts) == hipSuccess;
     c->bricks.nbricks = c->K / kBrickCells;
@@ -187,6 +189,7 @@ gic_status gic_destroy(gic_ctx *c)
     (void)hipFree(c->sort.vB);
     (void)hipFree(c->sort.hist);
     (void)hipFree(c->sort.sums);
+    (void)hipFree(c->sort.cnt);
     (void)hipFree(c->err);
     (void)hipFree(c->part);
     (void)hipFree(c->bricks.list);

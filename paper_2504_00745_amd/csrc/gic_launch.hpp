@@ -15,6 +15,7 @@ struct SortScratch {
     int32_t *vA, *vB;
     uint32_t *hist;     // RADIX x tiles
     uint32_t *sums;     // 1024 chunk totals of the digit-offset scan
+    uint32_t *cnt;      // [K] granules per cell; zero between sorts
     int64_t tiles_max;
     int passes;         // 8-bit digit passes over the key bits
 };

@@ -32,19 +32,32 @@ __global__ void __launch_bounds__(256) k_cell_keys(DevParams P, int64_t n, const
     key[i] = key_of_cell(P, c[0], c[1], c[2]);
 }
 
-// Per-tile histogram of one 8-bit digit: hist[d * tiles + tile].
+// Per-tile histogram of one 8-bit digit: hist[d * tiles + tile].  Keys are
+// usually close to sorted (the state was sorted by the previous step), so
+// neighbouring lanes mostly share a digit: the first lane of each run of
+// equal digits in a wave adds the run's length, one LDS atomic per run.
 __global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint32_t *__restrict__ keys, int64_t n,
                                                              int shift, uint32_t *__restrict__ hist, int64_t tiles)
 {
     __shared__ uint32_t h[kRadix];
     const int tid = threadIdx.x;
+    const int lane = tid & 63;
     h[tid] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
 #pragma unroll
     for (int it = 0; it < kSortItems; ++it) {
-        int64_t p = base + (int64_t)it * kSortThreads + tid;
-        if (p < n) atomicAdd(&h[(keys[p] >> shift) & (kRadix - 1)], 1u);
+        const int64_t p = base + (int64_t)it * kSortThreads + tid;
+        const bool valid = p < n;
+        const uint32_t d = valid ? (keys[p] >> shift) & (kRadix - 1) : 0u;
+        const uint32_t prev = __shfl_up(d, 1);
+        const bool start = valid && (lane == 0 || prev != d);
+        const uint64_t starts = __ballot(start) | (~__ballot(valid));  // invalid lanes end the last run
+        if (start) {
+            const uint64_t above = lane == 63 ? 0ull : (starts >> (lane + 1)) << (lane + 1);
+            const int next = above ? __ffsll((unsigned long long)above) - 1 : 64;
+            atomicAdd(&h[d], (uint32_t)(next - lane));
+        }
     }
     __syncthreads();
     hist[(int64_t)tid * tiles + blockIdx.x] = h[tid];
@@ -189,12 +202,6 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint32_t *
     }
 }
 
-__global__ void __launch_bounds__(256) k_fill_i32(int32_t *a, int64_t len, int32_t v)
-{
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x)
-        a[i] = v;
-}
-
 // Number of granules per cell key, from the sorted keys: the first lane of
 // each run of equal keys inside a wave adds the run's length.
 __global__ void __launch_bounds__(256) k_cell_count(const uint32_t *__restrict__ sk, int64_t n,
@@ -214,9 +221,10 @@ __global__ void __launch_bounds__(256) k_cell_count(const uint32_t *__restrict__
 }
 
 // Last phase of the scan of the per-cell counts: begin = exclusive prefix,
-// end = inclusive prefix (end overwrites the counts in place).
-__global__ void __launch_bounds__(kScanThreads) k_scan_down_ranges(uint32_t *__restrict__ cnt_end,
-                                                                   uint32_t *__restrict__ begin, int64_t len,
+// end = inclusive prefix; the counts are reset to zero for the next sort.
+__global__ void __launch_bounds__(kScanThreads) k_scan_down_ranges(uint32_t *__restrict__ cnt,
+                                                                   uint32_t *__restrict__ begin,
+                                                                   uint32_t *__restrict__ end, int64_t len,
                                                                    int64_t chunk, const uint32_t *__restrict__ sums)
 {
     __shared__ uint32_t lds[kScanThreads / 64];
@@ -225,12 +233,13 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_down_ranges(uint32_t *__r
     uint32_t carry = sums[blockIdx.x];
     for (int64_t base = lo; base < hi; base += kScanThreads) {
         const int64_t k = base + threadIdx.x;
-        const uint32_t v = k < hi ? cnt_end[k] : 0u;
+        const uint32_t v = k < hi ? cnt[k] : 0u;
         uint32_t total;
         const uint32_t inc = block_scan_inclusive(v, lds, &total);
         if (k < hi) {
             begin[k] = carry + inc - v;
-            cnt_end[k] = carry + inc;
+            end[k] = carry + inc;
+            cnt[k] = 0u;
         }
         carry += total;
     }
@@ -317,12 +326,7 @@ hipError_t launch_sort_cells(const DevParams &P, int64_t n, const double *x, uin
                              int32_t *cell_begin, int32_t *cell_end, int64_t K, SortScratch &S, int64_t *err,
                              hipStream_t s)
 {
-    uint32_t *cnt = reinterpret_cast<uint32_t *>(cell_end);
-    {
-        unsigned g = grid_for(K, 256);
-        if (g > 65536) g = 65536;
-        k_fill_i32<<<g, 256, 0, s>>>(cell_end, K, 0);
-    }
+    uint32_t *cnt = S.cnt;  // all zero between sorts
     if (n > 0) {
         k_cell_keys<<<grid_for(n, 256), 256, 0, s>>>(P, n, x, key, err);
         const int64_t tiles = (n + kSortTile - 1) / kSortTile;
@@ -350,7 +354,8 @@ hipError_t launch_sort_cells(const DevParams &P, int64_t n, const double *x, uin
     const int nb = (int)((K + chunk - 1) / chunk);
     k_scan_reduce<<<nb, kScanThreads, 0, s>>>(cnt, K, chunk, S.sums);
     k_scan_spine<<<1, kScanThreads, 0, s>>>(S.sums, nb);
-    k_scan_down_ranges<<<nb, kScanThreads, 0, s>>>(cnt, reinterpret_cast<uint32_t *>(cell_begin), K, chunk, S.sums);
+    k_scan_down_ranges<<<nb, kScanThreads, 0, s>>>(cnt, reinterpret_cast<uint32_t *>(cell_begin),
+                                                   reinterpret_cast<uint32_t *>(cell_end), K, chunk, S.sums);
     return hipGetLastError();
 }
 
