@@ -156,9 +156,12 @@ gic_status gic_reorder(gic_ctx *ctx, int64_t n, const int32_t *order, const doub
  * (dx*dx + dy*dy) + dz*dz.  Per pair: n = x_ij / d, delta = r_i + r_j - d,
  * v_n = v_ij . n, F_n = (k_n delta - gamma_n v_n) n, f_t = -k_t (v_ij - v_n
  * n), F_t = f_t capped to mu k_n delta along f_t.  Enabled box walls act as
- * infinite-mass partners with the same law.  Positions, overlaps and the
- * contact test are double in both forms; the pair force arithmetic and the
- * per-granule sum are in the form's real type.
+ * infinite-mass partners with the same law.  Positions, position
+ * differences, d^2 and the contact test are double in both forms; the
+ * overlap is R - d in double (plain form) or (R^2 - d^2) / (R + d) with the
+ * cancelling difference R^2 - d^2 in double and the quotient in float (FP32
+ * form); the pair force arithmetic and the per-granule sum are in the
+ * form's real type.
  *   x, v, r     sorted order (see Conventions).
  *   f_contact   out, 3n real: force per granule [N].
  *   n_contacts  out (optional, NULL = skip), n: touching partners + walls. */
