@@ -254,9 +254,8 @@ __global__ void __launch_bounds__(256) k_g2p_vjp_grid(DevParams P, int64_t n, co
     const int E = P.tile;
     const int E3 = E * E * E;
     for (int k = threadIdx.x; k < E3; k += 256) tile[k] = 0.0;
-    const int64_t bc[3] = {b % P.nb[0], (b / P.nb[0]) % P.nb[1], b / ((int64_t)P.nb[0] * P.nb[1])};
     int32_t o[3];
-    for (int a = 0; a < 3; ++a) o[a] = (int32_t)floor((double)(bc[a] * kBrick) * P.cell * P.inv_dx) - 1;
+    tile_origin(P, b, o);
     __syncthreads();
     for (int64_t q = beg + (int64_t)threadIdx.x; q < end; q += 256) {
         const double xa[3] = {x[q], x[n + q], x[2 * n + q]};

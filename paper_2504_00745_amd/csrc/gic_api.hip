@@ -53,9 +53,17 @@ bool params_valid(const gic_params *p)
 
 // Edge of the P2G LDS tile: the nodes touched by a brick's granules plus one
 // node of slack on each side.
+// Nodes per edge of a brick's node tile: the stencils of granules whose
+// cell lies in the brick span 4 cell / dx + 2 nodes when that is an integer
+// (the brick starts on a node boundary), one more otherwise.  Granules that
+// moved out of their cell since the sort reach outside the tile and take
+// the global path.
 int tile_edge(const gic_params *p)
 {
-    return (int)ceil((double)kBrick * p->cell / p->dx - 1e-9) + 3;
+    const double m4 = (double)kBrick * p->cell / p->dx;
+    const double r = floor(m4 + 0.5);
+    if (fabs(m4 - r) < 1e-9 * (r > 1.0 ? r : 1.0)) return (int)r + 2;
+    return (int)ceil(m4) + 3;
 }
 
 DevParams derive(const gic_params *p)

@@ -249,7 +249,9 @@ __device__ inline void integrate_one(const DevParams &P, double r, const T Fc[3]
 __device__ inline void tile_origin(const DevParams &P, int64_t b, int32_t o[3])
 {
     const int64_t bc[3] = {b % P.nb[0], (b / P.nb[0]) % P.nb[1], b / ((int64_t)P.nb[0] * P.nb[1])};
-    for (int a = 0; a < 3; ++a) o[a] = (int32_t)floor((double)(bc[a] * kBrick) * P.cell * P.inv_dx) - 1;
+    // the brick's lower face in node units; the tolerance keeps a face that
+    // lies on a node boundary from rounding to the node below
+    for (int a = 0; a < 3; ++a) o[a] = (int32_t)floor((double)(bc[a] * kBrick) * P.cell * P.inv_dx + 1e-7) - 1;
 }
 
 // Bit pattern of v + 1.5 * 2^52, i.e. rint(v) plus kRintBias, for |v| < 2^51.
