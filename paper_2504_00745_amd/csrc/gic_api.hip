@@ -153,7 +153,15 @@ gic_status gic_create(const gic_params *p, int64_t n_max, gic_ctx **out)
     bool ok = true;
     ok &= hipMalloc(&c->sort.kA, sizeof(uint32_t) * nn) == hipSuccess;
     ok &= hipMalloc(&c->sort.kB, sizeof(uint32_t) * nn) == hipSuccess;
-    ok &= hipMalloc(&c->sort.skeys, sizeof(uint32_t) * nn) == hipSuccess;
+    ok &= hipMalloc(&c->sort.skeys[0], sizeof(uint32_t) * nn) == hipSuccess;
+    ok &= hipMalloc(&c->sort.skeys[1], sizeof(uint32_t) * nn) == hipSuccess;
+    c->sort.cur = 0;
+    c->sort.last_n = -1;
+    ok &= hipMalloc(&c->sort.chg, sizeof(uint64_t) * kChgCap) == hipSuccess;
+    ok &= hipMalloc(&c->sort.chg_s, sizeof(uint64_t) * kChgCap) == hipSuccess;
+    ok &= hipMalloc(&c->sort.chg_p, sizeof(uint32_t) * kChgCap) == hipSuccess;
+    ok &= hipMalloc(&c->sort.ctl, sizeof(int32_t) * 2) == hipSuccess;
+    if (ok) ok = hipMemset(c->sort.ctl, 0, sizeof(int32_t) * 2) == hipSuccess;
     ok &= hipMalloc(&c->sort.vA, sizeof(int32_t) * nn) == hipSuccess;
     ok &= hipMalloc(&c->sort.vB, sizeof(int32_t) * nn) == hipSuccess;
     ok &= hipMalloc(&c->sort.hist, sizeof(uint32_t) * 256 * tiles) == hipSuccess;
@@ -192,7 +200,12 @@ gic_status gic_destroy(gic_ctx *c)
     hipError_t e = hipDeviceSynchronize();
     (void)hipFree(c->sort.kA);
     (void)hipFree(c->sort.kB);
-    (void)hipFree(c->sort.skeys);
+    (void)hipFree(c->sort.skeys[0]);
+    (void)hipFree(c->sort.skeys[1]);
+    (void)hipFree(c->sort.chg);
+    (void)hipFree(c->sort.chg_s);
+    (void)hipFree(c->sort.chg_p);
+    (void)hipFree(c->sort.ctl);
     (void)hipFree(c->sort.vA);
     (void)hipFree(c->sort.vB);
     (void)hipFree(c->sort.hist);

@@ -9,15 +9,26 @@
 
 namespace gic {
 
+// Granules whose key changed since the last sort that the incremental path
+// takes (more go through the radix passes).
+constexpr int kChgCap = 4096;
+
 // Sort scratch owned by a context.
 struct SortScratch {
-    uint32_t *kA, *kB, *skeys;
+    uint32_t *kA, *kB;
+    uint32_t *skeys[2];  // sorted keys; skeys[cur] holds those of the last sort
+    int cur;
+    int64_t last_n;      // granules of the last sort, -1 before the first
     int32_t *vA, *vB;
-    uint32_t *hist;     // RADIX x tiles
-    uint32_t *sums;     // 1024 chunk totals of the digit-offset scan
-    uint32_t *cnt;      // [K] granules per cell; zero between sorts
+    uint32_t *hist;      // RADIX x tiles
+    uint32_t *sums;      // 1024 chunk totals of the digit-offset scan
+    uint32_t *cnt;       // [K] granules per cell; zero between sorts
+    uint64_t *chg;       // [kChgCap] changed granules as (key << 32 | position), in arrival order
+    uint64_t *chg_s;     // [kChgCap] the same sorted
+    uint32_t *chg_p;     // [kChgCap] their positions sorted
+    int32_t *ctl;        // [2] changed count (zero between sorts), path of this sort (1 = incremental)
     int64_t tiles_max;
-    int passes;         // 8-bit digit passes over the key bits
+    int passes;          // 8-bit digit passes over the key bits
 };
 
 // Occupied bricks of a set of cell ranges, in brick order (see

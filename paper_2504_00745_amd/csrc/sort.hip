@@ -13,9 +13,14 @@ namespace {
 
 constexpr int kRadix = 256;
 
-// Key of every granule; flags non-finite and out-of-box positions.
+// Key of every granule; flags non-finite and out-of-box positions.  With
+// the previous sorted keys pk (same n), granules whose key differs from
+// pk at their position are appended to chg (up to kChgCap; ctl[0] counts
+// them all).
 __global__ void __launch_bounds__(256) k_cell_keys(DevParams P, int64_t n, const double *__restrict__ x,
-                                                   uint32_t *__restrict__ key, int64_t *err)
+                                                   uint32_t *__restrict__ key, int64_t *err,
+                                                   const uint32_t *__restrict__ pk, uint64_t *__restrict__ chg,
+                                                   int32_t *__restrict__ ctl)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -29,7 +34,12 @@ __global__ void __launch_bounds__(256) k_cell_keys(DevParams P, int64_t n, const
     }
     if (bad) raise_error(err, kErrNonFinite, i);
     else if (out) raise_error(err, kErrDomain, i);
-    key[i] = key_of_cell(P, c[0], c[1], c[2]);
+    const uint32_t k = key_of_cell(P, c[0], c[1], c[2]);
+    key[i] = k;
+    if (pk && pk[i] != k) {
+        const int32_t slot = atomicAdd(&ctl[0], 1);
+        if (slot < kChgCap) chg[slot] = ((uint64_t)k << 32) | (uint64_t)i;
+    }
 }
 
 // Per-tile histogram of one 8-bit digit: hist[d * tiles + tile].  Keys are
@@ -37,8 +47,10 @@ __global__ void __launch_bounds__(256) k_cell_keys(DevParams P, int64_t n, const
 // neighbouring lanes mostly share a digit: the first lane of each run of
 // equal digits in a wave adds the run's length, one LDS atomic per run.
 __global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint32_t *__restrict__ keys, int64_t n,
-                                                             int shift, uint32_t *__restrict__ hist, int64_t tiles)
+                                                             int shift, uint32_t *__restrict__ hist, int64_t tiles,
+                                                             const int32_t *__restrict__ skip)
 {
+    if (skip && skip[1]) return;  // the incremental path sorted this time
     __shared__ uint32_t h[kRadix];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -110,8 +122,10 @@ __device__ inline uint32_t block_scan_inclusive(uint32_t v, uint32_t *lds, uint3
 }
 
 __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const uint32_t *__restrict__ a, int64_t len,
-                                                              int64_t chunk, uint32_t *__restrict__ sums)
+                                                              int64_t chunk, uint32_t *__restrict__ sums,
+                                                              const int32_t *__restrict__ skip)
 {
+    if (skip && skip[1]) return;
     __shared__ uint32_t lds[kScanThreads / 64];
     const int64_t lo = (int64_t)blockIdx.x * chunk;
     const int64_t hi = lo + chunk < len ? lo + chunk : len;
@@ -121,8 +135,9 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const uint32_t *__
     if (threadIdx.x == 0) sums[blockIdx.x] = s;
 }
 
-__global__ void __launch_bounds__(kScanThreads) k_scan_spine(uint32_t *sums, int nb)
+__global__ void __launch_bounds__(kScanThreads) k_scan_spine(uint32_t *sums, int nb, const int32_t *__restrict__ skip)
 {
+    if (skip && skip[1]) return;
     __shared__ uint32_t lds[kScanThreads / 64];
     const uint32_t v = threadIdx.x < nb ? sums[threadIdx.x] : 0u;
     uint32_t total;
@@ -131,8 +146,10 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_spine(uint32_t *sums, int
 }
 
 __global__ void __launch_bounds__(kScanThreads) k_scan_down(uint32_t *__restrict__ a, int64_t len, int64_t chunk,
-                                                            const uint32_t *__restrict__ sums)
+                                                            const uint32_t *__restrict__ sums,
+                                                            const int32_t *__restrict__ skip)
 {
+    if (skip && skip[1]) return;
     __shared__ uint32_t lds[kScanThreads / 64];
     const int64_t lo = (int64_t)blockIdx.x * chunk;
     const int64_t hi = lo + chunk < len ? lo + chunk : len;
@@ -157,8 +174,10 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint32_t *
                                                                 const int32_t *__restrict__ vin,
                                                                 uint32_t *__restrict__ kout,
                                                                 int32_t *__restrict__ vout, int64_t n, int shift,
-                                                                const uint32_t *__restrict__ offs, int64_t tiles)
+                                                                const uint32_t *__restrict__ offs, int64_t tiles,
+                                                                const int32_t *__restrict__ skip)
 {
+    if (skip && skip[1]) return;
     __shared__ uint32_t base[kRadix];
     __shared__ uint32_t wcnt[kSortThreads / 64][kRadix];
     const int tid = threadIdx.x;
@@ -225,8 +244,10 @@ __global__ void __launch_bounds__(256) k_cell_count(const uint32_t *__restrict__
 __global__ void __launch_bounds__(kScanThreads) k_scan_down_ranges(uint32_t *__restrict__ cnt,
                                                                    uint32_t *__restrict__ begin,
                                                                    uint32_t *__restrict__ end, int64_t len,
-                                                                   int64_t chunk, const uint32_t *__restrict__ sums)
+                                                                   int64_t chunk, const uint32_t *__restrict__ sums,
+                                                                   int32_t *__restrict__ ctl)
 {
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctl[0] = 0;  // no changed granules counted for the next sort
     __shared__ uint32_t lds[kScanThreads / 64];
     const int64_t lo = (int64_t)blockIdx.x * chunk;
     const int64_t hi = lo + chunk < len ? lo + chunk : len;
@@ -260,6 +281,117 @@ __global__ void __launch_bounds__(256) k_reorder(int64_t n, const int32_t *__res
     }
     ro[q] = r[i];
     if (ido) ido[q] = id[i];
+}
+
+// ---- incremental path: few keys changed since the last sort -------------
+//
+// The previous sorted keys pk are non-decreasing by position, so the
+// granules whose key still equals pk at their position (U) are in sorted
+// order already, whatever state they come from; the others (C, at most
+// kChgCap) are sorted here.  The stable sort by (key, position) is then the
+// merge of U and C: an element's place is the number of U elements before
+// it plus the number of C elements before it.  For u in U at position i
+// that is (i - #C positions below i) + #C pairs below (key, i); for c in C
+// it is its rank in C plus #U pairs below (k_c, i_c) = L - #C positions
+// below L, with L the number of positions i with (pk[i], i) < (k_c, i_c).
+
+__device__ inline int lower_bound_u64(const uint64_t *a, int m, uint64_t v)
+{
+    int lo = 0, hi = m;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ inline int lower_bound_u32(const uint32_t *a, int m, uint32_t v)
+{
+    int lo = 0, hi = m;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// One workgroup: decides the path, sorts C by (key, position) and by
+// position (bitonic, in LDS), and places the C elements.
+__global__ void __launch_bounds__(1024) k_chg_sort(int64_t n, const uint32_t *__restrict__ pk,
+                                                   const uint64_t *__restrict__ chg, int32_t *__restrict__ ctl,
+                                                   uint64_t *__restrict__ chg_s, uint32_t *__restrict__ chg_p,
+                                                   uint32_t *__restrict__ skeys, int32_t *__restrict__ order)
+{
+    __shared__ uint64_t sk[kChgCap];
+    __shared__ uint32_t sp[kChgCap];
+    const int tid = threadIdx.x;
+    const int m = ctl[0];
+    const bool incremental = m <= kChgCap;
+    __syncthreads();  // every thread has read ctl[0] before thread 0 writes ctl[1]
+    if (tid == 0) ctl[1] = incremental ? 1 : 0;
+    if (!incremental || m == 0) return;
+    int N = 2;
+    while (N < m) N <<= 1;
+    for (int i = tid; i < N; i += 1024) {
+        const uint64_t e = i < m ? chg[i] : ~0ull;
+        sk[i] = e;
+        sp[i] = i < m ? (uint32_t)(e & 0xffffffffu) : 0xffffffffu;
+    }
+    __syncthreads();
+    for (int k = 2; k <= N; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < N; i += 1024) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const bool up = (i & k) == 0;
+                    const uint64_t a = sk[i], b = sk[l];
+                    if ((a > b) == up) {
+                        sk[i] = b;
+                        sk[l] = a;
+                    }
+                    const uint32_t c = sp[i], d = sp[l];
+                    if ((c > d) == up) {
+                        sp[i] = d;
+                        sp[l] = c;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    for (int r = tid; r < m; r += 1024) {
+        chg_s[r] = sk[r];
+        chg_p[r] = sp[r];
+        const uint32_t kc = (uint32_t)(sk[r] >> 32), ic = (uint32_t)(sk[r] & 0xffffffffu);
+        int64_t lo = 0, hi = n;  // L: positions i with (pk[i], i) < (kc, ic)
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            const uint32_t pm = pk[mid];
+            if (pm < kc || (pm == kc && mid < (int64_t)ic)) lo = mid + 1; else hi = mid;
+        }
+        const int64_t place = r + lo - lower_bound_u32(sp, m, (uint32_t)lo);
+        order[place] = (int32_t)ic;
+        skeys[place] = kc;
+    }
+}
+
+// Places the U elements (one thread per position).
+__global__ void __launch_bounds__(256) k_merge(int64_t n, const uint32_t *__restrict__ key,
+                                               const uint32_t *__restrict__ pk, const int32_t *__restrict__ ctl,
+                                               const uint64_t *__restrict__ chg_s, const uint32_t *__restrict__ chg_p,
+                                               uint32_t *__restrict__ skeys, int32_t *__restrict__ order)
+{
+    if (!ctl[1]) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t k = key[i];
+    if (k != pk[i]) return;  // an element of C, placed by k_chg_sort
+    const int m = ctl[0];
+    int64_t place = i;
+    if (m > 0)
+        place = i - lower_bound_u32(chg_p, m, (uint32_t)i) +
+                lower_bound_u64(chg_s, m, ((uint64_t)k << 32) | (uint64_t)i);
+    order[place] = (int32_t)i;
+    skeys[place] = k;
 }
 
 // ---- occupied bricks, in brick order (the schedule of the brick kernels) ----
@@ -327,35 +459,48 @@ hipError_t launch_sort_cells(const DevParams &P, int64_t n, const double *x, uin
                              hipStream_t s)
 {
     uint32_t *cnt = S.cnt;  // all zero between sorts
+    // previous sorted keys: usable when the last sort had the same n
+    const bool inc = n > 0 && S.last_n == n;
+    const uint32_t *pk = inc ? S.skeys[S.cur] : nullptr;
+    uint32_t *skeys = S.skeys[S.cur ^ 1];
+    const int32_t *skip = inc ? S.ctl : nullptr;
     if (n > 0) {
-        k_cell_keys<<<grid_for(n, 256), 256, 0, s>>>(P, n, x, key, err);
+        k_cell_keys<<<grid_for(n, 256), 256, 0, s>>>(P, n, x, key, err, pk, S.chg, S.ctl);
+        if (inc) {
+            k_chg_sort<<<1, 1024, 0, s>>>(n, pk, S.chg, S.ctl, S.chg_s, S.chg_p, skeys, order);
+            k_merge<<<grid_for(n, 256), 256, 0, s>>>(n, key, pk, S.ctl, S.chg_s, S.chg_p, skeys, order);
+        }
+        // radix passes (skipped on the device when the incremental path sorted)
         const int64_t tiles = (n + kSortTile - 1) / kSortTile;
         const uint32_t *kin = key;
         const int32_t *vin = nullptr;
         for (int pass = 0; pass < S.passes; ++pass) {
             const bool last = pass == S.passes - 1;
-            uint32_t *kout = last ? S.skeys : ((pass & 1) ? S.kB : S.kA);
+            uint32_t *kout = last ? skeys : ((pass & 1) ? S.kB : S.kA);
             int32_t *vout = last ? order : ((pass & 1) ? S.vB : S.vA);
             const int shift = 8 * pass;
-            k_radix_hist<<<(unsigned)tiles, kSortThreads, 0, s>>>(kin, n, shift, S.hist, tiles);
+            k_radix_hist<<<(unsigned)tiles, kSortThreads, 0, s>>>(kin, n, shift, S.hist, tiles, skip);
             const int64_t len = tiles * kRadix;
             const int64_t chunk = scan_chunk(len);
             const int nb = (int)((len + chunk - 1) / chunk);
-            k_scan_reduce<<<nb, kScanThreads, 0, s>>>(S.hist, len, chunk, S.sums);
-            k_scan_spine<<<1, kScanThreads, 0, s>>>(S.sums, nb);
-            k_scan_down<<<nb, kScanThreads, 0, s>>>(S.hist, len, chunk, S.sums);
-            k_radix_scatter<<<(unsigned)tiles, kSortThreads, 0, s>>>(kin, vin, kout, vout, n, shift, S.hist, tiles);
+            k_scan_reduce<<<nb, kScanThreads, 0, s>>>(S.hist, len, chunk, S.sums, skip);
+            k_scan_spine<<<1, kScanThreads, 0, s>>>(S.sums, nb, skip);
+            k_scan_down<<<nb, kScanThreads, 0, s>>>(S.hist, len, chunk, S.sums, skip);
+            k_radix_scatter<<<(unsigned)tiles, kSortThreads, 0, s>>>(kin, vin, kout, vout, n, shift, S.hist, tiles,
+                                                                     skip);
             kin = kout;
             vin = vout;
         }
-        k_cell_count<<<grid_for(n, 256), 256, 0, s>>>(S.skeys, n, cnt);
+        k_cell_count<<<grid_for(n, 256), 256, 0, s>>>(skeys, n, cnt);
     }
     const int64_t chunk = scan_chunk(K);
     const int nb = (int)((K + chunk - 1) / chunk);
-    k_scan_reduce<<<nb, kScanThreads, 0, s>>>(cnt, K, chunk, S.sums);
-    k_scan_spine<<<1, kScanThreads, 0, s>>>(S.sums, nb);
+    k_scan_reduce<<<nb, kScanThreads, 0, s>>>(cnt, K, chunk, S.sums, nullptr);
+    k_scan_spine<<<1, kScanThreads, 0, s>>>(S.sums, nb, nullptr);
     k_scan_down_ranges<<<nb, kScanThreads, 0, s>>>(cnt, reinterpret_cast<uint32_t *>(cell_begin),
-                                                   reinterpret_cast<uint32_t *>(cell_end), K, chunk, S.sums);
+                                                   reinterpret_cast<uint32_t *>(cell_end), K, chunk, S.sums, S.ctl);
+    S.cur ^= 1;  // this sort's keys are the previous keys of the next
+    S.last_n = n;
     return hipGetLastError();
 }
 
