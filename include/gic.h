@@ -65,8 +65,11 @@ typedef enum {
     GIC_E_ALLOC = 3,     /* device allocation failed in gic_create        */
     GIC_E_DOMAIN = 4,    /* latched: granule centre outside the box       */
     GIC_E_NONFINITE = 5, /* latched: non-finite position or velocity      */
-    GIC_E_RANGE = 6      /* latched: radius > r_max, or a fixed-point
-                            contribution of magnitude >= 2^51 units      */
+    GIC_E_RANGE = 6      /* latched: radius > r_max, a fixed-point
+                            contribution of magnitude >= 2^51 units, or
+                            cell ranges / sorted order that do not match
+                            the positions (ranges and order indices are
+                            clipped to [0, n) before any access)         */
 } gic_status;
 
 typedef enum { GIC_FP64 = 0, GIC_FP32 = 1 } gic_precision;

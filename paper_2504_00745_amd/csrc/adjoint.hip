@@ -127,7 +127,8 @@ __global__ void __launch_bounds__(256) k_contact_vjp(DevParams P, int64_t n, con
                 const int32_t brick_end = (cx & ~(kBrick - 1)) + (kBrick - 1);
                 const int32_t cend = hi[0] < brick_end ? hi[0] : brick_end;
                 const uint32_t k0 = key_of_cell(P, cx, cy, cz);
-                const int32_t jb = cb[k0], je = ce[k0 + (uint32_t)(cend - cx)];
+                int32_t jb = cb[k0], je = ce[k0 + (uint32_t)(cend - cx)];
+                clip_range(n, jb, je);
                 for (int32_t j = jb; j < je; ++j) {
                     double d2;
                     if (!touching_adj(xi[0] - x[j], xi[1] - x[n + j], xi[2] - x[2 * n + j], ri + r[j], d2) ||
@@ -249,7 +250,8 @@ __global__ void __launch_bounds__(256) k_g2p_vjp_grid(DevParams P, int64_t n, co
     extern __shared__ double tile[];
     const int64_t b = brick_of_block(bl, bcnt);
     if (b < 0) return;
-    const int32_t beg = cb[b * kBrickCells], end = ce[b * kBrickCells + kBrickCells - 1];
+    int32_t beg = cb[b * kBrickCells], end = ce[b * kBrickCells + kBrickCells - 1];
+    clip_range(n, beg, end);
     if (end <= beg) return;
     const int E = P.tile;
     const int E3 = E * E * E;
@@ -362,6 +364,7 @@ __global__ void __launch_bounds__(256) k_permute(int64_t n, int comps, const int
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n) return;
     const int64_t i = order[q];
+    if ((uint64_t)i >= (uint64_t)n) return;  // not a permutation of [0, n): left untouched
     for (int c = 0; c < comps; ++c) {
         if (scatter)
             out[c * n + i] = in[c * n + q];

@@ -40,7 +40,7 @@ __device__ inline bool touching(double dx0, double dx1, double dx2, double R, do
 // consecutive keys (a run ends at a brick face), and consecutive keys have
 // contiguous granule ranges, so each run is one range [begin, end).
 template <typename F>
-__device__ inline void for_each_run(const DevParams &P, const int32_t lo[3], const int32_t hi[3],
+__device__ inline void for_each_run(const DevParams &P, int64_t n, const int32_t lo[3], const int32_t hi[3],
                                     const int32_t *__restrict__ cb, const int32_t *__restrict__ ce, F &&f)
 {
     for (int32_t cz = lo[2]; cz <= hi[2]; ++cz)
@@ -50,7 +50,9 @@ __device__ inline void for_each_run(const DevParams &P, const int32_t lo[3], con
                 const int32_t brick_end = (cx & ~(kBrick - 1)) + (kBrick - 1);
                 const int32_t cend = hi[0] < brick_end ? hi[0] : brick_end;
                 const uint32_t k0 = key_of_cell(P, cx, cy, cz);
-                f(cb[k0], ce[k0 + (uint32_t)(cend - cx)]);
+                int32_t jb = cb[k0], je = ce[k0 + (uint32_t)(cend - cx)];
+                clip_range(n, jb, je);
+                f(jb, je);
                 cx = cend + 1;
             }
         }
@@ -158,7 +160,7 @@ __device__ inline void contact_global(const DevParams &P, int64_t n, const doubl
     for (int a = 0; a < 3; ++a) search_range(P, xi[a], Rs, P.nc[a], lo[a], hi[a]);
     T acc[3] = {(T)0, (T)0, (T)0};
     int32_t cnt = 0;
-    for_each_run(P, lo, hi, cb, ce, [&](int32_t jb, int32_t je) {
+    for_each_run(P, n, lo, hi, cb, ce, [&](int32_t jb, int32_t je) {
         for (int32_t j0 = jb; j0 < je; j0 += kUnroll) {
             double cx[kUnroll], cy[kUnroll], cz[kUnroll], cr[kUnroll];
 #pragma unroll
@@ -273,7 +275,8 @@ __global__ void __launch_bounds__(256) k_contact_lds(DevParams P, int64_t n, con
     const int32_t bc[3] = {(int32_t)(b % P.nb[0]), (int32_t)((b / P.nb[0]) % P.nb[1]),
                            (int32_t)(b / ((int64_t)P.nb[0] * P.nb[1]))};
     const int32_t c0[3] = {bc[0] * kBrick - 1, bc[1] * kBrick - 1, bc[2] * kBrick - 1};  // shell origin cell
-    const int32_t gb = cb[b * kBrickCells], ge = ce[b * kBrickCells + kBrickCells - 1];
+    int32_t gb = cb[b * kBrickCells], ge = ce[b * kBrickCells + kBrickCells - 1];
+    clip_range(n, gb, ge);
     if (ge <= gb) return;
     const double o[3] = {c0[0] * P.cell, c0[1] * P.cell, c0[2] * P.cell};  // shell corner
     // ---- shell cells: counts, then slots (count + 1 pad each) by a scan
@@ -283,8 +286,10 @@ __global__ void __launch_bounds__(256) k_contact_lds(DevParams P, int64_t n, con
         const int32_t cx = c0[0] + hx, cy = c0[1] + hy, cz = c0[2] + hz;
         if (cx >= 0 && cy >= 0 && cz >= 0 && cx < P.nc[0] && cy < P.nc[1] && cz < P.nc[2]) {
             const uint32_t k = key_of_cell(P, cx, cy, cz);
+            int32_t e = ce[k];
             gbeg = cb[k];
-            num = ce[k] - gbeg;
+            clip_range(n, gbeg, e);
+            num = e - gbeg;
         }
     }
     const int32_t slots = tid < kHaloCells ? num + 1 : 0;
@@ -348,6 +353,15 @@ __global__ void __launch_bounds__(256) k_contact_lds(DevParams P, int64_t n, con
             search_range(P, xi[a], Rs, P.nc[a], lo[a], hi[a]);
             lo[a] -= c0[a];
             hi[a] -= c0[a];
+        }
+        if (ca[0] < 1 || ca[0] > 4 || ca[1] < 1 || ca[1] > 4 || ca[2] < 1 || ca[2] > 4) {
+            // the cell ranges do not match the positions (not the ranges of this state's sort)
+            raise_error(err, kErrRange, q);
+            F[q] = (T)0;
+            F[n + q] = (T)0;
+            F[2 * n + q] = (T)0;
+            if (ncont) ncont[q] = 0;
+            continue;
         }
         // slot of q itself, skipped by the candidate pass (the exact test skips q too)
         const int own = (ca[2] * 6 + ca[1]) * 6 + ca[0];
@@ -425,7 +439,7 @@ __global__ void __launch_bounds__(256) k_contact_pairs(DevParams P, int64_t n, c
     const double Rs = (ri + P.r_max) * P.search_scale;
     int32_t lo[3], hi[3];
     for (int a = 0; a < 3; ++a) search_range(P, xi[a], Rs, P.nc[a], lo[a], hi[a]);
-    for_each_run(P, lo, hi, cb, ce, [&](int32_t jb, int32_t je) {
+    for_each_run(P, n, lo, hi, cb, ce, [&](int32_t jb, int32_t je) {
         for (int32_t j = jb; j < je; ++j) {
             if (j <= q) continue;
             double d2;

@@ -60,6 +60,16 @@ __device__ inline int64_t brick_of_block(const int32_t *__restrict__ list, const
     return j < per && l < nocc ? list[l] : -1;
 }
 
+// A range [b, e) of sorted positions read from caller-given cell ranges,
+// clipped to [0, n]: ranges that do not match the positions give wrong
+// results (and, where detected, a latched error) but never an access
+// outside the arrays.
+__device__ inline void clip_range(int64_t n, int32_t &b, int32_t &e)
+{
+    b = b < 0 ? 0 : (b > n ? (int32_t)n : b);
+    e = e < b ? b : (e > n ? (int32_t)n : e);
+}
+
 // Latched error codes (same values as gic_status).
 constexpr int kErrDomain = 4;
 constexpr int kErrNonFinite = 5;

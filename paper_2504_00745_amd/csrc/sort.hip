@@ -275,6 +275,7 @@ __global__ void __launch_bounds__(256) k_reorder(int64_t n, const int32_t *__res
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n) return;
     int64_t i = order[q];
+    if ((uint64_t)i >= (uint64_t)n) return;  // not a permutation of [0, n): position q left untouched
     for (int a = 0; a < 3; ++a) {
         xo[a * n + q] = x[a * n + i];
         vo[a * n + q] = v[a * n + i];

@@ -26,7 +26,8 @@ __global__ void __launch_bounds__(256) k_gather_g2p_drag(DevParams P, int64_t n,
     extern __shared__ double smem_d[];
     const int64_t b = brick_of_block(bl, bcnt);
     if (b < 0) return;
-    const int32_t gb = cb[b * kBrickCells], ge = ce[b * kBrickCells + kBrickCells - 1];
+    int32_t gb = cb[b * kBrickCells], ge = ce[b * kBrickCells + kBrickCells - 1];
+    clip_range(n, gb, ge);
     if (ge <= gb) return;
     const int E = P.tile, E3 = E * E * E;
     T *su = reinterpret_cast<T *>(smem_d);  // [4][E3]: u_x, u_y, u_z, clamped alpha
@@ -45,6 +46,7 @@ __global__ void __launch_bounds__(256) k_gather_g2p_drag(DevParams P, int64_t n,
     __syncthreads();
     for (int64_t q = gb + threadIdx.x; q < ge; q += 256) {
         const int64_t s = order[q];
+        if ((uint64_t)s >= (uint64_t)n) continue;  // not a permutation of [0, n): position q left untouched
         const double xa[3] = {x[s], x[n + s], x[2 * n + s]};
         const double va[3] = {v[s], v[n + s], v[2 * n + s]};
         const double rq = r[s];

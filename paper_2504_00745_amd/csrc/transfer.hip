@@ -35,13 +35,15 @@ __global__ void __launch_bounds__(256) k_fill_f64(double *a, int64_t len)
 }
 
 // [begin, end) of brick b in sorted order, from the 64 cell ranges of the
-// brick; returned through LDS to the whole workgroup.
-__device__ inline void brick_range(int64_t b, const int32_t *__restrict__ cb, const int32_t *__restrict__ ce,
-                                   int32_t *s_range)
+// brick (each clipped to [0, n)); returned through LDS to the whole
+// workgroup.
+__device__ inline void brick_range(int64_t n, int64_t b, const int32_t *__restrict__ cb,
+                                   const int32_t *__restrict__ ce, int32_t *s_range)
 {
     if (threadIdx.x < 64) {
         const int64_t key = b * kBrickCells + threadIdx.x;
-        const int32_t bb = cb[key], ee = ce[key];
+        int32_t bb = cb[key], ee = ce[key];
+        clip_range(n, bb, ee);
         int32_t lo = ee > bb ? bb : 0x7fffffff;
         int32_t hi = ee > bb ? ee : 0;
         for (int off = 32; off > 0; off >>= 1) {
@@ -102,7 +104,7 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g_fixed(DevParams P, int64_t 
     __shared__ int32_t s_wave[kP2GThreads / 64];
     const int64_t b = brick_of_block(bl, bcnt);
     if (b < 0) return;
-    brick_range(b, cb, ce, s_range);
+    brick_range(n, b, cb, ce, s_range);
     __syncthreads();
     const int32_t beg = s_range[0], end = s_range[1];
     if (end <= beg) return;
@@ -285,7 +287,7 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g_real(DevParams P, int64_t n
     __shared__ int32_t s_range[2];
     const int64_t b = brick_of_block(bl, bcnt);
     if (b < 0) return;
-    brick_range(b, cb, ce, s_range);
+    brick_range(n, b, cb, ce, s_range);
     __syncthreads();
     const int32_t beg = s_range[0], end = s_range[1];
     if (end <= beg) return;
