@@ -61,16 +61,35 @@ __device__ inline void for_each_run(const DevParams &P, int64_t n, const int32_t
 constexpr int kUnroll = 4;
 constexpr int kMaxPartners = 12;  // partners listed per granule before forces are evaluated
 
-// Force that partner j exerts on granule q (both in sorted positions): the
-// overlap, its normal and the relative velocity come from double positions
-// and velocities; the pair law of Eq. (1a)-(1c) runs in T.
-template <typename T>
-__device__ inline void add_pair(const DevParams &P, int64_t n, const double *__restrict__ x,
-                                const double *__restrict__ v, const double *__restrict__ r, const double xi[3],
-                                const double vi[3], double ri, double mi, int32_t j, T acc[3])
+// Double state of a partner granule, loaded in one go so that its loads
+// overlap.
+struct Partner {
+    double x[3], v[3], r;
+};
+
+__device__ inline Partner fetch_partner(int64_t n, const double *__restrict__ x, const double *__restrict__ v,
+                                        const double *__restrict__ r, int32_t j)
 {
-    const double d0 = xi[0] - x[j], d1 = xi[1] - x[n + j], d2c = xi[2] - x[2 * n + j];
-    const double rj = r[j];
+    Partner p;
+    p.x[0] = x[j];
+    p.x[1] = x[n + j];
+    p.x[2] = x[2 * n + j];
+    p.r = r[j];
+    p.v[0] = v[j];
+    p.v[1] = v[n + j];
+    p.v[2] = v[2 * n + j];
+    return p;
+}
+
+// Force that partner p exerts on granule i: the overlap, its normal and the
+// relative velocity come from double positions and velocities; the pair law
+// of Eq. (1a)-(1c) runs in T.
+template <typename T>
+__device__ inline void pair_from(const DevParams &P, const double xi[3], const double vi[3], double ri, double mi,
+                                 const Partner &p, T acc[3])
+{
+    const double d0 = xi[0] - p.x[0], d1 = xi[1] - p.x[1], d2c = xi[2] - p.x[2];
+    const double rj = p.r;
     double d2;
     {
 #pragma clang fp contract(off)
@@ -101,7 +120,7 @@ __device__ inline void add_pair(const DevParams &P, int64_t n, const double *__r
         nh[2] = d2c * inv_d;
         delta = R - d;
     }
-    const T w[3] = {(T)(vi[0] - v[j]), (T)(vi[1] - v[n + j]), (T)(vi[2] - v[2 * n + j])};
+    const T w[3] = {(T)(vi[0] - p.v[0]), (T)(vi[1] - p.v[1]), (T)(vi[2] - p.v[2])};
     const T mj = (T)mass_of(P, rj);
     const T mit = (T)mi;
     const T meff = law_div(mit * mj, mit + mj);
@@ -110,6 +129,15 @@ __device__ inline void add_pair(const DevParams &P, int64_t n, const double *__r
     acc[0] += Fp[0];
     acc[1] += Fp[1];
     acc[2] += Fp[2];
+}
+
+// Force that partner j exerts on granule q (both in sorted positions).
+template <typename T>
+__device__ inline void add_pair(const DevParams &P, int64_t n, const double *__restrict__ x,
+                                const double *__restrict__ v, const double *__restrict__ r, const double xi[3],
+                                const double vi[3], double ri, double mi, int32_t j, T acc[3])
+{
+    pair_from<T>(P, xi, vi, ri, mi, fetch_partner(n, x, v, r, j), acc);
 }
 
 // Wall forces of Eq. (1a)-(1c) with the box faces as infinite-mass partners.
@@ -211,45 +239,56 @@ __global__ void __launch_bounds__(256) k_contact(DevParams P, int64_t n, int64_t
 // ---------------------------------------------------------------------------
 // LDS-staged contact: one workgroup per brick of 4x4x4 cells.  The 6x6x6
 // cells around the brick (the brick and a one-cell shell) are copied once
-// into LDS, cell after cell in (z, y, x) order with one empty slot (NaN,
-// never a candidate) after each cell: when cells hold equal numbers of
-// granules the empty slot puts lanes that read different cells at the same
-// step on different LDS banks.  Consecutive cells of a row stay one
+// into LDS, cell after cell in (z, y, x) order, kPad empty slots (never a
+// candidate) after each cell; consecutive cells of a row stay one
 // contiguous range of slots.
 //
-// A slot holds the granule's position relative to the shell's corner and
-// its radius in single precision (16 bytes, one LDS read per candidate).
-// The candidate pass tests d^2 < (r_i + r_j + m)^2 on these with a margin m
-// well above their rounding error, so it keeps every pair the exact test
-// keeps; the force pass then runs the exact double test of Sec. 3.1 on the
-// listed partners (from global memory, as the force needs their double
-// state anyway) and evaluates Eq. (1) for those that touch.
+// A slot holds, in single precision, the granule's position p relative to
+// the brick's centre and Q = |p|^2 - 2 r^2 (16 bytes, one LDS read per
+// candidate).  For granule i at a (relative) with b_i = |a|^2 - 2 r_i^2,
+//     b_i + Q_j - 2 a.p_j = |x_i - x_j|^2 - 2 r_i^2 - 2 r_j^2
+//                        <= |x_i - x_j|^2 - (r_i + r_j)^2
+// because 2 r_i r_j <= r_i^2 + r_j^2 (equality for equal radii), so the
+// candidate pass keeps j when Q_j - 2 a.p_j < M - b_i: three FMAs and a
+// compare per candidate, and every touching pair passes as long as the
+// single-precision evaluation errs by less than M.  The force pass then
+// runs the exact double test of Sec. 3.1 on the listed partners (from
+// global memory, as the force needs their double state anyway) and
+// evaluates Eq. (1) for those that touch.
 //
-// Margin: relative coordinates lie within 6 cells of the corner, so each is
-// rounded by at most 6 cell 2^-24; a difference of two adds its own rounding
-// (at most 2^-24 of it), the squared distance a few ulps and each radius
-// 2^-24 of itself.  Altogether the single-precision distance is within
-// 2^-18 cell of the exact one; the margin is 2^-16 cell.  (For positions
-// outside the box, which the key kernel reports as a domain error, the
-// bound does not hold and the step's result is unspecified.)
+// Margin: relative coordinates lie within 3 cells of the centre per axis
+// (the own granule's within 2) and radii are at most half a cell, so Q is
+// below 27 cell^2, b_i below 12 cell^2 and every partial sum of the FMA
+// chain below 63 cell^2; the roundings of Q, b_i, M - b_i and the chain
+// (12 of at most 2^-24 of those bounds) sum to less than 2^-15.5 cell^2,
+// and rounding the positions and radii to float moves the exact value by
+// less than 2^-16.7 cell^2.  M = 2^-12 cell^2, eight times the total.  (For
+// positions outside the box, which the key kernel reports as a domain
+// error, the bound does not hold and the step's result is unspecified.)
 //
 // A brick whose shell does not fit in LDS takes the global path.
 constexpr int kHaloCells = 216;
 constexpr int kLdsPartners = 10;
 constexpr int kCand = 4;  // candidates read from LDS before they are tested
+constexpr int kPad = 1;   // empty slots after each cell
 
-// Exact contact test of Sec. 3.1 against partner j and, if the two touch,
-// the pair force added to acc.  Returns 1 for a contact.
+// Candidate test of the LDS pass (see above): p = (p, Q) of a slot,
+// m = -2 a, thr = M - b_i.
+__device__ inline bool near_slot(float4 p, float mx, float my, float mz, float thr)
+{
+    return fmaf(mx, p.x, fmaf(my, p.y, fmaf(mz, p.z, p.w))) < thr;
+}
+
+// Exact contact test of Sec. 3.1 against partner j (state p) and, if the
+// two touch, the pair force added to acc.  Returns 1 for a contact.
 template <typename T>
-__device__ inline int exact_pair(const DevParams &P, int64_t n, const double *__restrict__ x,
-                                 const double *__restrict__ v, const double *__restrict__ r, const double xi[3],
-                                 const double vi[3], double ri, double mi, int64_t q, int32_t j, T acc[3])
+__device__ inline int exact_pair(const DevParams &P, const double xi[3], const double vi[3], double ri, double mi,
+                                 int64_t q, int32_t j, const Partner &p, T acc[3])
 {
     if (j == q) return 0;
-    const double d0 = xi[0] - x[j], d1 = xi[1] - x[n + j], d2c = xi[2] - x[2 * n + j];
     double d2;
-    if (!touching(d0, d1, d2c, ri + r[j], d2) || d2 == 0.0) return 0;
-    add_pair<T>(P, n, x, v, r, xi, vi, ri, mi, j, acc);
+    if (!touching(xi[0] - p.x[0], xi[1] - p.x[1], xi[2] - p.x[2], ri + p.r, d2) || d2 == 0.0) return 0;
+    pair_from<T>(P, xi, vi, ri, mi, p, acc);
     return 1;
 }
 
@@ -262,8 +301,8 @@ __global__ void __launch_bounds__(256) k_contact_lds(DevParams P, int64_t n, con
                                                      int32_t *__restrict__ ncont, int64_t *err)
 {
     extern __shared__ float4 smem4[];
-    float4 *spos = smem4;                                                  // [cap] (x, y, z, r) relative
-    uint16_t *plist = reinterpret_cast<uint16_t *>(spos + cap);           // [kLdsPartners][256] partner slots
+    float4 *spos = smem4;                                        // [cap + kCand] (p, Q), see above
+    uint16_t *plist = reinterpret_cast<uint16_t *>(spos + cap + kCand);  // [kLdsPartners][256] partner slots
     int32_t *clo = reinterpret_cast<int32_t *>(plist + kLdsPartners * 256);  // [216] first slot of each cell
     int32_t *cnum = clo + kHaloCells;                                      // [216] granules of each shell cell
     int32_t *cgb = cnum + kHaloCells;                                      // [216] global begin of each shell cell
@@ -278,8 +317,8 @@ __global__ void __launch_bounds__(256) k_contact_lds(DevParams P, int64_t n, con
     int32_t gb = cb[b * kBrickCells], ge = ce[b * kBrickCells + kBrickCells - 1];
     clip_range(n, gb, ge);
     if (ge <= gb) return;
-    const double o[3] = {c0[0] * P.cell, c0[1] * P.cell, c0[2] * P.cell};  // shell corner
-    // ---- shell cells: counts, then slots (count + 1 pad each) by a scan
+    const double o[3] = {(c0[0] + 3) * P.cell, (c0[1] + 3) * P.cell, (c0[2] + 3) * P.cell};  // brick centre
+    // ---- shell cells: counts, then slots (count + kPad each) by a scan
     int32_t num = 0, gbeg = 0;
     if (tid < kHaloCells) {
         const int hx = tid % 6, hy = (tid / 6) % 6, hz = tid / 36;
@@ -292,7 +331,7 @@ __global__ void __launch_bounds__(256) k_contact_lds(DevParams P, int64_t n, con
             num = e - gbeg;
         }
     }
-    const int32_t slots = tid < kHaloCells ? num + 1 : 0;
+    const int32_t slots = tid < kHaloCells ? num + kPad : 0;
     int32_t first = 0;
     {
         const int lane = tid & 63, wave = tid >> 6;
@@ -319,110 +358,147 @@ __global__ void __launch_bounds__(256) k_contact_lds(DevParams P, int64_t n, con
         for (int64_t q = gb + tid; q < ge; q += 256) contact_global<T>(P, n, x, v, r, cb, ce, q, glist, tid, F, ncont, err);
         return;
     }
-    // ---- slot -> shell cell map (the NaN pad takes its cell's number too)
+    // ---- slot -> shell cell map (pads take their cell's number too)
     if (tid < kHaloCells)
         for (int32_t k = first; k < first + slots; ++k) scell[k] = (uint8_t)tid;
     __syncthreads();
-    // ---- copy the shell's granules, relative to the corner, in single precision
+    // ---- copy the shell's granules, relative to the centre, in single precision
     for (int k = tid; k < H; k += 256) {
         const int c = scell[k];
         const int off = k - clo[c];
         float4 p;
         if (off < cnum[c]) {
             const int64_t g = cgb[c] + off;
-            p = make_float4((float)(x[g] - o[0]), (float)(x[n + g] - o[1]), (float)(x[2 * n + g] - o[2]), (float)r[g]);
+            const float px = (float)(x[g] - o[0]), py = (float)(x[n + g] - o[1]), pz = (float)(x[2 * n + g] - o[2]);
+            const float rg = (float)r[g];
+            p = make_float4(px, py, pz, ((px * px + py * py) + pz * pz) - 2.0f * (rg * rg));
         } else {
             const float nan = __builtin_nanf("");
-            p = make_float4(nan, nan, nan, 0.0f);
+            p = make_float4(nan, nan, nan, nan);
         }
         spos[k] = p;
     }
     __syncthreads();
-    const float margin = (float)(P.cell * (1.0 / 65536.0));
-    // ---- granules of the brick
-    for (int64_t q = gb + tid; q < ge; q += 256) {
-        const double xi[3] = {x[q], x[n + q], x[2 * n + q]};
-        const double ri = r[q];
-        if (ri > P.r_max) raise_error(err, kErrRange, q);
-        const float xf = (float)(xi[0] - o[0]), yf = (float)(xi[1] - o[1]), zf = (float)(xi[2] - o[2]);
-        const float rim = (float)ri + margin;
-        const double Rs = (ri + P.r_max) * P.search_scale;
-        int32_t lo[3], hi[3], ca[3];
-        for (int a = 0; a < 3; ++a) {
-            ca[a] = cell_coord(xi[a], P.inv_cell, P.nc[a]) - c0[a];  // in [1, 4]: q lies in the brick
-            search_range(P, xi[a], Rs, P.nc[a], lo[a], hi[a]);
-            lo[a] -= c0[a];
-            hi[a] -= c0[a];
-        }
-        if (ca[0] < 1 || ca[0] > 4 || ca[1] < 1 || ca[1] > 4 || ca[2] < 1 || ca[2] > 4) {
-            // the cell ranges do not match the positions (not the ranges of this state's sort)
-            raise_error(err, kErrRange, q);
-            F[q] = (T)0;
-            F[n + q] = (T)0;
-            F[2 * n + q] = (T)0;
-            if (ncont) ncont[q] = 0;
-            continue;
-        }
-        // slot of q itself, skipped by the candidate pass (the exact test skips q too)
-        const int own = (ca[2] * 6 + ca[1]) * 6 + ca[0];
-        const int32_t qoff = (int32_t)(q - cgb[own]);
-        const int32_t kself = qoff >= 0 && qoff < cnum[own] ? clo[own] + qoff : -1;
-        int32_t cnt = 0;
-        for (int hz = lo[2]; hz <= hi[2]; ++hz)
-            for (int hy = lo[1]; hy <= hi[1]; ++hy) {
-                const int c = (hz * 6 + hy) * 6;
-                // cells lo..hi of this row: one contiguous run of slots
-                const int k0 = clo[c + lo[0]];
-                const int k1 = clo[c + hi[0]] + cnum[c + hi[0]];
-                for (int k = k0; k < k1; k += kCand) {
-                    float4 p[kCand];
-#pragma unroll
-                    for (int u = 0; u < kCand; ++u) p[u] = spos[k + u < k1 ? k + u : k1 - 1];
-#pragma unroll
-                    for (int u = 0; u < kCand; ++u) {
-                        const float ex = xf - p[u].x, ey = yf - p[u].y, ez = zf - p[u].z;
-                        const float R = rim + p[u].w;
-                        const float d2 = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
-                        if (k + u < k1 && k + u != kself && d2 < R * R) {
-                            if (cnt < kLdsPartners) plist[cnt * 256 + tid] = (uint16_t)(k + u);
-                            ++cnt;
-                        }
-                    }
-                }
-            }
-        const double vi[3] = {v[q], v[n + q], v[2 * n + q]};
-        const double mi = mass_of(P, ri);
+    const float M = (float)(P.cell * P.cell * (1.0 / 4096.0));
+    // ---- granules of the brick, 2^lg adjacent lanes per granule when the
+    // brick holds few (otherwise most waves of the workgroup would idle):
+    // lane `sub` of a granule takes rows sub, sub + L, ... of the search box,
+    // lists and evaluates its own partners, and the lanes' partial sums are
+    // added at the end ((s0 + s1) + (s2 + s3), the same in every lane).
+    const int32_t nq = ge - gb;
+    const int lg = nq <= 64 ? 2 : (nq <= 128 ? 1 : 0);
+    const int L = 1 << lg;
+    const int sub = tid & (L - 1);
+    for (int64_t qb = gb; qb < ge; qb += (256 >> lg)) {  // same trip count in every lane
+        const int64_t q = qb + (tid >> lg);
+        const bool live = q < ge;
         T acc[3] = {(T)0, (T)0, (T)0};
         int32_t nc = 0;
-        const int listed = cnt < kLdsPartners ? cnt : kLdsPartners;
-        for (int i = 0; i < listed; ++i) {
-            const int k = plist[i * 256 + tid];
-            const int c = scell[k];
-            nc += exact_pair<T>(P, n, x, v, r, xi, vi, ri, mi, q, cgb[c] + (k - clo[c]), acc);
-        }
-        if (cnt > kLdsPartners) {
-            // more candidates than listed: walk them again for the rest
-            int32_t seen = 0;
-            for (int hz = lo[2]; hz <= hi[2]; ++hz)
-                for (int hy = lo[1]; hy <= hi[1]; ++hy) {
-                    const int c = (hz * 6 + hy) * 6;
-                    const int k1 = clo[c + hi[0]] + cnum[c + hi[0]];
-                    for (int k = clo[c + lo[0]]; k < k1; ++k) {
-                        const float4 p = spos[k];
-                        const float ex = xf - p.x, ey = yf - p.y, ez = zf - p.z;
-                        const float R = rim + p.w;
-                        if (k == kself || !(fmaf(ex, ex, fmaf(ey, ey, ez * ez)) < R * R)) continue;
-                        if (seen++ < kLdsPartners) continue;
-                        const int cc = scell[k];
-                        nc += exact_pair<T>(P, n, x, v, r, xi, vi, ri, mi, q, cgb[cc] + (k - clo[cc]), acc);
+        bool bad = false;
+        double xi[3] = {0.0, 0.0, 0.0}, vi[3] = {0.0, 0.0, 0.0}, ri = 0.0, mi = 0.0;
+        if (live) {
+            xi[0] = x[q];
+            xi[1] = x[n + q];
+            xi[2] = x[2 * n + q];
+            ri = r[q];
+            if (ri > P.r_max) raise_error(err, kErrRange, q);
+            const float ax = (float)(xi[0] - o[0]), ay = (float)(xi[1] - o[1]), az = (float)(xi[2] - o[2]);
+            const float rf = (float)ri;
+            const float thr = M - (((ax * ax + ay * ay) + az * az) - 2.0f * (rf * rf));
+            const float mx = -2.0f * ax, my = -2.0f * ay, mz = -2.0f * az;
+            const double Rs = (ri + P.r_max) * P.search_scale;
+            int32_t lo[3], hi[3], ca[3];
+            for (int a = 0; a < 3; ++a) {
+                ca[a] = cell_coord(xi[a], P.inv_cell, P.nc[a]) - c0[a];  // in [1, 4]: q lies in the brick
+                search_range(P, xi[a], Rs, P.nc[a], lo[a], hi[a]);
+                lo[a] -= c0[a];
+                hi[a] -= c0[a];
+            }
+            // the cell ranges do not match the positions (not the ranges of this state's sort)
+            bad = ca[0] < 1 || ca[0] > 4 || ca[1] < 1 || ca[1] > 4 || ca[2] < 1 || ca[2] > 4;
+            if (bad) {
+                raise_error(err, kErrRange, q);
+            } else {
+                // slot of q itself, skipped by the candidate pass (the exact test skips q too)
+                const int own = (ca[2] * 6 + ca[1]) * 6 + ca[0];
+                const int32_t qoff = (int32_t)(q - cgb[own]);
+                const int32_t kself = qoff >= 0 && qoff < cnum[own] ? clo[own] + qoff : -1;
+                // this lane's rows (hz, hy) of the search box, f(first cell of the row)
+                auto for_rows = [&](auto &&f) {
+                    const int ny = hi[1] - lo[1] + 1, nz = hi[2] - lo[2] + 1;
+                    if (ny <= 0 || nz <= 0) return;  // empty box (a NaN or negative radius): no rows
+                    const int nrow = nz * ny;
+                    int hz = lo[2], hy = lo[1] + sub;
+                    while (hy > hi[1]) { hy -= ny; ++hz; }
+                    for (int row = sub; row < nrow; row += L) {
+                        f((hz * 6 + hy) * 6);
+                        hy += L;
+                        while (hy > hi[1]) { hy -= ny; ++hz; }
                     }
+                };
+                int32_t cnt = 0;
+                for_rows([&](int c) {
+                    // cells lo..hi of this row: one contiguous run of slots
+                    const int k0 = clo[c + lo[0]];
+                    const int k1 = clo[c + hi[0]] + cnum[c + hi[0]];
+                    for (int k = k0; k < k1; k += kCand) {
+                        // slots up to k1 + kCand - 2 < cap + kCand are read; those past k1 are ignored
+                        float4 p[kCand];
+#pragma unroll
+                        for (int u = 0; u < kCand; ++u) p[u] = spos[k + u];
+#pragma unroll
+                        for (int u = 0; u < kCand; ++u) {
+                            if (k + u < k1 && k + u != kself && near_slot(p[u], mx, my, mz, thr)) {
+                                if (cnt < kLdsPartners) plist[cnt * 256 + tid] = (uint16_t)(k + u);
+                                ++cnt;
+                            }
+                        }
+                    }
+                });
+                vi[0] = v[q];
+                vi[1] = v[n + q];
+                vi[2] = v[2 * n + q];
+                mi = mass_of(P, ri);
+                const int listed = cnt < kLdsPartners ? cnt : kLdsPartners;
+                auto global_of = [&](int k) { const int c = scell[k]; return cgb[c] + (k - clo[c]); };
+                for (int i = 0; i < listed; i += 2) {
+                    // two partners per round, their loads in flight together
+                    const bool two = i + 1 < listed;
+                    const int32_t j0 = global_of(plist[i * 256 + tid]);
+                    const int32_t j1 = two ? global_of(plist[(i + 1) * 256 + tid]) : j0;
+                    const Partner p0 = fetch_partner(n, x, v, r, j0);
+                    const Partner p1 = fetch_partner(n, x, v, r, j1);
+                    nc += exact_pair<T>(P, xi, vi, ri, mi, q, j0, p0, acc);
+                    if (two) nc += exact_pair<T>(P, xi, vi, ri, mi, q, j1, p1, acc);
                 }
+                if (cnt > kLdsPartners) {
+                    // more candidates than listed: walk this lane's rows again for the rest
+                    int32_t seen = 0;
+                    for_rows([&](int c) {
+                        const int k1 = clo[c + hi[0]] + cnum[c + hi[0]];
+                        for (int k = clo[c + lo[0]]; k < k1; ++k) {
+                            if (k == kself || !near_slot(spos[k], mx, my, mz, thr)) continue;
+                            if (seen++ < kLdsPartners) continue;
+                            const int32_t j = global_of(k);
+                            nc += exact_pair<T>(P, xi, vi, ri, mi, q, j, fetch_partner(n, x, v, r, j), acc);
+                        }
+                    });
+                }
+            }
         }
-        add_walls<T>(P, xi, vi, ri, mi, acc, nc);
-        F[q] = acc[0];
-        F[n + q] = acc[1];
-        F[2 * n + q] = acc[2];
-        if (ncont) ncont[q] = nc;
+        for (int m = 1; m < L; m <<= 1) {  // all lanes take part; groups of L lanes share q
+            acc[0] += __shfl_xor(acc[0], m);
+            acc[1] += __shfl_xor(acc[1], m);
+            acc[2] += __shfl_xor(acc[2], m);
+            nc += __shfl_xor(nc, m);
+        }
+        if (live && sub == 0) {
+            if (!bad) add_walls<T>(P, xi, vi, ri, mi, acc, nc);
+            F[q] = acc[0];
+            F[n + q] = acc[1];
+            F[2 * n + q] = acc[2];
+            if (ncont) ncont[q] = nc;
+        }
     }
 }
 
@@ -460,7 +536,7 @@ __global__ void k_zero_count(unsigned long long *c) { *c = 0ull; }
 // LDS bytes of the staged contact kernel for a shell capacity of cap granules.
 static size_t contact_lds_bytes(int cap)
 {
-    size_t b = (size_t)cap * (sizeof(float4) + 1) + sizeof(uint16_t) * kLdsPartners * 256 +
+    size_t b = (size_t)(cap + kCand) * sizeof(float4) + (size_t)cap + sizeof(uint16_t) * kLdsPartners * 256 +
                sizeof(int32_t) * (kHaloCells * 3 + 4);
     const size_t fallback = sizeof(int32_t) * kMaxPartners * 256;  // list of the global path, aliasing the slots
     return b > fallback ? b : fallback;
@@ -473,7 +549,7 @@ hipError_t launch_contact(const DevParams &P, int64_t n, const double *x, const 
 {
     if (n == 0) return hipSuccess;
     const int64_t nbricks = (int64_t)P.nb[0] * P.nb[1] * P.nb[2];
-    const int cap = 1952;  // shell slots held in LDS: 40,912 bytes, four workgroups per CU
+    const int cap = 1948;  // shell slots held in LDS: 40,908 bytes, four workgroups per CU
     k_contact_lds<T><<<brick_grid(nbricks), 256, contact_lds_bytes(cap), s>>>(P, n, B.list, B.count, cap, x, v, r, cb,
                                                                             ce, F, ncont, err);
     return hipGetLastError();
