@@ -136,7 +136,7 @@ gic_status gic_create(const gic_params *p, int64_t n_max, gic_ctx **out)
     *out = nullptr;
     const int E = tile_edge(p);
     if ((size_t)E * E * E * 4 * sizeof(double) > 65536) return GIC_E_ARG;  // P2G tile must fit in LDS
-    gic_ctx *c = new gic_ctx;
+    gic_ctx *c = new gic_ctx();  // value-initialised: every pointer starts null
     memset(c, 0, sizeof(*c));
     c->p = *p;
     c->dp = derive(p);
