@@ -75,8 +75,8 @@ typedef enum {
 typedef enum { GIC_FP64 = 0, GIC_FP32 = 1 } gic_precision;
 
 /* Parameters of the granule step.
- *   n[3], dx      grid nodes per axis and spacing [m]; nodes at cell centres
- *                 (Sec. 5.1: fractions "computed at the grid cell centers").
+ *   n[3], dx      grid nodes per axis (1 .. 32767) and spacing [m]; nodes at cell centres
+ *                 (Sec. 5.1: the solid fractions live at the cell centres).
  *   nc[3], cell   neighbour-search cells per axis and their edge [m];
  *                 cell >= 2 r_max and nc[a] cell <= n[a] dx; the last cell
  *                 of an axis extends to the box face.

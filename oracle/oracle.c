@@ -16,11 +16,11 @@
  *                            drag M_s = a_s rho_s (v_f - v_s) / tau_s)
  *   sub-step loop .......... Alg. 2 (SandSubstep): coupling force, collision,
  *                            move
- *   integrator ............. Sec. 4 ("similar to the symplectic Euler method")
+ *   integrator ............. Sec. 4 (semi-implicit, symplectic Euler type)
  *   volume fraction P2G .... Sec. 5.1, Eq. (7a), at cell centres
  *   alpha_s limit 0.740 .... Sec. 5.1 (densest sphere packing, 3D)
- *   fluid velocity G2P ..... Sec. 5.2 ("interpolating the fluid velocity at the
- *                            position x_s from the grid")
+ *   fluid velocity G2P ..... Sec. 5.2 (grid fluid velocity interpolated to
+ *                            each granule's position)
  *
  * Readings where the paper is silent (all recorded in the design notes):
  *   - normal dashpot from a restitution coefficient (Eq. 1a has none);

@@ -271,6 +271,7 @@ constexpr int kHaloCells = 216;
 constexpr int kLdsPartners = 10;
 constexpr int kCand = 4;  // candidates read from LDS before they are tested
 constexpr int kPad = 1;   // empty slots after each cell
+constexpr int kCopyRounds = 8;  // shell copy rounds of 256 slots: covers every cap <= 2047
 
 // Candidate test of the LDS pass (see above): p = (p, Q) of a slot,
 // m = -2 a, thr = M - b_i.
@@ -362,21 +363,45 @@ __global__ void __launch_bounds__(256) k_contact_lds(DevParams P, int64_t n, con
     if (tid < kHaloCells)
         for (int32_t k = first; k < first + slots; ++k) scell[k] = (uint8_t)tid;
     __syncthreads();
-    // ---- copy the shell's granules, relative to the centre, in single precision
-    for (int k = tid; k < H; k += 256) {
-        const int c = scell[k];
-        const int off = k - clo[c];
-        float4 p;
-        if (off < cnum[c]) {
-            const int64_t g = cgb[c] + off;
-            const float px = (float)(x[g] - o[0]), py = (float)(x[n + g] - o[1]), pz = (float)(x[2 * n + g] - o[2]);
-            const float rg = (float)r[g];
-            p = make_float4(px, py, pz, ((px * px + py * py) + pz * pz) - 2.0f * (rg * rg));
-        } else {
-            const float nan = __builtin_nanf("");
-            p = make_float4(nan, nan, nan, nan);
+    // ---- copy the shell's granules, relative to the centre, in single precision.
+    // H <= cap < kCopyRounds * 256: all loads of a thread are issued before
+    // any of them is used, so they are in flight together.
+    {
+        double gx[kCopyRounds], gy[kCopyRounds], gz[kCopyRounds], gr[kCopyRounds];
+        bool real[kCopyRounds];
+#pragma unroll
+        for (int it = 0; it < kCopyRounds; ++it) {
+            const int k = tid + it * 256;
+            real[it] = false;
+            gx[it] = gy[it] = gz[it] = gr[it] = 0.0;
+            if (k < H) {
+                const int c = scell[k];
+                const int off = k - clo[c];
+                if (off < cnum[c]) {
+                    const int64_t g = cgb[c] + off;
+                    gx[it] = x[g];
+                    gy[it] = x[n + g];
+                    gz[it] = x[2 * n + g];
+                    gr[it] = r[g];
+                    real[it] = true;
+                }
+            }
         }
-        spos[k] = p;
+#pragma unroll
+        for (int it = 0; it < kCopyRounds; ++it) {
+            const int k = tid + it * 256;
+            if (k >= H) continue;
+            float4 p;
+            if (real[it]) {
+                const float px = (float)(gx[it] - o[0]), py = (float)(gy[it] - o[1]), pz = (float)(gz[it] - o[2]);
+                const float rg = (float)gr[it];
+                p = make_float4(px, py, pz, ((px * px + py * py) + pz * pz) - 2.0f * (rg * rg));
+            } else {
+                const float nan = __builtin_nanf("");
+                p = make_float4(nan, nan, nan, nan);
+            }
+            spos[k] = p;
+        }
     }
     __syncthreads();
     const float M = (float)(P.cell * P.cell * (1.0 / 4096.0));

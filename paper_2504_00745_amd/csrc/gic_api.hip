@@ -34,7 +34,7 @@ bool params_valid(const gic_params *p)
 {
     if (!p) return false;
     for (int a = 0; a < 3; ++a) {
-        if (p->n[a] < 1 || p->nc[a] < 1) return false;
+        if (p->n[a] < 1 || p->nc[a] < 1 || p->n[a] > 32767) return false;  // stencil bases are 16-bit in LDS
         if ((double)p->nc[a] * p->cell > (double)p->n[a] * p->dx * (1.0 + 1e-12)) return false;
     }
     if (!(p->dx > 0.0) || !(p->cell > 0.0) || !isfinite(p->dx) || !isfinite(p->cell)) return false;

@@ -88,7 +88,7 @@ __device__ inline void tile_add(unsigned long long *tile, unsigned long long *gl
 // the granule is deposited at its new position; each granule is read and
 // written by one thread only.
 template <bool MOM, typename T, bool INTEG>
-__global__ void __launch_bounds__(kP2GThreads) k_p2g_fixed(DevParams P, int64_t n, const int32_t *__restrict__ bl,
+__global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_eu(4))) k_p2g_fixed(DevParams P, int64_t n, const int32_t *__restrict__ bl,
                                                            const int32_t *__restrict__ bcnt, int batch,
                                                            double *x, double *v, const double *__restrict__ r,
                                                            const T *__restrict__ Fc, const T *__restrict__ Fd,
@@ -113,8 +113,8 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g_fixed(DevParams P, int64_t 
     const int bs = batch + 1;  // padded stride: the arrays start on different LDS banks
     double *sf = reinterpret_cast<double *>(tile + NCH * E3);   // [3][bs] weight offsets f
     double *sS = sf + 3 * bs;                                    // [NCH][bs] scaled totals
-    int32_t *sbase = reinterpret_cast<int32_t *>(sS + NCH * bs);  // [3][bs] stencil base
-    int32_t *srun = sbase + 3 * bs;                              // [bs] run starts
+    int32_t *srun = reinterpret_cast<int32_t *>(sS + NCH * bs);   // [bs] run starts
+    int16_t *sbase = reinterpret_cast<int16_t *>(srun + bs);      // [3][bs] stencil base (grid edges < 2^15 nodes)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int k = tid; k < NCH * E3; k += kP2GThreads) tile[k] = 0ull;
     int32_t o[3];
@@ -144,7 +144,7 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g_fixed(DevParams P, int64_t 
                 sf[a * bs + i] = (t - fb) - 0.5;
                 if (!(fb >= -2.0)) fb = -2.0;
                 if (fb > (double)P.n[a]) fb = (double)P.n[a];
-                sbase[a * bs + i] = (int32_t)fb;
+                sbase[a * bs + i] = (int16_t)fb;
             }
             const double frac = volume_of(r[q]) * P.inv_vcell;
             double S[NCH];
@@ -387,7 +387,7 @@ hipError_t launch_fill_f64(double *a, int64_t len, hipStream_t s)
 // LDS bytes of the fixed-point P2G: node tile plus per-granule batch data.
 static size_t p2g_lds(int nch, int E3, int batch)
 {
-    return sizeof(unsigned long long) * (size_t)nch * E3 + (size_t)(batch + 1) * (3 * 8 + nch * 8 + 3 * 4 + 4);
+    return sizeof(unsigned long long) * (size_t)nch * E3 + (size_t)(batch + 1) * (3 * 8 + nch * 8 + 4 + 3 * 2);
 }
 
 template <typename T, bool INTEG>
