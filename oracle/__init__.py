@@ -41,6 +41,25 @@ def params(cfg: dict) -> OrcParams:
     return p
 
 
+class OrcCoupling(C.Structure):
+    _fields_ = [
+        ("rho_f", C.c_double), ("c_quad", C.c_double), ("f_unit", C.c_double),
+        ("drag_model", C.c_int32), ("vmass", C.c_int32),
+    ]
+
+
+def coupling(cfg: dict) -> OrcCoupling:
+    """Oracle parameters of the remaining interphase forces from a workload
+    parameter dict (absent keys: linear drag only, no virtual mass)."""
+    c = OrcCoupling()
+    c.rho_f = float(cfg.get("rho_f", 0.0))
+    c.c_quad = float(cfg.get("c_quad", 0.0))
+    c.f_unit = float(cfg.get("f_unit", 1.0))
+    c.drag_model = int(cfg.get("drag_model", 0))
+    c.vmass = int(cfg.get("vmass", 0))
+    return c
+
+
 def lib():
     global _LIB
     if _LIB is None:
@@ -58,6 +77,7 @@ _i64 = _P(C.c_int64)
 _i32 = _P(C.c_int32)
 _u32 = _P(C.c_uint32)
 _pp = _P(OrcParams)
+_pc = _P(OrcCoupling)
 
 
 def _declare(L):
@@ -84,6 +104,12 @@ def _declare(L):
         "orc_p2g_vjp": (None, [_pp, C.c_int64, _d, _d, _d, _d, _d, _d, _d]),
         "orc_rollout": (C.c_double, [_pp, C.c_int64, _d, _d, _d, _d, C.c_int32, _d, _P(C.c_uint64)]),
         "orc_rollout_vjp": (C.c_double, [_pp, C.c_int64, _d, _d, _d, _d, C.c_int32, _d, _d, _d]),
+        "orc_fluid_forces": (None, [_pp, _pc, C.c_int64, _d, _d, _d, _d, _i64, _d, _d, _d]),
+        "orc_integrate_vm": (None, [_pp, _pc, C.c_int64, _d, _d, _d, _d, _d]),
+        "orc_exchange_force": (None, [_pp, _pc, C.c_int64, _d, _d, _d, _d]),
+        "orc_exchange_p2g": (None, [_pp, _pc, C.c_int64, _d, _d, _d, _d, C.c_double, _i64]),
+        "orc_substeps": (C.c_int32, [C.c_double, C.c_double]),
+        "orc_sand_step": (C.c_int32, [_pp, _pc, C.c_int64, C.c_double, _d, _d, _d, _d, _d, _d, _i64, _i64, _i64]),
         "orc_num_threads": (C.c_int, []),
         "orc_set_num_threads": (None, [C.c_int]),
     }
@@ -311,6 +337,84 @@ def step(cfg, x, v, r, u, alpha_fx):
                    _ptr(u, C.c_double), _ptr(alpha, C.c_int64), _ptr(mom, C.c_int64), _ptr(Fc, C.c_double),
                    _ptr(Fd, C.c_double), _ptr(uat, C.c_double), _ptr(af, C.c_double))
     return dict(x=x, v=v, alpha=alpha, mom=mom, Fc=Fc, Fd=Fd, u_at=uat, alpha_f=af)
+
+
+# ---- remaining interphase forces (Sec. 3.3 Eq. 5a-5c, Sec. 5.2 Eq. 9) and the
+# ---- full sand step with the exchange momentum (Alg. 2, Sec. 5.2) -----------
+
+def fluid_forces(cfg, x, v, r, u, alpha_fx, gp=None, af=None):
+    """Fluid force on each granule (3,n): drag (cfg drag_model: 0 linear Stokes
+    form x alpha_f, 1 quadratic Eq. 5b) + pressure gradient -V grad p (if gp)
+    + (1/2) rho_f V dv_f/dt (if vmass and af); gp, af are (3,G) grid fields."""
+    x, v, r, u = _f64(x), _f64(v), _f64(r), _f64(u)
+    n = x.shape[1]
+    Ffl = np.zeros((3, n))
+    afx = np.ascontiguousarray(alpha_fx, np.int64)
+    gp = None if gp is None else _f64(gp)
+    af = None if af is None else _f64(af)
+    p, c = params(cfg), coupling(cfg)
+    lib().orc_fluid_forces(C.byref(p), C.byref(c), n, _ptr(x, C.c_double), _ptr(v, C.c_double),
+                           _ptr(r, C.c_double), _ptr(u, C.c_double), _ptr(afx, C.c_int64), _ptr(gp, C.c_double),
+                           _ptr(af, C.c_double), _ptr(Ffl, C.c_double))
+    return Ffl
+
+
+def integrate_vm(cfg, r, Fc, Ffl, x, v):
+    """Semi-implicit Euler with the effective mass m + (1/2) rho_f V of Eq. 9
+    (plain integrate when cfg vmass is 0).  Returns new (x, v)."""
+    r, Fc, Ffl = _f64(r), _f64(Fc), _f64(Ffl)
+    x = _f64(x).copy()
+    v = _f64(v).copy()
+    p, c = params(cfg), coupling(cfg)
+    lib().orc_integrate_vm(C.byref(p), C.byref(c), r.shape[0], _ptr(r, C.c_double), _ptr(Fc, C.c_double),
+                           _ptr(Ffl, C.c_double), _ptr(x, C.c_double), _ptr(v, C.c_double))
+    return x, v
+
+
+def exchange_force(cfg, r, Fc, Ffl):
+    """Whole fluid force of a sub-step on each granule (3,n)."""
+    r, Fc, Ffl = _f64(r), _f64(Fc), _f64(Ffl)
+    fex = np.zeros_like(Ffl)
+    p, c = params(cfg), coupling(cfg)
+    lib().orc_exchange_force(C.byref(p), C.byref(c), r.shape[0], _ptr(r, C.c_double), _ptr(Fc, C.c_double),
+                             _ptr(Ffl, C.c_double), _ptr(fex, C.c_double))
+    return fex
+
+
+def exchange_p2g(cfg, x, r, Fc, Ffl, weight, fs=None):
+    """Exchange deposit of one sub-step: fs (3,G) int64 in 2^-32 f_unit units
+    accumulates -weight * f_j N(x_j - x)."""
+    x, r, Fc, Ffl = _f64(x), _f64(r), _f64(Fc), _f64(Ffl)
+    G = nodes(cfg)
+    fs = np.zeros((3, G), np.int64) if fs is None else np.ascontiguousarray(fs, np.int64).copy()
+    p, c = params(cfg), coupling(cfg)
+    lib().orc_exchange_p2g(C.byref(p), C.byref(c), x.shape[1], _ptr(x, C.c_double), _ptr(r, C.c_double),
+                           _ptr(Fc, C.c_double), _ptr(Ffl, C.c_double), float(weight), _ptr(fs, C.c_int64))
+    return fs
+
+
+def substeps(Dt, dt_max):
+    return int(lib().orc_substeps(float(Dt), float(dt_max)))
+
+
+def sand_step(cfg, Dt, x, v, r, u, alpha_fx, gp=None, af=None):
+    """One sand step (Alg. 2) of length Dt in ceil(Dt / cfg dt) sub-steps.
+    Returns dict(x, v, alpha, mom, fs, N)."""
+    x = _f64(x).copy()
+    v = _f64(v).copy()
+    r, u = _f64(r), _f64(u)
+    gp = None if gp is None else _f64(gp)
+    af = None if af is None else _f64(af)
+    G = nodes(cfg)
+    alpha = np.ascontiguousarray(alpha_fx, np.int64).copy()
+    mom = np.zeros((3, G), np.int64)
+    fs = np.zeros((3, G), np.int64)
+    p, c = params(cfg), coupling(cfg)
+    N = lib().orc_sand_step(C.byref(p), C.byref(c), x.shape[1], float(Dt), _ptr(x, C.c_double),
+                            _ptr(v, C.c_double), _ptr(r, C.c_double), _ptr(u, C.c_double), _ptr(gp, C.c_double),
+                            _ptr(af, C.c_double), _ptr(alpha, C.c_int64), _ptr(mom, C.c_int64),
+                            _ptr(fs, C.c_int64))
+    return dict(x=x, v=v, alpha=alpha, mom=mom, fs=fs, N=int(N))
 
 
 # ---- differentiable form (unquantised transfers) and its reverse pass -------

@@ -1083,3 +1083,233 @@ double orc_rollout_vjp(const orc_params *p, int64_t n, const double *x0, const d
     free(gx); free(gv); free(gF); free(guat); free(gaf); free(galpha);
     return L;
 }
+
+/* ======================================================================== */
+/* Remaining interphase forces and the full sand step                        */
+/* ======================================================================== */
+/*
+ * Passages followed:
+ *   pressure-gradient force . Sec. 3.3 Eq. (5a), F_p = -(4/3) pi r^3 grad p,
+ *                             grad p interpolated from the grid (Sec. 5.2)
+ *   quadratic drag .......... Sec. 3.3 Eq. (5b), F_d = 12 pi r^2 rho_f C |u - v| (u - v)
+ *   virtual mass ............ Sec. 3.3 Eq. (5c) and Sec. 5.2 Eq. (9):
+ *                             (m + (2/3) pi r^3 rho_0) dv/dt = (2/3) pi r^3 rho_0 dv_f/dt + F_o,
+ *                             dv_f/dt interpolated from the grid (Eq. 10-12: the grid's
+ *                             velocity increment)
+ *   exchange momentum ....... Sec. 5.2: F_s(x) = -(dt'/dt) sum_i sum_j f_j^i N(x_j^i - x)
+ *   sub-step cycle .......... Alg. 1 and 2: N = ceil(dt / dt') sub-steps, fluid fields frozen
+ *
+ * Readings (recorded in the design notes):
+ *   - rho_f of Eq. (5b) and rho_0 of Eq. (9) are the same fluid density;
+ *   - the factor written mu in Eq. (5b) is a dimensionless coefficient C
+ *     (the product must be a force); the quadratic drag is used as printed,
+ *     without the fluid-fraction factor of the linear form;
+ *   - the virtual-mass force is F_v = (1/2) rho_f V (a_f - a_s) with
+ *     V = (4/3) pi r^3; moving its a_s part to the left of Eq. (9) gives the
+ *     effective mass m + (1/2) rho_f V, and gravity acts on m;
+ *   - f_j^i of the exchange is the whole fluid force on granule j in
+ *     sub-step i: drag + pressure gradient + virtual mass, with a_s the
+ *     sub-step's acceleration (F_c + F_fluid + m g) / (m + (1/2) rho_f V);
+ *   - a sand step of length dt is cut into N = ceil(dt / dt'_max) equal
+ *     sub-steps of dt / N, so each exchange weight dt'/dt is 1/N;
+ *   - the exchange grid is int64 fixed point in units of 2^-32 f_unit,
+ *     deposited like Eq. (7a): rint(w S) on the 26 outer nodes, the centre
+ *     node takes rint(S) minus their sum.
+ */
+
+typedef struct {
+    double rho_f;       /* fluid density rho_f = rho_0 [kg/m^3]                 */
+    double c_quad;      /* dimensionless coefficient of the quadratic drag      */
+    double f_unit;      /* exchange-force unit [N]                              */
+    int32_t drag_model; /* 0: linear Stokes form x alpha_f; 1: quadratic (5b)   */
+    int32_t vmass;      /* 1: virtual mass in the equation of motion (Eq. 9)    */
+} orc_coupling;
+
+#define ORC_C12PI (12.0 * ORC_PI)
+
+/* G2P of a 3-vector grid field (3G) to the granules (3n): sum_k w_k f_k. */
+static void orc_g2p_vec(const orc_params *p, int64_t n, const double *x, const double *f, double *out)
+{
+    double inv_dx = 1.0 / p->dx;
+    int64_t G = orc_nodes(p);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double xa[3];
+        orc_pos(n, x, i, xa);
+        orc_stencil s;
+        orc_stencil_of(p, inv_dx, xa, &s);
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int c = 0; c < 3; ++c)
+            for (int b = 0; b < 3; ++b)
+                for (int a = 0; a < 3; ++a) {
+                    double w = (s.w[0][a] * s.w[1][b]) * s.w[2][c];
+                    int64_t k = orc_node_index(p, &s, a, b, c);
+                    for (int d = 0; d < 3; ++d) acc[d] += w * f[d * G + k];
+                }
+        for (int d = 0; d < 3; ++d) out[d * n + i] = acc[d];
+    }
+}
+
+/* Fluid force on each granule (3n): drag (linear or quadratic) + pressure
+ * gradient (if gp) + the explicit virtual-mass term (1/2) rho_f V a_f (if
+ * vmass and af).  u, gp, af are 3G grid fields; alpha_fx the fixed-point
+ * solid fraction grid (P2G at x). */
+void orc_fluid_forces(const orc_params *p, const orc_coupling *cp, int64_t n, const double *x, const double *v,
+                      const double *r, const double *u, const int64_t *alpha_fx, const double *gp,
+                      const double *af, double *Ffl)
+{
+    double *uat = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    double *alf = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *gpa = gp ? (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1)) : NULL;
+    double *afa = (af && cp->vmass) ? (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1)) : NULL;
+    orc_g2p(p, n, x, u, alpha_fx, NULL, uat, alf);
+    if (gpa) orc_g2p_vec(p, n, x, gp, gpa);
+    if (afa) orc_g2p_vec(p, n, x, af, afa);
+    if (cp->drag_model == 0) {
+        orc_drag(p, n, r, v, uat, alf, Ffl);
+    } else {
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            double w[3];
+            for (int d = 0; d < 3; ++d) w[d] = uat[d * n + i] - v[d * n + i];
+            double sp = sqrt((w[0] * w[0] + w[1] * w[1]) + w[2] * w[2]);
+            double coef = (((ORC_C12PI * r[i]) * r[i]) * cp->rho_f) * cp->c_quad;
+            for (int d = 0; d < 3; ++d) Ffl[d * n + i] = (coef * sp) * w[d];
+        }
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double V = orc_volume(r[i]);
+        double hv = (0.5 * cp->rho_f) * V;
+        for (int d = 0; d < 3; ++d) {
+            double f = Ffl[d * n + i];
+            if (gpa) f = f - V * gpa[d * n + i];
+            if (afa) f = f + hv * afa[d * n + i];
+            Ffl[d * n + i] = f;
+        }
+    }
+    free(uat);
+    free(alf);
+    free(gpa);
+    free(afa);
+}
+
+/* Semi-implicit Euler with the virtual mass of Eq. (9):
+ * v += dt ((Fc + Ffl) + m g) / (m + (1/2) rho_f V); x += dt v.
+ * Without virtual mass this is orc_integrate. */
+void orc_integrate_vm(const orc_params *p, const orc_coupling *cp, int64_t n, const double *r, const double *Fc,
+                      const double *Ffl, double *x, double *v)
+{
+    if (!cp->vmass) {
+        orc_integrate(p, n, r, Fc, Ffl, x, v);
+        return;
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double m = orc_mass(p, r[i]);
+        double me = m + (0.5 * cp->rho_f) * orc_volume(r[i]);
+        for (int d = 0; d < 3; ++d) {
+            double a = ((Fc[d * n + i] + Ffl[d * n + i]) + m * p->g[d]) / me;
+            v[d * n + i] = v[d * n + i] + p->dt * a;
+            x[d * n + i] = x[d * n + i] + p->dt * v[d * n + i];
+        }
+    }
+}
+
+/* Whole fluid force of the sub-step on each granule (the f_j^i of the
+ * exchange): Ffl minus (1/2) rho_f V a_s under virtual mass, where
+ * a_s = ((Fc + Ffl) + m g) / (m + (1/2) rho_f V); Ffl otherwise. */
+void orc_exchange_force(const orc_params *p, const orc_coupling *cp, int64_t n, const double *r, const double *Fc,
+                        const double *Ffl, double *fex)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double m = orc_mass(p, r[i]);
+        double hv = (0.5 * cp->rho_f) * orc_volume(r[i]);
+        double me = m + hv;
+        for (int d = 0; d < 3; ++d) {
+            double f = Ffl[d * n + i];
+            if (cp->vmass) {
+                double as = ((Fc[d * n + i] + f) + m * p->g[d]) / me;
+                f = f - hv * as;
+            }
+            fex[d * n + i] = f;
+        }
+    }
+}
+
+/* Exchange P2G of one sub-step: adds -weight * f_j N(x_j - x) to fs (3G,
+ * int64, units of 2^-32 f_unit).  Per granule and component the target total
+ * is Q = rint(S), S = (s f) * 2^32 with s = -weight / f_unit; the 26 outer
+ * nodes take rint(w S), the centre node Q minus their sum. */
+void orc_exchange_p2g(const orc_params *p, const orc_coupling *cp, int64_t n, const double *x, const double *r,
+                      const double *Fc, const double *Ffl, double weight, int64_t *fs)
+{
+    double inv_dx = 1.0 / p->dx;
+    int64_t G = orc_nodes(p);
+    double *fex = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    orc_exchange_force(p, cp, n, r, Fc, Ffl, fex);
+    double sc = -weight / cp->f_unit;
+    for (int64_t i = 0; i < n; ++i) {
+        double xa[3];
+        orc_pos(n, x, i, xa);
+        orc_stencil s;
+        orc_stencil_of(p, inv_dx, xa, &s);
+        for (int ch = 0; ch < 3; ++ch) {
+            double S = (sc * fex[ch * n + i]) * ORC_TWO32;
+            int64_t Q = llrint(S);
+            int64_t rest = Q;
+            int64_t *dst = fs + (int64_t)ch * G;
+            for (int c = 0; c < 3; ++c)
+                for (int b = 0; b < 3; ++b)
+                    for (int a = 0; a < 3; ++a) {
+                        if (a == 1 && b == 1 && c == 1) continue;
+                        double w = (s.w[0][a] * s.w[1][b]) * s.w[2][c];
+                        int64_t q = llrint(w * S);
+                        rest -= q;
+                        dst[orc_node_index(p, &s, a, b, c)] += q;
+                    }
+            dst[orc_node_index(p, &s, 1, 1, 1)] += rest;
+        }
+    }
+    free(fex);
+}
+
+/* Sub-step count of a sand step of length Dt: ceil(Dt / dt'_max). */
+int32_t orc_substeps(double Dt, double dt_max)
+{
+    double q = ceil(Dt / dt_max);
+    return q < 1.0 ? 1 : (int32_t)q;
+}
+
+/* One sand step (Alg. 2) of length Dt in N = ceil(Dt / p->dt) equal
+ * sub-steps, the fluid fields u, gp, af (3G each; gp, af may be NULL) frozen.
+ * Per sub-step: fluid forces at x^i (alpha from alpha_fx = P2G(x^i)),
+ * contact forces, exchange deposit into fs (weight 1/N), move, P2G of
+ * alpha and momentum at x^{i+1} into alpha_fx, mom_fx.  x, v updated in
+ * place; fs accumulates.  Returns N. */
+int32_t orc_sand_step(const orc_params *p, const orc_coupling *cp, int64_t n, double Dt, double *x, double *v,
+                      const double *r, const double *u, const double *gp, const double *af, int64_t *alpha_fx,
+                      int64_t *mom_fx, int64_t *fs)
+{
+    int32_t N = orc_substeps(Dt, p->dt);
+    orc_params ps = *p;
+    ps.dt = Dt / (double)N;
+    double weight = ps.dt / Dt;
+    int64_t G = orc_nodes(p);
+    size_t n3 = sizeof(double) * 3 * (size_t)(n > 0 ? n : 1);
+    double *Fc = (double *)malloc(n3);
+    double *Ffl = (double *)malloc(n3);
+    for (int32_t i = 0; i < N; ++i) {
+        orc_fluid_forces(&ps, cp, n, x, v, r, u, alpha_fx, gp, af, Ffl);
+        orc_contact_forces(&ps, n, x, v, r, Fc, NULL, NULL, NULL);
+        if (fs) orc_exchange_p2g(&ps, cp, n, x, r, Fc, Ffl, weight, fs);
+        orc_integrate_vm(&ps, cp, n, r, Fc, Ffl, x, v);
+        memset(alpha_fx, 0, sizeof(int64_t) * (size_t)G);
+        memset(mom_fx, 0, sizeof(int64_t) * 3 * (size_t)G);
+        orc_p2g_fixed(&ps, n, x, v, r, alpha_fx, mom_fx);
+    }
+    free(Fc);
+    free(Ffl);
+    return N;
+}
