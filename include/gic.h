@@ -92,7 +92,23 @@ typedef enum { GIC_FP64 = 0, GIC_FP32 = 1 } gic_precision;
  *   g[3], dt      gravity [m/s^2] and step [s].
  *   r_max         largest granule radius that will be passed [m].
  *   walls         bit 2a: wall on the low face of axis a; bit 2a+1: high.
- *   precision     gic_precision. */
+ *   precision     gic_precision.
+ * Remaining interphase forces (Sec. 3.3 Eq. 5a-5c; Sec. 5.2 Eq. 9), all off
+ * when zero:
+ *   rho_f         fluid density rho_f = rho_0 [kg/m^3] >= 0: the pressure-
+ *                 gradient force is -V grad p (V = 4/3 pi r^3) whenever a
+ *                 grad p grid is passed; rho_f enters the quadratic drag and
+ *                 the virtual mass.
+ *   drag_model    0: the linear drag above; 1: Eq. (5b) as printed,
+ *                 F_d = 12 pi r^2 rho_f c_quad |u - v| (u - v), c_quad >= 0
+ *                 the dimensionless coefficient.
+ *   vmass         1: virtual mass: (m + rho_f V / 2) dv/dt = F_c + F_d + F_p
+ *                 + (rho_f V / 2) a_f + m g with a_f the fluid acceleration
+ *                 grid (Eq. 9); 0: none.
+ *   f_unit        unit of the fixed-point exchange-force grid [N] (> 0 for
+ *                 gic_exchange_p2g and gic_sand_step with an exchange grid).
+ * The adjoint form (the *_vjp calls) covers drag_model 0 without virtual
+ * mass and returns GIC_E_ARG otherwise. */
 typedef struct gic_params {
     int32_t n[3];
     int32_t pad0;
@@ -107,6 +123,11 @@ typedef struct gic_params {
     double r_max;
     uint32_t walls;
     int32_t precision;
+    double rho_f;
+    double c_quad;
+    double f_unit;
+    int32_t drag_model;
+    int32_t vmass;
 } gic_params;
 
 typedef struct gic_ctx gic_ctx;
@@ -259,6 +280,51 @@ gic_status gic_step(gic_ctx *ctx, int64_t n, const double *x_cur, const double *
                     const void *u, int64_t *alpha_fx, int64_t *mom_fx, uint32_t *key, int32_t *order,
                     int32_t *cell_begin, int32_t *cell_end, void *f_contact, void *f_drag, void *u_at,
                     void *alpha_f, void *stream);
+
+/* ---- remaining interphase forces and the sand step -------------------------
+ * gic_gather_g2p_fluid = gic_gather_g2p_drag with the whole fluid force of
+ * Sec. 3.3 (Eq. 5a-5c) written to f_fluid (3n real): the drag of
+ * params.drag_model, plus -V grad p with grad_p (3 x G real, the pressure
+ * gradient of the fluid step, Sec. 5.2) interpolated like u, plus
+ * (rho_f V / 2) a_f under params.vmass with acc_f (3 x G real, the fluid
+ * acceleration dv_f/dt of the grid, Eq. 12), V = 4/3 pi r^3.  grad_p and
+ * acc_f may be NULL (no such term).  The a_s part of the virtual-mass force
+ * is the effective mass of the integrator (gic_integrate_p2g with vmass).
+ * The _out arrays must not alias the inputs. */
+gic_status gic_gather_g2p_fluid(gic_ctx *ctx, int64_t n, const int32_t *order, const double *x, const double *v,
+                                const double *r, const int32_t *id, double *x_out, double *v_out, double *r_out,
+                                int32_t *id_out, const void *u, const int64_t *alpha_fx, const void *grad_p,
+                                const void *acc_f, const int32_t *cell_begin, const int32_t *cell_end,
+                                void *f_fluid, void *stream);
+
+/* Exchange momentum of one sub-step (Sec. 5.2): adds -weight f_j N(x_j - x)
+ * to fs_fx (3 x G int64, x-plane then y and z, units of 2^-32
+ * params.f_unit), f_j the whole fluid force on granule j: f_fluid, and under
+ * params.vmass minus (rho_f V / 2) a_s with a_s = ((f_contact + f_fluid) +
+ * m g) / (m + rho_f V / 2), the sub-step's acceleration.  Per granule and
+ * component the deposit totals rint(S), S = (-weight / f_unit) f 2^32, the 26
+ * outer nodes taking rint(w S) and the centre the rest (integer, so bit-exact
+ * in any order).  x, r, f_contact, f_fluid in the sorted order of
+ * cell_begin, cell_end (positions before the move).  GIC_E_ARG if
+ * params.f_unit <= 0.  Latches GIC_E_RANGE for |S| >= 2^51. */
+gic_status gic_exchange_p2g(gic_ctx *ctx, int64_t n, const double *x, const double *r, const void *f_contact,
+                            const void *f_fluid, const int32_t *cell_begin, const int32_t *cell_end, double weight,
+                            int64_t *fs_fx, void *stream);
+
+/* One sand step (Alg. 2) of length Dt: N = ceil(Dt / params.dt) equal
+ * sub-steps of Dt / N with the fluid fields u, grad_p, acc_f frozen, each
+ * gic_sort_cells -> gic_gather_g2p_fluid -> gic_contact_forces ->
+ * gic_exchange_p2g (weight 1/N; skipped when fs_fx is NULL) ->
+ * gic_integrate_p2g.  The state ping-pongs between the a and b arrays,
+ * starting in a; *which = 0 if it ends in a, 1 if in b; *nsub = N.  fs_fx
+ * accumulates (clear it before the first sand step of a fluid step);
+ * alpha_fx, mom_fx hold the P2G of the final state.  Scratch as for
+ * gic_step; f_contact, f_fluid hold the last sub-step's forces. */
+gic_status gic_sand_step(gic_ctx *ctx, int64_t n, double Dt, double *x_a, double *v_a, double *r_a, int32_t *id_a,
+                         double *x_b, double *v_b, double *r_b, int32_t *id_b, const void *u, const void *grad_p,
+                         const void *acc_f, int64_t *alpha_fx, int64_t *mom_fx, int64_t *fs_fx, uint32_t *key,
+                         int32_t *order, int32_t *cell_begin, int32_t *cell_end, void *f_contact, void *f_fluid,
+                         int32_t *nsub, int32_t *which, void *stream);
 
 /* ---- a9: adjoint form ------------------------------------------------------
  * Vector-Jacobian products of the stages of the differentiable step (all

@@ -42,6 +42,10 @@ bool params_valid(const gic_params *p)
     if (!(p->kn > 0.0) || !(p->restitution > 0.0) || !(p->restitution <= 1.0)) return false;
     if (!(p->kt_ratio >= 0.0) || !(p->mu >= 0.0) || !(p->rho_s > 0.0)) return false;
     if (!(p->eta_f >= 0.0) || !(p->c_drag >= 0.0) || !(p->alpha_max > 0.0) || !(p->dt > 0.0)) return false;
+    if (!(p->rho_f >= 0.0) || !isfinite(p->rho_f) || !(p->c_quad >= 0.0) || !isfinite(p->c_quad)) return false;
+    if (!(p->f_unit >= 0.0) || !isfinite(p->f_unit)) return false;
+    if (p->drag_model != 0 && p->drag_model != 1) return false;
+    if (p->vmass != 0 && p->vmass != 1) return false;
     for (int a = 0; a < 3; ++a)
         if (!isfinite(p->g[a])) return false;
     if (p->precision != GIC_FP64 && p->precision != GIC_FP32) return false;
@@ -98,6 +102,11 @@ DevParams derive(const gic_params *p)
     d.r_max = p->r_max;
     d.search_scale = 1.0 + 1.0 / 1073741824.0;  // 1 + 2^-30: slack for rounding
     d.walls = p->walls;
+    d.rho_f = p->rho_f;
+    d.half_rho_f = 0.5 * p->rho_f;
+    d.c_quad = p->c_quad;
+    d.drag_model = p->drag_model;
+    d.vmass = p->vmass;
     return d;
 }
 
@@ -430,12 +439,108 @@ gic_status gic_step(gic_ctx *c, int64_t n, const double *x_cur, const double *v_
     return st;
 }
 
+/* ---- remaining interphase forces and the sand step ----------------------- */
+
+gic_status gic_gather_g2p_fluid(gic_ctx *c, int64_t n, const int32_t *order, const double *x, const double *v,
+                                const double *r, const int32_t *id, double *x_out, double *v_out, double *r_out,
+                                int32_t *id_out, const void *u, const int64_t *alpha_fx, const void *grad_p,
+                                const void *acc_f, const int32_t *cell_begin, const int32_t *cell_end,
+                                void *f_fluid, void *stream)
+{
+    if (!n_ok(c, n) || !cell_begin || !cell_end) return GIC_E_ARG;
+    if (n > 0 && (!order || !x || !v || !r || !x_out || !v_out || !r_out || !u || !alpha_fx || !f_fluid))
+        return GIC_E_ARG;
+    if ((id == nullptr) != (id_out == nullptr)) return GIC_E_ARG;
+    if (n > 0 && (x_out == x || v_out == v || r_out == r || (id && id_out == id))) return GIC_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (n == 0) return GIC_OK;
+    if (brick_list(c, cell_begin, cell_end, s) != hipSuccess) return GIC_E_HIP;
+    if (fp32(c))
+        return hip_status(launch_gather_g2p_fluid<float>(
+            c->dp, n, c->K, order, x, v, r, id, x_out, v_out, r_out, id_out, (const float *)u, alpha_fx,
+            (const float *)grad_p, (const float *)acc_f, cell_begin, cell_end, c->bricks, (float *)f_fluid, s));
+    return hip_status(launch_gather_g2p_fluid<double>(
+        c->dp, n, c->K, order, x, v, r, id, x_out, v_out, r_out, id_out, (const double *)u, alpha_fx,
+        (const double *)grad_p, (const double *)acc_f, cell_begin, cell_end, c->bricks, (double *)f_fluid, s));
+}
+
+gic_status gic_exchange_p2g(gic_ctx *c, int64_t n, const double *x, const double *r, const void *f_contact,
+                            const void *f_fluid, const int32_t *cell_begin, const int32_t *cell_end, double weight,
+                            int64_t *fs_fx, void *stream)
+{
+    if (!n_ok(c, n) || !cell_begin || !cell_end || !fs_fx) return GIC_E_ARG;
+    if (n > 0 && (!x || !r || !f_contact || !f_fluid)) return GIC_E_ARG;
+    if (!(c->p.f_unit > 0.0) || !isfinite(weight)) return GIC_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (n == 0) return GIC_OK;
+    if (brick_list(c, cell_begin, cell_end, s) != hipSuccess) return GIC_E_HIP;
+    const double exsc = -weight / c->p.f_unit;
+    if (fp32(c))
+        return hip_status(launch_exchange_p2g<float>(c->dp, n, c->K, x, r, (const float *)f_contact,
+                                                     (const float *)f_fluid, cell_begin, cell_end, c->bricks, exsc,
+                                                     fs_fx, c->err, s));
+    return hip_status(launch_exchange_p2g<double>(c->dp, n, c->K, x, r, (const double *)f_contact,
+                                                  (const double *)f_fluid, cell_begin, cell_end, c->bricks, exsc,
+                                                  fs_fx, c->err, s));
+}
+
+gic_status gic_sand_step(gic_ctx *c, int64_t n, double Dt, double *x_a, double *v_a, double *r_a, int32_t *id_a,
+                         double *x_b, double *v_b, double *r_b, int32_t *id_b, const void *u, const void *grad_p,
+                         const void *acc_f, int64_t *alpha_fx, int64_t *mom_fx, int64_t *fs_fx, uint32_t *key,
+                         int32_t *order, int32_t *cell_begin, int32_t *cell_end, void *f_contact, void *f_fluid,
+                         int32_t *nsub, int32_t *which, void *stream)
+{
+    if (!n_ok(c, n) || !alpha_fx || !mom_fx || !cell_begin || !cell_end || !nsub || !which) return GIC_E_ARG;
+    if (!(Dt > 0.0) || !isfinite(Dt)) return GIC_E_ARG;
+    if (n > 0 && (!x_a || !v_a || !r_a || !x_b || !v_b || !r_b || !u || !key || !order || !f_contact || !f_fluid))
+        return GIC_E_ARG;
+    if ((id_a == nullptr) != (id_b == nullptr)) return GIC_E_ARG;
+    if (fs_fx && !(c->p.f_unit > 0.0)) return GIC_E_ARG;
+    const double q = ceil(Dt / c->p.dt);
+    if (!(q < 2147483647.0)) return GIC_E_ARG;
+    const int32_t N = q < 1.0 ? 1 : (int32_t)q;
+    const double dt_sub = Dt / (double)N;
+    const double weight = dt_sub / Dt;
+    hipStream_t s = (hipStream_t)stream;
+    const double dt_keep = c->dp.dt;
+    c->dp.dt = dt_sub;  // the sub-steps' length, captured by value at each launch
+    gic_status st = GIC_OK;
+    for (int32_t i = 0; i < N && st == GIC_OK; ++i) {
+        const bool even = (i & 1) == 0;
+        double *xc = even ? x_a : x_b, *vc = even ? v_a : v_b, *rc = even ? r_a : r_b;
+        double *xn = even ? x_b : x_a, *vn = even ? v_b : v_a, *rn = even ? r_b : r_a;
+        int32_t *ic = even ? id_a : id_b, *in = even ? id_b : id_a;
+        st = gic_sort_cells(c, n, xc, key, order, cell_begin, cell_end, stream);
+        if (st != GIC_OK) break;
+        if (n > 0 && launch_brick_list(cell_begin, cell_end, c->bricks, s) != hipSuccess) {
+            st = GIC_E_HIP;
+            break;
+        }
+        c->in_step = true;  // the stages below share this brick list
+        st = gic_gather_g2p_fluid(c, n, order, xc, vc, rc, ic, xn, vn, rn, in, u, alpha_fx, grad_p, acc_f,
+                                  cell_begin, cell_end, f_fluid, stream);
+        if (st == GIC_OK)
+            st = gic_contact_forces(c, n, xn, vn, rn, cell_begin, cell_end, f_contact, nullptr, stream);
+        if (st == GIC_OK && fs_fx)
+            st = gic_exchange_p2g(c, n, xn, rn, f_contact, f_fluid, cell_begin, cell_end, weight, fs_fx, stream);
+        if (st == GIC_OK)
+            st = gic_integrate_p2g(c, n, xn, vn, rn, f_contact, f_fluid, cell_begin, cell_end, alpha_fx, mom_fx, 0,
+                                   stream);
+        c->in_step = false;
+    }
+    c->dp.dt = dt_keep;
+    *nsub = N;
+    *which = N & 1;
+    return st;
+}
+
 /* ---- adjoint form (double) ---------------------------------------------- */
 
 gic_status gic_contact_forces_vjp(gic_ctx *c, int64_t n, const double *x, const double *v, const double *r,
                                   const int32_t *cell_begin, const int32_t *cell_end, const double *g_f, double *g_x,
                                   double *g_v, double *g_mu, void *stream)
 {
+    if (c && (c->p.drag_model != 0 || c->p.vmass != 0)) return GIC_E_ARG;  // the adjoint covers the linear drag only
     if (!n_ok(c, n) || fp32(c)) return GIC_E_ARG;
     if (n > 0 && (!x || !v || !r || !cell_begin || !cell_end || !g_f || !g_x || !g_v || !g_mu)) return GIC_E_ARG;
     return hip_status(launch_contact_vjp(c->dp, n, x, v, r, cell_begin, cell_end, g_f, g_x, g_v, g_mu,
@@ -446,6 +551,7 @@ gic_status gic_drag_vjp(gic_ctx *c, int64_t n, const double *r, const double *v,
                         const double *alpha_f, const double *g_f, double *g_v, double *g_u_at, double *g_alpha_f,
                         double *g_cdrag, void *stream)
 {
+    if (c && (c->p.drag_model != 0 || c->p.vmass != 0)) return GIC_E_ARG;  // the adjoint covers the linear drag only
     if (!n_ok(c, n) || fp32(c)) return GIC_E_ARG;
     if (n > 0 && (!r || !v || !u_at || !alpha_f || !g_f || !g_v || !g_u_at || !g_alpha_f || !g_cdrag))
         return GIC_E_ARG;
@@ -456,6 +562,7 @@ gic_status gic_drag_vjp(gic_ctx *c, int64_t n, const double *r, const double *v,
 gic_status gic_integrate_vjp(gic_ctx *c, int64_t n, const double *r, const double *g_x, double *g_v, double *g_f,
                              void *stream)
 {
+    if (c && (c->p.drag_model != 0 || c->p.vmass != 0)) return GIC_E_ARG;  // the adjoint covers the linear drag only
     if (!n_ok(c, n) || fp32(c)) return GIC_E_ARG;
     if (n > 0 && (!r || !g_x || !g_v || !g_f)) return GIC_E_ARG;
     return hip_status(launch_integrate_vjp(c->dp, n, r, g_x, g_v, g_f, (hipStream_t)stream));
@@ -465,6 +572,7 @@ gic_status gic_g2p_vjp(gic_ctx *c, int64_t n, const double *x, const double *u, 
                        const double *g_u_at, const double *g_alpha_f, const int32_t *cell_begin,
                        const int32_t *cell_end, double *g_x, double *g_alpha, void *stream)
 {
+    if (c && (c->p.drag_model != 0 || c->p.vmass != 0)) return GIC_E_ARG;  // the adjoint covers the linear drag only
     if (!n_ok(c, n) || fp32(c)) return GIC_E_ARG;
     if (n > 0 && (!x || !u || !alpha_real || !g_u_at || !g_alpha_f || !g_x)) return GIC_E_ARG;
     if (n > 0 && g_alpha && (!cell_begin || !cell_end)) return GIC_E_ARG;
@@ -477,6 +585,7 @@ gic_status gic_g2p_vjp(gic_ctx *c, int64_t n, const double *x, const double *u, 
 gic_status gic_p2g_vjp(gic_ctx *c, int64_t n, const double *x, const double *v, const double *r,
                        const double *g_alpha, const double *g_mom, double *g_x, double *g_v, void *stream)
 {
+    if (c && (c->p.drag_model != 0 || c->p.vmass != 0)) return GIC_E_ARG;  // the adjoint covers the linear drag only
     if (!n_ok(c, n)) return GIC_E_ARG;
     if (n > 0 && (!x || !r || !g_x || (g_mom && (!v || !g_v)) || (!g_alpha && !g_mom))) return GIC_E_ARG;
     return hip_status(launch_p2g_vjp(c->dp, n, x, v, r, g_alpha, g_mom, g_x, g_v, (hipStream_t)stream));

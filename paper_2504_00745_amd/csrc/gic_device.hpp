@@ -16,6 +16,7 @@ namespace gic {
 
 #define GIC_PI 3.14159265358979323846
 #define GIC_C43PI (4.0 * GIC_PI / 3.0)
+#define GIC_C12PI (12.0 * GIC_PI)
 #define GIC_TWO32 4294967296.0
 #define GIC_TWOM32 (1.0 / 4294967296.0)
 constexpr int kBrick = 4;                 // cells per brick edge in the key
@@ -93,6 +94,11 @@ struct DevParams {
     double g[3], dt;
     double r_max, search_scale;
     uint32_t walls;
+    // remaining interphase forces (Sec. 3.3 Eq. 5a-5c, Sec. 5.2 Eq. 9)
+    double rho_f, half_rho_f;  // fluid density and rho_f / 2 (virtual mass per volume)
+    double c_quad;             // coefficient of the quadratic drag
+    int32_t drag_model;        // 0: linear Stokes form x alpha_f; 1: quadratic of Eq. 5b
+    int32_t vmass;             // 1: virtual mass, effective mass m + rho_f V / 2
 };
 
 // Latch the first error: code and granule index.
@@ -195,10 +201,8 @@ __device__ inline int64_t rint_i64(double v)
 // k, u[3], al) supplies node (i, j, k)'s velocity and its clamped solid
 // fraction; the same summation order serves every caller.
 template <typename T, typename Fetch>
-__device__ inline void g2p_sample(const DevParams &P, const double xa[3], Fetch &&fetch, T uat[3], T &af)
+__device__ inline void g2p_sample_st(const Stencil &s, Fetch &&fetch, T uat[3], T &af)
 {
-    Stencil s;
-    stencil_of(P, xa, s);
     T acc[3] = {(T)0, (T)0, (T)0};
     T as = (T)0;
 #pragma unroll 1
@@ -221,6 +225,14 @@ __device__ inline void g2p_sample(const DevParams &P, const double xa[3], Fetch 
     af = (T)1 - as;
 }
 
+template <typename T, typename Fetch>
+__device__ inline void g2p_sample(const DevParams &P, const double xa[3], Fetch &&fetch, T uat[3], T &af)
+{
+    Stencil s;
+    stencil_of(P, xa, s);
+    g2p_sample_st<T>(s, fetch, uat, af);
+}
+
 // Solid fraction of a node for G2P: fixed point to cell volumes, clamped.
 __device__ inline double node_alpha(const DevParams &P, int64_t afx)
 {
@@ -229,20 +241,51 @@ __device__ inline double node_alpha(const DevParams &P, int64_t afx)
 }
 __device__ inline double node_alpha_real(const DevParams &P, double a) { return a > P.alpha_max ? P.alpha_max : a; }
 
-// Drag of Eq. (5b) in Stokes form scaled by the fluid fraction (App. A):
-// F_d = C_d 6 pi eta_f r alpha_f (u_at - v).
+// Drag.  Linear (drag_model 0): Eq. (5b) in the Stokes form of App. A,
+// scaled by the fluid fraction, F_d = C_d 6 pi eta_f r alpha_f (u_at - v).
+// Quadratic (drag_model 1): Eq. (5b) as printed, F_d = 12 pi r^2 rho_f C
+// |u_at - v| (u_at - v) with C the dimensionless coefficient c_quad.
 template <typename T>
 __device__ inline void drag_one(const DevParams &P, double r, const double v[3], const T uat[3], T af, T Fd[3])
 {
+#pragma clang fp contract(off)  // one rounding per operation in every kernel that inlines it
+    if (P.drag_model == 1) {
+        T w[3];
+        for (int a = 0; a < 3; ++a) w[a] = uat[a] - (T)v[a];
+        const T s2 = (w[0] * w[0] + w[1] * w[1]) + w[2] * w[2];
+        T sp;
+        if constexpr (sizeof(T) == sizeof(float))
+            sp = __builtin_amdgcn_sqrtf(s2);
+        else
+            sp = sqrt(s2);
+        const T coef = (T)((((GIC_C12PI * r) * r) * P.rho_f) * P.c_quad);
+        for (int a = 0; a < 3; ++a) Fd[a] = (coef * sp) * w[a];
+        return;
+    }
     const T beta = (T)(P.cdrag * r) * af;
     for (int a = 0; a < 3; ++a) Fd[a] = beta * (uat[a] - (T)v[a]);
 }
 
 // Semi-implicit Euler (Sec. 4): v += dt ((F_c + F_d) / m + g), then x += dt v.
+// With virtual mass (Eq. 9) the effective mass is m + rho_f V / 2 and
+// gravity acts on m: v += dt ((F_c + F_d) + m g) / (m + rho_f V / 2).
 template <typename T>
 __device__ inline void integrate_one(const DevParams &P, double r, const T Fc[3], const T *Fd, double x[3],
                                      double v[3])
 {
+#pragma clang fp contract(off)  // one rounding per operation in every kernel that inlines it
+    if (P.vmass) {
+        const double m = mass_of(P, r);
+        const double me = m + P.half_rho_f * volume_of(r);
+        for (int a = 0; a < 3; ++a) {
+            double f = (double)Fc[a];
+            if (Fd) f += (double)Fd[a];
+            const double vn = v[a] + P.dt * ((f + m * P.g[a]) / me);
+            v[a] = vn;
+            x[a] = x[a] + P.dt * vn;
+        }
+        return;
+    }
     const double inv_m = 1.0 / mass_of(P, r);
     for (int a = 0; a < 3; ++a) {
         double f = (double)Fc[a];

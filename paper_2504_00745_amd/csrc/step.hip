@@ -85,7 +85,149 @@ __global__ void __launch_bounds__(256) k_gather_g2p_drag(DevParams P, int64_t n,
     }
 }
 
+// The same gather and G2P with the remaining interphase forces (Sec. 3.3
+// Eq. 5a-5c): the node tile also holds grad p (gp) and the fluid
+// acceleration (fa) when given, and each granule's fluid force is the drag
+// of the drag model, plus -V grad p at the granule, plus (rho_f V / 2) a_f
+// under virtual mass (the a_s part of the virtual-mass force sits in the
+// effective mass of the integrator).  The interpolation of u and alpha is
+// the same function as in the drag-only kernel; gp and fa use the same
+// weights in the same order.
+template <typename T>
+__global__ void __launch_bounds__(256) k_gather_g2p_fluid(DevParams P, int64_t n, const int32_t *__restrict__ bl,
+                                                          const int32_t *__restrict__ bcnt,
+                                                          const int32_t *__restrict__ order,
+                                                          const double *__restrict__ x, const double *__restrict__ v,
+                                                          const double *__restrict__ r,
+                                                          const int32_t *__restrict__ id, double *__restrict__ xo,
+                                                          double *__restrict__ vo, double *__restrict__ ro,
+                                                          int32_t *__restrict__ ido, const T *__restrict__ u,
+                                                          const int64_t *__restrict__ afx, const T *__restrict__ gp,
+                                                          const T *__restrict__ fa, const int32_t *__restrict__ cb,
+                                                          const int32_t *__restrict__ ce, T *__restrict__ Ff)
+{
+    extern __shared__ double smem_d[];
+    const int64_t b = brick_of_block(bl, bcnt);
+    if (b < 0) return;
+    int32_t gb = cb[b * kBrickCells], ge = ce[b * kBrickCells + kBrickCells - 1];
+    clip_range(n, gb, ge);
+    if (ge <= gb) return;
+    const bool vm_acc = P.vmass && fa != nullptr;
+    const int E = P.tile, E3 = E * E * E;
+    T *su = reinterpret_cast<T *>(smem_d);  // [10][E3]: u_x, u_y, u_z, clamped alpha, grad p (3), a_f (3)
+    int32_t o[3];
+    tile_origin(P, b, o);
+    const int64_t G = P.G;
+    for (int k = threadIdx.x; k < E3; k += 256) {
+        const int32_t i = o[0] + k % E, j = o[1] + (k / E) % E, l = o[2] + k / (E * E);
+        if (i < 0 || j < 0 || l < 0 || i >= P.n[0] || j >= P.n[1] || l >= P.n[2]) continue;  // never referenced
+        const int64_t idx = node_index(P, i, j, l);
+        for (int c = 0; c < 3; ++c) su[c * E3 + k] = u[c * G + idx];
+        su[3 * E3 + k] = (T)node_alpha(P, afx[idx]);
+        for (int c = 0; c < 3; ++c) {
+            su[(4 + c) * E3 + k] = gp ? gp[c * G + idx] : (T)0;
+            su[(7 + c) * E3 + k] = vm_acc ? fa[c * G + idx] : (T)0;
+        }
+    }
+    __syncthreads();
+    // node (i, j, k) as a tile slot, or -1 outside the tile (a granule whose
+    // cell is clamped; its values then come from the grid)
+    auto slot = [&](int32_t i, int32_t j, int32_t k) {
+        const int32_t li = i - o[0], lj = j - o[1], lk = k - o[2];
+        return (li >= 0 && lj >= 0 && lk >= 0 && li < E && lj < E && lk < E) ? (lk * E + lj) * E + li : -1;
+    };
+    for (int64_t q = gb + threadIdx.x; q < ge; q += 256) {
+        const int64_t s = order[q];
+        if ((uint64_t)s >= (uint64_t)n) continue;  // not a permutation of [0, n): position q left untouched
+        const double xa[3] = {x[s], x[n + s], x[2 * n + s]};
+        const double va[3] = {v[s], v[n + s], v[2 * n + s]};
+        const double rq = r[s];
+        for (int a = 0; a < 3; ++a) {
+            xo[a * n + q] = xa[a];
+            vo[a * n + q] = va[a];
+        }
+        ro[q] = rq;
+        if (ido) ido[q] = id[s];
+        Stencil st;
+        stencil_of(P, xa, st);
+        T ua[3], a;
+        g2p_sample_st<T>(st, [&](int32_t i, int32_t j, int32_t k, T uu[3], T &al) {
+            const int t = slot(i, j, k);
+            if (t >= 0) {
+                uu[0] = su[t];
+                uu[1] = su[E3 + t];
+                uu[2] = su[2 * E3 + t];
+                al = su[3 * E3 + t];
+            } else {
+                const int64_t idx = node_index(P, i, j, k);
+                uu[0] = u[idx];
+                uu[1] = u[G + idx];
+                uu[2] = u[2 * G + idx];
+                al = (T)node_alpha(P, afx[idx]);
+            }
+        }, ua, a);
+        T f[3];
+        drag_one<T>(P, rq, va, ua, a, f);
+        if (gp || vm_acc) {
+            T gpa[3] = {(T)0, (T)0, (T)0}, faa[3] = {(T)0, (T)0, (T)0};
+#pragma unroll 1
+            for (int cz = 0; cz < 3; ++cz)
+                for (int cy = 0; cy < 3; ++cy) {
+                    const double wyz = st.w[1][cy] * st.w[2][cz];
+                    for (int cx = 0; cx < 3; ++cx) {
+                        const T w = (T)(st.w[0][cx] * wyz);
+                        const int32_t i = st.node[0][cx], j = st.node[1][cy], k = st.node[2][cz];
+                        const int t = slot(i, j, k);
+                        const int64_t idx = t >= 0 ? 0 : node_index(P, i, j, k);
+                        for (int c = 0; c < 3; ++c) {
+                            const T g = t >= 0 ? su[(4 + c) * E3 + t] : (gp ? gp[c * G + idx] : (T)0);
+                            const T h = t >= 0 ? su[(7 + c) * E3 + t] : (vm_acc ? fa[c * G + idx] : (T)0);
+                            gpa[c] += w * g;
+                            faa[c] += w * h;
+                        }
+                    }
+                }
+            const double V = volume_of(rq);
+            const T tV = (T)V, thv = (T)(P.half_rho_f * V);
+            for (int c = 0; c < 3; ++c) {
+                T fc = f[c];
+                if (gp) fc = fc - tV * gpa[c];
+                if (vm_acc) fc = fc + thv * faa[c];
+                f[c] = fc;
+            }
+        }
+        for (int c = 0; c < 3; ++c) Ff[c * n + q] = f[c];
+    }
+}
+
 }  // namespace
+
+template <typename T>
+hipError_t launch_gather_g2p_fluid(const DevParams &P, int64_t n, int64_t K, const int32_t *order, const double *x,
+                                   const double *v, const double *r, const int32_t *id, double *xo, double *vo,
+                                   double *ro, int32_t *ido, const T *u, const int64_t *afx, const T *gp,
+                                   const T *fa, const int32_t *cb, const int32_t *ce, const BrickList &B, T *Ff,
+                                   hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const int64_t bricks = K / kBrickCells;
+    const int E = P.tile;
+    const size_t lds = sizeof(T) * 10 * (size_t)E * E * E;
+    k_gather_g2p_fluid<T><<<brick_grid(bricks), 256, lds, s>>>(P, n, B.list, B.count, order, x, v, r, id, xo, vo, ro,
+                                                               ido, u, afx, gp, fa, cb, ce, Ff);
+    return hipGetLastError();
+}
+
+template hipError_t launch_gather_g2p_fluid<float>(const DevParams &, int64_t, int64_t, const int32_t *,
+                                                   const double *, const double *, const double *, const int32_t *,
+                                                   double *, double *, double *, int32_t *, const float *,
+                                                   const int64_t *, const float *, const float *, const int32_t *,
+                                                   const int32_t *, const BrickList &, float *, hipStream_t);
+template hipError_t launch_gather_g2p_fluid<double>(const DevParams &, int64_t, int64_t, const int32_t *,
+                                                    const double *, const double *, const double *, const int32_t *,
+                                                    double *, double *, double *, int32_t *, const double *,
+                                                    const int64_t *, const double *, const double *, const int32_t *,
+                                                    const int32_t *, const BrickList &, double *, hipStream_t);
 
 template <typename T>
 hipError_t launch_gather_g2p_drag(const DevParams &P, int64_t n, int64_t K, const int32_t *order, const double *x,

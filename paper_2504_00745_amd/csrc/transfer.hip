@@ -87,7 +87,14 @@ __device__ inline void tile_add(unsigned long long *tile, unsigned long long *gl
 // the contact and drag forces Fc, Fd, as the integration kernel does), and
 // the granule is deposited at its new position; each granule is read and
 // written by one thread only.
-template <bool MOM, typename T, bool INTEG>
+//
+// EXCH: the exchange deposit of a sub-step (Sec. 5.2) instead of alpha and
+// momentum: three channels, S_c = (exsc f_c) 2^32 with f the whole fluid
+// force on the granule (Fd, plus the virtual-mass part -(rho_f V / 2) a_s
+// with a_s = ((Fc + Fd) + m g) / (m + rho_f V / 2)), exsc = -weight / f_unit,
+// deposited at the granule's current position; alpha receives channel 0 and
+// mom channels 1 and 2.
+template <bool MOM, typename T, bool INTEG, bool EXCH = false>
 __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_eu(4))) k_p2g_fixed(DevParams P, int64_t n, const int32_t *__restrict__ bl,
                                                            const int32_t *__restrict__ bcnt, int batch,
                                                            double *x, double *v, const double *__restrict__ r,
@@ -95,10 +102,12 @@ __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_e
                                                            const int32_t *__restrict__ cb,
                                                            const int32_t *__restrict__ ce,
                                                            unsigned long long *__restrict__ alpha,
-                                                           unsigned long long *__restrict__ mom, int64_t *err)
+                                                           unsigned long long *__restrict__ mom, int64_t *err,
+                                                           double exsc)
 {
 #pragma clang fp contract(off)
-    constexpr int NCH = MOM ? 4 : 1;
+    static_assert(!(EXCH && (MOM || INTEG)), "the exchange deposit is a kind of its own");
+    constexpr int NCH = EXCH ? 3 : (MOM ? 4 : 1);
     extern __shared__ unsigned long long tile[];
     __shared__ int32_t s_range[2];
     __shared__ int32_t s_wave[kP2GThreads / 64];
@@ -146,12 +155,28 @@ __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_e
                 if (fb > (double)P.n[a]) fb = (double)P.n[a];
                 sbase[a * bs + i] = (int16_t)fb;
             }
-            const double frac = volume_of(r[q]) * P.inv_vcell;
             double S[NCH];
-            S[0] = frac * GIC_TWO32;
-            if (MOM)
+            if constexpr (EXCH) {
+                const double rq = r[q];
+                const double m = mass_of(P, rq);
+                const double hv = P.half_rho_f * volume_of(rq);
+                const double me = m + hv;
 #pragma unroll
-                for (int c = 1; c < NCH; ++c) S[c] = (frac * va[c - 1]) * GIC_TWO32;
+                for (int c = 0; c < 3; ++c) {
+                    double f = (double)Fd[c * n + q];
+                    if (P.vmass) {
+                        const double as = (((double)Fc[c * n + q] + f) + m * P.g[c]) / me;
+                        f = f - hv * as;
+                    }
+                    S[c] = (exsc * f) * GIC_TWO32;
+                }
+            } else {
+                const double frac = volume_of(r[q]) * P.inv_vcell;
+                S[0] = frac * GIC_TWO32;
+                if (MOM)
+#pragma unroll
+                    for (int c = 1; c < NCH; ++c) S[c] = (frac * va[c - 1]) * GIC_TWO32;
+            }
             bool ok = true;
 #pragma unroll
             for (int c = 0; c < NCH; ++c) ok &= fabs(S[c]) < kFixLimit;
@@ -406,12 +431,39 @@ static hipError_t p2g_fixed_impl(const DevParams &P, int64_t n, int64_t K, doubl
     unsigned long long *M = reinterpret_cast<unsigned long long *>(mom);
     if (mom)
         k_p2g_fixed<true, T, INTEG><<<brick_grid(bricks), kP2GThreads, lds, s>>>(P, n, B.list, B.count, batch, x, v, r,
-                                                                                 Fc, Fd, cb, ce, A, M, err);
+                                                                                 Fc, Fd, cb, ce, A, M, err, 0.0);
     else
         k_p2g_fixed<false, T, INTEG><<<brick_grid(bricks), kP2GThreads, lds, s>>>(P, n, B.list, B.count, batch, x, v,
-                                                                                  r, Fc, Fd, cb, ce, A, nullptr, err);
+                                                                                  r, Fc, Fd, cb, ce, A, nullptr, err,
+                                                                                  0.0);
     return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_exchange_p2g(const DevParams &P, int64_t n, int64_t K, const double *x, const double *r,
+                               const T *Fc, const T *Ffl, const int32_t *cb, const int32_t *ce, const BrickList &B,
+                               double exsc, int64_t *fs, int64_t *err, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const int64_t bricks = K / kBrickCells;
+    const int E3 = P.tile * P.tile * P.tile;
+    int batch = 512;
+    while (batch > 64 && p2g_lds(3, E3, batch) > 49152) batch /= 2;
+    const size_t lds = p2g_lds(3, E3, batch);
+    unsigned long long *F = reinterpret_cast<unsigned long long *>(fs);
+    // x is only read on this path
+    k_p2g_fixed<false, T, false, true><<<brick_grid(bricks), kP2GThreads, lds, s>>>(
+        P, n, B.list, B.count, batch, const_cast<double *>(x), nullptr, r, Fc, Ffl, cb, ce, F, F + P.G, err, exsc);
+    return hipGetLastError();
+}
+
+template hipError_t launch_exchange_p2g<float>(const DevParams &, int64_t, int64_t, const double *, const double *,
+                                               const float *, const float *, const int32_t *, const int32_t *,
+                                               const BrickList &, double, int64_t *, int64_t *, hipStream_t);
+template hipError_t launch_exchange_p2g<double>(const DevParams &, int64_t, int64_t, const double *,
+                                                const double *, const double *, const double *, const int32_t *,
+                                                const int32_t *, const BrickList &, double, int64_t *, int64_t *,
+                                                hipStream_t);
 
 hipError_t launch_p2g_fixed(const DevParams &P, int64_t n, int64_t K, const double *x, const double *v,
                             const double *r, const int32_t *cb, const int32_t *ce, const BrickList &B,

@@ -34,6 +34,8 @@ class gic_params(C.Structure):
         ("rho_s", C.c_double), ("eta_f", C.c_double), ("c_drag", C.c_double), ("alpha_max", C.c_double),
         ("g", C.c_double * 3), ("dt", C.c_double), ("r_max", C.c_double),
         ("walls", C.c_uint32), ("precision", C.c_int32),
+        ("rho_f", C.c_double), ("c_quad", C.c_double), ("f_unit", C.c_double),
+        ("drag_model", C.c_int32), ("vmass", C.c_int32),
     ]
 
 
@@ -68,6 +70,9 @@ def lib():
             "gic_gather_g2p_drag": (C.c_int, [_V, _I64] + [_V] * 16),
             "gic_integrate_p2g": (C.c_int, [_V, _I64] + [_V] * 9 + [_I32, _V]),
             "gic_step": (C.c_int, [_V, _I64] + [_V] * 19),
+            "gic_gather_g2p_fluid": (C.c_int, [_V, _I64] + [_V] * 17),
+            "gic_exchange_p2g": (C.c_int, [_V, _I64] + [_V] * 6 + [C.c_double, _V, _V]),
+            "gic_sand_step": (C.c_int, [_V, _I64, C.c_double] + [_V] * 22),
             "gic_contact_forces_vjp": (C.c_int, [_V, _I64] + [_V] * 10),
             "gic_drag_vjp": (C.c_int, [_V, _I64] + [_V] * 10),
             "gic_integrate_vjp": (C.c_int, [_V, _I64] + [_V] * 5),
@@ -97,6 +102,12 @@ def make_params(cfg: dict, precision: str = "fp32", r_max: float = None) -> gic_
     p.r_max = float(cfg["cell"] / 2.0 if r_max is None else r_max)
     p.walls = int(cfg["walls"])
     p.precision = GIC_FP32 if precision == "fp32" else GIC_FP64
+    # remaining interphase forces: off unless the workload sets them
+    p.rho_f = float(cfg.get("rho_f", 0.0))
+    p.c_quad = float(cfg.get("c_quad", 0.0))
+    p.f_unit = float(cfg.get("f_unit", 1.0))
+    p.drag_model = int(cfg.get("drag_model", 0))
+    p.vmass = int(cfg.get("vmass", 0))
     return p
 
 
@@ -285,6 +296,54 @@ def gic_step(ctx, cur, nxt, u, alpha_fx, mom_fx, scratch):
                           _ptr(s.get("alpha_f"), ctx.real, n), _stream()), "gic_step")
 
 
+# ---- remaining interphase forces and the sand step ------------------------------
+
+def gic_gather_g2p_fluid(ctx, order, x, v, r, id_, x_out, v_out, r_out, id_out, u, alpha_fx, cell_begin, cell_end,
+                         f_fluid, grad_p=None, acc_f=None):
+    n = x.shape[-1]
+    f64 = torch.float64
+    _check(lib().gic_gather_g2p_fluid(ctx.handle, n, _ptr(order, torch.int32, n), _ptr(x, f64, 3 * n),
+                                      _ptr(v, f64, 3 * n), _ptr(r, f64, n), _ptr(id_, torch.int32, n),
+                                      _ptr(x_out, f64, 3 * n), _ptr(v_out, f64, 3 * n), _ptr(r_out, f64, n),
+                                      _ptr(id_out, torch.int32, n), _ptr(u, ctx.real, 3 * ctx.G),
+                                      _ptr(alpha_fx, torch.int64, ctx.G), _ptr(grad_p, ctx.real, 3 * ctx.G),
+                                      _ptr(acc_f, ctx.real, 3 * ctx.G), _ptr(cell_begin, torch.int32, ctx.K),
+                                      _ptr(cell_end, torch.int32, ctx.K), _ptr(f_fluid, ctx.real, 3 * n, "f_fluid"),
+                                      _stream()), "gic_gather_g2p_fluid")
+
+
+def gic_exchange_p2g(ctx, x, r, f_contact, f_fluid, cell_begin, cell_end, weight, fs_fx):
+    n = x.shape[-1]
+    f64 = torch.float64
+    _check(lib().gic_exchange_p2g(ctx.handle, n, _ptr(x, f64, 3 * n), _ptr(r, f64, n),
+                                  _ptr(f_contact, ctx.real, 3 * n), _ptr(f_fluid, ctx.real, 3 * n),
+                                  _ptr(cell_begin, torch.int32, ctx.K), _ptr(cell_end, torch.int32, ctx.K),
+                                  float(weight), _ptr(fs_fx, torch.int64, 3 * ctx.G), _stream()), "gic_exchange_p2g")
+
+
+def gic_sand_step(ctx, a, b, Dt, u, alpha_fx, mom_fx, scratch, grad_p=None, acc_f=None, fs_fx=None):
+    """One sand step of length Dt in ceil(Dt / dt) sub-steps; a, b: dicts of
+    x, v, r, id tensors (the state starts in a).  Returns (N, which): the
+    number of sub-steps and 0 if the state ends in a, 1 if in b.  scratch:
+    key, order, cell_begin, cell_end, f_contact, f_drag (the fluid force)."""
+    n = a["x"].shape[-1]
+    f64 = torch.float64
+    s = scratch
+    N = C.c_int32(0)
+    which = C.c_int32(0)
+    _check(lib().gic_sand_step(ctx.handle, n, float(Dt), _ptr(a["x"], f64, 3 * n), _ptr(a["v"], f64, 3 * n),
+                               _ptr(a["r"], f64, n), _ptr(a.get("id"), torch.int32, n), _ptr(b["x"], f64, 3 * n),
+                               _ptr(b["v"], f64, 3 * n), _ptr(b["r"], f64, n), _ptr(b.get("id"), torch.int32, n),
+                               _ptr(u, ctx.real, 3 * ctx.G), _ptr(grad_p, ctx.real, 3 * ctx.G),
+                               _ptr(acc_f, ctx.real, 3 * ctx.G), _ptr(alpha_fx, torch.int64, ctx.G),
+                               _ptr(mom_fx, torch.int64, 3 * ctx.G), _ptr(fs_fx, torch.int64, 3 * ctx.G),
+                               _ptr(s["key"], torch.int32, n), _ptr(s["order"], torch.int32, n),
+                               _ptr(s["cell_begin"], torch.int32, ctx.K), _ptr(s["cell_end"], torch.int32, ctx.K),
+                               _ptr(s["f_contact"], ctx.real, 3 * n), _ptr(s["f_drag"], ctx.real, 3 * n),
+                               C.byref(N), C.byref(which), _stream()), "gic_sand_step")
+    return int(N.value), int(which.value)
+
+
 # ---- adjoint form (double) ----------------------------------------------------
 
 def gic_contact_forces_vjp(ctx, x, v, r, cell_begin, cell_end, g_f, g_x, g_v, g_mu):
@@ -390,6 +449,16 @@ class Simulator:
         for _ in range(k):
             gic_step(self.ctx, self.cur, self.nxt, self.u, self.alpha, self.mom, self.step_scratch)
             self.cur, self.nxt = self.nxt, self.cur
+
+    def sand_step(self, Dt, grad_p=None, acc_f=None, fs=None):
+        """One sand step of length Dt (Alg. 2) with frozen fluid fields;
+        grad_p, acc_f: (3G) real tensors or None; fs: (3G) int64 exchange grid
+        (accumulated) or None.  Returns the number of sub-steps."""
+        N, which = gic_sand_step(self.ctx, self.cur, self.nxt, Dt, self.u, self.alpha, self.mom, self.step_scratch,
+                                 grad_p=grad_p, acc_f=acc_f, fs_fx=fs)
+        if which:
+            self.cur, self.nxt = self.nxt, self.cur
+        return N
 
     def state_in_input_order(self):
         """(x, v) as (3, n) float64 CPU arrays indexed by input granule."""
