@@ -34,6 +34,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-coupled", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (read 1 GiB, write 1 GiB) three times, "
@@ -58,6 +59,18 @@ def stage_bytes(stage, n, nodes, real_bytes):
     }[stage]
     grid = {"gather_g2p_drag": 3 * B + 8, "integrate_p2g": 8 + 24}.get(stage, 0)  # node reads / writes
     return per * n + grid * nodes
+
+
+# The remaining interphase forces: the fluid gather also reads grad p and the
+# fluid acceleration at each node; the exchange deposit reads x, r, F_c, F_fluid
+# per granule and adds three int64 components per touched node.
+def coupled_bytes(stage, n, nodes, real_bytes):
+    B = real_bytes
+    if stage == "gather_g2p_fluid":
+        return (4 + 2 * (24 + 24 + 8 + 4) + 3 * B) * n + (3 * B + 8 + 6 * B) * nodes
+    if stage == "exchange_p2g":
+        return (24 + 8 + 3 * B + 3 * B) * n + 24 * nodes
+    return stage_bytes(stage, n, nodes, real_bytes)
 
 
 def time_steps(sim, steps, warmup):
@@ -206,6 +219,84 @@ def stored_traffic(stage, workload):
         return None
 
 
+def time_coupled(d, substeps=4, sand_steps=8):
+    """The workload with the remaining interphase forces on (Sec. 3.3 Eq.
+    5a-5c, Sec. 5.2 Eq. 9) in sand steps of `substeps` sub-steps (Alg. 2),
+    FP32 form: a hydrostatic pressure gradient rho_f g plus a seeded
+    perturbation, a seeded fluid-acceleration field, virtual mass and the
+    exchange-momentum deposit.  Whole sand steps timed with HIP events, then
+    each kernel of a sub-step one C-ABI call at a time."""
+    import torch
+    from paper_2504_00745_amd import gic
+    cfg = dict(d["params"], rho_f=1000.0, vmass=1, f_unit=1e-8)
+    n = d["x"].shape[1]
+    Gn = int(np.prod(cfg["n"]))
+    rng = np.random.Generator(np.random.PCG64(12))
+    gp = (np.array(cfg["g"])[:, None] * 1000.0 + rng.normal(0.0, 50.0, (3, Gn))).reshape(-1)
+    af = rng.normal(0.0, 0.1, 3 * Gn)
+    sim = gic.Simulator(cfg, d["x"], d["v"], d["r"], d["u"], "fp32", r_max=float(d["r"].max()))
+    GP = torch.as_tensor(gp, dtype=torch.float32, device="cuda")
+    AF = torch.as_tensor(af, dtype=torch.float32, device="cuda")
+    FS = torch.zeros(3 * Gn, dtype=torch.int64, device="cuda")
+    Dt = substeps * cfg["dt"]
+    sim.sand_step(Dt, grad_p=GP, acc_f=AF, fs=FS)  # warm-up
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    N = 0
+    for _ in range(sand_steps):
+        N += sim.sand_step(Dt, grad_p=GP, acc_f=AF, fs=FS)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3
+    code, idx = sim.ctx.error()
+    # per kernel, on the current state (sorted), all calls enqueued before one synchronisation
+    ctx, s = sim.ctx, sim.scratch
+    names = ["sort", "gather_g2p_fluid", "contact", "exchange_p2g", "integrate_p2g"]
+    acc = {k: 0.0 for k in names}
+    reps = 4
+    evs = []
+    for _ in range(reps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
+        cur, nxt = sim.cur, sim.nxt
+        ev[0].record()
+        gic.gic_sort_cells(ctx, cur["x"], s["key"], s["order"], s["cell_begin"], s["cell_end"])
+        ev[1].record()
+        gic.gic_gather_g2p_fluid(ctx, s["order"], cur["x"], cur["v"], cur["r"], cur["id"], nxt["x"], nxt["v"],
+                                 nxt["r"], nxt["id"], sim.u, sim.alpha, s["cell_begin"], s["cell_end"], s["f_drag"],
+                                 grad_p=GP, acc_f=AF)
+        ev[2].record()
+        gic.gic_contact_forces(ctx, nxt["x"], nxt["v"], nxt["r"], s["cell_begin"], s["cell_end"], s["f_contact"])
+        ev[3].record()
+        gic.gic_exchange_p2g(ctx, nxt["x"], nxt["r"], s["f_contact"], s["f_drag"], s["cell_begin"], s["cell_end"],
+                             1.0 / substeps, FS)
+        ev[4].record()
+        sim.alpha.zero_()
+        sim.mom.zero_()
+        ev_p = torch.cuda.Event(enable_timing=True)
+        ev_p.record()
+        gic.gic_integrate_p2g(ctx, nxt["x"], nxt["v"], nxt["r"], s["f_contact"], s["f_drag"], s["cell_begin"],
+                              s["cell_end"], sim.alpha, sim.mom, accumulate=True)
+        ev[5].record()
+        sim.cur, sim.nxt = nxt, cur
+        evs.append((ev, ev_p))
+    torch.cuda.synchronize()
+    for ev, ev_p in evs:
+        for i, k in enumerate(names[:4]):
+            acc[k] += ev[i].elapsed_time(ev[i + 1]) / 1e3 / reps
+        acc["integrate_p2g"] += ev_p.elapsed_time(ev[5]) / 1e3 / reps
+    nodes = touched_nodes(sim)
+    xb = coupled_bytes("exchange_p2g", n, nodes, 4)
+    ach = xb / acc["exchange_p2g"] / 1e9
+    return {"workload": f"same bed with grad p, fluid acceleration, virtual mass (rho_f = 1000) and the "
+                        f"exchange deposit, sand steps of {substeps} sub-steps, FP32",
+            "ms_per_substep": t / N * 1e3, "value": n * N / t, "unit": "granule-substeps/s",
+            "substeps": N, "stages_ms": {k: round(v * 1e3, 4) for k, v in acc.items()},
+            "exchange_roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": ach / HBM_PEAK_GBS, "algorithmic_bytes": xb},
+            "error": [code, idx]}
+
+
 def touched_nodes(sim):
     import torch
     return int((sim.alpha != 0).sum().item())
@@ -298,6 +389,10 @@ def main():
         line["fp64_value"] = n * a.steps / r64["t"]
         line["fp32_over_fp64"] = line["value"] / line["fp64_value"]
         line["fp64_stages_ms"] = {k: round(v * 1e3, 4) for k, v in r64["stages"].items()}
+    if not a.no_coupled:
+        log("[bench] coupled: remaining interphase forces and exchange, sand steps of 4 sub-steps")
+        line["coupled"] = time_coupled(d)
+        torch.cuda.empty_cache()
     if not a.no_adjoint:
         log("[bench] adjoint: forward and backward of the c4 rollout")
         line["bwd_fwd"] = time_adjoint()

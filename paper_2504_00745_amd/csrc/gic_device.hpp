@@ -200,8 +200,15 @@ __device__ inline int64_t rint_i64(double v)
 // alpha_max) over the 27 stencil nodes, weights and sums in T.  fetch(i, j,
 // k, u[3], al) supplies node (i, j, k)'s velocity and its clamped solid
 // fraction; the same summation order serves every caller.
-template <typename T, typename Fetch>
-__device__ inline void g2p_sample_st(const Stencil &s, Fetch &&fetch, T uat[3], T &af)
+// extra(w) runs after each fetch with that node's weight (further channels
+// sampled with the same weights, e.g. by the fluid gather).
+struct NoExtra {
+    template <typename T>
+    __device__ void operator()(T) const {}
+};
+
+template <typename T, typename Fetch, typename Extra = NoExtra>
+__device__ inline void g2p_sample_st(const Stencil &s, Fetch &&fetch, T uat[3], T &af, Extra &&extra = Extra())
 {
     T acc[3] = {(T)0, (T)0, (T)0};
     T as = (T)0;
@@ -217,6 +224,7 @@ __device__ inline void g2p_sample_st(const Stencil &s, Fetch &&fetch, T uat[3], 
                 acc[1] += w * u[1];
                 acc[2] += w * u[2];
                 as += w * al;
+                extra(w);
             }
         }
     uat[0] = acc[0];

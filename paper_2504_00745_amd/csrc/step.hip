@@ -90,9 +90,12 @@ __global__ void __launch_bounds__(256) k_gather_g2p_drag(DevParams P, int64_t n,
 // acceleration (fa) when given, and each granule's fluid force is the drag
 // of the drag model, plus -V grad p at the granule, plus (rho_f V / 2) a_f
 // under virtual mass (the a_s part of the virtual-mass force sits in the
-// effective mass of the integrator).  The interpolation of u and alpha is
-// the same function as in the drag-only kernel; gp and fa use the same
-// weights in the same order.
+// effective mass of the integrator).  Both extra terms are V times the
+// interpolation of one node field, e = -grad p + (rho_f / 2) a_f, so the
+// tile holds e (three channels) instead of grad p and a_f (six).  The
+// interpolation of u and alpha is the same function as in the drag-only
+// kernel; e is sampled in the same pass over the 27 nodes with the same
+// weights.
 template <typename T>
 __global__ void __launch_bounds__(256) k_gather_g2p_fluid(DevParams P, int64_t n, const int32_t *__restrict__ bl,
                                                           const int32_t *__restrict__ bcnt,
@@ -113,8 +116,15 @@ __global__ void __launch_bounds__(256) k_gather_g2p_fluid(DevParams P, int64_t n
     clip_range(n, gb, ge);
     if (ge <= gb) return;
     const bool vm_acc = P.vmass && fa != nullptr;
+    const T half_rho_f = (T)P.half_rho_f;
+    // e = -grad p + (rho_f / 2) a_f at grid node idx, component c
+    auto extra_field = [&](int c, int64_t idx) {
+        T e = gp ? -gp[c * P.G + idx] : (T)0;
+        if (vm_acc) e = e + half_rho_f * fa[c * P.G + idx];
+        return e;
+    };
     const int E = P.tile, E3 = E * E * E;
-    T *su = reinterpret_cast<T *>(smem_d);  // [10][E3]: u_x, u_y, u_z, clamped alpha, grad p (3), a_f (3)
+    T *su = reinterpret_cast<T *>(smem_d);  // [7][E3]: u_x, u_y, u_z, clamped alpha, e (3)
     int32_t o[3];
     tile_origin(P, b, o);
     const int64_t G = P.G;
@@ -124,10 +134,7 @@ __global__ void __launch_bounds__(256) k_gather_g2p_fluid(DevParams P, int64_t n
         const int64_t idx = node_index(P, i, j, l);
         for (int c = 0; c < 3; ++c) su[c * E3 + k] = u[c * G + idx];
         su[3 * E3 + k] = (T)node_alpha(P, afx[idx]);
-        for (int c = 0; c < 3; ++c) {
-            su[(4 + c) * E3 + k] = gp ? gp[c * G + idx] : (T)0;
-            su[(7 + c) * E3 + k] = vm_acc ? fa[c * G + idx] : (T)0;
-        }
+        for (int c = 0; c < 3; ++c) su[(4 + c) * E3 + k] = extra_field(c, idx);
     }
     __syncthreads();
     // node (i, j, k) as a tile slot, or -1 outside the tile (a granule whose
@@ -151,50 +158,33 @@ __global__ void __launch_bounds__(256) k_gather_g2p_fluid(DevParams P, int64_t n
         Stencil st;
         stencil_of(P, xa, st);
         T ua[3], a;
+        T ea[3] = {(T)0, (T)0, (T)0};
+        int t = -1;          // tile slot of the node just fetched, -1 outside the tile
+        int64_t gidx = 0;    // its grid index when outside
+        const bool extra = gp || vm_acc;
         g2p_sample_st<T>(st, [&](int32_t i, int32_t j, int32_t k, T uu[3], T &al) {
-            const int t = slot(i, j, k);
+            t = slot(i, j, k);
             if (t >= 0) {
                 uu[0] = su[t];
                 uu[1] = su[E3 + t];
                 uu[2] = su[2 * E3 + t];
                 al = su[3 * E3 + t];
             } else {
-                const int64_t idx = node_index(P, i, j, k);
-                uu[0] = u[idx];
-                uu[1] = u[G + idx];
-                uu[2] = u[2 * G + idx];
-                al = (T)node_alpha(P, afx[idx]);
+                gidx = node_index(P, i, j, k);
+                uu[0] = u[gidx];
+                uu[1] = u[G + gidx];
+                uu[2] = u[2 * G + gidx];
+                al = (T)node_alpha(P, afx[gidx]);
             }
-        }, ua, a);
+        }, ua, a, [&](T w) {
+            if (!extra) return;
+            for (int c = 0; c < 3; ++c) ea[c] += w * (t >= 0 ? su[(4 + c) * E3 + t] : extra_field(c, gidx));
+        });
         T f[3];
         drag_one<T>(P, rq, va, ua, a, f);
-        if (gp || vm_acc) {
-            T gpa[3] = {(T)0, (T)0, (T)0}, faa[3] = {(T)0, (T)0, (T)0};
-#pragma unroll 1
-            for (int cz = 0; cz < 3; ++cz)
-                for (int cy = 0; cy < 3; ++cy) {
-                    const double wyz = st.w[1][cy] * st.w[2][cz];
-                    for (int cx = 0; cx < 3; ++cx) {
-                        const T w = (T)(st.w[0][cx] * wyz);
-                        const int32_t i = st.node[0][cx], j = st.node[1][cy], k = st.node[2][cz];
-                        const int t = slot(i, j, k);
-                        const int64_t idx = t >= 0 ? 0 : node_index(P, i, j, k);
-                        for (int c = 0; c < 3; ++c) {
-                            const T g = t >= 0 ? su[(4 + c) * E3 + t] : (gp ? gp[c * G + idx] : (T)0);
-                            const T h = t >= 0 ? su[(7 + c) * E3 + t] : (vm_acc ? fa[c * G + idx] : (T)0);
-                            gpa[c] += w * g;
-                            faa[c] += w * h;
-                        }
-                    }
-                }
-            const double V = volume_of(rq);
-            const T tV = (T)V, thv = (T)(P.half_rho_f * V);
-            for (int c = 0; c < 3; ++c) {
-                T fc = f[c];
-                if (gp) fc = fc - tV * gpa[c];
-                if (vm_acc) fc = fc + thv * faa[c];
-                f[c] = fc;
-            }
+        if (extra) {
+            const T tV = (T)volume_of(rq);
+            for (int c = 0; c < 3; ++c) f[c] = f[c] + tV * ea[c];
         }
         for (int c = 0; c < 3; ++c) Ff[c * n + q] = f[c];
     }
@@ -212,7 +202,7 @@ hipError_t launch_gather_g2p_fluid(const DevParams &P, int64_t n, int64_t K, con
     if (n == 0) return hipSuccess;
     const int64_t bricks = K / kBrickCells;
     const int E = P.tile;
-    const size_t lds = sizeof(T) * 10 * (size_t)E * E * E;
+    const size_t lds = sizeof(T) * 7 * (size_t)E * E * E;
     k_gather_g2p_fluid<T><<<brick_grid(bricks), 256, lds, s>>>(P, n, B.list, B.count, order, x, v, r, id, xo, vo, ro,
                                                                ido, u, afx, gp, fa, cb, ce, Ff);
     return hipGetLastError();
