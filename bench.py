@@ -183,6 +183,8 @@ TRAFFIC_SOURCES = {
     "contact": ["contact.hip", "gic_device.hpp", "gic_launch.hpp"],
     "integrate_p2g": ["transfer.hip", "gic_device.hpp", "gic_launch.hpp"],
     "gather_g2p_drag": ["step.hip", "gic_device.hpp", "gic_launch.hpp"],
+    "gather_g2p_fluid": ["step.hip", "gic_device.hpp", "gic_launch.hpp"],
+    "exchange_p2g": ["transfer.hip", "gic_device.hpp", "gic_launch.hpp"],
 }
 
 
@@ -219,7 +221,7 @@ def stored_traffic(stage, workload):
         return None
 
 
-def time_coupled(d, substeps=4, sand_steps=8):
+def time_coupled(d, wl_name, substeps=4, sand_steps=8):
     """The workload with the remaining interphase forces on (Sec. 3.3 Eq.
     5a-5c, Sec. 5.2 Eq. 9) in sand steps of `substeps` sub-steps (Alg. 2),
     FP32 form: a hydrostatic pressure gradient rho_f g plus a seeded
@@ -293,7 +295,8 @@ def time_coupled(d, substeps=4, sand_steps=8):
             "ms_per_substep": t / N * 1e3, "value": n * N / t, "unit": "granule-substeps/s",
             "substeps": N, "stages_ms": {k: round(v * 1e3, 4) for k, v in acc.items()},
             "exchange_roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                  "frac": ach / HBM_PEAK_GBS, "algorithmic_bytes": xb},
+                                  "frac": ach / HBM_PEAK_GBS, "algorithmic_bytes": xb,
+                                  "traffic": stored_traffic("exchange_p2g", wl_name)},
             "error": [code, idx]}
 
 
@@ -391,7 +394,7 @@ def main():
         line["fp64_stages_ms"] = {k: round(v * 1e3, 4) for k, v in r64["stages"].items()}
     if not a.no_coupled:
         log("[bench] coupled: remaining interphase forces and exchange, sand steps of 4 sub-steps")
-        line["coupled"] = time_coupled(d)
+        line["coupled"] = time_coupled(d, a.workload)
         torch.cuda.empty_cache()
     if not a.no_adjoint:
         log("[bench] adjoint: forward and backward of the c4 rollout")

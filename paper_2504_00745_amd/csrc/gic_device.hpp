@@ -212,14 +212,18 @@ __device__ inline void g2p_sample_st(const Stencil &s, Fetch &&fetch, T uat[3], 
 {
     T acc[3] = {(T)0, (T)0, (T)0};
     T as = (T)0;
+    // the z-planes' weights and nodes rotate through registers: a stencil
+    // indexed with the loop counter would be placed in scratch memory
+    double wz = s.w[2][0], wz1 = s.w[2][1], wz2 = s.w[2][2];
+    int32_t nz = s.node[2][0], nz1 = s.node[2][1], nz2 = s.node[2][2];
 #pragma unroll 1
-    for (int cz = 0; cz < 3; ++cz)  // one node plane at a time keeps few loads in flight per lane
+    for (int cz = 0; cz < 3; ++cz) {  // one node plane at a time keeps few loads in flight per lane
         for (int cy = 0; cy < 3; ++cy) {
-            const double wyz = s.w[1][cy] * s.w[2][cz];
+            const double wyz = s.w[1][cy] * wz;
             for (int cx = 0; cx < 3; ++cx) {
                 const T w = (T)(s.w[0][cx] * wyz);
                 T u[3], al;
-                fetch(s.node[0][cx], s.node[1][cy], s.node[2][cz], u, al);
+                fetch(s.node[0][cx], s.node[1][cy], nz, u, al);
                 acc[0] += w * u[0];
                 acc[1] += w * u[1];
                 acc[2] += w * u[2];
@@ -227,6 +231,11 @@ __device__ inline void g2p_sample_st(const Stencil &s, Fetch &&fetch, T uat[3], 
                 extra(w);
             }
         }
+        wz = wz1;
+        wz1 = wz2;
+        nz = nz1;
+        nz1 = nz2;
+    }
     uat[0] = acc[0];
     uat[1] = acc[1];
     uat[2] = acc[2];

@@ -32,13 +32,12 @@ __global__ void __launch_bounds__(256) k_integrate(DevParams P, int64_t n, const
     double xq[3] = {x[q], x[n + q], x[2 * n + q]};
     double vq[3] = {v[q], v[n + q], v[2 * n + q]};
     const T fc[3] = {Fc[q], Fc[n + q], Fc[2 * n + q]};
-    T fd[3] = {(T)0, (T)0, (T)0};
     if (Fd) {
-        fd[0] = Fd[q];
-        fd[1] = Fd[n + q];
-        fd[2] = Fd[2 * n + q];
+        const T fd[3] = {Fd[q], Fd[n + q], Fd[2 * n + q]};
+        integrate_one<T>(P, r[q], fc, fd, xq, vq);
+    } else {
+        integrate_one<T>(P, r[q], fc, (const T *)nullptr, xq, vq);
     }
-    integrate_one<T>(P, r[q], fc, Fd ? fd : nullptr, xq, vq);
     for (int a = 0; a < 3; ++a) {
         x[a * n + q] = xq[a];
         v[a * n + q] = vq[a];

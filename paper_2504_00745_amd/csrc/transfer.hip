@@ -128,7 +128,10 @@ __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_e
     for (int k = tid; k < NCH * E3; k += kP2GThreads) tile[k] = 0ull;
     int32_t o[3];
     tile_origin(P, b, o);
-    unsigned long long *glob[4] = {alpha, mom, mom ? mom + P.G : nullptr, mom ? mom + 2 * P.G : nullptr};
+    // grid plane of channel c (computed, not an array indexed by c, which
+    // would live in scratch memory): alpha, then the momentum (or exchange)
+    // planes that follow mom
+    auto glob_of = [&](int c) { return c == 0 ? alpha : mom + (int64_t)(c - 1) * P.G; };
     for (int64_t b0 = beg; b0 < end; b0 += batch) {
         const int m = (int)(end - b0 < batch ? end - b0 : batch);
         // ---- phase 1: per granule
@@ -284,7 +287,7 @@ __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_e
                         const bool in = inb[0][cx] && inb[1][cy] && inb[2][cz];
                         const int lidx = ((nd[2][cz] - o[2]) * E + (nd[1][cy] - o[1])) * E + (nd[0][cx] - o[0]);
                         const int64_t gidx = node_index(P, nd[0][cx], nd[1][cy], nd[2][cz]);
-                        tile_add(tl, glob[c], in, lidx, gidx, (int64_t)acc[(cz * 3 + cy) * 3 + cx]);
+                        tile_add(tl, glob_of(c), in, lidx, gidx, (int64_t)acc[(cz * 3 + cy) * 3 + cx]);
                     }
         }
         __syncthreads();
@@ -295,7 +298,7 @@ __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_e
         const int c = k / E3;
         const int l = k - c * E3;
         const int32_t ni = o[0] + l % E, nj = o[1] + (l / E) % E, nk = o[2] + l / (E * E);
-        atomicAdd(&glob[c][node_index(P, ni, nj, nk)], val);
+        atomicAdd(&glob_of(c)[node_index(P, ni, nj, nk)], val);
     }
 }
 
