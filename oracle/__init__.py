@@ -60,6 +60,19 @@ def coupling(cfg: dict) -> OrcCoupling:
     return c
 
 
+class OrcCapillary(C.Structure):
+    _fields_ = [("sigma", C.c_double), ("vbridge", C.c_double), ("sr_peak", C.c_double)]
+
+
+def capillary(cfg: dict) -> OrcCapillary:
+    """Oracle parameters of the capillary pair force (absent keys: off)."""
+    c = OrcCapillary()
+    c.sigma = float(cfg.get("sigma", 0.0))
+    c.vbridge = float(cfg.get("vbridge", 1e-4))
+    c.sr_peak = float(cfg.get("sr_peak", 0.3))
+    return c
+
+
 def lib():
     global _LIB
     if _LIB is None:
@@ -78,6 +91,7 @@ _i32 = _P(C.c_int32)
 _u32 = _P(C.c_uint32)
 _pp = _P(OrcParams)
 _pc = _P(OrcCoupling)
+_pk = _P(OrcCapillary)
 
 
 def _declare(L):
@@ -110,6 +124,12 @@ def _declare(L):
         "orc_exchange_p2g": (None, [_pp, _pc, C.c_int64, _d, _d, _d, _d, C.c_double, _i64]),
         "orc_substeps": (C.c_int32, [C.c_double, C.c_double]),
         "orc_sand_step": (C.c_int32, [_pp, _pc, C.c_int64, C.c_double, _d, _d, _d, _d, _d, _d, _i64, _i64, _i64]),
+        "orc_gamma": (C.c_double, [_pk, C.c_double]),
+        "orc_bridge": (None, [_pk, C.c_double, _d, _d]),
+        "orc_bridge_energy": (C.c_double, [_pk, C.c_double, C.c_double]),
+        "orc_fst": (C.c_double, [_pk, C.c_double, C.c_double]),
+        "orc_capillary_pair_force": (None, [_pk, _d, _d, C.c_double, C.c_double, C.c_double, C.c_double, _d]),
+        "orc_capillary_forces": (None, [_pp, _pk, C.c_int64, _d, _d, _d, _d]),
         "orc_num_threads": (C.c_int, []),
         "orc_set_num_threads": (None, [C.c_int]),
     }
@@ -415,6 +435,45 @@ def sand_step(cfg, Dt, x, v, r, u, alpha_fx, gp=None, af=None):
                             _ptr(af, C.c_double), _ptr(alpha, C.c_int64), _ptr(mom, C.c_int64),
                             _ptr(fs, C.c_int64))
     return dict(x=x, v=v, alpha=alpha, mom=mom, fs=fs, N=int(N))
+
+
+# ---- capillary (concentration-gradient) pair force, Sec. 5.4 ---------------
+
+def gamma(cfg, sr):
+    return float(lib().orc_gamma(C.byref(capillary(cfg)), float(sr)))
+
+
+def bridge(cfg, rb):
+    """(V*, d_r) of a pair of mean radius rb."""
+    V, dr = np.zeros(1), np.zeros(1)
+    lib().orc_bridge(C.byref(capillary(cfg)), float(rb), _ptr(V, C.c_double), _ptr(dr, C.c_double))
+    return float(V[0]), float(dr[0])
+
+
+def bridge_energy(cfg, rb, s):
+    return float(lib().orc_bridge_energy(C.byref(capillary(cfg)), float(rb), float(s)))
+
+
+def fst(cfg, rb, s):
+    return float(lib().orc_fst(C.byref(capillary(cfg)), float(rb), float(s)))
+
+
+def capillary_pair(cfg, xi, xj, ri, rj, sri, srj):
+    """Capillary force of j on i (3,)."""
+    F = np.zeros(3)
+    a, b = _f64(xi), _f64(xj)
+    lib().orc_capillary_pair_force(C.byref(capillary(cfg)), _ptr(a, C.c_double), _ptr(b, C.c_double), float(ri),
+                                   float(rj), float(sri), float(srj), _ptr(F, C.c_double))
+    return F
+
+
+def capillary_forces(cfg, x, r, sr):
+    """Capillary force on each granule (3,n) from every bridged pair."""
+    x, r, sr = _f64(x), _f64(r), _f64(sr)
+    F = np.zeros((3, x.shape[1]))
+    lib().orc_capillary_forces(C.byref(params(cfg)), C.byref(capillary(cfg)), x.shape[1], _ptr(x, C.c_double),
+                               _ptr(r, C.c_double), _ptr(sr, C.c_double), _ptr(F, C.c_double))
+    return F
 
 
 # ---- differentiable form (unquantised transfers) and its reverse pass -------

@@ -1313,3 +1313,127 @@ int32_t orc_sand_step(const orc_params *p, const orc_coupling *cp, int64_t n, do
     free(Ffl);
     return N;
 }
+
+/* ======================================================================== */
+/* Capillary (concentration-gradient) pair force, Sec. 5.4                   */
+/* ======================================================================== */
+/*
+ * Passages followed: Sec. 5.4, the liquid-bridge energy E = -2 pi sigma r
+ * (-s + sqrt(s^2 + 2 V* / (pi r))) cos(theta) with cos(theta) = 1, its force
+ * F^st = -2 pi sigma r ((1 + 2 V* / (pi r s^2))^(-1/2) - 1), the rupture
+ * distance d_r = V*^(1/3) + 0.1 V*^(2/3), V* = 0.01 % of the granule volume,
+ * the moisture ratio sr_i = r_i + alpha_f,i / (1 - alpha_f,i), and the
+ * symmetrised pair force F_ij = -Gamma((sr_i + sr_j) / 2) F^st (x_i - x_j) /
+ * |x_i - x_j| for 0 < s_ij < d_r, zero otherwise.
+ *
+ * Readings (recorded in the design notes):
+ *   - polydisperse pairs: r of F^st, of V* and of d_r is the pair's mean
+ *     radius (r_i + r_j) / 2 and s_ij = |x_i - x_j| - (r_i + r_j);
+ *   - d_r is evaluated as printed with lengths in metres (its second term is
+ *     negligible at granule scales);
+ *   - Gamma's control points are not printed: a piecewise quadratic Bezier
+ *     bump, Gamma(sr) = u (2 - u), u = sr / sr_peak on (0, sr_peak], and
+ *     1 - u^2, u = (sr - sr_peak) / (1 - sr_peak) on (sr_peak, 1); zero at
+ *     sr <= 0 and sr >= 1, one at sr_peak (the maximum absorption ratio);
+ *   - the moisture ratios sr_i are inputs (the wetting of Sec. 5.3 is not on
+ *     this path).
+ * The cell list finds every bridged pair when cell >= 2 r_max + d_r(r_max).
+ */
+
+typedef struct {
+    double sigma;   /* surface tension [N/m]                                  */
+    double vbridge; /* liquid-bridge volume / granule volume (1e-4)           */
+    double sr_peak; /* moisture ratio of Gamma's maximum, in (0, 1)          */
+} orc_capillary;
+
+double orc_gamma(const orc_capillary *c, double sr)
+{
+    if (!(sr > 0.0) || !(sr < 1.0)) return 0.0;
+    if (sr <= c->sr_peak) {
+        double u = sr / c->sr_peak;
+        return u * (2.0 - u);
+    }
+    double u = (sr - c->sr_peak) / (1.0 - c->sr_peak);
+    return 1.0 - u * u;
+}
+
+/* Liquid-bridge volume V* and rupture distance d_r of a pair of mean radius rb. */
+void orc_bridge(const orc_capillary *c, double rb, double *vstar, double *dr)
+{
+    double V = c->vbridge * orc_volume(rb);
+    double t = cbrt(V);
+    *vstar = V;
+    *dr = t + 0.1 * (t * t);
+}
+
+/* Bridge energy E(s) and force F^st(s) of a pair of mean radius rb. */
+double orc_bridge_energy(const orc_capillary *c, double rb, double s)
+{
+    double V, dr;
+    orc_bridge(c, rb, &V, &dr);
+    return -(2.0 * ORC_PI * c->sigma * rb) * (-s + sqrt(s * s + (2.0 * V) / (ORC_PI * rb)));
+}
+
+double orc_fst(const orc_capillary *c, double rb, double s)
+{
+    double V, dr;
+    orc_bridge(c, rb, &V, &dr);
+    double q = 1.0 + (2.0 * V) / ((ORC_PI * rb) * (s * s));
+    return -(2.0 * ORC_PI * c->sigma * rb) * (1.0 / sqrt(q) - 1.0);
+}
+
+/* Capillary force of j on i (3), zero outside 0 < s < d_r. */
+static void orc_capillary_pair(const orc_capillary *c, const double xi[3], const double xj[3], double ri,
+                               double rj, double sri, double srj, double F[3])
+{
+    F[0] = F[1] = F[2] = 0.0;
+    double dv[3] = {xi[0] - xj[0], xi[1] - xj[1], xi[2] - xj[2]};
+    double d2 = (dv[0] * dv[0] + dv[1] * dv[1]) + dv[2] * dv[2];
+    if (d2 == 0.0) return;
+    double d = sqrt(d2);
+    double s = d - (ri + rj);
+    double rb = 0.5 * (ri + rj);
+    double V, dr;
+    orc_bridge(c, rb, &V, &dr);
+    if (!(s > 0.0) || !(s < dr)) return;
+    double g = orc_gamma(c, 0.5 * (sri + srj));
+    double f = -(g * orc_fst(c, rb, s));
+    for (int a = 0; a < 3; ++a) F[a] = f * (dv[a] / d);
+}
+
+/* Force on granule i from j alone (pins and brute-force checks). */
+void orc_capillary_pair_force(const orc_capillary *c, const double *xi, const double *xj, double ri, double rj,
+                              double sri, double srj, double *F)
+{
+    orc_capillary_pair(c, xi, xj, ri, rj, sri, srj, F);
+}
+
+/* Adds the capillary force of every bridged pair to F (3n); the candidates
+ * are the 27 cells around each granule's cell. */
+void orc_capillary_forces(const orc_params *p, const orc_capillary *c, int64_t n, const double *x, const double *r,
+                          const double *sr, double *F)
+{
+    orc_cells cl;
+    orc_cells_build(p, n, x, &cl);
+    int64_t cap = 27 * orc_cells_maxocc(p, &cl) + 1;
+#pragma omp parallel
+    {
+        int64_t *cand = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap);
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            double xi[3], acc[3] = {0.0, 0.0, 0.0};
+            orc_pos(n, x, i, xi);
+            int64_t m = orc_candidates(p, n, x, &cl, i, cand);
+            for (int64_t k = 0; k < m; ++k) {
+                int64_t j = cand[k];
+                double xj[3], Fp[3];
+                orc_pos(n, x, j, xj);
+                orc_capillary_pair(c, xi, xj, r[i], r[j], sr[i], sr[j], Fp);
+                for (int a = 0; a < 3; ++a) acc[a] += Fp[a];
+            }
+            for (int a = 0; a < 3; ++a) F[a * n + i] += acc[a];
+        }
+        free(cand);
+    }
+    orc_cells_free(&cl);
+}
