@@ -107,6 +107,14 @@ typedef enum { GIC_FP64 = 0, GIC_FP32 = 1 } gic_precision;
  *                 grid (Eq. 9); 0: none.
  *   f_unit        unit of the fixed-point exchange-force grid [N] (> 0 for
  *                 gic_exchange_p2g and gic_sand_step with an exchange grid).
+ * Capillary (concentration-gradient) pair force, Sec. 5.4, applied by
+ * gic_contact_capillary_forces only:
+ *   sigma         surface tension [N/m] >= 0 (0: off).
+ *   vbridge       liquid-bridge volume as a fraction of the pair's mean
+ *                 granule volume (Sec. 5.4: 1e-4), > 0 when sigma > 0.
+ *   sr_peak       moisture ratio where the moisture curve Gamma peaks (the
+ *                 maximum absorption ratio of Sec. 5.3), in (0, 1).
+ *                 With sigma > 0, cell >= 2 r_max + d_r(r_max) is required.
  * The adjoint form (the *_vjp calls) covers drag_model 0 without virtual
  * mass and returns GIC_E_ARG otherwise. */
 typedef struct gic_params {
@@ -128,6 +136,9 @@ typedef struct gic_params {
     double f_unit;
     int32_t drag_model;
     int32_t vmass;
+    double sigma;
+    double vbridge;
+    double sr_peak;
 } gic_params;
 
 typedef struct gic_ctx gic_ctx;
@@ -192,6 +203,27 @@ gic_status gic_reorder(gic_ctx *ctx, int64_t n, const int32_t *order, const doub
 gic_status gic_contact_forces(gic_ctx *ctx, int64_t n, const double *x, const double *v, const double *r,
                               const int32_t *cell_begin, const int32_t *cell_end, void *f_contact,
                               int32_t *n_contacts, void *stream);
+
+/* ---- f3: contact plus capillary liquid-bridge forces (Sec. 5.4) ----------
+ * gic_contact_forces plus, for every pair that does not touch and whose
+ * surface gap s = d - (r_i + r_j) lies in (0, d_r), the bridge force on i
+ *     -Gamma((sr_i + sr_j) / 2) F^st(s) (x_i - x_j) / d,
+ *     F^st = 2 pi sigma rb (1 - (1 + 2 V* / (pi rb s^2))^(-1/2)),
+ * with rb = (r_i + r_j) / 2, V* = vbridge (4/3) pi rb^3, d_r = V*^(1/3) +
+ * 0.1 V*^(2/3) and Gamma the moisture curve: u (2 - u) with u = sr / sr_peak
+ * up to sr_peak, 1 - u^2 with u = (sr - sr_peak) / (1 - sr_peak) after it,
+ * 0 outside (0, 1).  The bridge force is evaluated in double and added to
+ * the granule's sum in the form's real type, in the same partner order as
+ * the contact forces.  Requires sigma > 0 (GIC_E_ARG otherwise).
+ *   sr          n real (the form's type), sorted order: moisture ratio per
+ *               granule (Sec. 5.3).
+ *   f_contact   out, 3n real: contact plus bridge force per granule [N].
+ *   n_contacts  out (optional), n: touching partners + walls (bridged
+ *               pairs are not counted). */
+gic_status gic_contact_capillary_forces(gic_ctx *ctx, int64_t n, const double *x, const double *v,
+                                        const double *r, const void *sr, const int32_t *cell_begin,
+                                        const int32_t *cell_end, void *f_contact, int32_t *n_contacts,
+                                        void *stream);
 
 /* Touching pairs (q, j) with q < j in sorted positions, for checks of the
  * neighbour search.  Writes up to cap pairs to pairs[2*k], pairs[2*k+1];

@@ -131,15 +131,6 @@ __device__ inline void pair_from(const DevParams &P, const double xi[3], const d
     acc[2] += Fp[2];
 }
 
-// Force that partner j exerts on granule q (both in sorted positions).
-template <typename T>
-__device__ inline void add_pair(const DevParams &P, int64_t n, const double *__restrict__ x,
-                                const double *__restrict__ v, const double *__restrict__ r, const double xi[3],
-                                const double vi[3], double ri, double mi, int32_t j, T acc[3])
-{
-    pair_from<T>(P, xi, vi, ri, mi, fetch_partner(n, x, v, r, j), acc);
-}
-
 // Wall forces of Eq. (1a)-(1c) with the box faces as infinite-mass partners.
 template <typename T>
 __device__ inline void add_walls(const DevParams &P, const double xi[3], const double vi[3], double ri, double mi,
@@ -164,6 +155,26 @@ __device__ inline void add_walls(const DevParams &P, const double xi[3], const d
         }
 }
 
+// Exact contact test of Sec. 3.1 against partner j (state p) and, if the
+// two touch, the pair force added to acc (returns 1 for a contact).  With
+// moisture ratios (CAP) a pair that does not touch gets the
+// capillary force of its liquid bridge instead (Sec. 5.4).
+template <typename T, bool CAP>
+__device__ inline int exact_pair(const DevParams &P, const double xi[3], const double vi[3], double ri, double mi,
+                                 int64_t q, int32_t j, const Partner &p, T sri, const T *__restrict__ sr, T acc[3])
+{
+    if (j == q) return 0;
+    const double dx[3] = {xi[0] - p.x[0], xi[1] - p.x[1], xi[2] - p.x[2]};
+    double d2;
+    if (touching(dx[0], dx[1], dx[2], ri + p.r, d2)) {
+        if (d2 == 0.0) return 0;
+        pair_from<T>(P, xi, vi, ri, mi, p, acc);
+        return 1;
+    }
+    if (CAP) capillary_pair<T>(P, dx, d2, ri, p.r, sri, sr[j], acc);
+    return 0;
+}
+
 // Contact force on granule q reading its candidates from global memory, in
 // two passes: the candidate pass runs only the double contact test and lists
 // touching partners in `plist` (kMaxPartners x 256 ints in LDS, column tid);
@@ -171,23 +182,25 @@ __device__ inline void add_walls(const DevParams &P, const double xi[3], const d
 // of a wave touch partners at different candidate positions, so evaluating
 // forces inside the candidate loop would run the expensive branch for almost
 // every candidate.
-template <typename T>
+template <typename T, bool CAP>
 __device__ inline void contact_global(const DevParams &P, int64_t n, const double *__restrict__ x,
                                       const double *__restrict__ v, const double *__restrict__ r,
                                       const int32_t *__restrict__ cb, const int32_t *__restrict__ ce, int64_t q,
-                                      int32_t *plist, int tid, T *__restrict__ F, int32_t *__restrict__ ncont,
-                                      int64_t *err)
+                                      int32_t *plist, int tid, const T *__restrict__ sr, T *__restrict__ F,
+                                      int32_t *__restrict__ ncont, int64_t *err)
 {
     const double xi[3] = {x[q], x[n + q], x[2 * n + q]};
     const double vi[3] = {v[q], v[n + q], v[2 * n + q]};
     const double ri = r[q];
     if (ri > P.r_max) raise_error(err, kErrRange, q);
     const double mi = mass_of(P, ri);
-    const double Rs = (ri + P.r_max) * P.search_scale;
+    const double reach = CAP ? P.dr_max : 0.0;  // liquid bridges reach beyond contact
+    const T sri = CAP ? sr[q] : (T)0;
+    const double Rs = (ri + P.r_max + reach) * P.search_scale;
     int32_t lo[3], hi[3];
     for (int a = 0; a < 3; ++a) search_range(P, xi[a], Rs, P.nc[a], lo[a], hi[a]);
     T acc[3] = {(T)0, (T)0, (T)0};
-    int32_t cnt = 0;
+    int32_t cnt = 0, nc = 0;
     for_each_run(P, n, lo, hi, cb, ce, [&](int32_t jb, int32_t je) {
         for (int32_t j0 = jb; j0 < je; j0 += kUnroll) {
             double cx[kUnroll], cy[kUnroll], cz[kUnroll], cr[kUnroll];
@@ -204,36 +217,26 @@ __device__ inline void contact_global(const DevParams &P, int64_t n, const doubl
                 const int32_t j = j0 + u;
                 if (j >= je || j == q) continue;
                 double d2;
-                if (!touching(xi[0] - cx[u], xi[1] - cy[u], xi[2] - cz[u], ri + cr[u], d2) || d2 == 0.0) continue;
+                if (!touching(xi[0] - cx[u], xi[1] - cy[u], xi[2] - cz[u], ri + cr[u] + reach, d2) || d2 == 0.0)
+                    continue;
                 if (cnt < kMaxPartners)
                     plist[cnt * 256 + tid] = j;
-                else
-                    add_pair<T>(P, n, x, v, r, xi, vi, ri, mi, j, acc);  // rare: long partner list
+                else  // rare: long partner list
+                    nc += exact_pair<T, CAP>(P, xi, vi, ri, mi, q, j, fetch_partner(n, x, v, r, j), sri, sr, acc);
                 ++cnt;
             }
         }
     });
     const int listed = cnt < kMaxPartners ? cnt : kMaxPartners;
-    for (int k = 0; k < listed; ++k) add_pair<T>(P, n, x, v, r, xi, vi, ri, mi, plist[k * 256 + tid], acc);
-    add_walls<T>(P, xi, vi, ri, mi, acc, cnt);
+    for (int k = 0; k < listed; ++k) {
+        const int32_t j = plist[k * 256 + tid];
+        nc += exact_pair<T, CAP>(P, xi, vi, ri, mi, q, j, fetch_partner(n, x, v, r, j), sri, sr, acc);
+    }
+    add_walls<T>(P, xi, vi, ri, mi, acc, nc);
     F[q] = acc[0];
     F[n + q] = acc[1];
     F[2 * n + q] = acc[2];
-    if (ncont) ncont[q] = cnt;
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) k_contact(DevParams P, int64_t n, int64_t nblk, const double *__restrict__ x,
-                                                 const double *__restrict__ v, const double *__restrict__ r,
-                                                 const int32_t *__restrict__ cb, const int32_t *__restrict__ ce,
-                                                 T *__restrict__ F, int32_t *__restrict__ ncont, int64_t *err)
-{
-    __shared__ int32_t plist[kMaxPartners * 256];
-    const int64_t lb = xcd_block(nblk);
-    if (lb < 0) return;
-    const int64_t q = lb * 256 + threadIdx.x;
-    if (q >= n) return;
-    contact_global<T>(P, n, x, v, r, cb, ce, q, plist, threadIdx.x, F, ncont, err);
+    if (ncont) ncont[q] = nc;
 }
 
 // ---------------------------------------------------------------------------
@@ -280,26 +283,13 @@ __device__ inline bool near_slot(float4 p, float mx, float my, float mz, float t
     return fmaf(mx, p.x, fmaf(my, p.y, fmaf(mz, p.z, p.w))) < thr;
 }
 
-// Exact contact test of Sec. 3.1 against partner j (state p) and, if the
-// two touch, the pair force added to acc.  Returns 1 for a contact.
-template <typename T>
-__device__ inline int exact_pair(const DevParams &P, const double xi[3], const double vi[3], double ri, double mi,
-                                 int64_t q, int32_t j, const Partner &p, T acc[3])
-{
-    if (j == q) return 0;
-    double d2;
-    if (!touching(xi[0] - p.x[0], xi[1] - p.x[1], xi[2] - p.x[2], ri + p.r, d2) || d2 == 0.0) return 0;
-    pair_from<T>(P, xi, vi, ri, mi, p, acc);
-    return 1;
-}
-
-template <typename T>
+template <typename T, bool CAP>
 __global__ void __launch_bounds__(256) k_contact_lds(DevParams P, int64_t n, const int32_t *__restrict__ bl,
                                                      const int32_t *__restrict__ bcnt, int cap,
                                                      const double *__restrict__ x, const double *__restrict__ v,
                                                      const double *__restrict__ r, const int32_t *__restrict__ cb,
-                                                     const int32_t *__restrict__ ce, T *__restrict__ F,
-                                                     int32_t *__restrict__ ncont, int64_t *err)
+                                                     const int32_t *__restrict__ ce, const T *__restrict__ sr,
+                                                     T *__restrict__ F, int32_t *__restrict__ ncont, int64_t *err)
 {
     extern __shared__ float4 smem4[];
     float4 *spos = smem4;                                        // [cap + kCand] (p, Q), see above
@@ -356,13 +346,17 @@ __global__ void __launch_bounds__(256) k_contact_lds(DevParams P, int64_t n, con
     if (H > cap) {  // shell too large for LDS: global candidate path for this brick
         __syncthreads();  // every thread has read s_wave
         int32_t *glist = reinterpret_cast<int32_t *>(smem4);  // the slot arrays are unused on this path
-        for (int64_t q = gb + tid; q < ge; q += 256) contact_global<T>(P, n, x, v, r, cb, ce, q, glist, tid, F, ncont, err);
+        for (int64_t q = gb + tid; q < ge; q += 256)
+            contact_global<T, CAP>(P, n, x, v, r, cb, ce, q, glist, tid, sr, F, ncont, err);
         return;
     }
     // ---- slot -> shell cell map (pads take their cell's number too)
     if (tid < kHaloCells)
         for (int32_t k = first; k < first + slots; ++k) scell[k] = (uint8_t)tid;
     __syncthreads();
+    // with liquid bridges the candidate pass looks d_r further: each radius
+    // grows by d_r / 2 in Q and b_i, so r_i + r_j grows by d_r
+    const float hreach = CAP ? (float)(0.5 * P.dr_max) : 0.0f;
     // ---- copy the shell's granules, relative to the centre, in single precision.
     // H <= cap < kCopyRounds * 256: all loads of a thread are issued before
     // any of them is used, so they are in flight together.
@@ -394,7 +388,7 @@ __global__ void __launch_bounds__(256) k_contact_lds(DevParams P, int64_t n, con
             float4 p;
             if (real[it]) {
                 const float px = (float)(gx[it] - o[0]), py = (float)(gy[it] - o[1]), pz = (float)(gz[it] - o[2]);
-                const float rg = (float)gr[it];
+                const float rg = (float)gr[it] + hreach;
                 p = make_float4(px, py, pz, ((px * px + py * py) + pz * pz) - 2.0f * (rg * rg));
             } else {
                 const float nan = __builtin_nanf("");
@@ -428,10 +422,10 @@ __global__ void __launch_bounds__(256) k_contact_lds(DevParams P, int64_t n, con
             ri = r[q];
             if (ri > P.r_max) raise_error(err, kErrRange, q);
             const float ax = (float)(xi[0] - o[0]), ay = (float)(xi[1] - o[1]), az = (float)(xi[2] - o[2]);
-            const float rf = (float)ri;
+            const float rf = (float)ri + hreach;
             const float thr = M - (((ax * ax + ay * ay) + az * az) - 2.0f * (rf * rf));
             const float mx = -2.0f * ax, my = -2.0f * ay, mz = -2.0f * az;
-            const double Rs = (ri + P.r_max) * P.search_scale;
+            const double Rs = (ri + P.r_max + (CAP ? P.dr_max : 0.0)) * P.search_scale;
             int32_t lo[3], hi[3], ca[3];
             for (int a = 0; a < 3; ++a) {
                 ca[a] = cell_coord(xi[a], P.inv_cell, P.nc[a]) - c0[a];  // in [1, 4]: q lies in the brick
@@ -484,6 +478,7 @@ __global__ void __launch_bounds__(256) k_contact_lds(DevParams P, int64_t n, con
                 vi[1] = v[n + q];
                 vi[2] = v[2 * n + q];
                 mi = mass_of(P, ri);
+                const T sri = CAP ? sr[q] : (T)0;
                 const int listed = cnt < kLdsPartners ? cnt : kLdsPartners;
                 auto global_of = [&](int k) { const int c = scell[k]; return cgb[c] + (k - clo[c]); };
                 for (int i = 0; i < listed; i += 2) {
@@ -493,8 +488,8 @@ __global__ void __launch_bounds__(256) k_contact_lds(DevParams P, int64_t n, con
                     const int32_t j1 = two ? global_of(plist[(i + 1) * 256 + tid]) : j0;
                     const Partner p0 = fetch_partner(n, x, v, r, j0);
                     const Partner p1 = fetch_partner(n, x, v, r, j1);
-                    nc += exact_pair<T>(P, xi, vi, ri, mi, q, j0, p0, acc);
-                    if (two) nc += exact_pair<T>(P, xi, vi, ri, mi, q, j1, p1, acc);
+                    nc += exact_pair<T, CAP>(P, xi, vi, ri, mi, q, j0, p0, sri, sr, acc);
+                    if (two) nc += exact_pair<T, CAP>(P, xi, vi, ri, mi, q, j1, p1, sri, sr, acc);
                 }
                 if (cnt > kLdsPartners) {
                     // more candidates than listed: walk this lane's rows again for the rest
@@ -505,7 +500,8 @@ __global__ void __launch_bounds__(256) k_contact_lds(DevParams P, int64_t n, con
                             if (k == kself || !near_slot(spos[k], mx, my, mz, thr)) continue;
                             if (seen++ < kLdsPartners) continue;
                             const int32_t j = global_of(k);
-                            nc += exact_pair<T>(P, xi, vi, ri, mi, q, j, fetch_partner(n, x, v, r, j), acc);
+                            nc += exact_pair<T, CAP>(P, xi, vi, ri, mi, q, j, fetch_partner(n, x, v, r, j), sri, sr,
+                                                acc);
                         }
                     });
                 }
@@ -569,23 +565,27 @@ static size_t contact_lds_bytes(int cap)
 
 template <typename T>
 hipError_t launch_contact(const DevParams &P, int64_t n, const double *x, const double *v, const double *r,
-                          const int32_t *cb, const int32_t *ce, const BrickList &B, T *F, int32_t *ncont,
-                          int64_t *err, hipStream_t s)
+                          const int32_t *cb, const int32_t *ce, const BrickList &B, const T *sr, T *F,
+                          int32_t *ncont, int64_t *err, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     const int64_t nbricks = (int64_t)P.nb[0] * P.nb[1] * P.nb[2];
     const int cap = 1948;  // shell slots held in LDS: 40,908 bytes, four workgroups per CU
-    k_contact_lds<T><<<brick_grid(nbricks), 256, contact_lds_bytes(cap), s>>>(P, n, B.list, B.count, cap, x, v, r, cb,
-                                                                            ce, F, ncont, err);
+    if (sr)
+        k_contact_lds<T, true><<<brick_grid(nbricks), 256, contact_lds_bytes(cap), s>>>(P, n, B.list, B.count, cap, x,
+                                                                                       v, r, cb, ce, sr, F, ncont, err);
+    else
+        k_contact_lds<T, false><<<brick_grid(nbricks), 256, contact_lds_bytes(cap), s>>>(
+            P, n, B.list, B.count, cap, x, v, r, cb, ce, sr, F, ncont, err);
     return hipGetLastError();
 }
 
 template hipError_t launch_contact<float>(const DevParams &, int64_t, const double *, const double *,
                                           const double *, const int32_t *, const int32_t *, const BrickList &,
-                                          float *, int32_t *, int64_t *, hipStream_t);
+                                          const float *, float *, int32_t *, int64_t *, hipStream_t);
 template hipError_t launch_contact<double>(const DevParams &, int64_t, const double *, const double *,
                                            const double *, const int32_t *, const int32_t *, const BrickList &,
-                                           double *, int32_t *, int64_t *, hipStream_t);
+                                           const double *, double *, int32_t *, int64_t *, hipStream_t);
 
 hipError_t launch_contact_pairs(const DevParams &P, int64_t n, const double *x, const double *r,
                                 const int32_t *cb, const int32_t *ce, int32_t *pairs, int64_t cap,

@@ -30,6 +30,17 @@ int64_t key_space_of(const gic_params *p)
     return nb[0] * nb[1] * nb[2] * kBrickCells;
 }
 
+// Rupture distance of the liquid bridge between two granules of radius r_max
+// (Sec. 5.4): d_r = V*^(1/3) + 0.1 V*^(2/3), V* = vbridge (4/3) pi r_max^3;
+// 0 without capillary force.
+double rupture_max(const gic_params *p)
+{
+    if (!(p->sigma > 0.0)) return 0.0;
+    const double V = p->vbridge * (((4.0 * GIC_PI / 3.0) * p->r_max) * p->r_max) * p->r_max;
+    const double t = cbrt(V);
+    return t + 0.1 * (t * t);
+}
+
 bool params_valid(const gic_params *p)
 {
     if (!p) return false;
@@ -46,6 +57,11 @@ bool params_valid(const gic_params *p)
     if (!(p->f_unit >= 0.0) || !isfinite(p->f_unit)) return false;
     if (p->drag_model != 0 && p->drag_model != 1) return false;
     if (p->vmass != 0 && p->vmass != 1) return false;
+    if (!(p->sigma >= 0.0) || !isfinite(p->sigma)) return false;
+    if (p->sigma > 0.0) {
+        if (!(p->vbridge > 0.0) || !isfinite(p->vbridge) || !(p->sr_peak > 0.0) || !(p->sr_peak < 1.0)) return false;
+        if (p->cell < 2.0 * p->r_max + rupture_max(p)) return false;  // the cells must reach every bridge
+    }
     for (int a = 0; a < 3; ++a)
         if (!isfinite(p->g[a])) return false;
     if (p->precision != GIC_FP64 && p->precision != GIC_FP32) return false;
@@ -107,6 +123,10 @@ DevParams derive(const gic_params *p)
     d.c_quad = p->c_quad;
     d.drag_model = p->drag_model;
     d.vmass = p->vmass;
+    d.sigma = p->sigma;
+    d.vbridge = p->vbridge;
+    d.sr_peak = p->sr_peak;
+    d.dr_max = rupture_max(p);
     return d;
 }
 
@@ -275,10 +295,27 @@ gic_status gic_contact_forces(gic_ctx *c, int64_t n, const double *x, const doub
     if (n == 0) return GIC_OK;
     if (brick_list(c, cell_begin, cell_end, s) != hipSuccess) return GIC_E_HIP;
     if (fp32(c))
-        return hip_status(launch_contact<float>(c->dp, n, x, v, r, cell_begin, cell_end, c->bricks,
+        return hip_status(launch_contact<float>(c->dp, n, x, v, r, cell_begin, cell_end, c->bricks, nullptr,
                                                 (float *)f_contact, n_contacts, c->err, s));
-    return hip_status(launch_contact<double>(c->dp, n, x, v, r, cell_begin, cell_end, c->bricks,
+    return hip_status(launch_contact<double>(c->dp, n, x, v, r, cell_begin, cell_end, c->bricks, nullptr,
                                              (double *)f_contact, n_contacts, c->err, s));
+}
+
+gic_status gic_contact_capillary_forces(gic_ctx *c, int64_t n, const double *x, const double *v, const double *r,
+                                        const void *sr, const int32_t *cell_begin, const int32_t *cell_end,
+                                        void *f_contact, int32_t *n_contacts, void *stream)
+{
+    if (!n_ok(c, n)) return GIC_E_ARG;
+    if (!(c->p.sigma > 0.0)) return GIC_E_ARG;
+    if (n > 0 && (!x || !v || !r || !sr || !cell_begin || !cell_end || !f_contact)) return GIC_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (n == 0) return GIC_OK;
+    if (brick_list(c, cell_begin, cell_end, s) != hipSuccess) return GIC_E_HIP;
+    if (fp32(c))
+        return hip_status(launch_contact<float>(c->dp, n, x, v, r, cell_begin, cell_end, c->bricks,
+                                                (const float *)sr, (float *)f_contact, n_contacts, c->err, s));
+    return hip_status(launch_contact<double>(c->dp, n, x, v, r, cell_begin, cell_end, c->bricks,
+                                             (const double *)sr, (double *)f_contact, n_contacts, c->err, s));
 }
 
 gic_status gic_contact_pairs(gic_ctx *c, int64_t n, const double *x, const double *r, const int32_t *cell_begin,

@@ -99,6 +99,9 @@ struct DevParams {
     double c_quad;             // coefficient of the quadratic drag
     int32_t drag_model;        // 0: linear Stokes form x alpha_f; 1: quadratic of Eq. 5b
     int32_t vmass;             // 1: virtual mass, effective mass m + rho_f V / 2
+    // capillary (concentration-gradient) pair force, Sec. 5.4
+    double sigma, vbridge, sr_peak;  // surface tension, bridge volume / granule volume, peak of Gamma
+    double dr_max;                   // rupture distance of the largest pair (search reach)
 };
 
 // Latch the first error: code and granule index.
@@ -311,6 +314,47 @@ __device__ inline void integrate_one(const DevParams &P, double r, const T Fc[3]
         v[a] = vn;
         x[a] = x[a] + P.dt * vn;
     }
+}
+
+// Moisture curve Gamma of the capillary force (Sec. 5.4): zero when dry
+// (sr <= 0) and when saturated (sr >= 1), one at sr_peak, a quadratic Bezier
+// arc on each side with a level tangent at the peak.
+__device__ inline double gamma_of(const DevParams &P, double sr)
+{
+    if (!(sr > 0.0) || !(sr < 1.0)) return 0.0;
+    if (sr <= P.sr_peak) {
+        const double u = sr / P.sr_peak;
+        return u * (2.0 - u);
+    }
+    const double u = (sr - P.sr_peak) / (1.0 - P.sr_peak);
+    return 1.0 - u * u;
+}
+
+// Capillary force of the liquid bridge between granules i and j (Sec. 5.4)
+// added to acc: with s = d - (r_i + r_j), the pair's mean radius rb, the
+// bridge volume V* = vbridge (4/3) pi rb^3 and rupture distance d_r = V*^(1/3)
+// + 0.1 V*^(2/3), for 0 < s < d_r the force on i is -Gamma((sr_i + sr_j) / 2)
+// F^st (x_i - x_j) / d with F^st = -2 pi sigma rb ((1 + 2 V* / (pi rb s^2))^(-1/2)
+// - 1) > 0: an attraction.  dx = x_i - x_j, d2 = |dx|^2.  Double arithmetic
+// (s is a small difference of nearly equal lengths); returns 1 if bridged.
+template <typename T>
+__device__ inline int capillary_pair(const DevParams &P, const double dx[3], double d2, double ri, double rj, T sri,
+                                     T srj, T acc[3])
+{
+#pragma clang fp contract(off)
+    const double d = sqrt(d2);
+    const double s = d - (ri + rj);
+    const double rb = 0.5 * (ri + rj);
+    const double V = P.vbridge * volume_of(rb);
+    const double t = cbrt(V);
+    const double dr = t + 0.1 * (t * t);
+    if (!(s > 0.0) || !(s < dr)) return 0;
+    const double g = gamma_of(P, 0.5 * ((double)sri + (double)srj));
+    const double q = 1.0 + (2.0 * V) / ((GIC_PI * rb) * (s * s));
+    const double fst = -(2.0 * GIC_PI * P.sigma * rb) * (1.0 / sqrt(q) - 1.0);
+    const double f = -(g * fst);
+    for (int a = 0; a < 3; ++a) acc[a] += (T)(f * (dx[a] / d));
+    return 1;
 }
 
 // Origin of a brick's node tile: one node below the brick's first node per

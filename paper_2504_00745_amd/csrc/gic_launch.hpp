@@ -54,8 +54,8 @@ hipError_t launch_reorder(int64_t n, const int32_t *order, const double *x, cons
 
 template <typename T>
 hipError_t launch_contact(const DevParams &P, int64_t n, const double *x, const double *v, const double *r,
-                          const int32_t *cb, const int32_t *ce, const BrickList &B, T *F, int32_t *ncont,
-                          int64_t *err, hipStream_t s);
+                          const int32_t *cb, const int32_t *ce, const BrickList &B, const T *sr, T *F,
+                          int32_t *ncont, int64_t *err, hipStream_t s);
 hipError_t launch_contact_pairs(const DevParams &P, int64_t n, const double *x, const double *r,
                                 const int32_t *cb, const int32_t *ce, int32_t *pairs, int64_t cap,
                                 int64_t *count, hipStream_t s);

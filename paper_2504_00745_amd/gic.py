@@ -36,6 +36,7 @@ class gic_params(C.Structure):
         ("walls", C.c_uint32), ("precision", C.c_int32),
         ("rho_f", C.c_double), ("c_quad", C.c_double), ("f_unit", C.c_double),
         ("drag_model", C.c_int32), ("vmass", C.c_int32),
+        ("sigma", C.c_double), ("vbridge", C.c_double), ("sr_peak", C.c_double),
     ]
 
 
@@ -61,6 +62,7 @@ def lib():
             "gic_sort_cells": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V]),
             "gic_reorder": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V, _V, _V, _V]),
             "gic_contact_forces": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V, _V]),
+            "gic_contact_capillary_forces": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V, _V, _V]),
             "gic_contact_pairs": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _I64, _V, _V]),
             "gic_g2p": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V]),
             "gic_drag": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V]),
@@ -108,6 +110,9 @@ def make_params(cfg: dict, precision: str = "fp32", r_max: float = None) -> gic_
     p.f_unit = float(cfg.get("f_unit", 1.0))
     p.drag_model = int(cfg.get("drag_model", 0))
     p.vmass = int(cfg.get("vmass", 0))
+    p.sigma = float(cfg.get("sigma", 0.0))
+    p.vbridge = float(cfg.get("vbridge", 1e-4))
+    p.sr_peak = float(cfg.get("sr_peak", 0.3))
     return p
 
 
@@ -204,6 +209,17 @@ def gic_contact_forces(ctx, x, v, r, cell_begin, cell_end, f_contact, n_contacts
                                     _ptr(cell_begin, torch.int32, ctx.K), _ptr(cell_end, torch.int32, ctx.K),
                                     _ptr(f_contact, ctx.real, 3 * n, "f_contact"),
                                     _ptr(n_contacts, torch.int32, n), _stream()), "gic_contact_forces")
+
+
+def gic_contact_capillary_forces(ctx, x, v, r, sr, cell_begin, cell_end, f_contact, n_contacts=None):
+    n = x.shape[-1]
+    f64 = torch.float64
+    _check(lib().gic_contact_capillary_forces(ctx.handle, n, _ptr(x, f64, 3 * n), _ptr(v, f64, 3 * n),
+                                              _ptr(r, f64, n), _ptr(sr, ctx.real, n, "sr"),
+                                              _ptr(cell_begin, torch.int32, ctx.K), _ptr(cell_end, torch.int32, ctx.K),
+                                              _ptr(f_contact, ctx.real, 3 * n, "f_contact"),
+                                              _ptr(n_contacts, torch.int32, n), _stream()),
+           "gic_contact_capillary_forces")
 
 
 def gic_contact_pairs(ctx, x, r, cell_begin, cell_end, pairs, count):

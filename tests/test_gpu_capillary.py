@@ -1,0 +1,190 @@
+"""GPU parity of the contact plus capillary liquid-bridge forces (Sec. 3.1
+Eq. 1a-c, Sec. 5.4) through the C ABI, against the FP64 oracle's contact
+forces plus its capillary forces on the same seeded wet beds.
+
+Bar: per granule |F - F_or| <= tol S with S the sum of the magnitudes of the
+terms that sum into F (contact pairs and walls from the oracle, bridge pairs
+from the oracle's pair force over the pairs a k-d tree finds within the
+rupture range), tol 1e-5 (FP32 form) / 1e-12 (plain FP64 form); contact
+counts bit for bit.  The moisture curve's shape between its pinned points is
+the oracle's reading (parity unpinned, see the oracle's capillary pins).
+"""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-5, "fp64": 1e-12}
+CAP = dict(sigma=0.072, vbridge=1e-4, sr_peak=0.3)
+
+
+@pytest.fixture(scope="module")
+def G():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2504_00745_amd import gic
+    gic.lib()
+    import gpu_util
+    return gpu_util
+
+
+def wet_lattice(m=16, keep=3989, seed=5, rlo=0.97e-3, rhi=1.0e-3, sp=2.0e-3, walls=1):
+    """A jittered m^3 lattice (spacing sp) of spheres of radii in [rlo, rhi],
+    thinned to a ragged count.  The defaults spread the surface gaps over
+    about [-45, 105] um around the ~75 um rupture distance, so contacts,
+    bridges and free pairs all occur."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    g = np.stack(np.meshgrid(*[np.arange(m)] * 3, indexing="ij")).reshape(3, -1).astype(float)
+    x = (g + 0.5) * sp + rng.uniform(-2.5e-5, 2.5e-5, g.shape)
+    sel = np.sort(rng.choice(x.shape[1], keep, replace=False))
+    x = x[:, sel]
+    n = x.shape[1]
+    r = rng.uniform(rlo, rhi, n)
+    v = rng.normal(0, 0.02, (3, n))
+    sr = rng.uniform(0.0, 1.0, n)
+    sr[rng.random(n) < 0.1] = 0.0  # dry granules
+    sr[rng.random(n) < 0.05] = 1.0  # saturated granules
+    box = m * sp
+    nc = int(box / (2 * rhi + 7.5e-5 + 1e-5))  # cells reach every bridge: >= 2 r_max + d_r(r_max)
+    cell = box / nc
+    cfg = dict(n=[8, 8, 8], dx=box / 8, nc=[nc] * 3, cell=cell, kn=1e5, restitution=0.5, kt_ratio=1.0, mu=0.5,
+               rho_s=2500.0, eta_f=1e-3, c_drag=0.0, alpha_max=0.74, g=[0, 0, 0], dt=1e-5, walls=walls, **CAP)
+    return cfg, x, v, r, sr
+
+
+def run_capillary(G, cfg, x, v, r, sr, prec, r_max=None, entry="capillary"):
+    """Sort, reorder and one force call; returns (F, ncont, err) in input order."""
+    import torch
+    from paper_2504_00745_amd import gic
+    n = x.shape[1]
+    ctx = gic.Context(cfg, n, prec, r_max=float(r.max()) if r_max is None else r_max)
+    X, V, R = G.dev(x.reshape(-1)), G.dev(v.reshape(-1)), G.dev(r)
+    ID = torch.arange(n, dtype=torch.int32, device="cuda")
+    key = torch.empty(n, dtype=torch.int32, device="cuda")
+    order = torch.empty(n, dtype=torch.int32, device="cuda")
+    cb = torch.empty(ctx.K, dtype=torch.int32, device="cuda")
+    ce = torch.empty(ctx.K, dtype=torch.int32, device="cuda")
+    gic.gic_sort_cells(ctx, X.view(3, n), key, order, cb, ce)
+    Xs, Vs, Rs, IDs = torch.empty_like(X), torch.empty_like(V), torch.empty_like(R), torch.empty_like(ID)
+    gic.gic_reorder(ctx, order, X.view(3, n), V, R, ID, Xs, Vs, Rs, IDs)
+    SRs = G.dev(sr, ctx.real)[order.long()].contiguous()
+    F = torch.empty(3 * n, dtype=ctx.real, device="cuda")
+    nct = torch.empty(n, dtype=torch.int32, device="cuda")
+    if entry == "capillary":
+        gic.gic_contact_capillary_forces(ctx, Xs.view(3, n), Vs, Rs, SRs, cb, ce, F, nct)
+    else:
+        gic.gic_contact_forces(ctx, Xs.view(3, n), Vs, Rs, cb, ce, F, nct)
+    torch.cuda.synchronize()
+    ids = IDs.cpu().numpy()
+    Fo = np.empty((3, n))
+    Fo[:, ids] = F.double().cpu().numpy().reshape(3, n)
+    nco = np.empty(n, np.int64)
+    nco[ids] = nct.cpu().numpy()
+    return Fo, nco, ctx.error(), ctx
+
+
+def bridge_scale(orc, cfg, x, r, sr):
+    """Per granule sum of the magnitudes of its bridge forces, over the pairs
+    a k-d tree finds within 2 r_max + d_r(r_max); and the number of bridges."""
+    from scipy.spatial import cKDTree
+    _, drmax = orc.bridge(cfg, float(r.max()))
+    pairs = cKDTree(x.T).query_pairs(2 * float(r.max()) + drmax, output_type="ndarray")
+    S = np.zeros(x.shape[1])
+    nb = 0
+    for i, j in pairs:
+        f = np.linalg.norm(orc.capillary_pair(cfg, x[:, i], x[:, j], r[i], r[j], sr[i], sr[j]))
+        S[i] += f
+        S[j] += f
+        nb += f > 0
+    return S, nb
+
+
+def check(orc, cfg, x, v, r, sr, F, nco, prec):
+    Fc, fa, nc, ns = orc.contact_forces(cfg, x, v, r)
+    Fb = orc.capillary_forces(cfg, x, r, sr)
+    Sb, nb = bridge_scale(orc, cfg, x, r, sr)
+    assert np.array_equal(nco, nc), "contact counts differ"
+    err = np.linalg.norm(F - (Fc + Fb), axis=0)
+    S = fa + Sb
+    assert np.all(err <= TOL[prec] * S + 1e-300), f"max err/scale {np.max(err / (S + 1e-300))}"
+    return int(nc.sum()), nb
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("case", ["equal", "polydisperse"])
+def test_capillary_matches_oracle(G, orc, prec, case):
+    """Contact plus bridge forces of a wet bed (dry, wet and saturated
+    granules; walls on) match the oracle's sum of the two."""
+    G.say(f"[capillary] {case} {prec}")
+    if case == "equal":
+        cfg, x, v, r, sr = wet_lattice()
+    else:
+        cfg, x, v, r, sr = wet_lattice(m=15, keep=3001, seed=11, rlo=0.7e-3, sp=1.75e-3, walls=0)
+    F, nco, err, _ = run_capillary(G, cfg, x, v, r, sr, prec)
+    assert err == (0, -1)
+    ncon, nb = check(orc, cfg, x, v, r, sr, F, nco, prec)
+    assert ncon > 200 and nb > 1000, (ncon, nb)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_capillary_shell_overflow_path(G, orc, prec):
+    """A brick whose one-cell shell holds more granules than fit in LDS runs
+    the global candidate path, with bridges: still the oracle's forces."""
+    G.say(f"[capillary overflow] {prec}")
+    rng = np.random.Generator(np.random.PCG64(23))
+    cfg, x, v, r, sr = wet_lattice(m=12, keep=1500, seed=3, walls=0)
+    # 2600 small granules (r = 0.2 mm, d_r ~ 15 um) packed in one brick
+    xs = rng.uniform(0.0, 8.0e-3, (3, 2600)) + 4.0e-3
+    rs = rng.uniform(0.19e-3, 0.2e-3, 2600)
+    x = np.concatenate([x, xs], 1)
+    r = np.concatenate([r, rs])
+    n = x.shape[1]
+    v = rng.normal(0, 0.02, (3, n))
+    sr = rng.uniform(0.05, 0.95, n)
+    F, nco, err, _ = run_capillary(G, cfg, x, v, r, sr, prec, r_max=1.0e-3)
+    assert err == (0, -1)
+    ncon, nb = check(orc, cfg, x, v, r, sr, F, nco, prec)
+    assert nb > 500
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_dry_bed_equals_contact_forces(G, prec):
+    """With every moisture ratio 0 (Gamma = 0) the call returns the contact
+    forces and counts of gic_contact_forces bit for bit."""
+    G.say(f"[capillary dry] {prec}")
+    cfg, x, v, r, sr = wet_lattice(keep=2047, seed=9)
+    sr[:] = 0.0
+    F1, n1, e1, _ = run_capillary(G, cfg, x, v, r, sr, prec)
+    F0, n0, e0, _ = run_capillary(G, cfg, x, v, r, sr, prec, entry="contact")
+    assert np.array_equal(F1, F0) and np.array_equal(n1, n0)
+    assert e1 == e0 == (0, -1)
+
+
+def test_capillary_argument_checks(G):
+    """sigma = 0 or a missing moisture array is an argument error; n = 0 is
+    a no-op."""
+    import torch
+    from paper_2504_00745_amd import gic
+    cfg, x, v, r, sr = wet_lattice(keep=300)
+    dry = dict(cfg, sigma=0.0)
+    n = x.shape[1]
+    ctx = gic.Context(dry, n, "fp32", r_max=float(r.max()))
+    X, V, R = (torch.zeros(3 * n, dtype=torch.float64, device="cuda"),
+               torch.zeros(3 * n, dtype=torch.float64, device="cuda"),
+               torch.zeros(n, dtype=torch.float64, device="cuda"))
+    SR = torch.zeros(n, dtype=torch.float32, device="cuda")
+    cb = torch.zeros(ctx.K, dtype=torch.int32, device="cuda")
+    F = torch.empty(3 * n, dtype=torch.float32, device="cuda")
+    with pytest.raises(gic.GicError):
+        gic.gic_contact_capillary_forces(ctx, X.view(3, n), V, R, SR, cb, cb, F)
+    ctx2 = gic.Context(cfg, n, "fp32", r_max=float(r.max()))
+    assert ctx2.params.sigma == pytest.approx(0.072)
+    assert gic.lib().gic_contact_capillary_forces(ctx2.handle, n, gic._ptr(X, torch.float64, 3 * n),
+                                                  gic._ptr(V, torch.float64, 3 * n), gic._ptr(R, torch.float64, n),
+                                                  None, gic._ptr(cb, torch.int32, ctx2.K),
+                                                  gic._ptr(cb, torch.int32, ctx2.K),
+                                                  gic._ptr(F, torch.float32, 3 * n), None, None) == 1
+    gic.gic_contact_capillary_forces(ctx2, X[:0].view(3, 0), V[:0], R[:0], SR[:0], cb, cb, F[:0])
