@@ -35,6 +35,7 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-coupled", action="store_true")
+    ap.add_argument("--no-capillary", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (read 1 GiB, write 1 GiB) three times, "
@@ -71,6 +72,11 @@ def coupled_bytes(stage, n, nodes, real_bytes):
     if stage == "exchange_p2g":
         return (24 + 8 + 3 * B + 3 * B) * n + 24 * nodes
     return stage_bytes(stage, n, nodes, real_bytes)
+
+
+# Contact with liquid bridges (FP32 form): the dry contact's x, v, r and F_c
+# plus the moisture ratio of each granule.
+CAPILLARY_BYTES_PER_GRANULE = 24 + 24 + 8 + 3 * 4 + 4
 
 
 def time_steps(sim, steps, warmup):
@@ -300,6 +306,58 @@ def time_coupled(d, wl_name, substeps=4, sand_steps=8):
             "error": [code, idx]}
 
 
+def time_capillary(d, wl_name, reps=10):
+    """The workload as a wet bed (Sec. 5.4): the moisture ratio of every
+    granule from its sampled fluid fraction and a seeded held-water ratio,
+    then contact plus liquid-bridge forces, FP32 form, on the sorted state of
+    a step; the dry contact call timed on the same state beside it."""
+    import torch
+    from paper_2504_00745_amd import gic
+    cfg = dict(d["params"], sigma=0.072, vbridge=1e-4, sr_peak=0.3)
+    n = d["x"].shape[1]
+    sim = gic.Simulator(cfg, d["x"], d["v"], d["r"], d["u"], "fp32", r_max=float(d["r"].max()))
+    sim.step()
+    ctx, s = sim.ctx, sim.scratch
+    cur, nxt = sim.cur, sim.nxt
+    gic.gic_sort_cells(ctx, cur["x"], s["key"], s["order"], s["cell_begin"], s["cell_end"])
+    uat = torch.empty(3 * n, dtype=torch.float32, device="cuda")
+    af = torch.empty(n, dtype=torch.float32, device="cuda")
+    gic.gic_gather_g2p_drag(ctx, s["order"], cur["x"], cur["v"], cur["r"], cur["id"], nxt["x"], nxt["v"], nxt["r"],
+                            nxt["id"], sim.u, sim.alpha, s["cell_begin"], s["cell_end"], s["f_drag"], u_at=uat,
+                            alpha_f=af)
+    rng = np.random.Generator(np.random.PCG64(14))
+    held = torch.as_tensor(rng.uniform(0.0, 0.2, n), dtype=torch.float32, device="cuda")
+    sr = torch.empty(n, dtype=torch.float32, device="cuda")
+    F = s["f_contact"]
+    args = (nxt["x"], nxt["v"], nxt["r"])
+    gic.gic_moisture_ratio(ctx, held, af, sr)
+    gic.gic_contact_capillary_forces(ctx, *args, sr, s["cell_begin"], s["cell_end"], F)  # warm-up
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4 * reps)]
+    for i in range(reps):
+        ev[4 * i].record()
+        gic.gic_moisture_ratio(ctx, held, af, sr)
+        ev[4 * i + 1].record()
+        gic.gic_contact_capillary_forces(ctx, *args, sr, s["cell_begin"], s["cell_end"], F)
+        ev[4 * i + 2].record()
+        gic.gic_contact_forces(ctx, *args, s["cell_begin"], s["cell_end"], F)
+        ev[4 * i + 3].record()
+    torch.cuda.synchronize()
+    t = [sum(ev[4 * i + k].elapsed_time(ev[4 * i + k + 1]) for i in range(reps)) / reps / 1e3 for k in range(3)]
+    code, idx = ctx.error()
+    cb = n * CAPILLARY_BYTES_PER_GRANULE
+    ach = cb / t[1] / 1e9
+    srv = sr.cpu().numpy()
+    return {"workload": "same bed wet (sigma = 0.072 N/m, bridge volume 1e-4 of the granule volume, Gamma peak "
+                        "at sr = 0.3; held water U(0, 0.2) per granule), FP32",
+            "moisture_ratio_ms": round(t[0] * 1e3, 4), "contact_capillary_ms": round(t[1] * 1e3, 4),
+            "contact_dry_ms": round(t[2] * 1e3, 4), "value": n / t[1], "unit": "granules/s (contact + bridges)",
+            "sr_median": float(np.median(srv)),
+            "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBS, "algorithmic_bytes": cb, "traffic": None},
+            "error": [code, idx]}
+
+
 def touched_nodes(sim):
     import torch
     return int((sim.alpha != 0).sum().item())
@@ -395,6 +453,10 @@ def main():
     if not a.no_coupled:
         log("[bench] coupled: remaining interphase forces and exchange, sand steps of 4 sub-steps")
         line["coupled"] = time_coupled(d, a.workload)
+        torch.cuda.empty_cache()
+    if not a.no_capillary:
+        log("[bench] capillary: wet bed, moisture ratio and contact plus liquid-bridge forces")
+        line["capillary"] = time_capillary(d, a.workload)
         torch.cuda.empty_cache()
     if not a.no_adjoint:
         log("[bench] adjoint: forward and backward of the c4 rollout")

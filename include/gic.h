@@ -204,6 +204,19 @@ gic_status gic_contact_forces(gic_ctx *ctx, int64_t n, const double *x, const do
                               const int32_t *cell_begin, const int32_t *cell_end, void *f_contact,
                               int32_t *n_contacts, void *stream);
 
+/* ---- f3: moisture ratio (Sec. 5.4, the definition following Eq. 26) -------
+ * sr_i = held_i + alpha_f,i / (1 - alpha_f,i): the water granule i holds
+ * (per unit granule volume; the absorption of Sec. 5.3 that changes it is
+ * not part of this library) plus the free water around it per unit sand
+ * volume.  Evaluated in double, stored in the form's real type; +inf where
+ * alpha_f = 1.  n real each (the form's type), any order as long as the three
+ * agree; sr may alias neither input.
+ *   held      water held by each granule (>= 0).
+ *   alpha_f   fluid fraction sampled at each granule (gic_g2p).
+ *   sr        out: moisture ratio. */
+gic_status gic_moisture_ratio(gic_ctx *ctx, int64_t n, const void *held, const void *alpha_f, void *sr,
+                              void *stream);
+
 /* ---- f3: contact plus capillary liquid-bridge forces (Sec. 5.4) ----------
  * gic_contact_forces plus, for every pair that does not touch and whose
  * surface gap s = d - (r_i + r_j) lies in (0, d_r), the bridge force on i

@@ -125,6 +125,7 @@ def _declare(L):
         "orc_substeps": (C.c_int32, [C.c_double, C.c_double]),
         "orc_sand_step": (C.c_int32, [_pp, _pc, C.c_int64, C.c_double, _d, _d, _d, _d, _d, _d, _i64, _i64, _i64]),
         "orc_gamma": (C.c_double, [_pk, C.c_double]),
+        "orc_moisture_ratio": (None, [C.c_int64, _d, _d, _d]),
         "orc_bridge": (None, [_pk, C.c_double, _d, _d]),
         "orc_bridge_energy": (C.c_double, [_pk, C.c_double, C.c_double]),
         "orc_fst": (C.c_double, [_pk, C.c_double, C.c_double]),
@@ -441,6 +442,14 @@ def sand_step(cfg, Dt, x, v, r, u, alpha_fx, gp=None, af=None):
 
 def gamma(cfg, sr):
     return float(lib().orc_gamma(C.byref(capillary(cfg)), float(sr)))
+
+
+def moisture_ratio(held, alpha_f):
+    """sr_i = held_i + alpha_f,i / (1 - alpha_f,i) per granule."""
+    held, alpha_f = _f64(held), _f64(alpha_f)
+    sr = np.zeros(held.shape[0])
+    lib().orc_moisture_ratio(held.shape[0], _ptr(held, C.c_double), _ptr(alpha_f, C.c_double), _ptr(sr, C.c_double))
+    return sr
 
 
 def bridge(cfg, rb):

@@ -1335,8 +1335,9 @@ int32_t orc_sand_step(const orc_params *p, const orc_coupling *cp, int64_t n, do
  *     bump, Gamma(sr) = u (2 - u), u = sr / sr_peak on (0, sr_peak], and
  *     1 - u^2, u = (sr - sr_peak) / (1 - sr_peak) on (sr_peak, 1); zero at
  *     sr <= 0 and sr >= 1, one at sr_peak (the maximum absorption ratio);
- *   - the moisture ratios sr_i are inputs (the wetting of Sec. 5.3 is not on
- *     this path).
+ *   - the water a granule holds, r_i of the moisture ratio, is an input (the
+ *     wetting of Sec. 5.3 is not on this path); alpha_f,i is the fluid
+ *     fraction the granule samples from the grid (G2P).
  * The cell list finds every bridged pair when cell >= 2 r_max + d_r(r_max).
  */
 
@@ -1355,6 +1356,15 @@ double orc_gamma(const orc_capillary *c, double sr)
     }
     double u = (sr - c->sr_peak) / (1.0 - c->sr_peak);
     return 1.0 - u * u;
+}
+
+/* Moisture ratio of each granule (the definition following Eq. 26): the water
+ * it holds plus the free water around it per unit sand volume,
+ *     sr_i = r_i + alpha_f,i / (1 - alpha_f,i),
+ * +inf where alpha_f,i = 1 (no sand around: Gamma is zero there). */
+void orc_moisture_ratio(int64_t n, const double *held, const double *alpha_f, double *sr)
+{
+    for (int64_t i = 0; i < n; ++i) sr[i] = held[i] + alpha_f[i] / (1.0 - alpha_f[i]);
 }
 
 /* Liquid-bridge volume V* and rupture distance d_r of a pair of mean radius rb. */

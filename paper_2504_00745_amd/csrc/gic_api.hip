@@ -318,6 +318,18 @@ gic_status gic_contact_capillary_forces(gic_ctx *c, int64_t n, const double *x, 
                                              (const double *)sr, (double *)f_contact, n_contacts, c->err, s));
 }
 
+gic_status gic_moisture_ratio(gic_ctx *c, int64_t n, const void *held, const void *alpha_f, void *sr, void *stream)
+{
+    if (!n_ok(c, n)) return GIC_E_ARG;
+    if (n > 0 && (!held || !alpha_f || !sr)) return GIC_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (fp32(c))
+        return hip_status(
+            launch_moisture_ratio<float>(n, (const float *)held, (const float *)alpha_f, (float *)sr, s));
+    return hip_status(
+        launch_moisture_ratio<double>(n, (const double *)held, (const double *)alpha_f, (double *)sr, s));
+}
+
 gic_status gic_contact_pairs(gic_ctx *c, int64_t n, const double *x, const double *r, const int32_t *cell_begin,
                              const int32_t *cell_end, int32_t *pairs, int64_t cap, int64_t *count, void *stream)
 {

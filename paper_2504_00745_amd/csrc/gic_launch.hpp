@@ -64,6 +64,8 @@ template <typename T>
 hipError_t launch_g2p(const DevParams &P, int64_t n, const double *x, const T *u, const int64_t *afx,
                       const double *are, T *uat, T *af, hipStream_t s);
 template <typename T>
+hipError_t launch_moisture_ratio(int64_t n, const T *held, const T *af, T *sr, hipStream_t s);
+template <typename T>
 hipError_t launch_drag(const DevParams &P, int64_t n, const double *r, const double *v, const T *uat, const T *af,
                        T *Fd, hipStream_t s);
 template <typename T>

@@ -63,6 +63,7 @@ def lib():
             "gic_reorder": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V, _V, _V, _V]),
             "gic_contact_forces": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V, _V]),
             "gic_contact_capillary_forces": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V, _V, _V]),
+            "gic_moisture_ratio": (C.c_int, [_V, _I64, _V, _V, _V, _V]),
             "gic_contact_pairs": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _I64, _V, _V]),
             "gic_g2p": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V]),
             "gic_drag": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V]),
@@ -220,6 +221,13 @@ def gic_contact_capillary_forces(ctx, x, v, r, sr, cell_begin, cell_end, f_conta
                                               _ptr(f_contact, ctx.real, 3 * n, "f_contact"),
                                               _ptr(n_contacts, torch.int32, n), _stream()),
            "gic_contact_capillary_forces")
+
+
+def gic_moisture_ratio(ctx, held, alpha_f, sr):
+    n = held.shape[-1]
+    _check(lib().gic_moisture_ratio(ctx.handle, n, _ptr(held, ctx.real, n, "held"),
+                                    _ptr(alpha_f, ctx.real, n, "alpha_f"), _ptr(sr, ctx.real, n, "sr"), _stream()),
+           "gic_moisture_ratio")
 
 
 def gic_contact_pairs(ctx, x, r, cell_begin, cell_end, pairs, count):

@@ -188,3 +188,28 @@ def test_capillary_argument_checks(G):
                                                   gic._ptr(cb, torch.int32, ctx2.K),
                                                   gic._ptr(F, torch.float32, 3 * n), None, None) == 1
     gic.gic_contact_capillary_forces(ctx2, X[:0].view(3, 0), V[:0], R[:0], SR[:0], cb, cb, F[:0])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_moisture_ratio_matches_oracle(G, orc, prec):
+    """sr = held + alpha_f / (1 - alpha_f) on a ragged count, including the
+    clamp floor 0.26 and alpha_f = 1 (+inf): the oracle's double value,
+    rounded once to the form's type, on the same inputs."""
+    import torch
+    from paper_2504_00745_amd import gic
+    G.say(f"[moisture ratio] {prec}")
+    cfg, x, v, r, sr = wet_lattice(keep=300)
+    n = 5003
+    rng = np.random.Generator(np.random.PCG64(31))
+    held = rng.uniform(0.0, 0.4, n)
+    af = rng.uniform(0.26, 1.0, n)
+    af[:3] = [0.26, 1.0, 0.5]
+    ctx = gic.Context(cfg, n, prec, r_max=1e-3)
+    H, A = G.dev(held, ctx.real), G.dev(af, ctx.real)
+    S = torch.empty(n, dtype=ctx.real, device="cuda")
+    gic.gic_moisture_ratio(ctx, H, A, S)
+    want = orc.moisture_ratio(H.double().cpu().numpy(), A.double().cpu().numpy())
+    want = want.astype(np.float32) if prec == "fp32" else want
+    got = S.cpu().numpy()
+    assert np.array_equal(got, want)
+    assert got[1] == np.inf

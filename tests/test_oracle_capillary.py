@@ -116,3 +116,32 @@ def test_cell_list_equals_brute_force(orc):
     assert bridged > 50
     assert np.allclose(F, B, rtol=1e-12, atol=1e-20)
     assert np.abs(F.sum(axis=1)).max() <= 1e-12 * np.abs(F).sum()
+
+
+def test_moisture_ratio_is_water_per_sand_volume(orc):
+    """sr = held water + alpha_f / (1 - alpha_f): for a mixture of sand
+    volume Vs and free water Vw (alpha_f = Vw / (Vs + Vw)) the second term is
+    Vw / Vs; pure sand adds nothing and no sand gives +inf (Gamma = 0)."""
+    Vs = np.array([3.0, 1.0, 1.0, 5.0, 1.0])
+    Vw = np.array([1.0, 1.0, 3.0, 0.0, 0.0])
+    held = np.array([0.0, 0.25, 0.1, 0.2, 0.0])
+    sr = orc.moisture_ratio(held, Vw / (Vs + Vw))
+    assert np.allclose(sr, held + Vw / Vs, rtol=1e-15, atol=0)
+    assert orc.moisture_ratio([0.3], [1.0])[0] == math.inf
+    assert orc.gamma(CAP, math.inf) == 0.0
+
+
+def test_moisture_ratio_of_a_lone_granule(orc):
+    """A lone granule at a node centre samples alpha_s = frac 0.59375^3 of
+    itself (the pinned G2P), so its moisture ratio is held + (1 - alpha_s) /
+    alpha_s: the cell's free water over the granule's share of sand."""
+    cfg = dict(n=[16, 16, 16], dx=0.02, nc=[16, 16, 16], cell=0.02, kn=1e5, restitution=0.5, kt_ratio=1.0,
+               mu=0.5, rho_s=2500.0, eta_f=1e-3, c_drag=1.0, alpha_max=0.74, g=[0, 0, 0], dt=1e-5, walls=0)
+    dx = cfg["dx"]
+    r0 = 0.006
+    x = np.array([[7.5 * dx], [8.5 * dx], [6.5 * dx]])
+    alpha, _ = orc.p2g_fixed(cfg, x, np.zeros((3, 1)), np.array([r0]))
+    _, af = orc.g2p(cfg, x, np.zeros((3, 16 ** 3)), alpha_fx=alpha)
+    a_s = 4 / 3 * np.pi * r0 ** 3 / dx ** 3 * 0.59375 ** 3
+    sr = orc.moisture_ratio([0.15], af)[0]
+    assert sr == pytest.approx(0.15 + (1 - a_s) / a_s, rel=1e-7)
