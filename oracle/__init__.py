@@ -559,3 +559,4 @@ def rollout_vjp(cfg, x0, v0, r, u, steps):
                               _ptr(r, C.c_double), _ptr(u, C.c_double), int(steps), _ptr(gv0, C.c_double),
                               _ptr(gmu, C.c_double), _ptr(gcd, C.c_double))
     return L, gv0, float(gmu[0]), float(gcd[0])
+from . import idp  # noqa: E402,F401  (density projection, numpy/scipy)
