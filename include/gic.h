@@ -428,6 +428,69 @@ gic_status gic_sum(gic_ctx *ctx, int64_t n, const double *a, const double *b, do
 gic_status gic_permute(gic_ctx *ctx, int64_t n, int32_t comps, const int32_t *order, const double *in, double *out,
                        int32_t scatter, void *stream);
 
+/* ==== f4: density projection of the fluid fraction (Sec. 5.1) =============
+ * Eq. 12b on the MAC grid of App. B.  The cells are the transfer grid's nodes
+ * (params n, dx; cell centres, x fastest, G = n0 n1 n2 cells).  All grids
+ * here are double in both forms; labels are uint8 per cell: 0 fluid, 1 air,
+ * 2 solid.  With the scaled pressure q = (dt^2 / (rho_0 dx^2)) p_2 every
+ * fluid cell c satisfies
+ *     (L q)_c = sum_j beta_cj (q_c - q_j) = alpha_f'(c) (clamp(alpha_f*(c) / alpha_f'(c), 0.5, 1.5) - 1)
+ * over its six face neighbours j that are not solid and inside the box, with
+ * beta_cj = (alpha_f'(c) + alpha_f'(j)) / 2; air neighbours enter with
+ * q_j = 0 (p = 0 at the free surface), solid neighbours and the box boundary
+ * close the face (zero normal flux).  Rows of non-fluid cells are the
+ * identity with a zero right-hand side, so L is symmetric positive definite
+ * when every connected fluid region touches air, and the solution is zero
+ * off the fluid.  Reading: the sign of Eq. 12b is kept (the fluid moves out
+ * of a cell whose fraction exceeds its target); App. B prints the operator
+ * with the opposite sign of its right-hand side.
+ *
+ * gic_idp_setup: alpha_t = 1 - min(alpha_fx 2^-32, alpha_max) (the target
+ * fraction from the P2G grid, G int64) and rhs (the right-hand side above,
+ * zero off the fluid) from alpha_star (G, the fluid particles' own fraction,
+ * Eq. 7b: an input) and label.  Asynchronous. */
+gic_status gic_idp_setup(gic_ctx *ctx, const int64_t *alpha_fx, const double *alpha_star, const uint8_t *label,
+                         double *alpha_t, double *rhs, void *stream);
+
+/* out = L q (G doubles, out must not alias q).  Asynchronous. */
+gic_status gic_idp_apply(gic_ctx *ctx, const double *alpha_t, const uint8_t *label, const double *q, double *out,
+                         void *stream);
+
+/* Bytes of the caller-owned device workspace that gic_idp_solve and
+ * gic_density_projection need (about 48 G; -1 for a NULL context). */
+int64_t gic_idp_workspace_bytes(const gic_ctx *ctx);
+
+/* Solves L q = rhs by conjugate gradients with the Jacobi preconditioner,
+ * starting from the q passed in (q = 0 for a cold start); stops when
+ * |r|_2 <= tol |rhs|_2 (recursively updated residual) or after max_iter
+ * iterations.  Enqueues check_every iterations at a time and SYNCHRONISES the
+ * stream after each chunk to read the state; iterations of a chunk after
+ * convergence return at once.  *iters (host, optional) receives the
+ * iterations done, *relres (host, optional) |r| / |rhs| at the end (|r| when
+ * rhs = 0).  GIC_OK also when max_iter is reached: check *relres.  work: at
+ * least gic_idp_workspace_bytes bytes of device memory, 256-byte aligned. */
+gic_status gic_idp_solve(gic_ctx *ctx, const double *alpha_t, const uint8_t *label, const double *rhs, double *q,
+                         void *work, int32_t max_iter, double tol, int32_t check_every, int32_t *iters,
+                         double *relres, void *stream);
+
+/* Position change on the MAC faces (Eq. 13 in q): for the face between cell
+ * c and its +axis neighbour j, dx (q_c - q_j) (air sides count as q = 0; a
+ * positive value moves fluid along +axis) where one side is fluid and
+ * neither is solid, else 0; clamped to [-dx, dx] (Sec. 5.1).  Faces on the
+ * box boundary are 0.  fx: n2 x n1 x (n0 + 1), fy: n2 x (n1 + 1) x n0,
+ * fz: (n2 + 1) x n1 x n0, x fastest; face i + 1/2 along an axis is stored at
+ * index i + 1.  Asynchronous. */
+gic_status gic_idp_displacement(gic_ctx *ctx, const double *q, const uint8_t *label, double *fx, double *fy,
+                                double *fz, void *stream);
+
+/* The whole projection: gic_idp_setup into the workspace, gic_idp_solve
+ * (q in: initial guess, out: solution) and gic_idp_displacement.
+ * Synchronises like gic_idp_solve. */
+gic_status gic_density_projection(gic_ctx *ctx, const int64_t *alpha_fx, const double *alpha_star,
+                                  const uint8_t *label, double *q, double *fx, double *fy, double *fz, void *work,
+                                  int32_t max_iter, double tol, int32_t check_every, int32_t *iters,
+                                  double *relres, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgic.so")
 RSA_LIB = os.path.join(HERE, "libgicrsa.so")
-HIP_SOURCES = ["gic_api.hip", "sort.hip", "contact.hip", "transfer.hip", "integrate.hip", "adjoint.hip", "step.hip"]
+HIP_SOURCES = ["gic_api.hip", "sort.hip", "contact.hip", "transfer.hip", "integrate.hip", "adjoint.hip", "step.hip", "idp.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

@@ -153,6 +153,55 @@ hipError_t brick_list(gic_ctx *c, const int32_t *cb, const int32_t *ce, hipStrea
     return launch_brick_list(cb, ce, c->bricks, s);
 }
 
+// Density-projection workspace: alpha_f', s, r, d, w, 1/diag (G doubles
+// each), the partial sums and the solver state, each 256-byte aligned.
+int64_t idp_align(int64_t b) { return (b + 255) & ~(int64_t)255; }
+
+int64_t idp_work_bytes(int64_t G)
+{
+    return 6 * idp_align(G * 8) + idp_align(3 * kIdpMaxBlocks * 8) + idp_align(sizeof(CgState));
+}
+
+IdpWork idp_carve(void *work, int64_t G, double **at, double **s)
+{
+    char *p = (char *)work;
+    const int64_t a = idp_align(G * 8);
+    IdpWork W;
+    *at = (double *)p;
+    *s = (double *)(p + a);
+    W.r = (double *)(p + 2 * a);
+    W.d = (double *)(p + 3 * a);
+    W.w = (double *)(p + 4 * a);
+    W.dinv = (double *)(p + 5 * a);
+    W.part = (double *)(p + 6 * a);
+    W.state = (CgState *)(p + 6 * a + idp_align(3 * kIdpMaxBlocks * 8));
+    return W;
+}
+
+// Runs CG iterations in chunks of check_every, reading the state after each
+// chunk; the kernels of a chunk after convergence return at once.
+gic_status idp_cg(const gic_ctx *c, const double *at, const uint8_t *label, const double *s, double *q,
+                  const IdpWork &W, int32_t max_iter, double tol, int32_t check_every, int32_t *iters,
+                  double *relres, hipStream_t st)
+{
+    const IdpDims D = idp_dims(c->dp);
+    hipError_t e = launch_cg_start(D, at, label, s, q, W, tol, st);
+    CgState h;
+    int k = 0;
+    for (;;) {
+        if (e == hipSuccess) e = hipMemcpyAsync(&h, W.state, sizeof(h), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return GIC_E_HIP;
+        if (h.done >= 0 || k >= max_iter) break;
+        const int cnt = max_iter - k < check_every ? max_iter - k : check_every;
+        e = launch_cg_iterations(D, at, label, q, W, k, cnt, st);
+        k += cnt;
+    }
+    if (iters) *iters = (int32_t)(h.done >= 0 ? h.done : h.iters);
+    if (relres) *relres = h.ss > 0.0 ? sqrt(h.rr / h.ss) : sqrt(h.rr);
+    return GIC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -653,6 +702,64 @@ gic_status gic_permute(gic_ctx *c, int64_t n, int32_t comps, const int32_t *orde
     if (!n_ok(c, n) || comps < 1 || comps > 3) return GIC_E_ARG;
     if (n > 0 && (!order || !in || !out || in == out)) return GIC_E_ARG;
     return hip_status(launch_permute(n, comps, order, in, out, scatter ? 1 : 0, (hipStream_t)stream));
+}
+
+int64_t gic_idp_workspace_bytes(const gic_ctx *c)
+{
+    if (!c) return -1;
+    return idp_work_bytes(idp_dims(c->dp).G);
+}
+
+gic_status gic_idp_setup(gic_ctx *c, const int64_t *alpha_fx, const double *alpha_star, const uint8_t *label,
+                         double *alpha_t, double *rhs, void *stream)
+{
+    if (!c || !alpha_fx || !alpha_star || !label || !alpha_t || !rhs) return GIC_E_ARG;
+    return hip_status(launch_idp_setup(idp_dims(c->dp), c->dp.alpha_max, alpha_fx, alpha_star, label, alpha_t, rhs,
+                                       (hipStream_t)stream));
+}
+
+gic_status gic_idp_apply(gic_ctx *c, const double *alpha_t, const uint8_t *label, const double *q, double *out,
+                         void *stream)
+{
+    if (!c || !alpha_t || !label || !q || !out || out == q) return GIC_E_ARG;
+    return hip_status(launch_idp_apply(idp_dims(c->dp), alpha_t, label, q, out, (hipStream_t)stream));
+}
+
+gic_status gic_idp_solve(gic_ctx *c, const double *alpha_t, const uint8_t *label, const double *rhs, double *q,
+                         void *work, int32_t max_iter, double tol, int32_t check_every, int32_t *iters,
+                         double *relres, void *stream)
+{
+    if (!c || !alpha_t || !label || !rhs || !q || !work || max_iter < 0 || check_every < 1) return GIC_E_ARG;
+    if (!(tol >= 0.0) || !isfinite(tol)) return GIC_E_ARG;
+    const int64_t G = idp_dims(c->dp).G;
+    double *at_w, *s_w;
+    const IdpWork W = idp_carve(work, G, &at_w, &s_w);
+    return idp_cg(c, alpha_t, label, rhs, q, W, max_iter, tol, check_every, iters, relres, (hipStream_t)stream);
+}
+
+gic_status gic_idp_displacement(gic_ctx *c, const double *q, const uint8_t *label, double *fx, double *fy,
+                                double *fz, void *stream)
+{
+    if (!c || !q || !label || !fx || !fy || !fz) return GIC_E_ARG;
+    return hip_status(launch_idp_faces(idp_dims(c->dp), c->p.dx, q, label, fx, fy, fz, (hipStream_t)stream));
+}
+
+gic_status gic_density_projection(gic_ctx *c, const int64_t *alpha_fx, const double *alpha_star,
+                                  const uint8_t *label, double *q, double *fx, double *fy, double *fz, void *work,
+                                  int32_t max_iter, double tol, int32_t check_every, int32_t *iters,
+                                  double *relres, void *stream)
+{
+    if (!c || !alpha_fx || !alpha_star || !label || !q || !fx || !fy || !fz || !work) return GIC_E_ARG;
+    if (max_iter < 0 || check_every < 1 || !(tol >= 0.0) || !isfinite(tol)) return GIC_E_ARG;
+    const IdpDims D = idp_dims(c->dp);
+    hipStream_t s = (hipStream_t)stream;
+    double *at, *rhs;
+    const IdpWork W = idp_carve(work, D.G, &at, &rhs);
+    if (launch_idp_setup(D, c->dp.alpha_max, alpha_fx, alpha_star, label, at, rhs, s) != hipSuccess)
+        return GIC_E_HIP;
+    const gic_status st = idp_cg(c, at, label, rhs, q, W, max_iter, tol, check_every, iters, relres, s);
+    if (st != GIC_OK) return st;
+    return hip_status(launch_idp_faces(D, c->p.dx, q, label, fx, fy, fz, s));
 }
 
 }  // extern "C"

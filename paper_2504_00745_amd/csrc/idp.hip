@@ -1,0 +1,362 @@
+// f4: density projection of the fluid fraction (Sec. 5.1, Eq. 12b and 13;
+// App. B discretisation on the MAC grid) on gfx950.
+//
+// Cells are the transfer grid's nodes (cell centres, x fastest).  With the
+// scaled pressure q = (dt^2 / (rho_0 dx^2)) p_2, every fluid cell satisfies
+//     (L q)_c = sum_j beta_cj (q_c - q_j) = alpha'_c (clamp(alpha*_c / alpha'_c, 0.5, 1.5) - 1),
+// beta_cj = (alpha'_c + alpha'_j) / 2 over the six face neighbours that are
+// not solid (an air neighbour is a Dirichlet neighbour with q_j = 0; a solid
+// neighbour or the box boundary closes the face).  Non-fluid cells are
+// identity rows with a zero right-hand side, so L is symmetric positive
+// definite on the whole grid and the solution is zero off the fluid.
+//
+// The solve is Jacobi-preconditioned conjugate gradients.  Every kernel is a
+// streaming pass over the cells (HBM bound).  Dot products are reduced
+// without atomics: each block writes one partial per quantity, and every
+// block of the consuming kernel sums all partials in the same fixed order,
+// so the iteration is deterministic and needs no clearing between launches.
+#include "gic_launch.hpp"
+
+namespace gic {
+
+namespace {
+
+constexpr int kIdpThreads = 256;
+
+__device__ inline double block_sum(double v, double *red)
+{
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) red[w] = v;
+    __syncthreads();
+    return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Sum of the nb partials of a quantity, identical in every block.
+__device__ inline double sum_partials(const double *__restrict__ part, int nb, double *red)
+{
+    double v = 0.0;
+    for (int i = threadIdx.x; i < nb; i += kIdpThreads) v += part[i];
+    return block_sum(v, red);
+}
+
+struct Nbr {
+    int64_t off;   // index offset of the neighbour
+    bool inside;   // within the box
+};
+
+// The six face neighbours of cell (i, j, k) in the fixed order -x, +x, -y, +y, -z, +z.
+__device__ inline void neighbours(const IdpDims &D, int64_t c, Nbr nb[6])
+{
+    const int64_t i = c % D.nx, j = (c / D.nx) % D.ny, k = c / D.sxy;
+    nb[0] = {-1, i > 0};
+    nb[1] = {1, i < D.nx - 1};
+    nb[2] = {-D.nx, j > 0};
+    nb[3] = {D.nx, j < D.ny - 1};
+    nb[4] = {-D.sxy, k > 0};
+    nb[5] = {D.sxy, k < D.nz - 1};
+}
+
+// (L v)_c and the diagonal of L at c.
+__device__ inline void apply_row(const IdpDims &D, int64_t c, const double *__restrict__ at,
+                                 const uint8_t *__restrict__ lab, const double *__restrict__ v, double &Lv,
+                                 double &diag)
+{
+#pragma clang fp contract(off)
+    if (lab[c] != kIdpFluid) {
+        Lv = v[c];
+        diag = 1.0;
+        return;
+    }
+    Nbr nb[6];
+    neighbours(D, c, nb);
+    const double ac = at[c], vc = v[c];
+    double acc = 0.0, dg = 0.0;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        if (!nb[f].inside) continue;
+        const int64_t n = c + nb[f].off;
+        const uint8_t ln = lab[n];
+        if (ln == kIdpSolid) continue;
+        const double beta = (ac + at[n]) * 0.5;
+        const double vn = ln == kIdpFluid ? v[n] : 0.0;
+        acc += beta * (vc - vn);
+        dg += beta;
+    }
+    Lv = acc;
+    diag = dg;
+}
+
+__global__ void __launch_bounds__(kIdpThreads) k_idp_setup(IdpDims D, double alpha_max,
+                                                           const int64_t *__restrict__ afx,
+                                                           const double *__restrict__ astar,
+                                                           const uint8_t *__restrict__ lab, double *__restrict__ at,
+                                                           double *__restrict__ s)
+{
+#pragma clang fp contract(off)
+    for (int64_t c = (int64_t)blockIdx.x * kIdpThreads + threadIdx.x; c < D.G;
+         c += (int64_t)gridDim.x * kIdpThreads) {
+        double as = (double)afx[c] * 2.3283064365386963e-10;  // 2^-32
+        as = as < alpha_max ? as : alpha_max;
+        const double a = 1.0 - as;
+        at[c] = a;
+        double ratio = astar[c] / a;
+        ratio = ratio < 0.5 ? 0.5 : (ratio > 1.5 ? 1.5 : ratio);
+        s[c] = lab[c] == kIdpFluid ? a * (ratio - 1.0) : 0.0;
+    }
+}
+
+__global__ void __launch_bounds__(kIdpThreads) k_idp_apply(IdpDims D, const double *__restrict__ at,
+                                                           const uint8_t *__restrict__ lab,
+                                                           const double *__restrict__ v, double *__restrict__ out)
+{
+    for (int64_t c = (int64_t)blockIdx.x * kIdpThreads + threadIdx.x; c < D.G;
+         c += (int64_t)gridDim.x * kIdpThreads) {
+        double Lv, dg;
+        apply_row(D, c, at, lab, v, Lv, dg);
+        out[c] = Lv;
+    }
+}
+
+// CG start: r = s - L q, z = r / diag, d = z; partials of r.z, r.r, s.s.
+__global__ void __launch_bounds__(kIdpThreads) k_cg_init(IdpDims D, const double *__restrict__ at,
+                                                         const uint8_t *__restrict__ lab,
+                                                         const double *__restrict__ s, const double *__restrict__ q,
+                                                         double *__restrict__ r, double *__restrict__ d,
+                                                         double *__restrict__ dinv, double *__restrict__ part)
+{
+    __shared__ double red[4];
+    double rz = 0.0, rr = 0.0, ss = 0.0;
+    for (int64_t c = (int64_t)blockIdx.x * kIdpThreads + threadIdx.x; c < D.G;
+         c += (int64_t)gridDim.x * kIdpThreads) {
+        double Lq, dg;
+        apply_row(D, c, at, lab, q, Lq, dg);
+        const double sc = lab[c] == kIdpFluid ? s[c] : 0.0;
+        const double rc = sc - Lq;
+        const double di = dg > 0.0 ? 1.0 / dg : 0.0;  // a fluid cell walled in on all sides: singular row
+        const double zc = rc * di;
+        r[c] = rc;
+        d[c] = zc;
+        dinv[c] = di;
+        rz += rc * zc;
+        rr += rc * rc;
+        ss += sc * sc;
+    }
+    const int nb = gridDim.x;
+    rz = block_sum(rz, red);
+    rr = block_sum(rr, red);
+    ss = block_sum(ss, red);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = rz;
+        part[nb + blockIdx.x] = rr;
+        part[2 * nb + blockIdx.x] = ss;
+    }
+}
+
+// Reduces the start partials into the scalar state (one block).
+__global__ void __launch_bounds__(kIdpThreads) k_cg_start(int nb, const double *__restrict__ part, double tol,
+                                                          CgState *__restrict__ st)
+{
+    __shared__ double red[4];
+    const double rz = sum_partials(part, nb, red);
+    const double rr = sum_partials(part + nb, nb, red);
+    const double ss = sum_partials(part + 2 * nb, nb, red);
+    if (threadIdx.x == 0) {
+        st->rz[0] = rz;
+        st->rz[1] = rz;
+        st->ss = ss;
+        st->thr = tol * tol * ss;
+        st->rr = rr;
+        st->done = rr <= tol * tol * ss ? 0 : -1;
+        st->iters = 0;
+    }
+}
+
+// Iteration k, part 1: w = L d; partials of d.w.
+__global__ void __launch_bounds__(kIdpThreads) k_cg_apply(IdpDims D, const double *__restrict__ at,
+                                                          const uint8_t *__restrict__ lab,
+                                                          const double *__restrict__ d, double *__restrict__ w,
+                                                          double *__restrict__ part, const CgState *__restrict__ st)
+{
+    __shared__ double red[4];
+    if (st->done >= 0) return;
+    double dw = 0.0;
+    for (int64_t c = (int64_t)blockIdx.x * kIdpThreads + threadIdx.x; c < D.G;
+         c += (int64_t)gridDim.x * kIdpThreads) {
+        double Lv, dg;
+        apply_row(D, c, at, lab, d, Lv, dg);
+        w[c] = Lv;
+        dw += d[c] * Lv;
+    }
+    dw = block_sum(dw, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = dw;
+}
+
+// Iteration k, part 2: alpha = rz_k / (d.w); q += alpha d; r -= alpha w;
+// partials of r.z and r.r with z = r / diag.
+__global__ void __launch_bounds__(kIdpThreads) k_cg_update(IdpDims D, int k, const double *__restrict__ d,
+                                                           const double *__restrict__ w,
+                                                           const double *__restrict__ dinv, double *__restrict__ q,
+                                                           double *__restrict__ r, double *__restrict__ part,
+                                                           const CgState *__restrict__ st)
+{
+    __shared__ double red[4];
+    if (st->done >= 0) return;
+    const int nb = gridDim.x;
+    const double dw = sum_partials(part, nb, red);
+    const double alpha = st->rz[k & 1] / dw;
+    double rz = 0.0, rr = 0.0;
+    for (int64_t c = (int64_t)blockIdx.x * kIdpThreads + threadIdx.x; c < D.G;
+         c += (int64_t)gridDim.x * kIdpThreads) {
+        q[c] += alpha * d[c];
+        const double rc = r[c] - alpha * w[c];
+        r[c] = rc;
+        rz += rc * (rc * dinv[c]);
+        rr += rc * rc;
+    }
+    rz = block_sum(rz, red);
+    rr = block_sum(rr, red);
+    if (threadIdx.x == 0) {
+        part[nb + blockIdx.x] = rz;
+        part[2 * nb + blockIdx.x] = rr;
+    }
+}
+
+// Iteration k, part 3: rz_{k+1}, r.r; stop at r.r <= tol^2 s.s, else
+// d = z + (rz_{k+1} / rz_k) d.  Block 0 records the state for iteration k + 1
+// in the other rz slot (the current one is still read by other blocks).
+__global__ void __launch_bounds__(kIdpThreads) k_cg_direction(IdpDims D, int k, const double *__restrict__ r,
+                                                              const double *__restrict__ dinv,
+                                                              double *__restrict__ d,
+                                                              const double *__restrict__ part,
+                                                              CgState *__restrict__ st)
+{
+    __shared__ double red[4];
+    __shared__ int64_t s_done;
+    // block 0 of this kernel may set done while others start: read it once per block
+    if (threadIdx.x == 0) s_done = st->done;
+    __syncthreads();
+    if (s_done >= 0) return;
+    const int nb = gridDim.x;
+    const double rz1 = sum_partials(part + nb, nb, red);
+    const double rr = sum_partials(part + 2 * nb, nb, red);
+    const bool conv = rr <= st->thr;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->rz[(k + 1) & 1] = rz1;
+        st->rr = rr;
+        st->iters = k + 1;
+        if (conv) st->done = k + 1;
+    }
+    if (conv) return;
+    const double beta = rz1 / st->rz[k & 1];
+    for (int64_t c = (int64_t)blockIdx.x * kIdpThreads + threadIdx.x; c < D.G;
+         c += (int64_t)gridDim.x * kIdpThreads)
+        d[c] = r[c] * dinv[c] + beta * d[c];
+}
+
+// Face displacements (Eq. 13): for the face from cell c to its +axis
+// neighbour j, dx (q_c - q_j) with air sides at q = 0, where one side is fluid
+// and neither is solid, clamped to [-dx, dx]; faces on the box boundary are
+// zero.  The thread of cell c writes the three faces above it and, on the
+// lower box faces, the boundary face below it.
+__global__ void __launch_bounds__(kIdpThreads) k_idp_faces(IdpDims D, double dx, const double *__restrict__ q,
+                                                           const uint8_t *__restrict__ lab, double *__restrict__ fx,
+                                                           double *__restrict__ fy, double *__restrict__ fz)
+{
+#pragma clang fp contract(off)
+    for (int64_t c = (int64_t)blockIdx.x * kIdpThreads + threadIdx.x; c < D.G;
+         c += (int64_t)gridDim.x * kIdpThreads) {
+        const int64_t i = c % D.nx, j = (c / D.nx) % D.ny, k = c / D.sxy;
+        const uint8_t lc = lab[c];
+        const double qc = lc == kIdpFluid ? q[c] : 0.0;
+        const bool up[3] = {i < D.nx - 1, j < D.ny - 1, k < D.nz - 1};
+        const int64_t off[3] = {1, D.nx, D.sxy};
+        double *const F[3] = {fx, fy, fz};
+        // face index of the face above c along each axis
+        const int64_t fi[3] = {(k * D.ny + j) * (D.nx + 1) + i + 1, (k * (D.ny + 1) + j + 1) * D.nx + i,
+                               ((k + 1) * D.ny + j) * D.nx + i};
+        const int64_t step[3] = {1, D.nx, D.sxy};  // face-index distance to the face below c
+        const bool low[3] = {i == 0, j == 0, k == 0};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            double val = 0.0;
+            if (up[a]) {
+                const uint8_t ln = lab[c + off[a]];
+                const bool live =
+                    (lc == kIdpFluid || ln == kIdpFluid) && lc != kIdpSolid && ln != kIdpSolid;
+                if (live) {
+                    const double qn = ln == kIdpFluid ? q[c + off[a]] : 0.0;
+                    val = dx * (qc - qn);
+                    val = val > -dx ? val : -dx;
+                    val = val < dx ? val : dx;
+                }
+            }
+            F[a][fi[a]] = val;
+            if (low[a]) F[a][fi[a] - step[a]] = 0.0;
+        }
+    }
+}
+
+unsigned idp_blocks(int64_t G)
+{
+    const int64_t b = (G + kIdpThreads - 1) / kIdpThreads;
+    return (unsigned)(b < 1 ? 1 : (b > kIdpMaxBlocks ? kIdpMaxBlocks : b));
+}
+
+}  // namespace
+
+IdpDims idp_dims(const DevParams &P)
+{
+    IdpDims D;
+    D.nx = P.n[0];
+    D.ny = P.n[1];
+    D.nz = P.n[2];
+    D.sxy = D.nx * D.ny;
+    D.G = D.sxy * D.nz;
+    return D;
+}
+
+hipError_t launch_idp_setup(const IdpDims &D, double alpha_max, const int64_t *afx, const double *astar,
+                            const uint8_t *lab, double *at, double *s, hipStream_t st)
+{
+    k_idp_setup<<<idp_blocks(D.G), kIdpThreads, 0, st>>>(D, alpha_max, afx, astar, lab, at, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_idp_apply(const IdpDims &D, const double *at, const uint8_t *lab, const double *v, double *out,
+                            hipStream_t st)
+{
+    k_idp_apply<<<idp_blocks(D.G), kIdpThreads, 0, st>>>(D, at, lab, v, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_idp_faces(const IdpDims &D, double dx, const double *q, const uint8_t *lab, double *fx,
+                            double *fy, double *fz, hipStream_t st)
+{
+    k_idp_faces<<<idp_blocks(D.G), kIdpThreads, 0, st>>>(D, dx, q, lab, fx, fy, fz);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_start(const IdpDims &D, const double *at, const uint8_t *lab, const double *s, const double *q,
+                           const IdpWork &W, double tol, hipStream_t st)
+{
+    const unsigned nb = idp_blocks(D.G);
+    k_cg_init<<<nb, kIdpThreads, 0, st>>>(D, at, lab, s, q, W.r, W.d, W.dinv, W.part);
+    k_cg_start<<<1, kIdpThreads, 0, st>>>((int)nb, W.part, tol, W.state);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_iterations(const IdpDims &D, const double *at, const uint8_t *lab, double *q,
+                                const IdpWork &W, int k0, int count, hipStream_t st)
+{
+    const unsigned nb = idp_blocks(D.G);
+    for (int k = k0; k < k0 + count; ++k) {
+        k_cg_apply<<<nb, kIdpThreads, 0, st>>>(D, at, lab, W.d, W.w, W.part, W.state);
+        k_cg_update<<<nb, kIdpThreads, 0, st>>>(D, k, W.d, W.w, W.dinv, q, W.r, W.part, W.state);
+        k_cg_direction<<<nb, kIdpThreads, 0, st>>>(D, k, W.r, W.dinv, W.d, W.part, W.state);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace gic

@@ -64,6 +64,12 @@ def lib():
             "gic_contact_forces": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V, _V]),
             "gic_contact_capillary_forces": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V, _V, _V]),
             "gic_moisture_ratio": (C.c_int, [_V, _I64, _V, _V, _V, _V]),
+            "gic_idp_workspace_bytes": (_I64, [_V]),
+            "gic_idp_setup": (C.c_int, [_V] * 7),
+            "gic_idp_apply": (C.c_int, [_V] * 6),
+            "gic_idp_solve": (C.c_int, [_V] * 6 + [_I32, C.c_double, _I32, _V, _V, _V]),
+            "gic_idp_displacement": (C.c_int, [_V] * 7),
+            "gic_density_projection": (C.c_int, [_V] * 9 + [_I32, C.c_double, _I32, _V, _V, _V]),
             "gic_contact_pairs": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _I64, _V, _V]),
             "gic_g2p": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V]),
             "gic_drag": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V]),
@@ -228,6 +234,68 @@ def gic_moisture_ratio(ctx, held, alpha_f, sr):
     _check(lib().gic_moisture_ratio(ctx.handle, n, _ptr(held, ctx.real, n, "held"),
                                     _ptr(alpha_f, ctx.real, n, "alpha_f"), _ptr(sr, ctx.real, n, "sr"), _stream()),
            "gic_moisture_ratio")
+
+
+# ---- density projection (Sec. 5.1, Eq. 12b, 13): grids of G cells, double;
+# labels uint8 (0 fluid, 1 air, 2 solid) -------------------------------------
+
+def _faces(ctx):
+    n0, n1, n2 = (int(v) for v in ctx.cfg["n"])
+    return (n0 + 1) * n1 * n2, n0 * (n1 + 1) * n2, n0 * n1 * (n2 + 1)
+
+
+def idp_workspace(ctx):
+    """A device workspace for gic_idp_solve / gic_density_projection."""
+    nbytes = int(lib().gic_idp_workspace_bytes(ctx.handle))
+    return torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+
+
+def gic_idp_setup(ctx, alpha_fx, alpha_star, label, alpha_t, rhs):
+    G, f64 = ctx.G, torch.float64
+    _check(lib().gic_idp_setup(ctx.handle, _ptr(alpha_fx, torch.int64, G), _ptr(alpha_star, f64, G, "alpha_star"),
+                               _ptr(label, torch.uint8, G, "label"), _ptr(alpha_t, f64, G, "alpha_t"),
+                               _ptr(rhs, f64, G, "rhs"), _stream()), "gic_idp_setup")
+
+
+def gic_idp_apply(ctx, alpha_t, label, q, out):
+    G, f64 = ctx.G, torch.float64
+    _check(lib().gic_idp_apply(ctx.handle, _ptr(alpha_t, f64, G), _ptr(label, torch.uint8, G), _ptr(q, f64, G),
+                               _ptr(out, f64, G), _stream()), "gic_idp_apply")
+
+
+def gic_idp_solve(ctx, alpha_t, label, rhs, q, work, max_iter=2000, tol=1e-8, check_every=32):
+    """Solves L q = rhs in place (q: initial guess in, solution out);
+    returns (iterations, relative residual).  Synchronises."""
+    G, f64 = ctx.G, torch.float64
+    it, rel = _I32(), C.c_double()
+    _check(lib().gic_idp_solve(ctx.handle, _ptr(alpha_t, f64, G), _ptr(label, torch.uint8, G), _ptr(rhs, f64, G),
+                               _ptr(q, f64, G), _ptr(work, torch.uint8, int(lib().gic_idp_workspace_bytes(ctx.handle))),
+                               int(max_iter), float(tol), int(check_every), C.byref(it), C.byref(rel), _stream()),
+           "gic_idp_solve")
+    return int(it.value), float(rel.value)
+
+
+def gic_idp_displacement(ctx, q, label, fx, fy, fz):
+    G, f64 = ctx.G, torch.float64
+    nfx, nfy, nfz = _faces(ctx)
+    _check(lib().gic_idp_displacement(ctx.handle, _ptr(q, f64, G), _ptr(label, torch.uint8, G),
+                                      _ptr(fx, f64, nfx, "fx"), _ptr(fy, f64, nfy, "fy"), _ptr(fz, f64, nfz, "fz"),
+                                      _stream()), "gic_idp_displacement")
+
+
+def gic_density_projection(ctx, alpha_fx, alpha_star, label, q, fx, fy, fz, work, max_iter=2000, tol=1e-8,
+                           check_every=32):
+    """The whole projection; returns (iterations, relative residual)."""
+    G, f64 = ctx.G, torch.float64
+    nfx, nfy, nfz = _faces(ctx)
+    it, rel = _I32(), C.c_double()
+    _check(lib().gic_density_projection(ctx.handle, _ptr(alpha_fx, torch.int64, G), _ptr(alpha_star, f64, G),
+                                        _ptr(label, torch.uint8, G), _ptr(q, f64, G), _ptr(fx, f64, nfx, "fx"),
+                                        _ptr(fy, f64, nfy, "fy"), _ptr(fz, f64, nfz, "fz"),
+                                        _ptr(work, torch.uint8, int(lib().gic_idp_workspace_bytes(ctx.handle))),
+                                        int(max_iter), float(tol), int(check_every), C.byref(it), C.byref(rel),
+                                        _stream()), "gic_density_projection")
+    return int(it.value), float(rel.value)
 
 
 def gic_contact_pairs(ctx, x, r, cell_begin, cell_end, pairs, count):

@@ -256,3 +256,55 @@ def make(name: str, seed=None, n_override=None) -> dict:
     return dict(name=name, x=np.ascontiguousarray(x), v=np.ascontiguousarray(v), r=np.ascontiguousarray(r),
                 u=np.ascontiguousarray(u), params=p, steps=s["steps"], precision=s["precision"])
 
+
+
+# ---------------------------------------------------------------------------
+# Density-projection inputs (Sec. 5.1): a sand fraction grid in int64 fixed
+# point (what the P2G of a bed gives), the fluid particles' own fraction and
+# the cell labels (0 fluid, 1 air, 2 solid), seeded and synthetic.
+# ---------------------------------------------------------------------------
+
+IDP_CASES = ("p1", "p2", "c3")
+
+
+def idp_case(name: str, seed=None) -> dict:
+    """p1: 32^3 cells dx = 0.02; p2: a ragged 23 x 17 x 29 grid; c3: the
+    dam-break grid (256 x 128 x 128, dx = 0.004) with the sand column of the
+    c3 bed (x < 0.256 m, z < 0.256 m, solid fraction pi/6).  Each: fluid up
+    to 3/4 of the height and air above, a submerged solid block, the sand
+    fraction of the column (or blob) with +-0.01 noise, and the fluid
+    particles' fraction = (1 - sand fraction)(1 + 0.08 f) with f a smooth
+    seeded field of unit amplitude, compressed 1.8-fold in a ball (beyond the
+    1.5 clamp of the ratio)."""
+    if name == "p1":
+        n, dx, s0 = (32, 32, 32), 0.02, 11
+    elif name == "p2":
+        n, dx, s0 = (23, 17, 29), 0.02, 12
+    elif name == "c3":
+        n, dx, s0 = (256, 128, 128), 0.004, 13
+    else:
+        raise KeyError(name)
+    rng = np.random.Generator(np.random.PCG64(s0 if seed is None else seed))
+    nx, ny, nz = n
+    zc, yc, xc = np.meshgrid(*[(np.arange(m) + 0.5) * dx for m in (nz, ny, nx)], indexing="ij")
+    L = np.array([nx, ny, nz]) * dx
+    if name == "c3":
+        sand = np.where((xc < 0.256) & (zc < 0.256), math.pi / 6.0, 0.0)
+    else:
+        c = np.array([0.3, 0.5, 0.35]) * L
+        blob = np.exp(-(((xc - c[0]) ** 2 + (yc - c[1]) ** 2 + (zc - c[2]) ** 2) / (2 * (0.2 * L.min()) ** 2)))
+        sand = 0.62 * blob + np.where(xc < 0.2 * L[0], 0.55, 0.0)
+    sand = np.clip(sand + rng.uniform(-0.01, 0.01, sand.shape) * (sand > 0), 0.0, 0.95)
+    alpha_fx = np.rint(sand * 2.0 ** 32).astype(np.int64)
+    f = fourier_field(n, dx, 8, 1.0, rng)[0].reshape(nz, ny, nx)
+    f /= max(np.abs(f).max(), 1e-300)
+    astar = (1.0 - sand) * (1.0 + 0.08 * f)
+    cb = np.array([0.7, 0.4, 0.3]) * L
+    ball = (xc - cb[0]) ** 2 + (yc - cb[1]) ** 2 + (zc - cb[2]) ** 2 < (0.1 * L.min()) ** 2
+    astar = np.where(ball, 1.8 * astar, astar)
+    label = np.zeros((nz, ny, nx), np.uint8)
+    label[int(round(0.75 * nz)):] = 1
+    label[: nz // 3, ny // 3: ny // 2, int(0.6 * nx): int(0.75 * nx)] = 2
+    p = _params(n, dx, dx, 1e-4, (0.0, 0.0, -9.81))
+    return dict(name=name, params=p, alpha_fx=alpha_fx.reshape(-1), alpha_star=astar.reshape(-1),
+                label=label.reshape(-1), shape=(nz, ny, nx))
