@@ -363,13 +363,23 @@ def time_capillary(d, wl_name, reps=10):
 # per cell: w = L d (d, alpha_f', label; w), the update (d, w, 1/diag, q, r;
 # q, r) and the new direction (r, 1/diag, d; d).
 IDP_BYTES_PER_CELL_ITER = (8 + 8 + 1 + 8) + (5 * 8 + 2 * 8) + (3 * 8 + 8)
+# With the multigrid V-cycle: w = L d (25), the update without r.z (d, w, q, r;
+# q, r: 48), per fine cell pre-smoothing (b, 1/diag, alpha_f', label; e: 33),
+# restriction (e, b, alpha_f', label: 25 + 1/8 of a coarse write), the first
+# post-sweep with the coarse correction (e, b, 1/diag, alpha_f', label, 1/8 of
+# the coarse e and label; t: 42) and the second (t, b, 1/diag, alpha_f', label;
+# e: 41), the new direction (z, d; d: 24); coarser levels add the four passes'
+# bytes times 1/8 + 1/64 + ... = 1/7.
+IDP_MG_BYTES_PER_CELL_ITER = 25 + 48 + 33 + 26 + 42 + 41 + 24 + (33 + 26 + 42 + 41) / 7.0
 
 
 def time_idp(reps=3, tol=1e-6):
     """Density projection (Sec. 5.1, Eq. 12b-13) on the dam-break grid
-    (256 x 128 x 128 cells), cold start, relative residual 1e-6, checks every
-    32 iterations: whole projections timed with events, then the iteration
-    kernels alone (a fixed 64 iterations) for their per-iteration rate."""
+    (256 x 128 x 128 cells), cold start, relative residual 1e-6: whole
+    projections with the multigrid preconditioner (state checked every 8
+    iterations) and with the Jacobi one (every 32), timed with events; then
+    each solver's iterations alone (a fixed count with a tolerance never met)
+    for the per-iteration rate and its roofline."""
     import torch
     from paper_2504_00745_amd import gic, workloads as wl
     d = wl.idp_case("c3")
@@ -384,40 +394,44 @@ def time_idp(reps=3, tol=1e-6):
     fy = torch.empty(nx * (ny + 1) * nz, dtype=torch.float64, device="cuda")
     fz = torch.empty(nx * ny * (nz + 1), dtype=torch.float64, device="cuda")
     work = gic.idp_workspace(ctx)
-    gic.gic_density_projection(ctx, afx, ast, lab, q, fx, fy, fz, work, max_iter=5000, tol=tol)  # warm-up
-    ts, its = [], []
-    for _ in range(reps):
-        q.zero_()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        it, rel = gic.gic_density_projection(ctx, afx, ast, lab, q, fx, fy, fz, work, max_iter=5000, tol=tol,
-                                             check_every=32)
-        e1.record()
-        torch.cuda.synchronize()
-        ts.append(e0.elapsed_time(e1) / 1e3)
-        its.append(it)
-    # iteration kernels alone: 64 iterations with a tolerance that is never met
     at = torch.empty(G, dtype=torch.float64, device="cuda")
     s = torch.empty_like(at)
     gic.gic_idp_setup(ctx, afx, ast, lab, at, s)
-    q.zero_()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    gic.gic_idp_solve(ctx, at, lab, s, q, work, max_iter=64, tol=0.0, check_every=64)
-    e1.record()
-    torch.cuda.synchronize()
-    t_it = e0.elapsed_time(e1) / 1e3 / 64
-    ach = IDP_BYTES_PER_CELL_ITER * G / t_it / 1e9
-    t = float(np.median(ts))
+    out = {}
+    for pc, name, chk, fixed in ((1, "multigrid", 8, 16), (0, "jacobi", 32, 64)):
+        q.zero_()
+        gic.gic_density_projection(ctx, afx, ast, lab, q, fx, fy, fz, work, max_iter=5000, tol=tol,
+                                   check_every=chk, precond=pc)  # warm-up
+        ts = []
+        for _ in range(reps):
+            q.zero_()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            it, rel = gic.gic_density_projection(ctx, afx, ast, lab, q, fx, fy, fz, work, max_iter=5000, tol=tol,
+                                                 check_every=chk, precond=pc)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) / 1e3)
+        q.zero_()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        gic.gic_idp_solve(ctx, at, lab, s, q, work, max_iter=fixed, tol=0.0, check_every=fixed, precond=pc)
+        e1.record()
+        torch.cuda.synchronize()
+        t_it = e0.elapsed_time(e1) / 1e3 / fixed
+        per = IDP_MG_BYTES_PER_CELL_ITER if pc else IDP_BYTES_PER_CELL_ITER
+        ach = per * G / t_it / 1e9
+        out[name] = {"ms_per_projection": round(float(np.median(ts)) * 1e3, 3), "iterations": int(it),
+                     "relres": rel, "us_per_iteration": round(t_it * 1e6, 2),
+                     "roofline": {"bound": "hbm", "kernel": f"PCG iteration ({name})", "achieved": ach,
+                                  "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                                  "algorithmic_bytes": per * G, "traffic": None}}
+    t = out["multigrid"]["ms_per_projection"] / 1e3
     return {"workload": "dam-break grid 256 x 128 x 128 cells (dx = 0.004): sand column of the c3 bed, fluid to "
                         "3/4 height, air above, a submerged solid block, fluid fraction perturbed 8 % and "
-                        "compressed 1.8x in a ball; Jacobi-preconditioned CG from zero to relative residual 1e-6",
-            "ms_per_projection": round(t * 1e3, 3), "iterations": int(its[0]), "relres": rel,
-            "us_per_iteration": round(t_it * 1e6, 2), "value": G / t, "unit": "cells/s (whole projection)",
-            "roofline": {"bound": "hbm", "kernel": "CG iteration (3 kernels)", "achieved": ach,
-                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                         "algorithmic_bytes": IDP_BYTES_PER_CELL_ITER * G, "traffic": None}}
+                        "compressed 1.8x in a ball; PCG from zero to relative residual 1e-6",
+            "value": G / t, "unit": "cells/s (whole projection, multigrid)", **out}
 
 
 def touched_nodes(sim):

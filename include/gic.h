@@ -457,11 +457,19 @@ gic_status gic_idp_apply(gic_ctx *ctx, const double *alpha_t, const uint8_t *lab
                          void *stream);
 
 /* Bytes of the caller-owned device workspace that gic_idp_solve and
- * gic_density_projection need (about 48 G; -1 for a NULL context). */
+ * gic_density_projection need with either preconditioner (about 70 G; -1
+ * for a NULL context). */
 int64_t gic_idp_workspace_bytes(const gic_ctx *ctx);
 
-/* Solves L q = rhs by conjugate gradients with the Jacobi preconditioner,
- * starting from the q passed in (q = 0 for a cold start); stops when
+/* Solves L q = rhs by preconditioned conjugate gradients, starting from the
+ * q passed in (q = 0 for a cold start).  precond 0: Jacobi (1 / diag L);
+ * precond 1: one multigrid V-cycle per iteration (levels halve each axis,
+ * rounding up, down to at most 256 cells; a coarse cell is air if a child
+ * is, else fluid if a child is, else solid, with the mean alpha_f' of its
+ * children; level l uses 4^l L of its own cells; piecewise-constant
+ * prolongation and its transpose; two damped Jacobi sweeps, omega = 2/3,
+ * before and after the coarse correction; 48 sweeps on the coarsest level),
+ * a symmetric preconditioner, so CG applies.  Stops when
  * |r|_2 <= tol |rhs|_2 (recursively updated residual) or after max_iter
  * iterations.  Enqueues check_every iterations at a time and SYNCHRONISES the
  * stream after each chunk to read the state; iterations of a chunk after
@@ -470,8 +478,8 @@ int64_t gic_idp_workspace_bytes(const gic_ctx *ctx);
  * rhs = 0).  GIC_OK also when max_iter is reached: check *relres.  work: at
  * least gic_idp_workspace_bytes bytes of device memory, 256-byte aligned. */
 gic_status gic_idp_solve(gic_ctx *ctx, const double *alpha_t, const uint8_t *label, const double *rhs, double *q,
-                         void *work, int32_t max_iter, double tol, int32_t check_every, int32_t *iters,
-                         double *relres, void *stream);
+                         void *work, int32_t max_iter, double tol, int32_t check_every, int32_t precond,
+                         int32_t *iters, double *relres, void *stream);
 
 /* Position change on the MAC faces (Eq. 13 in q): for the face between cell
  * c and its +axis neighbour j, dx (q_c - q_j) (air sides count as q = 0; a
@@ -488,8 +496,8 @@ gic_status gic_idp_displacement(gic_ctx *ctx, const double *q, const uint8_t *la
  * Synchronises like gic_idp_solve. */
 gic_status gic_density_projection(gic_ctx *ctx, const int64_t *alpha_fx, const double *alpha_star,
                                   const uint8_t *label, double *q, double *fx, double *fy, double *fz, void *work,
-                                  int32_t max_iter, double tol, int32_t check_every, int32_t *iters,
-                                  double *relres, void *stream);
+                                  int32_t max_iter, double tol, int32_t check_every, int32_t precond,
+                                  int32_t *iters, double *relres, void *stream);
 
 #ifdef __cplusplus
 }

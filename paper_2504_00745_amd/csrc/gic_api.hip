@@ -157,15 +157,41 @@ hipError_t brick_list(gic_ctx *c, const int32_t *cb, const int32_t *ce, hipStrea
 // each), the partial sums and the solver state, each 256-byte aligned.
 int64_t idp_align(int64_t b) { return (b + 255) & ~(int64_t)255; }
 
-int64_t idp_work_bytes(int64_t G)
+// Levels of the multigrid hierarchy: halve every axis (rounding up) until a
+// level has at most kMgCoarsest cells.
+int idp_levels(const IdpDims &D0, IdpDims *out)
 {
-    return 6 * idp_align(G * 8) + idp_align(3 * kIdpMaxBlocks * 8) + idp_align(sizeof(CgState));
+    out[0] = D0;
+    int l = 0;
+    while (out[l].G > kMgCoarsest && l + 1 < kMgMaxLevels) {
+        IdpDims n;
+        n.nx = (out[l].nx + 1) / 2;
+        n.ny = (out[l].ny + 1) / 2;
+        n.nz = (out[l].nz + 1) / 2;
+        n.sxy = n.nx * n.ny;
+        n.G = n.sxy * n.nz;
+        out[++l] = n;
+    }
+    return l + 1;
 }
 
-IdpWork idp_carve(void *work, int64_t G, double **at, double **s)
+int64_t idp_work_bytes(const IdpDims &D0)
+{
+    IdpDims lv[kMgMaxLevels];
+    const int L = idp_levels(D0, lv);
+    int64_t b = 8 * idp_align(D0.G * 8) + idp_align(3 * kIdpMaxBlocks * 8) + idp_align(sizeof(CgState));
+    for (int l = 1; l < L; ++l) b += 5 * idp_align(lv[l].G * 8) + idp_align(lv[l].G);
+    return b;
+}
+
+// Carves the workspace: alpha_f' and s slots for gic_density_projection, the
+// CG vectors, and (multigrid) the levels; level 0 works on the caller's
+// alpha_f' and labels, the residual r and the preconditioned residual z.
+IdpWork idp_carve(void *work, const IdpDims &D0, int precond, const double *at0, const uint8_t *lab0, double **at,
+                  double **s)
 {
     char *p = (char *)work;
-    const int64_t a = idp_align(G * 8);
+    const int64_t a = idp_align(D0.G * 8);
     IdpWork W;
     *at = (double *)p;
     *s = (double *)(p + a);
@@ -173,8 +199,32 @@ IdpWork idp_carve(void *work, int64_t G, double **at, double **s)
     W.d = (double *)(p + 3 * a);
     W.w = (double *)(p + 4 * a);
     W.dinv = (double *)(p + 5 * a);
-    W.part = (double *)(p + 6 * a);
-    W.state = (CgState *)(p + 6 * a + idp_align(3 * kIdpMaxBlocks * 8));
+    double *z = (double *)(p + 6 * a), *t = (double *)(p + 7 * a);
+    p += 8 * a;
+    W.part = (double *)p;
+    p += idp_align(3 * kIdpMaxBlocks * 8);
+    W.state = (CgState *)p;
+    p += idp_align(sizeof(CgState));
+    IdpDims lv[kMgMaxLevels];
+    const int L = idp_levels(D0, lv);
+    W.nlev = precond == 1 ? L : 1;
+    W.lev[0] = MgLevel{D0, 1.0, const_cast<double *>(at0 ? at0 : *at), const_cast<uint8_t *>(lab0), W.dinv, W.r, z, t};
+    double scale = 1.0;
+    for (int l = 1; l < L; ++l) {
+        scale *= 4.0;
+        const int64_t g = idp_align(lv[l].G * 8);
+        MgLevel m;
+        m.D = lv[l];
+        m.scale = scale;
+        m.at = (double *)p;
+        m.dinv = (double *)(p + g);
+        m.b = (double *)(p + 2 * g);
+        m.e = (double *)(p + 3 * g);
+        m.t = (double *)(p + 4 * g);
+        m.lab = (uint8_t *)(p + 5 * g);
+        p += 5 * g + idp_align(lv[l].G);
+        W.lev[l] = m;
+    }
     return W;
 }
 
@@ -707,7 +757,7 @@ gic_status gic_permute(gic_ctx *c, int64_t n, int32_t comps, const int32_t *orde
 int64_t gic_idp_workspace_bytes(const gic_ctx *c)
 {
     if (!c) return -1;
-    return idp_work_bytes(idp_dims(c->dp).G);
+    return idp_work_bytes(idp_dims(c->dp));
 }
 
 gic_status gic_idp_setup(gic_ctx *c, const int64_t *alpha_fx, const double *alpha_star, const uint8_t *label,
@@ -726,14 +776,13 @@ gic_status gic_idp_apply(gic_ctx *c, const double *alpha_t, const uint8_t *label
 }
 
 gic_status gic_idp_solve(gic_ctx *c, const double *alpha_t, const uint8_t *label, const double *rhs, double *q,
-                         void *work, int32_t max_iter, double tol, int32_t check_every, int32_t *iters,
-                         double *relres, void *stream)
+                         void *work, int32_t max_iter, double tol, int32_t check_every, int32_t precond,
+                         int32_t *iters, double *relres, void *stream)
 {
     if (!c || !alpha_t || !label || !rhs || !q || !work || max_iter < 0 || check_every < 1) return GIC_E_ARG;
-    if (!(tol >= 0.0) || !isfinite(tol)) return GIC_E_ARG;
-    const int64_t G = idp_dims(c->dp).G;
+    if (!(tol >= 0.0) || !isfinite(tol) || (precond != 0 && precond != 1)) return GIC_E_ARG;
     double *at_w, *s_w;
-    const IdpWork W = idp_carve(work, G, &at_w, &s_w);
+    const IdpWork W = idp_carve(work, idp_dims(c->dp), precond, alpha_t, label, &at_w, &s_w);
     return idp_cg(c, alpha_t, label, rhs, q, W, max_iter, tol, check_every, iters, relres, (hipStream_t)stream);
 }
 
@@ -746,15 +795,16 @@ gic_status gic_idp_displacement(gic_ctx *c, const double *q, const uint8_t *labe
 
 gic_status gic_density_projection(gic_ctx *c, const int64_t *alpha_fx, const double *alpha_star,
                                   const uint8_t *label, double *q, double *fx, double *fy, double *fz, void *work,
-                                  int32_t max_iter, double tol, int32_t check_every, int32_t *iters,
-                                  double *relres, void *stream)
+                                  int32_t max_iter, double tol, int32_t check_every, int32_t precond,
+                                  int32_t *iters, double *relres, void *stream)
 {
     if (!c || !alpha_fx || !alpha_star || !label || !q || !fx || !fy || !fz || !work) return GIC_E_ARG;
     if (max_iter < 0 || check_every < 1 || !(tol >= 0.0) || !isfinite(tol)) return GIC_E_ARG;
+    if (precond != 0 && precond != 1) return GIC_E_ARG;
     const IdpDims D = idp_dims(c->dp);
     hipStream_t s = (hipStream_t)stream;
     double *at, *rhs;
-    const IdpWork W = idp_carve(work, D.G, &at, &rhs);
+    const IdpWork W = idp_carve(work, D, precond, nullptr, label, &at, &rhs);
     if (launch_idp_setup(D, c->dp.alpha_max, alpha_fx, alpha_star, label, at, rhs, s) != hipSuccess)
         return GIC_E_HIP;
     const gic_status st = idp_cg(c, at, label, rhs, q, W, max_iter, tol, check_every, iters, relres, s);

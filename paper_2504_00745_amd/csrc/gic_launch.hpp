@@ -137,11 +137,28 @@ struct CgState {
     int64_t iters;  // completed iterations
 };
 
-// Solver workspace carved from one caller buffer.
+// One level of the multigrid preconditioner: its cells, operator scale
+// (A_l = scale L_l), alpha_f', labels, 1 / diag(A_l), right-hand side,
+// correction and a second correction buffer.
+struct MgLevel {
+    IdpDims D;
+    double scale;
+    double *at;
+    uint8_t *lab;
+    double *dinv, *b, *e, *t;
+};
+
+constexpr int kMgMaxLevels = 24;
+constexpr int64_t kMgCoarsest = 256;  // cells of the coarsest level, solved in one block
+
+// Solver workspace carved from one caller buffer.  nlev = 1: Jacobi
+// preconditioner; nlev > 1: multigrid over lev[0 .. nlev).
 struct IdpWork {
     double *r, *d, *w, *dinv;
     double *part;     // [3 * kIdpMaxBlocks]
     CgState *state;
+    int nlev;
+    MgLevel lev[kMgMaxLevels];
 };
 
 IdpDims idp_dims(const DevParams &P);

@@ -46,16 +46,40 @@ struct Nbr {
     bool inside;   // within the box
 };
 
-// The six face neighbours of cell (i, j, k) in the fixed order -x, +x, -y, +y, -z, +z.
-__device__ inline void neighbours(const IdpDims &D, int64_t c, Nbr nb[6])
+// Coordinates of cell c (32-bit division when the grid allows it).
+__device__ inline void coords(const IdpDims &D, int64_t c, int64_t &i, int64_t &j, int64_t &k)
 {
-    const int64_t i = c % D.nx, j = (c / D.nx) % D.ny, k = c / D.sxy;
+    if (D.G <= 0xffffffffll) {
+        const uint32_t cc = (uint32_t)c, nx = (uint32_t)D.nx, ny = (uint32_t)D.ny;
+        const uint32_t row = cc / nx;
+        i = cc - row * nx;
+        const uint32_t kk = row / ny;
+        j = row - kk * ny;
+        k = kk;
+    } else {
+        const int64_t row = c / D.nx;
+        i = c - row * D.nx;
+        k = row / D.ny;
+        j = row - k * D.ny;
+    }
+}
+
+// The six face neighbours of cell c = (i, j, k) in the fixed order -x, +x, -y, +y, -z, +z.
+__device__ inline void neighbours(const IdpDims &D, int64_t i, int64_t j, int64_t k, Nbr nb[6])
+{
     nb[0] = {-1, i > 0};
     nb[1] = {1, i < D.nx - 1};
     nb[2] = {-D.nx, j > 0};
     nb[3] = {D.nx, j < D.ny - 1};
     nb[4] = {-D.sxy, k > 0};
     nb[5] = {D.sxy, k < D.nz - 1};
+}
+
+__device__ inline void neighbours(const IdpDims &D, int64_t c, Nbr nb[6])
+{
+    int64_t i, j, k;
+    coords(D, c, i, j, k);
+    neighbours(D, i, j, k, nb);
 }
 
 // (L v)_c and the diagonal of L at c.
@@ -119,12 +143,13 @@ __global__ void __launch_bounds__(kIdpThreads) k_idp_apply(IdpDims D, const doub
     }
 }
 
-// CG start: r = s - L q, z = r / diag, d = z; partials of r.z, r.r, s.s.
+// CG start: r = s - L q, z = r / diag, d = z; partials of s.s, r.z, r.r.
 __global__ void __launch_bounds__(kIdpThreads) k_cg_init(IdpDims D, const double *__restrict__ at,
                                                          const uint8_t *__restrict__ lab,
                                                          const double *__restrict__ s, const double *__restrict__ q,
                                                          double *__restrict__ r, double *__restrict__ d,
-                                                         double *__restrict__ dinv, double *__restrict__ part)
+                                                         double *__restrict__ dinv, double *__restrict__ part,
+                                                         CgState *__restrict__ st)
 {
     __shared__ double red[4];
     double rz = 0.0, rr = 0.0, ss = 0.0;
@@ -148,9 +173,10 @@ __global__ void __launch_bounds__(kIdpThreads) k_cg_init(IdpDims D, const double
     rr = block_sum(rr, red);
     ss = block_sum(ss, red);
     if (threadIdx.x == 0) {
-        part[blockIdx.x] = rz;
-        part[nb + blockIdx.x] = rr;
-        part[2 * nb + blockIdx.x] = ss;
+        part[blockIdx.x] = ss;
+        part[nb + blockIdx.x] = rz;
+        part[2 * nb + blockIdx.x] = rr;
+        if (blockIdx.x == 0) st->done = -1;  // kernels of a previous solve may have left it set
     }
 }
 
@@ -159,9 +185,9 @@ __global__ void __launch_bounds__(kIdpThreads) k_cg_start(int nb, const double *
                                                           CgState *__restrict__ st)
 {
     __shared__ double red[4];
-    const double rz = sum_partials(part, nb, red);
-    const double rr = sum_partials(part + nb, nb, red);
-    const double ss = sum_partials(part + 2 * nb, nb, red);
+    const double ss = sum_partials(part, nb, red);
+    const double rz = sum_partials(part + nb, nb, red);
+    const double rr = sum_partials(part + 2 * nb, nb, red);
     if (threadIdx.x == 0) {
         st->rz[0] = rz;
         st->rz[1] = rz;
@@ -194,7 +220,8 @@ __global__ void __launch_bounds__(kIdpThreads) k_cg_apply(IdpDims D, const doubl
 }
 
 // Iteration k, part 2: alpha = rz_k / (d.w); q += alpha d; r -= alpha w;
-// partials of r.z and r.r with z = r / diag.
+// partials of r.r and, with the Jacobi preconditioner, of r.z with z = r / diag.
+template <bool JAC>
 __global__ void __launch_bounds__(kIdpThreads) k_cg_update(IdpDims D, int k, const double *__restrict__ d,
                                                            const double *__restrict__ w,
                                                            const double *__restrict__ dinv, double *__restrict__ q,
@@ -212,13 +239,13 @@ __global__ void __launch_bounds__(kIdpThreads) k_cg_update(IdpDims D, int k, con
         q[c] += alpha * d[c];
         const double rc = r[c] - alpha * w[c];
         r[c] = rc;
-        rz += rc * (rc * dinv[c]);
+        if (JAC) rz += rc * (rc * dinv[c]);
         rr += rc * rc;
     }
-    rz = block_sum(rz, red);
+    if (JAC) rz = block_sum(rz, red);
     rr = block_sum(rr, red);
     if (threadIdx.x == 0) {
-        part[nb + blockIdx.x] = rz;
+        if (JAC) part[nb + blockIdx.x] = rz;  // with multigrid the V-cycle writes r.z
         part[2 * nb + blockIdx.x] = rr;
     }
 }
@@ -226,9 +253,10 @@ __global__ void __launch_bounds__(kIdpThreads) k_cg_update(IdpDims D, int k, con
 // Iteration k, part 3: rz_{k+1}, r.r; stop at r.r <= tol^2 s.s, else
 // d = z + (rz_{k+1} / rz_k) d.  Block 0 records the state for iteration k + 1
 // in the other rz slot (the current one is still read by other blocks).
+template <bool JAC>
 __global__ void __launch_bounds__(kIdpThreads) k_cg_direction(IdpDims D, int k, const double *__restrict__ r,
                                                               const double *__restrict__ dinv,
-                                                              double *__restrict__ d,
+                                                              const double *__restrict__ z, double *__restrict__ d,
                                                               const double *__restrict__ part,
                                                               CgState *__restrict__ st)
 {
@@ -252,7 +280,7 @@ __global__ void __launch_bounds__(kIdpThreads) k_cg_direction(IdpDims D, int k, 
     const double beta = rz1 / st->rz[k & 1];
     for (int64_t c = (int64_t)blockIdx.x * kIdpThreads + threadIdx.x; c < D.G;
          c += (int64_t)gridDim.x * kIdpThreads)
-        d[c] = r[c] * dinv[c] + beta * d[c];
+        d[c] = (JAC ? r[c] * dinv[c] : z[c]) + beta * d[c];
 }
 
 // Face displacements (Eq. 13): for the face from cell c to its +axis
@@ -267,7 +295,8 @@ __global__ void __launch_bounds__(kIdpThreads) k_idp_faces(IdpDims D, double dx,
 #pragma clang fp contract(off)
     for (int64_t c = (int64_t)blockIdx.x * kIdpThreads + threadIdx.x; c < D.G;
          c += (int64_t)gridDim.x * kIdpThreads) {
-        const int64_t i = c % D.nx, j = (c / D.nx) % D.ny, k = c / D.sxy;
+        int64_t i, j, k;
+        coords(D, c, i, j, k);
         const uint8_t lc = lab[c];
         const double qc = lc == kIdpFluid ? q[c] : 0.0;
         const bool up[3] = {i < D.nx - 1, j < D.ny - 1, k < D.nz - 1};
@@ -296,6 +325,229 @@ __global__ void __launch_bounds__(kIdpThreads) k_idp_faces(IdpDims D, double dx,
             if (low[a]) F[a][fi[a] - step[a]] = 0.0;
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Multigrid preconditioner: one symmetric V-cycle per CG iteration.  Level
+// l + 1 halves level l per axis (rounding up); a coarse cell is air if any of
+// its children is air, else fluid if any child is fluid, else solid, and its
+// alpha_f' is the mean of its children's.  The level operator is
+// A_l = 4^l L(alpha_f'_l, labels_l), which for constant coefficients is the
+// Galerkin product R A_{l-1} P of piecewise-constant prolongation P (a fluid
+// coarse cell's correction added to its fluid children) and R = P^T (the sum
+// of the fluid children's residuals).  Smoothing: two damped Jacobi sweeps
+// (omega = 2/3) before and after the coarse correction; the coarsest level
+// (at most 256 cells) takes 48 sweeps in LDS.  Equal pre- and post-sweeps
+// and R = P^T keep the preconditioner symmetric.
+constexpr double kOmega = 2.0 / 3.0;
+constexpr int kCoarseSweeps = 48;
+
+// sum over the open faces of c of beta (v_c - v_n), v given per cell by val
+// (called for c and its fluid neighbours only)
+// (val(n, i, j, k) gets the cell and its coordinates)
+template <typename V>
+__device__ inline double face_sum(const IdpDims &D, int64_t c, int64_t i, int64_t j, int64_t k,
+                                  const double *__restrict__ at, const uint8_t *__restrict__ lab, V val)
+{
+    Nbr nb[6];
+    neighbours(D, i, j, k, nb);
+    const int64_t di[6] = {-1, 1, 0, 0, 0, 0}, dj[6] = {0, 0, -1, 1, 0, 0}, dk[6] = {0, 0, 0, 0, -1, 1};
+    const double ac = at[c], vc = val(c, i, j, k);
+    double acc = 0.0;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        if (!nb[f].inside) continue;
+        const int64_t n = c + nb[f].off;
+        const uint8_t ln = lab[n];
+        if (ln == kIdpSolid) continue;
+        const double vn = ln == kIdpFluid ? val(n, i + di[f], j + dj[f], k + dk[f]) : 0.0;
+        acc += (ac + at[n]) * 0.5 * (vc - vn);
+    }
+    return acc;
+}
+
+template <typename V>
+__device__ inline double face_sum(const IdpDims &D, int64_t c, const double *__restrict__ at,
+                                  const uint8_t *__restrict__ lab, V val)
+{
+    int64_t i, j, k;
+    coords(D, c, i, j, k);
+    return face_sum(D, c, i, j, k, at, lab, val);
+}
+
+// uniform per block: read the solver state once
+__device__ inline bool cg_done(const CgState *st)
+{
+    __shared__ int64_t s_done;
+    if (threadIdx.x == 0) s_done = st->done;
+    __syncthreads();
+    return s_done >= 0;
+}
+
+__global__ void __launch_bounds__(kIdpThreads) k_mg_coarsen(MgLevel F, MgLevel Cl)
+{
+    for (int64_t C = (int64_t)blockIdx.x * kIdpThreads + threadIdx.x; C < Cl.D.G;
+         C += (int64_t)gridDim.x * kIdpThreads) {
+        int64_t I, J, K;
+        coords(Cl.D, C, I, J, K);
+        bool air = false, fluid = false;
+        double sum = 0.0;
+        int cnt = 0;
+        for (int c = 0; c < 2; ++c)
+            for (int b = 0; b < 2; ++b)
+                for (int a = 0; a < 2; ++a) {
+                    const int64_t i = 2 * I + a, j = 2 * J + b, k = 2 * K + c;
+                    if (i >= F.D.nx || j >= F.D.ny || k >= F.D.nz) continue;
+                    const int64_t f = (k * F.D.ny + j) * F.D.nx + i;
+                    const uint8_t l = F.lab[f];
+                    air |= l == kIdpAir;
+                    fluid |= l == kIdpFluid;
+                    sum += F.at[f];
+                    ++cnt;
+                }
+        Cl.lab[C] = air ? kIdpAir : (fluid ? kIdpFluid : kIdpSolid);
+        Cl.at[C] = sum / cnt;
+    }
+}
+
+__global__ void __launch_bounds__(kIdpThreads) k_mg_diag(MgLevel L)
+{
+    for (int64_t c = (int64_t)blockIdx.x * kIdpThreads + threadIdx.x; c < L.D.G;
+         c += (int64_t)gridDim.x * kIdpThreads) {
+        double di = 1.0;
+        if (L.lab[c] == kIdpFluid) {
+            Nbr nb[6];
+            neighbours(L.D, c, nb);
+            double dg = 0.0;
+            for (int k = 0; k < 6; ++k) {
+                if (!nb[k].inside) continue;
+                const int64_t n = c + nb[k].off;
+                if (L.lab[n] != kIdpSolid) dg += (L.at[c] + L.at[n]) * 0.5;
+            }
+            di = dg > 0.0 ? 1.0 / (L.scale * dg) : 0.0;
+        }
+        L.dinv[c] = di;
+    }
+}
+
+// Pre-smoothing from zero: e = w D^-1 b, then e += w D^-1 (b - A e).
+__global__ void __launch_bounds__(kIdpThreads) k_mg_pre(MgLevel L, const CgState *__restrict__ st)
+{
+    if (cg_done(st)) return;
+    for (int64_t c = (int64_t)blockIdx.x * kIdpThreads + threadIdx.x; c < L.D.G;
+         c += (int64_t)gridDim.x * kIdpThreads) {
+        if (L.lab[c] != kIdpFluid) {
+            L.e[c] = 0.0;
+            continue;
+        }
+        auto e1 = [&](int64_t n, int64_t, int64_t, int64_t) { return kOmega * L.dinv[n] * L.b[n]; };
+        const double Ae = L.scale * face_sum(L.D, c, L.at, L.lab, e1);
+        L.e[c] = e1(c, 0, 0, 0) + kOmega * L.dinv[c] * (L.b[c] - Ae);
+    }
+}
+
+// Coarse right-hand side: the sum of the fluid children's residuals b - A e.
+__global__ void __launch_bounds__(kIdpThreads) k_mg_restrict(MgLevel F, MgLevel Cl, const CgState *__restrict__ st)
+{
+    if (cg_done(st)) return;
+    for (int64_t C = (int64_t)blockIdx.x * kIdpThreads + threadIdx.x; C < Cl.D.G;
+         C += (int64_t)gridDim.x * kIdpThreads) {
+        double sum = 0.0;
+        if (Cl.lab[C] == kIdpFluid) {
+            int64_t I, J, K;
+            coords(Cl.D, C, I, J, K);
+            for (int c = 0; c < 2; ++c)
+                for (int b = 0; b < 2; ++b)
+                    for (int a = 0; a < 2; ++a) {
+                        const int64_t i = 2 * I + a, j = 2 * J + b, k = 2 * K + c;
+                        if (i >= F.D.nx || j >= F.D.ny || k >= F.D.nz) continue;
+                        const int64_t f = (k * F.D.ny + j) * F.D.nx + i;
+                        if (F.lab[f] != kIdpFluid) continue;
+                        const double Ae = F.scale * face_sum(F.D, f, i, j, k, F.at, F.lab,
+                                                             [&](int64_t n, int64_t, int64_t, int64_t) { return F.e[n]; });
+                        sum += F.b[f] - Ae;
+                    }
+        }
+        Cl.b[C] = sum;
+    }
+}
+
+// Coarse correction and the first post-sweep: u = e + P E, t = u + w D^-1 (b - A u).
+__global__ void __launch_bounds__(kIdpThreads) k_mg_post1(MgLevel F, MgLevel Cl, const CgState *__restrict__ st)
+{
+    if (cg_done(st)) return;
+    for (int64_t c = (int64_t)blockIdx.x * kIdpThreads + threadIdx.x; c < F.D.G;
+         c += (int64_t)gridDim.x * kIdpThreads) {
+        if (F.lab[c] != kIdpFluid) {
+            F.t[c] = 0.0;
+            continue;
+        }
+        auto u = [&](int64_t n, int64_t i, int64_t j, int64_t k) {
+            const int64_t p = ((k >> 1) * Cl.D.ny + (j >> 1)) * Cl.D.nx + (i >> 1);
+            return Cl.lab[p] == kIdpFluid ? F.e[n] + Cl.e[p] : F.e[n];
+        };
+        int64_t i, j, k;
+        coords(F.D, c, i, j, k);
+        const double Au = F.scale * face_sum(F.D, c, i, j, k, F.at, F.lab, u);
+        F.t[c] = u(c, i, j, k) + kOmega * F.dinv[c] * (F.b[c] - Au);
+    }
+}
+
+// Second post-sweep into e: e = t + w D^-1 (b - A t); on the finest level
+// also the partials of b.e (= r.z of the CG iteration).
+__global__ void __launch_bounds__(kIdpThreads) k_mg_post2(MgLevel L, double *__restrict__ part,
+                                                          const CgState *__restrict__ st)
+{
+    __shared__ double red[4];
+    if (cg_done(st)) return;
+    double rz = 0.0;
+    for (int64_t c = (int64_t)blockIdx.x * kIdpThreads + threadIdx.x; c < L.D.G;
+         c += (int64_t)gridDim.x * kIdpThreads) {
+        if (L.lab[c] != kIdpFluid) {
+            L.e[c] = 0.0;
+            continue;
+        }
+        const double At =
+            L.scale * face_sum(L.D, c, L.at, L.lab, [&](int64_t n, int64_t, int64_t, int64_t) { return L.t[n]; });
+        const double z = L.t[c] + kOmega * L.dinv[c] * (L.b[c] - At);
+        L.e[c] = z;
+        rz += L.b[c] * z;
+    }
+    if (part) {
+        rz = block_sum(rz, red);
+        if (threadIdx.x == 0) part[gridDim.x + blockIdx.x] = rz;
+    }
+}
+
+// The coarsest level (at most 256 cells) in one block: kCoarseSweeps damped
+// Jacobi sweeps from zero, in LDS.
+__global__ void __launch_bounds__(kIdpThreads) k_mg_coarsest(MgLevel L, const CgState *__restrict__ st)
+{
+    __shared__ double se[2][kIdpThreads], sb[kIdpThreads], sdi[kIdpThreads], sat[kIdpThreads];
+    __shared__ uint8_t slab[kIdpThreads];
+    if (cg_done(st)) return;
+    const int c = threadIdx.x;
+    const bool live = c < L.D.G;
+    if (live) {
+        sb[c] = L.b[c];
+        sdi[c] = L.dinv[c];
+        sat[c] = L.at[c];
+        slab[c] = L.lab[c];
+    }
+    se[0][c] = 0.0;
+    __syncthreads();
+    for (int s = 0; s < kCoarseSweeps; ++s) {
+        const int cur = s & 1;
+        double v = 0.0;
+        if (live && slab[c] == kIdpFluid) {
+            const double Ae = L.scale * face_sum(L.D, (int64_t)c, sat, slab,
+                                                 [&](int64_t n, int64_t, int64_t, int64_t) { return se[cur][n]; });
+            v = se[cur][c] + kOmega * sdi[c] * (sb[c] - Ae);
+        }
+        se[cur ^ 1][c] = v;
+        __syncthreads();
+    }
+    if (live) L.e[c] = se[kCoarseSweeps & 1][c];
 }
 
 unsigned idp_blocks(int64_t G)
@@ -338,11 +590,36 @@ hipError_t launch_idp_faces(const IdpDims &D, double dx, const double *q, const 
     return hipGetLastError();
 }
 
+// z = M^-1 r by one V-cycle over the levels of W (level 0 works on r and z).
+static void launch_vcycle(const IdpWork &W, hipStream_t st)
+{
+    const int L = W.nlev;
+    for (int l = 0; l + 1 < L; ++l) {
+        k_mg_pre<<<idp_blocks(W.lev[l].D.G), kIdpThreads, 0, st>>>(W.lev[l], W.state);
+        k_mg_restrict<<<idp_blocks(W.lev[l + 1].D.G), kIdpThreads, 0, st>>>(W.lev[l], W.lev[l + 1], W.state);
+    }
+    k_mg_coarsest<<<1, kIdpThreads, 0, st>>>(W.lev[L - 1], W.state);
+    for (int l = L - 2; l >= 0; --l) {
+        k_mg_post1<<<idp_blocks(W.lev[l].D.G), kIdpThreads, 0, st>>>(W.lev[l], W.lev[l + 1], W.state);
+        k_mg_post2<<<idp_blocks(W.lev[l].D.G), kIdpThreads, 0, st>>>(W.lev[l], l == 0 ? W.part : nullptr,
+                                                                      W.state);
+    }
+}
+
 hipError_t launch_cg_start(const IdpDims &D, const double *at, const uint8_t *lab, const double *s, const double *q,
                            const IdpWork &W, double tol, hipStream_t st)
 {
     const unsigned nb = idp_blocks(D.G);
-    k_cg_init<<<nb, kIdpThreads, 0, st>>>(D, at, lab, s, q, W.r, W.d, W.dinv, W.part);
+    k_cg_init<<<nb, kIdpThreads, 0, st>>>(D, at, lab, s, q, W.r, W.d, W.dinv, W.part, W.state);
+    if (W.nlev > 1) {
+        for (int l = 0; l + 1 < W.nlev; ++l) {
+            k_mg_coarsen<<<idp_blocks(W.lev[l + 1].D.G), kIdpThreads, 0, st>>>(W.lev[l], W.lev[l + 1]);
+            k_mg_diag<<<idp_blocks(W.lev[l + 1].D.G), kIdpThreads, 0, st>>>(W.lev[l + 1]);
+        }
+        launch_vcycle(W, st);
+        hipError_t e = hipMemcpyAsync(W.d, W.lev[0].e, sizeof(double) * D.G, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return e;
+    }
     k_cg_start<<<1, kIdpThreads, 0, st>>>((int)nb, W.part, tol, W.state);
     return hipGetLastError();
 }
@@ -351,10 +628,17 @@ hipError_t launch_cg_iterations(const IdpDims &D, const double *at, const uint8_
                                 const IdpWork &W, int k0, int count, hipStream_t st)
 {
     const unsigned nb = idp_blocks(D.G);
+    const bool mg = W.nlev > 1;
     for (int k = k0; k < k0 + count; ++k) {
         k_cg_apply<<<nb, kIdpThreads, 0, st>>>(D, at, lab, W.d, W.w, W.part, W.state);
-        k_cg_update<<<nb, kIdpThreads, 0, st>>>(D, k, W.d, W.w, W.dinv, q, W.r, W.part, W.state);
-        k_cg_direction<<<nb, kIdpThreads, 0, st>>>(D, k, W.r, W.dinv, W.d, W.part, W.state);
+        if (mg) {
+            k_cg_update<false><<<nb, kIdpThreads, 0, st>>>(D, k, W.d, W.w, W.dinv, q, W.r, W.part, W.state);
+            launch_vcycle(W, st);
+            k_cg_direction<false><<<nb, kIdpThreads, 0, st>>>(D, k, W.r, W.dinv, W.lev[0].e, W.d, W.part, W.state);
+        } else {
+            k_cg_update<true><<<nb, kIdpThreads, 0, st>>>(D, k, W.d, W.w, W.dinv, q, W.r, W.part, W.state);
+            k_cg_direction<true><<<nb, kIdpThreads, 0, st>>>(D, k, W.r, W.dinv, nullptr, W.d, W.part, W.state);
+        }
     }
     return hipGetLastError();
 }

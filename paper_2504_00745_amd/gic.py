@@ -67,9 +67,9 @@ def lib():
             "gic_idp_workspace_bytes": (_I64, [_V]),
             "gic_idp_setup": (C.c_int, [_V] * 7),
             "gic_idp_apply": (C.c_int, [_V] * 6),
-            "gic_idp_solve": (C.c_int, [_V] * 6 + [_I32, C.c_double, _I32, _V, _V, _V]),
+            "gic_idp_solve": (C.c_int, [_V] * 6 + [_I32, C.c_double, _I32, _I32, _V, _V, _V]),
             "gic_idp_displacement": (C.c_int, [_V] * 7),
-            "gic_density_projection": (C.c_int, [_V] * 9 + [_I32, C.c_double, _I32, _V, _V, _V]),
+            "gic_density_projection": (C.c_int, [_V] * 9 + [_I32, C.c_double, _I32, _I32, _V, _V, _V]),
             "gic_contact_pairs": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _I64, _V, _V]),
             "gic_g2p": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V]),
             "gic_drag": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V]),
@@ -263,15 +263,15 @@ def gic_idp_apply(ctx, alpha_t, label, q, out):
                                _ptr(out, f64, G), _stream()), "gic_idp_apply")
 
 
-def gic_idp_solve(ctx, alpha_t, label, rhs, q, work, max_iter=2000, tol=1e-8, check_every=32):
+def gic_idp_solve(ctx, alpha_t, label, rhs, q, work, max_iter=2000, tol=1e-8, check_every=32, precond=1):
     """Solves L q = rhs in place (q: initial guess in, solution out);
     returns (iterations, relative residual).  Synchronises."""
     G, f64 = ctx.G, torch.float64
     it, rel = _I32(), C.c_double()
     _check(lib().gic_idp_solve(ctx.handle, _ptr(alpha_t, f64, G), _ptr(label, torch.uint8, G), _ptr(rhs, f64, G),
                                _ptr(q, f64, G), _ptr(work, torch.uint8, int(lib().gic_idp_workspace_bytes(ctx.handle))),
-                               int(max_iter), float(tol), int(check_every), C.byref(it), C.byref(rel), _stream()),
-           "gic_idp_solve")
+                               int(max_iter), float(tol), int(check_every), int(precond), C.byref(it), C.byref(rel),
+                               _stream()), "gic_idp_solve")
     return int(it.value), float(rel.value)
 
 
@@ -284,7 +284,7 @@ def gic_idp_displacement(ctx, q, label, fx, fy, fz):
 
 
 def gic_density_projection(ctx, alpha_fx, alpha_star, label, q, fx, fy, fz, work, max_iter=2000, tol=1e-8,
-                           check_every=32):
+                           check_every=32, precond=1):
     """The whole projection; returns (iterations, relative residual)."""
     G, f64 = ctx.G, torch.float64
     nfx, nfy, nfz = _faces(ctx)
@@ -293,8 +293,8 @@ def gic_density_projection(ctx, alpha_fx, alpha_star, label, q, fx, fy, fz, work
                                         _ptr(label, torch.uint8, G), _ptr(q, f64, G), _ptr(fx, f64, nfx, "fx"),
                                         _ptr(fy, f64, nfy, "fy"), _ptr(fz, f64, nfz, "fz"),
                                         _ptr(work, torch.uint8, int(lib().gic_idp_workspace_bytes(ctx.handle))),
-                                        int(max_iter), float(tol), int(check_every), C.byref(it), C.byref(rel),
-                                        _stream()), "gic_density_projection")
+                                        int(max_iter), float(tol), int(check_every), int(precond), C.byref(it),
+                                        C.byref(rel), _stream()), "gic_density_projection")
     return int(it.value), float(rel.value)
 
 

@@ -88,14 +88,16 @@ def test_setup_apply_faces_bit_exact(G, orc, name):
             assert (np.abs(ox) == d["params"]["dx"]).any()  # the clamp acted
 
 
+@pytest.mark.parametrize("precond", [0, 1])
 @pytest.mark.parametrize("name", ["p1", "p2"])
-def test_projection_matches_direct_solve(G, orc, name):
-    """gic_density_projection from a cold start: converged, true residual
-    within 1.5 tol, distance to the oracle's direct solution within the
-    residual / lambda_min bound, faces = the oracle's faces of the GPU's q."""
+def test_projection_matches_direct_solve(G, orc, name, precond):
+    """gic_density_projection from a cold start with either preconditioner
+    (Jacobi, multigrid V-cycle): converged, true residual within 1.5 tol,
+    distance to the oracle's direct solution within the residual /
+    lambda_min bound, faces = the oracle's faces of the GPU's q."""
     import torch
     from paper_2504_00745_amd import gic
-    G.say(f"[idp projection] {name}")
+    G.say(f"[idp projection] {name} precond {precond}")
     d, ctx, D = setup(G, name)
     sh, Gc = d["shape"], ctx.G
     lab = d["label"].reshape(sh)
@@ -107,8 +109,8 @@ def test_projection_matches_direct_solve(G, orc, name):
     work = gic.idp_workspace(ctx)
     tol = 1e-10
     it, rel = gic.gic_density_projection(ctx, D["afx"], D["ast"], D["lab"], q, fx, fy, fz, work, max_iter=3000,
-                                         tol=tol, check_every=16)
-    assert 0 < it < 3000 and rel <= tol
+                                         tol=tol, check_every=16, precond=precond)
+    assert 0 < it < (3000 if precond == 0 else 60) and rel <= tol
     at_or = orc.idp.target_fraction(d["alpha_fx"].reshape(sh), d["params"]["alpha_max"])
     s_or = orc.idp.rhs(at_or, d["alpha_star"].reshape(sh), lab)
     qg = host(q, sh)
@@ -121,7 +123,7 @@ def test_projection_matches_direct_solve(G, orc, name):
     assert np.array_equal(host(fx, ox.shape), ox)
     assert np.array_equal(host(fy, oy.shape), oy)
     assert np.array_equal(host(fz, oz.shape), oz)
-    G.say(f"  {name}: {it} iterations, relres {rel:.2e}")
+    G.say(f"  {name} precond {precond}: {it} iterations, relres {rel:.2e}")
 
 
 def test_warm_start_and_separate_calls(G, orc):
@@ -161,14 +163,15 @@ def test_warm_start_and_separate_calls(G, orc):
     assert it5 == 0 and r5 == 0.0 and not bool(q5.any())
 
 
-def test_projection_full_size_c3_grid(G, orc):
+@pytest.mark.parametrize("precond", [1, 0])
+def test_projection_full_size_c3_grid(G, orc, precond):
     """The dam-break grid (256 x 128 x 128 cells) in the benchmark's
-    configuration (tol 1e-6, checks every 32 iterations): setup bit-exact,
-    the oracle's true residual within 1.5 tol, faces = the oracle's faces of
-    the GPU's q, q zero off the fluid."""
+    configuration (tol 1e-6, checks every 8 (multigrid) or 32 (Jacobi)
+    iterations): setup bit-exact, the oracle's true residual within 1.5 tol,
+    faces = the oracle's faces of the GPU's q, q zero off the fluid."""
     import torch
     from paper_2504_00745_amd import gic
-    G.say("[idp full size] c3 grid")
+    G.say(f"[idp full size] c3 grid precond {precond}")
     d, ctx, D = setup(G, "c3")
     sh, Gc = d["shape"], ctx.G
     lab = d["label"].reshape(sh)
@@ -180,8 +183,8 @@ def test_projection_full_size_c3_grid(G, orc):
     work = gic.idp_workspace(ctx)
     tol = 1e-6
     it, rel = gic.gic_density_projection(ctx, D["afx"], D["ast"], D["lab"], q, fx, fy, fz, work, max_iter=5000,
-                                         tol=tol, check_every=32)
-    G.say(f"  c3 grid: {it} iterations, relres {rel:.2e}")
+                                         tol=tol, check_every=8 if precond else 32, precond=precond)
+    G.say(f"  c3 grid precond {precond}: {it} iterations, relres {rel:.2e}")
     assert 0 < it < 5000 and rel <= tol
     at_or = orc.idp.target_fraction(d["alpha_fx"].reshape(sh), d["params"]["alpha_max"])
     s_or = orc.idp.rhs(at_or, d["alpha_star"].reshape(sh), lab)
@@ -217,3 +220,31 @@ def test_idp_argument_checks(G):
         gic.gic_idp_solve(ctx, at, D["lab"], at, at.clone(), work, tol=-1.0)
     with pytest.raises(gic.GicError):
         gic.gic_idp_apply(ctx, at, D["lab"], at, at)  # out aliases q
+    with pytest.raises(gic.GicError):
+        gic.gic_idp_solve(ctx, at, D["lab"], at, at.clone(), work, precond=2)
+
+
+def test_multigrid_on_tiny_and_flat_grids(G, orc):
+    """Grids of at most 256 cells (no coarser level: Jacobi) and a flat
+    40 x 9 x 1 grid (levels of one cell in z) still converge with
+    precond = 1 to the oracle's solution."""
+    import torch
+    from paper_2504_00745_amd import gic
+    G.say("[idp tiny / flat grids]")
+    for shape in ((4, 6, 5), (1, 9, 40)):
+        nz, ny, nx = shape
+        rng = np.random.Generator(np.random.PCG64(nx))
+        lab = np.zeros(shape, np.uint8)
+        lab[..., -1] = 1  # air column at the +x end
+        at = rng.uniform(0.3, 1.0, shape)
+        s = np.where(lab == 0, rng.normal(0, 0.1, shape), 0.0)
+        p = wl._params((nx, ny, nz), 0.01, 0.01, 1e-4, (0.0, 0.0, 0.0))
+        ctx = gic.Context(p, 1, "fp64", r_max=0.0025)
+        q = torch.zeros(ctx.G, dtype=torch.float64, device="cuda")
+        it, rel = gic.gic_idp_solve(ctx, G.dev(at.reshape(-1)), torch.as_tensor(lab.reshape(-1)).to("cuda"),
+                                    G.dev(s.reshape(-1)), q, gic.idp_workspace(ctx), tol=1e-10, precond=1)
+        assert rel <= 1e-10
+        q_or = orc.idp.solve(at, lab, s)
+        res = np.linalg.norm(s - orc.idp.apply(at, lab, host(q, shape)))
+        assert res <= 1.5e-10 * np.linalg.norm(s)
+        assert np.linalg.norm(host(q, shape) - q_or) <= res / lambda_min(orc, at, lab) * 1.01 + 1e-15
