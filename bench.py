@@ -360,17 +360,17 @@ def time_capillary(d, wl_name, reps=10):
 
 
 # One conjugate-gradient iteration of the density projection reads and writes,
-# per cell: w = L d (d, alpha_f', label; w), the update (d, w, 1/diag, q, r;
-# q, r) and the new direction (r, 1/diag, d; d).
-IDP_BYTES_PER_CELL_ITER = (8 + 8 + 1 + 8) + (5 * 8 + 2 * 8) + (3 * 8 + 8)
-# With the multigrid V-cycle: w = L d (25), the update without r.z (d, w, q, r;
-# q, r: 48), per fine cell pre-smoothing (b, 1/diag, alpha_f', label; e: 33),
-# restriction (e, b, alpha_f', label: 25 + 1/8 of a coarse write), the first
-# post-sweep with the coarse correction (e, b, 1/diag, alpha_f', label, 1/8 of
-# the coarse e and label; t: 42) and the second (t, b, 1/diag, alpha_f', label;
-# e: 41), the new direction (z, d; d: 24); coarser levels add the four passes'
-# bytes times 1/8 + 1/64 + ... = 1/7.
-IDP_MG_BYTES_PER_CELL_ITER = 25 + 48 + 33 + 26 + 42 + 41 + 24 + (33 + 26 + 42 + 41) / 7.0
+# per cell (ac: the signed coefficient that carries alpha_f' and the label):
+# w = L d (d, ac; w: 24), the update (d, w, 1/diag, q, r; q, r: 56) and the new
+# direction (r, 1/diag, d; d: 32).
+IDP_BYTES_PER_CELL_ITER = 24 + 56 + 32
+# With the multigrid V-cycle: w = L d (24), the update without r.z (d, w, q, r;
+# q, r: 48), per fine cell pre-smoothing (b, 1/diag, ac; e: 32), restriction
+# (e, b, ac: 24 plus 1/8 of a coarse write), the first post-sweep with the
+# coarse correction (e, b, 1/diag, ac, 1/8 of the coarse e and ac; t: 42) and
+# the second (t, b, 1/diag, ac; e: 40), the new direction (z, d; d: 24);
+# coarser levels add the four passes' bytes times 1/8 + 1/64 + ... = 1/7.
+IDP_MG_BYTES_PER_CELL_ITER = 24 + 48 + 32 + 25 + 42 + 40 + 24 + (32 + 25 + 42 + 40) / 7.0
 
 
 def time_idp(reps=3, tol=1e-6):

@@ -179,16 +179,16 @@ int64_t idp_work_bytes(const IdpDims &D0)
 {
     IdpDims lv[kMgMaxLevels];
     const int L = idp_levels(D0, lv);
-    int64_t b = 8 * idp_align(D0.G * 8) + idp_align(3 * kIdpMaxBlocks * 8) + idp_align(sizeof(CgState));
-    for (int l = 1; l < L; ++l) b += 5 * idp_align(lv[l].G * 8) + idp_align(lv[l].G);
+    int64_t b = 9 * idp_align(D0.G * 8) + idp_align(3 * kIdpMaxBlocks * 8) + idp_align(sizeof(CgState));
+    for (int l = 1; l < L; ++l) b += 5 * idp_align(lv[l].G * 8);
     return b;
 }
 
 // Carves the workspace: alpha_f' and s slots for gic_density_projection, the
-// CG vectors, and (multigrid) the levels; level 0 works on the caller's
-// alpha_f' and labels, the residual r and the preconditioned residual z.
-IdpWork idp_carve(void *work, const IdpDims &D0, int precond, const double *at0, const uint8_t *lab0, double **at,
-                  double **s)
+// CG vectors, the fine grid's signed coefficients, and (multigrid) the
+// coarser levels; level 0 works on the residual r and the preconditioned
+// residual z.
+IdpWork idp_carve(void *work, const IdpDims &D0, int precond, double **at, double **s)
 {
     char *p = (char *)work;
     const int64_t a = idp_align(D0.G * 8);
@@ -199,8 +199,8 @@ IdpWork idp_carve(void *work, const IdpDims &D0, int precond, const double *at0,
     W.d = (double *)(p + 3 * a);
     W.w = (double *)(p + 4 * a);
     W.dinv = (double *)(p + 5 * a);
-    double *z = (double *)(p + 6 * a), *t = (double *)(p + 7 * a);
-    p += 8 * a;
+    double *z = (double *)(p + 6 * a), *t = (double *)(p + 7 * a), *ac = (double *)(p + 8 * a);
+    p += 9 * a;
     W.part = (double *)p;
     p += idp_align(3 * kIdpMaxBlocks * 8);
     W.state = (CgState *)p;
@@ -208,7 +208,7 @@ IdpWork idp_carve(void *work, const IdpDims &D0, int precond, const double *at0,
     IdpDims lv[kMgMaxLevels];
     const int L = idp_levels(D0, lv);
     W.nlev = precond == 1 ? L : 1;
-    W.lev[0] = MgLevel{D0, 1.0, const_cast<double *>(at0 ? at0 : *at), const_cast<uint8_t *>(lab0), W.dinv, W.r, z, t};
+    W.lev[0] = MgLevel{D0, 1.0, ac, W.dinv, W.r, z, t};
     double scale = 1.0;
     for (int l = 1; l < L; ++l) {
         scale *= 4.0;
@@ -216,13 +216,12 @@ IdpWork idp_carve(void *work, const IdpDims &D0, int precond, const double *at0,
         MgLevel m;
         m.D = lv[l];
         m.scale = scale;
-        m.at = (double *)p;
+        m.ac = (double *)p;
         m.dinv = (double *)(p + g);
         m.b = (double *)(p + 2 * g);
         m.e = (double *)(p + 3 * g);
         m.t = (double *)(p + 4 * g);
-        m.lab = (uint8_t *)(p + 5 * g);
-        p += 5 * g + idp_align(lv[l].G);
+        p += 5 * g;
         W.lev[l] = m;
     }
     return W;
@@ -782,7 +781,7 @@ gic_status gic_idp_solve(gic_ctx *c, const double *alpha_t, const uint8_t *label
     if (!c || !alpha_t || !label || !rhs || !q || !work || max_iter < 0 || check_every < 1) return GIC_E_ARG;
     if (!(tol >= 0.0) || !isfinite(tol) || (precond != 0 && precond != 1)) return GIC_E_ARG;
     double *at_w, *s_w;
-    const IdpWork W = idp_carve(work, idp_dims(c->dp), precond, alpha_t, label, &at_w, &s_w);
+    const IdpWork W = idp_carve(work, idp_dims(c->dp), precond, &at_w, &s_w);
     return idp_cg(c, alpha_t, label, rhs, q, W, max_iter, tol, check_every, iters, relres, (hipStream_t)stream);
 }
 
@@ -804,7 +803,7 @@ gic_status gic_density_projection(gic_ctx *c, const int64_t *alpha_fx, const dou
     const IdpDims D = idp_dims(c->dp);
     hipStream_t s = (hipStream_t)stream;
     double *at, *rhs;
-    const IdpWork W = idp_carve(work, D, precond, nullptr, label, &at, &rhs);
+    const IdpWork W = idp_carve(work, D, precond, &at, &rhs);
     if (launch_idp_setup(D, c->dp.alpha_max, alpha_fx, alpha_star, label, at, rhs, s) != hipSuccess)
         return GIC_E_HIP;
     const gic_status st = idp_cg(c, at, label, rhs, q, W, max_iter, tol, check_every, iters, relres, s);

@@ -137,14 +137,14 @@ struct CgState {
     int64_t iters;  // completed iterations
 };
 
-// One level of the multigrid preconditioner: its cells, operator scale
-// (A_l = scale L_l), alpha_f', labels, 1 / diag(A_l), right-hand side,
-// correction and a second correction buffer.
+// One level of the solver's hierarchy: its cells, operator scale
+// (A_l = scale L_l), signed coefficients (alpha_f' on fluid cells, -alpha_f'
+// on air cells, 0 on solid cells), 1 / diag(A_l), right-hand side,
+// correction and a second correction buffer.  Level 0 is the fine grid.
 struct MgLevel {
     IdpDims D;
     double scale;
-    double *at;
-    uint8_t *lab;
+    double *ac;
     double *dinv, *b, *e, *t;
 };
 

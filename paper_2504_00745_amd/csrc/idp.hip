@@ -112,6 +112,37 @@ __device__ inline void apply_row(const IdpDims &D, int64_t c, const double *__re
     diag = dg;
 }
 
+// sum over the open faces of cell c = (i, j, k) of beta (v_c - v_n), from
+// the signed coefficients ac (alpha_f' on fluid cells, -alpha_f' on air
+// cells, 0 on solid cells): the six neighbours' coefficients and values are
+// loaded without branches; a closed face gets beta = 0 and an air neighbour
+// the value 0, so the sum is the operator's for any values v.  val(n, i, j, k)
+// gives the value of cell n at (i, j, k).
+template <typename V>
+__device__ inline double face_sum_ac(const IdpDims &D, int64_t c, int64_t i, int64_t j, int64_t k,
+                                     const double *__restrict__ ac, V val)
+{
+    const int64_t off[6] = {-1, 1, -D.nx, D.nx, -D.sxy, D.sxy};
+    const bool in[6] = {i > 0, i < D.nx - 1, j > 0, j < D.ny - 1, k > 0, k < D.nz - 1};
+    const int64_t di[6] = {-1, 1, 0, 0, 0, 0}, dj[6] = {0, 0, -1, 1, 0, 0}, dk[6] = {0, 0, 0, 0, -1, 1};
+    const double a = ac[c], vc = val(c, i, j, k);
+    double an[6], vn[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        const int64_t n = in[f] ? c + off[f] : c;
+        an[f] = in[f] ? ac[n] : 0.0;
+        vn[f] = val(n, in[f] ? i + di[f] : i, in[f] ? j + dj[f] : j, in[f] ? k + dk[f] : k);
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        const double beta = an[f] != 0.0 ? (a + fabs(an[f])) * 0.5 : 0.0;
+        const double v = an[f] > 0.0 ? vn[f] : 0.0;
+        acc += beta * (vc - v);
+    }
+    return acc;
+}
+
 __global__ void __launch_bounds__(kIdpThreads) k_idp_setup(IdpDims D, double alpha_max,
                                                            const int64_t *__restrict__ afx,
                                                            const double *__restrict__ astar,
@@ -143,13 +174,16 @@ __global__ void __launch_bounds__(kIdpThreads) k_idp_apply(IdpDims D, const doub
     }
 }
 
-// CG start: r = s - L q, z = r / diag, d = z; partials of s.s, r.z, r.r.
+// CG start: r = s - L q, z = r / diag, d = z, the signed coefficients ac
+// (alpha_f' on fluid cells, -alpha_f' on air cells, 0 on solid cells) that
+// the iteration kernels read instead of alpha_f' and the labels; partials of
+// s.s, r.z, r.r.
 __global__ void __launch_bounds__(kIdpThreads) k_cg_init(IdpDims D, const double *__restrict__ at,
                                                          const uint8_t *__restrict__ lab,
                                                          const double *__restrict__ s, const double *__restrict__ q,
                                                          double *__restrict__ r, double *__restrict__ d,
-                                                         double *__restrict__ dinv, double *__restrict__ part,
-                                                         CgState *__restrict__ st)
+                                                         double *__restrict__ dinv, double *__restrict__ ac,
+                                                         double *__restrict__ part, CgState *__restrict__ st)
 {
     __shared__ double red[4];
     double rz = 0.0, rr = 0.0, ss = 0.0;
@@ -157,6 +191,8 @@ __global__ void __launch_bounds__(kIdpThreads) k_cg_init(IdpDims D, const double
          c += (int64_t)gridDim.x * kIdpThreads) {
         double Lq, dg;
         apply_row(D, c, at, lab, q, Lq, dg);
+        const uint8_t lc = lab[c];
+        ac[c] = lc == kIdpFluid ? at[c] : (lc == kIdpAir ? -at[c] : 0.0);
         const double sc = lab[c] == kIdpFluid ? s[c] : 0.0;
         const double rc = sc - Lq;
         const double di = dg > 0.0 ? 1.0 / dg : 0.0;  // a fluid cell walled in on all sides: singular row
@@ -200,8 +236,7 @@ __global__ void __launch_bounds__(kIdpThreads) k_cg_start(int nb, const double *
 }
 
 // Iteration k, part 1: w = L d; partials of d.w.
-__global__ void __launch_bounds__(kIdpThreads) k_cg_apply(IdpDims D, const double *__restrict__ at,
-                                                          const uint8_t *__restrict__ lab,
+__global__ void __launch_bounds__(kIdpThreads) k_cg_apply(IdpDims D, const double *__restrict__ ac,
                                                           const double *__restrict__ d, double *__restrict__ w,
                                                           double *__restrict__ part, const CgState *__restrict__ st)
 {
@@ -210,8 +245,14 @@ __global__ void __launch_bounds__(kIdpThreads) k_cg_apply(IdpDims D, const doubl
     double dw = 0.0;
     for (int64_t c = (int64_t)blockIdx.x * kIdpThreads + threadIdx.x; c < D.G;
          c += (int64_t)gridDim.x * kIdpThreads) {
-        double Lv, dg;
-        apply_row(D, c, at, lab, d, Lv, dg);
+        double Lv;
+        if (ac[c] > 0.0) {
+            int64_t i, j, k;
+            coords(D, c, i, j, k);
+            Lv = face_sum_ac(D, c, i, j, k, ac, [&](int64_t n, int64_t, int64_t, int64_t) { return d[n]; });
+        } else {
+            Lv = d[c];  // identity row
+        }
         w[c] = Lv;
         dw += d[c] * Lv;
     }
@@ -219,8 +260,6 @@ __global__ void __launch_bounds__(kIdpThreads) k_cg_apply(IdpDims D, const doubl
     if (threadIdx.x == 0) part[blockIdx.x] = dw;
 }
 
-// Iteration k, part 2: alpha = rz_k / (d.w); q += alpha d; r -= alpha w;
-// partials of r.r and, with the Jacobi preconditioner, of r.z with z = r / diag.
 template <bool JAC>
 __global__ void __launch_bounds__(kIdpThreads) k_cg_update(IdpDims D, int k, const double *__restrict__ d,
                                                            const double *__restrict__ w,
@@ -331,49 +370,18 @@ __global__ void __launch_bounds__(kIdpThreads) k_idp_faces(IdpDims D, double dx,
 // Multigrid preconditioner: one symmetric V-cycle per CG iteration.  Level
 // l + 1 halves level l per axis (rounding up); a coarse cell is air if any of
 // its children is air, else fluid if any child is fluid, else solid, and its
-// alpha_f' is the mean of its children's.  The level operator is
-// A_l = 4^l L(alpha_f'_l, labels_l), which for constant coefficients is the
-// Galerkin product R A_{l-1} P of piecewise-constant prolongation P (a fluid
-// coarse cell's correction added to its fluid children) and R = P^T (the sum
-// of the fluid children's residuals).  Smoothing: two damped Jacobi sweeps
-// (omega = 2/3) before and after the coarse correction; the coarsest level
-// (at most 256 cells) takes 48 sweeps in LDS.  Equal pre- and post-sweeps
-// and R = P^T keep the preconditioner symmetric.
+// alpha_f' is the mean over its children that are not solid.  The level
+// operator is A_l = 4^l L(alpha_f'_l, labels_l), which for constant
+// coefficients is the Galerkin product R A_{l-1} P of piecewise-constant
+// prolongation P (a fluid coarse cell's correction added to its fluid
+// children) and R = P^T (the sum of the fluid children's residuals).
+// Smoothing: two damped Jacobi sweeps (omega = 2/3) before and after the
+// coarse correction; the coarsest level (at most 256 cells) takes 48 sweeps
+// in LDS.  Equal pre- and post-sweeps and R = P^T keep the preconditioner
+// symmetric.  Non-fluid rows of the finest level are identity rows and get
+// z = r.  Levels carry the signed coefficients (see face_sum_ac).
 constexpr double kOmega = 2.0 / 3.0;
 constexpr int kCoarseSweeps = 48;
-
-// sum over the open faces of c of beta (v_c - v_n), v given per cell by val
-// (called for c and its fluid neighbours only)
-// (val(n, i, j, k) gets the cell and its coordinates)
-template <typename V>
-__device__ inline double face_sum(const IdpDims &D, int64_t c, int64_t i, int64_t j, int64_t k,
-                                  const double *__restrict__ at, const uint8_t *__restrict__ lab, V val)
-{
-    Nbr nb[6];
-    neighbours(D, i, j, k, nb);
-    const int64_t di[6] = {-1, 1, 0, 0, 0, 0}, dj[6] = {0, 0, -1, 1, 0, 0}, dk[6] = {0, 0, 0, 0, -1, 1};
-    const double ac = at[c], vc = val(c, i, j, k);
-    double acc = 0.0;
-#pragma unroll
-    for (int f = 0; f < 6; ++f) {
-        if (!nb[f].inside) continue;
-        const int64_t n = c + nb[f].off;
-        const uint8_t ln = lab[n];
-        if (ln == kIdpSolid) continue;
-        const double vn = ln == kIdpFluid ? val(n, i + di[f], j + dj[f], k + dk[f]) : 0.0;
-        acc += (ac + at[n]) * 0.5 * (vc - vn);
-    }
-    return acc;
-}
-
-template <typename V>
-__device__ inline double face_sum(const IdpDims &D, int64_t c, const double *__restrict__ at,
-                                  const uint8_t *__restrict__ lab, V val)
-{
-    int64_t i, j, k;
-    coords(D, c, i, j, k);
-    return face_sum(D, c, i, j, k, at, lab, val);
-}
 
 // uniform per block: read the solver state once
 __device__ inline bool cg_done(const CgState *st)
@@ -398,15 +406,16 @@ __global__ void __launch_bounds__(kIdpThreads) k_mg_coarsen(MgLevel F, MgLevel C
                 for (int a = 0; a < 2; ++a) {
                     const int64_t i = 2 * I + a, j = 2 * J + b, k = 2 * K + c;
                     if (i >= F.D.nx || j >= F.D.ny || k >= F.D.nz) continue;
-                    const int64_t f = (k * F.D.ny + j) * F.D.nx + i;
-                    const uint8_t l = F.lab[f];
-                    air |= l == kIdpAir;
-                    fluid |= l == kIdpFluid;
-                    sum += F.at[f];
-                    ++cnt;
+                    const double v = F.ac[(k * F.D.ny + j) * F.D.nx + i];
+                    air |= v < 0.0;
+                    fluid |= v > 0.0;
+                    if (v != 0.0) {
+                        sum += fabs(v);
+                        ++cnt;
+                    }
                 }
-        Cl.lab[C] = air ? kIdpAir : (fluid ? kIdpFluid : kIdpSolid);
-        Cl.at[C] = sum / cnt;
+        const double mean = cnt ? sum / cnt : 0.0;
+        Cl.ac[C] = air ? -mean : (fluid ? mean : 0.0);
     }
 }
 
@@ -415,15 +424,12 @@ __global__ void __launch_bounds__(kIdpThreads) k_mg_diag(MgLevel L)
     for (int64_t c = (int64_t)blockIdx.x * kIdpThreads + threadIdx.x; c < L.D.G;
          c += (int64_t)gridDim.x * kIdpThreads) {
         double di = 1.0;
-        if (L.lab[c] == kIdpFluid) {
-            Nbr nb[6];
-            neighbours(L.D, c, nb);
-            double dg = 0.0;
-            for (int k = 0; k < 6; ++k) {
-                if (!nb[k].inside) continue;
-                const int64_t n = c + nb[k].off;
-                if (L.lab[n] != kIdpSolid) dg += (L.at[c] + L.at[n]) * 0.5;
-            }
+        if (L.ac[c] > 0.0) {
+            int64_t i, j, k;
+            coords(L.D, c, i, j, k);
+            // the face sum of v = 1 on c and 0 on every neighbour is the diagonal
+            const double dg =
+                face_sum_ac(L.D, c, i, j, k, L.ac, [&](int64_t n, int64_t, int64_t, int64_t) { return n == c ? 1.0 : 0.0; });
             di = dg > 0.0 ? 1.0 / (L.scale * dg) : 0.0;
         }
         L.dinv[c] = di;
@@ -436,13 +442,15 @@ __global__ void __launch_bounds__(kIdpThreads) k_mg_pre(MgLevel L, const CgState
     if (cg_done(st)) return;
     for (int64_t c = (int64_t)blockIdx.x * kIdpThreads + threadIdx.x; c < L.D.G;
          c += (int64_t)gridDim.x * kIdpThreads) {
-        if (L.lab[c] != kIdpFluid) {
+        if (!(L.ac[c] > 0.0)) {
             L.e[c] = 0.0;
             continue;
         }
+        int64_t i, j, k;
+        coords(L.D, c, i, j, k);
         auto e1 = [&](int64_t n, int64_t, int64_t, int64_t) { return kOmega * L.dinv[n] * L.b[n]; };
-        const double Ae = L.scale * face_sum(L.D, c, L.at, L.lab, e1);
-        L.e[c] = e1(c, 0, 0, 0) + kOmega * L.dinv[c] * (L.b[c] - Ae);
+        const double Ae = L.scale * face_sum_ac(L.D, c, i, j, k, L.ac, e1);
+        L.e[c] = e1(c, i, j, k) + kOmega * L.dinv[c] * (L.b[c] - Ae);
     }
 }
 
@@ -453,7 +461,7 @@ __global__ void __launch_bounds__(kIdpThreads) k_mg_restrict(MgLevel F, MgLevel 
     for (int64_t C = (int64_t)blockIdx.x * kIdpThreads + threadIdx.x; C < Cl.D.G;
          C += (int64_t)gridDim.x * kIdpThreads) {
         double sum = 0.0;
-        if (Cl.lab[C] == kIdpFluid) {
+        if (Cl.ac[C] > 0.0) {
             int64_t I, J, K;
             coords(Cl.D, C, I, J, K);
             for (int c = 0; c < 2; ++c)
@@ -462,9 +470,9 @@ __global__ void __launch_bounds__(kIdpThreads) k_mg_restrict(MgLevel F, MgLevel 
                         const int64_t i = 2 * I + a, j = 2 * J + b, k = 2 * K + c;
                         if (i >= F.D.nx || j >= F.D.ny || k >= F.D.nz) continue;
                         const int64_t f = (k * F.D.ny + j) * F.D.nx + i;
-                        if (F.lab[f] != kIdpFluid) continue;
-                        const double Ae = F.scale * face_sum(F.D, f, i, j, k, F.at, F.lab,
-                                                             [&](int64_t n, int64_t, int64_t, int64_t) { return F.e[n]; });
+                        if (!(F.ac[f] > 0.0)) continue;
+                        const double Ae = F.scale * face_sum_ac(F.D, f, i, j, k, F.ac,
+                                                                [&](int64_t n, int64_t, int64_t, int64_t) { return F.e[n]; });
                         sum += F.b[f] - Ae;
                     }
         }
@@ -478,23 +486,24 @@ __global__ void __launch_bounds__(kIdpThreads) k_mg_post1(MgLevel F, MgLevel Cl,
     if (cg_done(st)) return;
     for (int64_t c = (int64_t)blockIdx.x * kIdpThreads + threadIdx.x; c < F.D.G;
          c += (int64_t)gridDim.x * kIdpThreads) {
-        if (F.lab[c] != kIdpFluid) {
+        if (!(F.ac[c] > 0.0)) {
             F.t[c] = 0.0;
             continue;
         }
         auto u = [&](int64_t n, int64_t i, int64_t j, int64_t k) {
             const int64_t p = ((k >> 1) * Cl.D.ny + (j >> 1)) * Cl.D.nx + (i >> 1);
-            return Cl.lab[p] == kIdpFluid ? F.e[n] + Cl.e[p] : F.e[n];
+            return Cl.ac[p] > 0.0 ? F.e[n] + Cl.e[p] : F.e[n];
         };
         int64_t i, j, k;
         coords(F.D, c, i, j, k);
-        const double Au = F.scale * face_sum(F.D, c, i, j, k, F.at, F.lab, u);
+        const double Au = F.scale * face_sum_ac(F.D, c, i, j, k, F.ac, u);
         F.t[c] = u(c, i, j, k) + kOmega * F.dinv[c] * (F.b[c] - Au);
     }
 }
 
-// Second post-sweep into e: e = t + w D^-1 (b - A t); on the finest level
-// also the partials of b.e (= r.z of the CG iteration).
+// Second post-sweep into e: e = t + w D^-1 (b - A t) (e = b on non-fluid
+// rows); on the finest level also the partials of b.e (= r.z of the CG
+// iteration).
 __global__ void __launch_bounds__(kIdpThreads) k_mg_post2(MgLevel L, double *__restrict__ part,
                                                           const CgState *__restrict__ st)
 {
@@ -503,13 +512,14 @@ __global__ void __launch_bounds__(kIdpThreads) k_mg_post2(MgLevel L, double *__r
     double rz = 0.0;
     for (int64_t c = (int64_t)blockIdx.x * kIdpThreads + threadIdx.x; c < L.D.G;
          c += (int64_t)gridDim.x * kIdpThreads) {
-        if (L.lab[c] != kIdpFluid) {
-            L.e[c] = 0.0;
-            continue;
+        double z = L.b[c];
+        if (L.ac[c] > 0.0) {
+            int64_t i, j, k;
+            coords(L.D, c, i, j, k);
+            const double At = L.scale * face_sum_ac(L.D, c, i, j, k, L.ac,
+                                                    [&](int64_t n, int64_t, int64_t, int64_t) { return L.t[n]; });
+            z = L.t[c] + kOmega * L.dinv[c] * (L.b[c] - At);
         }
-        const double At =
-            L.scale * face_sum(L.D, c, L.at, L.lab, [&](int64_t n, int64_t, int64_t, int64_t) { return L.t[n]; });
-        const double z = L.t[c] + kOmega * L.dinv[c] * (L.b[c] - At);
         L.e[c] = z;
         rz += L.b[c] * z;
     }
@@ -523,25 +533,23 @@ __global__ void __launch_bounds__(kIdpThreads) k_mg_post2(MgLevel L, double *__r
 // Jacobi sweeps from zero, in LDS.
 __global__ void __launch_bounds__(kIdpThreads) k_mg_coarsest(MgLevel L, const CgState *__restrict__ st)
 {
-    __shared__ double se[2][kIdpThreads], sb[kIdpThreads], sdi[kIdpThreads], sat[kIdpThreads];
-    __shared__ uint8_t slab[kIdpThreads];
+    __shared__ double se[2][kIdpThreads], sb[kIdpThreads], sdi[kIdpThreads], sac[kIdpThreads];
     if (cg_done(st)) return;
     const int c = threadIdx.x;
     const bool live = c < L.D.G;
-    if (live) {
-        sb[c] = L.b[c];
-        sdi[c] = L.dinv[c];
-        sat[c] = L.at[c];
-        slab[c] = L.lab[c];
-    }
+    sb[c] = live ? L.b[c] : 0.0;
+    sdi[c] = live ? L.dinv[c] : 0.0;
+    sac[c] = live ? L.ac[c] : 0.0;
     se[0][c] = 0.0;
+    int64_t i = 0, j = 0, k = 0;
+    if (live) coords(L.D, c, i, j, k);
     __syncthreads();
     for (int s = 0; s < kCoarseSweeps; ++s) {
         const int cur = s & 1;
         double v = 0.0;
-        if (live && slab[c] == kIdpFluid) {
-            const double Ae = L.scale * face_sum(L.D, (int64_t)c, sat, slab,
-                                                 [&](int64_t n, int64_t, int64_t, int64_t) { return se[cur][n]; });
+        if (live && sac[c] > 0.0) {
+            const double Ae = L.scale * face_sum_ac(L.D, (int64_t)c, i, j, k, sac,
+                                                    [&](int64_t n, int64_t, int64_t, int64_t) { return se[cur][n]; });
             v = se[cur][c] + kOmega * sdi[c] * (sb[c] - Ae);
         }
         se[cur ^ 1][c] = v;
@@ -610,7 +618,7 @@ hipError_t launch_cg_start(const IdpDims &D, const double *at, const uint8_t *la
                            const IdpWork &W, double tol, hipStream_t st)
 {
     const unsigned nb = idp_blocks(D.G);
-    k_cg_init<<<nb, kIdpThreads, 0, st>>>(D, at, lab, s, q, W.r, W.d, W.dinv, W.part, W.state);
+    k_cg_init<<<nb, kIdpThreads, 0, st>>>(D, at, lab, s, q, W.r, W.d, W.dinv, W.lev[0].ac, W.part, W.state);
     if (W.nlev > 1) {
         for (int l = 0; l + 1 < W.nlev; ++l) {
             k_mg_coarsen<<<idp_blocks(W.lev[l + 1].D.G), kIdpThreads, 0, st>>>(W.lev[l], W.lev[l + 1]);
@@ -630,7 +638,7 @@ hipError_t launch_cg_iterations(const IdpDims &D, const double *at, const uint8_
     const unsigned nb = idp_blocks(D.G);
     const bool mg = W.nlev > 1;
     for (int k = k0; k < k0 + count; ++k) {
-        k_cg_apply<<<nb, kIdpThreads, 0, st>>>(D, at, lab, W.d, W.w, W.part, W.state);
+        k_cg_apply<<<nb, kIdpThreads, 0, st>>>(D, W.lev[0].ac, W.d, W.w, W.part, W.state);
         if (mg) {
             k_cg_update<false><<<nb, kIdpThreads, 0, st>>>(D, k, W.d, W.w, W.dinv, q, W.r, W.part, W.state);
             launch_vcycle(W, st);
