@@ -5,6 +5,7 @@
 
 #include "../../include/gic.h"
 #include "gic_launch.hpp"
+#include "idp_launch.hpp"
 
 using namespace gic;
 

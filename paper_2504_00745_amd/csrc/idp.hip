@@ -15,7 +15,7 @@
 // without atomics: each block writes one partial per quantity, and every
 // block of the consuming kernel sums all partials in the same fixed order,
 // so the iteration is deterministic and needs no clearing between launches.
-#include "gic_launch.hpp"
+#include "idp_launch.hpp"
 
 namespace gic {
 
