@@ -365,12 +365,11 @@ def time_capillary(d, wl_name, reps=10):
 # direction (r, 1/diag, d; d: 32).
 IDP_BYTES_PER_CELL_ITER = 24 + 56 + 32
 # With the multigrid V-cycle: w = L d (24), the update without r.z (d, w, q, r;
-# q, r: 48), per fine cell pre-smoothing (b, 1/diag, ac; e: 32), restriction
-# (e, b, ac: 24 plus 1/8 of a coarse write), the first post-sweep with the
-# coarse correction (e, b, 1/diag, ac, 1/8 of the coarse e and ac; t: 42) and
-# the second (t, b, 1/diag, ac; e: 40), the new direction (z, d; d: 24);
-# coarser levels add the four passes' bytes times 1/8 + 1/64 + ... = 1/7.
-IDP_MG_BYTES_PER_CELL_ITER = 24 + 48 + 32 + 25 + 42 + 40 + 24 + (32 + 25 + 42 + 40) / 7.0
+# q, r: 48), per fine cell the restriction (b, 1/diag, ac: 24 plus 1/8 of a
+# coarse write) and the correction with the post-sweep (b, 1/diag, ac, 1/8 of
+# the coarse e and ac; e: 34), the new direction (z, d; d: 24); coarser levels
+# add the two passes' bytes times 1/8 + 1/64 + ... = 1/7.
+IDP_MG_BYTES_PER_CELL_ITER = 24 + 48 + 25 + 34 + 24 + (25 + 34) / 7.0
 
 
 def time_idp(reps=3, tol=1e-6):

@@ -466,9 +466,10 @@ int64_t gic_idp_workspace_bytes(const gic_ctx *ctx);
  * precond 1: one multigrid V-cycle per iteration (levels halve each axis,
  * rounding up, down to at most 256 cells; a coarse cell is air if a child
  * is, else fluid if a child is, else solid, with the mean alpha_f' of its
- * children; level l uses 4^l L of its own cells; piecewise-constant
- * prolongation and its transpose; two damped Jacobi sweeps, omega = 2/3,
- * before and after the coarse correction; 48 sweeps on the coarsest level),
+ * children that are not solid; level l uses 4^l L of its own cells;
+ * piecewise-constant prolongation and its transpose; one damped Jacobi
+ * sweep, omega = 2/3, before and one after the coarse correction; 48 sweeps
+ * on the coarsest level),
  * a symmetric preconditioner, so CG applies.  Stops when
  * |r|_2 <= tol |rhs|_2 (recursively updated residual) or after max_iter
  * iterations.  Enqueues check_every iterations at a time and SYNCHRONISES the

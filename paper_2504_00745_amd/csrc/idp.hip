@@ -375,9 +375,11 @@ __global__ void __launch_bounds__(kIdpThreads) k_idp_faces(IdpDims D, double dx,
 // coefficients is the Galerkin product R A_{l-1} P of piecewise-constant
 // prolongation P (a fluid coarse cell's correction added to its fluid
 // children) and R = P^T (the sum of the fluid children's residuals).
-// Smoothing: two damped Jacobi sweeps (omega = 2/3) before and after the
-// coarse correction; the coarsest level (at most 256 cells) takes 48 sweeps
-// in LDS.  Equal pre- and post-sweeps and R = P^T keep the preconditioner
+// Smoothing: one damped Jacobi sweep (omega = 2/3) before and one after the
+// coarse correction; the pre-sweep from zero, w D^-1 b, is formed on the fly
+// where it is used, so a level costs two passes (restriction, correction and
+// post-sweep).  The coarsest level (at most 256 cells) takes 48 sweeps in
+// LDS.  Equal pre- and post-sweeps and R = P^T keep the preconditioner
 // symmetric.  Non-fluid rows of the finest level are identity rows and get
 // z = r.  Levels carry the signed coefficients (see face_sum_ac).
 constexpr double kOmega = 2.0 / 3.0;
@@ -436,28 +438,13 @@ __global__ void __launch_bounds__(kIdpThreads) k_mg_diag(MgLevel L)
     }
 }
 
-// Pre-smoothing from zero: e = w D^-1 b, then e += w D^-1 (b - A e).
-__global__ void __launch_bounds__(kIdpThreads) k_mg_pre(MgLevel L, const CgState *__restrict__ st)
-{
-    if (cg_done(st)) return;
-    for (int64_t c = (int64_t)blockIdx.x * kIdpThreads + threadIdx.x; c < L.D.G;
-         c += (int64_t)gridDim.x * kIdpThreads) {
-        if (!(L.ac[c] > 0.0)) {
-            L.e[c] = 0.0;
-            continue;
-        }
-        int64_t i, j, k;
-        coords(L.D, c, i, j, k);
-        auto e1 = [&](int64_t n, int64_t, int64_t, int64_t) { return kOmega * L.dinv[n] * L.b[n]; };
-        const double Ae = L.scale * face_sum_ac(L.D, c, i, j, k, L.ac, e1);
-        L.e[c] = e1(c, i, j, k) + kOmega * L.dinv[c] * (L.b[c] - Ae);
-    }
-}
-
-// Coarse right-hand side: the sum of the fluid children's residuals b - A e.
+// Restriction after one pre-smoothing sweep from zero, e1 = w D^-1 b (formed
+// on the fly): the coarse right-hand side is the sum of the fluid children's
+// residuals b - A e1.
 __global__ void __launch_bounds__(kIdpThreads) k_mg_restrict(MgLevel F, MgLevel Cl, const CgState *__restrict__ st)
 {
     if (cg_done(st)) return;
+    auto e1 = [&](int64_t n, int64_t, int64_t, int64_t) { return kOmega * F.dinv[n] * F.b[n]; };
     for (int64_t C = (int64_t)blockIdx.x * kIdpThreads + threadIdx.x; C < Cl.D.G;
          C += (int64_t)gridDim.x * kIdpThreads) {
         double sum = 0.0;
@@ -471,57 +458,38 @@ __global__ void __launch_bounds__(kIdpThreads) k_mg_restrict(MgLevel F, MgLevel 
                         if (i >= F.D.nx || j >= F.D.ny || k >= F.D.nz) continue;
                         const int64_t f = (k * F.D.ny + j) * F.D.nx + i;
                         if (!(F.ac[f] > 0.0)) continue;
-                        const double Ae = F.scale * face_sum_ac(F.D, f, i, j, k, F.ac,
-                                                                [&](int64_t n, int64_t, int64_t, int64_t) { return F.e[n]; });
-                        sum += F.b[f] - Ae;
+                        sum += F.b[f] - F.scale * face_sum_ac(F.D, f, i, j, k, F.ac, e1);
                     }
         }
         Cl.b[C] = sum;
     }
 }
 
-// Coarse correction and the first post-sweep: u = e + P E, t = u + w D^-1 (b - A u).
-__global__ void __launch_bounds__(kIdpThreads) k_mg_post1(MgLevel F, MgLevel Cl, const CgState *__restrict__ st)
-{
-    if (cg_done(st)) return;
-    for (int64_t c = (int64_t)blockIdx.x * kIdpThreads + threadIdx.x; c < F.D.G;
-         c += (int64_t)gridDim.x * kIdpThreads) {
-        if (!(F.ac[c] > 0.0)) {
-            F.t[c] = 0.0;
-            continue;
-        }
-        auto u = [&](int64_t n, int64_t i, int64_t j, int64_t k) {
-            const int64_t p = ((k >> 1) * Cl.D.ny + (j >> 1)) * Cl.D.nx + (i >> 1);
-            return Cl.ac[p] > 0.0 ? F.e[n] + Cl.e[p] : F.e[n];
-        };
-        int64_t i, j, k;
-        coords(F.D, c, i, j, k);
-        const double Au = F.scale * face_sum_ac(F.D, c, i, j, k, F.ac, u);
-        F.t[c] = u(c, i, j, k) + kOmega * F.dinv[c] * (F.b[c] - Au);
-    }
-}
-
-// Second post-sweep into e: e = t + w D^-1 (b - A t) (e = b on non-fluid
-// rows); on the finest level also the partials of b.e (= r.z of the CG
-// iteration).
-__global__ void __launch_bounds__(kIdpThreads) k_mg_post2(MgLevel L, double *__restrict__ part,
-                                                          const CgState *__restrict__ st)
+// Coarse correction and one post-smoothing sweep: u = e1 + P E, e = u + w D^-1
+// (b - A u) (e = b on non-fluid rows); on the finest level also the partials
+// of b.e (= r.z of the CG iteration).
+__global__ void __launch_bounds__(kIdpThreads) k_mg_post(MgLevel F, MgLevel Cl, double *__restrict__ part,
+                                                         const CgState *__restrict__ st)
 {
     __shared__ double red[4];
     if (cg_done(st)) return;
+    auto u = [&](int64_t n, int64_t i, int64_t j, int64_t k) {
+        const int64_t p = ((k >> 1) * Cl.D.ny + (j >> 1)) * Cl.D.nx + (i >> 1);
+        const double e1 = kOmega * F.dinv[n] * F.b[n];
+        return Cl.ac[p] > 0.0 ? e1 + Cl.e[p] : e1;
+    };
     double rz = 0.0;
-    for (int64_t c = (int64_t)blockIdx.x * kIdpThreads + threadIdx.x; c < L.D.G;
+    for (int64_t c = (int64_t)blockIdx.x * kIdpThreads + threadIdx.x; c < F.D.G;
          c += (int64_t)gridDim.x * kIdpThreads) {
-        double z = L.b[c];
-        if (L.ac[c] > 0.0) {
+        double z = F.b[c];
+        if (F.ac[c] > 0.0) {
             int64_t i, j, k;
-            coords(L.D, c, i, j, k);
-            const double At = L.scale * face_sum_ac(L.D, c, i, j, k, L.ac,
-                                                    [&](int64_t n, int64_t, int64_t, int64_t) { return L.t[n]; });
-            z = L.t[c] + kOmega * L.dinv[c] * (L.b[c] - At);
+            coords(F.D, c, i, j, k);
+            const double Au = F.scale * face_sum_ac(F.D, c, i, j, k, F.ac, u);
+            z = u(c, i, j, k) + kOmega * F.dinv[c] * (F.b[c] - Au);
         }
-        L.e[c] = z;
-        rz += L.b[c] * z;
+        F.e[c] = z;
+        rz += F.b[c] * z;
     }
     if (part) {
         rz = block_sum(rz, red);
@@ -602,16 +570,12 @@ hipError_t launch_idp_faces(const IdpDims &D, double dx, const double *q, const 
 static void launch_vcycle(const IdpWork &W, hipStream_t st)
 {
     const int L = W.nlev;
-    for (int l = 0; l + 1 < L; ++l) {
-        k_mg_pre<<<idp_blocks(W.lev[l].D.G), kIdpThreads, 0, st>>>(W.lev[l], W.state);
+    for (int l = 0; l + 1 < L; ++l)
         k_mg_restrict<<<idp_blocks(W.lev[l + 1].D.G), kIdpThreads, 0, st>>>(W.lev[l], W.lev[l + 1], W.state);
-    }
     k_mg_coarsest<<<1, kIdpThreads, 0, st>>>(W.lev[L - 1], W.state);
-    for (int l = L - 2; l >= 0; --l) {
-        k_mg_post1<<<idp_blocks(W.lev[l].D.G), kIdpThreads, 0, st>>>(W.lev[l], W.lev[l + 1], W.state);
-        k_mg_post2<<<idp_blocks(W.lev[l].D.G), kIdpThreads, 0, st>>>(W.lev[l], l == 0 ? W.part : nullptr,
-                                                                      W.state);
-    }
+    for (int l = L - 2; l >= 0; --l)
+        k_mg_post<<<idp_blocks(W.lev[l].D.G), kIdpThreads, 0, st>>>(W.lev[l], W.lev[l + 1],
+                                                                     l == 0 ? W.part : nullptr, W.state);
 }
 
 hipError_t launch_cg_start(const IdpDims &D, const double *at, const uint8_t *lab, const double *s, const double *q,
