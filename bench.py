@@ -365,11 +365,13 @@ def time_capillary(d, wl_name, reps=10):
 # direction (r, 1/diag, d; d: 32).
 IDP_BYTES_PER_CELL_ITER = 24 + 56 + 32
 # With the multigrid V-cycle: w = L d (24), the update without r.z (d, w, q, r;
-# q, r: 48), per fine cell the restriction (b, 1/diag, ac: 24 plus 1/8 of a
-# coarse write) and the correction with the post-sweep (b, 1/diag, ac, 1/8 of
-# the coarse e and ac; e: 34), the new direction (z, d; d: 24); coarser levels
-# add the two passes' bytes times 1/8 + 1/64 + ... = 1/7.
-IDP_MG_BYTES_PER_CELL_ITER = 24 + 48 + 25 + 34 + 24 + (25 + 34) / 7.0
+# q, r: 48), the new direction (z, d; d: 24) and per fine cell the
+# restriction (b, 1/diag, ac: 24 plus 1/8 of a coarse write), the coarse
+# correction (b, 1/diag, ac, 1/8 of the coarse e and ac; u: 34) and the
+# post-sweep (u, ac, 1/diag, b; e: 40), on every level of at least 2^18
+# cells (the finest two here: 1 + 1/8); smaller levels correct and sweep in
+# one pass (b, 1/diag, ac, coarse e and ac; e: 34), 1/64 + 1/512 + ... = 1/56.
+IDP_MG_BYTES_PER_CELL_ITER = 24 + 48 + 24 + (25 + 34 + 40) * (1 + 1 / 8.0) + (25 + 34) / 56.0
 
 
 def time_idp(reps=3, tol=1e-6):

@@ -180,8 +180,8 @@ int64_t idp_work_bytes(const IdpDims &D0)
 {
     IdpDims lv[kMgMaxLevels];
     const int L = idp_levels(D0, lv);
-    int64_t b = 8 * idp_align(D0.G * 8) + idp_align(3 * kIdpMaxBlocks * 8) + idp_align(sizeof(CgState));
-    for (int l = 1; l < L; ++l) b += 4 * idp_align(lv[l].G * 8);
+    int64_t b = 9 * idp_align(D0.G * 8) + idp_align(3 * kIdpMaxBlocks * 8) + idp_align(sizeof(CgState));
+    for (int l = 1; l < L; ++l) b += 5 * idp_align(lv[l].G * 8);
     return b;
 }
 
@@ -200,8 +200,8 @@ IdpWork idp_carve(void *work, const IdpDims &D0, int precond, double **at, doubl
     W.d = (double *)(p + 3 * a);
     W.w = (double *)(p + 4 * a);
     W.dinv = (double *)(p + 5 * a);
-    double *z = (double *)(p + 6 * a), *ac = (double *)(p + 7 * a);
-    p += 8 * a;
+    double *z = (double *)(p + 6 * a), *ac = (double *)(p + 7 * a), *t = (double *)(p + 8 * a);
+    p += 9 * a;
     W.part = (double *)p;
     p += idp_align(3 * kIdpMaxBlocks * 8);
     W.state = (CgState *)p;
@@ -209,7 +209,7 @@ IdpWork idp_carve(void *work, const IdpDims &D0, int precond, double **at, doubl
     IdpDims lv[kMgMaxLevels];
     const int L = idp_levels(D0, lv);
     W.nlev = precond == 1 ? L : 1;
-    W.lev[0] = MgLevel{D0, 1.0, ac, W.dinv, W.r, z};
+    W.lev[0] = MgLevel{D0, 1.0, ac, W.dinv, W.r, z, t};
     double scale = 1.0;
     for (int l = 1; l < L; ++l) {
         scale *= 4.0;
@@ -221,7 +221,8 @@ IdpWork idp_carve(void *work, const IdpDims &D0, int precond, double **at, doubl
         m.dinv = (double *)(p + g);
         m.b = (double *)(p + 2 * g);
         m.e = (double *)(p + 3 * g);
-        p += 4 * g;
+        m.t = (double *)(p + 4 * g);
+        p += 5 * g;
         W.lev[l] = m;
     }
     return W;

@@ -440,28 +440,79 @@ __global__ void __launch_bounds__(kIdpThreads) k_mg_diag(MgLevel L)
 
 // Restriction after one pre-smoothing sweep from zero, e1 = w D^-1 b (formed
 // on the fly): the coarse right-hand side is the sum of the fluid children's
-// residuals b - A e1.
+// residuals b - A e1.  Eight adjacent lanes take the eight children of one
+// coarse cell (lane bits: x, y, z offset) and add their residuals with three
+// butterfly shuffles, the same order in every group.
 __global__ void __launch_bounds__(kIdpThreads) k_mg_restrict(MgLevel F, MgLevel Cl, const CgState *__restrict__ st)
 {
     if (cg_done(st)) return;
     auto e1 = [&](int64_t n, int64_t, int64_t, int64_t) { return kOmega * F.dinv[n] * F.b[n]; };
-    for (int64_t C = (int64_t)blockIdx.x * kIdpThreads + threadIdx.x; C < Cl.D.G;
-         C += (int64_t)gridDim.x * kIdpThreads) {
-        double sum = 0.0;
+    const int64_t total = 8 * Cl.D.G;  // a multiple of 8: the lanes of a group leave the loop together
+    for (int64_t t = (int64_t)blockIdx.x * kIdpThreads + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * kIdpThreads) {
+        const int64_t C = t >> 3;
+        const int ch = (int)(t & 7);
+        double v = 0.0;
         if (Cl.ac[C] > 0.0) {
             int64_t I, J, K;
             coords(Cl.D, C, I, J, K);
-            for (int c = 0; c < 2; ++c)
-                for (int b = 0; b < 2; ++b)
-                    for (int a = 0; a < 2; ++a) {
-                        const int64_t i = 2 * I + a, j = 2 * J + b, k = 2 * K + c;
-                        if (i >= F.D.nx || j >= F.D.ny || k >= F.D.nz) continue;
-                        const int64_t f = (k * F.D.ny + j) * F.D.nx + i;
-                        if (!(F.ac[f] > 0.0)) continue;
-                        sum += F.b[f] - F.scale * face_sum_ac(F.D, f, i, j, k, F.ac, e1);
-                    }
+            const int64_t i = 2 * I + (ch & 1), j = 2 * J + ((ch >> 1) & 1), k = 2 * K + (ch >> 2);
+            if (i < F.D.nx && j < F.D.ny && k < F.D.nz) {
+                const int64_t f = (k * F.D.ny + j) * F.D.nx + i;
+                if (F.ac[f] > 0.0) v = F.b[f] - F.scale * face_sum_ac(F.D, f, i, j, k, F.ac, e1);
+            }
         }
-        Cl.b[C] = sum;
+        v += __shfl_xor(v, 1);
+        v += __shfl_xor(v, 2);
+        v += __shfl_xor(v, 4);
+        if (ch == 0) Cl.b[C] = v;
+    }
+}
+
+// Coarse correction alone: u = e1 + P E on fluid cells (0 elsewhere) into t,
+// for the larger levels, where the post-sweep then reads u once per
+// neighbour.
+__global__ void __launch_bounds__(kIdpThreads) k_mg_prolong(MgLevel F, MgLevel Cl, const CgState *__restrict__ st)
+{
+    if (cg_done(st)) return;
+    for (int64_t c = (int64_t)blockIdx.x * kIdpThreads + threadIdx.x; c < F.D.G;
+         c += (int64_t)gridDim.x * kIdpThreads) {
+        double u = 0.0;
+        if (F.ac[c] > 0.0) {
+            int64_t i, j, k;
+            coords(F.D, c, i, j, k);
+            const int64_t p = ((k >> 1) * Cl.D.ny + (j >> 1)) * Cl.D.nx + (i >> 1);
+            u = kOmega * F.dinv[c] * F.b[c];
+            if (Cl.ac[p] > 0.0) u += Cl.e[p];
+        }
+        F.t[c] = u;
+    }
+}
+
+// Post-sweep from the prolonged iterate u (in t): e = u + w D^-1 (b - A u)
+// (e = b on non-fluid rows); on the finest level also the partials of b.e.
+__global__ void __launch_bounds__(kIdpThreads) k_mg_sweep(MgLevel F, double *__restrict__ part,
+                                                          const CgState *__restrict__ st)
+{
+    __shared__ double red[4];
+    if (cg_done(st)) return;
+    double rz = 0.0;
+    for (int64_t c = (int64_t)blockIdx.x * kIdpThreads + threadIdx.x; c < F.D.G;
+         c += (int64_t)gridDim.x * kIdpThreads) {
+        double z = F.b[c];
+        if (F.ac[c] > 0.0) {
+            int64_t i, j, k;
+            coords(F.D, c, i, j, k);
+            const double Au = F.scale * face_sum_ac(F.D, c, i, j, k, F.ac,
+                                                    [&](int64_t n, int64_t, int64_t, int64_t) { return F.t[n]; });
+            z = F.t[c] + kOmega * F.dinv[c] * (F.b[c] - Au);
+        }
+        F.e[c] = z;
+        rz += F.b[c] * z;
+    }
+    if (part) {
+        rz = block_sum(rz, red);
+        if (threadIdx.x == 0) part[gridDim.x + blockIdx.x] = rz;
     }
 }
 
@@ -567,15 +618,26 @@ hipError_t launch_idp_faces(const IdpDims &D, double dx, const double *q, const 
 }
 
 // z = M^-1 r by one V-cycle over the levels of W (level 0 works on r and z).
+// Levels with at least this many cells prolong in a pass of their own and
+// then sweep; smaller levels do both in one pass (launch latency dominates).
+constexpr int64_t kMgSplitCells = 1 << 18;
+
 static void launch_vcycle(const IdpWork &W, hipStream_t st)
 {
     const int L = W.nlev;
     for (int l = 0; l + 1 < L; ++l)
-        k_mg_restrict<<<idp_blocks(W.lev[l + 1].D.G), kIdpThreads, 0, st>>>(W.lev[l], W.lev[l + 1], W.state);
+        k_mg_restrict<<<idp_blocks(8 * W.lev[l + 1].D.G), kIdpThreads, 0, st>>>(W.lev[l], W.lev[l + 1], W.state);
     k_mg_coarsest<<<1, kIdpThreads, 0, st>>>(W.lev[L - 1], W.state);
-    for (int l = L - 2; l >= 0; --l)
-        k_mg_post<<<idp_blocks(W.lev[l].D.G), kIdpThreads, 0, st>>>(W.lev[l], W.lev[l + 1],
-                                                                     l == 0 ? W.part : nullptr, W.state);
+    for (int l = L - 2; l >= 0; --l) {
+        const unsigned nb = idp_blocks(W.lev[l].D.G);
+        double *part = l == 0 ? W.part : nullptr;
+        if (W.lev[l].D.G >= kMgSplitCells) {
+            k_mg_prolong<<<nb, kIdpThreads, 0, st>>>(W.lev[l], W.lev[l + 1], W.state);
+            k_mg_sweep<<<nb, kIdpThreads, 0, st>>>(W.lev[l], part, W.state);
+        } else {
+            k_mg_post<<<nb, kIdpThreads, 0, st>>>(W.lev[l], W.lev[l + 1], part, W.state);
+        }
+    }
 }
 
 hipError_t launch_cg_start(const IdpDims &D, const double *at, const uint8_t *lab, const double *s, const double *q,

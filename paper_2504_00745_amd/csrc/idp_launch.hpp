@@ -26,13 +26,13 @@ struct CgState {
 
 // One level of the solver's hierarchy: its cells, operator scale
 // (A_l = scale L_l), signed coefficients (alpha_f' on fluid cells, -alpha_f'
-// on air cells, 0 on solid cells), 1 / diag(A_l), right-hand side and
-// correction.  Level 0 is the fine grid.
+// on air cells, 0 on solid cells), 1 / diag(A_l), right-hand side,
+// correction and the prolonged iterate.  Level 0 is the fine grid.
 struct MgLevel {
     IdpDims D;
     double scale;
     double *ac;
-    double *dinv, *b, *e;
+    double *dinv, *b, *e, *t;
 };
 
 constexpr int kMgMaxLevels = 24;
