@@ -462,8 +462,8 @@ def cpu_baseline(d, steps):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported by this build "
-              "(multi-GPU sharding is a design note, not code).", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported: the path runs on one GPU "
+              "and its sharding across GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2504_00745_amd import gic, workloads as wl
