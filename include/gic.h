@@ -69,7 +69,10 @@ typedef enum {
                             contribution of magnitude >= 2^51 units, or
                             cell ranges / sorted order that do not match
                             the positions (ranges and order indices are
-                            clipped to [0, n) before any access)         */
+                            clipped to [0, n) before any access); in the
+                            density projection a cell label outside 0..2
+                            or alpha_f' not in (0, inf) on a fluid or air
+                            cell (index = the cell)                      */
 } gic_status;
 
 typedef enum { GIC_FP64 = 0, GIC_FP32 = 1 } gic_precision;
@@ -444,6 +447,9 @@ gic_status gic_permute(gic_ctx *ctx, int64_t n, int32_t comps, const int32_t *or
  * off the fluid.  Reading: the sign of Eq. 12b is kept (the fluid moves out
  * of a cell whose fraction exceeds its target); App. B prints the operator
  * with the opposite sign of its right-hand side.
+ *
+ * A label outside 0..2 (setup, solve) or alpha_t not in (0, inf) on a fluid
+ * or air cell (solve) latches GIC_E_RANGE with the cell's index.
  *
  * gic_idp_setup: alpha_t = 1 - min(alpha_fx 2^-32, alpha_max) (the target
  * fraction from the P2G grid, G int64) and rhs (the right-hand side above,

@@ -235,7 +235,7 @@ gic_status idp_cg(const gic_ctx *c, const double *at, const uint8_t *label, cons
                   double *relres, hipStream_t st)
 {
     const IdpDims D = idp_dims(c->dp);
-    hipError_t e = launch_cg_start(D, at, label, s, q, W, tol, st);
+    hipError_t e = launch_cg_start(D, at, label, s, q, W, tol, c->err, st);
     CgState h;
     int k = 0;
     for (;;) {
@@ -765,7 +765,7 @@ gic_status gic_idp_setup(gic_ctx *c, const int64_t *alpha_fx, const double *alph
 {
     if (!c || !alpha_fx || !alpha_star || !label || !alpha_t || !rhs) return GIC_E_ARG;
     return hip_status(launch_idp_setup(idp_dims(c->dp), c->dp.alpha_max, alpha_fx, alpha_star, label, alpha_t, rhs,
-                                       (hipStream_t)stream));
+                                       c->err, (hipStream_t)stream));
 }
 
 gic_status gic_idp_apply(gic_ctx *c, const double *alpha_t, const uint8_t *label, const double *q, double *out,
@@ -805,7 +805,7 @@ gic_status gic_density_projection(gic_ctx *c, const int64_t *alpha_fx, const dou
     hipStream_t s = (hipStream_t)stream;
     double *at, *rhs;
     const IdpWork W = idp_carve(work, D, precond, &at, &rhs);
-    if (launch_idp_setup(D, c->dp.alpha_max, alpha_fx, alpha_star, label, at, rhs, s) != hipSuccess)
+    if (launch_idp_setup(D, c->dp.alpha_max, alpha_fx, alpha_star, label, at, rhs, c->err, s) != hipSuccess)
         return GIC_E_HIP;
     const gic_status st = idp_cg(c, at, label, rhs, q, W, max_iter, tol, check_every, iters, relres, s);
     if (st != GIC_OK) return st;

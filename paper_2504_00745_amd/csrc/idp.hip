@@ -147,11 +147,12 @@ __global__ void __launch_bounds__(kIdpThreads) k_idp_setup(IdpDims D, double alp
                                                            const int64_t *__restrict__ afx,
                                                            const double *__restrict__ astar,
                                                            const uint8_t *__restrict__ lab, double *__restrict__ at,
-                                                           double *__restrict__ s)
+                                                           double *__restrict__ s, int64_t *err)
 {
 #pragma clang fp contract(off)
     for (int64_t c = (int64_t)blockIdx.x * kIdpThreads + threadIdx.x; c < D.G;
          c += (int64_t)gridDim.x * kIdpThreads) {
+        if (lab[c] > kIdpSolid) raise_error(err, kErrRange, c);
         double as = (double)afx[c] * 2.3283064365386963e-10;  // 2^-32
         as = as < alpha_max ? as : alpha_max;
         const double a = 1.0 - as;
@@ -183,7 +184,8 @@ __global__ void __launch_bounds__(kIdpThreads) k_cg_init(IdpDims D, const double
                                                          const double *__restrict__ s, const double *__restrict__ q,
                                                          double *__restrict__ r, double *__restrict__ d,
                                                          double *__restrict__ dinv, double *__restrict__ ac,
-                                                         double *__restrict__ part, CgState *__restrict__ st)
+                                                         double *__restrict__ part, CgState *__restrict__ st,
+                                                         int64_t *err)
 {
     __shared__ double red[4];
     double rz = 0.0, rr = 0.0, ss = 0.0;
@@ -192,6 +194,9 @@ __global__ void __launch_bounds__(kIdpThreads) k_cg_init(IdpDims D, const double
         double Lq, dg;
         apply_row(D, c, at, lab, q, Lq, dg);
         const uint8_t lc = lab[c];
+        // the signed coefficients need alpha_f' > 0 on fluid and air cells and a known label
+        if (lc > kIdpSolid || (lc != kIdpSolid && !(at[c] > 0.0 && at[c] < INFINITY)))
+            raise_error(err, kErrRange, c);
         ac[c] = lc == kIdpFluid ? at[c] : (lc == kIdpAir ? -at[c] : 0.0);
         const double sc = lab[c] == kIdpFluid ? s[c] : 0.0;
         const double rc = sc - Lq;
@@ -597,9 +602,9 @@ IdpDims idp_dims(const DevParams &P)
 }
 
 hipError_t launch_idp_setup(const IdpDims &D, double alpha_max, const int64_t *afx, const double *astar,
-                            const uint8_t *lab, double *at, double *s, hipStream_t st)
+                            const uint8_t *lab, double *at, double *s, int64_t *err, hipStream_t st)
 {
-    k_idp_setup<<<idp_blocks(D.G), kIdpThreads, 0, st>>>(D, alpha_max, afx, astar, lab, at, s);
+    k_idp_setup<<<idp_blocks(D.G), kIdpThreads, 0, st>>>(D, alpha_max, afx, astar, lab, at, s, err);
     return hipGetLastError();
 }
 
@@ -641,10 +646,10 @@ static void launch_vcycle(const IdpWork &W, hipStream_t st)
 }
 
 hipError_t launch_cg_start(const IdpDims &D, const double *at, const uint8_t *lab, const double *s, const double *q,
-                           const IdpWork &W, double tol, hipStream_t st)
+                           const IdpWork &W, double tol, int64_t *err, hipStream_t st)
 {
     const unsigned nb = idp_blocks(D.G);
-    k_cg_init<<<nb, kIdpThreads, 0, st>>>(D, at, lab, s, q, W.r, W.d, W.dinv, W.lev[0].ac, W.part, W.state);
+    k_cg_init<<<nb, kIdpThreads, 0, st>>>(D, at, lab, s, q, W.r, W.d, W.dinv, W.lev[0].ac, W.part, W.state, err);
     if (W.nlev > 1) {
         for (int l = 0; l + 1 < W.nlev; ++l) {
             k_mg_coarsen<<<idp_blocks(W.lev[l + 1].D.G), kIdpThreads, 0, st>>>(W.lev[l], W.lev[l + 1]);

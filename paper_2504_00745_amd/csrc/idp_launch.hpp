@@ -50,13 +50,13 @@ struct IdpWork {
 
 IdpDims idp_dims(const DevParams &P);
 hipError_t launch_idp_setup(const IdpDims &D, double alpha_max, const int64_t *afx, const double *astar,
-                            const uint8_t *lab, double *at, double *s, hipStream_t st);
+                            const uint8_t *lab, double *at, double *s, int64_t *err, hipStream_t st);
 hipError_t launch_idp_apply(const IdpDims &D, const double *at, const uint8_t *lab, const double *v, double *out,
                             hipStream_t st);
 hipError_t launch_idp_faces(const IdpDims &D, double dx, const double *q, const uint8_t *lab, double *fx,
                             double *fy, double *fz, hipStream_t st);
 hipError_t launch_cg_start(const IdpDims &D, const double *at, const uint8_t *lab, const double *s, const double *q,
-                           const IdpWork &W, double tol, hipStream_t st);
+                           const IdpWork &W, double tol, int64_t *err, hipStream_t st);
 hipError_t launch_cg_iterations(const IdpDims &D, const double *at, const uint8_t *lab, double *q,
                                 const IdpWork &W, int k0, int count, hipStream_t st);
 

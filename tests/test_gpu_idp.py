@@ -123,6 +123,7 @@ def test_projection_matches_direct_solve(G, orc, name, precond):
     assert np.array_equal(host(fx, ox.shape), ox)
     assert np.array_equal(host(fy, oy.shape), oy)
     assert np.array_equal(host(fz, oz.shape), oz)
+    assert ctx.error() == (0, -1)
     G.say(f"  {name} precond {precond}: {it} iterations, relres {rel:.2e}")
 
 
@@ -248,3 +249,25 @@ def test_multigrid_on_tiny_and_flat_grids(G, orc):
         res = np.linalg.norm(s - orc.idp.apply(at, lab, host(q, shape)))
         assert res <= 1.5e-10 * np.linalg.norm(s)
         assert np.linalg.norm(host(q, shape) - q_or) <= res / lambda_min(orc, at, lab) * 1.01 + 1e-15
+
+
+def test_invalid_labels_and_fractions_latch_errors(G):
+    """A label outside 0..2 latches GIC_E_RANGE at setup; alpha_f' = 0 on an
+    air cell latches it at the start of a solve; the index is the cell."""
+    import torch
+    from paper_2504_00745_amd import gic
+    G.say("[idp latched errors]")
+    d, ctx, D = setup(G, "p2")
+    at = torch.empty(ctx.G, dtype=torch.float64, device="cuda")
+    s = torch.empty_like(at)
+    lab = D["lab"].clone()
+    lab[1234] = 3
+    gic.gic_idp_setup(ctx, D["afx"], D["ast"], lab, at, s)
+    assert ctx.error() == (6, 1234)
+    gic.gic_idp_setup(ctx, D["afx"], D["ast"], D["lab"], at, s)
+    assert ctx.error() == (0, -1)
+    air = int(np.flatnonzero(d["label"] == 1)[7])
+    at[air] = 0.0
+    q = torch.zeros_like(at)
+    gic.gic_idp_solve(ctx, at, D["lab"], s, q, gic.idp_workspace(ctx), max_iter=4, tol=1e-6)
+    assert ctx.error() == (6, air)
