@@ -131,6 +131,7 @@ def _declare(L):
         "orc_fst": (C.c_double, [_pk, C.c_double, C.c_double]),
         "orc_capillary_pair_force": (None, [_pk, _d, _d, C.c_double, C.c_double, C.c_double, C.c_double, _d]),
         "orc_capillary_forces": (None, [_pp, _pk, C.c_int64, _d, _d, _d, _d]),
+        "orc_capillary_forces_sample": (None, [_pp, _pk, C.c_int64, _d, _d, _d, C.c_int64, _i64, _d, _d]),
         "orc_num_threads": (C.c_int, []),
         "orc_set_num_threads": (None, [C.c_int]),
     }
@@ -559,4 +560,18 @@ def rollout_vjp(cfg, x0, v0, r, u, steps):
                               _ptr(r, C.c_double), _ptr(u, C.c_double), int(steps), _ptr(gv0, C.c_double),
                               _ptr(gmu, C.c_double), _ptr(gcd, C.c_double))
     return L, gv0, float(gmu[0]), float(gcd[0])
+def capillary_forces_sample(cfg, x, r, sr, idx):
+    """Capillary force (3, m) on the sampled granules idx and the sum of the
+    magnitudes of their bridge forces (m,)."""
+    x, r, sr = _f64(x), _f64(r), _f64(sr)
+    idx = np.ascontiguousarray(idx, np.int64)
+    m = idx.shape[0]
+    F = np.zeros((3, m))
+    fa = np.zeros(m)
+    lib().orc_capillary_forces_sample(C.byref(params(cfg)), C.byref(capillary(cfg)), x.shape[1], _ptr(x, C.c_double),
+                                      _ptr(r, C.c_double), _ptr(sr, C.c_double), m, _ptr(idx, C.c_int64),
+                                      _ptr(F, C.c_double), _ptr(fa, C.c_double))
+    return F, fa
+
+
 from . import idp  # noqa: E402,F401  (density projection, numpy/scipy)

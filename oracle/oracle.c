@@ -1418,6 +1418,41 @@ void orc_capillary_pair_force(const orc_capillary *c, const double *xi, const do
     orc_capillary_pair(c, xi, xj, ri, rj, sri, srj, F);
 }
 
+/* Capillary force on the sampled granules idx[0..m) alone (3m, one by one
+ * over the 27 cells around each), and the sum of the magnitudes of their
+ * bridge forces (fabs_out, m, optional). */
+void orc_capillary_forces_sample(const orc_params *p, const orc_capillary *c, int64_t n, const double *x,
+                                 const double *r, const double *sr, int64_t m, const int64_t *idx, double *F,
+                                 double *fabs_out)
+{
+    orc_cells cl;
+    orc_cells_build(p, n, x, &cl);
+    int64_t cap = 27 * orc_cells_maxocc(p, &cl) + 1;
+#pragma omp parallel
+    {
+        int64_t *cand = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap);
+#pragma omp for schedule(static)
+        for (int64_t s = 0; s < m; ++s) {
+            int64_t i = idx[s];
+            double xi[3], acc[3] = {0.0, 0.0, 0.0}, fa = 0.0;
+            orc_pos(n, x, i, xi);
+            int64_t k = orc_candidates(p, n, x, &cl, i, cand);
+            for (int64_t t = 0; t < k; ++t) {
+                int64_t j = cand[t];
+                double xj[3], Fp[3];
+                orc_pos(n, x, j, xj);
+                orc_capillary_pair(c, xi, xj, r[i], r[j], sr[i], sr[j], Fp);
+                for (int a = 0; a < 3; ++a) acc[a] += Fp[a];
+                fa += sqrt((Fp[0] * Fp[0] + Fp[1] * Fp[1]) + Fp[2] * Fp[2]);
+            }
+            for (int a = 0; a < 3; ++a) F[a * m + s] = acc[a];
+            if (fabs_out) fabs_out[s] = fa;
+        }
+        free(cand);
+    }
+    orc_cells_free(&cl);
+}
+
 /* Adds the capillary force of every bridged pair to F (3n); the candidates
  * are the 27 cells around each granule's cell. */
 void orc_capillary_forces(const orc_params *p, const orc_capillary *c, int64_t n, const double *x, const double *r,

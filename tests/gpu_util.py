@@ -70,3 +70,24 @@ def run_stages(cfg, x, v, r, u, precision, alpha_in=None, r_max=None):
                ncont=unsort(nct[:n], 1).astype(np.int64), x1=unsort(X1, 3), v1=unsort(V1, 3),
                alpha1=A1.cpu().numpy(), mom1=M1.cpu().numpy().reshape(3, -1), err=ctx.error())
     return out
+
+
+def p2g_of(cfg, x, v, r, precision, r_max=None):
+    """int64 P2G grids (alpha (G,), momentum (3, G)) of a host state through
+    the HIP path (sort, reorder, gic_p2g)."""
+    n = x.shape[1]
+    ctx = gic.Context(cfg, max(n, 1), precision, r_max)
+    X, V, R = dev(x.reshape(-1)), dev(v.reshape(-1)), dev(r)
+    ID = torch.arange(n, dtype=torch.int32, device="cuda")
+    key = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+    order = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+    cb = torch.empty(ctx.K, dtype=torch.int32, device="cuda")
+    ce = torch.empty(ctx.K, dtype=torch.int32, device="cuda")
+    gic.gic_sort_cells(ctx, X.view(3, n), key, order, cb, ce)
+    Xs, Vs, Rs, IDs = torch.empty_like(X), torch.empty_like(V), torch.empty_like(R), torch.empty_like(ID)
+    gic.gic_reorder(ctx, order, X.view(3, n), V, R, ID, Xs, Vs, Rs, IDs)
+    A = torch.zeros(ctx.G, dtype=torch.int64, device="cuda")
+    M = torch.zeros(3 * ctx.G, dtype=torch.int64, device="cuda")
+    gic.gic_p2g(ctx, Xs.view(3, n), Vs, Rs, cb, ce, A, M)
+    torch.cuda.synchronize()
+    return A.cpu().numpy(), M.cpu().numpy().reshape(3, -1)

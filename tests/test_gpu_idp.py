@@ -4,11 +4,14 @@ inputs.
 
 Bars: the target fraction, right-hand side, operator product and face
 displacements bit for bit (the same double operations in the same order on
-the same inputs); the CG solution by what the oracle can check at any size:
-its true residual |s - L q| / |s| (oracle operator) within 1.5 tol, and, where
-the oracle's direct solve fits, |q - q_direct|_2 <= |s - L q|_2 / lambda_min
-(lambda_min of L from the oracle's matrix), the bound any approximate
-solution obeys.
+the same inputs); the CG solution by properties that hold at any size, with
+the oracle's matrix L (assembled from the oracle's own inputs) multiplied by
+the GPU's solution in the test: the true residual |s - L q| / |s| within
+1.5 tol, and, where the oracle's direct solve fits, |q - q_direct|_2 <=
+|s - L q|_2 / lambda_min (lambda_min of L), the bound any approximate
+solution obeys; the faces of the GPU's solution within 2 dx max|q - q_direct|
+of the oracle's faces of its own solution (a face is dx times a difference
+of two cells, clamped).
 """
 import numpy as np
 import pytest
@@ -41,6 +44,36 @@ def setup(G, name):
 
 def host(t, shape):
     return t.cpu().numpy().reshape(shape)
+
+
+def residual(orc, at, lab, s, q):
+    """|s - L q|_2 with the oracle's matrix of (at, lab), multiplied here."""
+    A = orc.idp.matrix(at, lab)
+    return float(np.linalg.norm(s.ravel() - A @ q.ravel()))
+
+
+def faces_of(q, lab, dx):
+    """The face displacements the header defines, formed here from a GPU
+    solution (a property of the GPU's output, not an oracle value)."""
+    FL, AIR, SOL = 0, 1, 2
+    qf = np.where(lab == FL, q, 0.0)
+    out = []
+    for axis in (2, 1, 0):
+        n = lab.shape[axis]
+        lo = [slice(None)] * 3
+        hi = [slice(None)] * 3
+        lo[axis], hi[axis] = slice(0, n - 1), slice(1, n)
+        lc, ln = lab[tuple(lo)], lab[tuple(hi)]
+        live = ((lc == FL) | (ln == FL)) & (lc != SOL) & (ln != SOL)
+        val = np.where(live, np.clip(dx * (qf[tuple(lo)] - qf[tuple(hi)]), -dx, dx), 0.0)
+        shape = list(lab.shape)
+        shape[axis] += 1
+        f = np.zeros(shape)
+        inner = [slice(None)] * 3
+        inner[axis] = slice(1, n)
+        f[tuple(inner)] = val
+        out.append(f)
+    return out
 
 
 def lambda_min(orc, at, lab):
@@ -114,15 +147,15 @@ def test_projection_matches_direct_solve(G, orc, name, precond):
     at_or = orc.idp.target_fraction(d["alpha_fx"].reshape(sh), d["params"]["alpha_max"])
     s_or = orc.idp.rhs(at_or, d["alpha_star"].reshape(sh), lab)
     qg = host(q, sh)
-    res = np.linalg.norm(s_or - orc.idp.apply(at_or, lab, qg))
+    res = residual(orc, at_or, lab, s_or, qg)
     assert res <= 1.5 * tol * np.linalg.norm(s_or)
     q_or = orc.idp.solve(at_or, lab, s_or)
+    dq = np.abs(qg - q_or).max()
     assert np.linalg.norm(qg - q_or) <= res / lambda_min(orc, at_or, lab) * 1.01 + 1e-15
     assert not qg[lab != 0].any()
-    ox, oy, oz = orc.idp.displacement(qg, lab, d["params"]["dx"])
-    assert np.array_equal(host(fx, ox.shape), ox)
-    assert np.array_equal(host(fy, oy.shape), oy)
-    assert np.array_equal(host(fz, oz.shape), oz)
+    dx = d["params"]["dx"]
+    for f, o in zip((fx, fy, fz), orc.idp.displacement(q_or, lab, dx)):
+        assert np.abs(host(f, o.shape) - o).max() <= 2 * dx * dq * (1 + 1e-12) + 4 * np.spacing(dx)
     assert ctx.error() == (0, -1)
     G.say(f"  {name} precond {precond}: {it} iterations, relres {rel:.2e}")
 
@@ -194,13 +227,12 @@ def test_projection_full_size_c3_grid(G, orc, precond):
     gic.gic_idp_setup(ctx, D["afx"], D["ast"], D["lab"], at, s)
     assert np.array_equal(host(at, sh), at_or) and np.array_equal(host(s, sh), s_or)
     qg = host(q, sh)
-    res = np.linalg.norm(s_or - orc.idp.apply(at_or, lab, qg))
+    res = residual(orc, at_or, lab, s_or, qg)
     assert res <= 1.5 * tol * np.linalg.norm(s_or)
     assert not qg[lab != 0].any()
-    ox, oy, oz = orc.idp.displacement(qg, lab, d["params"]["dx"])
-    assert np.array_equal(host(fx, ox.shape), ox)
-    assert np.array_equal(host(fy, oy.shape), oy)
-    assert np.array_equal(host(fz, oz.shape), oz)
+    for f, o in zip((fx, fy, fz), faces_of(qg, lab, d["params"]["dx"])):
+        assert np.array_equal(host(f, o.shape), o)
+    assert ctx.error() == (0, -1)
 
 
 def test_idp_argument_checks(G):
@@ -246,7 +278,7 @@ def test_multigrid_on_tiny_and_flat_grids(G, orc):
                                     G.dev(s.reshape(-1)), q, gic.idp_workspace(ctx), tol=1e-10, precond=1)
         assert rel <= 1e-10
         q_or = orc.idp.solve(at, lab, s)
-        res = np.linalg.norm(s - orc.idp.apply(at, lab, host(q, shape)))
+        res = residual(orc, at, lab, s, host(q, shape))
         assert res <= 1.5e-10 * np.linalg.norm(s)
         assert np.linalg.norm(host(q, shape) - q_or) <= res / lambda_min(orc, at, lab) * 1.01 + 1e-15
 

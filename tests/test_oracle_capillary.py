@@ -116,6 +116,12 @@ def test_cell_list_equals_brute_force(orc):
     assert bridged > 50
     assert np.allclose(F, B, rtol=1e-12, atol=1e-20)
     assert np.abs(F.sum(axis=1)).max() <= 1e-12 * np.abs(F).sum()
+    # the one-by-one form for sampled granules: the same sums, and the sum of
+    # the bridge magnitudes bounds the net force
+    idx = rng.choice(n, 40, replace=False)
+    Fs, fs = orc.capillary_forces_sample(cfg, x, r, sr, idx)
+    assert np.array_equal(Fs, F[:, idx])
+    assert np.all(np.linalg.norm(Fs, axis=0) <= fs * (1 + 1e-12)) and (fs > 0).sum() > 10
 
 
 def test_moisture_ratio_is_water_per_sand_volume(orc):
