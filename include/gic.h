@@ -463,7 +463,7 @@ gic_status gic_idp_apply(gic_ctx *ctx, const double *alpha_t, const uint8_t *lab
                          void *stream);
 
 /* Bytes of the caller-owned device workspace that gic_idp_solve and
- * gic_density_projection need with either preconditioner (about 70 G; -1
+ * gic_density_projection need with either preconditioner (about 80 G; -1
  * for a NULL context). */
 int64_t gic_idp_workspace_bytes(const gic_ctx *ctx);
 
