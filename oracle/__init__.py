@@ -126,6 +126,11 @@ def _declare(L):
         "orc_sand_step": (C.c_int32, [_pp, _pc, C.c_int64, C.c_double, _d, _d, _d, _d, _d, _d, _i64, _i64, _i64]),
         "orc_gamma": (C.c_double, [_pk, C.c_double]),
         "orc_moisture_ratio": (None, [C.c_int64, _d, _d, _d]),
+        "orc_wet_mass": (None, [_pp, C.c_double, C.c_int64, _d, _d, _d]),
+        "orc_contact_forces_wet": (None, [_pp, C.c_int64, _d, _d, _d, _d, _d, _d, _P(C.c_int32)]),
+        "orc_contact_forces_sample_wet": (None, [_pp, C.c_int64, _d, _d, _d, _d, C.c_int64, _i64, _d, _d]),
+        "orc_integrate_wet": (None, [_pp, _pc, C.c_int64, _d, _d, _d, _d, _d, _d]),
+        "orc_p2g_fixed_wet": (None, [_pp, C.c_double, C.c_int64, _d, _d, _d, _d, _i64, _i64]),
         "orc_bridge": (None, [_pk, C.c_double, _d, _d]),
         "orc_bridge_energy": (C.c_double, [_pk, C.c_double, C.c_double]),
         "orc_fst": (C.c_double, [_pk, C.c_double, C.c_double]),
@@ -572,6 +577,64 @@ def capillary_forces_sample(cfg, x, r, sr, idx):
                                       _ptr(r, C.c_double), _ptr(sr, C.c_double), m, _ptr(idx, C.c_int64),
                                       _ptr(F, C.c_double), _ptr(fa, C.c_double))
     return F, fa
+
+
+# ---- wet granules (Sec. 5.3, Eq. 19) ----
+
+def wet_mass(cfg, r, held):
+    """m = V (rho_s + held rho_f) per granule."""
+    r, held = _f64(r), _f64(held)
+    m = np.zeros(r.shape[0])
+    lib().orc_wet_mass(C.byref(params(cfg)), float(cfg.get("rho_f", 0.0)), r.shape[0], _ptr(r, C.c_double),
+                       _ptr(held, C.c_double), _ptr(m, C.c_double))
+    return m
+
+
+def contact_forces_wet(cfg, x, v, r, m):
+    """Contact forces with per-granule masses: (F (3,n), fabs (n), ncontacts (n))."""
+    x, v, r, m = _f64(x), _f64(v), _f64(r), _f64(m)
+    n = x.shape[1]
+    F = np.zeros((3, n))
+    fa = np.zeros(n)
+    nc = np.zeros(n, np.int32)
+    lib().orc_contact_forces_wet(C.byref(params(cfg)), n, _ptr(x, C.c_double), _ptr(v, C.c_double),
+                                 _ptr(r, C.c_double), _ptr(m, C.c_double), _ptr(F, C.c_double),
+                                 _ptr(fa, C.c_double), _ptr(nc, C.c_int32))
+    return F, fa, nc
+
+
+def contact_forces_sample_wet(cfg, x, v, r, m, idx):
+    x, v, r, m = _f64(x), _f64(v), _f64(r), _f64(m)
+    idx = np.ascontiguousarray(idx, np.int64)
+    k = idx.shape[0]
+    F = np.zeros((3, k))
+    fa = np.zeros(k)
+    lib().orc_contact_forces_sample_wet(C.byref(params(cfg)), x.shape[1], _ptr(x, C.c_double), _ptr(v, C.c_double),
+                                        _ptr(r, C.c_double), _ptr(m, C.c_double), k, _ptr(idx, C.c_int64),
+                                        _ptr(F, C.c_double), _ptr(fa, C.c_double))
+    return F, fa
+
+
+def integrate_wet(cfg, r, m, Fc, Fd, x, v):
+    """(x, v) advanced with per-granule masses (virtual mass per cfg)."""
+    r, m, Fc, Fd = _f64(r), _f64(m), _f64(Fc), _f64(Fd)
+    x, v = np.array(x, np.float64, copy=True), np.array(v, np.float64, copy=True)
+    lib().orc_integrate_wet(C.byref(params(cfg)), C.byref(coupling(cfg)), r.shape[0], _ptr(r, C.c_double),
+                            _ptr(m, C.c_double), _ptr(Fc, C.c_double), _ptr(Fd, C.c_double), _ptr(x, C.c_double),
+                            _ptr(v, C.c_double))
+    return x, v
+
+
+def p2g_fixed_wet(cfg, x, v, r, held):
+    """(alpha (G,), mom (3, G)) with the wet granules' momentum."""
+    x, v, r, held = _f64(x), _f64(v), _f64(r), _f64(held)
+    G = nodes(cfg)
+    a = np.zeros(G, np.int64)
+    mo = np.zeros(3 * G, np.int64)
+    lib().orc_p2g_fixed_wet(C.byref(params(cfg)), float(cfg.get("rho_f", 0.0)), x.shape[1], _ptr(x, C.c_double),
+                            _ptr(v, C.c_double), _ptr(r, C.c_double), _ptr(held, C.c_double), _ptr(a, C.c_int64),
+                            _ptr(mo, C.c_int64))
+    return a, mo.reshape(3, G)
 
 
 from . import idp  # noqa: E402,F401  (density projection, numpy/scipy)

@@ -354,10 +354,11 @@ static int orc_pair_force(const orc_params *p, double zeta, const double nh[3], 
  * every enabled wall.  Fabs[i] (optional) = sum of the norms of the pair and
  * wall forces, the scale of the sum's rounding error. */
 static void orc_contact_one(const orc_params *p, double zeta, int64_t n, const double *x, const double *v,
-                            const double *r, const orc_cells *cl, int64_t i, int64_t *cand, double Fi[3],
-                            double *fabs_i, int32_t *ncont, int32_t *nslide)
+                            const double *r, const double *mass, const orc_cells *cl, int64_t i, int64_t *cand,
+                            double Fi[3], double *fabs_i, int32_t *ncont, int32_t *nslide)
 {
-    double mi = orc_mass(p, r[i]);
+    /* mass: per-granule masses (wet granules, Eq. 19), NULL for rho_s V */
+    double mi = mass ? mass[i] : orc_mass(p, r[i]);
     double acc[3] = {0.0, 0.0, 0.0};
     double sabs = 0.0;
     int32_t nc_ = 0, ns_ = 0;
@@ -371,7 +372,7 @@ static void orc_contact_one(const orc_params *p, double zeta, int64_t n, const d
         double nh[3] = {dv[0] / d, dv[1] / d, dv[2] / d};
         double delta = (r[i] + r[j]) - d;
         double w[3] = {v[i] - v[j], v[n + i] - v[n + j], v[2 * n + i] - v[2 * n + j]};
-        double mj = orc_mass(p, r[j]);
+        double mj = mass ? mass[j] : orc_mass(p, r[j]);
         double meff = (mi * mj) / (mi + mj);
         double F[3];
         ns_ += orc_pair_force(p, zeta, nh, delta, w, meff, F);
@@ -418,7 +419,7 @@ void orc_contact_forces(const orc_params *p, int64_t n, const double *x, const d
         for (int64_t i = 0; i < n; ++i) {
             double Fi[3], fa;
             int32_t c1, c2;
-            orc_contact_one(p, zeta, n, x, v, r, &cl, i, cand, Fi, &fa, &c1, &c2);
+            orc_contact_one(p, zeta, n, x, v, r, NULL, &cl, i, cand, Fi, &fa, &c1, &c2);
             for (int a = 0; a < 3; ++a) F[a * n + i] = Fi[a];
             if (fabs_out) fabs_out[i] = fa;
             if (ncont) ncont[i] = c1;
@@ -444,7 +445,7 @@ void orc_contact_forces_sample(const orc_params *p, int64_t n, const double *x, 
 #pragma omp for schedule(static)
         for (int64_t s = 0; s < m; ++s) {
             double Fi[3], fa;
-            orc_contact_one(p, zeta, n, x, v, r, &cl, idx[s], cand, Fi, &fa, NULL, NULL);
+            orc_contact_one(p, zeta, n, x, v, r, NULL, &cl, idx[s], cand, Fi, &fa, NULL, NULL);
             for (int a = 0; a < 3; ++a) F[a * m + s] = Fi[a];
             if (fabs_out) fabs_out[s] = fa;
         }
@@ -554,8 +555,8 @@ void orc_stencil27(const orc_params *p, const double *xa, double *w27, int64_t *
  * Q = rint(S) with S = frac * 2^32 (alpha) or (frac * v_c) * 2^32 (momentum),
  * frac = V_i / dx^3.  The 26 outer nodes take rint(w * S); the centre node
  * takes Q minus their sum.  Adds into alpha (G) and mom (3G). */
-void orc_p2g_fixed(const orc_params *p, int64_t n, const double *x, const double *v, const double *r,
-                   int64_t *alpha, int64_t *mom)
+static void orc_p2g_fixed_held(const orc_params *p, double rho_0, int64_t n, const double *x, const double *v,
+                               const double *r, const double *held, int64_t *alpha, int64_t *mom)
 {
     double inv_dx = 1.0 / p->dx;
     double inv_vcell = 1.0 / ((p->dx * p->dx) * p->dx);
@@ -566,8 +567,11 @@ void orc_p2g_fixed(const orc_params *p, int64_t n, const double *x, const double
         orc_stencil s;
         orc_stencil_of(p, inv_dx, xa, &s);
         double frac = orc_volume(r[i]) * inv_vcell;
-        double S[4] = {frac * ORC_TWO32, (frac * v[i]) * ORC_TWO32, (frac * v[n + i]) * ORC_TWO32,
-                       (frac * v[2 * n + i]) * ORC_TWO32};
+        /* momentum in rho_s dx^3 units: a wet granule carries m_wet / (rho_s dx^3)
+         * = frac (rho_s + held rho_0) / rho_s per unit velocity (Eq. 19) */
+        double fm = held ? (frac * (p->rho_s + held[i] * rho_0)) / p->rho_s : frac;
+        double S[4] = {frac * ORC_TWO32, (fm * v[i]) * ORC_TWO32, (fm * v[n + i]) * ORC_TWO32,
+                       (fm * v[2 * n + i]) * ORC_TWO32};
         for (int ch = 0; ch < 4; ++ch) {
             int64_t Q = llrint(S[ch]);
             int64_t rest = Q;
@@ -584,6 +588,12 @@ void orc_p2g_fixed(const orc_params *p, int64_t n, const double *x, const double
             dst[orc_node_index(p, &s, 1, 1, 1)] += rest;
         }
     }
+}
+
+void orc_p2g_fixed(const orc_params *p, int64_t n, const double *x, const double *v, const double *r,
+                   int64_t *alpha, int64_t *mom)
+{
+    orc_p2g_fixed_held(p, 0.0, n, x, v, r, NULL, alpha, mom);
 }
 
 /* Unquantised P2G for the differentiable form: alpha in cell volumes
@@ -1482,3 +1492,90 @@ void orc_capillary_forces(const orc_params *p, const orc_capillary *c, int64_t n
     }
     orc_cells_free(&cl);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Wet granules: mass with the water a granule holds (Sec. 5.3, Eq. 19)      */
+/* ------------------------------------------------------------------------ */
+/* A granule holding water of held times its own volume has the mass
+ * m = V (rho_s + held rho_0), rho_0 the fluid density.  The wet forms below
+ * take per-granule masses where the dry ones use rho_s V: the contact's
+ * effective mass (damping), the integrator, the momentum deposit. */
+
+void orc_wet_mass(const orc_params *p, double rho_0, int64_t n, const double *r, const double *held, double *m)
+{
+    for (int64_t i = 0; i < n; ++i) m[i] = orc_volume(r[i]) * (p->rho_s + held[i] * rho_0);
+}
+
+void orc_contact_forces_wet(const orc_params *p, int64_t n, const double *x, const double *v, const double *r,
+                            const double *m, double *F, double *fabs_out, int32_t *ncont)
+{
+    orc_cells cl;
+    orc_cells_build(p, n, x, &cl);
+    double zeta = orc_zeta(p->restitution);
+    int64_t cap = 27 * orc_cells_maxocc(p, &cl) + 1;
+#pragma omp parallel
+    {
+        int64_t *cand = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap);
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            double Fi[3], fa;
+            int32_t c1, c2;
+            orc_contact_one(p, zeta, n, x, v, r, m, &cl, i, cand, Fi, &fa, &c1, &c2);
+            for (int a = 0; a < 3; ++a) F[a * n + i] = Fi[a];
+            if (fabs_out) fabs_out[i] = fa;
+            if (ncont) ncont[i] = c1;
+        }
+        free(cand);
+    }
+    orc_cells_free(&cl);
+}
+
+void orc_contact_forces_sample_wet(const orc_params *p, int64_t n, const double *x, const double *v,
+                                   const double *r, const double *mass, int64_t cnt, const int64_t *idx,
+                                   double *F, double *fabs_out)
+{
+    orc_cells cl;
+    orc_cells_build(p, n, x, &cl);
+    double zeta = orc_zeta(p->restitution);
+    int64_t cap = 27 * orc_cells_maxocc(p, &cl) + 1;
+#pragma omp parallel
+    {
+        int64_t *cand = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap);
+#pragma omp for schedule(static)
+        for (int64_t s = 0; s < cnt; ++s) {
+            double Fi[3], fa;
+            orc_contact_one(p, zeta, n, x, v, r, mass, &cl, idx[s], cand, Fi, &fa, NULL, NULL);
+            for (int a = 0; a < 3; ++a) F[a * cnt + s] = Fi[a];
+            if (fabs_out) fabs_out[s] = fa;
+        }
+        free(cand);
+    }
+    orc_cells_free(&cl);
+}
+
+/* Semi-implicit Euler with per-granule masses; under virtual mass the
+ * effective mass is m + (1/2) rho_f V and gravity acts on m (as
+ * orc_integrate_vm). */
+void orc_integrate_wet(const orc_params *p, const orc_coupling *cp, int64_t n, const double *r, const double *m,
+                       const double *Fc, const double *Fd, double *x, double *v)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double me = cp->vmass ? m[i] + (0.5 * cp->rho_f) * orc_volume(r[i]) : m[i];
+        for (int d = 0; d < 3; ++d) {
+            double a = cp->vmass ? ((Fc[d * n + i] + Fd[d * n + i]) + m[i] * p->g[d]) / me
+                                 : (Fc[d * n + i] + Fd[d * n + i]) / m[i] + p->g[d];
+            v[d * n + i] = v[d * n + i] + p->dt * a;
+            x[d * n + i] = x[d * n + i] + p->dt * v[d * n + i];
+        }
+    }
+}
+
+/* P2G of volume fraction (the sand's own volume) and of the wet granules'
+ * momentum: the momentum channels deposit frac (rho_s + held rho_0) / rho_s v. */
+void orc_p2g_fixed_wet(const orc_params *p, double rho_0, int64_t n, const double *x, const double *v,
+                       const double *r, const double *held, int64_t *alpha, int64_t *mom)
+{
+    orc_p2g_fixed_held(p, rho_0, n, x, v, r, held, alpha, mom);
+}
+
