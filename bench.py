@@ -76,8 +76,8 @@ def coupled_bytes(stage, n, nodes, real_bytes):
 
 
 # Contact with liquid bridges (FP32 form): the dry contact's x, v, r and F_c
-# plus the moisture ratio of each granule.
-CAPILLARY_BYTES_PER_GRANULE = 24 + 24 + 8 + 3 * 4 + 4
+# plus the moisture ratio and the held water (wet mass) of each granule.
+CAPILLARY_BYTES_PER_GRANULE = 24 + 24 + 8 + 3 * 4 + 4 + 8
 
 
 def time_steps(sim, steps, warmup):
@@ -308,13 +308,15 @@ def time_coupled(d, wl_name, substeps=4, sand_steps=8):
 
 
 def time_capillary(d, wl_name, reps=10):
-    """The workload as a wet bed (Sec. 5.4): the moisture ratio of every
+    """The workload as a wet bed (Sec. 5.3-5.4): the moisture ratio of every
     granule from its sampled fluid fraction and a seeded held-water ratio,
-    then contact plus liquid-bridge forces, FP32 form, on the sorted state of
-    a step; the dry contact call timed on the same state beside it."""
+    contact plus liquid-bridge forces with the wet masses of Eq. 19 in the
+    damping, and the wet integrate + P2G, FP32 form, on the sorted state of a
+    step; the dry contact and dry integrate + P2G timed on the same state
+    beside them (the state is restored before every integrate call)."""
     import torch
     from paper_2504_00745_amd import gic
-    cfg = dict(d["params"], sigma=0.072, vbridge=1e-4, sr_peak=0.3)
+    cfg = dict(d["params"], sigma=0.072, vbridge=1e-4, sr_peak=0.3, rho_f=1000.0)
     n = d["x"].shape[1]
     sim = gic.Simulator(cfg, d["x"], d["v"], d["r"], d["u"], "fp32", r_max=float(d["r"].max()))
     sim.step()
@@ -327,33 +329,54 @@ def time_capillary(d, wl_name, reps=10):
                             nxt["id"], sim.u, sim.alpha, s["cell_begin"], s["cell_end"], s["f_drag"], u_at=uat,
                             alpha_f=af)
     rng = np.random.Generator(np.random.PCG64(14))
-    held = torch.as_tensor(rng.uniform(0.0, 0.2, n), dtype=torch.float32, device="cuda")
+    held = torch.as_tensor(rng.uniform(0.0, 0.2, n), dtype=torch.float64, device="cuda")
     sr = torch.empty(n, dtype=torch.float32, device="cuda")
-    F = s["f_contact"]
+    F, Fd = s["f_contact"], s["f_drag"]
+    cb_, ce_ = s["cell_begin"], s["cell_end"]
     args = (nxt["x"], nxt["v"], nxt["r"])
+    x0, v0 = nxt["x"].clone(), nxt["v"].clone()
+    X, V = torch.empty_like(x0), torch.empty_like(v0)
     gic.gic_moisture_ratio(ctx, held, af, sr)
-    gic.gic_contact_capillary_forces(ctx, *args, sr, s["cell_begin"], s["cell_end"], F)  # warm-up
+    gic.gic_contact_capillary_forces(ctx, *args, sr, cb_, ce_, F, held=held)  # warm-up
     torch.cuda.synchronize()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4 * reps)]
+    K = 6
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * K * reps)]
     for i in range(reps):
-        ev[4 * i].record()
+        e = ev[2 * K * i:2 * K * (i + 1)]
+        e[0].record()
         gic.gic_moisture_ratio(ctx, held, af, sr)
-        ev[4 * i + 1].record()
-        gic.gic_contact_capillary_forces(ctx, *args, sr, s["cell_begin"], s["cell_end"], F)
-        ev[4 * i + 2].record()
-        gic.gic_contact_forces(ctx, *args, s["cell_begin"], s["cell_end"], F)
-        ev[4 * i + 3].record()
+        e[1].record()
+        e[2].record()
+        gic.gic_contact_capillary_forces(ctx, *args, sr, cb_, ce_, F, held=held)
+        e[3].record()
+        e[4].record()
+        gic.gic_contact_forces(ctx, *args, cb_, ce_, F)
+        e[5].record()
+        X.copy_(x0)
+        V.copy_(v0)
+        e[6].record()
+        gic.gic_integrate_p2g_wet(ctx, X, V, nxt["r"], held, F, Fd, cb_, ce_, sim.alpha, sim.mom)
+        e[7].record()
+        X.copy_(x0)
+        V.copy_(v0)
+        e[8].record()
+        gic.gic_integrate_p2g(ctx, X, V, nxt["r"], F, Fd, cb_, ce_, sim.alpha, sim.mom)
+        e[9].record()
+        e[10].record()
+        e[11].record()
     torch.cuda.synchronize()
-    t = [sum(ev[4 * i + k].elapsed_time(ev[4 * i + k + 1]) for i in range(reps)) / reps / 1e3 for k in range(3)]
+    t = [sum(ev[2 * K * i + 2 * k].elapsed_time(ev[2 * K * i + 2 * k + 1]) for i in range(reps)) / reps / 1e3
+         for k in range(5)]
     code, idx = ctx.error()
     cb = n * CAPILLARY_BYTES_PER_GRANULE
     ach = cb / t[1] / 1e9
     srv = sr.cpu().numpy()
     return {"workload": "same bed wet (sigma = 0.072 N/m, bridge volume 1e-4 of the granule volume, Gamma peak "
-                        "at sr = 0.3; held water U(0, 0.2) per granule), FP32",
+                        "at sr = 0.3; held water U(0, 0.2) per granule volume, rho_f = 1000), FP32",
             "moisture_ratio_ms": round(t[0] * 1e3, 4), "contact_capillary_ms": round(t[1] * 1e3, 4),
-            "contact_dry_ms": round(t[2] * 1e3, 4), "value": n / t[1], "unit": "granules/s (contact + bridges)",
-            "sr_median": float(np.median(srv)),
+            "contact_dry_ms": round(t[2] * 1e3, 4), "integrate_p2g_wet_ms": round(t[3] * 1e3, 4),
+            "integrate_p2g_dry_ms": round(t[4] * 1e3, 4), "value": n / t[1],
+            "unit": "granules/s (contact + bridges, wet masses)", "sr_median": float(np.median(srv)),
             "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": ach / HBM_PEAK_GBS, "algorithmic_bytes": cb, "traffic": None},
             "error": [code, idx]}

@@ -212,12 +212,13 @@ gic_status gic_contact_forces(gic_ctx *ctx, int64_t n, const double *x, const do
  * (per unit granule volume; the absorption of Sec. 5.3 that changes it is
  * not part of this library) plus the free water around it per unit sand
  * volume.  Evaluated in double, stored in the form's real type; +inf where
- * alpha_f = 1.  n real each (the form's type), any order as long as the three
- * agree; sr may alias neither input.
- *   held      water held by each granule (>= 0).
- *   alpha_f   fluid fraction sampled at each granule (gic_g2p).
- *   sr        out: moisture ratio. */
-gic_status gic_moisture_ratio(gic_ctx *ctx, int64_t n, const void *held, const void *alpha_f, void *sr,
+ * alpha_f = 1.  n each, any order as long as the three agree; sr may alias
+ * neither input.
+ *   held      n double: water held by each granule (>= 0), the same array
+ *             the wet masses of Eq. 19 take.
+ *   alpha_f   n real: fluid fraction sampled at each granule (gic_g2p).
+ *   sr        out, n real: moisture ratio. */
+gic_status gic_moisture_ratio(gic_ctx *ctx, int64_t n, const double *held, const void *alpha_f, void *sr,
                               void *stream);
 
 /* ---- f3: contact plus capillary liquid-bridge forces (Sec. 5.4) ----------
@@ -233,13 +234,17 @@ gic_status gic_moisture_ratio(gic_ctx *ctx, int64_t n, const void *held, const v
  * the contact forces.  Requires sigma > 0 (GIC_E_ARG otherwise).
  *   sr          n real (the form's type), sorted order: moisture ratio per
  *               granule (Sec. 5.3).
+ *   held        n double, sorted order (optional, NULL = dry masses): water
+ *               each granule holds per unit of its volume; the contact
+ *               damping then uses the wet masses V (rho_s + held rho_f) of
+ *               Eq. 19.
  *   f_contact   out, 3n real: contact plus bridge force per granule [N].
  *   n_contacts  out (optional), n: touching partners + walls (bridged
  *               pairs are not counted). */
 gic_status gic_contact_capillary_forces(gic_ctx *ctx, int64_t n, const double *x, const double *v,
-                                        const double *r, const void *sr, const int32_t *cell_begin,
-                                        const int32_t *cell_end, void *f_contact, int32_t *n_contacts,
-                                        void *stream);
+                                        const double *r, const void *sr, const double *held,
+                                        const int32_t *cell_begin, const int32_t *cell_end, void *f_contact,
+                                        int32_t *n_contacts, void *stream);
 
 /* Touching pairs (q, j) with q < j in sorted positions, for checks of the
  * neighbour search.  Writes up to cap pairs to pairs[2*k], pairs[2*k+1];
@@ -309,6 +314,18 @@ gic_status gic_gather_g2p_drag(gic_ctx *ctx, int64_t n, const int32_t *order, co
 gic_status gic_integrate_p2g(gic_ctx *ctx, int64_t n, double *x, double *v, const double *r, const void *f_contact,
                              const void *f_drag, const int32_t *cell_begin, const int32_t *cell_end,
                              int64_t *alpha_fx, int64_t *mom_fx, int32_t accumulate, void *stream);
+
+/* gic_integrate_p2g for wet granules (Sec. 5.3, Eq. 19): held (n double,
+ * sorted order, required for n > 0) is the water each granule holds per unit
+ * of its volume; the integrator uses the mass V (rho_s + held rho_f) (with
+ * virtual mass: that mass plus rho_f V / 2, gravity on the wet mass) and
+ * the momentum channels deposit frac (rho_s + held rho_f) / rho_s v; the
+ * fraction channel stays the sand's own volume.  The exchange deposit
+ * (gic_exchange_p2g) keeps the dry mass. */
+gic_status gic_integrate_p2g_wet(gic_ctx *ctx, int64_t n, double *x, double *v, const double *r, const double *held,
+                                 const void *f_contact, const void *f_drag, const int32_t *cell_begin,
+                                 const int32_t *cell_end, int64_t *alpha_fx, int64_t *mom_fx, int32_t accumulate,
+                                 void *stream);
 
 /* ---- one full sub-step -------------------------------------------------------
  * Sort, reorder, G2P (alpha_fx at the current positions, as left by the

@@ -86,7 +86,7 @@ __device__ inline Partner fetch_partner(int64_t n, const double *__restrict__ x,
 // of Eq. (1a)-(1c) runs in T.
 template <typename T>
 __device__ inline void pair_from(const DevParams &P, const double xi[3], const double vi[3], double ri, double mi,
-                                 const Partner &p, T acc[3])
+                                 const Partner &p, double mj_d, T acc[3])
 {
     const double d0 = xi[0] - p.x[0], d1 = xi[1] - p.x[1], d2c = xi[2] - p.x[2];
     const double rj = p.r;
@@ -121,7 +121,7 @@ __device__ inline void pair_from(const DevParams &P, const double xi[3], const d
         delta = R - d;
     }
     const T w[3] = {(T)(vi[0] - p.v[0]), (T)(vi[1] - p.v[1]), (T)(vi[2] - p.v[2])};
-    const T mj = (T)mass_of(P, rj);
+    const T mj = (T)mj_d;
     const T mit = (T)mi;
     const T meff = law_div(mit * mj, mit + mj);
     T Fp[3];
@@ -161,14 +161,17 @@ __device__ inline void add_walls(const DevParams &P, const double xi[3], const d
 // capillary force of its liquid bridge instead (Sec. 5.4).
 template <typename T, bool CAP>
 __device__ inline int exact_pair(const DevParams &P, const double xi[3], const double vi[3], double ri, double mi,
-                                 int64_t q, int32_t j, const Partner &p, T sri, const T *__restrict__ sr, T acc[3])
+                                 int64_t q, int32_t j, const Partner &p, T sri, const T *__restrict__ sr,
+                                 const double *__restrict__ held, T acc[3])
 {
     if (j == q) return 0;
     const double dx[3] = {xi[0] - p.x[0], xi[1] - p.x[1], xi[2] - p.x[2]};
     double d2;
     if (touching(dx[0], dx[1], dx[2], ri + p.r, d2)) {
         if (d2 == 0.0) return 0;
-        pair_from<T>(P, xi, vi, ri, mi, p, acc);
+        // a wet partner's mass includes the water it holds (Eq. 19)
+        const double mj = (CAP && held) ? wet_mass(P, p.r, held[j]) : mass_of(P, p.r);
+        pair_from<T>(P, xi, vi, ri, mi, p, mj, acc);
         return 1;
     }
     if (CAP) capillary_pair<T>(P, dx, d2, ri, p.r, sri, sr[j], acc);
@@ -186,14 +189,15 @@ template <typename T, bool CAP>
 __device__ inline void contact_global(const DevParams &P, int64_t n, const double *__restrict__ x,
                                       const double *__restrict__ v, const double *__restrict__ r,
                                       const int32_t *__restrict__ cb, const int32_t *__restrict__ ce, int64_t q,
-                                      int32_t *plist, int tid, const T *__restrict__ sr, T *__restrict__ F,
+                                      int32_t *plist, int tid, const T *__restrict__ sr,
+                                      const double *__restrict__ held, T *__restrict__ F,
                                       int32_t *__restrict__ ncont, int64_t *err)
 {
     const double xi[3] = {x[q], x[n + q], x[2 * n + q]};
     const double vi[3] = {v[q], v[n + q], v[2 * n + q]};
     const double ri = r[q];
     if (ri > P.r_max) raise_error(err, kErrRange, q);
-    const double mi = mass_of(P, ri);
+    const double mi = (CAP && held) ? wet_mass(P, ri, held[q]) : mass_of(P, ri);
     const double reach = CAP ? P.dr_max : 0.0;  // liquid bridges reach beyond contact
     const T sri = CAP ? sr[q] : (T)0;
     const double Rs = (ri + P.r_max + reach) * P.search_scale;
@@ -222,7 +226,7 @@ __device__ inline void contact_global(const DevParams &P, int64_t n, const doubl
                 if (cnt < kMaxPartners)
                     plist[cnt * 256 + tid] = j;
                 else  // rare: long partner list
-                    nc += exact_pair<T, CAP>(P, xi, vi, ri, mi, q, j, fetch_partner(n, x, v, r, j), sri, sr, acc);
+                    nc += exact_pair<T, CAP>(P, xi, vi, ri, mi, q, j, fetch_partner(n, x, v, r, j), sri, sr, held, acc);
                 ++cnt;
             }
         }
@@ -230,7 +234,7 @@ __device__ inline void contact_global(const DevParams &P, int64_t n, const doubl
     const int listed = cnt < kMaxPartners ? cnt : kMaxPartners;
     for (int k = 0; k < listed; ++k) {
         const int32_t j = plist[k * 256 + tid];
-        nc += exact_pair<T, CAP>(P, xi, vi, ri, mi, q, j, fetch_partner(n, x, v, r, j), sri, sr, acc);
+        nc += exact_pair<T, CAP>(P, xi, vi, ri, mi, q, j, fetch_partner(n, x, v, r, j), sri, sr, held, acc);
     }
     add_walls<T>(P, xi, vi, ri, mi, acc, nc);
     F[q] = acc[0];
@@ -284,12 +288,13 @@ __device__ inline bool near_slot(float4 p, float mx, float my, float mz, float t
 }
 
 template <typename T, bool CAP>
-__global__ void __launch_bounds__(256) k_contact_lds(DevParams P, int64_t n, const int32_t *__restrict__ bl,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_contact_lds(DevParams P, int64_t n, const int32_t *__restrict__ bl,
                                                      const int32_t *__restrict__ bcnt, int cap,
                                                      const double *__restrict__ x, const double *__restrict__ v,
                                                      const double *__restrict__ r, const int32_t *__restrict__ cb,
                                                      const int32_t *__restrict__ ce, const T *__restrict__ sr,
-                                                     T *__restrict__ F, int32_t *__restrict__ ncont, int64_t *err)
+                                                     const double *__restrict__ held, T *__restrict__ F,
+                                                     int32_t *__restrict__ ncont, int64_t *err)
 {
     extern __shared__ float4 smem4[];
     float4 *spos = smem4;                                        // [cap + kCand] (p, Q), see above
@@ -347,7 +352,7 @@ __global__ void __launch_bounds__(256) k_contact_lds(DevParams P, int64_t n, con
         __syncthreads();  // every thread has read s_wave
         int32_t *glist = reinterpret_cast<int32_t *>(smem4);  // the slot arrays are unused on this path
         for (int64_t q = gb + tid; q < ge; q += 256)
-            contact_global<T, CAP>(P, n, x, v, r, cb, ce, q, glist, tid, sr, F, ncont, err);
+            contact_global<T, CAP>(P, n, x, v, r, cb, ce, q, glist, tid, sr, held, F, ncont, err);
         return;
     }
     // ---- slot -> shell cell map (pads take their cell's number too)
@@ -477,7 +482,7 @@ __global__ void __launch_bounds__(256) k_contact_lds(DevParams P, int64_t n, con
                 vi[0] = v[q];
                 vi[1] = v[n + q];
                 vi[2] = v[2 * n + q];
-                mi = mass_of(P, ri);
+                mi = (CAP && held) ? wet_mass(P, ri, held[q]) : mass_of(P, ri);
                 const T sri = CAP ? sr[q] : (T)0;
                 const int listed = cnt < kLdsPartners ? cnt : kLdsPartners;
                 auto global_of = [&](int k) { const int c = scell[k]; return cgb[c] + (k - clo[c]); };
@@ -488,8 +493,8 @@ __global__ void __launch_bounds__(256) k_contact_lds(DevParams P, int64_t n, con
                     const int32_t j1 = two ? global_of(plist[(i + 1) * 256 + tid]) : j0;
                     const Partner p0 = fetch_partner(n, x, v, r, j0);
                     const Partner p1 = fetch_partner(n, x, v, r, j1);
-                    nc += exact_pair<T, CAP>(P, xi, vi, ri, mi, q, j0, p0, sri, sr, acc);
-                    if (two) nc += exact_pair<T, CAP>(P, xi, vi, ri, mi, q, j1, p1, sri, sr, acc);
+                    nc += exact_pair<T, CAP>(P, xi, vi, ri, mi, q, j0, p0, sri, sr, held, acc);
+                    if (two) nc += exact_pair<T, CAP>(P, xi, vi, ri, mi, q, j1, p1, sri, sr, held, acc);
                 }
                 if (cnt > kLdsPartners) {
                     // more candidates than listed: walk this lane's rows again for the rest
@@ -501,7 +506,7 @@ __global__ void __launch_bounds__(256) k_contact_lds(DevParams P, int64_t n, con
                             if (seen++ < kLdsPartners) continue;
                             const int32_t j = global_of(k);
                             nc += exact_pair<T, CAP>(P, xi, vi, ri, mi, q, j, fetch_partner(n, x, v, r, j), sri, sr,
-                                                acc);
+                                                     held, acc);
                         }
                     });
                 }
@@ -565,27 +570,30 @@ static size_t contact_lds_bytes(int cap)
 
 template <typename T>
 hipError_t launch_contact(const DevParams &P, int64_t n, const double *x, const double *v, const double *r,
-                          const int32_t *cb, const int32_t *ce, const BrickList &B, const T *sr, T *F,
-                          int32_t *ncont, int64_t *err, hipStream_t s)
+                          const int32_t *cb, const int32_t *ce, const BrickList &B, const T *sr, const double *held,
+                          T *F, int32_t *ncont, int64_t *err, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     const int64_t nbricks = (int64_t)P.nb[0] * P.nb[1] * P.nb[2];
     const int cap = 1948;  // shell slots held in LDS: 40,908 bytes, four workgroups per CU
     if (sr)
         k_contact_lds<T, true><<<brick_grid(nbricks), 256, contact_lds_bytes(cap), s>>>(P, n, B.list, B.count, cap, x,
-                                                                                       v, r, cb, ce, sr, F, ncont, err);
+                                                                                       v, r, cb, ce, sr, held, F,
+                                                                                       ncont, err);
     else
         k_contact_lds<T, false><<<brick_grid(nbricks), 256, contact_lds_bytes(cap), s>>>(
-            P, n, B.list, B.count, cap, x, v, r, cb, ce, sr, F, ncont, err);
+            P, n, B.list, B.count, cap, x, v, r, cb, ce, sr, nullptr, F, ncont, err);
     return hipGetLastError();
 }
 
 template hipError_t launch_contact<float>(const DevParams &, int64_t, const double *, const double *,
                                           const double *, const int32_t *, const int32_t *, const BrickList &,
-                                          const float *, float *, int32_t *, int64_t *, hipStream_t);
+                                          const float *, const double *, float *, int32_t *, int64_t *,
+                                          hipStream_t);
 template hipError_t launch_contact<double>(const DevParams &, int64_t, const double *, const double *,
                                            const double *, const int32_t *, const int32_t *, const BrickList &,
-                                           const double *, double *, int32_t *, int64_t *, hipStream_t);
+                                           const double *, const double *, double *, int32_t *, int64_t *,
+                                           hipStream_t);
 
 hipError_t launch_contact_pairs(const DevParams &P, int64_t n, const double *x, const double *r,
                                 const int32_t *cb, const int32_t *ce, int32_t *pairs, int64_t cap,

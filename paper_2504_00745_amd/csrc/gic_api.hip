@@ -395,14 +395,14 @@ gic_status gic_contact_forces(gic_ctx *c, int64_t n, const double *x, const doub
     if (brick_list(c, cell_begin, cell_end, s) != hipSuccess) return GIC_E_HIP;
     if (fp32(c))
         return hip_status(launch_contact<float>(c->dp, n, x, v, r, cell_begin, cell_end, c->bricks, nullptr,
-                                                (float *)f_contact, n_contacts, c->err, s));
-    return hip_status(launch_contact<double>(c->dp, n, x, v, r, cell_begin, cell_end, c->bricks, nullptr,
+                                                nullptr, (float *)f_contact, n_contacts, c->err, s));
+    return hip_status(launch_contact<double>(c->dp, n, x, v, r, cell_begin, cell_end, c->bricks, nullptr, nullptr,
                                              (double *)f_contact, n_contacts, c->err, s));
 }
 
 gic_status gic_contact_capillary_forces(gic_ctx *c, int64_t n, const double *x, const double *v, const double *r,
-                                        const void *sr, const int32_t *cell_begin, const int32_t *cell_end,
-                                        void *f_contact, int32_t *n_contacts, void *stream)
+                                        const void *sr, const double *held, const int32_t *cell_begin,
+                                        const int32_t *cell_end, void *f_contact, int32_t *n_contacts, void *stream)
 {
     if (!n_ok(c, n)) return GIC_E_ARG;
     if (!(c->p.sigma > 0.0)) return GIC_E_ARG;
@@ -412,21 +412,21 @@ gic_status gic_contact_capillary_forces(gic_ctx *c, int64_t n, const double *x, 
     if (brick_list(c, cell_begin, cell_end, s) != hipSuccess) return GIC_E_HIP;
     if (fp32(c))
         return hip_status(launch_contact<float>(c->dp, n, x, v, r, cell_begin, cell_end, c->bricks,
-                                                (const float *)sr, (float *)f_contact, n_contacts, c->err, s));
+                                                (const float *)sr, held, (float *)f_contact, n_contacts, c->err,
+                                                s));
     return hip_status(launch_contact<double>(c->dp, n, x, v, r, cell_begin, cell_end, c->bricks,
-                                             (const double *)sr, (double *)f_contact, n_contacts, c->err, s));
+                                             (const double *)sr, held, (double *)f_contact, n_contacts, c->err, s));
 }
 
-gic_status gic_moisture_ratio(gic_ctx *c, int64_t n, const void *held, const void *alpha_f, void *sr, void *stream)
+gic_status gic_moisture_ratio(gic_ctx *c, int64_t n, const double *held, const void *alpha_f, void *sr,
+                              void *stream)
 {
     if (!n_ok(c, n)) return GIC_E_ARG;
     if (n > 0 && (!held || !alpha_f || !sr)) return GIC_E_ARG;
     hipStream_t s = (hipStream_t)stream;
     if (fp32(c))
-        return hip_status(
-            launch_moisture_ratio<float>(n, (const float *)held, (const float *)alpha_f, (float *)sr, s));
-    return hip_status(
-        launch_moisture_ratio<double>(n, (const double *)held, (const double *)alpha_f, (double *)sr, s));
+        return hip_status(launch_moisture_ratio<float>(n, held, (const float *)alpha_f, (float *)sr, s));
+    return hip_status(launch_moisture_ratio<double>(n, held, (const double *)alpha_f, (double *)sr, s));
 }
 
 gic_status gic_contact_pairs(gic_ctx *c, int64_t n, const double *x, const double *r, const int32_t *cell_begin,
@@ -536,9 +536,10 @@ gic_status gic_gather_g2p_drag(gic_ctx *c, int64_t n, const int32_t *order, cons
                                                      (double *)f_drag, (double *)u_at, (double *)alpha_f, s));
 }
 
-gic_status gic_integrate_p2g(gic_ctx *c, int64_t n, double *x, double *v, const double *r, const void *f_contact,
-                             const void *f_drag, const int32_t *cell_begin, const int32_t *cell_end,
-                             int64_t *alpha_fx, int64_t *mom_fx, int32_t accumulate, void *stream)
+static gic_status integrate_p2g_impl(gic_ctx *c, int64_t n, double *x, double *v, const double *r,
+                                     const double *held, const void *f_contact, const void *f_drag,
+                                     const int32_t *cell_begin, const int32_t *cell_end, int64_t *alpha_fx,
+                                     int64_t *mom_fx, int32_t accumulate, void *stream)
 {
     if (!n_ok(c, n) || !alpha_fx || !mom_fx || !cell_begin || !cell_end) return GIC_E_ARG;
     if (n > 0 && (!x || !v || !r || !f_contact || !f_drag)) return GIC_E_ARG;
@@ -553,10 +554,28 @@ gic_status gic_integrate_p2g(gic_ctx *c, int64_t n, double *x, double *v, const 
     if (fp32(c))
         return hip_status(launch_integrate_p2g<float>(c->dp, n, c->K, x, v, r, (const float *)f_contact,
                                                       (const float *)f_drag, cell_begin, cell_end, c->bricks,
-                                                      alpha_fx, mom_fx, c->err, s));
+                                                      alpha_fx, mom_fx, c->err, s, held));
     return hip_status(launch_integrate_p2g<double>(c->dp, n, c->K, x, v, r, (const double *)f_contact,
                                                    (const double *)f_drag, cell_begin, cell_end, c->bricks, alpha_fx,
-                                                   mom_fx, c->err, s));
+                                                   mom_fx, c->err, s, held));
+}
+
+gic_status gic_integrate_p2g(gic_ctx *c, int64_t n, double *x, double *v, const double *r, const void *f_contact,
+                             const void *f_drag, const int32_t *cell_begin, const int32_t *cell_end,
+                             int64_t *alpha_fx, int64_t *mom_fx, int32_t accumulate, void *stream)
+{
+    return integrate_p2g_impl(c, n, x, v, r, nullptr, f_contact, f_drag, cell_begin, cell_end, alpha_fx, mom_fx,
+                              accumulate, stream);
+}
+
+gic_status gic_integrate_p2g_wet(gic_ctx *c, int64_t n, double *x, double *v, const double *r, const double *held,
+                                 const void *f_contact, const void *f_drag, const int32_t *cell_begin,
+                                 const int32_t *cell_end, int64_t *alpha_fx, int64_t *mom_fx, int32_t accumulate,
+                                 void *stream)
+{
+    if (n > 0 && !held) return GIC_E_ARG;
+    return integrate_p2g_impl(c, n, x, v, r, held, f_contact, f_drag, cell_begin, cell_end, alpha_fx, mom_fx,
+                              accumulate, stream);
 }
 
 gic_status gic_step(gic_ctx *c, int64_t n, const double *x_cur, const double *v_cur, const double *r_cur,

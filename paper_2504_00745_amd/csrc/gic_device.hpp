@@ -119,6 +119,14 @@ __device__ inline double volume_of(double r)
 
 __device__ inline double mass_of(const DevParams &P, double r) { return P.rho_s * volume_of(r); }
 
+// Mass of a wet granule that holds water of `held` times its own volume
+// (Sec. 5.3, Eq. 19): V (rho_s + held rho_f).
+__device__ inline double wet_mass(const DevParams &P, double r, double held)
+{
+#pragma clang fp contract(off)
+    return volume_of(r) * (P.rho_s + held * P.rho_f);
+}
+
 // clamp(floor(x / cell), 0, nc - 1); NaN -> 0.
 __device__ inline int32_t cell_coord(double x, double inv_cell, int32_t nc)
 {
@@ -289,13 +297,13 @@ __device__ inline void drag_one(const DevParams &P, double r, const double v[3],
 // Semi-implicit Euler (Sec. 4): v += dt ((F_c + F_d) / m + g), then x += dt v.
 // With virtual mass (Eq. 9) the effective mass is m + rho_f V / 2 and
 // gravity acts on m: v += dt ((F_c + F_d) + m g) / (m + rho_f V / 2).
+// m: the granule's mass (rho_s V, or the wet mass of Eq. 19).
 template <typename T>
-__device__ inline void integrate_one(const DevParams &P, double r, const T Fc[3], const T *Fd, double x[3],
-                                     double v[3])
+__device__ inline void integrate_one_m(const DevParams &P, double r, double m, const T Fc[3], const T *Fd,
+                                       double x[3], double v[3])
 {
 #pragma clang fp contract(off)  // one rounding per operation in every kernel that inlines it
     if (P.vmass) {
-        const double m = mass_of(P, r);
         const double me = m + P.half_rho_f * volume_of(r);
         for (int a = 0; a < 3; ++a) {
             double f = (double)Fc[a];
@@ -306,7 +314,7 @@ __device__ inline void integrate_one(const DevParams &P, double r, const T Fc[3]
         }
         return;
     }
-    const double inv_m = 1.0 / mass_of(P, r);
+    const double inv_m = 1.0 / m;
     for (int a = 0; a < 3; ++a) {
         double f = (double)Fc[a];
         if (Fd) f += (double)Fd[a];
@@ -314,6 +322,13 @@ __device__ inline void integrate_one(const DevParams &P, double r, const T Fc[3]
         v[a] = vn;
         x[a] = x[a] + P.dt * vn;
     }
+}
+
+template <typename T>
+__device__ inline void integrate_one(const DevParams &P, double r, const T Fc[3], const T *Fd, double x[3],
+                                     double v[3])
+{
+    integrate_one_m<T>(P, r, mass_of(P, r), Fc, Fd, x, v);
 }
 
 // Moisture curve Gamma of the capillary force (Sec. 5.4): zero when dry

@@ -54,8 +54,8 @@ hipError_t launch_reorder(int64_t n, const int32_t *order, const double *x, cons
 
 template <typename T>
 hipError_t launch_contact(const DevParams &P, int64_t n, const double *x, const double *v, const double *r,
-                          const int32_t *cb, const int32_t *ce, const BrickList &B, const T *sr, T *F,
-                          int32_t *ncont, int64_t *err, hipStream_t s);
+                          const int32_t *cb, const int32_t *ce, const BrickList &B, const T *sr, const double *held,
+                          T *F, int32_t *ncont, int64_t *err, hipStream_t s);
 hipError_t launch_contact_pairs(const DevParams &P, int64_t n, const double *x, const double *r,
                                 const int32_t *cb, const int32_t *ce, int32_t *pairs, int64_t cap,
                                 int64_t *count, hipStream_t s);
@@ -64,7 +64,7 @@ template <typename T>
 hipError_t launch_g2p(const DevParams &P, int64_t n, const double *x, const T *u, const int64_t *afx,
                       const double *are, T *uat, T *af, hipStream_t s);
 template <typename T>
-hipError_t launch_moisture_ratio(int64_t n, const T *held, const T *af, T *sr, hipStream_t s);
+hipError_t launch_moisture_ratio(int64_t n, const double *held, const T *af, T *sr, hipStream_t s);
 template <typename T>
 hipError_t launch_drag(const DevParams &P, int64_t n, const double *r, const double *v, const T *uat, const T *af,
                        T *Fd, hipStream_t s);
@@ -80,7 +80,8 @@ hipError_t launch_p2g_fixed(const DevParams &P, int64_t n, int64_t K, const doub
 template <typename T>
 hipError_t launch_integrate_p2g(const DevParams &P, int64_t n, int64_t K, double *x, double *v, const double *r,
                                 const T *Fc, const T *Fd, const int32_t *cb, const int32_t *ce, const BrickList &B,
-                                int64_t *alpha, int64_t *mom, int64_t *err, hipStream_t s);
+                                int64_t *alpha, int64_t *mom, int64_t *err, hipStream_t s,
+                                const double *held = nullptr);  // held: water per granule volume (wet mass), or NULL
 // Exchange deposit of one sub-step (Sec. 5.2) into the 3 x G int64 grid fs.
 template <typename T>
 hipError_t launch_exchange_p2g(const DevParams &P, int64_t n, int64_t K, const double *x, const double *r,

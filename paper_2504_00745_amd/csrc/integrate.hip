@@ -48,27 +48,27 @@ __global__ void __launch_bounds__(256) k_integrate(DevParams P, int64_t n, const
 // the water it holds plus the free water around it per unit sand volume,
 // sr = held + alpha_f / (1 - alpha_f), in double (+inf at alpha_f = 1).
 template <typename T>
-__global__ void __launch_bounds__(256) k_moisture_ratio(int64_t n, const T *__restrict__ held,
+__global__ void __launch_bounds__(256) k_moisture_ratio(int64_t n, const double *__restrict__ held,
                                                         const T *__restrict__ af, T *__restrict__ sr)
 {
 #pragma clang fp contract(off)
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n) return;
     const double a = (double)af[q];
-    sr[q] = (T)((double)held[q] + a / (1.0 - a));
+    sr[q] = (T)(held[q] + a / (1.0 - a));
 }
 
 }  // namespace
 
 template <typename T>
-hipError_t launch_moisture_ratio(int64_t n, const T *held, const T *af, T *sr, hipStream_t s)
+hipError_t launch_moisture_ratio(int64_t n, const double *held, const T *af, T *sr, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     k_moisture_ratio<T><<<grid_for(n, 256), 256, 0, s>>>(n, held, af, sr);
     return hipGetLastError();
 }
 
-template hipError_t launch_moisture_ratio<float>(int64_t, const float *, const float *, float *, hipStream_t);
+template hipError_t launch_moisture_ratio<float>(int64_t, const double *, const float *, float *, hipStream_t);
 template hipError_t launch_moisture_ratio<double>(int64_t, const double *, const double *, double *, hipStream_t);
 
 template <typename T>

@@ -94,7 +94,7 @@ __device__ inline void tile_add(unsigned long long *tile, unsigned long long *gl
 // with a_s = ((Fc + Fd) + m g) / (m + rho_f V / 2)), exsc = -weight / f_unit,
 // deposited at the granule's current position; alpha receives channel 0 and
 // mom channels 1 and 2.
-template <bool MOM, typename T, bool INTEG, bool EXCH = false>
+template <bool MOM, typename T, bool INTEG, bool EXCH = false, bool WET = false>
 __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_eu(4))) k_p2g_fixed(DevParams P, int64_t n, const int32_t *__restrict__ bl,
                                                            const int32_t *__restrict__ bcnt, int batch,
                                                            double *x, double *v, const double *__restrict__ r,
@@ -103,10 +103,11 @@ __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_e
                                                            const int32_t *__restrict__ ce,
                                                            unsigned long long *__restrict__ alpha,
                                                            unsigned long long *__restrict__ mom, int64_t *err,
-                                                           double exsc)
+                                                           double exsc, const double *__restrict__ held)
 {
 #pragma clang fp contract(off)
     static_assert(!(EXCH && (MOM || INTEG)), "the exchange deposit is a kind of its own");
+    static_assert(!(WET && EXCH), "the exchange deposit uses the dry mass");
     constexpr int NCH = EXCH ? 3 : (MOM ? 4 : 1);
     extern __shared__ unsigned long long tile[];
     __shared__ int32_t s_range[2];
@@ -144,7 +145,10 @@ __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_e
             if (INTEG) {
                 const T fc[3] = {Fc[q], Fc[n + q], Fc[2 * n + q]};
                 const T fd[3] = {Fd[q], Fd[n + q], Fd[2 * n + q]};
-                integrate_one<T>(P, r[q], fc, fd, xa, va);
+                if (WET)
+                    integrate_one_m<T>(P, r[q], wet_mass(P, r[q], held[q]), fc, fd, xa, va);
+                else
+                    integrate_one<T>(P, r[q], fc, fd, xa, va);
                 for (int a = 0; a < 3; ++a) {
                     x[a * n + q] = xa[a];
                     v[a * n + q] = va[a];
@@ -176,9 +180,12 @@ __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_e
             } else {
                 const double frac = volume_of(r[q]) * P.inv_vcell;
                 S[0] = frac * GIC_TWO32;
+                // momentum in rho_s dx^3 units: a wet granule (Eq. 19) carries
+                // frac (rho_s + held rho_f) / rho_s per unit velocity
+                const double fm = WET ? (frac * (P.rho_s + held[q] * P.rho_f)) / P.rho_s : frac;
                 if (MOM)
 #pragma unroll
-                    for (int c = 1; c < NCH; ++c) S[c] = (frac * va[c - 1]) * GIC_TWO32;
+                    for (int c = 1; c < NCH; ++c) S[c] = (fm * va[c - 1]) * GIC_TWO32;
             }
             bool ok = true;
 #pragma unroll
@@ -418,10 +425,11 @@ static size_t p2g_lds(int nch, int E3, int batch)
     return sizeof(unsigned long long) * (size_t)nch * E3 + (size_t)(batch + 1) * (3 * 8 + nch * 8 + 4 + 3 * 2);
 }
 
-template <typename T, bool INTEG>
+template <typename T, bool INTEG, bool WET = false>
 static hipError_t p2g_fixed_impl(const DevParams &P, int64_t n, int64_t K, double *x, double *v, const double *r,
                                  const T *Fc, const T *Fd, const int32_t *cb, const int32_t *ce, const BrickList &B,
-                                 int64_t *alpha, int64_t *mom, int64_t *err, hipStream_t s)
+                                 int64_t *alpha, int64_t *mom, int64_t *err, hipStream_t s,
+                                 const double *held = nullptr)
 {
     if (n == 0) return hipSuccess;
     const int64_t bricks = K / kBrickCells;
@@ -433,12 +441,11 @@ static hipError_t p2g_fixed_impl(const DevParams &P, int64_t n, int64_t K, doubl
     unsigned long long *A = reinterpret_cast<unsigned long long *>(alpha);
     unsigned long long *M = reinterpret_cast<unsigned long long *>(mom);
     if (mom)
-        k_p2g_fixed<true, T, INTEG><<<brick_grid(bricks), kP2GThreads, lds, s>>>(P, n, B.list, B.count, batch, x, v, r,
-                                                                                 Fc, Fd, cb, ce, A, M, err, 0.0);
+        k_p2g_fixed<true, T, INTEG, false, WET><<<brick_grid(bricks), kP2GThreads, lds, s>>>(
+            P, n, B.list, B.count, batch, x, v, r, Fc, Fd, cb, ce, A, M, err, 0.0, held);
     else
-        k_p2g_fixed<false, T, INTEG><<<brick_grid(bricks), kP2GThreads, lds, s>>>(P, n, B.list, B.count, batch, x, v,
-                                                                                  r, Fc, Fd, cb, ce, A, nullptr, err,
-                                                                                  0.0);
+        k_p2g_fixed<false, T, INTEG, false, WET><<<brick_grid(bricks), kP2GThreads, lds, s>>>(
+            P, n, B.list, B.count, batch, x, v, r, Fc, Fd, cb, ce, A, nullptr, err, 0.0, held);
     return hipGetLastError();
 }
 
@@ -456,7 +463,8 @@ hipError_t launch_exchange_p2g(const DevParams &P, int64_t n, int64_t K, const d
     unsigned long long *F = reinterpret_cast<unsigned long long *>(fs);
     // x is only read on this path
     k_p2g_fixed<false, T, false, true><<<brick_grid(bricks), kP2GThreads, lds, s>>>(
-        P, n, B.list, B.count, batch, const_cast<double *>(x), nullptr, r, Fc, Ffl, cb, ce, F, F + P.G, err, exsc);
+        P, n, B.list, B.count, batch, const_cast<double *>(x), nullptr, r, Fc, Ffl, cb, ce, F, F + P.G, err, exsc,
+        nullptr);
     return hipGetLastError();
 }
 
@@ -480,19 +488,21 @@ hipError_t launch_p2g_fixed(const DevParams &P, int64_t n, int64_t K, const doub
 template <typename T>
 hipError_t launch_integrate_p2g(const DevParams &P, int64_t n, int64_t K, double *x, double *v, const double *r,
                                 const T *Fc, const T *Fd, const int32_t *cb, const int32_t *ce, const BrickList &B,
-                                int64_t *alpha, int64_t *mom, int64_t *err, hipStream_t s)
+                                int64_t *alpha, int64_t *mom, int64_t *err, hipStream_t s, const double *held)
 {
+    if (held)
+        return p2g_fixed_impl<T, true, true>(P, n, K, x, v, r, Fc, Fd, cb, ce, B, alpha, mom, err, s, held);
     return p2g_fixed_impl<T, true>(P, n, K, x, v, r, Fc, Fd, cb, ce, B, alpha, mom, err, s);
 }
 
 template hipError_t launch_integrate_p2g<float>(const DevParams &, int64_t, int64_t, double *, double *,
                                                 const double *, const float *, const float *, const int32_t *,
                                                 const int32_t *, const BrickList &, int64_t *, int64_t *, int64_t *,
-                                                hipStream_t);
+                                                hipStream_t, const double *);
 template hipError_t launch_integrate_p2g<double>(const DevParams &, int64_t, int64_t, double *, double *,
                                                  const double *, const double *, const double *, const int32_t *,
                                                  const int32_t *, const BrickList &, int64_t *, int64_t *, int64_t *,
-                                                 hipStream_t);
+                                                 hipStream_t, const double *);
 
 hipError_t launch_p2g_real(const DevParams &P, int64_t n, int64_t K, const double *x, const double *v,
                            const double *r, const int32_t *cb, const int32_t *ce, const BrickList &B,

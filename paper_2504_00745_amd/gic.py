@@ -62,7 +62,8 @@ def lib():
             "gic_sort_cells": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V]),
             "gic_reorder": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V, _V, _V, _V]),
             "gic_contact_forces": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V, _V]),
-            "gic_contact_capillary_forces": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V, _V, _V]),
+            "gic_contact_capillary_forces": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V, _V, _V, _V]),
+            "gic_integrate_p2g_wet": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V, _V, _V, _V, _I32, _V]),
             "gic_moisture_ratio": (C.c_int, [_V, _I64, _V, _V, _V, _V]),
             "gic_idp_workspace_bytes": (_I64, [_V]),
             "gic_idp_setup": (C.c_int, [_V] * 7),
@@ -218,11 +219,11 @@ def gic_contact_forces(ctx, x, v, r, cell_begin, cell_end, f_contact, n_contacts
                                     _ptr(n_contacts, torch.int32, n), _stream()), "gic_contact_forces")
 
 
-def gic_contact_capillary_forces(ctx, x, v, r, sr, cell_begin, cell_end, f_contact, n_contacts=None):
+def gic_contact_capillary_forces(ctx, x, v, r, sr, cell_begin, cell_end, f_contact, n_contacts=None, held=None):
     n = x.shape[-1]
     f64 = torch.float64
     _check(lib().gic_contact_capillary_forces(ctx.handle, n, _ptr(x, f64, 3 * n), _ptr(v, f64, 3 * n),
-                                              _ptr(r, f64, n), _ptr(sr, ctx.real, n, "sr"),
+                                              _ptr(r, f64, n), _ptr(sr, ctx.real, n, "sr"), _ptr(held, f64, n, "held"),
                                               _ptr(cell_begin, torch.int32, ctx.K), _ptr(cell_end, torch.int32, ctx.K),
                                               _ptr(f_contact, ctx.real, 3 * n, "f_contact"),
                                               _ptr(n_contacts, torch.int32, n), _stream()),
@@ -231,7 +232,7 @@ def gic_contact_capillary_forces(ctx, x, v, r, sr, cell_begin, cell_end, f_conta
 
 def gic_moisture_ratio(ctx, held, alpha_f, sr):
     n = held.shape[-1]
-    _check(lib().gic_moisture_ratio(ctx.handle, n, _ptr(held, ctx.real, n, "held"),
+    _check(lib().gic_moisture_ratio(ctx.handle, n, _ptr(held, torch.float64, n, "held"),
                                     _ptr(alpha_f, ctx.real, n, "alpha_f"), _ptr(sr, ctx.real, n, "sr"), _stream()),
            "gic_moisture_ratio")
 
@@ -368,6 +369,18 @@ def gic_integrate_p2g(ctx, x, v, r, f_contact, f_drag, cell_begin, cell_end, alp
                                    _ptr(cell_begin, torch.int32, ctx.K), _ptr(cell_end, torch.int32, ctx.K),
                                    _ptr(alpha_fx, torch.int64, ctx.G), _ptr(mom_fx, torch.int64, 3 * ctx.G),
                                    int(bool(accumulate)), _stream()), "gic_integrate_p2g")
+
+
+def gic_integrate_p2g_wet(ctx, x, v, r, held, f_contact, f_drag, cell_begin, cell_end, alpha_fx, mom_fx,
+                          accumulate=False):
+    n = x.shape[-1]
+    f64 = torch.float64
+    _check(lib().gic_integrate_p2g_wet(ctx.handle, n, _ptr(x, f64, 3 * n), _ptr(v, f64, 3 * n), _ptr(r, f64, n),
+                                       _ptr(held, f64, n, "held"), _ptr(f_contact, ctx.real, 3 * n),
+                                       _ptr(f_drag, ctx.real, 3 * n), _ptr(cell_begin, torch.int32, ctx.K),
+                                       _ptr(cell_end, torch.int32, ctx.K), _ptr(alpha_fx, torch.int64, ctx.G),
+                                       _ptr(mom_fx, torch.int64, 3 * ctx.G), int(bool(accumulate)), _stream()),
+           "gic_integrate_p2g_wet")
 
 
 def gic_step(ctx, cur, nxt, u, alpha_fx, mom_fx, scratch):

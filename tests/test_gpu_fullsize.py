@@ -89,7 +89,8 @@ def test_full_size_step(T, orc, name):
 
 
 def test_full_size_wet_bed(T, orc):
-    """The c3 bed wet (seeded moisture ratios U(0, 1)): the input state
+    """The c3 bed wet (seeded moisture ratios U(0, 1), held water U(0, 0.3)
+    per granule volume, so wet masses in the damping): the input state
     sorted and reordered as a step begins, then the contact plus
     liquid-bridge call on it, launched as the benchmark's wet-bed leg does;
     sampled forces against the oracle's contact plus capillary forces of the
@@ -104,6 +105,8 @@ def test_full_size_wet_bed(T, orc):
     n = x.shape[1]
     rng = np.random.Generator(np.random.PCG64(17))
     sr = rng.uniform(0.0, 1.0, n).astype(np.float32).astype(np.float64)  # the FP32 form's values
+    held = rng.uniform(0.0, 0.3, n)  # water held per granule volume: wet masses (Eq. 19)
+    cfg["rho_f"] = 1000.0
     sim = gic.Simulator(cfg, x, v, r, u, "fp32", r_max=float(r.max()))
     ctx, s = sim.ctx, sim.scratch
     cur, nxt = sim.cur, sim.nxt
@@ -113,9 +116,11 @@ def test_full_size_wet_bed(T, orc):
                     nxt["id"])
     ids = nxt["id"].long()
     SR = torch.as_tensor(sr, dtype=torch.float32, device="cuda")[ids].contiguous()
+    H = torch.as_tensor(held, dtype=torch.float64, device="cuda")[ids].contiguous()
     F = torch.empty(3 * n, dtype=torch.float32, device="cuda")
     T.say("[full size] c3 wet bed: GPU contact + bridges")
-    gic.gic_contact_capillary_forces(ctx, nxt["x"], nxt["v"], nxt["r"], SR, s["cell_begin"], s["cell_end"], F)
+    gic.gic_contact_capillary_forces(ctx, nxt["x"], nxt["v"], nxt["r"], SR, s["cell_begin"], s["cell_end"], F,
+                                     held=H)
     torch.cuda.synchronize()
     assert ctx.error() == (0, -1)
     idv = ids.cpu().numpy()
@@ -123,7 +128,7 @@ def test_full_size_wet_bed(T, orc):
     pos[idv] = np.arange(n)
     idx = rng.choice(n, 3000, replace=False)
     T.say("[full size] c3 wet bed: oracle samples")
-    Fs, fa = orc.contact_forces_sample(cfg, x, v, r, idx)
+    Fs, fa = orc.contact_forces_sample_wet(cfg, x, v, r, orc.wet_mass(cfg, r, held), idx)
     Fb, fb = orc.capillary_forces_sample(cfg, x, r, sr, idx)
     Fg = F.view(3, n).double().cpu().numpy()[:, pos[idx]]
     err = np.linalg.norm(Fg - (Fs + Fb), axis=0)
