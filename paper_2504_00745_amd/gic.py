@@ -77,12 +77,12 @@ def lib():
             "gic_integrate": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V]),
             "gic_p2g": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V, _I32, _V]),
             "gic_p2g_real": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V, _I32, _V]),
-            "gic_gather_g2p_drag": (C.c_int, [_V, _I64] + [_V] * 16),
+            "gic_gather_g2p_drag": (C.c_int, [_V, _I64] + [_V] * 17),
             "gic_integrate_p2g": (C.c_int, [_V, _I64] + [_V] * 9 + [_I32, _V]),
-            "gic_step": (C.c_int, [_V, _I64] + [_V] * 19),
+            "gic_step": (C.c_int, [_V, _I64] + [_V] * 20),
             "gic_gather_g2p_fluid": (C.c_int, [_V, _I64] + [_V] * 17),
             "gic_exchange_p2g": (C.c_int, [_V, _I64] + [_V] * 6 + [C.c_double, _V, _V]),
-            "gic_sand_step": (C.c_int, [_V, _I64, C.c_double] + [_V] * 22),
+            "gic_sand_step": (C.c_int, [_V, _I64, C.c_double] + [_V] * 23),
             "gic_contact_forces_vjp": (C.c_int, [_V, _I64] + [_V] * 10),
             "gic_drag_vjp": (C.c_int, [_V, _I64] + [_V] * 10),
             "gic_integrate_vjp": (C.c_int, [_V, _I64] + [_V] * 5),

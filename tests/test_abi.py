@@ -33,6 +33,28 @@ def test_library_exports_every_declared_function():
     assert set(names) <= exported
 
 
+def declared_arity():
+    """Number of parameters of each function the header declares."""
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    out = {}
+    for m in re.finditer(r"^\s*(?:gic_status|int64_t|const char \*)\s+(gic_\w+)\s*\(([^;]*?)\)\s*;", src, flags=re.M | re.S):
+        args = m.group(2).strip()
+        out[m.group(1)] = 0 if args in ("", "void") else args.count(",") + 1
+    return out
+
+
+def test_binding_signatures_match_header():
+    """The binding declares every function with as many arguments as the
+    header does (a wrong count would pass garbage through ctypes)."""
+    L = gic.lib()
+    ar = declared_arity()
+    assert len(ar) == len(declared_functions())
+    for name, k in ar.items():
+        f = getattr(L, name)
+        assert f.argtypes is not None and len(f.argtypes) == k, (name, k, f.argtypes)
+
+
 def test_params_struct_layout_matches_header(tmp_path):
     prog = tmp_path / "layout.c"
     fields = [f[0] for f in gic.gic_params._fields_]

@@ -196,7 +196,7 @@ def test_capillary_argument_checks(G):
     assert ctx2.params.sigma == pytest.approx(0.072)
     assert gic.lib().gic_contact_capillary_forces(ctx2.handle, n, gic._ptr(X, torch.float64, 3 * n),
                                                   gic._ptr(V, torch.float64, 3 * n), gic._ptr(R, torch.float64, n),
-                                                  None, gic._ptr(cb, torch.int32, ctx2.K),
+                                                  None, None, gic._ptr(cb, torch.int32, ctx2.K),
                                                   gic._ptr(cb, torch.int32, ctx2.K),
                                                   gic._ptr(F, torch.float32, 3 * n), None, None) == 1
     gic.gic_contact_capillary_forces(ctx2, X[:0].view(3, 0), V[:0], R[:0], SR[:0], cb, cb, F[:0])
