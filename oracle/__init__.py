@@ -618,7 +618,7 @@ def contact_forces_sample_wet(cfg, x, v, r, m, idx):
 def integrate_wet(cfg, r, m, Fc, Fd, x, v):
     """(x, v) advanced with per-granule masses (virtual mass per cfg)."""
     r, m, Fc, Fd = _f64(r), _f64(m), _f64(Fc), _f64(Fd)
-    x, v = np.array(x, np.float64, copy=True), np.array(v, np.float64, copy=True)
+    x, v = np.array(x, np.float64, order="C", copy=True), np.array(v, np.float64, order="C", copy=True)
     lib().orc_integrate_wet(C.byref(params(cfg)), C.byref(coupling(cfg)), r.shape[0], _ptr(r, C.c_double),
                             _ptr(m, C.c_double), _ptr(Fc, C.c_double), _ptr(Fd, C.c_double), _ptr(x, C.c_double),
                             _ptr(v, C.c_double))
