@@ -319,7 +319,7 @@ gic_status gic_integrate_p2g(gic_ctx *ctx, int64_t n, double *x, double *v, cons
  * sorted order, required for n > 0) is the water each granule holds per unit
  * of its volume; the integrator uses the mass V (rho_s + held rho_f) (with
  * virtual mass: that mass plus rho_f V / 2, gravity on the wet mass) and
- * the momentum channels deposit frac (rho_s + held rho_f) / rho_s v; the
+ * the momentum channels deposit (frac + frac held rho_f / rho_s) v; the
  * fraction channel stays the sand's own volume.  The exchange deposit
  * (gic_exchange_p2g) keeps the dry mass. */
 gic_status gic_integrate_p2g_wet(gic_ctx *ctx, int64_t n, double *x, double *v, const double *r, const double *held,

@@ -568,8 +568,9 @@ static void orc_p2g_fixed_held(const orc_params *p, double rho_0, int64_t n, con
         orc_stencil_of(p, inv_dx, xa, &s);
         double frac = orc_volume(r[i]) * inv_vcell;
         /* momentum in rho_s dx^3 units: a wet granule carries m_wet / (rho_s dx^3)
-         * = frac (rho_s + held rho_0) / rho_s per unit velocity (Eq. 19) */
-        double fm = held ? (frac * (p->rho_s + held[i] * rho_0)) / p->rho_s : frac;
+         * = frac (rho_s + held rho_0) / rho_s = frac + frac held rho_0 / rho_s
+         * per unit velocity (Eq. 19), written so that held = 0 gives frac exactly */
+        double fm = held ? frac + (frac * (held[i] * rho_0)) / p->rho_s : frac;
         double S[4] = {frac * ORC_TWO32, (fm * v[i]) * ORC_TWO32, (fm * v[n + i]) * ORC_TWO32,
                        (fm * v[2 * n + i]) * ORC_TWO32};
         for (int ch = 0; ch < 4; ++ch) {

@@ -181,8 +181,9 @@ __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_e
                 const double frac = volume_of(r[q]) * P.inv_vcell;
                 S[0] = frac * GIC_TWO32;
                 // momentum in rho_s dx^3 units: a wet granule (Eq. 19) carries
-                // frac (rho_s + held rho_f) / rho_s per unit velocity
-                const double fm = WET ? (frac * (P.rho_s + held[q] * P.rho_f)) / P.rho_s : frac;
+                // frac (rho_s + held rho_f) / rho_s = frac + frac held rho_f / rho_s
+                // per unit velocity (held = 0 gives frac exactly)
+                const double fm = WET ? frac + (frac * (held[q] * P.rho_f)) / P.rho_s : frac;
                 if (MOM)
 #pragma unroll
                     for (int c = 1; c < NCH; ++c) S[c] = (fm * va[c - 1]) * GIC_TWO32;
