@@ -84,7 +84,9 @@ __device__ inline Partner fetch_partner(int64_t n, const double *__restrict__ x,
 // Force that partner p exerts on granule i: the overlap, its normal and the
 // relative velocity come from double positions and velocities; the pair law
 // of Eq. (1a)-(1c) runs in T.
-template <typename T>
+// WET: the partner's mass mj_d is given (the wet mass of Eq. 19); otherwise
+// it is rho_s V of the partner's radius.
+template <typename T, bool WET = false>
 __device__ inline void pair_from(const DevParams &P, const double xi[3], const double vi[3], double ri, double mi,
                                  const Partner &p, double mj_d, T acc[3])
 {
@@ -121,7 +123,7 @@ __device__ inline void pair_from(const DevParams &P, const double xi[3], const d
         delta = R - d;
     }
     const T w[3] = {(T)(vi[0] - p.v[0]), (T)(vi[1] - p.v[1]), (T)(vi[2] - p.v[2])};
-    const T mj = (T)mj_d;
+    const T mj = WET ? (T)mj_d : (T)mass_of(P, rj);
     const T mit = (T)mi;
     const T meff = law_div(mit * mj, mit + mj);
     T Fp[3];
@@ -169,9 +171,13 @@ __device__ inline int exact_pair(const DevParams &P, const double xi[3], const d
     double d2;
     if (touching(dx[0], dx[1], dx[2], ri + p.r, d2)) {
         if (d2 == 0.0) return 0;
-        // a wet partner's mass includes the water it holds (Eq. 19)
-        const double mj = (CAP && held) ? wet_mass(P, p.r, held[j]) : mass_of(P, p.r);
-        pair_from<T>(P, xi, vi, ri, mi, p, mj, acc);
+        if constexpr (CAP) {
+            // a wet partner's mass includes the water it holds (Eq. 19)
+            const double mj = held ? wet_mass(P, p.r, held[j]) : mass_of(P, p.r);
+            pair_from<T, true>(P, xi, vi, ri, mi, p, mj, acc);
+        } else {
+            pair_from<T>(P, xi, vi, ri, mi, p, 0.0, acc);
+        }
         return 1;
     }
     if (CAP) capillary_pair<T>(P, dx, d2, ri, p.r, sri, sr[j], acc);
@@ -288,7 +294,7 @@ __device__ inline bool near_slot(float4 p, float mx, float my, float mz, float t
 }
 
 template <typename T, bool CAP>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_contact_lds(DevParams P, int64_t n, const int32_t *__restrict__ bl,
+__device__ __forceinline__ void contact_lds_body(DevParams P, int64_t n, const int32_t *__restrict__ bl,
                                                      const int32_t *__restrict__ bcnt, int cap,
                                                      const double *__restrict__ x, const double *__restrict__ v,
                                                      const double *__restrict__ r, const int32_t *__restrict__ cb,
@@ -528,6 +534,30 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256) k_contact_lds(DevParams P, int64_t n, const int32_t *__restrict__ bl,
+                                                     const int32_t *__restrict__ bcnt, int cap,
+                                                     const double *__restrict__ x, const double *__restrict__ v,
+                                                     const double *__restrict__ r, const int32_t *__restrict__ cb,
+                                                     const int32_t *__restrict__ ce, T *__restrict__ F,
+                                                     int32_t *__restrict__ ncont, int64_t *err)
+{
+    contact_lds_body<T, false>(P, n, bl, bcnt, cap, x, v, r, cb, ce, nullptr, nullptr, F, ncont, err);
+}
+
+// With liquid bridges: the same body, held to four waves per SIMD (the
+// bridge force and the wet masses need a few more registers than the
+// dry kernel's 114; a small spill costs less than a quarter of the waves).
+template <typename T>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+k_contact_lds_cap(DevParams P, int64_t n, const int32_t *__restrict__ bl, const int32_t *__restrict__ bcnt, int cap,
+                  const double *__restrict__ x, const double *__restrict__ v, const double *__restrict__ r,
+                  const int32_t *__restrict__ cb, const int32_t *__restrict__ ce, const T *__restrict__ sr,
+                  const double *__restrict__ held, T *__restrict__ F, int32_t *__restrict__ ncont, int64_t *err)
+{
+    contact_lds_body<T, true>(P, n, bl, bcnt, cap, x, v, r, cb, ce, sr, held, F, ncont, err);
+}
+
 __global__ void __launch_bounds__(256) k_contact_pairs(DevParams P, int64_t n, const double *__restrict__ x,
                                                        const double *__restrict__ r,
                                                        const int32_t *__restrict__ cb,
@@ -577,12 +607,12 @@ hipError_t launch_contact(const DevParams &P, int64_t n, const double *x, const 
     const int64_t nbricks = (int64_t)P.nb[0] * P.nb[1] * P.nb[2];
     const int cap = 1948;  // shell slots held in LDS: 40,908 bytes, four workgroups per CU
     if (sr)
-        k_contact_lds<T, true><<<brick_grid(nbricks), 256, contact_lds_bytes(cap), s>>>(P, n, B.list, B.count, cap, x,
-                                                                                       v, r, cb, ce, sr, held, F,
-                                                                                       ncont, err);
+        k_contact_lds_cap<T><<<brick_grid(nbricks), 256, contact_lds_bytes(cap), s>>>(P, n, B.list, B.count, cap, x,
+                                                                                     v, r, cb, ce, sr, held, F,
+                                                                                     ncont, err);
     else
-        k_contact_lds<T, false><<<brick_grid(nbricks), 256, contact_lds_bytes(cap), s>>>(
-            P, n, B.list, B.count, cap, x, v, r, cb, ce, sr, nullptr, F, ncont, err);
+        k_contact_lds<T><<<brick_grid(nbricks), 256, contact_lds_bytes(cap), s>>>(P, n, B.list, B.count, cap, x, v,
+                                                                                 r, cb, ce, F, ncont, err);
     return hipGetLastError();
 }
 
