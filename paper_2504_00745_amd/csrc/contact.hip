@@ -294,7 +294,7 @@ __device__ inline bool near_slot(float4 p, float mx, float my, float mz, float t
 }
 
 template <typename T, bool CAP>
-__device__ __forceinline__ void contact_lds_body(DevParams P, int64_t n, const int32_t *__restrict__ bl,
+__global__ void __launch_bounds__(256) k_contact_lds(DevParams P, int64_t n, const int32_t *__restrict__ bl,
                                                      const int32_t *__restrict__ bcnt, int cap,
                                                      const double *__restrict__ x, const double *__restrict__ v,
                                                      const double *__restrict__ r, const int32_t *__restrict__ cb,
@@ -534,30 +534,6 @@ __device__ __forceinline__ void contact_lds_body(DevParams P, int64_t n, const i
     }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_contact_lds(DevParams P, int64_t n, const int32_t *__restrict__ bl,
-                                                     const int32_t *__restrict__ bcnt, int cap,
-                                                     const double *__restrict__ x, const double *__restrict__ v,
-                                                     const double *__restrict__ r, const int32_t *__restrict__ cb,
-                                                     const int32_t *__restrict__ ce, T *__restrict__ F,
-                                                     int32_t *__restrict__ ncont, int64_t *err)
-{
-    contact_lds_body<T, false>(P, n, bl, bcnt, cap, x, v, r, cb, ce, nullptr, nullptr, F, ncont, err);
-}
-
-// With liquid bridges: the same body, held to four waves per SIMD (the
-// bridge force and the wet masses need a few more registers than the
-// dry kernel's 114; a small spill costs less than a quarter of the waves).
-template <typename T>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
-k_contact_lds_cap(DevParams P, int64_t n, const int32_t *__restrict__ bl, const int32_t *__restrict__ bcnt, int cap,
-                  const double *__restrict__ x, const double *__restrict__ v, const double *__restrict__ r,
-                  const int32_t *__restrict__ cb, const int32_t *__restrict__ ce, const T *__restrict__ sr,
-                  const double *__restrict__ held, T *__restrict__ F, int32_t *__restrict__ ncont, int64_t *err)
-{
-    contact_lds_body<T, true>(P, n, bl, bcnt, cap, x, v, r, cb, ce, sr, held, F, ncont, err);
-}
-
 __global__ void __launch_bounds__(256) k_contact_pairs(DevParams P, int64_t n, const double *__restrict__ x,
                                                        const double *__restrict__ r,
                                                        const int32_t *__restrict__ cb,
@@ -607,12 +583,12 @@ hipError_t launch_contact(const DevParams &P, int64_t n, const double *x, const 
     const int64_t nbricks = (int64_t)P.nb[0] * P.nb[1] * P.nb[2];
     const int cap = 1948;  // shell slots held in LDS: 40,908 bytes, four workgroups per CU
     if (sr)
-        k_contact_lds_cap<T><<<brick_grid(nbricks), 256, contact_lds_bytes(cap), s>>>(P, n, B.list, B.count, cap, x,
-                                                                                     v, r, cb, ce, sr, held, F,
-                                                                                     ncont, err);
+        k_contact_lds<T, true><<<brick_grid(nbricks), 256, contact_lds_bytes(cap), s>>>(P, n, B.list, B.count, cap, x,
+                                                                                       v, r, cb, ce, sr, held, F,
+                                                                                       ncont, err);
     else
-        k_contact_lds<T><<<brick_grid(nbricks), 256, contact_lds_bytes(cap), s>>>(P, n, B.list, B.count, cap, x, v,
-                                                                                 r, cb, ce, F, ncont, err);
+        k_contact_lds<T, false><<<brick_grid(nbricks), 256, contact_lds_bytes(cap), s>>>(
+            P, n, B.list, B.count, cap, x, v, r, cb, ce, sr, nullptr, F, ncont, err);
     return hipGetLastError();
 }
 
