@@ -293,8 +293,12 @@ __device__ inline bool near_slot(float4 p, float mx, float my, float mz, float t
     return fmaf(mx, p.x, fmaf(my, p.y, fmaf(mz, p.z, p.w))) < thr;
 }
 
+// The bridge-force instantiation is held to four waves per SIMD (it needs one
+// register more than 128 and spills three); the dry one keeps its own
+// allocation (the hint value 1 puts no limit on it).
 template <typename T, bool CAP>
-__global__ void __launch_bounds__(256) k_contact_lds(DevParams P, int64_t n, const int32_t *__restrict__ bl,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CAP ? 4 : 1)))
+k_contact_lds(DevParams P, int64_t n, const int32_t *__restrict__ bl,
                                                      const int32_t *__restrict__ bcnt, int cap,
                                                      const double *__restrict__ x, const double *__restrict__ v,
                                                      const double *__restrict__ r, const int32_t *__restrict__ cb,
