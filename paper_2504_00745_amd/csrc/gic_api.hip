@@ -169,8 +169,7 @@ int idp_levels(const IdpDims &D0, IdpDims *out)
         n.nx = (out[l].nx + 1) / 2;
         n.ny = (out[l].ny + 1) / 2;
         n.nz = (out[l].nz + 1) / 2;
-        n.sxy = n.nx * n.ny;
-        n.G = n.sxy * n.nz;
+        idp_dims_finish(n);
         out[++l] = n;
     }
     return l + 1;

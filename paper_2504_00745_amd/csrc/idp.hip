@@ -46,14 +46,16 @@ struct Nbr {
     bool inside;   // within the box
 };
 
-// Coordinates of cell c (32-bit division when the grid allows it).
+// Coordinates of cell c.  Below 2^31 cells the two divisions are a multiply
+// by a reciprocal and a shift (the stencil kernels would otherwise spend
+// most of their instructions on them); larger grids divide in 64 bits.
 __device__ inline void coords(const IdpDims &D, int64_t c, int64_t &i, int64_t &j, int64_t &k)
 {
-    if (D.G <= 0xffffffffll) {
+    if (D.G <= 0x80000000ll) {
         const uint32_t cc = (uint32_t)c, nx = (uint32_t)D.nx, ny = (uint32_t)D.ny;
-        const uint32_t row = cc / nx;
+        const uint32_t row = (uint32_t)(((uint64_t)cc * D.mx) >> D.shx);
         i = cc - row * nx;
-        const uint32_t kk = row / ny;
+        const uint32_t kk = (uint32_t)(((uint64_t)row * D.my) >> D.shy);
         j = row - kk * ny;
         k = kk;
     } else {
@@ -127,11 +129,11 @@ __device__ inline double face_sum_ac(const IdpDims &D, int64_t c, int64_t i, int
     const int64_t di[6] = {-1, 1, 0, 0, 0, 0}, dj[6] = {0, 0, -1, 1, 0, 0}, dk[6] = {0, 0, 0, 0, -1, 1};
     const double a = ac[c], vc = val(c, i, j, k);
     double an[6], vn[6];
+    // a neighbour outside the box has an = 0 and contributes nothing, whatever vn holds
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
-        const int64_t n = in[f] ? c + off[f] : c;
-        an[f] = in[f] ? ac[n] : 0.0;
-        vn[f] = val(n, in[f] ? i + di[f] : i, in[f] ? j + dj[f] : j, in[f] ? k + dk[f] : k);
+        an[f] = in[f] ? ac[c + off[f]] : 0.0;
+        vn[f] = in[f] ? val(c + off[f], i + di[f], j + dj[f], k + dk[f]) : 0.0;
     }
     double acc = 0.0;
 #pragma unroll
@@ -588,7 +590,39 @@ unsigned idp_blocks(int64_t G)
     return (unsigned)(b < 1 ? 1 : (b > kIdpMaxBlocks ? kIdpMaxBlocks : b));
 }
 
+// One thread per cell for kernels that write no partials (grid-stride
+// beyond 2^31 - 1 blocks).
+unsigned idp_blocks_full(int64_t G)
+{
+    const int64_t b = (G + kIdpThreads - 1) / kIdpThreads;
+    return (unsigned)(b < 1 ? 1 : (b > 0x7fffffffll ? 0x7fffffffll : b));
+}
+
 }  // namespace
+
+// m = ceil(2^(31+s) / d) with 2^(s-1) < d <= 2^s: m < 2^32, and m d - 2^(31+s)
+// < d <= 2^s, so floor(n m / 2^(31+s)) = floor(n / d) for every n < 2^31
+// (the round-up reciprocal of Granlund and Montgomery, 1994).
+static void div_constants(int64_t d, uint32_t &m, int32_t &sh)
+{
+    int s = 0;
+    while ((int64_t(1) << s) < d) ++s;
+    if (d < 1 || s > 31) {  // grids of 2^31 cells or more divide in 64 bits
+        m = 0;
+        sh = 0;
+        return;
+    }
+    m = (uint32_t)(((uint64_t(1) << (31 + s)) + (uint64_t)d - 1) / (uint64_t)d);
+    sh = 31 + s;
+}
+
+void idp_dims_finish(IdpDims &D)
+{
+    D.sxy = D.nx * D.ny;
+    D.G = D.sxy * D.nz;
+    div_constants(D.nx, D.mx, D.shx);
+    div_constants(D.ny, D.my, D.shy);
+}
 
 IdpDims idp_dims(const DevParams &P)
 {
@@ -596,8 +630,7 @@ IdpDims idp_dims(const DevParams &P)
     D.nx = P.n[0];
     D.ny = P.n[1];
     D.nz = P.n[2];
-    D.sxy = D.nx * D.ny;
-    D.G = D.sxy * D.nz;
+    idp_dims_finish(D);
     return D;
 }
 
@@ -631,13 +664,14 @@ static void launch_vcycle(const IdpWork &W, hipStream_t st)
 {
     const int L = W.nlev;
     for (int l = 0; l + 1 < L; ++l)
-        k_mg_restrict<<<idp_blocks(8 * W.lev[l + 1].D.G), kIdpThreads, 0, st>>>(W.lev[l], W.lev[l + 1], W.state);
+        k_mg_restrict<<<idp_blocks_full(8 * W.lev[l + 1].D.G), kIdpThreads, 0, st>>>(W.lev[l], W.lev[l + 1],
+                                                                                     W.state);
     k_mg_coarsest<<<1, kIdpThreads, 0, st>>>(W.lev[L - 1], W.state);
     for (int l = L - 2; l >= 0; --l) {
         const unsigned nb = idp_blocks(W.lev[l].D.G);
         double *part = l == 0 ? W.part : nullptr;
         if (W.lev[l].D.G >= kMgSplitCells) {
-            k_mg_prolong<<<nb, kIdpThreads, 0, st>>>(W.lev[l], W.lev[l + 1], W.state);
+            k_mg_prolong<<<idp_blocks_full(W.lev[l].D.G), kIdpThreads, 0, st>>>(W.lev[l], W.lev[l + 1], W.state);
             k_mg_sweep<<<nb, kIdpThreads, 0, st>>>(W.lev[l], part, W.state);
         } else {
             k_mg_post<<<nb, kIdpThreads, 0, st>>>(W.lev[l], W.lev[l + 1], part, W.state);

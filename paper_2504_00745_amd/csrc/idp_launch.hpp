@@ -12,6 +12,10 @@ constexpr int kIdpMaxBlocks = 1024;  // partial sums per reduced quantity
 
 struct IdpDims {
     int64_t nx, ny, nz, sxy, G;
+    // floor(n / nx) = (n * mx) >> shx and floor(n / ny) = (n * my) >> shy for
+    // 0 <= n < 2^31 (set by idp_dims_finish)
+    uint32_t mx, my;
+    int32_t shx, shy;
 };
 
 // Conjugate-gradient scalars kept on the device between kernels.
@@ -49,6 +53,8 @@ struct IdpWork {
 };
 
 IdpDims idp_dims(const DevParams &P);
+// Fills sxy, G and the division constants from nx, ny, nz.
+void idp_dims_finish(IdpDims &D);
 hipError_t launch_idp_setup(const IdpDims &D, double alpha_max, const int64_t *afx, const double *astar,
                             const uint8_t *lab, double *at, double *s, int64_t *err, hipStream_t st);
 hipError_t launch_idp_apply(const IdpDims &D, const double *at, const uint8_t *lab, const double *v, double *out,
