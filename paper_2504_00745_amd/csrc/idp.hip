@@ -242,26 +242,81 @@ __global__ void __launch_bounds__(kIdpThreads) k_cg_start(int nb, const double *
     }
 }
 
-// Iteration k, part 1: w = L d; partials of d.w.
-__global__ void __launch_bounds__(kIdpThreads) k_cg_apply(IdpDims D, const double *__restrict__ ac,
-                                                          const double *__restrict__ d, double *__restrict__ w,
-                                                          double *__restrict__ part, const CgState *__restrict__ st)
+// Iteration k, part 1: w = L d and the partials of d.w, in a pass blocked in
+// 2.5D.  A block takes x-y tiles of kTileX x kTileY cells (one wave per tile
+// row) and a run of zlen planes; it keeps its column's coefficients and
+// values for planes z - 1, z, z + 1 in registers and the tile of plane z
+// with a one-cell halo in LDS, so that each operand is read from memory
+// about once instead of once per neighbour.  The next plane of the column
+// and the next halo are loaded one step ahead.  The face sum is
+// face_sum_ac's, term by term in the same order (cells outside the box hold
+// coefficient 0 and value 0).  Items (tile, run of planes) are dealt to the
+// blocks in turn; the block count is the other iteration kernels', whose
+// partial sums this kernel's must match.
+constexpr int kTileX = 64, kTileY = kIdpThreads / 64;
+
+__global__ void __launch_bounds__(kIdpThreads) k_cg_apply(IdpDims D, int ntx, int nty, int zlen,
+                                                          const double *__restrict__ ac, const double *__restrict__ d,
+                                                          double *__restrict__ w, double *__restrict__ part,
+                                                          const CgState *__restrict__ st)
 {
     __shared__ double red[4];
+    __shared__ double sa[kTileY + 2][kTileX + 2], sv[kTileY + 2][kTileX + 2];
     if (st->done >= 0) return;
+    const int lane = threadIdx.x & 63, row = threadIdx.x >> 6, t = threadIdx.x;
+    const int64_t nx = D.nx, ny = D.ny, nz = D.nz;
+    const int64_t tiles = (int64_t)ntx * nty, nzc = (nz + zlen - 1) / zlen, items = tiles * nzc;
+    // halo slot of this thread: rows below and above the tile (t < 128), columns left and right (t < 136)
+    int hr = -1, hc = -1, hdi = 0, hdj = 0;
+    if (t < kTileX) { hr = 0; hc = t + 1; hdi = t; hdj = -1; }
+    else if (t < 2 * kTileX) { hr = kTileY + 1; hc = t - kTileX + 1; hdi = t - kTileX; hdj = kTileY; }
+    else if (t < 2 * kTileX + kTileY) { hr = t - 2 * kTileX + 1; hc = 0; hdi = -1; hdj = t - 2 * kTileX; }
+    else if (t < 2 * kTileX + 2 * kTileY) { hr = t - 2 * kTileX - kTileY + 1; hc = kTileX + 1; hdi = kTileX; hdj = t - 2 * kTileX - kTileY; }
     double dw = 0.0;
-    for (int64_t c = (int64_t)blockIdx.x * kIdpThreads + threadIdx.x; c < D.G;
-         c += (int64_t)gridDim.x * kIdpThreads) {
-        double Lv;
-        if (ac[c] > 0.0) {
-            int64_t i, j, k;
-            coords(D, c, i, j, k);
-            Lv = face_sum_ac(D, c, i, j, k, ac, [&](int64_t n, int64_t, int64_t, int64_t) { return d[n]; });
-        } else {
-            Lv = d[c];  // identity row
+    for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+        const int64_t tile = it % tiles, z0 = (it / tiles) * zlen;
+        const int64_t z1 = z0 + zlen < nz ? z0 + zlen : nz;
+        const int64_t i0 = (tile % ntx) * kTileX, j0 = (tile / ntx) * kTileY;
+        const int64_t i = i0 + lane, j = j0 + row;
+        const bool own = i < nx && j < ny;
+        const int64_t col = j * nx + i;  // cell index of (i, j, 0)
+        const int64_t hi = i0 + hdi, hj = j0 + hdj;
+        const bool hown = hr >= 0 && hi >= 0 && hi < nx && hj >= 0 && hj < ny;
+        const int64_t hcol = hj * nx + hi;
+        // column: m = z - 1, c = z, p = z + 1; halo of plane z
+        double am = 0.0, vm = 0.0, a0 = 0.0, v0 = 0.0, ap = 0.0, vp = 0.0, ha = 0.0, hv = 0.0;
+        if (own && z0 > 0) { am = ac[col + (z0 - 1) * D.sxy]; vm = d[col + (z0 - 1) * D.sxy]; }
+        if (own) { a0 = ac[col + z0 * D.sxy]; v0 = d[col + z0 * D.sxy]; }
+        if (own && z0 + 1 < nz) { ap = ac[col + (z0 + 1) * D.sxy]; vp = d[col + (z0 + 1) * D.sxy]; }
+        if (hown) { ha = ac[hcol + z0 * D.sxy]; hv = d[hcol + z0 * D.sxy]; }
+        for (int64_t z = z0; z < z1; ++z) {
+            // one step ahead: the column's plane z + 2 and the halo of plane z + 1
+            double an2 = 0.0, vn2 = 0.0, ha1 = 0.0, hv1 = 0.0;
+            if (own && z + 2 < nz) { an2 = ac[col + (z + 2) * D.sxy]; vn2 = d[col + (z + 2) * D.sxy]; }
+            if (hown && z + 1 < nz) { ha1 = ac[hcol + (z + 1) * D.sxy]; hv1 = d[hcol + (z + 1) * D.sxy]; }
+            __syncthreads();  // the previous plane's reads of the tile are done
+            sa[row + 1][lane + 1] = a0;
+            sv[row + 1][lane + 1] = v0;
+            if (hr >= 0) { sa[hr][hc] = ha; sv[hr][hc] = hv; }
+            __syncthreads();
+            if (own) {
+                const double an[6] = {sa[row + 1][lane], sa[row + 1][lane + 2], sa[row][lane + 1],
+                                      sa[row + 2][lane + 1], am, ap};
+                const double vn[6] = {sv[row + 1][lane], sv[row + 1][lane + 2], sv[row][lane + 1],
+                                      sv[row + 2][lane + 1], vm, vp};
+                double acc = 0.0;
+#pragma unroll
+                for (int f = 0; f < 6; ++f) {
+                    const double beta = an[f] != 0.0 ? (a0 + fabs(an[f])) * 0.5 : 0.0;
+                    const double v = an[f] > 0.0 ? vn[f] : 0.0;
+                    acc += beta * (v0 - v);
+                }
+                const double Lv = a0 > 0.0 ? acc : v0;  // identity row off the fluid
+                w[col + z * D.sxy] = Lv;
+                dw += v0 * Lv;
+            }
+            am = a0; vm = v0; a0 = ap; v0 = vp; ap = an2; vp = vn2; ha = ha1; hv = hv1;
         }
-        w[c] = Lv;
-        dw += d[c] * Lv;
     }
     dw = block_sum(dw, red);
     if (threadIdx.x == 0) part[blockIdx.x] = dw;
@@ -702,8 +757,12 @@ hipError_t launch_cg_iterations(const IdpDims &D, const double *at, const uint8_
 {
     const unsigned nb = idp_blocks(D.G);
     const bool mg = W.nlev > 1;
+    // tiles of the blocked operator and the planes per item: about one item per block
+    const int ntx = (int)((D.nx + kTileX - 1) / kTileX), nty = (int)((D.ny + kTileY - 1) / kTileY);
+    const int64_t zl = (D.nz * ntx * nty + nb - 1) / nb;
+    const int zlen = (int)(zl < 1 ? 1 : (zl > D.nz ? D.nz : zl));
     for (int k = k0; k < k0 + count; ++k) {
-        k_cg_apply<<<nb, kIdpThreads, 0, st>>>(D, W.lev[0].ac, W.d, W.w, W.part, W.state);
+        k_cg_apply<<<nb, kIdpThreads, 0, st>>>(D, ntx, nty, zlen, W.lev[0].ac, W.d, W.w, W.part, W.state);
         if (mg) {
             k_cg_update<false><<<nb, kIdpThreads, 0, st>>>(D, k, W.d, W.w, W.dinv, q, W.r, W.part, W.state);
             launch_vcycle(W, st);
