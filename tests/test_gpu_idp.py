@@ -283,6 +283,52 @@ def test_multigrid_on_tiny_and_flat_grids(G, orc):
         assert np.linalg.norm(host(q, shape) - q_or) <= res / lambda_min(orc, at, lab) * 1.01 + 1e-15
 
 
+@pytest.mark.parametrize("precond", [0, 1])
+def test_blocked_operator_ragged_and_many_tiles(G, orc, precond):
+    """The iteration's operator pass runs on x-y tiles of 64 x 4 cells and
+    runs of planes: a 70 x 6 x 37 grid (a partial x tile of 6 cells and a
+    partial y tile of 2 rows) and a flat 1024 x 260 x 2 grid (1,040 tiles,
+    more than the 1,024 blocks, so some blocks take two).  Both solve to the
+    oracle's direct solution within the residual bound.  On the flat grid
+    every fluid cell lies under air, so lambda_min is at least the smallest
+    beta of those air faces (L is that diagonal plus a positive
+    semi-definite graph Laplacian)."""
+    import torch
+    from paper_2504_00745_amd import gic
+    for shape in ((37, 6, 70), (2, 260, 1024)):
+        G.say(f"[idp blocked operator] {shape} precond {precond}")
+        nz, ny, nx = shape
+        rng = np.random.Generator(np.random.PCG64(nx + precond))
+        lab = np.zeros(shape, np.uint8)
+        at = rng.uniform(0.3, 1.0, shape)
+        if nz == 2:
+            lab[1] = 1
+            lab[0, 100:120, 500:560] = 2
+        else:
+            lab[28:] = 1
+            lab[:9, 2:4, 40:66] = 2
+        s = np.where(lab == 0, rng.normal(0, 0.1, shape), 0.0)
+        p = wl._params((nx, ny, nz), 0.01, 0.01, 1e-4, (0.0, 0.0, 0.0))
+        ctx = gic.Context(p, 1, "fp64", r_max=0.0025)
+        q = torch.zeros(ctx.G, dtype=torch.float64, device="cuda")
+        it, rel = gic.gic_idp_solve(ctx, G.dev(at.reshape(-1)), torch.as_tensor(lab.reshape(-1)).to("cuda"),
+                                    G.dev(s.reshape(-1)), q, gic.idp_workspace(ctx), max_iter=4000, tol=1e-10,
+                                    precond=precond)
+        assert 0 < it < 4000 and rel <= 1e-10
+        qg = host(q, shape)
+        q_or = orc.idp.solve(at, lab, s)
+        res = residual(orc, at, lab, s, qg)
+        assert res <= 1.5e-10 * np.linalg.norm(s)
+        if nz == 2:
+            lmin = float((0.5 * (at[0] + at[1]))[lab[0] == 0].min())
+        else:
+            lmin = lambda_min(orc, at, lab)
+        assert np.linalg.norm(qg - q_or) <= res / lmin * 1.01 + 1e-15
+        assert not qg[lab != 0].any()
+        assert ctx.error() == (0, -1)
+        G.say(f"  {shape} precond {precond}: {it} iterations")
+
+
 def test_invalid_labels_and_fractions_latch_errors(G):
     """A label outside 0..2 latches GIC_E_RANGE at setup; alpha_f' = 0 on an
     air cell latches it at the start of a solve; the index is the cell."""
