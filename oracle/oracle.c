@@ -1345,7 +1345,9 @@ int32_t orc_sand_step(const orc_params *p, const orc_coupling *cp, int64_t n, do
  *   - Gamma's control points are not printed: a piecewise quadratic Bezier
  *     bump, Gamma(sr) = u (2 - u), u = sr / sr_peak on (0, sr_peak], and
  *     1 - u^2, u = (sr - sr_peak) / (1 - sr_peak) on (sr_peak, 1); zero at
- *     sr <= 0 and sr >= 1, one at sr_peak (the maximum absorption ratio);
+ *     sr <= 0 and sr >= 1, one at sr_peak (the maximum absorption ratio).
+ *     Parity unpinned for the shape of Gamma between those three points: the
+ *     tests pin Gamma(0) = Gamma(1) = 0 and Gamma(sr_peak) = 1 only;
  *   - the water a granule holds, r_i of the moisture ratio, is an input (the
  *     wetting of Sec. 5.3 is not on this path); alpha_f,i is the fluid
  *     fraction the granule samples from the grid (G2P).
