@@ -243,8 +243,8 @@ __global__ void __launch_bounds__(kIdpThreads) k_cg_start(int nb, const double *
 }
 
 // Iteration k, part 1: w = L d and the partials of d.w, in a pass blocked in
-// 2.5D.  A block takes x-y tiles of kTileX x kTileY cells (one wave per tile
-// row) and a run of zlen planes; it keeps its column's coefficients and
+// 2.5D.  A block takes x-y tiles of kTileX x kTileY cells (each wave takes
+// kTileRows rows) and a run of zlen planes; it keeps its columns' coefficients and
 // values for planes z - 1, z, z + 1 in registers and the tile of plane z
 // with a one-cell halo in LDS, so that each operand is read from memory
 // about once instead of once per neighbour.  The next plane of the column
@@ -253,20 +253,22 @@ __global__ void __launch_bounds__(kIdpThreads) k_cg_start(int nb, const double *
 // coefficient 0 and value 0).  Items (tile, run of planes) are dealt to the
 // blocks in turn; the block count is the other iteration kernels', whose
 // partial sums this kernel's must match.
-constexpr int kTileX = 64, kTileY = kIdpThreads / 64;
+constexpr int kTileRows = 2;  // tile rows per wave (rows row and row + 4 of the tile)
+constexpr int kTileX = 64, kTileY = kIdpThreads / 64 * kTileRows;
 
 __global__ void __launch_bounds__(kIdpThreads) k_cg_apply(IdpDims D, int ntx, int nty, int zlen,
                                                           const double *__restrict__ ac, const double *__restrict__ d,
                                                           double *__restrict__ w, double *__restrict__ part,
                                                           const CgState *__restrict__ st)
 {
+    constexpr int kWaves = kIdpThreads / 64;
     __shared__ double red[4];
     __shared__ double sa[kTileY + 2][kTileX + 2], sv[kTileY + 2][kTileX + 2];
     if (st->done >= 0) return;
     const int lane = threadIdx.x & 63, row = threadIdx.x >> 6, t = threadIdx.x;
     const int64_t nx = D.nx, ny = D.ny, nz = D.nz;
     const int64_t tiles = (int64_t)ntx * nty, nzc = (nz + zlen - 1) / zlen, items = tiles * nzc;
-    // halo slot of this thread: rows below and above the tile (t < 128), columns left and right (t < 136)
+    // halo slot of this thread: rows below and above the tile (t < 128), columns left and right (t < 144)
     int hr = -1, hc = -1, hdi = 0, hdj = 0;
     if (t < kTileX) { hr = 0; hc = t + 1; hdi = t; hdj = -1; }
     else if (t < 2 * kTileX) { hr = kTileY + 1; hc = t - kTileX + 1; hdi = t - kTileX; hdj = kTileY; }
@@ -277,45 +279,68 @@ __global__ void __launch_bounds__(kIdpThreads) k_cg_apply(IdpDims D, int ntx, in
         const int64_t tile = it % tiles, z0 = (it / tiles) * zlen;
         const int64_t z1 = z0 + zlen < nz ? z0 + zlen : nz;
         const int64_t i0 = (tile % ntx) * kTileX, j0 = (tile / ntx) * kTileY;
-        const int64_t i = i0 + lane, j = j0 + row;
-        const bool own = i < nx && j < ny;
-        const int64_t col = j * nx + i;  // cell index of (i, j, 0)
+        const int64_t i = i0 + lane;
+        bool own[kTileRows];
+        int64_t col[kTileRows];  // cell index of (i, j, 0) for the thread's rows
+#pragma unroll
+        for (int q = 0; q < kTileRows; ++q) {
+            const int64_t j = j0 + row + q * kWaves;
+            own[q] = i < nx && j < ny;
+            col[q] = j * nx + i;
+        }
         const int64_t hi = i0 + hdi, hj = j0 + hdj;
         const bool hown = hr >= 0 && hi >= 0 && hi < nx && hj >= 0 && hj < ny;
         const int64_t hcol = hj * nx + hi;
-        // column: m = z - 1, c = z, p = z + 1; halo of plane z
-        double am = 0.0, vm = 0.0, a0 = 0.0, v0 = 0.0, ap = 0.0, vp = 0.0, ha = 0.0, hv = 0.0;
-        if (own && z0 > 0) { am = ac[col + (z0 - 1) * D.sxy]; vm = d[col + (z0 - 1) * D.sxy]; }
-        if (own) { a0 = ac[col + z0 * D.sxy]; v0 = d[col + z0 * D.sxy]; }
-        if (own && z0 + 1 < nz) { ap = ac[col + (z0 + 1) * D.sxy]; vp = d[col + (z0 + 1) * D.sxy]; }
+        // columns: m = z - 1, 0 = z, p = z + 1; halo of plane z
+        double am[kTileRows], vm[kTileRows], a0[kTileRows], v0[kTileRows], ap[kTileRows], vp[kTileRows];
+        double ha = 0.0, hv = 0.0;
+#pragma unroll
+        for (int q = 0; q < kTileRows; ++q) {
+            am[q] = vm[q] = a0[q] = v0[q] = ap[q] = vp[q] = 0.0;
+            if (own[q] && z0 > 0) { am[q] = ac[col[q] + (z0 - 1) * D.sxy]; vm[q] = d[col[q] + (z0 - 1) * D.sxy]; }
+            if (own[q]) { a0[q] = ac[col[q] + z0 * D.sxy]; v0[q] = d[col[q] + z0 * D.sxy]; }
+            if (own[q] && z0 + 1 < nz) { ap[q] = ac[col[q] + (z0 + 1) * D.sxy]; vp[q] = d[col[q] + (z0 + 1) * D.sxy]; }
+        }
         if (hown) { ha = ac[hcol + z0 * D.sxy]; hv = d[hcol + z0 * D.sxy]; }
         for (int64_t z = z0; z < z1; ++z) {
-            // one step ahead: the column's plane z + 2 and the halo of plane z + 1
-            double an2 = 0.0, vn2 = 0.0, ha1 = 0.0, hv1 = 0.0;
-            if (own && z + 2 < nz) { an2 = ac[col + (z + 2) * D.sxy]; vn2 = d[col + (z + 2) * D.sxy]; }
+            // one step ahead: the columns' plane z + 2 and the halo of plane z + 1
+            double a2[kTileRows], v2[kTileRows], ha1 = 0.0, hv1 = 0.0;
+#pragma unroll
+            for (int q = 0; q < kTileRows; ++q) {
+                a2[q] = v2[q] = 0.0;
+                if (own[q] && z + 2 < nz) { a2[q] = ac[col[q] + (z + 2) * D.sxy]; v2[q] = d[col[q] + (z + 2) * D.sxy]; }
+            }
             if (hown && z + 1 < nz) { ha1 = ac[hcol + (z + 1) * D.sxy]; hv1 = d[hcol + (z + 1) * D.sxy]; }
             __syncthreads();  // the previous plane's reads of the tile are done
-            sa[row + 1][lane + 1] = a0;
-            sv[row + 1][lane + 1] = v0;
+#pragma unroll
+            for (int q = 0; q < kTileRows; ++q) {
+                sa[row + q * kWaves + 1][lane + 1] = a0[q];
+                sv[row + q * kWaves + 1][lane + 1] = v0[q];
+            }
             if (hr >= 0) { sa[hr][hc] = ha; sv[hr][hc] = hv; }
             __syncthreads();
-            if (own) {
-                const double an[6] = {sa[row + 1][lane], sa[row + 1][lane + 2], sa[row][lane + 1],
-                                      sa[row + 2][lane + 1], am, ap};
-                const double vn[6] = {sv[row + 1][lane], sv[row + 1][lane + 2], sv[row][lane + 1],
-                                      sv[row + 2][lane + 1], vm, vp};
+#pragma unroll
+            for (int q = 0; q < kTileRows; ++q) {
+                if (!own[q]) continue;
+                const int r = row + q * kWaves + 1;  // the cell's row in the tile
+                const double an[6] = {sa[r][lane], sa[r][lane + 2], sa[r - 1][lane + 1], sa[r + 1][lane + 1], am[q], ap[q]};
+                const double vn[6] = {sv[r][lane], sv[r][lane + 2], sv[r - 1][lane + 1], sv[r + 1][lane + 1], vm[q], vp[q]};
                 double acc = 0.0;
 #pragma unroll
                 for (int f = 0; f < 6; ++f) {
-                    const double beta = an[f] != 0.0 ? (a0 + fabs(an[f])) * 0.5 : 0.0;
+                    const double beta = an[f] != 0.0 ? (a0[q] + fabs(an[f])) * 0.5 : 0.0;
                     const double v = an[f] > 0.0 ? vn[f] : 0.0;
-                    acc += beta * (v0 - v);
+                    acc += beta * (v0[q] - v);
                 }
-                const double Lv = a0 > 0.0 ? acc : v0;  // identity row off the fluid
-                w[col + z * D.sxy] = Lv;
-                dw += v0 * Lv;
+                const double Lv = a0[q] > 0.0 ? acc : v0[q];  // identity row off the fluid
+                w[col[q] + z * D.sxy] = Lv;
+                dw += v0[q] * Lv;
             }
-            am = a0; vm = v0; a0 = ap; v0 = vp; ap = an2; vp = vn2; ha = ha1; hv = hv1;
+#pragma unroll
+            for (int q = 0; q < kTileRows; ++q) {
+                am[q] = a0[q]; vm[q] = v0[q]; a0[q] = ap[q]; v0[q] = vp[q]; ap[q] = a2[q]; vp[q] = v2[q];
+            }
+            ha = ha1; hv = hv1;
         }
     }
     dw = block_sum(dw, red);

@@ -285,9 +285,9 @@ def test_multigrid_on_tiny_and_flat_grids(G, orc):
 
 @pytest.mark.parametrize("precond", [0, 1])
 def test_blocked_operator_ragged_and_many_tiles(G, orc, precond):
-    """The iteration's operator pass runs on x-y tiles of 64 x 4 cells and
+    """The iteration's operator pass runs on x-y tiles of 64 x 8 cells and
     runs of planes: a 70 x 6 x 37 grid (a partial x tile of 6 cells and a
-    partial y tile of 2 rows) and a flat 1024 x 260 x 2 grid (1,040 tiles,
+    partial y tile of 6 rows) and a flat 1024 x 520 x 2 grid (1,040 tiles,
     more than the 1,024 blocks, so some blocks take two).  Both solve to the
     oracle's direct solution within the residual bound.  On the flat grid
     every fluid cell lies under air, so lambda_min is at least the smallest
@@ -295,7 +295,7 @@ def test_blocked_operator_ragged_and_many_tiles(G, orc, precond):
     semi-definite graph Laplacian)."""
     import torch
     from paper_2504_00745_amd import gic
-    for shape in ((37, 6, 70), (2, 260, 1024)):
+    for shape in ((37, 6, 70), (2, 520, 1024)):
         G.say(f"[idp blocked operator] {shape} precond {precond}")
         nz, ny, nx = shape
         rng = np.random.Generator(np.random.PCG64(nx + precond))
@@ -303,7 +303,7 @@ def test_blocked_operator_ragged_and_many_tiles(G, orc, precond):
         at = rng.uniform(0.3, 1.0, shape)
         if nz == 2:
             lab[1] = 1
-            lab[0, 100:120, 500:560] = 2
+            lab[0, 200:230, 500:560] = 2
         else:
             lab[28:] = 1
             lab[:9, 2:4, 40:66] = 2
