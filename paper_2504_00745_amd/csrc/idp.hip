@@ -129,12 +129,17 @@ __device__ inline double face_sum_ac(const IdpDims &D, int64_t c, int64_t i, int
     const int64_t di[6] = {-1, 1, 0, 0, 0, 0}, dj[6] = {0, 0, -1, 1, 0, 0}, dk[6] = {0, 0, 0, 0, -1, 1};
     const double a = ac[c], vc = val(c, i, j, k);
     double an[6], vn[6];
-    // a neighbour outside the box has an = 0 and contributes nothing, whatever vn holds
+    // a neighbour outside the box reads the cell itself (so that every load is
+    // issued without a branch, all before any is used) and gets an = 0: it
+    // contributes nothing, whatever vn holds
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
-        an[f] = in[f] ? ac[c + off[f]] : 0.0;
-        vn[f] = in[f] ? val(c + off[f], i + di[f], j + dj[f], k + dk[f]) : 0.0;
+        const int64_t n = c + (in[f] ? off[f] : 0);
+        an[f] = ac[n];
+        vn[f] = val(n, in[f] ? i + di[f] : i, in[f] ? j + dj[f] : j, in[f] ? k + dk[f] : k);
     }
+#pragma unroll
+    for (int f = 0; f < 6; ++f) an[f] = in[f] ? an[f] : 0.0;
     double acc = 0.0;
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
