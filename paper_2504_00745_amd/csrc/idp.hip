@@ -279,8 +279,13 @@ __global__ void __launch_bounds__(kIdpThreads) k_cg_apply(IdpDims D, int ntx, in
     else if (t < 2 * kTileX) { hr = kTileY + 1; hc = t - kTileX + 1; hdi = t - kTileX; hdj = kTileY; }
     else if (t < 2 * kTileX + kTileY) { hr = t - 2 * kTileX + 1; hc = 0; hdi = -1; hdj = t - 2 * kTileX; }
     else if (t < 2 * kTileX + 2 * kTileY) { hr = t - 2 * kTileX - kTileY + 1; hc = kTileX + 1; hdi = kTileX; hdj = t - 2 * kTileX - kTileY; }
+    // items in tile order within a run of planes; workgroups are dealt to the
+    // eight XCDs in turn, so block b starts at item (b % 8) nb/8 + b/8 and each
+    // XCD takes a contiguous eighth (y-adjacent tiles share its L2)
+    const int64_t nb = gridDim.x;
+    const int64_t first = nb % 8 ? (int64_t)blockIdx.x : (blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8;
     double dw = 0.0;
-    for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+    for (int64_t it = first; it < items; it += nb) {
         const int64_t tile = it % tiles, z0 = (it / tiles) * zlen;
         const int64_t z1 = z0 + zlen < nz ? z0 + zlen : nz;
         const int64_t i0 = (tile % ntx) * kTileX, j0 = (tile / ntx) * kTileY;
@@ -313,9 +318,13 @@ __global__ void __launch_bounds__(kIdpThreads) k_cg_apply(IdpDims D, int ntx, in
 #pragma unroll
             for (int q = 0; q < kTileRows; ++q) {
                 a2[q] = v2[q] = 0.0;
-                if (own[q] && z + 2 < nz) { a2[q] = ac[col[q] + (z + 2) * D.sxy]; v2[q] = d[col[q] + (z + 2) * D.sxy]; }
+                // plane z1 is the last one the run reads (the +z neighbour of its last plane)
+                if (own[q] && z + 2 <= z1 && z + 2 < nz) {
+                    a2[q] = ac[col[q] + (z + 2) * D.sxy];
+                    v2[q] = d[col[q] + (z + 2) * D.sxy];
+                }
             }
-            if (hown && z + 1 < nz) { ha1 = ac[hcol + (z + 1) * D.sxy]; hv1 = d[hcol + (z + 1) * D.sxy]; }
+            if (hown && z + 1 < z1) { ha1 = ac[hcol + (z + 1) * D.sxy]; hv1 = d[hcol + (z + 1) * D.sxy]; }
             __syncthreads();  // the previous plane's reads of the tile are done
 #pragma unroll
             for (int q = 0; q < kTileRows; ++q) {
