@@ -247,8 +247,11 @@ __global__ void __launch_bounds__(kIdpThreads) k_cg_start(int nb, const double *
     }
 }
 
-// Iteration k, part 1: w = L d and the partials of d.w, in a pass blocked in
-// 2.5D.  A block takes x-y tiles of kTileX x kTileY cells (each wave takes
+// Stencil passes blocked in 2.5D: SWEEP = false is iteration k, part 1:
+// w = L d and the partials of d.w in part[block]; SWEEP = true is the
+// multigrid post-sweep from the prolonged iterate (d = u): w = e = u + omega
+// D^-1 (b - A u) on fluid cells, b elsewhere, and the partials of b.e in
+// part[nblocks + block] when part is given.  The pass is blocked in 2.5D.  A block takes x-y tiles of kTileX x kTileY cells (each wave takes
 // kTileRows rows) and a run of zlen planes; it keeps its columns' coefficients and
 // values for planes z - 1, z, z + 1 in registers and the tile of plane z
 // with a one-cell halo in LDS, so that each operand is read from memory
@@ -258,13 +261,18 @@ __global__ void __launch_bounds__(kIdpThreads) k_cg_start(int nb, const double *
 // coefficient 0 and value 0).  Items (tile, run of planes) are dealt to the
 // blocks in turn; the block count is the other iteration kernels', whose
 // partial sums this kernel's must match.
+constexpr double kOmega = 2.0 / 3.0;  // damping of the multigrid's Jacobi sweeps
 constexpr int kTileRows = 2;  // tile rows per wave (rows row and row + 4 of the tile)
 constexpr int kTileX = 64, kTileY = kIdpThreads / 64 * kTileRows;
 
-__global__ void __launch_bounds__(kIdpThreads) k_cg_apply(IdpDims D, int ntx, int nty, int zlen,
-                                                          const double *__restrict__ ac, const double *__restrict__ d,
-                                                          double *__restrict__ w, double *__restrict__ part,
-                                                          const CgState *__restrict__ st)
+template <bool SWEEP>
+__global__ void __launch_bounds__(kIdpThreads) k_stencil_tiled(IdpDims D, int ntx, int nty, int zlen,
+                                                               const double *__restrict__ ac,
+                                                               const double *__restrict__ d,
+                                                               const double *__restrict__ b,
+                                                               const double *__restrict__ dinv, double scale,
+                                                               double *__restrict__ w, double *__restrict__ part,
+                                                               const CgState *__restrict__ st)
 {
     constexpr int kWaves = kIdpThreads / 64;
     __shared__ double red[4];
@@ -303,10 +311,12 @@ __global__ void __launch_bounds__(kIdpThreads) k_cg_apply(IdpDims D, int ntx, in
         const int64_t hcol = hj * nx + hi;
         // columns: m = z - 1, 0 = z, p = z + 1; halo of plane z
         double am[kTileRows], vm[kTileRows], a0[kTileRows], v0[kTileRows], ap[kTileRows], vp[kTileRows];
+        double b0[kTileRows], di0[kTileRows];  // right-hand side and 1/diag of plane z (sweep)
         double ha = 0.0, hv = 0.0;
 #pragma unroll
         for (int q = 0; q < kTileRows; ++q) {
-            am[q] = vm[q] = a0[q] = v0[q] = ap[q] = vp[q] = 0.0;
+            am[q] = vm[q] = a0[q] = v0[q] = ap[q] = vp[q] = b0[q] = di0[q] = 0.0;
+            if (SWEEP && own[q]) { b0[q] = b[col[q] + z0 * D.sxy]; di0[q] = dinv[col[q] + z0 * D.sxy]; }
             if (own[q] && z0 > 0) { am[q] = ac[col[q] + (z0 - 1) * D.sxy]; vm[q] = d[col[q] + (z0 - 1) * D.sxy]; }
             if (own[q]) { a0[q] = ac[col[q] + z0 * D.sxy]; v0[q] = d[col[q] + z0 * D.sxy]; }
             if (own[q] && z0 + 1 < nz) { ap[q] = ac[col[q] + (z0 + 1) * D.sxy]; vp[q] = d[col[q] + (z0 + 1) * D.sxy]; }
@@ -314,10 +324,14 @@ __global__ void __launch_bounds__(kIdpThreads) k_cg_apply(IdpDims D, int ntx, in
         if (hown) { ha = ac[hcol + z0 * D.sxy]; hv = d[hcol + z0 * D.sxy]; }
         for (int64_t z = z0; z < z1; ++z) {
             // one step ahead: the columns' plane z + 2 and the halo of plane z + 1
-            double a2[kTileRows], v2[kTileRows], ha1 = 0.0, hv1 = 0.0;
+            double a2[kTileRows], v2[kTileRows], b1[kTileRows], di1[kTileRows], ha1 = 0.0, hv1 = 0.0;
 #pragma unroll
             for (int q = 0; q < kTileRows; ++q) {
-                a2[q] = v2[q] = 0.0;
+                a2[q] = v2[q] = b1[q] = di1[q] = 0.0;
+                if (SWEEP && own[q] && z + 1 < z1) {
+                    b1[q] = b[col[q] + (z + 1) * D.sxy];
+                    di1[q] = dinv[col[q] + (z + 1) * D.sxy];
+                }
                 // plane z1 is the last one the run reads (the +z neighbour of its last plane)
                 if (own[q] && z + 2 <= z1 && z + 2 < nz) {
                     a2[q] = ac[col[q] + (z + 2) * D.sxy];
@@ -346,19 +360,29 @@ __global__ void __launch_bounds__(kIdpThreads) k_cg_apply(IdpDims D, int ntx, in
                     const double v = an[f] > 0.0 ? vn[f] : 0.0;
                     acc += beta * (v0[q] - v);
                 }
-                const double Lv = a0[q] > 0.0 ? acc : v0[q];  // identity row off the fluid
-                w[col[q] + z * D.sxy] = Lv;
-                dw += v0[q] * Lv;
+                if (SWEEP) {
+                    const double Au = scale * acc;
+                    const double e = a0[q] > 0.0 ? v0[q] + kOmega * di0[q] * (b0[q] - Au) : b0[q];
+                    w[col[q] + z * D.sxy] = e;
+                    dw += b0[q] * e;
+                } else {
+                    const double Lv = a0[q] > 0.0 ? acc : v0[q];  // identity row off the fluid
+                    w[col[q] + z * D.sxy] = Lv;
+                    dw += v0[q] * Lv;
+                }
             }
 #pragma unroll
             for (int q = 0; q < kTileRows; ++q) {
                 am[q] = a0[q]; vm[q] = v0[q]; a0[q] = ap[q]; v0[q] = vp[q]; ap[q] = a2[q]; vp[q] = v2[q];
+                b0[q] = b1[q]; di0[q] = di1[q];
             }
             ha = ha1; hv = hv1;
         }
     }
-    dw = block_sum(dw, red);
-    if (threadIdx.x == 0) part[blockIdx.x] = dw;
+    if (!SWEEP || part) {
+        dw = block_sum(dw, red);
+        if (threadIdx.x == 0) part[(SWEEP ? nb : 0) + blockIdx.x] = dw;
+    }
 }
 
 template <bool JAC>
@@ -483,7 +507,6 @@ __global__ void __launch_bounds__(kIdpThreads) k_idp_faces(IdpDims D, double dx,
 // LDS.  Equal pre- and post-sweeps and R = P^T keep the preconditioner
 // symmetric.  Non-fluid rows of the finest level are identity rows and get
 // z = r.  Levels carry the signed coefficients (see face_sum_ac).
-constexpr double kOmega = 2.0 / 3.0;
 constexpr int kCoarseSweeps = 48;
 
 // uniform per block: read the solver state once
@@ -587,33 +610,6 @@ __global__ void __launch_bounds__(kIdpThreads) k_mg_prolong(MgLevel F, MgLevel C
             if (Cl.ac[p] > 0.0) u += Cl.e[p];
         }
         F.t[c] = u;
-    }
-}
-
-// Post-sweep from the prolonged iterate u (in t): e = u + w D^-1 (b - A u)
-// (e = b on non-fluid rows); on the finest level also the partials of b.e.
-__global__ void __launch_bounds__(kIdpThreads) k_mg_sweep(MgLevel F, double *__restrict__ part,
-                                                          const CgState *__restrict__ st)
-{
-    __shared__ double red[4];
-    if (cg_done(st)) return;
-    double rz = 0.0;
-    for (int64_t c = (int64_t)blockIdx.x * kIdpThreads + threadIdx.x; c < F.D.G;
-         c += (int64_t)gridDim.x * kIdpThreads) {
-        double z = F.b[c];
-        if (F.ac[c] > 0.0) {
-            int64_t i, j, k;
-            coords(F.D, c, i, j, k);
-            const double Au = F.scale * face_sum_ac(F.D, c, i, j, k, F.ac,
-                                                    [&](int64_t n, int64_t, int64_t, int64_t) { return F.t[n]; });
-            z = F.t[c] + kOmega * F.dinv[c] * (F.b[c] - Au);
-        }
-        F.e[c] = z;
-        rz += F.b[c] * z;
-    }
-    if (part) {
-        rz = block_sum(rz, red);
-        if (threadIdx.x == 0) part[gridDim.x + blockIdx.x] = rz;
     }
 }
 
@@ -754,6 +750,16 @@ hipError_t launch_idp_faces(const IdpDims &D, double dx, const double *q, const 
 // then sweep; smaller levels do both in one pass (launch latency dominates).
 constexpr int64_t kMgSplitCells = 1 << 18;
 
+// Tiles of a blocked stencil pass over D and the planes per item: about one
+// item per block of nb.
+static void stencil_items(const IdpDims &D, unsigned nb, int &ntx, int &nty, int &zlen)
+{
+    ntx = (int)((D.nx + kTileX - 1) / kTileX);
+    nty = (int)((D.ny + kTileY - 1) / kTileY);
+    const int64_t zl = (D.nz * ntx * nty + nb - 1) / nb;
+    zlen = (int)(zl < 1 ? 1 : (zl > D.nz ? D.nz : zl));
+}
+
 static void launch_vcycle(const IdpWork &W, hipStream_t st)
 {
     const int L = W.nlev;
@@ -766,7 +772,11 @@ static void launch_vcycle(const IdpWork &W, hipStream_t st)
         double *part = l == 0 ? W.part : nullptr;
         if (W.lev[l].D.G >= kMgSplitCells) {
             k_mg_prolong<<<idp_blocks_full(W.lev[l].D.G), kIdpThreads, 0, st>>>(W.lev[l], W.lev[l + 1], W.state);
-            k_mg_sweep<<<nb, kIdpThreads, 0, st>>>(W.lev[l], part, W.state);
+            const MgLevel &F = W.lev[l];
+            int ntx, nty, zlen;
+            stencil_items(F.D, nb, ntx, nty, zlen);
+            k_stencil_tiled<true><<<nb, kIdpThreads, 0, st>>>(F.D, ntx, nty, zlen, F.ac, F.t, F.b, F.dinv, F.scale,
+                                                               F.e, part, W.state);
         } else {
             k_mg_post<<<nb, kIdpThreads, 0, st>>>(W.lev[l], W.lev[l + 1], part, W.state);
         }
@@ -796,12 +806,11 @@ hipError_t launch_cg_iterations(const IdpDims &D, const double *at, const uint8_
 {
     const unsigned nb = idp_blocks(D.G);
     const bool mg = W.nlev > 1;
-    // tiles of the blocked operator and the planes per item: about one item per block
-    const int ntx = (int)((D.nx + kTileX - 1) / kTileX), nty = (int)((D.ny + kTileY - 1) / kTileY);
-    const int64_t zl = (D.nz * ntx * nty + nb - 1) / nb;
-    const int zlen = (int)(zl < 1 ? 1 : (zl > D.nz ? D.nz : zl));
+    int ntx, nty, zlen;
+    stencil_items(D, nb, ntx, nty, zlen);
     for (int k = k0; k < k0 + count; ++k) {
-        k_cg_apply<<<nb, kIdpThreads, 0, st>>>(D, ntx, nty, zlen, W.lev[0].ac, W.d, W.w, W.part, W.state);
+        k_stencil_tiled<false><<<nb, kIdpThreads, 0, st>>>(D, ntx, nty, zlen, W.lev[0].ac, W.d, nullptr, nullptr,
+                                                            1.0, W.w, W.part, W.state);
         if (mg) {
             k_cg_update<false><<<nb, kIdpThreads, 0, st>>>(D, k, W.d, W.w, W.dinv, q, W.r, W.part, W.state);
             launch_vcycle(W, st);
