@@ -247,20 +247,22 @@ __global__ void __launch_bounds__(kIdpThreads) k_cg_start(int nb, const double *
     }
 }
 
-// Stencil passes blocked in 2.5D: SWEEP = false is iteration k, part 1:
-// w = L d and the partials of d.w in part[block]; SWEEP = true is the
-// multigrid post-sweep from the prolonged iterate (d = u): w = e = u + omega
-// D^-1 (b - A u) on fluid cells, b elsewhere, and the partials of b.e in
-// part[nblocks + block] when part is given.  The pass is blocked in 2.5D.  A block takes x-y tiles of kTileX x kTileY cells (each wave takes
-// kTileRows rows) and a run of zlen planes; it keeps its columns' coefficients and
-// values for planes z - 1, z, z + 1 in registers and the tile of plane z
-// with a one-cell halo in LDS, so that each operand is read from memory
-// about once instead of once per neighbour.  The next plane of the column
-// and the next halo are loaded one step ahead.  The face sum is
-// face_sum_ac's, term by term in the same order (cells outside the box hold
-// coefficient 0 and value 0).  Items (tile, run of planes) are dealt to the
-// blocks in turn; the block count is the other iteration kernels', whose
-// partial sums this kernel's must match.
+// Stencil passes blocked in 2.5D.
+//   SWEEP = false, iteration k, part 1: w = L d, the partials of d.w in
+//     part[block].
+//   SWEEP = true, the multigrid post-sweep from the prolonged iterate d = u:
+//     w = e = u + omega D^-1 (b - A u) on fluid cells, b elsewhere; the
+//     partials of b.e in part[nblocks + block] when part is given.
+// A block takes x-y tiles of kTileX x kTileY cells (each wave kTileRows rows)
+// and a run of zlen planes.  It keeps its columns' coefficients and values for
+// planes z - 1, z, z + 1 in registers and the tile of plane z with a one-cell
+// halo in LDS, so that each operand is read from memory about once instead of
+// once per neighbour; the next plane of each column and the next halo are
+// loaded one step ahead, within the run.  The face sum is face_sum_ac's, term
+// by term in the same order (cells outside the box hold coefficient 0 and
+// value 0).  Items (tile, run of planes) are dealt to the blocks; the block
+// count is the other iteration kernels', whose partial sums these kernels'
+// must match.
 constexpr double kOmega = 2.0 / 3.0;  // damping of the multigrid's Jacobi sweeps
 constexpr int kTileRows = 2;  // tile rows per wave (rows row and row + 4 of the tile)
 constexpr int kTileX = 64, kTileY = kIdpThreads / 64 * kTileRows;
