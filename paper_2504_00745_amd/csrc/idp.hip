@@ -248,11 +248,14 @@ __global__ void __launch_bounds__(kIdpThreads) k_cg_start(int nb, const double *
 }
 
 // Stencil passes blocked in 2.5D.
-//   SWEEP = false, iteration k, part 1: w = L d, the partials of d.w in
+//   MODE 0, iteration k, part 1: w = L d, the partials of d.w in
 //     part[block].
-//   SWEEP = true, the multigrid post-sweep from the prolonged iterate d = u:
+//   MODE 1, the multigrid post-sweep from the prolonged iterate d = u:
 //     w = e = u + omega D^-1 (b - A u) on fluid cells, b elsewhere; the
 //     partials of b.e in part[nblocks + block] when part is given.
+//   MODE 2, the residual after the pre-sweep from zero, e1 = omega D^-1 b
+//     (formed as each value is loaded): w = b - A e1 on fluid cells, 0
+//     elsewhere, for the restriction.
 // A block takes x-y tiles of kTileX x kTileY cells (each wave kTileRows rows)
 // and a run of zlen planes.  It keeps its columns' coefficients and values for
 // planes z - 1, z, z + 1 in registers and the tile of plane z with a one-cell
@@ -267,7 +270,7 @@ constexpr double kOmega = 2.0 / 3.0;  // damping of the multigrid's Jacobi sweep
 constexpr int kTileRows = 2;  // tile rows per wave (rows row and row + 4 of the tile)
 constexpr int kTileX = 64, kTileY = kIdpThreads / 64 * kTileRows;
 
-template <bool SWEEP>
+template <int MODE>
 __global__ void __launch_bounds__(kIdpThreads) k_stencil_tiled(IdpDims D, int ntx, int nty, int zlen,
                                                                const double *__restrict__ ac,
                                                                const double *__restrict__ d,
@@ -280,6 +283,8 @@ __global__ void __launch_bounds__(kIdpThreads) k_stencil_tiled(IdpDims D, int nt
     __shared__ double red[4];
     __shared__ double sa[kTileY + 2][kTileX + 2], sv[kTileY + 2][kTileX + 2];
     if (st->done >= 0) return;
+    // the value a cell contributes: d, or the pre-sweep iterate w D^-1 b of the residual pass
+    auto val = [&](int64_t n) { return MODE == 2 ? kOmega * dinv[n] * b[n] : d[n]; };
     const int lane = threadIdx.x & 63, row = threadIdx.x >> 6, t = threadIdx.x;
     const int64_t nx = D.nx, ny = D.ny, nz = D.nz;
     const int64_t tiles = (int64_t)ntx * nty, nzc = (nz + zlen - 1) / zlen, items = tiles * nzc;
@@ -318,29 +323,28 @@ __global__ void __launch_bounds__(kIdpThreads) k_stencil_tiled(IdpDims D, int nt
 #pragma unroll
         for (int q = 0; q < kTileRows; ++q) {
             am[q] = vm[q] = a0[q] = v0[q] = ap[q] = vp[q] = b0[q] = di0[q] = 0.0;
-            if (SWEEP && own[q]) { b0[q] = b[col[q] + z0 * D.sxy]; di0[q] = dinv[col[q] + z0 * D.sxy]; }
-            if (own[q] && z0 > 0) { am[q] = ac[col[q] + (z0 - 1) * D.sxy]; vm[q] = d[col[q] + (z0 - 1) * D.sxy]; }
-            if (own[q]) { a0[q] = ac[col[q] + z0 * D.sxy]; v0[q] = d[col[q] + z0 * D.sxy]; }
-            if (own[q] && z0 + 1 < nz) { ap[q] = ac[col[q] + (z0 + 1) * D.sxy]; vp[q] = d[col[q] + (z0 + 1) * D.sxy]; }
+            if (MODE != 0 && own[q]) b0[q] = b[col[q] + z0 * D.sxy];
+            if (MODE == 1 && own[q]) di0[q] = dinv[col[q] + z0 * D.sxy];
+            if (own[q] && z0 > 0) { am[q] = ac[col[q] + (z0 - 1) * D.sxy]; vm[q] = val(col[q] + (z0 - 1) * D.sxy); }
+            if (own[q]) { a0[q] = ac[col[q] + z0 * D.sxy]; v0[q] = val(col[q] + z0 * D.sxy); }
+            if (own[q] && z0 + 1 < nz) { ap[q] = ac[col[q] + (z0 + 1) * D.sxy]; vp[q] = val(col[q] + (z0 + 1) * D.sxy); }
         }
-        if (hown) { ha = ac[hcol + z0 * D.sxy]; hv = d[hcol + z0 * D.sxy]; }
+        if (hown) { ha = ac[hcol + z0 * D.sxy]; hv = val(hcol + z0 * D.sxy); }
         for (int64_t z = z0; z < z1; ++z) {
             // one step ahead: the columns' plane z + 2 and the halo of plane z + 1
             double a2[kTileRows], v2[kTileRows], b1[kTileRows], di1[kTileRows], ha1 = 0.0, hv1 = 0.0;
 #pragma unroll
             for (int q = 0; q < kTileRows; ++q) {
                 a2[q] = v2[q] = b1[q] = di1[q] = 0.0;
-                if (SWEEP && own[q] && z + 1 < z1) {
-                    b1[q] = b[col[q] + (z + 1) * D.sxy];
-                    di1[q] = dinv[col[q] + (z + 1) * D.sxy];
-                }
+                if (MODE != 0 && own[q] && z + 1 < z1) b1[q] = b[col[q] + (z + 1) * D.sxy];
+                if (MODE == 1 && own[q] && z + 1 < z1) di1[q] = dinv[col[q] + (z + 1) * D.sxy];
                 // plane z1 is the last one the run reads (the +z neighbour of its last plane)
                 if (own[q] && z + 2 <= z1 && z + 2 < nz) {
                     a2[q] = ac[col[q] + (z + 2) * D.sxy];
-                    v2[q] = d[col[q] + (z + 2) * D.sxy];
+                    v2[q] = val(col[q] + (z + 2) * D.sxy);
                 }
             }
-            if (hown && z + 1 < z1) { ha1 = ac[hcol + (z + 1) * D.sxy]; hv1 = d[hcol + (z + 1) * D.sxy]; }
+            if (hown && z + 1 < z1) { ha1 = ac[hcol + (z + 1) * D.sxy]; hv1 = val(hcol + (z + 1) * D.sxy); }
             __syncthreads();  // the previous plane's reads of the tile are done
 #pragma unroll
             for (int q = 0; q < kTileRows; ++q) {
@@ -362,7 +366,9 @@ __global__ void __launch_bounds__(kIdpThreads) k_stencil_tiled(IdpDims D, int nt
                     const double v = an[f] > 0.0 ? vn[f] : 0.0;
                     acc += beta * (v0[q] - v);
                 }
-                if (SWEEP) {
+                if (MODE == 2) {
+                    w[col[q] + z * D.sxy] = a0[q] > 0.0 ? b0[q] - scale * acc : 0.0;
+                } else if (MODE == 1) {
                     const double Au = scale * acc;
                     const double e = a0[q] > 0.0 ? v0[q] + kOmega * di0[q] * (b0[q] - Au) : b0[q];
                     w[col[q] + z * D.sxy] = e;
@@ -381,9 +387,9 @@ __global__ void __launch_bounds__(kIdpThreads) k_stencil_tiled(IdpDims D, int nt
             ha = ha1; hv = hv1;
         }
     }
-    if (!SWEEP || part) {
+    if (MODE == 0 || (MODE == 1 && part)) {
         dw = block_sum(dw, red);
-        if (threadIdx.x == 0) part[(SWEEP ? nb : 0) + blockIdx.x] = dw;
+        if (threadIdx.x == 0) part[(MODE == 1 ? nb : 0) + blockIdx.x] = dw;
     }
 }
 
@@ -569,7 +575,8 @@ __global__ void __launch_bounds__(kIdpThreads) k_mg_diag(MgLevel L)
 // residuals b - A e1.  Eight adjacent lanes take the eight children of one
 // coarse cell (lane bits: x, y, z offset) and add their residuals with three
 // butterfly shuffles, the same order in every group.
-__global__ void __launch_bounds__(kIdpThreads) k_mg_restrict(MgLevel F, MgLevel Cl, const CgState *__restrict__ st)
+__global__ void __launch_bounds__(kIdpThreads) k_mg_restrict(MgLevel F, MgLevel Cl, const double *__restrict__ r1,
+                                                            const CgState *__restrict__ st)
 {
     if (cg_done(st)) return;
     auto e1 = [&](int64_t n, int64_t, int64_t, int64_t) { return kOmega * F.dinv[n] * F.b[n]; };
@@ -585,7 +592,10 @@ __global__ void __launch_bounds__(kIdpThreads) k_mg_restrict(MgLevel F, MgLevel 
             const int64_t i = 2 * I + (ch & 1), j = 2 * J + ((ch >> 1) & 1), k = 2 * K + (ch >> 2);
             if (i < F.D.nx && j < F.D.ny && k < F.D.nz) {
                 const int64_t f = (k * F.D.ny + j) * F.D.nx + i;
-                if (F.ac[f] > 0.0) v = F.b[f] - F.scale * face_sum_ac(F.D, f, i, j, k, F.ac, e1);
+                if (r1)
+                    v = r1[f];  // the residual pass's value: zero off the fluid
+                else if (F.ac[f] > 0.0)
+                    v = F.b[f] - F.scale * face_sum_ac(F.D, f, i, j, k, F.ac, e1);
             }
         }
         v += __shfl_xor(v, 1);
@@ -765,9 +775,19 @@ static void stencil_items(const IdpDims &D, unsigned nb, int &ntx, int &nty, int
 static void launch_vcycle(const IdpWork &W, hipStream_t st)
 {
     const int L = W.nlev;
-    for (int l = 0; l + 1 < L; ++l)
-        k_mg_restrict<<<idp_blocks_full(8 * W.lev[l + 1].D.G), kIdpThreads, 0, st>>>(W.lev[l], W.lev[l + 1],
-                                                                                     W.state);
+    for (int l = 0; l + 1 < L; ++l) {
+        const MgLevel &F = W.lev[l];
+        const double *r1 = nullptr;
+        if (F.D.G >= kMgSplitCells) {  // the fine residual by the blocked pass, into t (free until prolongation)
+            const unsigned nb = idp_blocks(F.D.G);
+            int ntx, nty, zlen;
+            stencil_items(F.D, nb, ntx, nty, zlen);
+            k_stencil_tiled<2><<<nb, kIdpThreads, 0, st>>>(F.D, ntx, nty, zlen, F.ac, nullptr, F.b, F.dinv, F.scale,
+                                                           F.t, nullptr, W.state);
+            r1 = F.t;
+        }
+        k_mg_restrict<<<idp_blocks_full(8 * W.lev[l + 1].D.G), kIdpThreads, 0, st>>>(F, W.lev[l + 1], r1, W.state);
+    }
     k_mg_coarsest<<<1, kIdpThreads, 0, st>>>(W.lev[L - 1], W.state);
     for (int l = L - 2; l >= 0; --l) {
         const unsigned nb = idp_blocks(W.lev[l].D.G);
@@ -777,7 +797,7 @@ static void launch_vcycle(const IdpWork &W, hipStream_t st)
             const MgLevel &F = W.lev[l];
             int ntx, nty, zlen;
             stencil_items(F.D, nb, ntx, nty, zlen);
-            k_stencil_tiled<true><<<nb, kIdpThreads, 0, st>>>(F.D, ntx, nty, zlen, F.ac, F.t, F.b, F.dinv, F.scale,
+            k_stencil_tiled<1><<<nb, kIdpThreads, 0, st>>>(F.D, ntx, nty, zlen, F.ac, F.t, F.b, F.dinv, F.scale,
                                                                F.e, part, W.state);
         } else {
             k_mg_post<<<nb, kIdpThreads, 0, st>>>(W.lev[l], W.lev[l + 1], part, W.state);
@@ -811,7 +831,7 @@ hipError_t launch_cg_iterations(const IdpDims &D, const double *at, const uint8_
     int ntx, nty, zlen;
     stencil_items(D, nb, ntx, nty, zlen);
     for (int k = k0; k < k0 + count; ++k) {
-        k_stencil_tiled<false><<<nb, kIdpThreads, 0, st>>>(D, ntx, nty, zlen, W.lev[0].ac, W.d, nullptr, nullptr,
+        k_stencil_tiled<0><<<nb, kIdpThreads, 0, st>>>(D, ntx, nty, zlen, W.lev[0].ac, W.d, nullptr, nullptr,
                                                             1.0, W.w, W.part, W.state);
         if (mg) {
             k_cg_update<false><<<nb, kIdpThreads, 0, st>>>(D, k, W.d, W.w, W.dinv, q, W.r, W.part, W.state);
