@@ -605,6 +605,33 @@ __global__ void __launch_bounds__(kIdpThreads) k_mg_restrict(MgLevel F, MgLevel 
     }
 }
 
+// Restriction of stored residuals r1 (zero off the fluid): one thread per
+// coarse cell adds its eight children in the order of k_mg_restrict's
+// butterfly, ((c0 + c1) + (c2 + c3)) + ((c4 + c5) + (c6 + c7)) with child
+// bits (x, y, z), so the coarse right-hand side is the same bit for bit.
+__global__ void __launch_bounds__(kIdpThreads) k_mg_restrict_sum(MgLevel F, MgLevel Cl,
+                                                                const double *__restrict__ r1,
+                                                                const CgState *__restrict__ st)
+{
+    if (cg_done(st)) return;
+    for (int64_t C = (int64_t)blockIdx.x * kIdpThreads + threadIdx.x; C < Cl.D.G;
+         C += (int64_t)gridDim.x * kIdpThreads) {
+        double v = 0.0;
+        if (Cl.ac[C] > 0.0) {
+            int64_t I, J, K;
+            coords(Cl.D, C, I, J, K);
+            double c[8];
+#pragma unroll
+            for (int ch = 0; ch < 8; ++ch) {
+                const int64_t i = 2 * I + (ch & 1), j = 2 * J + ((ch >> 1) & 1), k = 2 * K + (ch >> 2);
+                c[ch] = i < F.D.nx && j < F.D.ny && k < F.D.nz ? r1[(k * F.D.ny + j) * F.D.nx + i] : 0.0;
+            }
+            v = ((c[0] + c[1]) + (c[2] + c[3])) + ((c[4] + c[5]) + (c[6] + c[7]));
+        }
+        Cl.b[C] = v;
+    }
+}
+
 // Coarse correction alone: u = e1 + P E on fluid cells (0 elsewhere) into t,
 // for the larger levels, where the post-sweep then reads u once per
 // neighbour.
@@ -786,7 +813,12 @@ static void launch_vcycle(const IdpWork &W, hipStream_t st)
                                                            F.t, nullptr, W.state);
             r1 = F.t;
         }
-        k_mg_restrict<<<idp_blocks_full(8 * W.lev[l + 1].D.G), kIdpThreads, 0, st>>>(F, W.lev[l + 1], r1, W.state);
+        if (r1)
+            k_mg_restrict_sum<<<idp_blocks_full(W.lev[l + 1].D.G), kIdpThreads, 0, st>>>(F, W.lev[l + 1], r1,
+                                                                                      W.state);
+        else
+            k_mg_restrict<<<idp_blocks_full(8 * W.lev[l + 1].D.G), kIdpThreads, 0, st>>>(F, W.lev[l + 1], nullptr,
+                                                                                         W.state);
     }
     k_mg_coarsest<<<1, kIdpThreads, 0, st>>>(W.lev[L - 1], W.state);
     for (int l = L - 2; l >= 0; --l) {
