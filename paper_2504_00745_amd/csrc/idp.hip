@@ -510,8 +510,9 @@ __global__ void __launch_bounds__(kIdpThreads) k_idp_faces(IdpDims D, double dx,
 // children) and R = P^T (the sum of the fluid children's residuals).
 // Smoothing: one damped Jacobi sweep (omega = 2/3) before and one after the
 // coarse correction; the pre-sweep from zero, w D^-1 b, is formed on the fly
-// where it is used, so a level costs two passes (restriction, correction and
-// post-sweep).  The coarsest level (at most 256 cells) takes 48 sweeps in
+// where it is used.  A small level costs two passes (restriction; correction
+// and post-sweep); a level of at least kMgSplitCells cells four (residual into
+// t, restriction of t, prolongation into t, post-sweep).  The coarsest level (at most 256 cells) takes 48 sweeps in
 // LDS.  Equal pre- and post-sweeps and R = P^T keep the preconditioner
 // symmetric.  Non-fluid rows of the finest level are identity rows and get
 // z = r.  Levels carry the signed coefficients (see face_sum_ac).
