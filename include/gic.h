@@ -118,6 +118,12 @@ typedef enum { GIC_FP64 = 0, GIC_FP32 = 1 } gic_precision;
  *   sr_peak       moisture ratio where the moisture curve Gamma peaks (the
  *                 maximum absorption ratio of Sec. 5.3), in (0, 1).
  *                 With sigma > 0, cell >= 2 r_max + d_r(r_max) is required.
+ * Absorbed water, Sec. 5.3:
+ *   absorb_max    the maximum absorption ratio r_max of Sec. 5.3 (held water
+ *                 per unit granule volume), >= 0 (0: dry).  Held water fills
+ *                 part of the voids, so every clamp of alpha_s (G2P, the
+ *                 density projection's target) is alpha_max (1 + absorb_max),
+ *                 the 0.740 (1 + r_max) of Sec. 5.3.
  * The adjoint form (the *_vjp calls) covers drag_model 0 without virtual
  * mass and returns GIC_E_ARG otherwise. */
 typedef struct gic_params {
@@ -142,6 +148,7 @@ typedef struct gic_params {
     double sigma;
     double vbridge;
     double sr_peak;
+    double absorb_max;
 } gic_params;
 
 typedef struct gic_ctx gic_ctx;
@@ -318,10 +325,11 @@ gic_status gic_integrate_p2g(gic_ctx *ctx, int64_t n, double *x, double *v, cons
 /* gic_integrate_p2g for wet granules (Sec. 5.3, Eq. 19): held (n double,
  * sorted order, required for n > 0) is the water each granule holds per unit
  * of its volume; the integrator uses the mass V (rho_s + held rho_f) (with
- * virtual mass: that mass plus rho_f V / 2, gravity on the wet mass) and
- * the momentum channels deposit (frac + frac held rho_f / rho_s) v; the
- * fraction channel stays the sand's own volume.  The exchange deposit
- * (gic_exchange_p2g) keeps the dry mass. */
+ * virtual mass: that mass plus rho_f V (1 + held) / 2, gravity on the wet
+ * mass), the fraction channel deposits frac (1 + held) (the absorbed water
+ * counts as volume in alpha_s, Sec. 5.3) and the momentum channels
+ * (frac + frac held rho_f / rho_s) v.  held = 0 gives gic_integrate_p2g's
+ * bits. */
 gic_status gic_integrate_p2g_wet(gic_ctx *ctx, int64_t n, double *x, double *v, const double *r, const double *held,
                                  const void *f_contact, const void *f_drag, const int32_t *cell_begin,
                                  const int32_t *cell_end, int64_t *alpha_fx, int64_t *mom_fx, int32_t accumulate,
@@ -355,12 +363,16 @@ gic_status gic_step(gic_ctx *ctx, int64_t n, const double *x_cur, const double *
  * acceleration dv_f/dt of the grid, Eq. 12), V = 4/3 pi r^3.  grad_p and
  * acc_f may be NULL (no such term).  The a_s part of the virtual-mass force
  * is the effective mass of the integrator (gic_integrate_p2g with vmass).
- * The _out arrays must not alias the inputs. */
+ * held, held_out (n double each, both or neither): wet granules (Sec. 5.3):
+ * held (input order) is the water each granule holds per unit of its
+ * volume and counts as volume, V = 4/3 pi r^3 (1 + held), in -V grad p and
+ * the virtual mass (the drag keeps the granule's radius); it is written in
+ * sorted order to held_out.  The _out arrays must not alias the inputs. */
 gic_status gic_gather_g2p_fluid(gic_ctx *ctx, int64_t n, const int32_t *order, const double *x, const double *v,
                                 const double *r, const int32_t *id, double *x_out, double *v_out, double *r_out,
                                 int32_t *id_out, const void *u, const int64_t *alpha_fx, const void *grad_p,
                                 const void *acc_f, const int32_t *cell_begin, const int32_t *cell_end,
-                                void *f_fluid, void *stream);
+                                void *f_fluid, const double *held, double *held_out, void *stream);
 
 /* Exchange momentum of one sub-step (Sec. 5.2): adds -weight f_j N(x_j - x)
  * to fs_fx (3 x G int64, x-plane then y and z, units of 2^-32
@@ -370,11 +382,13 @@ gic_status gic_gather_g2p_fluid(gic_ctx *ctx, int64_t n, const int32_t *order, c
  * component the deposit totals rint(S), S = (-weight / f_unit) f 2^32, the 26
  * outer nodes taking rint(w S) and the centre the rest (integer, so bit-exact
  * in any order).  x, r, f_contact, f_fluid in the sorted order of
- * cell_begin, cell_end (positions before the move).  GIC_E_ARG if
- * params.f_unit <= 0.  Latches GIC_E_RANGE for |S| >= 2^51. */
+ * cell_begin, cell_end (positions before the move).  held (n double,
+ * sorted order, or NULL): wet granules take the wet mass V (rho_s + held
+ * rho_f) and the volume V (1 + held) in a_s and the virtual mass (Sec. 5.3).
+ * GIC_E_ARG if params.f_unit <= 0.  Latches GIC_E_RANGE for |S| >= 2^51. */
 gic_status gic_exchange_p2g(gic_ctx *ctx, int64_t n, const double *x, const double *r, const void *f_contact,
                             const void *f_fluid, const int32_t *cell_begin, const int32_t *cell_end, double weight,
-                            int64_t *fs_fx, void *stream);
+                            int64_t *fs_fx, const double *held, void *stream);
 
 /* One sand step (Alg. 2) of length Dt: N = ceil(Dt / params.dt) equal
  * sub-steps of Dt / N with the fluid fields u, grad_p, acc_f frozen, each
@@ -468,7 +482,7 @@ gic_status gic_permute(gic_ctx *ctx, int64_t n, int32_t comps, const int32_t *or
  * A label outside 0..2 (setup, solve) or alpha_t not in (0, inf) on a fluid
  * or air cell (solve) latches GIC_E_RANGE with the cell's index.
  *
- * gic_idp_setup: alpha_t = 1 - min(alpha_fx 2^-32, alpha_max) (the target
+ * gic_idp_setup: alpha_t = 1 - min(alpha_fx 2^-32, alpha_max (1 + absorb_max)) (the target
  * fraction from the P2G grid, G int64) and rhs (the right-hand side above,
  * zero off the fluid) from alpha_star (G, the fluid particles' own fraction,
  * Eq. 7b: an input) and label.  Asynchronous. */

@@ -24,6 +24,7 @@ class OrcParams(C.Structure):
         ("kn", C.c_double), ("restitution", C.c_double), ("kt_ratio", C.c_double), ("mu", C.c_double),
         ("rho_s", C.c_double), ("eta_f", C.c_double), ("c_drag", C.c_double), ("alpha_max", C.c_double),
         ("g", C.c_double * 3), ("dt", C.c_double), ("walls", C.c_uint32), ("pad", C.c_int32),
+        ("absorb_max", C.c_double),
     ]
 
 
@@ -38,6 +39,8 @@ def params(cfg: dict) -> OrcParams:
         setattr(p, k, float(cfg[k]))
     p.g = (C.c_double * 3)(*cfg["g"])
     p.walls = int(cfg["walls"])
+    # maximum absorption ratio of Sec. 5.3: raises the alpha_s clamp (0: dry)
+    p.absorb_max = float(cfg.get("absorb_max", 0.0))
     return p
 
 
@@ -118,10 +121,10 @@ def _declare(L):
         "orc_p2g_vjp": (None, [_pp, C.c_int64, _d, _d, _d, _d, _d, _d, _d]),
         "orc_rollout": (C.c_double, [_pp, C.c_int64, _d, _d, _d, _d, C.c_int32, _d, _P(C.c_uint64)]),
         "orc_rollout_vjp": (C.c_double, [_pp, C.c_int64, _d, _d, _d, _d, C.c_int32, _d, _d, _d]),
-        "orc_fluid_forces": (None, [_pp, _pc, C.c_int64, _d, _d, _d, _d, _i64, _d, _d, _d]),
+        "orc_fluid_forces": (None, [_pp, _pc, C.c_int64, _d, _d, _d, _d, _d, _i64, _d, _d, _d]),
         "orc_integrate_vm": (None, [_pp, _pc, C.c_int64, _d, _d, _d, _d, _d]),
-        "orc_exchange_force": (None, [_pp, _pc, C.c_int64, _d, _d, _d, _d]),
-        "orc_exchange_p2g": (None, [_pp, _pc, C.c_int64, _d, _d, _d, _d, C.c_double, _i64]),
+        "orc_exchange_force": (None, [_pp, _pc, C.c_int64, _d, _d, _d, _d, _d]),
+        "orc_exchange_p2g": (None, [_pp, _pc, C.c_int64, _d, _d, _d, _d, _d, C.c_double, _i64]),
         "orc_substeps": (C.c_int32, [C.c_double, C.c_double]),
         "orc_sand_step": (C.c_int32, [_pp, _pc, C.c_int64, C.c_double, _d, _d, _d, _d, _d, _d, _i64, _i64, _i64]),
         "orc_gamma": (C.c_double, [_pk, C.c_double]),
@@ -129,7 +132,7 @@ def _declare(L):
         "orc_wet_mass": (None, [_pp, C.c_double, C.c_int64, _d, _d, _d]),
         "orc_contact_forces_wet": (None, [_pp, C.c_int64, _d, _d, _d, _d, _d, _d, _P(C.c_int32)]),
         "orc_contact_forces_sample_wet": (None, [_pp, C.c_int64, _d, _d, _d, _d, C.c_int64, _i64, _d, _d]),
-        "orc_integrate_wet": (None, [_pp, _pc, C.c_int64, _d, _d, _d, _d, _d, _d]),
+        "orc_integrate_wet": (None, [_pp, _pc, C.c_int64, _d, _d, _d, _d, _d, _d, _d]),
         "orc_p2g_fixed_wet": (None, [_pp, C.c_double, C.c_int64, _d, _d, _d, _d, _i64, _i64]),
         "orc_bridge": (None, [_pk, C.c_double, _d, _d]),
         "orc_bridge_energy": (C.c_double, [_pk, C.c_double, C.c_double]),
@@ -369,11 +372,14 @@ def step(cfg, x, v, r, u, alpha_fx):
 # ---- remaining interphase forces (Sec. 3.3 Eq. 5a-5c, Sec. 5.2 Eq. 9) and the
 # ---- full sand step with the exchange momentum (Alg. 2, Sec. 5.2) -----------
 
-def fluid_forces(cfg, x, v, r, u, alpha_fx, gp=None, af=None):
+def fluid_forces(cfg, x, v, r, u, alpha_fx, gp=None, af=None, held=None):
     """Fluid force on each granule (3,n): drag (cfg drag_model: 0 linear Stokes
     form x alpha_f, 1 quadratic Eq. 5b) + pressure gradient -V grad p (if gp)
-    + (1/2) rho_f V dv_f/dt (if vmass and af); gp, af are (3,G) grid fields."""
+    + (1/2) rho_f V dv_f/dt (if vmass and af); gp, af are (3,G) grid fields.
+    held (n,): absorbed water per granule volume, extra volume V held in the
+    volume forces (Sec. 5.3); None for dry granules."""
     x, v, r, u = _f64(x), _f64(v), _f64(r), _f64(u)
+    held = None if held is None else _f64(held)
     n = x.shape[1]
     Ffl = np.zeros((3, n))
     afx = np.ascontiguousarray(alpha_fx, np.int64)
@@ -381,8 +387,8 @@ def fluid_forces(cfg, x, v, r, u, alpha_fx, gp=None, af=None):
     af = None if af is None else _f64(af)
     p, c = params(cfg), coupling(cfg)
     lib().orc_fluid_forces(C.byref(p), C.byref(c), n, _ptr(x, C.c_double), _ptr(v, C.c_double),
-                           _ptr(r, C.c_double), _ptr(u, C.c_double), _ptr(afx, C.c_int64), _ptr(gp, C.c_double),
-                           _ptr(af, C.c_double), _ptr(Ffl, C.c_double))
+                           _ptr(r, C.c_double), _ptr(held, C.c_double), _ptr(u, C.c_double), _ptr(afx, C.c_int64),
+                           _ptr(gp, C.c_double), _ptr(af, C.c_double), _ptr(Ffl, C.c_double))
     return Ffl
 
 
@@ -398,25 +404,29 @@ def integrate_vm(cfg, r, Fc, Ffl, x, v):
     return x, v
 
 
-def exchange_force(cfg, r, Fc, Ffl):
-    """Whole fluid force of a sub-step on each granule (3,n)."""
+def exchange_force(cfg, r, Fc, Ffl, held=None):
+    """Whole fluid force of a sub-step on each granule (3,n); held: wet
+    granules (wet mass and volume, Sec. 5.3) or None."""
     r, Fc, Ffl = _f64(r), _f64(Fc), _f64(Ffl)
+    held = None if held is None else _f64(held)
     fex = np.zeros_like(Ffl)
     p, c = params(cfg), coupling(cfg)
-    lib().orc_exchange_force(C.byref(p), C.byref(c), r.shape[0], _ptr(r, C.c_double), _ptr(Fc, C.c_double),
-                             _ptr(Ffl, C.c_double), _ptr(fex, C.c_double))
+    lib().orc_exchange_force(C.byref(p), C.byref(c), r.shape[0], _ptr(r, C.c_double), _ptr(held, C.c_double),
+                             _ptr(Fc, C.c_double), _ptr(Ffl, C.c_double), _ptr(fex, C.c_double))
     return fex
 
 
-def exchange_p2g(cfg, x, r, Fc, Ffl, weight, fs=None):
+def exchange_p2g(cfg, x, r, Fc, Ffl, weight, fs=None, held=None):
     """Exchange deposit of one sub-step: fs (3,G) int64 in 2^-32 f_unit units
     accumulates -weight * f_j N(x_j - x)."""
     x, r, Fc, Ffl = _f64(x), _f64(r), _f64(Fc), _f64(Ffl)
+    held = None if held is None else _f64(held)
     G = nodes(cfg)
     fs = np.zeros((3, G), np.int64) if fs is None else np.ascontiguousarray(fs, np.int64).copy()
     p, c = params(cfg), coupling(cfg)
     lib().orc_exchange_p2g(C.byref(p), C.byref(c), x.shape[1], _ptr(x, C.c_double), _ptr(r, C.c_double),
-                           _ptr(Fc, C.c_double), _ptr(Ffl, C.c_double), float(weight), _ptr(fs, C.c_int64))
+                           _ptr(held, C.c_double), _ptr(Fc, C.c_double), _ptr(Ffl, C.c_double), float(weight),
+                           _ptr(fs, C.c_int64))
     return fs
 
 
@@ -615,18 +625,22 @@ def contact_forces_sample_wet(cfg, x, v, r, m, idx):
     return F, fa
 
 
-def integrate_wet(cfg, r, m, Fc, Fd, x, v):
-    """(x, v) advanced with per-granule masses (virtual mass per cfg)."""
+def integrate_wet(cfg, r, m, Fc, Fd, x, v, held=None):
+    """(x, v) advanced with per-granule masses (virtual mass per cfg, with the
+    volume V (1 + held) when held is given, Sec. 5.3)."""
     r, m, Fc, Fd = _f64(r), _f64(m), _f64(Fc), _f64(Fd)
+    held = None if held is None else _f64(held)
     x, v = np.array(x, np.float64, order="C", copy=True), np.array(v, np.float64, order="C", copy=True)
     lib().orc_integrate_wet(C.byref(params(cfg)), C.byref(coupling(cfg)), r.shape[0], _ptr(r, C.c_double),
-                            _ptr(m, C.c_double), _ptr(Fc, C.c_double), _ptr(Fd, C.c_double), _ptr(x, C.c_double),
-                            _ptr(v, C.c_double))
+                            _ptr(held, C.c_double), _ptr(m, C.c_double), _ptr(Fc, C.c_double), _ptr(Fd, C.c_double),
+                            _ptr(x, C.c_double), _ptr(v, C.c_double))
     return x, v
 
 
 def p2g_fixed_wet(cfg, x, v, r, held):
-    """(alpha (G,), mom (3, G)) with the wet granules' momentum."""
+    """(alpha (G,), mom (3, G)) of wet granules (Sec. 5.3): the fraction
+    channel counts the held water's volume, frac (1 + held), and the momentum
+    channels the wet mass."""
     x, v, r, held = _f64(x), _f64(v), _f64(r), _f64(held)
     G = nodes(cfg)
     a = np.zeros(G, np.int64)

@@ -29,10 +29,13 @@ import numpy as np
 FLUID, AIR, SOLID = 0, 1, 2
 
 
-def target_fraction(alpha_fx, alpha_max):
-    """alpha_f' = 1 - min(alpha * 2^-32, alpha_max) from the int64 P2G grid
-    (Eq. 7a in 2^-32 cell volumes; the densest-packing clamp of Sec. 5.1)."""
-    a_s = np.minimum(np.asarray(alpha_fx, np.int64).astype(np.float64) * 2.0 ** -32, alpha_max)
+def target_fraction(alpha_fx, alpha_max, absorb_max=0.0):
+    """alpha_f' = 1 - min(alpha * 2^-32, alpha_max (1 + absorb_max)) from the
+    int64 P2G grid (Eq. 7a in 2^-32 cell volumes; the densest-packing clamp
+    of Sec. 5.1, raised by the maximum absorption ratio of Sec. 5.3 when the
+    granules hold water: the water fills part of the voids)."""
+    amax = alpha_max * (1.0 + absorb_max)
+    a_s = np.minimum(np.asarray(alpha_fx, np.int64).astype(np.float64) * 2.0 ** -32, amax)
     return 1.0 - a_s
 
 
@@ -148,10 +151,10 @@ def displacement(q, label, dx):
     return tuple(out)
 
 
-def projection(alpha_fx, alpha_max, alpha_star, label, dx):
+def projection(alpha_fx, alpha_max, alpha_star, label, dx, absorb_max=0.0):
     """The whole density projection: target fraction, right-hand side,
     direct solve and face displacements.  Returns (alpha_t, s, q, faces)."""
-    alpha_t = target_fraction(alpha_fx, alpha_max)
+    alpha_t = target_fraction(alpha_fx, alpha_max, absorb_max)
     s = rhs(alpha_t, alpha_star, label)
     q = solve(alpha_t, label, s)
     return alpha_t, s, q, displacement(q, label, dx)

@@ -83,6 +83,7 @@ typedef struct {
     double dt;          /* step [s]                                         */
     uint32_t walls;     /* bit 2a: low face of axis a, bit 2a+1: high face  */
     int32_t pad;
+    double absorb_max;  /* maximum absorption ratio r_max of Sec. 5.3 (0: dry) */
 } orc_params;
 
 /* ------------------------------------------------------------------------ */
@@ -101,6 +102,19 @@ static double orc_volume(double r)
 }
 
 /* Damping ratio of the linear spring-dashpot that gives restitution e. */
+/* Volume of a granule with its absorbed water (Sec. 5.3): V (1 + held),
+ * written so that held = 0 gives V exactly. */
+static double orc_wet_volume(double r, double held)
+{
+    double V = orc_volume(r);
+    return held != 0.0 ? V + V * held : V;
+}
+
+/* Clamp of alpha_s (Sec. 5.1), raised to 0.740 (1 + r_max) when granules
+ * absorb water (Sec. 5.3): the held water fills part of the voids, so the
+ * densest packing of wet granules holds more than the sand's own volume. */
+static double orc_alpha_clamp(const orc_params *p) { return p->alpha_max * (1.0 + p->absorb_max); }
+
 static double orc_zeta(double e)
 {
     double le = log(e);
@@ -567,11 +581,14 @@ static void orc_p2g_fixed_held(const orc_params *p, double rho_0, int64_t n, con
         orc_stencil s;
         orc_stencil_of(p, inv_dx, xa, &s);
         double frac = orc_volume(r[i]) * inv_vcell;
+        /* a wet granule's absorbed water counts as extra volume in alpha_s
+         * (Sec. 5.3): frac (1 + held) = frac + frac held (held = 0: frac) */
+        double fa = held ? frac + frac * held[i] : frac;
         /* momentum in rho_s dx^3 units: a wet granule carries m_wet / (rho_s dx^3)
          * = frac (rho_s + held rho_0) / rho_s = frac + frac held rho_0 / rho_s
          * per unit velocity (Eq. 19), written so that held = 0 gives frac exactly */
         double fm = held ? frac + (frac * (held[i] * rho_0)) / p->rho_s : frac;
-        double S[4] = {frac * ORC_TWO32, (fm * v[i]) * ORC_TWO32, (fm * v[n + i]) * ORC_TWO32,
+        double S[4] = {fa * ORC_TWO32, (fm * v[i]) * ORC_TWO32, (fm * v[n + i]) * ORC_TWO32,
                        (fm * v[2 * n + i]) * ORC_TWO32};
         for (int ch = 0; ch < 4; ++ch) {
             int64_t Q = llrint(S[ch]);
@@ -628,13 +645,15 @@ void orc_p2g_real(const orc_params *p, int64_t n, const double *x, const double 
 /* G2P of fluid velocity and volume fraction (Sec. 5.2; Sec. 5.1 clamp)       */
 /* ------------------------------------------------------------------------ */
 
-/* u_at (3n) = sum_k w u_k; alpha_f (n) = 1 - sum_k w min(alpha_k, alpha_max).
+/* u_at (3n) = sum_k w u_k; alpha_f (n) = 1 - sum_k w min(alpha_k, amax), amax
+ * the clamp of orc_alpha_clamp.
  * The alpha grid is either fixed point (alpha_fx, 2^-32 units) or real
  * (alpha_real, cell volumes); exactly one is non-NULL. */
 void orc_g2p(const orc_params *p, int64_t n, const double *x, const double *u, const int64_t *alpha_fx,
              const double *alpha_real, double *u_at, double *alpha_f)
 {
     double inv_dx = 1.0 / p->dx;
+    double amax = orc_alpha_clamp(p);
     int64_t G = orc_nodes(p);
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
@@ -650,7 +669,7 @@ void orc_g2p(const orc_params *p, int64_t n, const double *x, const double *u, c
                     int64_t k = orc_node_index(p, &s, a, b, c);
                     for (int d = 0; d < 3; ++d) acc[d] += w * u[d * G + k];
                     double al = alpha_fx ? (double)alpha_fx[k] * ORC_TWOM32 : alpha_real[k];
-                    if (al > p->alpha_max) al = p->alpha_max;
+                    if (al > amax) al = amax;
                     as += w * al;
                 }
         for (int d = 0; d < 3; ++d) u_at[d * n + i] = acc[d];
@@ -917,8 +936,8 @@ void orc_g2p_vjp(const orc_params *p, int64_t n, const double *x, const double *
                     double gw[3] = {(s.dw[0][a] * s.w[1][b]) * s.w[2][c], (s.w[0][a] * s.dw[1][b]) * s.w[2][c],
                                     (s.w[0][a] * s.w[1][b]) * s.dw[2][c]};
                     double ul = (u[k] * guat[i] + u[G + k] * guat[n + i]) + u[2 * G + k] * guat[2 * n + i];
-                    int clamped = !(alpha[k] < p->alpha_max);
-                    double al = clamped ? p->alpha_max : alpha[k];
+                    int clamped = !(alpha[k] < orc_alpha_clamp(p));
+                    double al = clamped ? orc_alpha_clamp(p) : alpha[k];
                     /* alpha_f = 1 - sum w al */
                     double coef = ul - al * gaf[i];
                     for (int d = 0; d < 3; ++d) gx[d * n + i] += gw[d] * coef;
@@ -982,7 +1001,7 @@ static void orc_clamp_counts(const orc_params *p, int64_t n, const double *x, co
         int32_t c_ = 0;
         for (int c = 0; c < 3; ++c)
             for (int b = 0; b < 3; ++b)
-                for (int a = 0; a < 3; ++a) c_ += !(alpha[orc_node_index(p, &s, a, b, c)] < p->alpha_max);
+                for (int a = 0; a < 3; ++a) c_ += !(alpha[orc_node_index(p, &s, a, b, c)] < orc_alpha_clamp(p));
         cnt[i] = c_;
     }
 }
@@ -1164,10 +1183,13 @@ static void orc_g2p_vec(const orc_params *p, int64_t n, const double *x, const d
 /* Fluid force on each granule (3n): drag (linear or quadratic) + pressure
  * gradient (if gp) + the explicit virtual-mass term (1/2) rho_f V a_f (if
  * vmass and af).  u, gp, af are 3G grid fields; alpha_fx the fixed-point
- * solid fraction grid (P2G at x). */
+ * solid fraction grid (P2G at x).  held (n, or NULL for dry granules): the
+ * water a granule holds per unit of its volume, which counts as extra volume
+ * in the volume forces (Sec. 5.3): V = (4/3) pi r^3 (1 + held); the drag
+ * keeps the granule's radius, which the water does not change. */
 void orc_fluid_forces(const orc_params *p, const orc_coupling *cp, int64_t n, const double *x, const double *v,
-                      const double *r, const double *u, const int64_t *alpha_fx, const double *gp,
-                      const double *af, double *Ffl)
+                      const double *r, const double *held, const double *u, const int64_t *alpha_fx,
+                      const double *gp, const double *af, double *Ffl)
 {
     double *uat = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
     double *alf = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
@@ -1190,7 +1212,7 @@ void orc_fluid_forces(const orc_params *p, const orc_coupling *cp, int64_t n, co
     }
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
-        double V = orc_volume(r[i]);
+        double V = orc_wet_volume(r[i], held ? held[i] : 0.0);
         double hv = (0.5 * cp->rho_f) * V;
         for (int d = 0; d < 3; ++d) {
             double f = Ffl[d * n + i];
@@ -1229,14 +1251,17 @@ void orc_integrate_vm(const orc_params *p, const orc_coupling *cp, int64_t n, co
 
 /* Whole fluid force of the sub-step on each granule (the f_j^i of the
  * exchange): Ffl minus (1/2) rho_f V a_s under virtual mass, where
- * a_s = ((Fc + Ffl) + m g) / (m + (1/2) rho_f V); Ffl otherwise. */
-void orc_exchange_force(const orc_params *p, const orc_coupling *cp, int64_t n, const double *r, const double *Fc,
-                        const double *Ffl, double *fex)
+ * a_s = ((Fc + Ffl) + m g) / (m + (1/2) rho_f V); Ffl otherwise.  held (n,
+ * or NULL): wet granules (Sec. 5.3) take the wet mass V (rho_s + held rho_f)
+ * of Eq. 19 and the volume V (1 + held). */
+void orc_exchange_force(const orc_params *p, const orc_coupling *cp, int64_t n, const double *r,
+                        const double *held, const double *Fc, const double *Ffl, double *fex)
 {
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
-        double m = orc_mass(p, r[i]);
-        double hv = (0.5 * cp->rho_f) * orc_volume(r[i]);
+        double h = held ? held[i] : 0.0;
+        double m = held ? orc_volume(r[i]) * (p->rho_s + h * cp->rho_f) : orc_mass(p, r[i]);
+        double hv = (0.5 * cp->rho_f) * orc_wet_volume(r[i], h);
         double me = m + hv;
         for (int d = 0; d < 3; ++d) {
             double f = Ffl[d * n + i];
@@ -1254,12 +1279,12 @@ void orc_exchange_force(const orc_params *p, const orc_coupling *cp, int64_t n, 
  * is Q = rint(S), S = (s f) * 2^32 with s = -weight / f_unit; the 26 outer
  * nodes take rint(w S), the centre node Q minus their sum. */
 void orc_exchange_p2g(const orc_params *p, const orc_coupling *cp, int64_t n, const double *x, const double *r,
-                      const double *Fc, const double *Ffl, double weight, int64_t *fs)
+                      const double *held, const double *Fc, const double *Ffl, double weight, int64_t *fs)
 {
     double inv_dx = 1.0 / p->dx;
     int64_t G = orc_nodes(p);
     double *fex = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
-    orc_exchange_force(p, cp, n, r, Fc, Ffl, fex);
+    orc_exchange_force(p, cp, n, r, held, Fc, Ffl, fex);
     double sc = -weight / cp->f_unit;
     for (int64_t i = 0; i < n; ++i) {
         double xa[3];
@@ -1312,9 +1337,9 @@ int32_t orc_sand_step(const orc_params *p, const orc_coupling *cp, int64_t n, do
     double *Fc = (double *)malloc(n3);
     double *Ffl = (double *)malloc(n3);
     for (int32_t i = 0; i < N; ++i) {
-        orc_fluid_forces(&ps, cp, n, x, v, r, u, alpha_fx, gp, af, Ffl);
+        orc_fluid_forces(&ps, cp, n, x, v, r, NULL, u, alpha_fx, gp, af, Ffl);
         orc_contact_forces(&ps, n, x, v, r, Fc, NULL, NULL, NULL);
-        if (fs) orc_exchange_p2g(&ps, cp, n, x, r, Fc, Ffl, weight, fs);
+        if (fs) orc_exchange_p2g(&ps, cp, n, x, r, NULL, Fc, Ffl, weight, fs);
         orc_integrate_vm(&ps, cp, n, r, Fc, Ffl, x, v);
         memset(alpha_fx, 0, sizeof(int64_t) * (size_t)G);
         memset(mom_fx, 0, sizeof(int64_t) * 3 * (size_t)G);
@@ -1502,7 +1527,12 @@ void orc_capillary_forces(const orc_params *p, const orc_capillary *c, int64_t n
 /* A granule holding water of held times its own volume has the mass
  * m = V (rho_s + held rho_0), rho_0 the fluid density.  The wet forms below
  * take per-granule masses where the dry ones use rho_s V: the contact's
- * effective mass (damping), the integrator, the momentum deposit. */
+ * effective mass (damping), the integrator, the momentum deposit.  The held
+ * water also counts as volume V held where the fluid sees the granule
+ * (Sec. 5.3): in the solid fraction alpha_s that P2G deposits, in the volume
+ * forces (pressure gradient, virtual mass; orc_fluid_forces,
+ * orc_exchange_force) and in the virtual mass of the integrator; the clamp
+ * of alpha_s rises to 0.740 (1 + r_max) (orc_alpha_clamp). */
 
 void orc_wet_mass(const orc_params *p, double rho_0, int64_t n, const double *r, const double *held, double *m)
 {
@@ -1558,13 +1588,14 @@ void orc_contact_forces_sample_wet(const orc_params *p, int64_t n, const double 
 
 /* Semi-implicit Euler with per-granule masses; under virtual mass the
  * effective mass is m + (1/2) rho_f V and gravity acts on m (as
- * orc_integrate_vm). */
-void orc_integrate_wet(const orc_params *p, const orc_coupling *cp, int64_t n, const double *r, const double *m,
-                       const double *Fc, const double *Fd, double *x, double *v)
+ * orc_integrate_vm), V = (4/3) pi r^3 (1 + held) counting the absorbed water
+ * (Sec. 5.3; held may be NULL: dry volume). */
+void orc_integrate_wet(const orc_params *p, const orc_coupling *cp, int64_t n, const double *r, const double *held,
+                       const double *m, const double *Fc, const double *Fd, double *x, double *v)
 {
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
-        double me = cp->vmass ? m[i] + (0.5 * cp->rho_f) * orc_volume(r[i]) : m[i];
+        double me = cp->vmass ? m[i] + (0.5 * cp->rho_f) * orc_wet_volume(r[i], held ? held[i] : 0.0) : m[i];
         for (int d = 0; d < 3; ++d) {
             double a = cp->vmass ? ((Fc[d * n + i] + Fd[d * n + i]) + m[i] * p->g[d]) / me
                                  : (Fc[d * n + i] + Fd[d * n + i]) / m[i] + p->g[d];
@@ -1574,8 +1605,9 @@ void orc_integrate_wet(const orc_params *p, const orc_coupling *cp, int64_t n, c
     }
 }
 
-/* P2G of volume fraction (the sand's own volume) and of the wet granules'
- * momentum: the momentum channels deposit frac (rho_s + held rho_0) / rho_s v. */
+/* P2G of the wet granules' volume fraction and momentum (Sec. 5.3, Eq. 19):
+ * the fraction channel deposits frac (1 + held), the sand's volume plus the
+ * water it holds, and the momentum channels frac (rho_s + held rho_0) / rho_s v. */
 void orc_p2g_fixed_wet(const orc_params *p, double rho_0, int64_t n, const double *x, const double *v,
                        const double *r, const double *held, int64_t *alpha, int64_t *mom)
 {

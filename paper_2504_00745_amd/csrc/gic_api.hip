@@ -59,6 +59,7 @@ bool params_valid(const gic_params *p)
     if (p->drag_model != 0 && p->drag_model != 1) return false;
     if (p->vmass != 0 && p->vmass != 1) return false;
     if (!(p->sigma >= 0.0) || !isfinite(p->sigma)) return false;
+    if (!(p->absorb_max >= 0.0) || !isfinite(p->absorb_max)) return false;
     if (p->sigma > 0.0) {
         if (!(p->vbridge > 0.0) || !isfinite(p->vbridge) || !(p->sr_peak > 0.0) || !(p->sr_peak < 1.0)) return false;
         if (p->cell < 2.0 * p->r_max + rupture_max(p)) return false;  // the cells must reach every bridge
@@ -114,7 +115,7 @@ DevParams derive(const gic_params *p)
     d.cdrag = (p->c_drag * (6.0 * GIC_PI)) * p->eta_f;
     d.c_drag = p->c_drag;
     d.cdrag_unit = (6.0 * GIC_PI) * p->eta_f;
-    d.alpha_max = p->alpha_max;
+    d.alpha_max = p->alpha_max * (1.0 + p->absorb_max);  // raised for absorbed water (Sec. 5.3)
     d.dt = p->dt;
     d.r_max = p->r_max;
     d.search_scale = 1.0 + 1.0 / 1073741824.0;  // 1 + 2^-30: slack for rounding
@@ -611,28 +612,31 @@ gic_status gic_gather_g2p_fluid(gic_ctx *c, int64_t n, const int32_t *order, con
                                 const double *r, const int32_t *id, double *x_out, double *v_out, double *r_out,
                                 int32_t *id_out, const void *u, const int64_t *alpha_fx, const void *grad_p,
                                 const void *acc_f, const int32_t *cell_begin, const int32_t *cell_end,
-                                void *f_fluid, void *stream)
+                                void *f_fluid, const double *held, double *held_out, void *stream)
 {
     if (!n_ok(c, n) || !cell_begin || !cell_end) return GIC_E_ARG;
     if (n > 0 && (!order || !x || !v || !r || !x_out || !v_out || !r_out || !u || !alpha_fx || !f_fluid))
         return GIC_E_ARG;
-    if ((id == nullptr) != (id_out == nullptr)) return GIC_E_ARG;
-    if (n > 0 && (x_out == x || v_out == v || r_out == r || (id && id_out == id))) return GIC_E_ARG;
+    if ((id == nullptr) != (id_out == nullptr) || (held == nullptr) != (held_out == nullptr)) return GIC_E_ARG;
+    if (n > 0 && (x_out == x || v_out == v || r_out == r || (id && id_out == id) || (held && held_out == held)))
+        return GIC_E_ARG;
     hipStream_t s = (hipStream_t)stream;
     if (n == 0) return GIC_OK;
     if (brick_list(c, cell_begin, cell_end, s) != hipSuccess) return GIC_E_HIP;
     if (fp32(c))
         return hip_status(launch_gather_g2p_fluid<float>(
             c->dp, n, c->K, order, x, v, r, id, x_out, v_out, r_out, id_out, (const float *)u, alpha_fx,
-            (const float *)grad_p, (const float *)acc_f, cell_begin, cell_end, c->bricks, (float *)f_fluid, s));
+            (const float *)grad_p, (const float *)acc_f, cell_begin, cell_end, c->bricks, (float *)f_fluid, s, held,
+            held_out));
     return hip_status(launch_gather_g2p_fluid<double>(
         c->dp, n, c->K, order, x, v, r, id, x_out, v_out, r_out, id_out, (const double *)u, alpha_fx,
-        (const double *)grad_p, (const double *)acc_f, cell_begin, cell_end, c->bricks, (double *)f_fluid, s));
+        (const double *)grad_p, (const double *)acc_f, cell_begin, cell_end, c->bricks, (double *)f_fluid, s, held,
+        held_out));
 }
 
 gic_status gic_exchange_p2g(gic_ctx *c, int64_t n, const double *x, const double *r, const void *f_contact,
                             const void *f_fluid, const int32_t *cell_begin, const int32_t *cell_end, double weight,
-                            int64_t *fs_fx, void *stream)
+                            int64_t *fs_fx, const double *held, void *stream)
 {
     if (!n_ok(c, n) || !cell_begin || !cell_end || !fs_fx) return GIC_E_ARG;
     if (n > 0 && (!x || !r || !f_contact || !f_fluid)) return GIC_E_ARG;
@@ -644,10 +648,10 @@ gic_status gic_exchange_p2g(gic_ctx *c, int64_t n, const double *x, const double
     if (fp32(c))
         return hip_status(launch_exchange_p2g<float>(c->dp, n, c->K, x, r, (const float *)f_contact,
                                                      (const float *)f_fluid, cell_begin, cell_end, c->bricks, exsc,
-                                                     fs_fx, c->err, s));
+                                                     fs_fx, c->err, s, held));
     return hip_status(launch_exchange_p2g<double>(c->dp, n, c->K, x, r, (const double *)f_contact,
                                                   (const double *)f_fluid, cell_begin, cell_end, c->bricks, exsc,
-                                                  fs_fx, c->err, s));
+                                                  fs_fx, c->err, s, held));
 }
 
 gic_status gic_sand_step(gic_ctx *c, int64_t n, double Dt, double *x_a, double *v_a, double *r_a, int32_t *id_a,
@@ -684,11 +688,12 @@ gic_status gic_sand_step(gic_ctx *c, int64_t n, double Dt, double *x_a, double *
         }
         c->in_step = true;  // the stages below share this brick list
         st = gic_gather_g2p_fluid(c, n, order, xc, vc, rc, ic, xn, vn, rn, in, u, alpha_fx, grad_p, acc_f,
-                                  cell_begin, cell_end, f_fluid, stream);
+                                  cell_begin, cell_end, f_fluid, nullptr, nullptr, stream);
         if (st == GIC_OK)
             st = gic_contact_forces(c, n, xn, vn, rn, cell_begin, cell_end, f_contact, nullptr, stream);
         if (st == GIC_OK && fs_fx)
-            st = gic_exchange_p2g(c, n, xn, rn, f_contact, f_fluid, cell_begin, cell_end, weight, fs_fx, stream);
+            st = gic_exchange_p2g(c, n, xn, rn, f_contact, f_fluid, cell_begin, cell_end, weight, fs_fx, nullptr,
+                                  stream);
         if (st == GIC_OK)
             st = gic_integrate_p2g(c, n, xn, vn, rn, f_contact, f_fluid, cell_begin, cell_end, alpha_fx, mom_fx, 0,
                                    stream);

@@ -90,7 +90,7 @@ struct DevParams {
     double kn, zeta, kt_ratio, mu;
     double rho_s, cdrag;  // cdrag = c_drag 6 pi eta_f
     double c_drag, cdrag_unit;  // C_d and 6 pi eta_f separately (adjoint)
-    double alpha_max;
+    double alpha_max;   // clamp of alpha_s: 0.740, times (1 + r_max) when granules absorb water (Sec. 5.3)
     double g[3], dt;
     double r_max, search_scale;
     uint32_t walls;
@@ -125,6 +125,15 @@ __device__ inline double wet_mass(const DevParams &P, double r, double held)
 {
 #pragma clang fp contract(off)
     return volume_of(r) * (P.rho_s + held * P.rho_f);
+}
+
+// Volume the fluid sees of a wet granule (Sec. 5.3: the absorbed water
+// counts as extra volume): V (1 + held), V exactly when held = 0.
+__device__ inline double wet_volume(double r, double held)
+{
+#pragma clang fp contract(off)
+    const double V = volume_of(r);
+    return held != 0.0 ? V + V * held : V;
 }
 
 // clamp(floor(x / cell), 0, nc - 1); NaN -> 0.
@@ -297,14 +306,15 @@ __device__ inline void drag_one(const DevParams &P, double r, const double v[3],
 // Semi-implicit Euler (Sec. 4): v += dt ((F_c + F_d) / m + g), then x += dt v.
 // With virtual mass (Eq. 9) the effective mass is m + rho_f V / 2 and
 // gravity acts on m: v += dt ((F_c + F_d) + m g) / (m + rho_f V / 2).
-// m: the granule's mass (rho_s V, or the wet mass of Eq. 19).
+// m: the granule's mass (rho_s V, or the wet mass of Eq. 19); vol: the
+// volume of the virtual mass (V, or V (1 + held) for a wet granule).
 template <typename T>
-__device__ inline void integrate_one_m(const DevParams &P, double r, double m, const T Fc[3], const T *Fd,
+__device__ inline void integrate_one_m(const DevParams &P, double vol, double m, const T Fc[3], const T *Fd,
                                        double x[3], double v[3])
 {
 #pragma clang fp contract(off)  // one rounding per operation in every kernel that inlines it
     if (P.vmass) {
-        const double me = m + P.half_rho_f * volume_of(r);
+        const double me = m + P.half_rho_f * vol;
         for (int a = 0; a < 3; ++a) {
             double f = (double)Fc[a];
             if (Fd) f += (double)Fd[a];
@@ -328,7 +338,7 @@ template <typename T>
 __device__ inline void integrate_one(const DevParams &P, double r, const T Fc[3], const T *Fd, double x[3],
                                      double v[3])
 {
-    integrate_one_m<T>(P, r, mass_of(P, r), Fc, Fd, x, v);
+    integrate_one_m<T>(P, volume_of(r), mass_of(P, r), Fc, Fd, x, v);
 }
 
 // Moisture curve Gamma of the capillary force (Sec. 5.4): zero when dry

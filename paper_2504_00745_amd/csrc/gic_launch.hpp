@@ -86,13 +86,14 @@ hipError_t launch_integrate_p2g(const DevParams &P, int64_t n, int64_t K, double
 template <typename T>
 hipError_t launch_exchange_p2g(const DevParams &P, int64_t n, int64_t K, const double *x, const double *r,
                                const T *Fc, const T *Ffl, const int32_t *cb, const int32_t *ce, const BrickList &B,
-                               double exsc, int64_t *fs, int64_t *err, hipStream_t s);
+                               double exsc, int64_t *fs, int64_t *err, hipStream_t s,
+                               const double *held = nullptr);  // held: wet mass and volume, or NULL
 template <typename T>
 hipError_t launch_gather_g2p_fluid(const DevParams &P, int64_t n, int64_t K, const int32_t *order, const double *x,
                                    const double *v, const double *r, const int32_t *id, double *xo, double *vo,
                                    double *ro, int32_t *ido, const T *u, const int64_t *afx, const T *gp,
                                    const T *fa, const int32_t *cb, const int32_t *ce, const BrickList &B, T *Ff,
-                                   hipStream_t s);
+                                   hipStream_t s, const double *held = nullptr, double *heldo = nullptr);
 template <typename T>
 hipError_t launch_gather_g2p_drag(const DevParams &P, int64_t n, int64_t K, const int32_t *order, const double *x,
                                   const double *v, const double *r, const int32_t *id, double *xo, double *vo,

@@ -95,7 +95,9 @@ __global__ void __launch_bounds__(256) k_gather_g2p_drag(DevParams P, int64_t n,
 // tile holds e (three channels) instead of grad p and a_f (six).  The
 // interpolation of u and alpha is the same function as in the drag-only
 // kernel; e is sampled in the same pass over the 27 nodes with the same
-// weights.
+// weights.  For wet granules (held given, in the input order)
+// V = (4/3) pi r^3 (1 + held): the absorbed water counts as volume
+// (Sec. 5.3); held is gathered into heldo with the rest of the state.
 template <typename T>
 __global__ void __launch_bounds__(256) k_gather_g2p_fluid(DevParams P, int64_t n, const int32_t *__restrict__ bl,
                                                           const int32_t *__restrict__ bcnt,
@@ -107,7 +109,9 @@ __global__ void __launch_bounds__(256) k_gather_g2p_fluid(DevParams P, int64_t n
                                                           int32_t *__restrict__ ido, const T *__restrict__ u,
                                                           const int64_t *__restrict__ afx, const T *__restrict__ gp,
                                                           const T *__restrict__ fa, const int32_t *__restrict__ cb,
-                                                          const int32_t *__restrict__ ce, T *__restrict__ Ff)
+                                                          const int32_t *__restrict__ ce, T *__restrict__ Ff,
+                                                          const double *__restrict__ held,
+                                                          double *__restrict__ heldo)
 {
     extern __shared__ double smem_d[];
     const int64_t b = brick_of_block(bl, bcnt);
@@ -155,6 +159,8 @@ __global__ void __launch_bounds__(256) k_gather_g2p_fluid(DevParams P, int64_t n
         }
         ro[q] = rq;
         if (ido) ido[q] = id[s];
+        const double hq = held ? held[s] : 0.0;
+        if (heldo) heldo[q] = hq;
         Stencil st;
         stencil_of(P, xa, st);
         T ua[3], a;
@@ -183,7 +189,7 @@ __global__ void __launch_bounds__(256) k_gather_g2p_fluid(DevParams P, int64_t n
         T f[3];
         drag_one<T>(P, rq, va, ua, a, f);
         if (extra) {
-            const T tV = (T)volume_of(rq);
+            const T tV = (T)wet_volume(rq, hq);
             for (int c = 0; c < 3; ++c) f[c] = f[c] + tV * ea[c];
         }
         for (int c = 0; c < 3; ++c) Ff[c * n + q] = f[c];
@@ -197,14 +203,14 @@ hipError_t launch_gather_g2p_fluid(const DevParams &P, int64_t n, int64_t K, con
                                    const double *v, const double *r, const int32_t *id, double *xo, double *vo,
                                    double *ro, int32_t *ido, const T *u, const int64_t *afx, const T *gp,
                                    const T *fa, const int32_t *cb, const int32_t *ce, const BrickList &B, T *Ff,
-                                   hipStream_t s)
+                                   hipStream_t s, const double *held, double *heldo)
 {
     if (n == 0) return hipSuccess;
     const int64_t bricks = K / kBrickCells;
     const int E = P.tile;
     const size_t lds = sizeof(T) * 7 * (size_t)E * E * E;
     k_gather_g2p_fluid<T><<<brick_grid(bricks), 256, lds, s>>>(P, n, B.list, B.count, order, x, v, r, id, xo, vo, ro,
-                                                               ido, u, afx, gp, fa, cb, ce, Ff);
+                                                               ido, u, afx, gp, fa, cb, ce, Ff, held, heldo);
     return hipGetLastError();
 }
 
@@ -212,12 +218,14 @@ template hipError_t launch_gather_g2p_fluid<float>(const DevParams &, int64_t, i
                                                    const double *, const double *, const double *, const int32_t *,
                                                    double *, double *, double *, int32_t *, const float *,
                                                    const int64_t *, const float *, const float *, const int32_t *,
-                                                   const int32_t *, const BrickList &, float *, hipStream_t);
+                                                   const int32_t *, const BrickList &, float *, hipStream_t,
+                                                   const double *, double *);
 template hipError_t launch_gather_g2p_fluid<double>(const DevParams &, int64_t, int64_t, const int32_t *,
                                                     const double *, const double *, const double *, const int32_t *,
                                                     double *, double *, double *, int32_t *, const double *,
                                                     const int64_t *, const double *, const double *, const int32_t *,
-                                                    const int32_t *, const BrickList &, double *, hipStream_t);
+                                                    const int32_t *, const BrickList &, double *, hipStream_t,
+                                                    const double *, double *);
 
 template <typename T>
 hipError_t launch_gather_g2p_drag(const DevParams &P, int64_t n, int64_t K, const int32_t *order, const double *x,

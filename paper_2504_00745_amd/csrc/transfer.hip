@@ -93,7 +93,12 @@ __device__ inline void tile_add(unsigned long long *tile, unsigned long long *gl
 // force on the granule (Fd, plus the virtual-mass part -(rho_f V / 2) a_s
 // with a_s = ((Fc + Fd) + m g) / (m + rho_f V / 2)), exsc = -weight / f_unit,
 // deposited at the granule's current position; alpha receives channel 0 and
-// mom channels 1 and 2.
+// mom channels 1 and 2.  With held (not NULL) m and V are the wet mass and
+// volume (Sec. 5.3).
+//
+// WET: granules hold water (held, per unit of their volume): the move takes
+// the wet mass of Eq. 19 (and the wet volume in the virtual mass), alpha
+// receives frac (1 + held) and momentum the wet mass's (Sec. 5.3).
 template <bool MOM, typename T, bool INTEG, bool EXCH = false, bool WET = false>
 __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_eu(4))) k_p2g_fixed(DevParams P, int64_t n, const int32_t *__restrict__ bl,
                                                            const int32_t *__restrict__ bcnt, int batch,
@@ -107,7 +112,6 @@ __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_e
 {
 #pragma clang fp contract(off)
     static_assert(!(EXCH && (MOM || INTEG)), "the exchange deposit is a kind of its own");
-    static_assert(!(WET && EXCH), "the exchange deposit uses the dry mass");
     constexpr int NCH = EXCH ? 3 : (MOM ? 4 : 1);
     extern __shared__ unsigned long long tile[];
     __shared__ int32_t s_range[2];
@@ -146,7 +150,7 @@ __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_e
                 const T fc[3] = {Fc[q], Fc[n + q], Fc[2 * n + q]};
                 const T fd[3] = {Fd[q], Fd[n + q], Fd[2 * n + q]};
                 if (WET)
-                    integrate_one_m<T>(P, r[q], wet_mass(P, r[q], held[q]), fc, fd, xa, va);
+                    integrate_one_m<T>(P, wet_volume(r[q], held[q]), wet_mass(P, r[q], held[q]), fc, fd, xa, va);
                 else
                     integrate_one<T>(P, r[q], fc, fd, xa, va);
                 for (int a = 0; a < 3; ++a) {
@@ -164,9 +168,12 @@ __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_e
             }
             double S[NCH];
             if constexpr (EXCH) {
+                // wet granules (held given): the wet mass of Eq. 19 and the
+                // volume with the held water (Sec. 5.3)
                 const double rq = r[q];
-                const double m = mass_of(P, rq);
-                const double hv = P.half_rho_f * volume_of(rq);
+                const double hq = held ? held[q] : 0.0;
+                const double m = held ? wet_mass(P, rq, hq) : mass_of(P, rq);
+                const double hv = P.half_rho_f * wet_volume(rq, hq);
                 const double me = m + hv;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
@@ -179,7 +186,9 @@ __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_e
                 }
             } else {
                 const double frac = volume_of(r[q]) * P.inv_vcell;
-                S[0] = frac * GIC_TWO32;
+                // a wet granule's held water counts as volume in alpha_s
+                // (Sec. 5.3): frac (1 + held), frac exactly when held = 0
+                S[0] = (WET ? frac + frac * held[q] : frac) * GIC_TWO32;
                 // momentum in rho_s dx^3 units: a wet granule (Eq. 19) carries
                 // frac (rho_s + held rho_f) / rho_s = frac + frac held rho_f / rho_s
                 // per unit velocity (held = 0 gives frac exactly)
@@ -453,7 +462,7 @@ static hipError_t p2g_fixed_impl(const DevParams &P, int64_t n, int64_t K, doubl
 template <typename T>
 hipError_t launch_exchange_p2g(const DevParams &P, int64_t n, int64_t K, const double *x, const double *r,
                                const T *Fc, const T *Ffl, const int32_t *cb, const int32_t *ce, const BrickList &B,
-                               double exsc, int64_t *fs, int64_t *err, hipStream_t s)
+                               double exsc, int64_t *fs, int64_t *err, hipStream_t s, const double *held)
 {
     if (n == 0) return hipSuccess;
     const int64_t bricks = K / kBrickCells;
@@ -465,17 +474,18 @@ hipError_t launch_exchange_p2g(const DevParams &P, int64_t n, int64_t K, const d
     // x is only read on this path
     k_p2g_fixed<false, T, false, true><<<brick_grid(bricks), kP2GThreads, lds, s>>>(
         P, n, B.list, B.count, batch, const_cast<double *>(x), nullptr, r, Fc, Ffl, cb, ce, F, F + P.G, err, exsc,
-        nullptr);
+        held);
     return hipGetLastError();
 }
 
 template hipError_t launch_exchange_p2g<float>(const DevParams &, int64_t, int64_t, const double *, const double *,
                                                const float *, const float *, const int32_t *, const int32_t *,
-                                               const BrickList &, double, int64_t *, int64_t *, hipStream_t);
+                                               const BrickList &, double, int64_t *, int64_t *, hipStream_t,
+                                               const double *);
 template hipError_t launch_exchange_p2g<double>(const DevParams &, int64_t, int64_t, const double *,
                                                 const double *, const double *, const double *, const int32_t *,
                                                 const int32_t *, const BrickList &, double, int64_t *, int64_t *,
-                                                hipStream_t);
+                                                hipStream_t, const double *);
 
 hipError_t launch_p2g_fixed(const DevParams &P, int64_t n, int64_t K, const double *x, const double *v,
                             const double *r, const int32_t *cb, const int32_t *ce, const BrickList &B,

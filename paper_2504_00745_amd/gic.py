@@ -37,6 +37,7 @@ class gic_params(C.Structure):
         ("rho_f", C.c_double), ("c_quad", C.c_double), ("f_unit", C.c_double),
         ("drag_model", C.c_int32), ("vmass", C.c_int32),
         ("sigma", C.c_double), ("vbridge", C.c_double), ("sr_peak", C.c_double),
+        ("absorb_max", C.c_double),
     ]
 
 
@@ -80,8 +81,8 @@ def lib():
             "gic_gather_g2p_drag": (C.c_int, [_V, _I64] + [_V] * 17),
             "gic_integrate_p2g": (C.c_int, [_V, _I64] + [_V] * 9 + [_I32, _V]),
             "gic_step": (C.c_int, [_V, _I64] + [_V] * 20),
-            "gic_gather_g2p_fluid": (C.c_int, [_V, _I64] + [_V] * 17),
-            "gic_exchange_p2g": (C.c_int, [_V, _I64] + [_V] * 6 + [C.c_double, _V, _V]),
+            "gic_gather_g2p_fluid": (C.c_int, [_V, _I64] + [_V] * 19),
+            "gic_exchange_p2g": (C.c_int, [_V, _I64] + [_V] * 6 + [C.c_double, _V, _V, _V]),
             "gic_sand_step": (C.c_int, [_V, _I64, C.c_double] + [_V] * 23),
             "gic_contact_forces_vjp": (C.c_int, [_V, _I64] + [_V] * 10),
             "gic_drag_vjp": (C.c_int, [_V, _I64] + [_V] * 10),
@@ -121,6 +122,7 @@ def make_params(cfg: dict, precision: str = "fp32", r_max: float = None) -> gic_
     p.sigma = float(cfg.get("sigma", 0.0))
     p.vbridge = float(cfg.get("vbridge", 1e-4))
     p.sr_peak = float(cfg.get("sr_peak", 0.3))
+    p.absorb_max = float(cfg.get("absorb_max", 0.0))
     return p
 
 
@@ -404,7 +406,7 @@ def gic_step(ctx, cur, nxt, u, alpha_fx, mom_fx, scratch):
 # ---- remaining interphase forces and the sand step ------------------------------
 
 def gic_gather_g2p_fluid(ctx, order, x, v, r, id_, x_out, v_out, r_out, id_out, u, alpha_fx, cell_begin, cell_end,
-                         f_fluid, grad_p=None, acc_f=None):
+                         f_fluid, grad_p=None, acc_f=None, held=None, held_out=None):
     n = x.shape[-1]
     f64 = torch.float64
     _check(lib().gic_gather_g2p_fluid(ctx.handle, n, _ptr(order, torch.int32, n), _ptr(x, f64, 3 * n),
@@ -414,16 +416,18 @@ def gic_gather_g2p_fluid(ctx, order, x, v, r, id_, x_out, v_out, r_out, id_out, 
                                       _ptr(alpha_fx, torch.int64, ctx.G), _ptr(grad_p, ctx.real, 3 * ctx.G),
                                       _ptr(acc_f, ctx.real, 3 * ctx.G), _ptr(cell_begin, torch.int32, ctx.K),
                                       _ptr(cell_end, torch.int32, ctx.K), _ptr(f_fluid, ctx.real, 3 * n, "f_fluid"),
-                                      _stream()), "gic_gather_g2p_fluid")
+                                      _ptr(held, f64, n, "held"), _ptr(held_out, f64, n, "held_out"), _stream()),
+           "gic_gather_g2p_fluid")
 
 
-def gic_exchange_p2g(ctx, x, r, f_contact, f_fluid, cell_begin, cell_end, weight, fs_fx):
+def gic_exchange_p2g(ctx, x, r, f_contact, f_fluid, cell_begin, cell_end, weight, fs_fx, held=None):
     n = x.shape[-1]
     f64 = torch.float64
     _check(lib().gic_exchange_p2g(ctx.handle, n, _ptr(x, f64, 3 * n), _ptr(r, f64, n),
                                   _ptr(f_contact, ctx.real, 3 * n), _ptr(f_fluid, ctx.real, 3 * n),
                                   _ptr(cell_begin, torch.int32, ctx.K), _ptr(cell_end, torch.int32, ctx.K),
-                                  float(weight), _ptr(fs_fx, torch.int64, 3 * ctx.G), _stream()), "gic_exchange_p2g")
+                                  float(weight), _ptr(fs_fx, torch.int64, 3 * ctx.G), _ptr(held, f64, n, "held"),
+                                  _stream()), "gic_exchange_p2g")
 
 
 def gic_sand_step(ctx, a, b, Dt, u, alpha_fx, mom_fx, scratch, grad_p=None, acc_f=None, fs_fx=None):
