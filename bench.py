@@ -1,18 +1,24 @@
 """Throughput of the granule hot path on one MI355X.
 
-One step = one sand sub-step (Alg. 2) through the C ABI: cell sort, reorder,
-G2P, drag, contact, integration and P2G, on the c3 workload (dam-break
-column, 4,194,304 granules, 256x128x128 grid), FP32 form; the plain FP64 GPU
-path is timed the same way.  Inputs are resident in HBM before timing.
+One step = one sand sub-step (Alg. 2) through the C ABI (gic_step): cell
+sort, reorder, G2P, drag, contact, integration and P2G, on the c3 workload
+(dam-break column, 4,194,304 granules, 256x128x128 grid), FP32 form; the
+plain FP64 GPU path is timed the same way.  Inputs are resident in HBM
+before timing.
 
 Prints ONE JSON line (rank 0, N=1):
   value         granule-steps/s of the FP32 form (whole step)
   fp64_value    granule-steps/s of the plain FP64 path
   roofline      dominant kernel: algorithmic bytes per launch / its average
-                duration from HIP events on its own stream, vs 8 TB/s
-  cpu_baseline  the FP64 CPU oracle on this host's cores, bounded sample
+                duration from HIP events recorded between the step's stages on
+                the step's own stream, vs 8 TB/s
+  fp32_error    the FP32 form's error against the plain FP64 path, per output
+  c2, c5        the polydisperse moving bed (262,144 granules, 100 steps) and
+                the large bed (16,777,216 granules, 20 steps), per-stage GB/s
+  cpu_baseline  the FP64 CPU oracle on this host's cores, bounded sample,
+                one thread and all threads
 
-    python bench.py [--steps K] [--warmup W] [--workload c3] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--workload c3] [--no-cpu] ...
 """
 import argparse
 import json
@@ -37,6 +43,9 @@ def parse():
     ap.add_argument("--no-coupled", action="store_true")
     ap.add_argument("--no-capillary", action="store_true")
     ap.add_argument("--no-idp", action="store_true")
+    ap.add_argument("--no-c2", action="store_true")
+    ap.add_argument("--no-c5", action="store_true")
+    ap.add_argument("--no-error", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (read 1 GiB, write 1 GiB) three times, "
@@ -81,10 +90,13 @@ CAPILLARY_BYTES_PER_GRANULE = 24 + 24 + 8 + 3 * 4 + 4 + 8
 
 
 def time_steps(sim, steps, warmup):
+    """K whole steps (gic_step) between two HIP events on the step's stream,
+    after W warm-up steps; also the neighbour-list builds during the K."""
     import torch
     for _ in range(warmup):
         sim.step()
     torch.cuda.synchronize()
+    b0 = sim.ctx.neighbour_builds()
     t0 = time.perf_counter()
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
@@ -93,48 +105,141 @@ def time_steps(sim, steps, warmup):
     end.record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    return start.elapsed_time(end) / 1e3, t1 - t0
+    return start.elapsed_time(end) / 1e3, t1 - t0, sim.ctx.neighbour_builds() - b0
 
 
-def time_stages(sim, steps):
-    """Per-kernel times of the step from HIP events recorded on the stream the
-    kernels are launched on (torch's current stream), between the C-ABI calls
-    that gic_step makes; each launches one kernel of the step, the sort aside
-    (its passes), and the grid clear is issued outside the bracket."""
+STAGE_KEYS = {"sort": "sort", "gather": "gather_g2p_drag", "contact": "contact", "exchange": "exchange_p2g",
+              "grid_clear": "grid_clear", "integrate_p2g": "integrate_p2g"}
+
+
+def time_stages(sim, steps, sand_dt=None, **sand):
+    """Per-stage times of the step itself: the library records HIP events on
+    the step's stream between its stages (gic_stage_timing) over `steps`
+    further steps (or sand steps of length sand_dt); mean seconds per
+    (sub-)step of each stage."""
+    ctx = sim.ctx
+    ctx.stage_timing(steps * 64)
+    for _ in range(steps):
+        if sand_dt is None:
+            sim.step()
+        else:
+            sim.sand_step(sand_dt, **sand)
+    ms, k = ctx.stage_times()
+    ctx.stage_timing(0)
+    out = {STAGE_KEYS[key]: v / 1e3 / max(k, 1) for key, v in ms.items()}
+    if sand_dt is None:
+        out.pop("exchange_p2g")
+    else:
+        out["gather_g2p_fluid"] = out.pop("gather_g2p_drag")
+    return out, k
+
+
+# Kernels whose time is one launch of one kernel per (sub-)step (the sort is
+# a sequence of kernels; the contact stage is the neighbour-list kernel plus
+# the list build, which returns at once when the list is kept).
+SINGLE_KERNEL_STAGES = ("gather_g2p_drag", "contact", "integrate_p2g")
+
+
+def dominant_roofline(stages, n, nodes, real_bytes, workload):
+    dom = max(SINGLE_KERNEL_STAGES, key=lambda k: stages[k])
+    abytes = stage_bytes(dom, n, nodes, real_bytes)
+    ach = abytes / stages[dom] / 1e9
+    return {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "traffic": stored_traffic(dom, workload), "algorithmic_bytes": abytes}
+
+
+def stage_rooflines(stages, n, nodes, real_bytes):
+    """Algorithmic GB/s and fraction of the HBM peak of each single-kernel stage."""
+    out = {}
+    for k in SINGLE_KERNEL_STAGES:
+        ab = stage_bytes(k, n, nodes, real_bytes)
+        out[k] = {"ms": round(stages[k] * 1e3, 4), "algorithmic_bytes": ab,
+                  "GB_s": round(ab / stages[k] / 1e9, 1), "frac": round(ab / stages[k] / 1e9 / HBM_PEAK_GBS, 4)}
+    return out
+
+
+def fp32_error(d, rmax):
+    """Error of the FP32 form against the plain FP64 path (itself within
+    1e-12 of the FP64 oracle in the parity tests) after one step from the
+    same state, per output and per granule: max and 99th percentile of
+      F_c  |dF_c| / (|F_c| + m |g|)     F_d  |dF_d| / (beta (|u_at| + |v|))
+      u_at |du| / (|u_at| + max|u|)     alpha_f |d alpha_f| (a fraction)
+      v    |dv| / (|v| + dt (|F_c| + |F_d| + m |g|) / m)
+      x    |dx| / (dt times the v scale)
+    with the FP64 values on the right."""
     import torch
     from paper_2504_00745_amd import gic
-    ctx, s = sim.ctx, sim.scratch
-    names = ["sort", "gather_g2p_drag", "contact", "integrate_p2g"]
-    acc = {k: 0.0 for k in names}
-    # all steps are enqueued before the first synchronisation, so the stream
-    # never runs dry and each event pair brackets its kernel(s) only
-    evs = []
-    for _ in range(steps):
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
-        cur, nxt = sim.cur, sim.nxt
-        ev[0].record()
-        gic.gic_sort_cells(ctx, cur["x"], s["key"], s["order"], s["cell_begin"], s["cell_end"])
-        ev[1].record()
-        gic.gic_gather_g2p_drag(ctx, s["order"], cur["x"], cur["v"], cur["r"], cur["id"], nxt["x"], nxt["v"],
-                                nxt["r"], nxt["id"], sim.u, sim.alpha, s["cell_begin"], s["cell_end"], s["f_drag"])
-        ev[2].record()
-        gic.gic_contact_forces(ctx, nxt["x"], nxt["v"], nxt["r"], s["cell_begin"], s["cell_end"], s["f_contact"])
-        ev[3].record()
-        sim.alpha.zero_()  # the grid clear, outside the timed kernel
-        sim.mom.zero_()
-        ev_p = torch.cuda.Event(enable_timing=True)
-        ev_p.record()
-        gic.gic_integrate_p2g(ctx, nxt["x"], nxt["v"], nxt["r"], s["f_contact"], s["f_drag"], s["cell_begin"],
-                              s["cell_end"], sim.alpha, sim.mom, accumulate=True)
-        ev[4].record()
-        sim.cur, sim.nxt = nxt, cur
-        evs.append((ev, ev_p))
-    torch.cuda.synchronize()
-    for ev, ev_p in evs:
-        for i, k in enumerate(names[:3]):
-            acc[k] += ev[i].elapsed_time(ev[i + 1]) / 1e3
-        acc["integrate_p2g"] += ev_p.elapsed_time(ev[4]) / 1e3
-    return {k: v / steps for k, v in acc.items()}
+    cfg = d["params"]
+    outs = {}
+    for prec in ("fp32", "fp64"):
+        sim = gic.Simulator(cfg, d["x"], d["v"], d["r"], d["u"], prec, r_max=rmax)
+        gic.gic_step(sim.ctx, sim.cur, sim.nxt, sim.u, sim.alpha, sim.mom, sim.scratch)
+        s = sim.scratch
+        ids = sim.nxt["id"].long()
+        n = ids.numel()
+
+        def unsort(t, comps):
+            o = torch.empty(comps, n, dtype=torch.float64, device="cuda")
+            o[:, ids] = t.view(comps, n).double()
+            return o
+        outs[prec] = dict(Fc=unsort(s["f_contact"], 3), Fd=unsort(s["f_drag"], 3), uat=unsort(s["u_at"], 3),
+                          af=unsort(s["alpha_f"], 1)[0], v=unsort(sim.nxt["v"], 3), x=unsort(sim.nxt["x"], 3))
+        del sim
+        torch.cuda.empty_cache()
+    a, b = outs["fp32"], outs["fp64"]
+    r = torch.as_tensor(d["r"], device="cuda")
+    v0 = torch.as_tensor(d["v"], device="cuda")
+    m = cfg["rho_s"] * (4.0 / 3.0) * np.pi * r ** 3
+    g = float(np.linalg.norm(cfg["g"]))
+    beta = cfg["c_drag"] * 6.0 * np.pi * cfg["eta_f"] * r
+    nrm = lambda t: torch.linalg.norm(t, dim=0)
+    umax = float(np.abs(d["u"]).max())
+    vscale = nrm(b["v"]) + cfg["dt"] * (nrm(b["Fc"]) + nrm(b["Fd"]) + m * g) / m
+    rel = {"F_c": nrm(a["Fc"] - b["Fc"]) / (nrm(b["Fc"]) + m * g + 1e-300),
+           "F_d": nrm(a["Fd"] - b["Fd"]) / (beta * (nrm(b["uat"]) + nrm(v0)) + 1e-300),
+           "u_at": nrm(a["uat"] - b["uat"]) / (nrm(b["uat"]) + umax + 1e-300),
+           "alpha_f": (a["af"] - b["af"]).abs(),
+           "v": nrm(a["v"] - b["v"]) / (vscale + 1e-300),
+           "x": nrm(a["x"] - b["x"]) / (cfg["dt"] * vscale + 1e-300)}
+    return {k: {"max": float(t.max()), "p99": float(torch.quantile(t[::max(1, t.numel() // 1000000)], 0.99))}
+            for k, t in rel.items()}
+
+
+def run_leg(name, steps, warmup, with_fp64=False):
+    """Another workload as its own leg: whole FP32 steps (and FP64 if asked)
+    timed with events, the stage times and each single-kernel stage's
+    algorithmic GB/s."""
+    import torch
+    from paper_2504_00745_amd import gic, workloads as wl
+    d = wl.make(name)
+    n = d["x"].shape[1]
+    rmax = float(d["r"].max())
+    res = {"workload": WORKLOAD_TEXT[name](d), "granules": n, "steps": steps}
+    for prec in (["fp32", "fp64"] if with_fp64 else ["fp32"]):
+        sim = gic.Simulator(d["params"], d["x"], d["v"], d["r"], d["u"], prec, r_max=rmax)
+        t, _, builds = time_steps(sim, steps, warmup)
+        stages, k = time_stages(sim, min(steps, 10))
+        nodes = touched_nodes(sim)
+        code, idx = sim.ctx.error()
+        B = 4 if prec == "fp32" else 8
+        r = {"value": n * steps / t, "unit": "granule-steps/s", "ms_per_step": t / steps * 1e3,
+             "neighbour_builds": builds, "stages_ms": {k_: round(v * 1e3, 4) for k_, v in stages.items()},
+             "stage_rooflines": stage_rooflines(stages, n, nodes, B), "error": [code, idx]}
+        res[prec] = r
+        del sim
+        torch.cuda.empty_cache()
+    return res
+
+
+WORKLOAD_TEXT = {
+    "c2": lambda d: (f"c2: {d['x'].shape[1]} granules, log-normal radii (median 5 mm, sigma 0.2, clipped to "
+                     f"[3, 10] mm), random sequential addition at solid fraction 0.30, gravity, 128^3 grid "
+                     f"dx=0.01, 16 Fourier modes A=0.2, dt=5e-6, FP32 form"),
+    "c3": lambda d: (f"c3: dam-break column, {d['x'].shape[1]} granules r=1 mm, {d['params']['n']} grid "
+                     f"dx={d['params']['dx']}, dt={d['params']['dt']}"),
+    "c5": lambda d: (f"c5: {d['x'].shape[1]} granules, radii U[0.75, 1.5] mm on a jittered lattice, "
+                     f"{d['params']['n']} grid dx=0.003, shear flow plus 32 modes, gravity, dt=1e-6, FP32 form"),
+}
 
 
 def time_adjoint(reps=3):
@@ -234,7 +339,8 @@ def time_coupled(d, wl_name, substeps=4, sand_steps=8):
     FP32 form: a hydrostatic pressure gradient rho_f g plus a seeded
     perturbation, a seeded fluid-acceleration field, virtual mass and the
     exchange-momentum deposit.  Whole sand steps timed with HIP events, then
-    each kernel of a sub-step one C-ABI call at a time."""
+    the stages of each sub-step from the events the library records between
+    them."""
     import torch
     from paper_2504_00745_amd import gic
     cfg = dict(d["params"], rho_f=1000.0, vmass=1, f_unit=1e-8)
@@ -259,41 +365,10 @@ def time_coupled(d, wl_name, substeps=4, sand_steps=8):
     torch.cuda.synchronize()
     t = e0.elapsed_time(e1) / 1e3
     code, idx = sim.ctx.error()
-    # per kernel, on the current state (sorted), all calls enqueued before one synchronisation
-    ctx, s = sim.ctx, sim.scratch
-    names = ["sort", "gather_g2p_fluid", "contact", "exchange_p2g", "integrate_p2g"]
-    acc = {k: 0.0 for k in names}
-    reps = 4
-    evs = []
-    for _ in range(reps):
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
-        cur, nxt = sim.cur, sim.nxt
-        ev[0].record()
-        gic.gic_sort_cells(ctx, cur["x"], s["key"], s["order"], s["cell_begin"], s["cell_end"])
-        ev[1].record()
-        gic.gic_gather_g2p_fluid(ctx, s["order"], cur["x"], cur["v"], cur["r"], cur["id"], nxt["x"], nxt["v"],
-                                 nxt["r"], nxt["id"], sim.u, sim.alpha, s["cell_begin"], s["cell_end"], s["f_drag"],
-                                 grad_p=GP, acc_f=AF)
-        ev[2].record()
-        gic.gic_contact_forces(ctx, nxt["x"], nxt["v"], nxt["r"], s["cell_begin"], s["cell_end"], s["f_contact"])
-        ev[3].record()
-        gic.gic_exchange_p2g(ctx, nxt["x"], nxt["r"], s["f_contact"], s["f_drag"], s["cell_begin"], s["cell_end"],
-                             1.0 / substeps, FS)
-        ev[4].record()
-        sim.alpha.zero_()
-        sim.mom.zero_()
-        ev_p = torch.cuda.Event(enable_timing=True)
-        ev_p.record()
-        gic.gic_integrate_p2g(ctx, nxt["x"], nxt["v"], nxt["r"], s["f_contact"], s["f_drag"], s["cell_begin"],
-                              s["cell_end"], sim.alpha, sim.mom, accumulate=True)
-        ev[5].record()
-        sim.cur, sim.nxt = nxt, cur
-        evs.append((ev, ev_p))
-    torch.cuda.synchronize()
-    for ev, ev_p in evs:
-        for i, k in enumerate(names[:4]):
-            acc[k] += ev[i].elapsed_time(ev[i + 1]) / 1e3 / reps
-        acc["integrate_p2g"] += ev_p.elapsed_time(ev[5]) / 1e3 / reps
+    # per stage, from the events the library records between the stages of
+    # each sub-step
+    st, k = time_stages(sim, 4, sand_dt=Dt, grad_p=GP, acc_f=AF, fs=FS)
+    acc = {key: st[key] for key in ("sort", "gather_g2p_fluid", "contact", "exchange_p2g", "integrate_p2g")}
     nodes = touched_nodes(sim)
     xb = coupled_bytes("exchange_p2g", n, nodes, 4)
     ach = xb / acc["exchange_p2g"] / 1e9
@@ -463,23 +538,53 @@ def touched_nodes(sim):
     return int((sim.alpha != 0).sum().item())
 
 
+def cpu_info():
+    """Host cores visible to this process and the CPU model (lscpu)."""
+    import subprocess
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "model": model}
+
+
 def cpu_baseline(d, steps):
-    """The FP64 oracle as it stands, on this host's cores, for a bounded
-    number of steps of the same workload."""
+    """The FP64 oracle as it stands, on this host's cores: `steps` full steps
+    of the workload with all threads, and one step of a slab of a quarter of
+    its granules (the quarter with the smallest x) on one thread."""
     import oracle
     cfg = d["params"]
     x, v, r, u = d["x"], d["v"], d["r"], d["u"]
-    a0, _ = oracle.p2g_fixed(cfg, x, v, r)
-    t0 = time.perf_counter()
-    st = None
-    for _ in range(steps):
-        st = oracle.step(cfg, x, v, r, u, a0)
-        x, v, a0 = st["x"], st["v"], st["alpha"]
-    dt = time.perf_counter() - t0
     n = x.shape[1]
-    return dict(value=n * steps / dt, unit="granule-steps/s", cores=oracle.num_threads(), kind="oracle",
-                sample=f"{steps} full steps of the {d['name']} workload ({n} granules), FP64 C oracle with OpenMP",
-                seconds=round(dt, 3))
+    all_threads = oracle.num_threads()
+    res = {"kind": "oracle", "unit": "granule-steps/s", **cpu_info()}
+
+    def run(xx, vv, rr, k):
+        a0, _ = oracle.p2g_fixed(cfg, xx, vv, rr)
+        t0 = time.perf_counter()
+        for _ in range(k):
+            st = oracle.step(cfg, xx, vv, rr, u, a0)
+            xx, vv, a0 = st["x"], st["v"], st["alpha"]
+        return time.perf_counter() - t0
+
+    oracle.set_num_threads(all_threads)
+    t = run(x, v, r, steps)
+    res.update(value=n * steps / t, cores=all_threads, seconds=round(t, 3),
+               sample=f"{steps} full steps of the {d['name']} workload ({n} granules), FP64 C oracle, "
+                      f"{all_threads} OpenMP threads")
+    m = n // 4
+    sel = np.argsort(x[0], kind="stable")[:m]
+    xs, vs, rs = np.ascontiguousarray(x[:, sel]), np.ascontiguousarray(v[:, sel]), r[sel]
+    oracle.set_num_threads(1)
+    t1 = run(xs, vs, rs, 1)
+    oracle.set_num_threads(all_threads)
+    res["single_thread"] = {"value": m / t1, "cores": 1, "seconds": round(t1, 3),
+                            "sample": f"1 step of the {m} granules with the smallest x of the {d['name']} workload"}
+    return res
 
 
 def main():
@@ -506,24 +611,20 @@ def main():
         log(f"[bench] {prec}: building state")
         sim = gic.Simulator(d["params"], d["x"], d["v"], d["r"], d["u"], prec, r_max=rmax)
         log(f"[bench] {prec}: timing {a.steps} steps after {a.warmup} warmup")
-        t_ev, t_wall = time_steps(sim, a.steps, a.warmup)
+        t_ev, t_wall, builds = time_steps(sim, a.steps, a.warmup)
         code, idx = sim.ctx.error()
         if code:
             log(f"[bench] {prec}: kernel error latched: code {code} index {idx}")
-        stages = time_stages(sim, max(3, min(a.steps, 10)))
+        stages, _ = time_stages(sim, max(3, min(a.steps, 10)))
         nodes = touched_nodes(sim)
-        out[prec] = dict(t=t_ev, wall=t_wall, stages=stages, nodes=nodes, err=code)
+        out[prec] = dict(t=t_ev, wall=t_wall, stages=stages, nodes=nodes, err=code, builds=builds)
         log(f"[bench] {prec}: {t_ev / a.steps * 1e3:.3f} ms/step  stages(ms) " +
-            " ".join(f"{k}={v * 1e3:.3f}" for k, v in stages.items()))
+            " ".join(f"{k}={v * 1e3:.3f}" for k, v in stages.items()) + f"  list builds {builds}")
         del sim
         torch.cuda.empty_cache()
     r32 = out["fp32"]
     value = n * a.steps / r32["t"]
-    # dominant kernel of the FP32 step
     st = r32["stages"]
-    dom = max(st, key=st.get)
-    abytes = stage_bytes(dom, n, r32["nodes"], 4)
-    achieved = abytes / st[dom] / 1e9
     line = {
         "metric": "granule-steps/s FP32 vs plain FP64 GPU path at 4M granules; bwd/fwd time",
         "value": value,
@@ -537,19 +638,32 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 forces / f64 state / i64 grids",
         "data": "synthetic",
-        "config": {"workload": f"{a.workload}: dam-break column, {n} granules r=1 mm, {d['params']['n']} grid "
-                               f"dx={d['params']['dx']}, dt={d['params']['dt']}", "granules": n, "grid_nodes": G,
-                   "parallelism": "single GPU"},
+        "config": {"workload": WORKLOAD_TEXT[a.workload](d) if a.workload in WORKLOAD_TEXT else a.workload,
+                   "granules": n, "grid_nodes": G, "parallelism": "single GPU"},
         "stages_ms": {k: round(v * 1e3, 4) for k, v in st.items()},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(dom, a.workload),
-                     "algorithmic_bytes": abytes},
+        "neighbour_builds": r32["builds"],
+        "roofline": dominant_roofline(st, n, r32["nodes"], 4, a.workload),
+        "stage_rooflines": stage_rooflines(st, n, r32["nodes"], 4),
     }
     if "fp64" in out:
         r64 = out["fp64"]
         line["fp64_value"] = n * a.steps / r64["t"]
         line["fp32_over_fp64"] = line["value"] / line["fp64_value"]
         line["fp64_stages_ms"] = {k: round(v * 1e3, 4) for k, v in r64["stages"].items()}
+    if not a.no_error:
+        log("[bench] FP32 form against the plain FP64 path, per output")
+        line["fp32_error"] = {a.workload: fp32_error(d, rmax)}
+        if not a.no_c2:
+            d2 = wl.make("c2")
+            line["fp32_error"]["c2"] = fp32_error(d2, float(d2["r"].max()))
+            del d2
+        torch.cuda.empty_cache()
+    if not a.no_c2:
+        log("[bench] c2: polydisperse moving bed, 100 steps")
+        line["c2"] = run_leg("c2", 100, 3, with_fp64=True)
+    if not a.no_c5:
+        log("[bench] c5: large bed, 20 steps")
+        line["c5"] = run_leg("c5", 20, 2)
     if not a.no_coupled:
         log("[bench] coupled: remaining interphase forces and exchange, sand steps of 4 sub-steps")
         line["coupled"] = time_coupled(d, a.workload)
@@ -566,7 +680,7 @@ def main():
         log("[bench] adjoint: forward and backward of the c4 rollout")
         line["bwd_fwd"] = time_adjoint()
     if not a.no_cpu:
-        log(f"[bench] cpu baseline: {a.cpu_steps} oracle steps")
+        log(f"[bench] cpu baseline: {a.cpu_steps} oracle steps, all threads; a quarter slab on one thread")
         line["cpu_baseline"] = cpu_baseline(d, a.cpu_steps)
     print(json.dumps(line), flush=True)
 

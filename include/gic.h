@@ -206,13 +206,29 @@ gic_status gic_reorder(gic_ctx *ctx, int64_t n, const int32_t *order, const doub
  * overlap is R - d in double (plain form) or (R^2 - d^2) / (R + d) with the
  * cancelling difference R^2 - d^2 in double and the quotient in float (FP32
  * form); the pair force arithmetic and the per-granule sum are in the
- * form's real type.
+ * form's real type, over the touching partners in the order of their cells
+ * (z, then y, then x) and of their sorted positions inside a cell, then the
+ * walls.  The call builds the context's neighbour list (every granule closer
+ * than r_i + r_j + skin, in that order; see gic_step) and evaluates the
+ * forces from it.
  *   x, v, r     sorted order (see Conventions).
  *   f_contact   out, 3n real: force per granule [N].
- *   n_contacts  out (optional, NULL = skip), n: touching partners + walls. */
+ *   n_contacts  out (optional, NULL = skip), n: touching partners + walls.
+ *   pair_ids    out (optional, NULL = skip), pair_cap x n int32,
+ *               column-major: pair_ids[k n + q] is the sorted position of
+ *               the k-th partner touching granule q (k < pair_cap), in the
+ *               order its force is summed, then -1 up to pair_cap; the pair
+ *               set is the exact test's, from the same kernel that sums the
+ *               forces.
+ *   pair_cap    entries per granule in pair_ids (0 with pair_ids NULL). */
 gic_status gic_contact_forces(gic_ctx *ctx, int64_t n, const double *x, const double *v, const double *r,
                               const int32_t *cell_begin, const int32_t *cell_end, void *f_contact,
-                              int32_t *n_contacts, void *stream);
+                              int32_t *n_contacts, int32_t *pair_ids, int32_t pair_cap, void *stream);
+
+/* Number of neighbour-list builds on this context so far (gic_contact_forces
+ * builds once per call, gic_step and gic_sand_step when their list must be
+ * rebuilt).  Synchronises the stream. */
+gic_status gic_neighbour_builds(gic_ctx *ctx, void *stream, int64_t *builds);
 
 /* ---- f3: moisture ratio (Sec. 5.4, the definition following Eq. 26) -------
  * sr_i = held_i + alpha_f,i / (1 - alpha_f,i): the water granule i holds
@@ -252,13 +268,6 @@ gic_status gic_contact_capillary_forces(gic_ctx *ctx, int64_t n, const double *x
                                         const double *r, const void *sr, const double *held,
                                         const int32_t *cell_begin, const int32_t *cell_end, void *f_contact,
                                         int32_t *n_contacts, void *stream);
-
-/* Touching pairs (q, j) with q < j in sorted positions, for checks of the
- * neighbour search.  Writes up to cap pairs to pairs[2*k], pairs[2*k+1];
- * *count (device int64, zeroed by the call) receives the total number. */
-gic_status gic_contact_pairs(gic_ctx *ctx, int64_t n, const double *x, const double *r,
-                             const int32_t *cell_begin, const int32_t *cell_end, int32_t *pairs, int64_t cap,
-                             int64_t *count, void *stream);
 
 /* ---- a5: G2P of fluid velocity and fraction (Sec. 5.2; Sec. 5.1 clamp) ----
  * Quadratic B-spline on cell-centred nodes, out-of-range nodes folded onto
@@ -347,12 +356,37 @@ gic_status gic_integrate_p2g_wet(gic_ctx *ctx, int64_t n, double *x, double *v, 
  * int32), cell_begin, cell_end (K int32), f_contact, f_drag (3n real; they
  * hold the step's forces afterwards); u_at (3n real) and alpha_f (n real)
  * receive the sampled fluid velocity and fraction, or are skipped when
- * NULL. */
+ * NULL.
+ * Neighbour list: the contact stage keeps the context's list of every pair
+ * closer than r_i + r_j + skin (skin = min(r_max / 10, cell - 2 r_max)) from
+ * one step to the next while x_cur is the x_nxt of the previous gic_step on
+ * this context with the same n, the sort finds no changed cell key and no
+ * granule has moved by skin / 2 since the list was built (measured on the
+ * device from the positions of the build); otherwise the step rebuilds it.
+ * The exact contact test runs on every listed pair every step, and a
+ * granule's forces are summed over its touching partners in cell order
+ * either way, so f_contact is the same bits as gic_contact_forces on the
+ * sorted state.  Calls of gic_sort_cells or gic_contact_forces on the
+ * context, gic_set_params, or radii changed by the caller between steps:
+ * the first two and the third make the next step rebuild; radii must only
+ * change through new arrays (x_cur then differs) or gic_set_params. */
 gic_status gic_step(gic_ctx *ctx, int64_t n, const double *x_cur, const double *v_cur, const double *r_cur,
                     const int32_t *id_cur, double *x_nxt, double *v_nxt, double *r_nxt, int32_t *id_nxt,
                     const void *u, int64_t *alpha_fx, int64_t *mom_fx, uint32_t *key, int32_t *order,
                     int32_t *cell_begin, int32_t *cell_end, void *f_contact, void *f_drag, void *u_at,
                     void *alpha_f, void *stream);
+
+/* Stage timing of gic_step and gic_sand_step for measurement: with
+ * max_steps > 0 the next max_steps (sub-)steps record HIP events on their
+ * stream between their stages (creates the events; 0 switches timing off and
+ * destroys them).  gic_stage_times synchronises the stream and returns, over
+ * the (sub-)steps recorded since the last call, the summed milliseconds of
+ * ms[0] sort (keys, sort, cell ranges, brick list), ms[1] gather + G2P +
+ * fluid force, ms[2] contact (neighbour-list build when needed, forces),
+ * ms[3] exchange deposit (0 in gic_step), ms[4] grid clear, ms[5] integrate
+ * + P2G; *steps receives their number. */
+gic_status gic_stage_timing(gic_ctx *ctx, int32_t max_steps);
+gic_status gic_stage_times(gic_ctx *ctx, void *stream, double *ms, int32_t *steps);
 
 /* ---- remaining interphase forces and the sand step -------------------------
  * gic_gather_g2p_fluid = gic_gather_g2p_drag with the whole fluid force of
@@ -456,6 +490,12 @@ gic_status gic_p2g_vjp(gic_ctx *ctx, int64_t n, const double *x, const double *v
  * or of a[i] b[i], i < n, summed in a fixed order (reproducible). */
 gic_status gic_sum(gic_ctx *ctx, int64_t n, const double *a, const double *b, double *out, int32_t accumulate,
                    void *stream);
+
+/* out[i] = (factor s[0]) a[i], i < n, with s a DEVICE scalar: e.g. the
+ * cotangent of the rollout loss L = sum P^2, dL/dP = (2 gL) P, formed
+ * without reading gL back to the host.  out may alias a. */
+gic_status gic_scale(gic_ctx *ctx, int64_t n, const double *a, const double *s, double factor, double *out,
+                     void *stream);
 
 /* Permute comps (1..3) planes of n doubles: scatter = 0: out[c n + q] =
  * in[c n + order[q]];  scatter = 1: out[c n + order[q]] = in[c n + q]. */

@@ -105,6 +105,7 @@ def _declare(L):
         "orc_cell_ranges": (None, [_pp, C.c_int64, _u32, _i32, _i32, _i32]),
         "orc_pairs_brute": (C.c_int64, [C.c_int64, _d, _d, C.c_int64, _i32, _i32]),
         "orc_pairs_cells": (C.c_int64, [_pp, C.c_int64, _d, _d, C.c_int64, _i32, _i32]),
+        "orc_pairs_sample": (None, [_pp, C.c_int64, _d, _d, C.c_int64, _i64, C.c_int64, _i32, _i32]),
         "orc_contact_forces": (None, [_pp, C.c_int64, _d, _d, _d, _d, _d, _i32, _i32]),
         "orc_contact_forces_sample": (None, [_pp, C.c_int64, _d, _d, _d, C.c_int64, _i64, _d, _d]),
         "orc_pair": (C.c_int, [_pp, _d, _d, _d, _d, C.c_double, C.c_double, _d, _i32]),
@@ -233,6 +234,19 @@ def pairs_cells(cfg, x, r):
     p = params(cfg)
     return _pairs(lib().orc_pairs_cells,
                   (C.byref(p), x.shape[1], _ptr(x, C.c_double), _ptr(r, C.c_double)), 8 * x.shape[1])
+
+
+def pairs_sample(cfg, x, r, idx, cap=64):
+    """Touching partners of the sampled granules idx: a list of sets."""
+    x, r = _f64(x), _f64(r)
+    idx = np.ascontiguousarray(idx, np.int64)
+    m = idx.shape[0]
+    part = np.zeros(m * cap, np.int32)
+    cnt = np.zeros(m, np.int32)
+    lib().orc_pairs_sample(C.byref(params(cfg)), x.shape[1], _ptr(x, C.c_double), _ptr(r, C.c_double), m,
+                           _ptr(idx, C.c_int64), cap, _ptr(part, C.c_int32), _ptr(cnt, C.c_int32))
+    assert cnt.max(initial=0) <= cap
+    return [set(part[s * cap:s * cap + cnt[s]].tolist()) for s in range(m)]
 
 
 # ---- contact force, Eq. (1a)-(1c) --------------------------------------------

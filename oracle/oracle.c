@@ -337,6 +337,36 @@ int64_t orc_pairs_cells(const orc_params *p, int64_t n, const double *x, const d
     return cnt;
 }
 
+/* Touching partners of sampled granules idx[0..m) through the cell list:
+ * the partners of idx[s] go to part[s cap + k] (k < cap, in candidate
+ * order), their number to cnt[s]. */
+void orc_pairs_sample(const orc_params *p, int64_t n, const double *x, const double *r, int64_t m,
+                      const int64_t *idx, int64_t cap, int32_t *part, int32_t *cnt)
+{
+    orc_cells cl;
+    orc_cells_build(p, n, x, &cl);
+    int64_t ccap = 27 * orc_cells_maxocc(p, &cl) + 1;
+#pragma omp parallel
+    {
+        int64_t *cand = (int64_t *)malloc(sizeof(int64_t) * (size_t)ccap);
+#pragma omp for schedule(static)
+        for (int64_t s = 0; s < m; ++s) {
+            int64_t i = idx[s], k = 0;
+            int64_t nc_ = orc_candidates(p, n, x, &cl, i, cand);
+            for (int64_t t = 0; t < nc_; ++t) {
+                double dv[3], d2;
+                if (orc_touch(n, x, r, i, cand[t], dv, &d2)) {
+                    if (k < cap) part[s * cap + k] = (int32_t)cand[t];
+                    ++k;
+                }
+            }
+            cnt[s] = (int32_t)k;
+        }
+        free(cand);
+    }
+    orc_cells_free(&cl);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Pair force, Eq. (1a)-(1c) with the dashpot reading                        */
 /* ------------------------------------------------------------------------ */

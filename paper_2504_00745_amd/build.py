@@ -19,7 +19,6 @@ HIPCC_FLAGS = [
     "-Wall", "-Wno-unused-result",
     # no packed FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-munsafe-fp-atomics",
 ]
 
 

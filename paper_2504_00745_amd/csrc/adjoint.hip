@@ -8,8 +8,9 @@
 // Every kernel reads its forward inputs and recomputes what it needs; the
 // contact pullback is a gather (granule i collects, for each touching
 // partner j, the pair term with cotangent g_i - g_j), so no atomics are used
-// except in the grid scatter of the G2P pullback (FP64 atomics into an LDS
-// tile per brick, then into the grid).
+// except in the grid scatter of the G2P pullback, which sums integers
+// (contributions rounded at the scale of the largest one; transfer.hip), so
+// every result is the same bits in every run.
 #include "gic_launch.hpp"
 
 namespace gic {
@@ -237,56 +238,6 @@ __global__ void __launch_bounds__(256) k_g2p_vjp_x(DevParams P, int64_t n, const
     for (int a = 0; a < 3; ++a) gx[a * n + q] += acc[a];
 }
 
-// Grid part of the G2P pullback: gA_k += -sum_i w_ik gaf_i for nodes below
-// the clamp.  One workgroup per brick, FP64 atomics into an LDS tile, then
-// into the grid.
-__global__ void __launch_bounds__(256) k_g2p_vjp_grid(DevParams P, int64_t n, const int32_t *__restrict__ bl,
-                                                      const int32_t *__restrict__ bcnt,
-                                                      const double *__restrict__ x, const double *__restrict__ A,
-                                                      const double *__restrict__ gaf,
-                                                      const int32_t *__restrict__ cb, const int32_t *__restrict__ ce,
-                                                      double *__restrict__ gA)
-{
-    extern __shared__ double tile[];
-    const int64_t b = brick_of_block(bl, bcnt);
-    if (b < 0) return;
-    int32_t beg = cb[b * kBrickCells], end = ce[b * kBrickCells + kBrickCells - 1];
-    clip_range(n, beg, end);
-    if (end <= beg) return;
-    const int E = P.tile;
-    const int E3 = E * E * E;
-    for (int k = threadIdx.x; k < E3; k += 256) tile[k] = 0.0;
-    int32_t o[3];
-    tile_origin(P, b, o);
-    __syncthreads();
-    for (int64_t q = beg + (int64_t)threadIdx.x; q < end; q += 256) {
-        const double xa[3] = {x[q], x[n + q], x[2 * n + q]};
-        Stencil s;
-        stencil_of(P, xa, s);
-        const double sg = -gaf[q];
-        for (int cz = 0; cz < 3; ++cz)
-            for (int cy = 0; cy < 3; ++cy)
-                for (int cx = 0; cx < 3; ++cx) {
-                    const int32_t ni = s.node[0][cx], nj = s.node[1][cy], nk = s.node[2][cz];
-                    const int64_t gidx = node_index(P, ni, nj, nk);
-                    if (!(A[gidx] < P.alpha_max)) continue;
-                    const double val = ((s.w[0][cx] * s.w[1][cy]) * s.w[2][cz]) * sg;
-                    const int32_t li = ni - o[0], lj = nj - o[1], lk = nk - o[2];
-                    if (li >= 0 && lj >= 0 && lk >= 0 && li < E && lj < E && lk < E)
-                        atomicAdd(&tile[(lk * E + lj) * E + li], val);
-                    else
-                        unsafeAtomicAdd(&gA[gidx], val);
-                }
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < E3; k += 256) {
-        const double val = tile[k];
-        if (val == 0.0) continue;
-        const int32_t ni = o[0] + k % E, nj = o[1] + (k / E) % E, nk = o[2] + k / (E * E);
-        unsafeAtomicAdd(&gA[node_index(P, ni, nj, nk)], val);
-    }
-}
-
 // P2G pullback (gather): gx += frac sum_k gA_k grad w_k + m sum_k (gP_k . v)
 // grad w_k;  gv += m sum_k w_k gP_k.
 __global__ void __launch_bounds__(256) k_p2g_vjp(DevParams P, int64_t n, const double *__restrict__ x,
@@ -358,6 +309,16 @@ __global__ void __launch_bounds__(256) k_final_sum(const double *__restrict__ pa
     }
 }
 
+// out = (factor s[0]) a, s a device scalar (a cotangent that stays on the
+// device).
+__global__ void __launch_bounds__(256) k_scale(int64_t n, const double *__restrict__ a, const double *__restrict__ sp,
+                                               double factor, double *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[i] = (factor * sp[0]) * a[i];
+}
+
 __global__ void __launch_bounds__(256) k_permute(int64_t n, int comps, const int32_t *__restrict__ order,
                                                  const double *__restrict__ in, double *__restrict__ out, int scatter)
 {
@@ -403,17 +364,11 @@ hipError_t launch_integrate_vjp(const DevParams &P, int64_t n, const double *r, 
 
 hipError_t launch_g2p_vjp(const DevParams &P, int64_t n, int64_t K, const double *x, const double *u,
                           const double *A, const double *guat, const double *gaf, const int32_t *cb,
-                          const int32_t *ce, const BrickList &B, double *gx, double *gA, hipStream_t s)
+                          const int32_t *ce, const BrickList &B, double *gx, double *gA, int64_t *fx, double *part,
+                          hipStream_t s)
 {
-    if (n == 0) return gA ? launch_fill_f64(gA, P.G, s) : hipSuccess;
-    k_g2p_vjp_x<<<grid_for(n, 256), 256, 0, s>>>(P, n, x, u, A, guat, gaf, gx);
-    if (gA) {
-        hipError_t e = launch_fill_f64(gA, P.G, s);
-        if (e != hipSuccess) return e;
-        const int64_t bricks = K / kBrickCells;
-        const size_t lds = sizeof(double) * (size_t)P.tile * P.tile * P.tile;
-        k_g2p_vjp_grid<<<brick_grid(bricks), 256, lds, s>>>(P, n, B.list, B.count, x, A, gaf, cb, ce, gA);
-    }
+    if (n > 0) k_g2p_vjp_x<<<grid_for(n, 256), 256, 0, s>>>(P, n, x, u, A, guat, gaf, gx);
+    if (gA) return launch_g2p_vjp_grid(P, n, K, x, A, gaf, cb, ce, B, gA, fx, part, s);
     return hipGetLastError();
 }
 
@@ -432,6 +387,13 @@ hipError_t launch_sum(const double *a, const double *b, int64_t n, double *part,
     const int nb = (int)(n > 0 ? (n + per - 1) / per : 0);
     if (nb > 0) k_partial_sums<<<nb, 256, 0, s>>>(a, b, n, per, part);
     k_final_sum<<<1, 256, 0, s>>>(part, nb, out, acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale(int64_t n, const double *a, const double *sp, double factor, double *out, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    k_scale<<<grid_for(n, 256), 256, 0, s>>>(n, a, sp, factor, out);
     return hipGetLastError();
 }
 

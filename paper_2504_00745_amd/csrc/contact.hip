@@ -1,13 +1,24 @@
 // a2 + a3: neighbour candidates and contact forces (Sec. 3.1, Eq. 1a-c) on
 // gfx950.
 //
-// One thread per granule in sorted order.  Each granule visits only the
-// neighbour cells its search box [x - (r_i + r_max), x + (r_i + r_max)]
-// overlaps (at most 27, typically 8 when the cell is twice the largest
-// diameter); candidates of a cell are contiguous in sorted order, so a wave's
-// candidate loads fall in a few cache lines.  The contact test, the overlap
-// and the normal are double in both forms (the overlap is a small difference
-// of nearly equal distances); the pair law and the per-granule sum run in T.
+// The dry contact runs in two kernels: a neighbour-list build (k_nbr_build,
+// one workgroup per brick, candidates from an LDS copy of the brick's cell
+// shell) that lists every granule closer than r_i + r_j + skin, and the
+// contact forces from that list (k_contact_list, one thread per granule),
+// which runs the exact double test of Sec. 3.1 on every listed partner each
+// step.  The stepping path builds the list only when the sorted order
+// changed or a granule moved by skin / 2 since the last build; a granule's
+// force sum runs over its touching partners in cell order either way, so the
+// forces do not depend on when the list was built.  The capillary
+// instantiation of k_contact_lds (candidates and forces in one brick kernel)
+// serves wet beds.
+//
+// Each granule visits only the neighbour cells its search box
+// [x - (r_i + r_max), x + (r_i + r_max)] overlaps (at most 27, typically 8
+// when the cell is twice the largest diameter); candidates of a cell are
+// contiguous in sorted order.  The contact test, the overlap and the normal
+// are double in both forms (the overlap is a small difference of nearly
+// equal distances); the pair law and the per-granule sum run in T.
 #include "gic_launch.hpp"
 
 namespace gic {
@@ -293,9 +304,8 @@ __device__ inline bool near_slot(float4 p, float mx, float my, float mz, float t
     return fmaf(mx, p.x, fmaf(my, p.y, fmaf(mz, p.z, p.w))) < thr;
 }
 
-// The bridge-force instantiation is held to four waves per SIMD (it needs one
-// register more than 128 and spills three); the dry one keeps its own
-// allocation (the hint value 1 puts no limit on it).
+// The bridge-force instantiation (the one launched) is held to four waves
+// per SIMD: it needs one register more than 128 and spills three.
 template <typename T, bool CAP>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CAP ? 4 : 1)))
 k_contact_lds(DevParams P, int64_t n, const int32_t *__restrict__ bl,
@@ -414,17 +424,14 @@ k_contact_lds(DevParams P, int64_t n, const int32_t *__restrict__ bl,
     }
     __syncthreads();
     const float M = (float)(P.cell * P.cell * (1.0 / 4096.0));
-    // ---- granules of the brick, 2^lg adjacent lanes per granule when the
-    // brick holds few (otherwise most waves of the workgroup would idle):
-    // lane `sub` of a granule takes rows sub, sub + L, ... of the search box,
-    // lists and evaluates its own partners, and the lanes' partial sums are
-    // added at the end ((s0 + s1) + (s2 + s3), the same in every lane).
-    const int32_t nq = ge - gb;
-    const int lg = nq <= 64 ? 2 : (nq <= 128 ? 1 : 0);
-    const int L = 1 << lg;
-    const int sub = tid & (L - 1);
-    for (int64_t qb = gb; qb < ge; qb += (256 >> lg)) {  // same trip count in every lane
-        const int64_t q = qb + (tid >> lg);
+    // ---- granules of the brick, one thread each: partners are taken in
+    // slot order (cells z, y, x; positions inside a cell), the order of the
+    // dry contact's neighbour list, so a bed without bridges gives the dry
+    // contact's bits
+    constexpr int L = 1;
+    constexpr int sub = 0;
+    for (int64_t qb = gb; qb < ge; qb += 256) {  // same trip count in every lane
+        const int64_t q = qb + tid;
         const bool live = q < ge;
         T acc[3] = {(T)0, (T)0, (T)0};
         int32_t nc = 0;
@@ -522,13 +529,7 @@ k_contact_lds(DevParams P, int64_t n, const int32_t *__restrict__ bl,
                 }
             }
         }
-        for (int m = 1; m < L; m <<= 1) {  // all lanes take part; groups of L lanes share q
-            acc[0] += __shfl_xor(acc[0], m);
-            acc[1] += __shfl_xor(acc[1], m);
-            acc[2] += __shfl_xor(acc[2], m);
-            nc += __shfl_xor(nc, m);
-        }
-        if (live && sub == 0) {
+        if (live) {
             if (!bad) add_walls<T>(P, xi, vi, ri, mi, acc, nc);
             F[q] = acc[0];
             F[n + q] = acc[1];
@@ -538,34 +539,285 @@ k_contact_lds(DevParams P, int64_t n, const int32_t *__restrict__ bl,
     }
 }
 
-__global__ void __launch_bounds__(256) k_contact_pairs(DevParams P, int64_t n, const double *__restrict__ x,
-                                                       const double *__restrict__ r,
-                                                       const int32_t *__restrict__ cb,
-                                                       const int32_t *__restrict__ ce, int32_t *pairs, int64_t cap,
-                                                       unsigned long long *count)
+// ---------------------------------------------------------------------------
+// Neighbour list.  The list build stages the brick's shell in LDS like the
+// contact kernel above, with every radius grown by skin / 2, and keeps, in
+// slot order (cells z, y, x; positions inside a cell), every shell granule
+// that passes the three-FMA test and then a single-precision distance test
+// d^2 < (r_i + r_j + skin)^2 + M (same margin M: the float evaluation errs
+// by less than M / 8), so the list holds every pair closer than
+// r_i + r_j + skin.  One thread per granule, so the order is canonical: the
+// touching pairs of two lists built from the same sorted order (whatever the
+// positions) come in the same order, and the forces summed over them are the
+// same bits.
+constexpr int kNbrThreads = 256;
+
+// Partners of granule q by a search of its cells in global memory (shells
+// that do not fit in LDS), exact double test with the skin; the same order.
+__device__ inline int nbr_global(const DevParams &P, int64_t n, const double *__restrict__ x,
+                                 const double *__restrict__ r, const int32_t *__restrict__ cb,
+                                 const int32_t *__restrict__ ce, int64_t q, const double xi[3], double ri,
+                                 double skin, int32_t *__restrict__ nbr)
 {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n) return;
-    const double xi[3] = {x[q], x[n + q], x[2 * n + q]};
-    const double ri = r[q];
-    const double Rs = (ri + P.r_max) * P.search_scale;
+    const double Rs = (ri + P.r_max + skin) * P.search_scale;
     int32_t lo[3], hi[3];
     for (int a = 0; a < 3; ++a) search_range(P, xi[a], Rs, P.nc[a], lo[a], hi[a]);
+    int cnt = 0;
     for_each_run(P, n, lo, hi, cb, ce, [&](int32_t jb, int32_t je) {
         for (int32_t j = jb; j < je; ++j) {
-            if (j <= q) continue;
+            if (j == q) continue;
             double d2;
-            if (!touching(xi[0] - x[j], xi[1] - x[n + j], xi[2] - x[2 * n + j], ri + r[j], d2)) continue;
-            unsigned long long k = atomicAdd(count, 1ull);
-            if ((int64_t)k < cap) {
-                pairs[2 * k] = (int32_t)q;
-                pairs[2 * k + 1] = j;
-            }
+            if (!touching(xi[0] - x[j], xi[1] - x[n + j], xi[2] - x[2 * n + j], ri + r[j] + skin, d2)) continue;
+            if (cnt < kNbrCap) nbr[(int64_t)cnt * n + q] = j;
+            ++cnt;
         }
     });
+    return cnt;
 }
 
-__global__ void k_zero_count(unsigned long long *c) { *c = 0ull; }
+__global__ void __launch_bounds__(kNbrThreads) k_nbr_build(DevParams P, int64_t n, const int32_t *__restrict__ bl,
+                                                           const int32_t *__restrict__ bcnt, int cap,
+                                                           const double *__restrict__ x, const double *__restrict__ r,
+                                                           const int32_t *__restrict__ cb,
+                                                           const int32_t *__restrict__ ce, int32_t *__restrict__ nbr,
+                                                           int32_t *__restrict__ ncnt, float *__restrict__ xref,
+                                                           uint32_t *__restrict__ ctl, int force, double skin,
+                                                           int64_t *err)
+{
+    if (!force && !ctl[0]) return;  // the list of the last build still holds every pair that can touch
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&ctl[2], 1u);  // builds, for the caller's statistics
+    extern __shared__ float4 smem4[];
+    float4 *spos = smem4;                                                 // [cap + kCand] (p, Q)
+    float *srad = reinterpret_cast<float *>(spos + cap + kCand);          // [cap] radius + skin / 2
+    uint16_t *plist = reinterpret_cast<uint16_t *>(srad + cap);           // [kNbrCap][256] listed slots
+    int32_t *clo = reinterpret_cast<int32_t *>(plist + kNbrCap * kNbrThreads);  // [216] first slot of each cell
+    int32_t *cnum = clo + kHaloCells;                                     // [216] granules of each shell cell
+    int32_t *cgb = cnum + kHaloCells;                                     // [216] global begin of each shell cell
+    int32_t *s_wave = cgb + kHaloCells;                                   // [4]
+    uint8_t *scell = reinterpret_cast<uint8_t *>(s_wave + 4);             // [cap] shell cell of each slot
+    const int tid = threadIdx.x;
+    const int64_t b = brick_of_block(bl, bcnt);
+    if (b < 0) return;
+    const int32_t bc[3] = {(int32_t)(b % P.nb[0]), (int32_t)((b / P.nb[0]) % P.nb[1]),
+                           (int32_t)(b / ((int64_t)P.nb[0] * P.nb[1]))};
+    const int32_t c0[3] = {bc[0] * kBrick - 1, bc[1] * kBrick - 1, bc[2] * kBrick - 1};
+    int32_t gb = cb[b * kBrickCells], ge = ce[b * kBrickCells + kBrickCells - 1];
+    clip_range(n, gb, ge);
+    if (ge <= gb) return;
+    const double o[3] = {(c0[0] + 3) * P.cell, (c0[1] + 3) * P.cell, (c0[2] + 3) * P.cell};
+    int32_t num = 0, gbeg = 0;
+    if (tid < kHaloCells) {
+        const int hx = tid % 6, hy = (tid / 6) % 6, hz = tid / 36;
+        const int32_t cx = c0[0] + hx, cy = c0[1] + hy, cz = c0[2] + hz;
+        if (cx >= 0 && cy >= 0 && cz >= 0 && cx < P.nc[0] && cy < P.nc[1] && cz < P.nc[2]) {
+            const uint32_t k = key_of_cell(P, cx, cy, cz);
+            int32_t e = ce[k];
+            gbeg = cb[k];
+            clip_range(n, gbeg, e);
+            num = e - gbeg;
+        }
+    }
+    const int32_t slots = tid < kHaloCells ? num + kPad : 0;
+    int32_t first = 0;
+    {
+        const int lane = tid & 63, wave = tid >> 6;
+        int32_t incl = slots;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int32_t t = __shfl_up(incl, off);
+            if (lane >= off) incl += t;
+        }
+        if (lane == 63) s_wave[wave] = incl;
+        __syncthreads();
+        int32_t before = 0;
+        for (int w = 0; w < wave; ++w) before += s_wave[w];
+        first = before + incl - slots;
+        if (tid < kHaloCells) {
+            clo[tid] = first;
+            cnum[tid] = num;
+            cgb[tid] = gbeg;
+        }
+    }
+    const int32_t H = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+    if (H > cap) {  // shell too large for LDS: search the cells in global memory
+        for (int64_t q = gb + tid; q < ge; q += kNbrThreads) {
+            const double xi[3] = {x[q], x[n + q], x[2 * n + q]};
+            const double ri = r[q];
+            if (ri > P.r_max) raise_error(err, kErrRange, q);
+            ncnt[q] = nbr_global(P, n, x, r, cb, ce, q, xi, ri, skin, nbr);
+            for (int a = 0; a < 3; ++a) xref[a * n + q] = (float)xi[a];
+        }
+        return;
+    }
+    if (tid < kHaloCells)
+        for (int32_t k = first; k < first + slots; ++k) scell[k] = (uint8_t)tid;
+    __syncthreads();
+    const float hskin = (float)(0.5 * skin);
+    {
+        double gx[kCopyRounds], gy[kCopyRounds], gz[kCopyRounds], gr[kCopyRounds];
+        bool real[kCopyRounds];
+#pragma unroll
+        for (int it = 0; it < kCopyRounds; ++it) {
+            const int k = tid + it * kNbrThreads;
+            real[it] = false;
+            gx[it] = gy[it] = gz[it] = gr[it] = 0.0;
+            if (k < H) {
+                const int c = scell[k];
+                const int off = k - clo[c];
+                if (off < cnum[c]) {
+                    const int64_t g = cgb[c] + off;
+                    gx[it] = x[g];
+                    gy[it] = x[n + g];
+                    gz[it] = x[2 * n + g];
+                    gr[it] = r[g];
+                    real[it] = true;
+                }
+            }
+        }
+#pragma unroll
+        for (int it = 0; it < kCopyRounds; ++it) {
+            const int k = tid + it * kNbrThreads;
+            if (k >= H) continue;
+            float4 p;
+            float rg = 0.0f;
+            if (real[it]) {
+                const float px = (float)(gx[it] - o[0]), py = (float)(gy[it] - o[1]), pz = (float)(gz[it] - o[2]);
+                rg = (float)gr[it] + hskin;
+                p = make_float4(px, py, pz, ((px * px + py * py) + pz * pz) - 2.0f * (rg * rg));
+            } else {
+                const float nan = __builtin_nanf("");
+                p = make_float4(nan, nan, nan, nan);
+            }
+            spos[k] = p;
+            srad[k] = rg;
+        }
+    }
+    __syncthreads();
+    const float M = (float)(P.cell * P.cell * (1.0 / 4096.0));
+    for (int64_t q = gb + tid; q < ge; q += kNbrThreads) {
+        const double xi[3] = {x[q], x[n + q], x[2 * n + q]};
+        const double ri = r[q];
+        if (ri > P.r_max) raise_error(err, kErrRange, q);
+        for (int a = 0; a < 3; ++a) xref[a * n + q] = (float)xi[a];
+        const float ax = (float)(xi[0] - o[0]), ay = (float)(xi[1] - o[1]), az = (float)(xi[2] - o[2]);
+        const float rf = (float)ri + hskin;
+        const float thr = M - (((ax * ax + ay * ay) + az * az) - 2.0f * (rf * rf));
+        const float mx = -2.0f * ax, my = -2.0f * ay, mz = -2.0f * az;
+        const double Rs = (ri + P.r_max + skin) * P.search_scale;
+        int32_t lo[3], hi[3], ca[3];
+        for (int a = 0; a < 3; ++a) {
+            ca[a] = cell_coord(xi[a], P.inv_cell, P.nc[a]) - c0[a];
+            search_range(P, xi[a], Rs, P.nc[a], lo[a], hi[a]);
+            lo[a] -= c0[a];
+            hi[a] -= c0[a];
+        }
+        if (ca[0] < 1 || ca[0] > 4 || ca[1] < 1 || ca[1] > 4 || ca[2] < 1 || ca[2] > 4) {
+            // the cell ranges do not match the positions
+            raise_error(err, kErrRange, q);
+            ncnt[q] = 0;
+            continue;
+        }
+        const int own = (ca[2] * 6 + ca[1]) * 6 + ca[0];
+        const int32_t qoff = (int32_t)(q - cgb[own]);
+        const int kself = qoff >= 0 && qoff < cnum[own] ? clo[own] + qoff : -1;
+        int32_t cnt = 0;
+        for (int hz = lo[2]; hz <= hi[2]; ++hz)
+            for (int hy = lo[1]; hy <= hi[1]; ++hy) {
+                const int c = (hz * 6 + hy) * 6;
+                const int k0 = clo[c + lo[0]];
+                const int k1 = clo[c + hi[0]] + cnum[c + hi[0]];
+                for (int k = k0; k < k1; k += kCand) {
+                    float4 p[kCand];
+#pragma unroll
+                    for (int u = 0; u < kCand; ++u) p[u] = spos[k + u];
+#pragma unroll
+                    for (int u = 0; u < kCand; ++u) {
+                        if (k + u >= k1 || k + u == kself || !near_slot(p[u], mx, my, mz, thr)) continue;
+                        const float ex = ax - p[u].x, ey = ay - p[u].y, ez = az - p[u].z;
+                        const float rs = rf + srad[k + u];
+                        if (!(((ex * ex + ey * ey) + ez * ez) < rs * rs + M)) continue;
+                        if (cnt < kNbrCap) plist[cnt * kNbrThreads + tid] = (uint16_t)(k + u);
+                        ++cnt;
+                    }
+                }
+            }
+        ncnt[q] = cnt;
+        const int listed = cnt < kNbrCap ? cnt : kNbrCap;
+        for (int k = 0; k < listed; ++k) {
+            const int slot = plist[k * kNbrThreads + tid];
+            const int c = scell[slot];
+            nbr[(int64_t)k * n + q] = cgb[c] + (slot - clo[c]);
+        }
+    }
+}
+
+// Contact forces from the neighbour list: one thread per granule in sorted
+// order (each XCD one contiguous eighth, so partners mostly share its L2);
+// the listed partners' double state is fetched kListBatch at a time so their
+// loads overlap, and each runs the exact test of Sec. 3.1 and, if touching,
+// Eq. (1); walls last.  A granule whose partners did not fit in its list
+// searches its cells in the same order.
+constexpr int kListBatch = 2;
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_contact_list(DevParams P, int64_t n, int64_t nblk,
+                                                      const double *__restrict__ x, const double *__restrict__ v,
+                                                      const double *__restrict__ r, const int32_t *__restrict__ cb,
+                                                      const int32_t *__restrict__ ce,
+                                                      const int32_t *__restrict__ nbr,
+                                                      const int32_t *__restrict__ ncnt, T *__restrict__ F,
+                                                      int32_t *__restrict__ ncont, int32_t *__restrict__ pairs,
+                                                      int pair_cap, int64_t *err)
+{
+    const int64_t lb = xcd_block(nblk);
+    if (lb < 0) return;
+    const int64_t q = lb * 256 + threadIdx.x;
+    if (q >= n) return;
+    const double xi[3] = {x[q], x[n + q], x[2 * n + q]};
+    const double vi[3] = {v[q], v[n + q], v[2 * n + q]};
+    const double ri = r[q];
+    const int32_t cnt = ncnt[q];
+    if (ri > P.r_max) raise_error(err, kErrRange, q);
+    const double mi = mass_of(P, ri);
+    T acc[3] = {(T)0, (T)0, (T)0};
+    int32_t nc = 0, np = 0;
+    auto take = [&](int32_t j, const Partner &p) {
+        if (exact_pair<T, false>(P, xi, vi, ri, mi, q, j, p, (T)0, nullptr, nullptr, acc)) {
+            ++nc;
+            if (pairs && np < pair_cap) pairs[(int64_t)np * n + q] = j;
+            ++np;
+        }
+    };
+    if (cnt <= kNbrCap) {
+        for (int k = 0; k < cnt; k += kListBatch) {
+            int32_t j[kListBatch];
+            Partner p[kListBatch];
+#pragma unroll
+            for (int u = 0; u < kListBatch; ++u) {
+                const int32_t jj = k + u < cnt ? nbr[(int64_t)(k + u) * n + q] : -1;
+                j[u] = (uint32_t)jj < (uint32_t)n ? jj : -1;  // a list entry outside [0, n) is skipped
+            }
+#pragma unroll
+            for (int u = 0; u < kListBatch; ++u) p[u] = fetch_partner(n, x, v, r, j[u] >= 0 ? j[u] : (int32_t)q);
+#pragma unroll
+            for (int u = 0; u < kListBatch; ++u)
+                if (j[u] >= 0) take(j[u], p[u]);
+        }
+    } else {
+        const double Rs = (ri + P.r_max) * P.search_scale;
+        int32_t lo[3], hi[3];
+        for (int a = 0; a < 3; ++a) search_range(P, xi[a], Rs, P.nc[a], lo[a], hi[a]);
+        for_each_run(P, n, lo, hi, cb, ce, [&](int32_t jb, int32_t je) {
+            for (int32_t jj = jb; jj < je; ++jj) take(jj, fetch_partner(n, x, v, r, jj));
+        });
+    }
+    add_walls<T>(P, xi, vi, ri, mi, acc, nc);
+    F[q] = acc[0];
+    F[n + q] = acc[1];
+    F[2 * n + q] = acc[2];
+    if (ncont) ncont[q] = nc;
+    if (pairs)
+        for (int k = np; k < pair_cap; ++k) pairs[(int64_t)k * n + q] = -1;
+}
 
 }  // namespace
 
@@ -586,13 +838,10 @@ hipError_t launch_contact(const DevParams &P, int64_t n, const double *x, const 
     if (n == 0) return hipSuccess;
     const int64_t nbricks = (int64_t)P.nb[0] * P.nb[1] * P.nb[2];
     const int cap = 1948;  // shell slots held in LDS: 40,908 bytes, four workgroups per CU
-    if (sr)
-        k_contact_lds<T, true><<<brick_grid(nbricks), 256, contact_lds_bytes(cap), s>>>(P, n, B.list, B.count, cap, x,
-                                                                                       v, r, cb, ce, sr, held, F,
-                                                                                       ncont, err);
-    else
-        k_contact_lds<T, false><<<brick_grid(nbricks), 256, contact_lds_bytes(cap), s>>>(
-            P, n, B.list, B.count, cap, x, v, r, cb, ce, sr, nullptr, F, ncont, err);
+    if (!sr) return hipErrorInvalidValue;  // the dry contact runs from the neighbour list
+    k_contact_lds<T, true><<<brick_grid(nbricks), 256, contact_lds_bytes(cap), s>>>(P, n, B.list, B.count, cap, x, v,
+                                                                                   r, cb, ce, sr, held, F, ncont,
+                                                                                   err);
     return hipGetLastError();
 }
 
@@ -605,14 +854,42 @@ template hipError_t launch_contact<double>(const DevParams &, int64_t, const dou
                                            const double *, const double *, double *, int32_t *, int64_t *,
                                            hipStream_t);
 
-hipError_t launch_contact_pairs(const DevParams &P, int64_t n, const double *x, const double *r,
-                                const int32_t *cb, const int32_t *ce, int32_t *pairs, int64_t cap,
-                                int64_t *count, hipStream_t s)
+// LDS bytes of the neighbour-list build for a shell capacity of cap granules.
+static size_t nbr_lds_bytes(int cap)
 {
-    unsigned long long *c = reinterpret_cast<unsigned long long *>(count);
-    k_zero_count<<<1, 1, 0, s>>>(c);
-    if (n > 0) k_contact_pairs<<<grid_for(n, 256), 256, 0, s>>>(P, n, x, r, cb, ce, pairs, cap, c);
+    return (size_t)(cap + kCand) * sizeof(float4) + (size_t)cap * sizeof(float) +
+           sizeof(uint16_t) * kNbrCap * kNbrThreads + sizeof(int32_t) * (kHaloCells * 3 + 4) + (size_t)cap;
+}
+
+hipError_t launch_nbr_build(const DevParams &P, int64_t n, const double *x, const double *r, const int32_t *cb,
+                            const int32_t *ce, const BrickList &B, NbrList &L, int force, int64_t *err,
+                            hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const int64_t nbricks = (int64_t)P.nb[0] * P.nb[1] * P.nb[2];
+    const int cap = 1948;  // shell slots in LDS: 51,772 bytes, three workgroups per CU
+    k_nbr_build<<<brick_grid(nbricks), kNbrThreads, nbr_lds_bytes(cap), s>>>(
+        P, n, B.list, B.count, cap, x, r, cb, ce, L.nbr, L.cnt, L.xref, L.ctl, force, L.skin, err);
     return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_contact_list(const DevParams &P, int64_t n, const double *x, const double *v, const double *r,
+                               const int32_t *cb, const int32_t *ce, const NbrList &L, T *F, int32_t *ncont,
+                               int32_t *pairs, int pair_cap, int64_t *err, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const int64_t nblk = (n + 255) / 256;
+    k_contact_list<T><<<xcd_grid(nblk), 256, 0, s>>>(P, n, nblk, x, v, r, cb, ce, L.nbr, L.cnt, F, ncont, pairs,
+                                                      pair_cap, err);
+    return hipGetLastError();
+}
+
+template hipError_t launch_contact_list<float>(const DevParams &, int64_t, const double *, const double *,
+                                               const double *, const int32_t *, const int32_t *, const NbrList &,
+                                               float *, int32_t *, int32_t *, int, int64_t *, hipStream_t);
+template hipError_t launch_contact_list<double>(const DevParams &, int64_t, const double *, const double *,
+                                                const double *, const int32_t *, const int32_t *, const NbrList &,
+                                                double *, int32_t *, int32_t *, int, int64_t *, hipStream_t);
 
 }  // namespace gic

@@ -20,7 +20,29 @@ struct gic_ctx {
     BrickList bricks;  // device: occupied bricks of the last cell ranges given
     bool in_step;      // inside gic_step, which builds the brick list once
     int device;
+    int64_t *fxs;      // device: 4 G int64, integer sums of the unquantised transfers
+    double *fxp;       // device: 4 x 1024 partial maxima (their scales)
+    NbrList nl;        // device: neighbour list of the stepping path
+    // The list holds the stepping path's state when nl_n == n and the state
+    // to step is the array that the last step wrote (nl_x): its sorted
+    // order is the one of the list's last build or check.
+    int64_t nl_n;
+    const double *nl_x;
+    // The cell tables rng_cb, rng_ce hold the ranges of the last sort on the
+    // context, and the brick list is theirs (set by the stepping calls,
+    // cleared by any other call that sorts or builds a brick list).
+    bool rng_ok;
+    const int32_t *rng_cb, *rng_ce;
+    // stage timing of gic_step / gic_sand_step (gic_stage_timing): events
+    // recorded on the step's stream between its stages, kStageEvents per step
+    int tm_cap, tm_used;
+    hipEvent_t *tm_ev;
 };
+
+// Events per timed (sub-)step: start, after the sort and brick list, after
+// the gather, after the contact, after the exchange deposit, after the grid
+// clear, after integrate + P2G.
+constexpr int kStageEvents = 7;
 
 namespace {
 
@@ -40,6 +62,25 @@ double rupture_max(const gic_params *p)
     const double V = p->vbridge * (((4.0 * GIC_PI / 3.0) * p->r_max) * p->r_max) * p->r_max;
     const double t = cbrt(V);
     return t + 0.1 * (t * t);
+}
+
+// Reach of the stepping path's neighbour list beyond r_i + r_j: a tenth of
+// the largest radius, as far as the cells allow (cell >= 2 r_max + skin keeps
+// every listed pair inside the 27 cells); 0 when the cells are exactly
+// 2 r_max, and the list is then rebuilt every step.
+void nbr_reach(const gic_params *p, NbrList &L)
+{
+    const double room = p->cell - 2.0 * p->r_max;
+    double skin = 0.1 * p->r_max;
+    if (skin > room) skin = room;
+    if (!(skin > 0.0)) skin = 0.0;
+    L.skin = skin;
+    // rebuild when a granule has moved by skin / 2 since the build, less the
+    // rounding of the single-precision positions kept at the build
+    double lmax = 0.0;
+    for (int a = 0; a < 3; ++a) lmax = fmax(lmax, (double)p->n[a] * p->dx);
+    const double thr = 0.5 * skin - lmax * (1.0 / 1048576.0);
+    L.thr2 = thr > 0.0 ? (float)(thr * thr) : -1.0f;
 }
 
 bool params_valid(const gic_params *p)
@@ -152,7 +193,26 @@ constexpr int kSumParts = 1024;
 hipError_t brick_list(gic_ctx *c, const int32_t *cb, const int32_t *ce, hipStream_t s)
 {
     if (c->in_step) return hipSuccess;
+    c->rng_ok = false;  // the brick list is now that of these tables
     return launch_brick_list(cb, ce, c->bricks, s);
+}
+
+// Sort of a stepping call: keeps the neighbour list when the last step's
+// state continues (force = 0) and the cell tables and brick list when the
+// tables are the last step's and no key changed.
+hipError_t step_sort(gic_ctx *c, int64_t n, const double *x, uint32_t *key, int32_t *order, int32_t *cb, int32_t *ce,
+                     int force, hipStream_t s)
+{
+    const int keep = c->rng_ok && c->rng_cb == cb && c->rng_ce == ce && c->sort.last_n == n ? 1 : 0;
+    c->rng_ok = false;
+    hipError_t e = launch_sort_cells(c->dp, n, x, key, order, cb, ce, c->K, c->sort, c->err, s, &c->nl, force, keep);
+    if (e == hipSuccess && n > 0) e = launch_brick_list(cb, ce, c->bricks, s, keep ? c->sort.ctl : nullptr);
+    if (e == hipSuccess) {
+        c->rng_ok = true;
+        c->rng_cb = cb;
+        c->rng_ce = ce;
+    }
+    return e;
 }
 
 // Density-projection workspace: alpha_f', s, r, d, w, 1/diag (G doubles
@@ -288,11 +348,14 @@ gic_status gic_create(const gic_params *p, int64_t n_max, gic_ctx **out)
     ok &= hipMalloc(&c->sort.chg, sizeof(uint64_t) * kChgCap) == hipSuccess;
     ok &= hipMalloc(&c->sort.chg_s, sizeof(uint64_t) * kChgCap) == hipSuccess;
     ok &= hipMalloc(&c->sort.chg_p, sizeof(uint32_t) * kChgCap) == hipSuccess;
-    ok &= hipMalloc(&c->sort.ctl, sizeof(int32_t) * 2) == hipSuccess;
-    if (ok) ok = hipMemset(c->sort.ctl, 0, sizeof(int32_t) * 2) == hipSuccess;
+    ok &= hipMalloc(&c->sort.ctl, sizeof(int32_t) * 4) == hipSuccess;
+    if (ok) ok = hipMemset(c->sort.ctl, 0, sizeof(int32_t) * 4) == hipSuccess;
     ok &= hipMalloc(&c->sort.vA, sizeof(int32_t) * nn) == hipSuccess;
     ok &= hipMalloc(&c->sort.vB, sizeof(int32_t) * nn) == hipSuccess;
-    ok &= hipMalloc(&c->sort.hist, sizeof(uint32_t) * 256 * tiles) == hipSuccess;
+    ok &= hipMalloc(&c->sort.ghist, sizeof(uint32_t) * (4 * 256 + 4)) == hipSuccess;
+    ok &= hipMalloc(&c->sort.flags, sizeof(uint64_t) * 4 * 256 * tiles) == hipSuccess;
+    if (ok) ok = hipMemset(c->sort.flags, 0, sizeof(uint64_t) * 4 * 256 * tiles) == hipSuccess;
+    c->sort.epoch = 0;
     ok &= hipMalloc(&c->sort.sums, sizeof(uint32_t) * 1024) == hipSuccess;
     ok &= hipMalloc(&c->sort.cnt, sizeof(uint32_t) * (c->K > 0 ? c->K : 1)) == hipSuccess;
     if (ok) ok = hipMemset(c->sort.cnt, 0, sizeof(uint32_t) * (c->K > 0 ? c->K : 1)) == hipSuccess;
@@ -302,6 +365,17 @@ gic_status gic_create(const gic_params *p, int64_t n_max, gic_ctx **out)
     ok &= hipMalloc(&c->bricks.list, sizeof(int32_t) * (c->bricks.nbricks > 0 ? c->bricks.nbricks : 1)) == hipSuccess;
     ok &= hipMalloc(&c->bricks.count, sizeof(int32_t)) == hipSuccess;
     ok &= hipMalloc(&c->bricks.sums, sizeof(uint32_t) * 1024) == hipSuccess;
+    ok &= hipMalloc(&c->fxs, sizeof(int64_t) * 4 * (size_t)(c->dp.G > 0 ? c->dp.G : 1)) == hipSuccess;
+    ok &= hipMalloc(&c->fxp, sizeof(double) * 4 * 1024) == hipSuccess;
+    ok &= hipMalloc(&c->nl.nbr, sizeof(int32_t) * kNbrCap * nn) == hipSuccess;
+    ok &= hipMalloc(&c->nl.cnt, sizeof(int32_t) * nn) == hipSuccess;
+    ok &= hipMalloc(&c->nl.xref, sizeof(float) * 3 * nn) == hipSuccess;
+    ok &= hipMalloc(&c->nl.ctl, sizeof(uint32_t) * 4) == hipSuccess;
+    ok &= hipMalloc(&c->nl.dpart, sizeof(float) * (size_t)((nn + 255) / 256)) == hipSuccess;
+    if (ok) ok = hipMemset(c->nl.ctl, 0, sizeof(uint32_t) * 4) == hipSuccess;
+    nbr_reach(p, c->nl);
+    c->nl_n = -1;
+    c->nl_x = nullptr;
     if (ok) ok = hipMemset(c->err, 0, sizeof(int64_t) * 2) == hipSuccess;
     if (!ok) {
         gic_destroy(c);
@@ -319,6 +393,8 @@ gic_status gic_set_params(gic_ctx *c, const gic_params *p)
     if (p->dx != c->p.dx || p->cell != c->p.cell || p->precision != c->p.precision) return GIC_E_ARG;
     c->p = *p;
     c->dp = derive(p);
+    nbr_reach(p, c->nl);
+    c->nl_n = -1;  // radii or r_max may differ: the next step builds its list afresh
     return GIC_OK;
 }
 
@@ -336,7 +412,8 @@ gic_status gic_destroy(gic_ctx *c)
     (void)hipFree(c->sort.ctl);
     (void)hipFree(c->sort.vA);
     (void)hipFree(c->sort.vB);
-    (void)hipFree(c->sort.hist);
+    (void)hipFree(c->sort.ghist);
+    (void)hipFree(c->sort.flags);
     (void)hipFree(c->sort.sums);
     (void)hipFree(c->sort.cnt);
     (void)hipFree(c->err);
@@ -344,6 +421,17 @@ gic_status gic_destroy(gic_ctx *c)
     (void)hipFree(c->bricks.list);
     (void)hipFree(c->bricks.count);
     (void)hipFree(c->bricks.sums);
+    if (c->tm_ev) {
+        for (int i = 0; i < c->tm_cap * kStageEvents; ++i) (void)hipEventDestroy(c->tm_ev[i]);
+        delete[] c->tm_ev;
+    }
+    (void)hipFree(c->fxs);
+    (void)hipFree(c->fxp);
+    (void)hipFree(c->nl.nbr);
+    (void)hipFree(c->nl.cnt);
+    (void)hipFree(c->nl.xref);
+    (void)hipFree(c->nl.ctl);
+    (void)hipFree(c->nl.dpart);
     delete c;
     return hip_status(e);
 }
@@ -365,10 +453,24 @@ gic_status gic_get_error(gic_ctx *c, void *stream, int32_t *code, int64_t *index
     return hip_status(e);
 }
 
+gic_status gic_neighbour_builds(gic_ctx *c, void *stream, int64_t *builds)
+{
+    if (!c || !builds) return GIC_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t h[4] = {0, 0, 0, 0};
+    hipError_t e = hipMemcpyAsync(h, c->nl.ctl, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return GIC_E_HIP;
+    *builds = (int64_t)h[2];
+    return GIC_OK;
+}
+
 gic_status gic_sort_cells(gic_ctx *c, int64_t n, const double *x, uint32_t *key, int32_t *order,
                           int32_t *cell_begin, int32_t *cell_end, void *stream)
 {
     if (!n_ok(c, n) || !cell_begin || !cell_end || (n > 0 && (!x || !key || !order))) return GIC_E_ARG;
+    c->nl_n = -1;  // the next gic_step cannot rely on this sort's keys for its neighbour list
+    c->rng_ok = false;
     return hip_status(launch_sort_cells(c->dp, n, x, key, order, cell_begin, cell_end, c->K, c->sort, c->err,
                                         (hipStream_t)stream));
 }
@@ -384,20 +486,33 @@ gic_status gic_reorder(gic_ctx *c, int64_t n, const int32_t *order, const double
     return hip_status(launch_reorder(n, order, x, v, r, id, x_out, v_out, r_out, id_out, (hipStream_t)stream));
 }
 
+// Neighbour list (built when force is set or the sort asked for it) and the
+// contact forces from it.
+static gic_status contact_impl(gic_ctx *c, int64_t n, const double *x, const double *v, const double *r,
+                               const int32_t *cell_begin, const int32_t *cell_end, void *f_contact,
+                               int32_t *n_contacts, int32_t *pair_ids, int32_t pair_cap, int force, hipStream_t s)
+{
+    if (launch_nbr_build(c->dp, n, x, r, cell_begin, cell_end, c->bricks, c->nl, force, c->err, s) != hipSuccess)
+        return GIC_E_HIP;
+    if (fp32(c))
+        return hip_status(launch_contact_list<float>(c->dp, n, x, v, r, cell_begin, cell_end, c->nl,
+                                                     (float *)f_contact, n_contacts, pair_ids, pair_cap, c->err, s));
+    return hip_status(launch_contact_list<double>(c->dp, n, x, v, r, cell_begin, cell_end, c->nl,
+                                                  (double *)f_contact, n_contacts, pair_ids, pair_cap, c->err, s));
+}
+
 gic_status gic_contact_forces(gic_ctx *c, int64_t n, const double *x, const double *v, const double *r,
                               const int32_t *cell_begin, const int32_t *cell_end, void *f_contact,
-                              int32_t *n_contacts, void *stream)
+                              int32_t *n_contacts, int32_t *pair_ids, int32_t pair_cap, void *stream)
 {
-    if (!n_ok(c, n)) return GIC_E_ARG;
+    if (!n_ok(c, n) || pair_cap < 0 || (pair_cap > 0 && !pair_ids)) return GIC_E_ARG;
     if (n > 0 && (!x || !v || !r || !cell_begin || !cell_end || !f_contact)) return GIC_E_ARG;
     hipStream_t s = (hipStream_t)stream;
     if (n == 0) return GIC_OK;
     if (brick_list(c, cell_begin, cell_end, s) != hipSuccess) return GIC_E_HIP;
-    if (fp32(c))
-        return hip_status(launch_contact<float>(c->dp, n, x, v, r, cell_begin, cell_end, c->bricks, nullptr,
-                                                nullptr, (float *)f_contact, n_contacts, c->err, s));
-    return hip_status(launch_contact<double>(c->dp, n, x, v, r, cell_begin, cell_end, c->bricks, nullptr, nullptr,
-                                             (double *)f_contact, n_contacts, c->err, s));
+    c->nl_n = -1;  // the list now belongs to these arrays, not to the stepping path
+    return contact_impl(c, n, x, v, r, cell_begin, cell_end, f_contact, n_contacts, pair_cap > 0 ? pair_ids : nullptr,
+                        pair_cap, 1, s);
 }
 
 gic_status gic_contact_capillary_forces(gic_ctx *c, int64_t n, const double *x, const double *v, const double *r,
@@ -427,15 +542,6 @@ gic_status gic_moisture_ratio(gic_ctx *c, int64_t n, const double *held, const v
     if (fp32(c))
         return hip_status(launch_moisture_ratio<float>(n, held, (const float *)alpha_f, (float *)sr, s));
     return hip_status(launch_moisture_ratio<double>(n, held, (const double *)alpha_f, (double *)sr, s));
-}
-
-gic_status gic_contact_pairs(gic_ctx *c, int64_t n, const double *x, const double *r, const int32_t *cell_begin,
-                             const int32_t *cell_end, int32_t *pairs, int64_t cap, int64_t *count, void *stream)
-{
-    if (!n_ok(c, n) || !count || cap < 0 || (cap > 0 && !pairs)) return GIC_E_ARG;
-    if (n > 0 && (!x || !r || !cell_begin || !cell_end)) return GIC_E_ARG;
-    return hip_status(
-        launch_contact_pairs(c->dp, n, x, r, cell_begin, cell_end, pairs, cap, count, (hipStream_t)stream));
 }
 
 gic_status gic_g2p(gic_ctx *c, int64_t n, const double *x, const void *u, const int64_t *alpha_fx,
@@ -503,15 +609,9 @@ gic_status gic_p2g_real(gic_ctx *c, int64_t n, const double *x, const double *v,
     if (!n_ok(c, n) || (!alpha && !mom)) return GIC_E_ARG;
     if (n > 0 && (!x || !r || !cell_begin || !cell_end || (mom && !v))) return GIC_E_ARG;
     hipStream_t s = (hipStream_t)stream;
-    const int64_t G = c->dp.G;
-    if (!accumulate) {
-        hipError_t e = alpha ? launch_fill_f64(alpha, G, s) : hipSuccess;
-        if (e == hipSuccess && mom) e = launch_fill_f64(mom, 3 * G, s);
-        if (e != hipSuccess) return GIC_E_HIP;
-    }
-    if (n == 0) return GIC_OK;
-    if (brick_list(c, cell_begin, cell_end, s) != hipSuccess) return GIC_E_HIP;
-    return hip_status(launch_p2g_real(c->dp, n, c->K, x, v, r, cell_begin, cell_end, c->bricks, alpha, mom, s));
+    if (n > 0 && brick_list(c, cell_begin, cell_end, s) != hipSuccess) return GIC_E_HIP;
+    return hip_status(launch_p2g_real(c->dp, n, c->K, x, v, r, cell_begin, cell_end, c->bricks, alpha, mom,
+                                      accumulate ? 1 : 0, c->fxs, c->fxp, s));
 }
 
 gic_status gic_gather_g2p_drag(gic_ctx *c, int64_t n, const int32_t *order, const double *x, const double *v,
@@ -578,6 +678,59 @@ gic_status gic_integrate_p2g_wet(gic_ctx *c, int64_t n, double *x, double *v, co
                               accumulate, stream);
 }
 
+// Stage event k of the current timed step (no-op unless timing is on and
+// the event buffer has room).
+static void stage_mark(gic_ctx *c, int k, hipStream_t s)
+{
+    if (c->tm_used < c->tm_cap) (void)hipEventRecord(c->tm_ev[c->tm_used * kStageEvents + k], s);
+}
+
+static void stage_done(gic_ctx *c)
+{
+    if (c->tm_used < c->tm_cap) ++c->tm_used;
+}
+
+gic_status gic_stage_timing(gic_ctx *c, int32_t max_steps)
+{
+    if (!c || max_steps < 0) return GIC_E_ARG;
+    if (c->tm_ev) {
+        (void)hipDeviceSynchronize();
+        for (int i = 0; i < c->tm_cap * kStageEvents; ++i) (void)hipEventDestroy(c->tm_ev[i]);
+        delete[] c->tm_ev;
+    }
+    c->tm_ev = nullptr;
+    c->tm_cap = c->tm_used = 0;
+    if (max_steps == 0) return GIC_OK;
+    c->tm_ev = new hipEvent_t[(size_t)max_steps * kStageEvents];
+    for (int i = 0; i < max_steps * kStageEvents; ++i)
+        if (hipEventCreate(&c->tm_ev[i]) != hipSuccess) {
+            for (int j = 0; j < i; ++j) (void)hipEventDestroy(c->tm_ev[j]);
+            delete[] c->tm_ev;
+            c->tm_ev = nullptr;
+            return GIC_E_HIP;
+        }
+    c->tm_cap = max_steps;
+    return GIC_OK;
+}
+
+gic_status gic_stage_times(gic_ctx *c, void *stream, double *ms, int32_t *steps)
+{
+    if (!c || !ms || !steps) return GIC_E_ARG;
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return GIC_E_HIP;
+    for (int k = 0; k < kStageEvents - 1; ++k) ms[k] = 0.0;
+    for (int t = 0; t < c->tm_used; ++t)
+        for (int k = 0; k < kStageEvents - 1; ++k) {
+            float e = 0.0f;
+            if (hipEventElapsedTime(&e, c->tm_ev[t * kStageEvents + k], c->tm_ev[t * kStageEvents + k + 1]) !=
+                hipSuccess)
+                return GIC_E_HIP;
+            ms[k] += (double)e;
+        }
+    *steps = c->tm_used;
+    c->tm_used = 0;
+    return GIC_OK;
+}
+
 gic_status gic_step(gic_ctx *c, int64_t n, const double *x_cur, const double *v_cur, const double *r_cur,
                     const int32_t *id_cur, double *x_nxt, double *v_nxt, double *r_nxt, int32_t *id_nxt,
                     const void *u, int64_t *alpha_fx, int64_t *mom_fx, uint32_t *key, int32_t *order,
@@ -589,20 +742,38 @@ gic_status gic_step(gic_ctx *c, int64_t n, const double *x_cur, const double *v_
                   !f_contact || !f_drag))
         return GIC_E_ARG;
     if ((id_cur == nullptr) != (id_nxt == nullptr) || (u_at == nullptr) != (alpha_f == nullptr)) return GIC_E_ARG;
-    gic_status st;
-    if ((st = gic_sort_cells(c, n, x_cur, key, order, cell_begin, cell_end, stream)) != GIC_OK) return st;
-    if (n > 0 && launch_brick_list(cell_begin, cell_end, c->bricks, (hipStream_t)stream) != hipSuccess) return GIC_E_HIP;
-    c->in_step = true;  // the three stages below share this brick list
+    hipStream_t s = (hipStream_t)stream;
+    // the neighbour list of the last step is kept when this step continues
+    // that step's state (the sort then checks order and displacement)
+    const int force = !(c->nl_n == n && c->nl_x == x_cur && c->sort.last_n == n);
+    c->nl_n = -1;
+    stage_mark(c, 0, s);
+    if (step_sort(c, n, x_cur, key, order, cell_begin, cell_end, force, s) != hipSuccess) return GIC_E_HIP;
+    stage_mark(c, 1, s);
+    c->in_step = true;  // the stages below share this brick list
     // alpha_fx was deposited at the current positions and is read by node,
     // so the gather into sorted order does not change it
-    st = gic_gather_g2p_drag(c, n, order, x_cur, v_cur, r_cur, id_cur, x_nxt, v_nxt, r_nxt, id_nxt, u, alpha_fx,
-                             cell_begin, cell_end, f_drag, u_at, alpha_f, stream);
+    gic_status st = gic_gather_g2p_drag(c, n, order, x_cur, v_cur, r_cur, id_cur, x_nxt, v_nxt, r_nxt, id_nxt, u,
+                                        alpha_fx, cell_begin, cell_end, f_drag, u_at, alpha_f, stream);
+    stage_mark(c, 2, s);
+    if (st == GIC_OK && n > 0)
+        st = contact_impl(c, n, x_nxt, v_nxt, r_nxt, cell_begin, cell_end, f_contact, nullptr, nullptr, 0, force, s);
+    stage_mark(c, 3, s);
+    stage_mark(c, 4, s);  // no exchange deposit in this step
+    if (st == GIC_OK && (launch_fill_i64(alpha_fx, c->dp.G, s) != hipSuccess ||
+                         launch_fill_i64(mom_fx, 3 * c->dp.G, s) != hipSuccess))
+        st = GIC_E_HIP;
+    stage_mark(c, 5, s);
     if (st == GIC_OK)
-        st = gic_contact_forces(c, n, x_nxt, v_nxt, r_nxt, cell_begin, cell_end, f_contact, nullptr, stream);
-    if (st == GIC_OK)
-        st = gic_integrate_p2g(c, n, x_nxt, v_nxt, r_nxt, f_contact, f_drag, cell_begin, cell_end, alpha_fx, mom_fx, 0,
+        st = gic_integrate_p2g(c, n, x_nxt, v_nxt, r_nxt, f_contact, f_drag, cell_begin, cell_end, alpha_fx, mom_fx, 1,
                                stream);
+    stage_mark(c, 6, s);
+    stage_done(c);
     c->in_step = false;
+    if (st == GIC_OK) {
+        c->nl_n = n;  // the list holds the sorted order of the state now in x_nxt
+        c->nl_x = x_nxt;
+    }
     return st;
 }
 
@@ -680,24 +851,39 @@ gic_status gic_sand_step(gic_ctx *c, int64_t n, double Dt, double *x_a, double *
         double *xc = even ? x_a : x_b, *vc = even ? v_a : v_b, *rc = even ? r_a : r_b;
         double *xn = even ? x_b : x_a, *vn = even ? v_b : v_a, *rn = even ? r_b : r_a;
         int32_t *ic = even ? id_a : id_b, *in = even ? id_b : id_a;
-        st = gic_sort_cells(c, n, xc, key, order, cell_begin, cell_end, stream);
-        if (st != GIC_OK) break;
-        if (n > 0 && launch_brick_list(cell_begin, cell_end, c->bricks, s) != hipSuccess) {
+        const int force = !(c->nl_n == n && c->nl_x == xc && c->sort.last_n == n);
+        c->nl_n = -1;
+        stage_mark(c, 0, s);
+        if (step_sort(c, n, xc, key, order, cell_begin, cell_end, force, s) != hipSuccess) {
             st = GIC_E_HIP;
             break;
         }
+        stage_mark(c, 1, s);
         c->in_step = true;  // the stages below share this brick list
         st = gic_gather_g2p_fluid(c, n, order, xc, vc, rc, ic, xn, vn, rn, in, u, alpha_fx, grad_p, acc_f,
                                   cell_begin, cell_end, f_fluid, nullptr, nullptr, stream);
-        if (st == GIC_OK)
-            st = gic_contact_forces(c, n, xn, vn, rn, cell_begin, cell_end, f_contact, nullptr, stream);
+        stage_mark(c, 2, s);
+        if (st == GIC_OK && n > 0)
+            st = contact_impl(c, n, xn, vn, rn, cell_begin, cell_end, f_contact, nullptr, nullptr, 0, force, s);
+        stage_mark(c, 3, s);
         if (st == GIC_OK && fs_fx)
             st = gic_exchange_p2g(c, n, xn, rn, f_contact, f_fluid, cell_begin, cell_end, weight, fs_fx, nullptr,
                                   stream);
+        stage_mark(c, 4, s);
+        if (st == GIC_OK && (launch_fill_i64(alpha_fx, c->dp.G, s) != hipSuccess ||
+                             launch_fill_i64(mom_fx, 3 * c->dp.G, s) != hipSuccess))
+            st = GIC_E_HIP;
+        stage_mark(c, 5, s);
         if (st == GIC_OK)
-            st = gic_integrate_p2g(c, n, xn, vn, rn, f_contact, f_fluid, cell_begin, cell_end, alpha_fx, mom_fx, 0,
+            st = gic_integrate_p2g(c, n, xn, vn, rn, f_contact, f_fluid, cell_begin, cell_end, alpha_fx, mom_fx, 1,
                                    stream);
+        stage_mark(c, 6, s);
+        stage_done(c);
         c->in_step = false;
+        if (st == GIC_OK) {
+            c->nl_n = n;
+            c->nl_x = xn;
+        }
     }
     c->dp.dt = dt_keep;
     *nsub = N;
@@ -750,7 +936,7 @@ gic_status gic_g2p_vjp(gic_ctx *c, int64_t n, const double *x, const double *u, 
     if (n > 0 && g_alpha && brick_list(c, cell_begin, cell_end, (hipStream_t)stream) != hipSuccess)
         return GIC_E_HIP;
     return hip_status(launch_g2p_vjp(c->dp, n, c->K, x, u, alpha_real, g_u_at, g_alpha_f, cell_begin, cell_end,
-                                     c->bricks, g_x, g_alpha, (hipStream_t)stream));
+                                     c->bricks, g_x, g_alpha, c->fxs, c->fxp, (hipStream_t)stream));
 }
 
 gic_status gic_p2g_vjp(gic_ctx *c, int64_t n, const double *x, const double *v, const double *r,
@@ -767,6 +953,13 @@ gic_status gic_sum(gic_ctx *c, int64_t n, const double *a, const double *b, doub
 {
     if (!c || n < 0 || !out || (n > 0 && !a)) return GIC_E_ARG;
     return hip_status(launch_sum(a, b, n, c->part, kSumParts, out, accumulate ? 1 : 0, (hipStream_t)stream));
+}
+
+gic_status gic_scale(gic_ctx *c, int64_t n, const double *a, const double *s, double factor, double *out,
+                     void *stream)
+{
+    if (!c || n < 0 || (n > 0 && (!a || !s || !out)) || !isfinite(factor)) return GIC_E_ARG;
+    return hip_status(launch_scale(n, a, s, factor, out, (hipStream_t)stream));
 }
 
 gic_status gic_permute(gic_ctx *c, int64_t n, int32_t comps, const int32_t *order, const double *in, double *out,

@@ -20,15 +20,18 @@ struct SortScratch {
     int cur;
     int64_t last_n;      // granules of the last sort, -1 before the first
     int32_t *vA, *vB;
-    uint32_t *hist;      // RADIX x tiles
     uint32_t *sums;      // 1024 chunk totals of the digit-offset scan
     uint32_t *cnt;       // [K] granules per cell; zero between sorts
     uint64_t *chg;       // [kChgCap] changed granules as (key << 32 | position), in arrival order
     uint64_t *chg_s;     // [kChgCap] the same sorted
     uint32_t *chg_p;     // [kChgCap] their positions sorted
-    int32_t *ctl;        // [2] changed count (zero between sorts), path of this sort (1 = incremental)
+    int32_t *ctl;        // [4] changed count (zero between sorts), path of this sort (1 = incremental),
+                         // no key changed (1: order, ranges and bricks of the last sort hold), spare
     int64_t tiles_max;
     int passes;          // 8-bit digit passes over the key bits
+    uint32_t *ghist;     // [4 x 256 + 4] digit counts of every pass, then the 4 passes' tile counters
+    uint64_t *flags;     // [4][tiles_max][256] look-back words of the digit passes
+    uint32_t epoch;      // sort number, tags the look-back words of this sort
 };
 
 // Occupied bricks of a set of cell ranges, in brick order (see
@@ -40,15 +43,45 @@ struct BrickList {
     int64_t nbricks;
 };
 
-hipError_t launch_brick_list(const int32_t *cb, const int32_t *ce, BrickList &B, hipStream_t s);
+// skip (optional): the sort's control words; the list is kept when the sort
+// found no changed key (the caller checked that cb, ce are the tables the
+// list was built from).
+hipError_t launch_brick_list(const int32_t *cb, const int32_t *ce, BrickList &B, hipStream_t s,
+                             const int32_t *skip = nullptr);
+
+// Persistent neighbour list of the contact stage (owned by a context): for
+// every granule (sorted position q) the sorted positions of the granules
+// closer than r_i + r_j + skin when the list was built, in the order of
+// their cells (z, then y, then x) and of their positions inside a cell.  The
+// contact kernel runs the exact test of Sec. 3.1 on the listed granules
+// every step, so the list only has to hold every pair that can touch: it
+// stays valid while the sorted order is unchanged and no granule has moved
+// by skin / 2 since the build.
+constexpr int kNbrCap = 16;  // partners listed per granule; more: the contact kernel searches the cells
+struct NbrList {
+    int32_t *nbr;   // [kNbrCap][n]: partner k of granule q at k * n + q
+    int32_t *cnt;   // [n] partners found (> kNbrCap: not listed, searched)
+    float *xref;    // [3][n] positions at the build
+    uint32_t *ctl;  // [4] rebuild flag of this step, spare, builds, spare
+    float *dpart;   // [n / 256] largest squared displacement since the build per key-kernel workgroup
+    double skin;    // reach of the list beyond r_i + r_j [m]
+    float thr2;     // squared displacement since the build that calls for a rebuild (< 0: every step)
+};
 
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 8;
 constexpr int kSortTile = kSortThreads * kSortItems;
 
+// nl: the neighbour list of the stepping path, or NULL.  With nl, the key
+// kernel also measures every granule's displacement since the list's build
+// (x in the order of that build) and the sort decides nl->ctl[0]: rebuild
+// when force is set, when the sorted order changes, or when a granule moved
+// by more than the list's skin / 2.
+// keep_ranges: cell_begin, cell_end hold the ranges of the last sort on S
+// (same n); they are then rewritten only if a key changed.
 hipError_t launch_sort_cells(const DevParams &P, int64_t n, const double *x, uint32_t *key, int32_t *order,
                              int32_t *cell_begin, int32_t *cell_end, int64_t K, SortScratch &S, int64_t *err,
-                             hipStream_t s);
+                             hipStream_t s, const NbrList *nl = nullptr, int force = 1, int keep_ranges = 0);
 hipError_t launch_reorder(int64_t n, const int32_t *order, const double *x, const double *v, const double *r,
                           const int32_t *id, double *xo, double *vo, double *ro, int32_t *ido, hipStream_t s);
 
@@ -56,9 +89,17 @@ template <typename T>
 hipError_t launch_contact(const DevParams &P, int64_t n, const double *x, const double *v, const double *r,
                           const int32_t *cb, const int32_t *ce, const BrickList &B, const T *sr, const double *held,
                           T *F, int32_t *ncont, int64_t *err, hipStream_t s);
-hipError_t launch_contact_pairs(const DevParams &P, int64_t n, const double *x, const double *r,
-                                const int32_t *cb, const int32_t *ce, int32_t *pairs, int64_t cap,
-                                int64_t *count, hipStream_t s);
+// Neighbour-list build (only when force is set or the sort asked for it)
+// and the contact forces from the list (Sec. 3.1, Eq. 1a-1c, walls).
+// pairs (optional, pair_cap x n, column-major): the partners that touch, in
+// the order their forces are summed, -1 after the last.
+hipError_t launch_nbr_build(const DevParams &P, int64_t n, const double *x, const double *r, const int32_t *cb,
+                            const int32_t *ce, const BrickList &B, NbrList &L, int force, int64_t *err,
+                            hipStream_t s);
+template <typename T>
+hipError_t launch_contact_list(const DevParams &P, int64_t n, const double *x, const double *v, const double *r,
+                               const int32_t *cb, const int32_t *ce, const NbrList &L, T *F, int32_t *ncont,
+                               int32_t *pairs, int pair_cap, int64_t *err, hipStream_t s);
 
 template <typename T>
 hipError_t launch_g2p(const DevParams &P, int64_t n, const double *x, const T *u, const int64_t *afx,
@@ -99,9 +140,15 @@ hipError_t launch_gather_g2p_drag(const DevParams &P, int64_t n, int64_t K, cons
                                   const double *v, const double *r, const int32_t *id, double *xo, double *vo,
                                   double *ro, int32_t *ido, const T *u, const int64_t *afx, const int32_t *cb,
                                   const int32_t *ce, const BrickList &B, T *Fd, T *uat, T *af, hipStream_t s);
+// Unquantised P2G (alpha G, momentum 3G doubles; = or += with acc),
+// summed deterministically as integers at a scale set by the largest
+// contribution; fx: 4 G int64 and part: 4 x 1024 doubles of scratch.
 hipError_t launch_p2g_real(const DevParams &P, int64_t n, int64_t K, const double *x, const double *v,
                            const double *r, const int32_t *cb, const int32_t *ce, const BrickList &B,
-                           double *alpha, double *mom, hipStream_t s);
+                           double *alpha, double *mom, int acc, int64_t *fx, double *part, hipStream_t s);
+hipError_t launch_g2p_vjp_grid(const DevParams &P, int64_t n, int64_t K, const double *x, const double *A,
+                               const double *gaf, const int32_t *cb, const int32_t *ce, const BrickList &B,
+                               double *gA, int64_t *fx, double *part, hipStream_t s);
 
 hipError_t launch_contact_vjp(const DevParams &P, int64_t n, const double *x, const double *v, const double *r,
                               const int32_t *cb, const int32_t *ce, const double *gF, double *gx, double *gv,
@@ -113,13 +160,15 @@ hipError_t launch_integrate_vjp(const DevParams &P, int64_t n, const double *r, 
                                 double *gF, hipStream_t s);
 hipError_t launch_g2p_vjp(const DevParams &P, int64_t n, int64_t K, const double *x, const double *u,
                           const double *A, const double *guat, const double *gaf, const int32_t *cb,
-                          const int32_t *ce, const BrickList &B, double *gx, double *gA, hipStream_t s);
+                          const int32_t *ce, const BrickList &B, double *gx, double *gA, int64_t *fx, double *part,
+                          hipStream_t s);
 hipError_t launch_p2g_vjp(const DevParams &P, int64_t n, const double *x, const double *v, const double *r,
                           const double *gA, const double *gP, double *gx, double *gv, hipStream_t s);
 hipError_t launch_sum(const double *a, const double *b, int64_t n, double *part, int nparts, double *out, int acc,
                       hipStream_t s);
 hipError_t launch_permute(int64_t n, int comps, const int32_t *order, const double *in, double *out, int scatter,
                           hipStream_t s);
+hipError_t launch_scale(int64_t n, const double *a, const double *sp, double factor, double *out, hipStream_t s);
 
 inline unsigned grid_for(int64_t n, int threads)
 {

@@ -16,13 +16,37 @@ constexpr int kRadix = 256;
 // Key of every granule; flags non-finite and out-of-box positions.  With
 // the previous sorted keys pk (same n), granules whose key differs from
 // pk at their position are appended to chg (up to kChgCap; ctl[0] counts
-// them all).
+// them all).  With xref (the positions of the neighbour list's build, same
+// order), each workgroup writes the largest squared displacement of its
+// granules since the build to dpart[block] (no atomics: one address hit by
+// every wave would serialise them).
 __global__ void __launch_bounds__(256) k_cell_keys(DevParams P, int64_t n, const double *__restrict__ x,
                                                    uint32_t *__restrict__ key, int64_t *err,
                                                    const uint32_t *__restrict__ pk, uint64_t *__restrict__ chg,
-                                                   int32_t *__restrict__ ctl)
+                                                   int32_t *__restrict__ ctl, const float *__restrict__ xref,
+                                                   float *__restrict__ dpart, uint32_t *__restrict__ ghist)
 {
+    // the digit counts and tile counters of this sort's digit passes start at zero
+    if (blockIdx.x == 0)
+        for (int k = threadIdx.x; k < 4 * kRadix + 4; k += blockDim.x) ghist[k] = 0u;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (xref) {
+        float d2 = 0.0f;
+        if (i < n) {
+            double s2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                const double d = x[a * n + i] - (double)xref[a * n + i];
+                s2 += d * d;
+            }
+            d2 = (float)s2;
+            if (!(d2 >= 0.0f)) d2 = __builtin_huge_valf();  // NaN: rebuild (the position is flagged below)
+        }
+        __shared__ float s_d2[4];
+        for (int off = 32; off > 0; off >>= 1) d2 = fmaxf(d2, __shfl_xor(d2, off));
+        if ((threadIdx.x & 63) == 0) s_d2[threadIdx.x >> 6] = d2;
+        __syncthreads();
+        if (threadIdx.x == 0) dpart[blockIdx.x] = fmaxf(fmaxf(s_d2[0], s_d2[1]), fmaxf(s_d2[2], s_d2[3]));
+    }
     if (i >= n) return;
     double xa[3] = {x[i], x[n + i], x[2 * n + i]};
     int32_t c[3];
@@ -40,39 +64,6 @@ __global__ void __launch_bounds__(256) k_cell_keys(DevParams P, int64_t n, const
         const int32_t slot = atomicAdd(&ctl[0], 1);
         if (slot < kChgCap) chg[slot] = ((uint64_t)k << 32) | (uint64_t)i;
     }
-}
-
-// Per-tile histogram of one 8-bit digit: hist[d * tiles + tile].  Keys are
-// usually close to sorted (the state was sorted by the previous step), so
-// neighbouring lanes mostly share a digit: the first lane of each run of
-// equal digits in a wave adds the run's length, one LDS atomic per run.
-__global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint32_t *__restrict__ keys, int64_t n,
-                                                             int shift, uint32_t *__restrict__ hist, int64_t tiles,
-                                                             const int32_t *__restrict__ skip)
-{
-    if (skip && skip[1]) return;  // the incremental path sorted this time
-    __shared__ uint32_t h[kRadix];
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    h[tid] = 0;
-    __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kSortTile;
-#pragma unroll
-    for (int it = 0; it < kSortItems; ++it) {
-        const int64_t p = base + (int64_t)it * kSortThreads + tid;
-        const bool valid = p < n;
-        const uint32_t d = valid ? (keys[p] >> shift) & (kRadix - 1) : 0u;
-        const uint32_t prev = __shfl_up(d, 1);
-        const bool start = valid && (lane == 0 || prev != d);
-        const uint64_t starts = __ballot(start) | (~__ballot(valid));  // invalid lanes end the last run
-        if (start) {
-            const uint64_t above = lane == 63 ? 0ull : (starts >> (lane + 1)) << (lane + 1);
-            const int next = above ? __ffsll((unsigned long long)above) - 1 : 64;
-            atomicAdd(&h[d], (uint32_t)(next - lane));
-        }
-    }
-    __syncthreads();
-    hist[(int64_t)tid * tiles + blockIdx.x] = h[tid];
 }
 
 // Exclusive prefix sum in place, in three coalesced phases: each workgroup
@@ -121,11 +112,13 @@ __device__ inline uint32_t block_scan_inclusive(uint32_t v, uint32_t *lds, uint3
     return v + before;
 }
 
+// skip (optional): the sort's control words; skip[2] set means the cell
+// ranges of the last sort still hold (no key changed) and are kept.
 __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const uint32_t *__restrict__ a, int64_t len,
                                                               int64_t chunk, uint32_t *__restrict__ sums,
                                                               const int32_t *__restrict__ skip)
 {
-    if (skip && skip[1]) return;
+    if (skip && skip[2]) return;
     __shared__ uint32_t lds[kScanThreads / 64];
     const int64_t lo = (int64_t)blockIdx.x * chunk;
     const int64_t hi = lo + chunk < len ? lo + chunk : len;
@@ -137,7 +130,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const uint32_t *__
 
 __global__ void __launch_bounds__(kScanThreads) k_scan_spine(uint32_t *sums, int nb, const int32_t *__restrict__ skip)
 {
-    if (skip && skip[1]) return;
+    if (skip && skip[2]) return;
     __shared__ uint32_t lds[kScanThreads / 64];
     const uint32_t v = threadIdx.x < nb ? sums[threadIdx.x] : 0u;
     uint32_t total;
@@ -145,70 +138,169 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_spine(uint32_t *sums, int
     if (threadIdx.x < nb) sums[threadIdx.x] = inc - v;
 }
 
-__global__ void __launch_bounds__(kScanThreads) k_scan_down(uint32_t *__restrict__ a, int64_t len, int64_t chunk,
-                                                            const uint32_t *__restrict__ sums,
-                                                            const int32_t *__restrict__ skip)
+// ---- single-pass digit passes (decoupled look-back) ----------------------
+//
+// The counts of every digit of every pass are taken in one read of the keys
+// (k_radix_hist_all).  Each digit pass is then one kernel: a workgroup takes
+// the next tile in launch order (a counter), counts its tile's digits,
+// publishes them, and finds the keys of earlier tiles with each digit by
+// walking back over the tiles' published words until one that carries the
+// inclusive count of all tiles before it (decoupled look-back); it publishes
+// its own inclusive count and scatters its keys stably.  A tile only waits
+// for tiles that took a smaller number, i.e. workgroups that are already
+// running, and every wait is bounded: after kSpinLimit polls the kernel
+// latches an error and goes on, so no launch can hang.
+//
+// A published word is [epoch: 30 | state: 2 | count: 32], state 1 = this
+// tile's own count, 2 = count of this tile and all before it; the epoch of
+// the sort tells words of this sort from those left by earlier ones, so the
+// words need no clearing.
+constexpr uint32_t kSpinLimit = 1u << 22;
+constexpr int kErrSort = 6;  // latched as GIC_E_RANGE with index -2
+
+__device__ inline uint64_t lb_word(uint32_t epoch, uint32_t state, uint32_t count)
 {
-    if (skip && skip[1]) return;
-    __shared__ uint32_t lds[kScanThreads / 64];
-    const int64_t lo = (int64_t)blockIdx.x * chunk;
-    const int64_t hi = lo + chunk < len ? lo + chunk : len;
-    uint32_t carry = sums[blockIdx.x];
-    for (int64_t base = lo; base < hi; base += kScanThreads) {
-        const int64_t k = base + threadIdx.x;
-        const uint32_t v = k < hi ? a[k] : 0u;
-        uint32_t total;
-        const uint32_t inc = block_scan_inclusive(v, lds, &total);
-        if (k < hi) a[k] = carry + inc - v;
-        carry += total;
-    }
+    return ((uint64_t)(epoch & 0x3fffffffu) << 34) | ((uint64_t)state << 32) | (uint64_t)count;
 }
 
-// Stable scatter of one digit pass.  The tile is processed in rounds of 256
-// consecutive keys; inside a wave, lanes with equal digits are found with
-// eight ballots (one per digit bit), which gives each key its rank among
-// earlier lanes of the same digit; per-wave digit counts in LDS order the
-// four waves, and a running count per digit orders the rounds.  vin == NULL
-// means the values are the input positions.
-__global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint32_t *__restrict__ kin,
-                                                                const int32_t *__restrict__ vin,
-                                                                uint32_t *__restrict__ kout,
-                                                                int32_t *__restrict__ vout, int64_t n, int shift,
-                                                                const uint32_t *__restrict__ offs, int64_t tiles,
-                                                                const int32_t *__restrict__ skip)
+__global__ void __launch_bounds__(kSortThreads) k_radix_hist_all(const uint32_t *__restrict__ keys, int64_t n,
+                                                                 int passes, uint32_t *__restrict__ ghist,
+                                                                 const int32_t *__restrict__ skip)
+{
+    if (skip && skip[1]) return;  // the incremental path sorted this time
+    __shared__ uint32_t h[4][kRadix];
+    const int tid = threadIdx.x;
+    for (int p = 0; p < 4; ++p) h[p][tid] = 0;
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * kSortThreads + tid; i < n; i += (int64_t)gridDim.x * kSortThreads) {
+        const uint32_t k = keys[i];
+        for (int p = 0; p < passes; ++p) atomicAdd(&h[p][(k >> (8 * p)) & (kRadix - 1)], 1u);
+    }
+    __syncthreads();
+    for (int p = 0; p < passes; ++p)
+        if (h[p][tid]) atomicAdd(&ghist[p * kRadix + tid], h[p][tid]);
+}
+
+// Rank of each lane's digit among the lanes of its wave with the same digit
+// (8 ballots), and the number of such lanes.
+__device__ inline uint64_t digit_mask(uint32_t d, bool valid)
+{
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bb = __ballot(bit);
+        m &= bit ? bb : ~bb;
+    }
+    return m;
+}
+
+__global__ void __launch_bounds__(kSortThreads) k_onesweep(const uint32_t *__restrict__ kin,
+                                                           const int32_t *__restrict__ vin,
+                                                           uint32_t *__restrict__ kout, int32_t *__restrict__ vout,
+                                                           int64_t n, int pass, const uint32_t *__restrict__ ghist,
+                                                           uint32_t *__restrict__ tctr, uint64_t *__restrict__ flags,
+                                                           int64_t tiles, uint32_t epoch,
+                                                           const int32_t *__restrict__ skip, int64_t *err)
 {
     if (skip && skip[1]) return;
-    __shared__ uint32_t base[kRadix];
+    __shared__ uint32_t s_base[kRadix];               // where this tile's keys of each digit start
+    __shared__ uint32_t s_cnt[kRadix];                // this tile's count of each digit
     __shared__ uint32_t wcnt[kSortThreads / 64][kRadix];
+    __shared__ uint32_t s_scan[kSortThreads / 64];
+    __shared__ int64_t s_tile;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    base[tid] = offs[(int64_t)tid * tiles + blockIdx.x];
+    const int shift = 8 * pass;
+    if (tid == 0) s_tile = (int64_t)atomicAdd(&tctr[pass], 1u);
+    s_cnt[tid] = 0;
     for (int w = 0; w < kSortThreads / 64; ++w) wcnt[w][tid] = 0;
+    // exclusive prefix of the digit counts over all keys
+    const uint32_t g = ghist[pass * kRadix + tid];
+    uint32_t incl = g;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t t = __shfl_up(incl, off);
+        if (lane >= off) incl += t;
+    }
+    if (lane == 63) s_scan[wave] = incl;
     __syncthreads();
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
+    uint32_t gexcl = incl - g;
+    for (int w = 0; w < wave; ++w) gexcl += s_scan[w];
+    const int64_t t = s_tile;
+    if (t >= tiles) return;  // more workgroups than tiles: never launched so
+    // the tile's keys, in registers
+    uint32_t k[kSortItems];
+    int32_t val[kSortItems];
+    const int64_t tile0 = t * kSortTile;
+#pragma unroll
     for (int it = 0; it < kSortItems; ++it) {
         const int64_t p = tile0 + (int64_t)it * kSortThreads + tid;
         const bool valid = p < n;
-        const uint32_t k = valid ? kin[p] : 0u;
-        const int32_t val = valid ? (vin ? vin[p] : (int32_t)p) : 0;
-        const uint32_t d = (k >> shift) & (kRadix - 1);
-        uint64_t m = __ballot(valid);
+        k[it] = valid ? kin[p] : 0xffffffffu;
+        val[it] = valid ? (vin ? vin[p] : (int32_t)p) : 0;
+    }
+    // this tile's digit counts
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t bb = __ballot(bit);
-            m &= bit ? bb : ~bb;
+    for (int it = 0; it < kSortItems; ++it) {
+        const int64_t p = tile0 + (int64_t)it * kSortThreads + tid;
+        const bool valid = p < n;
+        const uint32_t d = (k[it] >> shift) & (kRadix - 1);
+        const uint64_t m = digit_mask(d, valid);
+        const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+        if (valid && (m & lt) == 0) atomicAdd(&s_cnt[d], (uint32_t)__popcll(m));
+    }
+    __syncthreads();
+    // publish, look back, publish the inclusive count
+    {
+        const uint32_t agg = s_cnt[tid];
+        uint64_t *fl = flags + (size_t)t * kRadix + tid;
+        uint32_t before = 0;
+        if (t == 0) {
+            __hip_atomic_store(fl, lb_word(epoch, 2u, agg), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            __hip_atomic_store(fl, lb_word(epoch, 1u, agg), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            int64_t j = t - 1;
+            uint32_t spins = 0;
+            while (j >= 0) {
+                const uint64_t w =
+                    __hip_atomic_load(flags + (size_t)j * kRadix + tid, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t st = (uint32_t)(w >> 32) & 3u;
+                if ((uint32_t)(w >> 34) != (epoch & 0x3fffffffu) || st == 0u) {
+                    if (++spins > kSpinLimit) {  // never expected: give up rather than hang
+                        raise_error(err, kErrSort, -2);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                before += (uint32_t)w;
+                if (st == 2u) break;
+                --j;
+            }
+            __hip_atomic_store(fl, lb_word(epoch, 2u, before + agg), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
+        s_base[tid] = gexcl + before;
+    }
+    __syncthreads();
+    // stable scatter, in rounds of 256 keys in position order
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+        const int64_t p = tile0 + (int64_t)it * kSortThreads + tid;
+        const bool valid = p < n;
+        const uint32_t d = (k[it] >> shift) & (kRadix - 1);
+        const uint64_t m = digit_mask(d, valid);
         const uint32_t rank = (uint32_t)__popcll(m & lt_mask);
         if (valid && rank == 0) wcnt[wave][d] = (uint32_t)__popcll(m);
         __syncthreads();
         if (valid) {
-            uint32_t pos = base[d] + rank;
+            uint32_t pos = s_base[d] + rank;
             for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
-            kout[pos] = k;
-            vout[pos] = val;
+            if ((int64_t)pos < n) {
+                kout[pos] = k[it];
+                vout[pos] = val[it];
+            }
         }
         __syncthreads();
         uint32_t add = 0;
@@ -216,7 +308,7 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint32_t *
             add += wcnt[w][tid];
             wcnt[w][tid] = 0;
         }
-        base[tid] += add;
+        s_base[tid] += add;
         __syncthreads();
     }
 }
@@ -224,8 +316,9 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint32_t *
 // Number of granules per cell key, from the sorted keys: the first lane of
 // each run of equal keys inside a wave adds the run's length.
 __global__ void __launch_bounds__(256) k_cell_count(const uint32_t *__restrict__ sk, int64_t n,
-                                                    uint32_t *__restrict__ cnt)
+                                                    uint32_t *__restrict__ cnt, const int32_t *__restrict__ skip)
 {
+    if (skip && skip[2]) return;
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const bool valid = q < n;
@@ -245,8 +338,9 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_down_ranges(uint32_t *__r
                                                                    uint32_t *__restrict__ begin,
                                                                    uint32_t *__restrict__ end, int64_t len,
                                                                    int64_t chunk, const uint32_t *__restrict__ sums,
-                                                                   int32_t *__restrict__ ctl)
+                                                                   int32_t *__restrict__ ctl, int keep)
 {
+    if (keep && ctl[2]) return;  // ranges unchanged (and no changed granule to uncount)
     if (blockIdx.x == 0 && threadIdx.x == 0) ctl[0] = 0;  // no changed granules counted for the next sort
     __shared__ uint32_t lds[kScanThreads / 64];
     const int64_t lo = (int64_t)blockIdx.x * chunk;
@@ -317,19 +411,39 @@ __device__ inline int lower_bound_u32(const uint32_t *a, int m, uint32_t v)
 }
 
 // One workgroup: decides the path, sorts C by (key, position) and by
-// position (bitonic, in LDS), and places the C elements.
+// position (bitonic, in LDS), and places the C elements.  With nl it also
+// decides whether the neighbour list must be rebuilt this step (nl[0]):
+// when force is set, when any key changed (the sorted order may change), or
+// when the largest squared displacement since the build (the maximum of the
+// nd per-workgroup maxima dpart of the key kernel) reaches thr2.
 __global__ void __launch_bounds__(1024) k_chg_sort(int64_t n, const uint32_t *__restrict__ pk,
                                                    const uint64_t *__restrict__ chg, int32_t *__restrict__ ctl,
                                                    uint64_t *__restrict__ chg_s, uint32_t *__restrict__ chg_p,
-                                                   uint32_t *__restrict__ skeys, int32_t *__restrict__ order)
+                                                   uint32_t *__restrict__ skeys, int32_t *__restrict__ order,
+                                                   uint32_t *__restrict__ nl, int force, float thr2,
+                                                   const float *__restrict__ dpart, int64_t nd)
 {
     __shared__ uint64_t sk[kChgCap];
     __shared__ uint32_t sp[kChgCap];
+    __shared__ float s_dm[1024 / 64];
     const int tid = threadIdx.x;
     const int m = ctl[0];
     const bool incremental = m <= kChgCap;
+    float dm = 0.0f;
+    if (dpart)
+        for (int64_t i = tid; i < nd; i += 1024) dm = fmaxf(dm, dpart[i]);
+    for (int off = 32; off > 0; off >>= 1) dm = fmaxf(dm, __shfl_xor(dm, off));
+    if ((tid & 63) == 0) s_dm[tid >> 6] = dm;
     __syncthreads();  // every thread has read ctl[0] before thread 0 writes ctl[1]
-    if (tid == 0) ctl[1] = incremental ? 1 : 0;
+    if (tid == 0) {
+        ctl[1] = incremental ? 1 : 0;
+        ctl[2] = m == 0 ? 1 : 0;  // no key changed: the last sort's order, ranges and bricks hold
+    }
+    if (tid == 0 && nl) {
+        float d2 = 0.0f;
+        for (int w = 0; w < 1024 / 64; ++w) d2 = fmaxf(d2, s_dm[w]);
+        nl[0] = (force || m != 0 || !(d2 < thr2)) ? 1u : 0u;
+    }
     if (!incremental || m == 0) return;
     int N = 2;
     while (N < m) N <<= 1;
@@ -403,8 +517,10 @@ __device__ inline bool brick_occupied(int64_t b, const int32_t *__restrict__ cb,
 }
 
 __global__ void __launch_bounds__(256) k_brick_count(int64_t nbricks, int64_t per_block, const int32_t *__restrict__ cb,
-                                                     const int32_t *__restrict__ ce, uint32_t *__restrict__ sums)
+                                                     const int32_t *__restrict__ ce, uint32_t *__restrict__ sums,
+                                                     const int32_t *__restrict__ skip)
 {
+    if (skip && skip[2]) return;
     __shared__ uint32_t lds[4];
     const int64_t lo = (int64_t)blockIdx.x * per_block;
     const int64_t hi = lo + per_block < nbricks ? lo + per_block : nbricks;
@@ -415,8 +531,10 @@ __global__ void __launch_bounds__(256) k_brick_count(int64_t nbricks, int64_t pe
 }
 
 // Exclusive scan of the block counts in place; the total is the list length.
-__global__ void __launch_bounds__(kScanThreads) k_brick_spine(uint32_t *sums, int nb, int32_t *count)
+__global__ void __launch_bounds__(kScanThreads) k_brick_spine(uint32_t *sums, int nb, int32_t *count,
+                                                              const int32_t *__restrict__ skip)
 {
+    if (skip && skip[2]) return;
     __shared__ uint32_t lds[kScanThreads / 64];
     const uint32_t v = threadIdx.x < nb ? sums[threadIdx.x] : 0u;
     uint32_t total;
@@ -427,8 +545,10 @@ __global__ void __launch_bounds__(kScanThreads) k_brick_spine(uint32_t *sums, in
 
 __global__ void __launch_bounds__(256) k_brick_scatter(int64_t nbricks, int64_t per_block,
                                                        const int32_t *__restrict__ cb, const int32_t *__restrict__ ce,
-                                                       const uint32_t *__restrict__ sums, int32_t *__restrict__ list)
+                                                       const uint32_t *__restrict__ sums, int32_t *__restrict__ list,
+                                                       const int32_t *__restrict__ skip)
 {
+    if (skip && skip[2]) return;
     __shared__ uint32_t lds[4];
     const int64_t lo = (int64_t)blockIdx.x * per_block;
     const int64_t hi = lo + per_block < nbricks ? lo + per_block : nbricks;
@@ -457,7 +577,7 @@ int64_t scan_chunk(int64_t len)
 
 hipError_t launch_sort_cells(const DevParams &P, int64_t n, const double *x, uint32_t *key, int32_t *order,
                              int32_t *cell_begin, int32_t *cell_end, int64_t K, SortScratch &S, int64_t *err,
-                             hipStream_t s)
+                             hipStream_t s, const NbrList *nl, int force, int keep_ranges)
 {
     uint32_t *cnt = S.cnt;  // all zero between sorts
     // previous sorted keys: usable when the last sort had the same n
@@ -465,56 +585,70 @@ hipError_t launch_sort_cells(const DevParams &P, int64_t n, const double *x, uin
     const uint32_t *pk = inc ? S.skeys[S.cur] : nullptr;
     uint32_t *skeys = S.skeys[S.cur ^ 1];
     const int32_t *skip = inc ? S.ctl : nullptr;
+    // the displacement since the list's build is measured when the list may
+    // be kept (its build had this sorted order: the caller checked that)
+    const bool measure = nl && inc && !force && nl->thr2 > 0.0f;
     if (n > 0) {
-        k_cell_keys<<<grid_for(n, 256), 256, 0, s>>>(P, n, x, key, err, pk, S.chg, S.ctl);
+        k_cell_keys<<<grid_for(n, 256), 256, 0, s>>>(P, n, x, key, err, pk, S.chg, S.ctl,
+                                                     measure ? nl->xref : nullptr, measure ? nl->dpart : nullptr,
+                                                     S.ghist);
         if (inc) {
-            k_chg_sort<<<1, 1024, 0, s>>>(n, pk, S.chg, S.ctl, S.chg_s, S.chg_p, skeys, order);
+            k_chg_sort<<<1, 1024, 0, s>>>(n, pk, S.chg, S.ctl, S.chg_s, S.chg_p, skeys, order,
+                                          nl ? nl->ctl : nullptr, measure ? 0 : 1, nl ? nl->thr2 : 0.0f,
+                                          measure ? nl->dpart : nullptr, (int64_t)grid_for(n, 256));
             k_merge<<<grid_for(n, 256), 256, 0, s>>>(n, key, pk, S.ctl, S.chg_s, S.chg_p, skeys, order);
         }
-        // radix passes (skipped on the device when the incremental path sorted)
+        // digit passes (skipped on the device when the incremental path sorted)
         const int64_t tiles = (n + kSortTile - 1) / kSortTile;
+        if ((++S.epoch & 0x3fffffffu) == 0u) {
+            // the 30-bit sort number wrapped: clear the words it tags
+            if (launch_fill_i64(reinterpret_cast<int64_t *>(S.flags), 4 * S.tiles_max * kRadix, s) != hipSuccess)
+                return hipGetLastError();
+            ++S.epoch;
+        }
+        unsigned hb = (unsigned)(tiles < 1024 ? tiles : 1024);
+        k_radix_hist_all<<<hb, kSortThreads, 0, s>>>(key, n, S.passes, S.ghist, skip);
         const uint32_t *kin = key;
         const int32_t *vin = nullptr;
         for (int pass = 0; pass < S.passes; ++pass) {
             const bool last = pass == S.passes - 1;
             uint32_t *kout = last ? skeys : ((pass & 1) ? S.kB : S.kA);
             int32_t *vout = last ? order : ((pass & 1) ? S.vB : S.vA);
-            const int shift = 8 * pass;
-            k_radix_hist<<<(unsigned)tiles, kSortThreads, 0, s>>>(kin, n, shift, S.hist, tiles, skip);
-            const int64_t len = tiles * kRadix;
-            const int64_t chunk = scan_chunk(len);
-            const int nb = (int)((len + chunk - 1) / chunk);
-            k_scan_reduce<<<nb, kScanThreads, 0, s>>>(S.hist, len, chunk, S.sums, skip);
-            k_scan_spine<<<1, kScanThreads, 0, s>>>(S.sums, nb, skip);
-            k_scan_down<<<nb, kScanThreads, 0, s>>>(S.hist, len, chunk, S.sums, skip);
-            k_radix_scatter<<<(unsigned)tiles, kSortThreads, 0, s>>>(kin, vin, kout, vout, n, shift, S.hist, tiles,
-                                                                     skip);
+            k_onesweep<<<(unsigned)tiles, kSortThreads, 0, s>>>(kin, vin, kout, vout, n, pass, S.ghist,
+                                                                 S.ghist + 4 * kRadix,
+                                                                 S.flags + (size_t)pass * S.tiles_max * kRadix,
+                                                                 tiles, S.epoch, skip, err);
             kin = kout;
             vin = vout;
         }
-        k_cell_count<<<grid_for(n, 256), 256, 0, s>>>(skeys, n, cnt);
     }
+    // cell ranges: kept when the caller's tables hold the last sort's ranges
+    // and no key changed (decided on the device by k_chg_sort)
+    const int keep = keep_ranges && inc ? 1 : 0;
+    const int32_t *kskip = keep ? S.ctl : nullptr;
+    if (n > 0) k_cell_count<<<grid_for(n, 256), 256, 0, s>>>(skeys, n, cnt, kskip);
     const int64_t chunk = scan_chunk(K);
     const int nb = (int)((K + chunk - 1) / chunk);
-    k_scan_reduce<<<nb, kScanThreads, 0, s>>>(cnt, K, chunk, S.sums, nullptr);
-    k_scan_spine<<<1, kScanThreads, 0, s>>>(S.sums, nb, nullptr);
+    k_scan_reduce<<<nb, kScanThreads, 0, s>>>(cnt, K, chunk, S.sums, kskip);
+    k_scan_spine<<<1, kScanThreads, 0, s>>>(S.sums, nb, kskip);
     k_scan_down_ranges<<<nb, kScanThreads, 0, s>>>(cnt, reinterpret_cast<uint32_t *>(cell_begin),
-                                                   reinterpret_cast<uint32_t *>(cell_end), K, chunk, S.sums, S.ctl);
+                                                   reinterpret_cast<uint32_t *>(cell_end), K, chunk, S.sums, S.ctl,
+                                                   keep);
     S.cur ^= 1;  // this sort's keys are the previous keys of the next
     S.last_n = n;
     return hipGetLastError();
 }
 
-hipError_t launch_brick_list(const int32_t *cb, const int32_t *ce, BrickList &B, hipStream_t s)
+hipError_t launch_brick_list(const int32_t *cb, const int32_t *ce, BrickList &B, hipStream_t s, const int32_t *skip)
 {
     const int64_t nb = B.nbricks;
     if (nb <= 0) return hipSuccess;
     int64_t per = 1024;
     while ((nb + per - 1) / per > kScanThreads) per *= 2;
     const int blocks = (int)((nb + per - 1) / per);
-    k_brick_count<<<blocks, 256, 0, s>>>(nb, per, cb, ce, B.sums);
-    k_brick_spine<<<1, kScanThreads, 0, s>>>(B.sums, blocks, B.count);
-    k_brick_scatter<<<blocks, 256, 0, s>>>(nb, per, cb, ce, B.sums, B.list);
+    k_brick_count<<<blocks, 256, 0, s>>>(nb, per, cb, ce, B.sums, skip);
+    k_brick_spine<<<1, kScanThreads, 0, s>>>(B.sums, blocks, B.count, skip);
+    k_brick_scatter<<<blocks, 256, 0, s>>>(nb, per, cb, ce, B.sums, B.list, skip);
     return hipGetLastError();
 }
 

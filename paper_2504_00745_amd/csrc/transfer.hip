@@ -14,6 +14,11 @@
 //
 // G2P: one thread per granule, 27 node reads from L1/L2 (sorted granules
 // read overlapping stencils).
+//
+// The unquantised transfers of the differentiable form (P2G and the grid
+// part of the G2P pullback) round every contribution to an integer at a
+// scale set by the largest contribution of the call and sum integers, so
+// their grids are the same bits in every run.
 #include "gic_launch.hpp"
 
 namespace gic {
@@ -319,39 +324,95 @@ __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_e
     }
 }
 
+// Unquantised P2G of the differentiable form, deterministic: every
+// contribution c of channel ch is rounded to the integer
+// rint(c 2^(50 - e_ch)), 2^e_ch the power of two at or above the largest
+// contribution bound of the channel in this call (frac_i for alpha,
+// |m_i v_i,a| for momentum), and the integers are summed in LDS and grid
+// atomics, exactly and in any order; k_fix_finish scales the sums back.  A
+// contribution is then off by at most 2^(e_ch - 51), the rounding of one
+// double addition at that magnitude, and a node's sum holds while fewer than
+// 2^12 granules reach it (|sum| < 2^62).
+constexpr int kFixParts = 1024;  // partial maxima per channel
+
+// Clears len int64 of fx and writes each workgroup's largest per-granule
+// bound of each channel to part[ch * kFixParts + block]: frac, |m v_x|,
+// |m v_y|, |m v_z| (P2G) or |gaf| (the G2P pullback, gaf given).
+__global__ void __launch_bounds__(256) k_fix_prep(DevParams P, int64_t n, int64_t per, const double *__restrict__ v,
+                                                  const double *__restrict__ r, const double *__restrict__ gaf,
+                                                  int64_t *__restrict__ fx, int64_t len, double *__restrict__ part)
+{
+    __shared__ double wm[4][4];
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < len; i += (int64_t)gridDim.x * 256) fx[i] = 0;
+    const int nch = gaf ? 1 : 4;
+    double m[4] = {0.0, 0.0, 0.0, 0.0};
+    const int64_t lo = (int64_t)blockIdx.x * per, hi = lo + per < n ? lo + per : n;
+    for (int64_t q = lo + threadIdx.x; q < hi; q += 256) {
+        if (gaf) {
+            m[0] = fmax(m[0], fabs(gaf[q]));
+        } else {
+            const double rq = r[q];
+            m[0] = fmax(m[0], volume_of(rq) * P.inv_vcell);
+            const double mq = mass_of(P, rq);
+            for (int c = 0; c < 3; ++c) m[c + 1] = fmax(m[c + 1], fabs(mq * v[c * n + q]));
+        }
+    }
+    for (int c = 0; c < nch; ++c) {
+        double t = m[c];
+        for (int off = 32; off > 0; off >>= 1) t = fmax(t, __shfl_xor(t, off));
+        if ((threadIdx.x & 63) == 0) wm[c][threadIdx.x >> 6] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < nch)
+        part[threadIdx.x * kFixParts + blockIdx.x] =
+            fmax(fmax(wm[threadIdx.x][0], wm[threadIdx.x][1]), fmax(wm[threadIdx.x][2], wm[threadIdx.x][3]));
+}
+
+// 2^(50 - e) with 2^e the power of two above the largest of nb partial
+// maxima (1 when they are all zero): contributions times it stay below 2^50.
+__device__ inline double fix_scale(const double *__restrict__ part, int nb)
+{
+    double M = 0.0;
+    for (int b = 0; b < nb; ++b) M = fmax(M, part[b]);
+    if (!(M > 0.0)) return 1.0;
+    int e;
+    (void)frexp(M, &e);  // M = f 2^e, f in [0.5, 1)
+    return ldexp(1.0, 50 - e);
+}
+
 __global__ void __launch_bounds__(kP2GThreads) k_p2g_real(DevParams P, int64_t n, const int32_t *__restrict__ bl,
                                                           const int32_t *__restrict__ bcnt,
                                                           const double *__restrict__ x,
                                                           const double *__restrict__ v,
                                                           const double *__restrict__ r,
                                                           const int32_t *__restrict__ cb,
-                                                          const int32_t *__restrict__ ce, double *__restrict__ alpha,
-                                                          double *__restrict__ mom)
+                                                          const int32_t *__restrict__ ce,
+                                                          const double *__restrict__ part, int nb, int nch,
+                                                          unsigned long long *__restrict__ fx)
 {
-    extern __shared__ double dtile[];
+    extern __shared__ unsigned long long itile[];
     __shared__ int32_t s_range[2];
     const int64_t b = brick_of_block(bl, bcnt);
     if (b < 0) return;
     brick_range(n, b, cb, ce, s_range);
+    const int E = P.tile;
+    const int E3 = E * E * E;
+    for (int k = threadIdx.x; k < nch * E3; k += kP2GThreads) itile[k] = 0ull;
     __syncthreads();
     const int32_t beg = s_range[0], end = s_range[1];
     if (end <= beg) return;
-    const int E = P.tile;
-    const int E3 = E * E * E;
-    const bool wa = alpha != nullptr, wm = mom != nullptr;
-    for (int k = threadIdx.x; k < 4 * E3; k += kP2GThreads) dtile[k] = 0.0;
+    double sc[4];
+    for (int c = 0; c < nch; ++c) sc[c] = fix_scale(part + c * kFixParts, nb);
     int32_t o[3];
     tile_origin(P, b, o);
-    __syncthreads();
     const int64_t G = P.G;
     for (int64_t q = beg + (int64_t)threadIdx.x; q < end; q += kP2GThreads) {
         const double xa[3] = {x[q], x[n + q], x[2 * n + q]};
         Stencil s;
         stencil_of(P, xa, s);
-        const double frac = volume_of(r[q]) * P.inv_vcell;
         const double m = mass_of(P, r[q]);
-        double S[4] = {frac, 0.0, 0.0, 0.0};
-        if (wm)
+        double S[4] = {volume_of(r[q]) * P.inv_vcell, 0.0, 0.0, 0.0};
+        if (nch > 1)
             for (int c = 0; c < 3; ++c) S[c + 1] = m * v[c * n + q];
         for (int cz = 0; cz < 3; ++cz)
             for (int cy = 0; cy < 3; ++cy)
@@ -362,24 +423,35 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g_real(DevParams P, int64_t n
                     const bool in = li >= 0 && lj >= 0 && lk >= 0 && li < E && lj < E && lk < E;
                     const int lidx = (lk * E + lj) * E + li;
                     const int64_t gidx = node_index(P, ni, nj, nk);
-                    for (int c = wa ? 0 : 1; c < (wm ? 4 : 1); ++c) {
-                        const double val = w * S[c];
-                        if (in)
-                            atomicAdd(&dtile[c * E3 + lidx], val);
-                        else
-                            unsafeAtomicAdd(c == 0 ? &alpha[gidx] : &mom[(c - 1) * G + gidx], val);
-                    }
+                    for (int c = 0; c < nch; ++c)
+                        tile_add(itile + c * E3, fx + c * G, in, lidx, gidx, rint_i64((w * S[c]) * sc[c]));
                 }
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < 4 * E3; k += kP2GThreads) {
-        const double val = dtile[k];
-        if (val == 0.0) continue;
+    for (int k = threadIdx.x; k < nch * E3; k += kP2GThreads) {
+        const unsigned long long val = itile[k];
+        if (val == 0ull) continue;
         const int c = k / E3;
         const int l = k - c * E3;
         const int32_t ni = o[0] + l % E, nj = o[1] + (l / E) % E, nk = o[2] + l / (E * E);
-        const int64_t gidx = node_index(P, ni, nj, nk);
-        unsafeAtomicAdd(c == 0 ? &alpha[gidx] : &mom[(c - 1) * G + gidx], val);
+        atomicAdd(&fx[c * G + node_index(P, ni, nj, nk)], val);
+    }
+}
+
+// out[c] (= or +=) the integer sums of channel c scaled back: fx / scale_c.
+__global__ void __launch_bounds__(256) k_fix_finish(int64_t G, int nch, const double *__restrict__ part, int nb,
+                                                    const int64_t *__restrict__ fx, double *__restrict__ out0,
+                                                    double *__restrict__ out1, int acc)
+{
+    __shared__ double inv[4];
+    if (threadIdx.x < nch) inv[threadIdx.x] = 1.0 / fix_scale(part + threadIdx.x * kFixParts, nb);
+    __syncthreads();
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < nch * G; k += (int64_t)gridDim.x * 256) {
+        const int c = (int)(k / G);
+        double *o = c == 0 ? (out0 ? out0 + k : nullptr) : (out1 ? out1 + (k - G) : nullptr);
+        if (!o) continue;
+        const double val = (double)fx[k] * inv[c];
+        *o = acc ? *o + val : val;
     }
 }
 
@@ -517,13 +589,94 @@ template hipError_t launch_integrate_p2g<double>(const DevParams &, int64_t, int
 
 hipError_t launch_p2g_real(const DevParams &P, int64_t n, int64_t K, const double *x, const double *v,
                            const double *r, const int32_t *cb, const int32_t *ce, const BrickList &B,
-                           double *alpha, double *mom, hipStream_t s)
+                           double *alpha, double *mom, int acc, int64_t *fx, double *part, hipStream_t s)
 {
-    if (n == 0) return hipSuccess;
-    const int64_t bricks = K / kBrickCells;
-    const int E3 = P.tile * P.tile * P.tile;
-    const size_t lds = sizeof(double) * 4 * (size_t)E3;
-    k_p2g_real<<<brick_grid(bricks), kP2GThreads, lds, s>>>(P, n, B.list, B.count, x, v, r, cb, ce, alpha, mom);
+    const int64_t G = P.G;
+    const int nch = mom ? 4 : 1;  // alpha is computed with the momentum and written when asked for
+    const int64_t per = n > 0 ? (n + kFixParts - 1) / kFixParts : 1;
+    const int nb = (int)(n > 0 ? (n + per - 1) / per : 1);
+    k_fix_prep<<<nb, 256, 0, s>>>(P, n, per, v, r, nullptr, fx, nch * G, part);
+    if (n > 0) {
+        const int64_t bricks = K / kBrickCells;
+        const int E3 = P.tile * P.tile * P.tile;
+        const size_t lds = sizeof(unsigned long long) * (size_t)nch * E3;
+        k_p2g_real<<<brick_grid(bricks), kP2GThreads, lds, s>>>(P, n, B.list, B.count, x, v, r, cb, ce, part, nb,
+                                                                 nch, reinterpret_cast<unsigned long long *>(fx));
+    }
+    unsigned g = grid_for(nch * G, 256);
+    if (g > 4096) g = 4096;
+    k_fix_finish<<<g, 256, 0, s>>>(G, nch, part, nb, fx, alpha, mom, acc);
+    return hipGetLastError();
+}
+
+// Grid part of the G2P pullback, deterministic like k_p2g_real: g_alpha_k =
+// -sum_i w_ik gaf_i on nodes below the clamp, the contributions rounded to
+// integers at the scale of the largest |gaf_i|.
+__global__ void __launch_bounds__(256) k_g2p_vjp_grid(DevParams P, int64_t n, const int32_t *__restrict__ bl,
+                                                      const int32_t *__restrict__ bcnt,
+                                                      const double *__restrict__ x, const double *__restrict__ A,
+                                                      const double *__restrict__ gaf,
+                                                      const int32_t *__restrict__ cb, const int32_t *__restrict__ ce,
+                                                      const double *__restrict__ part, int nb,
+                                                      unsigned long long *__restrict__ fx)
+{
+    extern __shared__ unsigned long long itile[];
+    __shared__ int32_t s_range[2];
+    const int64_t b = brick_of_block(bl, bcnt);
+    if (b < 0) return;
+    brick_range(n, b, cb, ce, s_range);
+    const int E = P.tile;
+    const int E3 = E * E * E;
+    for (int k = threadIdx.x; k < E3; k += 256) itile[k] = 0ull;
+    __syncthreads();
+    const int32_t beg = s_range[0], end = s_range[1];
+    if (end <= beg) return;
+    const double sc = fix_scale(part, nb);
+    int32_t o[3];
+    tile_origin(P, b, o);
+    for (int64_t q = beg + (int64_t)threadIdx.x; q < end; q += 256) {
+        const double xa[3] = {x[q], x[n + q], x[2 * n + q]};
+        Stencil s;
+        stencil_of(P, xa, s);
+        const double sg = -gaf[q];
+        for (int cz = 0; cz < 3; ++cz)
+            for (int cy = 0; cy < 3; ++cy)
+                for (int cx = 0; cx < 3; ++cx) {
+                    const int32_t ni = s.node[0][cx], nj = s.node[1][cy], nk = s.node[2][cz];
+                    const int64_t gidx = node_index(P, ni, nj, nk);
+                    if (!(A[gidx] < P.alpha_max)) continue;
+                    const int64_t val = rint_i64((((s.w[0][cx] * s.w[1][cy]) * s.w[2][cz]) * sg) * sc);
+                    const int32_t li = ni - o[0], lj = nj - o[1], lk = nk - o[2];
+                    const bool in = li >= 0 && lj >= 0 && lk >= 0 && li < E && lj < E && lk < E;
+                    tile_add(itile, fx, in, (lk * E + lj) * E + li, gidx, val);
+                }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < E3; k += 256) {
+        const unsigned long long val = itile[k];
+        if (val == 0ull) continue;
+        const int32_t ni = o[0] + k % E, nj = o[1] + (k / E) % E, nk = o[2] + k / (E * E);
+        atomicAdd(&fx[node_index(P, ni, nj, nk)], val);
+    }
+}
+
+hipError_t launch_g2p_vjp_grid(const DevParams &P, int64_t n, int64_t K, const double *x, const double *A,
+                               const double *gaf, const int32_t *cb, const int32_t *ce, const BrickList &B,
+                               double *gA, int64_t *fx, double *part, hipStream_t s)
+{
+    const int64_t G = P.G;
+    const int64_t per = n > 0 ? (n + kFixParts - 1) / kFixParts : 1;
+    const int nb = (int)(n > 0 ? (n + per - 1) / per : 1);
+    k_fix_prep<<<nb, 256, 0, s>>>(P, n, per, nullptr, nullptr, gaf, fx, G, part);
+    if (n > 0) {
+        const int64_t bricks = K / kBrickCells;
+        const size_t lds = sizeof(unsigned long long) * (size_t)P.tile * P.tile * P.tile;
+        k_g2p_vjp_grid<<<brick_grid(bricks), 256, lds, s>>>(P, n, B.list, B.count, x, A, gaf, cb, ce, part, nb,
+                                                            reinterpret_cast<unsigned long long *>(fx));
+    }
+    unsigned g = grid_for(G, 256);
+    if (g > 4096) g = 4096;
+    k_fix_finish<<<g, 256, 0, s>>>(G, 1, part, nb, fx, gA, nullptr, 0);
     return hipGetLastError();
 }
 

@@ -60,9 +60,12 @@ def lib():
             "gic_set_params": (C.c_int, [_V, _PP]),
             "gic_destroy": (C.c_int, [_V]),
             "gic_get_error": (C.c_int, [_V, _V, C.POINTER(_I32), C.POINTER(_I64), _I32]),
+            "gic_neighbour_builds": (C.c_int, [_V, _V, C.POINTER(_I64)]),
+            "gic_stage_timing": (C.c_int, [_V, _I32]),
+            "gic_stage_times": (C.c_int, [_V, _V, C.POINTER(C.c_double), C.POINTER(_I32)]),
             "gic_sort_cells": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V]),
             "gic_reorder": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V, _V, _V, _V]),
-            "gic_contact_forces": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V, _V]),
+            "gic_contact_forces": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V, _V, _I32, _V]),
             "gic_contact_capillary_forces": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V, _V, _V, _V]),
             "gic_integrate_p2g_wet": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V, _V, _V, _V, _I32, _V]),
             "gic_moisture_ratio": (C.c_int, [_V, _I64, _V, _V, _V, _V]),
@@ -72,7 +75,6 @@ def lib():
             "gic_idp_solve": (C.c_int, [_V] * 6 + [_I32, C.c_double, _I32, _I32, _V, _V, _V]),
             "gic_idp_displacement": (C.c_int, [_V] * 7),
             "gic_density_projection": (C.c_int, [_V] * 9 + [_I32, C.c_double, _I32, _I32, _V, _V, _V]),
-            "gic_contact_pairs": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _I64, _V, _V]),
             "gic_g2p": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V]),
             "gic_drag": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V]),
             "gic_integrate": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V]),
@@ -91,6 +93,7 @@ def lib():
             "gic_p2g_vjp": (C.c_int, [_V, _I64] + [_V] * 8),
             "gic_sum": (C.c_int, [_V, _I64, _V, _V, _V, _I32, _V]),
             "gic_permute": (C.c_int, [_V, _I64, _I32, _V, _V, _V, _I32, _V]),
+            "gic_scale": (C.c_int, [_V, _I64, _V, _V, C.c_double, _V, _V]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -184,6 +187,26 @@ class Context:
                "gic_get_error")
         return int(code.value), int(idx.value)
 
+    def neighbour_builds(self):
+        """Neighbour-list builds on this context so far (synchronises)."""
+        b = _I64()
+        _check(lib().gic_neighbour_builds(self.handle, _stream(), C.byref(b)), "gic_neighbour_builds")
+        return int(b.value)
+
+    STAGES = ("sort", "gather", "contact", "exchange", "grid_clear", "integrate_p2g")
+
+    def stage_timing(self, max_steps):
+        """Record stage events in the next max_steps (sub-)steps (0: off)."""
+        _check(lib().gic_stage_timing(self.handle, int(max_steps)), "gic_stage_timing")
+
+    def stage_times(self):
+        """(dict stage -> summed ms, number of steps) since the last call
+        (synchronises)."""
+        ms = (C.c_double * 6)()
+        k = _I32()
+        _check(lib().gic_stage_times(self.handle, _stream(), ms, C.byref(k)), "gic_stage_times")
+        return dict(zip(self.STAGES, list(ms))), int(k.value)
+
     def close(self):
         if getattr(self, "handle", None):
             lib().gic_destroy(self.handle)
@@ -212,13 +235,17 @@ def gic_reorder(ctx, order, x, v, r, id_, x_out, v_out, r_out, id_out):
            "gic_reorder")
 
 
-def gic_contact_forces(ctx, x, v, r, cell_begin, cell_end, f_contact, n_contacts=None):
+def gic_contact_forces(ctx, x, v, r, cell_begin, cell_end, f_contact, n_contacts=None, pair_ids=None):
+    """pair_ids: optional (cap, n) int32 tensor receiving the touching
+    partners of every granule (sorted positions, -1 after the last)."""
     n = x.shape[-1]
     f64 = torch.float64
+    cap = 0 if pair_ids is None else pair_ids.numel() // max(n, 1)
     _check(lib().gic_contact_forces(ctx.handle, n, _ptr(x, f64, 3 * n), _ptr(v, f64, 3 * n), _ptr(r, f64, n),
                                     _ptr(cell_begin, torch.int32, ctx.K), _ptr(cell_end, torch.int32, ctx.K),
                                     _ptr(f_contact, ctx.real, 3 * n, "f_contact"),
-                                    _ptr(n_contacts, torch.int32, n), _stream()), "gic_contact_forces")
+                                    _ptr(n_contacts, torch.int32, n), _ptr(pair_ids, torch.int32, cap * n, "pair_ids"),
+                                    int(cap), _stream()), "gic_contact_forces")
 
 
 def gic_contact_capillary_forces(ctx, x, v, r, sr, cell_begin, cell_end, f_contact, n_contacts=None, held=None):
@@ -299,15 +326,6 @@ def gic_density_projection(ctx, alpha_fx, alpha_star, label, q, fx, fy, fz, work
                                         int(max_iter), float(tol), int(check_every), int(precond), C.byref(it),
                                         C.byref(rel), _stream()), "gic_density_projection")
     return int(it.value), float(rel.value)
-
-
-def gic_contact_pairs(ctx, x, r, cell_begin, cell_end, pairs, count):
-    n = x.shape[-1]
-    cap = pairs.numel() // 2
-    _check(lib().gic_contact_pairs(ctx.handle, n, _ptr(x, torch.float64, 3 * n), _ptr(r, torch.float64, n),
-                                   _ptr(cell_begin, torch.int32, ctx.K), _ptr(cell_end, torch.int32, ctx.K),
-                                   _ptr(pairs, torch.int32), cap, _ptr(count, torch.int64, 1), _stream()),
-           "gic_contact_pairs")
 
 
 def gic_g2p(ctx, x, u, alpha_fx, alpha_real, u_at, alpha_f):
@@ -500,6 +518,13 @@ def gic_p2g_vjp(ctx, x, v, r, g_alpha, g_mom, g_x, g_v):
 def gic_sum(ctx, a, out, b=None, accumulate=False):
     _check(lib().gic_sum(ctx.handle, a.numel(), _ptr(a, torch.float64), _ptr(b, torch.float64, a.numel()),
                          _ptr(out, torch.float64, 1), int(bool(accumulate)), _stream()), "gic_sum")
+
+
+def gic_scale(ctx, a, s, factor, out):
+    """out = (factor s[0]) a, s a one-element device tensor (float64)."""
+    n = a.numel()
+    _check(lib().gic_scale(ctx.handle, n, _ptr(a, torch.float64), _ptr(s, torch.float64, 1, "s"), float(factor),
+                           _ptr(out, torch.float64, n, "out"), _stream()), "gic_scale")
 
 
 def gic_permute(ctx, order, src, dst, comps, scatter):

@@ -12,7 +12,9 @@ steps in the forward, each segment is recomputed in the backward and walked
 in reverse.  The granule state is kept in input order; each step sorts, works
 on a sorted copy and scatters the result back, so adjoints are gathered and
 scattered with the same permutations.  PyTorch provides device memory and
-the stream only.
+the stream only: the loss cotangent is scaled on the device (gic_scale) and
+the parameters mu and c_drag, kernel arguments, are read from host tensors
+(or numbers), so neither pass reads the device back.
 """
 import torch
 
@@ -48,12 +50,10 @@ class Rollout:
 
     # ---- forward pieces --------------------------------------------------
     def _sorted(self, x, v):
-        """Sort by cell, gather x, v, r into sorted order."""
+        """Sort by cell, gather x, v, r into sorted order (one kernel)."""
         c = self.ctx
         gic.gic_sort_cells(c, x.view(3, -1), self.key, self.order, self.cb, self.ce)
-        gic.gic_permute(c, self.order, x, self.xs, 3, False)
-        gic.gic_permute(c, self.order, v, self.vs, 3, False)
-        gic.gic_permute(c, self.order, self.r, self.rs, 1, False)
+        gic.gic_reorder(c, self.order, x.view(3, -1), v, self.r, None, self.xs, self.vs, self.rs, None)
 
     def _forces(self):
         c = self.ctx
@@ -101,9 +101,10 @@ class Rollout:
         gx = torch.zeros(3 * n, dtype=torch.float64, device="cuda")
         gv = torch.zeros_like(gx)
         self.scal[1:3].zero_()
-        # L = sum P^2  ->  dL/dP = 2 gL P
+        # L = sum P^2  ->  dL/dP = 2 gL P, gL a device scalar
         self.loss(x, v)
-        gP = self.P * (2.0 * float(gL))
+        gP = torch.empty_like(self.P)
+        gic.gic_scale(c, self.P, gL.reshape(1).to(torch.float64), 2.0, gP)
         self.gxs.zero_()
         self.gvs.zero_()
         gic.gic_p2g_vjp(c, self.xs.view(3, -1), self.vs, self.rs, None, gP, self.gxs, self.gvs)
@@ -146,7 +147,10 @@ class GICRollout(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, x0, v0, mu, c_drag, sim):
-        sim.set_params(mu.item(), c_drag.item())
+        # mu and c_drag are kernel arguments: host values (CPU tensors or
+        # numbers), read without a device synchronisation
+        sim.set_params(float(mu.detach().cpu()) if mu.is_cuda else float(mu),
+                       float(c_drag.detach().cpu()) if c_drag.is_cuda else float(c_drag))
         L, ckpts, final = sim.forward(x0, v0)
         ctx.sim = sim
         ctx.ckpts = ckpts
@@ -155,5 +159,5 @@ class GICRollout(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, gL):
-        gv0, gmu, gcd = ctx.sim.backward(ctx.ckpts, ctx.final, gL.item())
+        gv0, gmu, gcd = ctx.sim.backward(ctx.ckpts, ctx.final, gL)
         return None, gv0, gmu.view(()), gcd.view(()), None

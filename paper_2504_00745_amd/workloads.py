@@ -26,6 +26,8 @@ Workloads (granules N, grid, neighbour cell edge h):
   c4      65,536 bidisperse r=0.004/0.006 (70/30 by count) by random
           sequential addition at 0.30 in z<0.245, v ~ N(0,0.05^2), 64^3 grid
           dx=0.01, h=0.016, 8 modes A=0.1, C_d=1000, dt=1e-5, 20 steps.
+  c3s     the c3 bed scaled down for tests: 8,192 granules on a 16x32x16
+          lattice in a 32^3 grid, the same spacing, jitter, cell and step.
   c5      16,777,216 radii U[0.00075, 0.0015] on a jittered 512x256x128
           lattice of spacing 0.003 (lower half of a 512x256x256 grid,
           dx=0.003, h=dx), v ~ N(0, 0.02^2), shear u_x = 0.5 z/L_z plus 32
@@ -42,7 +44,7 @@ import numpy as np
 _BASE = dict(kn=1.0e5, restitution=0.5, kt_ratio=1.0, mu=0.5, rho_s=2500.0, eta_f=1.0e-3, c_drag=1.0,
              alpha_max=0.740, walls=0x3F)
 
-WORKLOADS = ("c1", "c1b", "c2", "c3", "c4", "c5")
+WORKLOADS = ("c1", "c1b", "c2", "c3", "c3s", "c4", "c5")
 
 
 def _params(n, dx, cell, dt, g, **kw):
@@ -68,6 +70,9 @@ def spec(name: str) -> dict:
     if name == "c3":
         p = _params([256, 128, 128], 0.004, 0.004, 2e-6, G0)
         return dict(name=name, N=4194304, steps=50, precision="fp32", params=p, seed=3)
+    if name == "c3s":
+        p = _params([32, 32, 32], 0.004, 0.004, 2e-6, G0)
+        return dict(name=name, N=8192, steps=50, precision="fp32", params=p, seed=3)
     if name == "c4":
         p = _params([64] * 3, 0.01, 0.016, 1e-5, Z, c_drag=1000.0)
         return dict(name=name, N=65536, steps=20, precision="fp64", params=p, seed=4, checkpoint=5)
@@ -230,10 +235,10 @@ def make(name: str, seed=None, n_override=None) -> dict:
         else:
             v = rng.normal(0.0, 0.05, size=(3, N))
             u = fourier_field(n, dx, 8, 0.1, rng)
-    elif name == "c3":
+    elif name in ("c3", "c3s"):
         r0 = 0.001
         sp = 2 * r0 - 1e-8
-        x = _lattice((128, 256, 128), sp, (0.0, 0.0, 0.0), 2e-9, rng)
+        x = _lattice((128, 256, 128) if name == "c3" else (16, 32, 16), sp, (0.0, 0.0, 0.0), 2e-9, rng)
         N = x.shape[1]
         r = np.full(N, r0)
         v = np.zeros((3, N))

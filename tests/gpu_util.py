@@ -48,7 +48,8 @@ def run_stages(cfg, x, v, r, u, precision, alpha_in=None, r_max=None):
     gic.gic_drag(ctx, Rs, Vs, uat, af, Fd)
     Fc = torch.empty(3 * n, dtype=real, device="cuda")
     nct = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
-    gic.gic_contact_forces(ctx, Xs.view(3, n), Vs, Rs, cb, ce, Fc, nct)
+    pairs = torch.empty(PAIR_CAP * max(n, 1), dtype=torch.int32, device="cuda")
+    gic.gic_contact_forces(ctx, Xs.view(3, n), Vs, Rs, cb, ce, Fc, nct, pair_ids=pairs[:PAIR_CAP * n])
     X1, V1 = Xs.clone(), Vs.clone()
     gic.gic_integrate(ctx, Rs, Fc, Fd, X1, V1)
     A1 = torch.empty(ctx.G, dtype=torch.int64, device="cuda")
@@ -66,10 +67,30 @@ def run_stages(cfg, x, v, r, u, precision, alpha_in=None, r_max=None):
             o[ids] = a
         return o
 
+    out["pairs"] = pair_set(pairs[:PAIR_CAP * n].cpu().numpy().reshape(PAIR_CAP, n), ids)
     out.update(u_at=unsort(uat, 3), alpha_f=unsort(af, 1), Fd=unsort(Fd, 3), Fc=unsort(Fc, 3),
                ncont=unsort(nct[:n], 1).astype(np.int64), x1=unsort(X1, 3), v1=unsort(V1, 3),
                alpha1=A1.cpu().numpy(), mom1=M1.cpu().numpy().reshape(3, -1), err=ctx.error())
     return out
+
+
+PAIR_CAP = 32  # touching partners kept per granule by the pair output of gic_contact_forces
+
+
+def pair_set(P, ids):
+    """Set of touching pairs (i, j), i < j, in input indices, from the pair
+    output of gic_contact_forces (P: cap x n sorted positions, -1 after the
+    last; ids[q] = input index at sorted position q).  Every pair must be
+    listed from both of its granules."""
+    cap, n = P.shape
+    mask = P >= 0
+    q = np.nonzero(mask)[1]
+    j = P[mask]
+    a, b = ids[q], ids[j]
+    directed = set(zip(a.tolist(), b.tolist()))
+    assert len(directed) == q.size, "a partner listed twice"
+    assert all((y, x) in directed for x, y in directed), "a pair listed from one side only"
+    return set((min(x, y), max(x, y)) for x, y in directed)
 
 
 def p2g_of(cfg, x, v, r, precision, r_max=None):

@@ -149,17 +149,67 @@ def test_rollout_gradient(T, orc, n_gran, steps):
         Lt, _, _ = sim.forward(x0, T.dev(vv.reshape(3, -1)))
         return Lt.item()
 
-    eps_floor = lambda h: 50 * np.finfo(float).eps * Lg / h
-    h = 1e-6 * max(cfg["mu"], 1)
-    fd = (L_gpu(mu_=cfg["mu"] + h) - L_gpu(mu_=cfg["mu"] - h)) / (2 * h)
-    assert fd == pytest.approx(g_mu, rel=1e-4, abs=eps_floor(h))
-    h = 1e-6 * max(cfg["c_drag"], 1)
-    fd = (L_gpu(cd_=cfg["c_drag"] + h) - L_gpu(cd_=cfg["c_drag"] - h)) / (2 * h)
-    assert fd == pytest.approx(g_cd, rel=1e-4, abs=eps_floor(h))
-    h = 1e-6 * max(np.linalg.norm(v), 1)
-    fd = (L_gpu(vv=v + h * dv) - L_gpu(vv=v - h * dv)) / (2 * h)
-    assert fd == pytest.approx(np.sum(g_v0 * dv), rel=1e-4, abs=eps_floor(h))
-    # non-vacuity on the full bed: the parameters move the loss well above the
-    # FD floor (the thinned bed has too few sliding contacts for mu to matter)
+    # FD round-off floor: the loss carries ~eps |L| of rounding per
+    # evaluation, so a central difference resolves a derivative only to about
+    # 50 eps |L| / h; the FD comparison is made, at 1e-4 with no absolute
+    # slack, wherever that floor is below a tenth of the bar (else it could
+    # not tell a wrong gradient from a right one, and only the oracle's reverse
+    # pass above checks it)
+    eps_floor = lambda h: 50 * np.finfo(float).eps * abs(Lg) / h
+    # v0 directions with a derivative the differences can resolve: the
+    # oracle's gradient direction and the unit vectors of its 8 largest
+    # components (a random direction over 196,608 components has a
+    # derivative below the round-off floor)
+    og = ogv.reshape(-1)
+    dirs = [("v0 along the oracle gradient", og / np.linalg.norm(og))]
+    for k in np.argsort(-np.abs(og))[:8]:
+        e = np.zeros_like(og)
+        e[k] = 1.0
+        dirs.append((f"v0 component {int(k)}", e))
+    cases = [("mu", g_mu, dict(mu_=cfg["mu"] + 1e-6 * max(cfg["mu"], 1)),
+              dict(mu_=cfg["mu"] - 1e-6 * max(cfg["mu"], 1)), 1e-6 * max(cfg["mu"], 1)),
+             ("c_drag", g_cd, dict(cd_=cfg["c_drag"] + 1e-6 * max(cfg["c_drag"], 1)),
+              dict(cd_=cfg["c_drag"] - 1e-6 * max(cfg["c_drag"], 1)), 1e-6 * max(cfg["c_drag"], 1))]
+    for name_, e in dirs:
+        e = e.reshape(v.shape)
+        h = 1e-6 * max(np.abs(v[e != 0]).max(), 1.0) if np.count_nonzero(e) == 1 else 1e-6 * max(
+            np.linalg.norm(v), 1.0)
+        cases.append((name_, np.sum(g_v0 * e), dict(vv=v + h * e), dict(vv=v - h * e), h))
+    checked = []
+    for name_, g_, plus, minus, h in cases:
+        if eps_floor(h) > 1e-5 * abs(g_):
+            continue
+        fd = (L_gpu(**plus) - L_gpu(**minus)) / (2 * h)
+        assert fd == pytest.approx(g_, rel=1e-4), name_
+        checked.append(name_)
+    T.say(f"[adjoint rollout] FD-checked: {checked}")
+    assert "c_drag" in checked and "v0 along the oracle gradient" in checked
+    assert any(c.startswith("v0 component") for c in checked)
+    # on the full bed every parameter moves the loss well above the FD floor
+    # (the thinned bed has too few sliding contacts for mu to matter)
     if n_gran == 65536:
+        assert "mu" in checked
         assert abs(g_mu * cfg["mu"]) > 1e-5 * Lg and abs(g_cd * cfg["c_drag"]) > 1e-5 * Lg
+
+
+def test_rollout_is_deterministic(T):
+    """The c4 rollout (65,536 granules, 20 steps, checkpoint 5) twice, each
+    on a fresh context: loss and all gradients are the same bits (every
+    transfer of the differentiable form sums integers; the parameter sums
+    run in a fixed order)."""
+    import torch
+    from paper_2504_00745_amd.rollout import GICRollout, Rollout
+    T.say("[adjoint rollout] determinism, c4")
+    d = wl.make("c4")
+    cfg, x, v, r, u = d["params"], d["x"], d["v"], d["r"], d["u"]
+    outs = []
+    for _ in range(2):
+        sim = Rollout(cfg, r, u, 20, ckpt=5, r_max=float(r.max()))
+        v0 = T.dev(v.reshape(3, -1)).requires_grad_(True)
+        mu = torch.tensor(cfg["mu"], dtype=torch.float64, requires_grad=True)
+        cd = torch.tensor(cfg["c_drag"], dtype=torch.float64, requires_grad=True)
+        L = GICRollout.apply(T.dev(x.reshape(3, -1)), v0, mu, cd, sim)
+        L.backward()
+        outs.append((L.detach().cpu(), v0.grad.cpu(), mu.grad.clone(), cd.grad.clone()))
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)

@@ -10,7 +10,9 @@ the oracle over the whole grid, and the advanced grid's total (independent
 of positions) equal to it; contact forces and advanced velocities of a
 random sample of granules against the oracle (computed one by one: contact,
 G2P and drag of the input state), to the 1e-5 FP32-form bar of the
-pair-force sums.
+pair-force sums; the touching partners of the sampled granules from the
+contact kernel's pair output equal the oracle's; at c3, the HIP P2G of the
+oracle's whole advanced state equals the oracle's P2G of it bit for bit.
 """
 import math
 
@@ -85,6 +87,35 @@ def test_full_size_step(T, orc, name):
     v_pred = v[:, idx] + cfg["dt"] * ((Fs + Fd) / m + g)
     scale = np.linalg.norm(v_pred, axis=0) + cfg["dt"] * (fa + np.linalg.norm(Fd, axis=0) + m * 9.81) / m
     assert np.all(np.linalg.norm(v1[:, idx] - v_pred, axis=0) <= 1e-5 * scale)
+    # touching partners of the sample from the production contact kernel's
+    # pair output, on the sorted input state
+    T.say(f"[full size] {name}: pair sets of the sample")
+    cur, nxt = sim.cur, sim.nxt
+    X0 = T.dev(x.reshape(-1))
+    gic.gic_sort_cells(sim.ctx, X0.view(3, n), s["key"], s["order"], s["cell_begin"], s["cell_end"])
+    ID0 = torch.arange(n, dtype=torch.int32, device="cuda")
+    gic.gic_reorder(sim.ctx, s["order"], X0.view(3, n), T.dev(v.reshape(-1)), T.dev(r), ID0, nxt["x"], nxt["v"],
+                    nxt["r"], nxt["id"])
+    del X0
+    cap = 16
+    PR = torch.empty(cap * n, dtype=torch.int32, device="cuda")
+    gic.gic_contact_forces(sim.ctx, nxt["x"], nxt["v"], nxt["r"], s["cell_begin"], s["cell_end"], s["f_contact"],
+                           pair_ids=PR)
+    torch.cuda.synchronize()
+    ids = nxt["id"].cpu().numpy()
+    sp = np.empty(n, np.int64)
+    sp[ids] = np.arange(n)
+    P = PR.view(cap, n)[:, torch.as_tensor(sp[idx], device="cuda")].cpu().numpy()
+    del PR
+    got = [set(ids[P[:, k][P[:, k] >= 0]].tolist()) for k in range(idx.size)]
+    ref = orc.pairs_sample(cfg, x, r, idx)
+    assert got == ref and sum(map(len, ref)) > 0
+    if name == "c3":
+        # P2G of the oracle's advanced state (every granule) through the HIP path
+        T.say(f"[full size] {name}: oracle step of every granule")
+        st = orc.step(cfg, x, v, r, u, a0)
+        a1g, m1g = T.p2g_of(cfg, st["x"], st["v"], r, "fp32", r_max=float(r.max()))
+        assert np.array_equal(a1g, st["alpha"]) and np.array_equal(m1g, st["mom"])
     T.say(f"[full size] {name}: ok, contacts in sample {int((fa > 0).sum())}")
 
 

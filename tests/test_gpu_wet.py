@@ -204,7 +204,7 @@ def test_raised_clamp_in_g2p_and_projection_target(G, orc, prec):
     import torch
     import oracle.idp as oidp
     from paper_2504_00745_amd import gic
-    d = wl.make("c1", n_override=3001)
+    d = wl.make("c1")
     cfg = dict(d["params"], absorb_max=0.3)
     x, u = d["x"], d["u"]
     n = x.shape[1]
@@ -214,7 +214,8 @@ def test_raised_clamp_in_g2p_and_projection_target(G, orc, prec):
     ctx = gic.Context(cfg, n, prec, r_max=float(d["r"].max()))
     real = ctx.real
     Ua, Af = torch.empty(3 * n, dtype=real, device="cuda"), torch.empty(n, dtype=real, device="cuda")
-    gic.gic_g2p(ctx, G.dev(x.reshape(-1)), G.dev(u.reshape(-1), real), G.dev(a, torch.int64), None, Ua, Af)
+    gic.gic_g2p(ctx, G.dev(x.reshape(-1)).view(3, n), G.dev(u.reshape(-1), real), G.dev(a, torch.int64), None, Ua,
+                Af)
     _, af_o = orc.g2p(cfg, x, u, alpha_fx=a)
     tol = 1e-5 if prec == "fp32" else 1e-12
     assert np.max(np.abs(Af.double().cpu().numpy() - af_o)) <= tol
