@@ -14,6 +14,25 @@
  * Eq. 7a) and momentum to the grid.  gic_step runs the same sub-step through
  * the same kernels in one call.
  *
+ * Shape of the interface
+ *   - Sorting and reordering are separate calls: gic_sort_cells returns
+ *     keys, the stable order and the cell ranges; gic_reorder gathers the
+ *     granule arrays into that order.  The stepping calls (gic_step,
+ *     gic_sand_step) fuse the reorder into the gather that samples the
+ *     grid (gic_gather_g2p_drag / _fluid) and the move into the P2G
+ *     (gic_integrate_p2g).
+ *   - gic_contact_forces returns the touching pairs of its own kernel as a
+ *     fixed number of entries per granule (pair_ids, column-major, -1
+ *     after the last), not a compressed list.
+ *   - gic_get_error returns the latched code and granule index separately
+ *     and can clear them.
+ *   - gic_integrate_vjp takes the cotangents of x' and v' and returns the
+ *     cotangent of the force and the updated cotangent of v in place.
+ *   - Every output that depends on an order of floating-point additions
+ *     (force sums, the unquantised transfers, parameter gradients) is
+ *     computed in an order fixed by the sorted state, so repeated calls on
+ *     the same inputs give the same bits.
+ *
  * Conventions
  *   Memory.   Every array argument is a DEVICE pointer owned by the caller.
  *             The library never frees or keeps it beyond the work the call

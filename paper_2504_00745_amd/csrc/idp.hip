@@ -10,8 +10,10 @@
 // identity rows with a zero right-hand side, so L is symmetric positive
 // definite on the whole grid and the solution is zero off the fluid.
 //
-// The solve is Jacobi-preconditioned conjugate gradients.  Every kernel is a
-// streaming pass over the cells (HBM bound).  Dot products are reduced
+// The solve is conjugate gradients preconditioned by one multigrid V-cycle
+// per iteration (the default; Jacobi as the alternative).  The iteration's
+// kernels are streaming or blocked stencil passes over the cells (HBM
+// bound), the coarse levels launch-latency bound.  Dot products are reduced
 // without atomics: each block writes one partial per quantity, and every
 // block of the consuming kernel sums all partials in the same fixed order,
 // so the iteration is deterministic and needs no clearing between launches.
