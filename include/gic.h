@@ -510,6 +510,20 @@ gic_status gic_p2g_vjp(gic_ctx *ctx, int64_t n, const double *x, const double *v
 gic_status gic_sum(gic_ctx *ctx, int64_t n, const double *a, const double *b, double *out, int32_t accumulate,
                    void *stream);
 
+/* gic_sum without a context, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same kernels and summation order as gic_sum (so the same
+ * bits), with its 1,024 partial sums in a fixed 8 KiB array that the library
+ * holds on each device until the process ends.  Nothing is allocated, and
+ * the call neither synchronises nor clears memory (the partials are written
+ * before they are read).  GIC_E_ARG for n > 2^30 (1,024 partials of at most
+ * 2^20 values), n < 0, a or out NULL; GIC_E_HIP if the array's address
+ * cannot be looked up.  Every call on one GPU uses that GPU's one array:
+ * calls that overlap on a GPU (concurrent streams) race and must be
+ * serialised by the caller. */
+gic_status gic_sum_noalloc(int64_t n, const double *a, const double *b, double *out, int32_t accumulate,
+                           void *stream);
+
 /* out[i] = (factor s[0]) a[i], i < n, with s a DEVICE scalar: e.g. the
  * cotangent of the rollout loss L = sum P^2, dL/dP = (2 gL) P, formed
  * without reading gL back to the host.  out may alias a. */

@@ -3,6 +3,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "../../include/gic.h"
 #include "gic_launch.hpp"
 #include "idp_launch.hpp"
@@ -187,6 +189,8 @@ bool fp32(const gic_ctx *c) { return c->p.precision == GIC_FP32; }
 bool n_ok(const gic_ctx *c, int64_t n) { return c && n >= 0 && n <= c->n_max; }
 
 constexpr int kSumParts = 1024;
+// Largest n of gic_sum_noalloc: 1,024 partial sums of at most 2^20 values each.
+constexpr int64_t kSumNoallocMax = (int64_t)kSumParts << 20;
 
 // The brick schedule of the cell ranges a call is given, built on the stream
 // before its brick kernel; gic_step builds it once after its sort.
@@ -953,6 +957,42 @@ gic_status gic_sum(gic_ctx *c, int64_t n, const double *a, const double *b, doub
 {
     if (!c || n < 0 || !out || (n > 0 && !a)) return GIC_E_ARG;
     return hip_status(launch_sum(a, b, n, c->part, kSumParts, out, accumulate ? 1 : 0, (hipStream_t)stream));
+}
+
+// Partial sums of gic_sum_noalloc: a fixed array per device, so that the
+// call needs neither a context nor an allocation.  Host code uses the
+// per-device address from hipGetSymbolAddress, never the symbol itself.
+static __device__ __align__(256) double scratch[kSumParts];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double *g_scratch_ptr[kMaxDevices];  // address of `scratch` on each device, once looked up
+
+// Address of this device's scratch array (looked up on the first call on the
+// device, with it current), or NULL on failure.
+double *device_scratch()
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
+gic_status gic_sum_noalloc(int64_t n, const double *a, const double *b, double *out, int32_t accumulate,
+                           void *stream)
+{
+    if (n < 0 || !out || (n > 0 && !a)) return GIC_E_ARG;
+    if (n > kSumNoallocMax) return GIC_E_ARG;
+    double *part = device_scratch();
+    if (!part) return GIC_E_HIP;
+    return hip_status(launch_sum(a, b, n, part, kSumParts, out, accumulate ? 1 : 0, (hipStream_t)stream));
 }
 
 gic_status gic_scale(gic_ctx *c, int64_t n, const double *a, const double *s, double factor, double *out,

@@ -92,6 +92,7 @@ def lib():
             "gic_g2p_vjp": (C.c_int, [_V, _I64] + [_V] * 10),
             "gic_p2g_vjp": (C.c_int, [_V, _I64] + [_V] * 8),
             "gic_sum": (C.c_int, [_V, _I64, _V, _V, _V, _I32, _V]),
+            "gic_sum_noalloc": (C.c_int, [_I64, _V, _V, _V, _I32, _V]),
             "gic_permute": (C.c_int, [_V, _I64, _I32, _V, _V, _V, _I32, _V]),
             "gic_scale": (C.c_int, [_V, _I64, _V, _V, C.c_double, _V, _V]),
         }
@@ -518,6 +519,13 @@ def gic_p2g_vjp(ctx, x, v, r, g_alpha, g_mom, g_x, g_v):
 def gic_sum(ctx, a, out, b=None, accumulate=False):
     _check(lib().gic_sum(ctx.handle, a.numel(), _ptr(a, torch.float64), _ptr(b, torch.float64, a.numel()),
                          _ptr(out, torch.float64, 1), int(bool(accumulate)), _stream()), "gic_sum")
+
+
+def gic_sum_noalloc(a, out, b=None, accumulate=False):
+    """gic_sum without a context: its partial sums live in a fixed array
+    that the library holds on each device (no allocation in the call)."""
+    _check(lib().gic_sum_noalloc(a.numel(), _ptr(a, torch.float64), _ptr(b, torch.float64, a.numel()),
+                                 _ptr(out, torch.float64, 1), int(bool(accumulate)), _stream()), "gic_sum_noalloc")
 
 
 def gic_scale(ctx, a, s, factor, out):
