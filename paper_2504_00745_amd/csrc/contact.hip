@@ -575,18 +575,13 @@ __device__ inline int nbr_global(const DevParams &P, int64_t n, const double *__
     return cnt;
 }
 
-__global__ void __launch_bounds__(kNbrThreads) k_nbr_build(DevParams P, int64_t n, const int32_t *__restrict__ bl,
-                                                           const int32_t *__restrict__ bcnt, int cap,
-                                                           const double *__restrict__ x, const double *__restrict__ r,
-                                                           const int32_t *__restrict__ cb,
-                                                           const int32_t *__restrict__ ce, int32_t *__restrict__ nbr,
-                                                           int32_t *__restrict__ ncnt, float *__restrict__ xref,
-                                                           uint32_t *__restrict__ ctl, int force, double skin,
-                                                           int64_t *err)
+// The list of the granules of brick b (one workgroup; LDS from smem4).
+__device__ inline void nbr_build_brick(const DevParams &P, int64_t n, int64_t b, int cap,
+                                       const double *__restrict__ x, const double *__restrict__ r,
+                                       const int32_t *__restrict__ cb, const int32_t *__restrict__ ce,
+                                       int32_t *__restrict__ nbr, int32_t *__restrict__ ncnt,
+                                       float *__restrict__ xref, double skin, int64_t *err, float4 *smem4)
 {
-    if (!force && !ctl[0]) return;  // the list of the last build still holds every pair that can touch
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&ctl[2], 1u);  // builds, for the caller's statistics
-    extern __shared__ float4 smem4[];
     float4 *spos = smem4;                                                 // [cap + kCand] (p, Q)
     float *srad = reinterpret_cast<float *>(spos + cap + kCand);          // [cap] radius + skin / 2
     uint16_t *plist = reinterpret_cast<uint16_t *>(srad + cap);           // [kNbrCap][256] listed slots
@@ -596,8 +591,6 @@ __global__ void __launch_bounds__(kNbrThreads) k_nbr_build(DevParams P, int64_t 
     int32_t *s_wave = cgb + kHaloCells;                                   // [4]
     uint8_t *scell = reinterpret_cast<uint8_t *>(s_wave + 4);             // [cap] shell cell of each slot
     const int tid = threadIdx.x;
-    const int64_t b = brick_of_block(bl, bcnt);
-    if (b < 0) return;
     const int32_t bc[3] = {(int32_t)(b % P.nb[0]), (int32_t)((b / P.nb[0]) % P.nb[1]),
                            (int32_t)(b / ((int64_t)P.nb[0] * P.nb[1]))};
     const int32_t c0[3] = {bc[0] * kBrick - 1, bc[1] * kBrick - 1, bc[2] * kBrick - 1};
@@ -750,6 +743,29 @@ __global__ void __launch_bounds__(kNbrThreads) k_nbr_build(DevParams P, int64_t 
     }
 }
 
+// Builds the list when asked (force, or ctl[0] set by the sort); a small
+// grid loops over the occupied bricks, so the launch costs little when the
+// list is kept.
+__global__ void __launch_bounds__(kNbrThreads) k_nbr_build(DevParams P, int64_t n, const int32_t *__restrict__ bl,
+                                                           const int32_t *__restrict__ bcnt, int cap,
+                                                           const double *__restrict__ x, const double *__restrict__ r,
+                                                           const int32_t *__restrict__ cb,
+                                                           const int32_t *__restrict__ ce, int32_t *__restrict__ nbr,
+                                                           int32_t *__restrict__ ncnt, float *__restrict__ xref,
+                                                           uint32_t *__restrict__ ctl, int force, double skin,
+                                                           int64_t *err)
+{
+    if (!force && !ctl[0]) return;  // the list of the last build still holds every pair that can touch
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&ctl[2], 1u);  // builds, for the caller's statistics
+    extern __shared__ float4 smem4[];
+    for (int64_t it = 0;; ++it) {
+        const int64_t b = brick_at(bl, bcnt, it);
+        if (b < 0) break;
+        nbr_build_brick(P, n, b, cap, x, r, cb, ce, nbr, ncnt, xref, skin, err, smem4);
+        __syncthreads();  // the next brick reuses the LDS
+    }
+}
+
 // Contact forces from the neighbour list: one thread per granule in sorted
 // order (each XCD one contiguous eighth, so partners mostly share its L2);
 // the listed partners' double state is fetched kListBatch at a time so their
@@ -868,7 +884,7 @@ hipError_t launch_nbr_build(const DevParams &P, int64_t n, const double *x, cons
     if (n == 0) return hipSuccess;
     const int64_t nbricks = (int64_t)P.nb[0] * P.nb[1] * P.nb[2];
     const int cap = 1948;  // shell slots in LDS: 51,772 bytes, three workgroups per CU
-    k_nbr_build<<<brick_grid(nbricks), kNbrThreads, nbr_lds_bytes(cap), s>>>(
+    k_nbr_build<<<brick_loop_grid(nbricks), kNbrThreads, nbr_lds_bytes(cap), s>>>(
         P, n, B.list, B.count, cap, x, r, cb, ce, L.nbr, L.cnt, L.xref, L.ctl, force, L.skin, err);
     return hipGetLastError();
 }

@@ -356,10 +356,8 @@ gic_status gic_create(const gic_params *p, int64_t n_max, gic_ctx **out)
     if (ok) ok = hipMemset(c->sort.ctl, 0, sizeof(int32_t) * 4) == hipSuccess;
     ok &= hipMalloc(&c->sort.vA, sizeof(int32_t) * nn) == hipSuccess;
     ok &= hipMalloc(&c->sort.vB, sizeof(int32_t) * nn) == hipSuccess;
-    ok &= hipMalloc(&c->sort.ghist, sizeof(uint32_t) * (4 * 256 + 4)) == hipSuccess;
-    ok &= hipMalloc(&c->sort.flags, sizeof(uint64_t) * 4 * 256 * tiles) == hipSuccess;
-    if (ok) ok = hipMemset(c->sort.flags, 0, sizeof(uint64_t) * 4 * 256 * tiles) == hipSuccess;
-    c->sort.epoch = 0;
+    ok &= hipMalloc(&c->sort.rowtot, sizeof(uint32_t) * 256) == hipSuccess;
+    ok &= hipMalloc(&c->sort.tcnt, sizeof(uint32_t) * 256 * tiles) == hipSuccess;
     ok &= hipMalloc(&c->sort.sums, sizeof(uint32_t) * 1024) == hipSuccess;
     ok &= hipMalloc(&c->sort.cnt, sizeof(uint32_t) * (c->K > 0 ? c->K : 1)) == hipSuccess;
     if (ok) ok = hipMemset(c->sort.cnt, 0, sizeof(uint32_t) * (c->K > 0 ? c->K : 1)) == hipSuccess;
@@ -416,8 +414,8 @@ gic_status gic_destroy(gic_ctx *c)
     (void)hipFree(c->sort.ctl);
     (void)hipFree(c->sort.vA);
     (void)hipFree(c->sort.vB);
-    (void)hipFree(c->sort.ghist);
-    (void)hipFree(c->sort.flags);
+    (void)hipFree(c->sort.rowtot);
+    (void)hipFree(c->sort.tcnt);
     (void)hipFree(c->sort.sums);
     (void)hipFree(c->sort.cnt);
     (void)hipFree(c->err);

@@ -61,6 +61,26 @@ __device__ inline int64_t brick_of_block(const int32_t *__restrict__ list, const
     return j < per && l < nocc ? list[l] : -1;
 }
 
+// Brick kernels that loop: workgroup b takes the entries j = b / kXcds +
+// it * (gridDim.x / kXcds), it = 0, 1, ..., of its XCD's eighth of the list
+// (the same split as brick_of_block); -1 when it has no more.  The grid is
+// brick_loop_grid(nbricks) workgroups (a multiple of kXcds).
+constexpr int64_t kBrickLoopGrid = 2048;
+inline unsigned brick_loop_grid(int64_t nbricks)
+{
+    const unsigned g = xcd_grid(nbricks);
+    return g < (unsigned)kBrickLoopGrid ? g : (unsigned)kBrickLoopGrid;
+}
+
+__device__ inline int64_t brick_at(const int32_t *__restrict__ list, const int32_t *__restrict__ count, int64_t it)
+{
+    const int64_t nocc = *count;
+    const int64_t per = (nocc + kXcds - 1) / kXcds;
+    const int64_t j = (int64_t)blockIdx.x / kXcds + it * ((int64_t)gridDim.x / kXcds);
+    const int64_t l = ((int64_t)blockIdx.x % kXcds) * per + j;
+    return j < per && l < nocc ? list[l] : -1;
+}
+
 // A range [b, e) of sorted positions read from caller-given cell ranges,
 // clipped to [0, n]: ranges that do not match the positions give wrong
 // results (and, where detected, a latched error) but never an access

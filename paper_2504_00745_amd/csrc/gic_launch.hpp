@@ -29,9 +29,8 @@ struct SortScratch {
                          // no key changed (1: order, ranges and bricks of the last sort hold), spare
     int64_t tiles_max;
     int passes;          // 8-bit digit passes over the key bits
-    uint32_t *ghist;     // [4 x 256 + 4] digit counts of every pass, then the 4 passes' tile counters
-    uint64_t *flags;     // [4][tiles_max][256] look-back words of the digit passes
-    uint32_t epoch;      // sort number, tags the look-back words of this sort
+    uint32_t *tcnt;      // [256][tiles_max] digit counts, then output offsets, of each tile in a digit pass
+    uint32_t *rowtot;    // [256] keys with each digit in a digit pass
 };
 
 // Occupied bricks of a set of cell ranges, in brick order (see

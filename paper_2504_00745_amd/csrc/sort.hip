@@ -12,6 +12,7 @@ namespace gic {
 namespace {
 
 constexpr int kRadix = 256;
+constexpr int64_t kRtsGrid = 1024;  // workgroups of the tile loops of the digit passes
 
 // Key of every granule; flags non-finite and out-of-box positions.  With
 // the previous sorted keys pk (same n), granules whose key differs from
@@ -24,11 +25,8 @@ __global__ void __launch_bounds__(256) k_cell_keys(DevParams P, int64_t n, const
                                                    uint32_t *__restrict__ key, int64_t *err,
                                                    const uint32_t *__restrict__ pk, uint64_t *__restrict__ chg,
                                                    int32_t *__restrict__ ctl, const float *__restrict__ xref,
-                                                   float *__restrict__ dpart, uint32_t *__restrict__ ghist)
+                                                   float *__restrict__ dpart)
 {
-    // the digit counts and tile counters of this sort's digit passes start at zero
-    if (blockIdx.x == 0)
-        for (int k = threadIdx.x; k < 4 * kRadix + 4; k += blockDim.x) ghist[k] = 0u;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (xref) {
         float d2 = 0.0f;
@@ -138,48 +136,16 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_spine(uint32_t *sums, int
     if (threadIdx.x < nb) sums[threadIdx.x] = inc - v;
 }
 
-// ---- single-pass digit passes (decoupled look-back) ----------------------
+// ---- digit passes (reduce, scan, scatter) --------------------------------
 //
-// The counts of every digit of every pass are taken in one read of the keys
-// (k_radix_hist_all).  Each digit pass is then one kernel: a workgroup takes
-// the next tile in launch order (a counter), counts its tile's digits,
-// publishes them, and finds the keys of earlier tiles with each digit by
-// walking back over the tiles' published words until one that carries the
-// inclusive count of all tiles before it (decoupled look-back); it publishes
-// its own inclusive count and scatters its keys stably.  A tile only waits
-// for tiles that took a smaller number, i.e. workgroups that are already
-// running, and every wait is bounded: after kSpinLimit polls the kernel
-// latches an error and goes on, so no launch can hang.
-//
-// A published word is [epoch: 30 | state: 2 | count: 32], state 1 = this
-// tile's own count, 2 = count of this tile and all before it; the epoch of
-// the sort tells words of this sort from those left by earlier ones, so the
-// words need no clearing.
-constexpr uint32_t kSpinLimit = 1u << 22;
-constexpr int kErrSort = 6;  // latched as GIC_E_RANGE with index -2
-
-__device__ inline uint64_t lb_word(uint32_t epoch, uint32_t state, uint32_t count)
-{
-    return ((uint64_t)(epoch & 0x3fffffffu) << 34) | ((uint64_t)state << 32) | (uint64_t)count;
-}
-
-__global__ void __launch_bounds__(kSortThreads) k_radix_hist_all(const uint32_t *__restrict__ keys, int64_t n,
-                                                                 int passes, uint32_t *__restrict__ ghist,
-                                                                 const int32_t *__restrict__ skip)
-{
-    if (skip && skip[1]) return;  // the incremental path sorted this time
-    __shared__ uint32_t h[4][kRadix];
-    const int tid = threadIdx.x;
-    for (int p = 0; p < 4; ++p) h[p][tid] = 0;
-    __syncthreads();
-    for (int64_t i = (int64_t)blockIdx.x * kSortThreads + tid; i < n; i += (int64_t)gridDim.x * kSortThreads) {
-        const uint32_t k = keys[i];
-        for (int p = 0; p < passes; ++p) atomicAdd(&h[p][(k >> (8 * p)) & (kRadix - 1)], 1u);
-    }
-    __syncthreads();
-    for (int p = 0; p < passes; ++p)
-        if (h[p][tid]) atomicAdd(&ghist[p * kRadix + tid], h[p][tid]);
-}
+// Each 8-bit digit pass is three kernels with no waits between workgroups:
+// every tile of kSortTile keys counts its digits (k_rts_count, into
+// tcnt[digit][tile]); one workgroup per digit turns its row into the
+// exclusive prefix over the tiles and records the row's total (k_rts_scan);
+// every tile then scatters its keys stably (k_rts_scatter) from the prefix
+// of its tile plus the keys of all smaller digits (a scan of the 256 row
+// totals).  The tile loops stride over the grid, so a launch needs no more
+// workgroups than it has tiles.
 
 // Rank of each lane's digit among the lanes of its wave with the same digit
 // (8 ballots), and the number of such lanes.
@@ -195,121 +161,129 @@ __device__ inline uint64_t digit_mask(uint32_t d, bool valid)
     return m;
 }
 
-__global__ void __launch_bounds__(kSortThreads) k_onesweep(const uint32_t *__restrict__ kin,
-                                                           const int32_t *__restrict__ vin,
-                                                           uint32_t *__restrict__ kout, int32_t *__restrict__ vout,
-                                                           int64_t n, int pass, const uint32_t *__restrict__ ghist,
-                                                           uint32_t *__restrict__ tctr, uint64_t *__restrict__ flags,
-                                                           int64_t tiles, uint32_t epoch,
-                                                           const int32_t *__restrict__ skip, int64_t *err)
+// Mask of the lanes below this one in its wave.
+__device__ inline uint64_t lanes_below()
+{
+    const int lane = threadIdx.x & 63;
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Digit counts of every tile: tcnt[d * tiles + t].
+__global__ void __launch_bounds__(kSortThreads) k_rts_count(const uint32_t *__restrict__ kin, int64_t n, int pass,
+                                                            int64_t tiles, uint32_t *__restrict__ tcnt,
+                                                            const int32_t *__restrict__ skip)
+{
+    if (skip && skip[1]) return;  // the incremental path sorted this time
+    __shared__ uint32_t s_cnt[kRadix];
+    const int tid = threadIdx.x;
+    const int shift = 8 * pass;
+    const uint64_t lt = lanes_below();
+    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        s_cnt[tid] = 0;
+        __syncthreads();
+        const int64_t tile0 = t * kSortTile;
+#pragma unroll
+        for (int it = 0; it < kSortItems; ++it) {
+            const int64_t p = tile0 + (int64_t)it * kSortThreads + tid;
+            const bool valid = p < n;
+            const uint32_t d = valid ? (kin[p] >> shift) & (kRadix - 1) : 0u;
+            const uint64_t m = digit_mask(d, valid);
+            if (valid && (m & lt) == 0) atomicAdd(&s_cnt[d], (uint32_t)__popcll(m));
+        }
+        __syncthreads();
+        tcnt[(int64_t)tid * tiles + t] = s_cnt[tid];
+        __syncthreads();
+    }
+}
+
+// Workgroup d: tcnt[d][t] <- keys with digit d in tiles before t;
+// rowtot[d] <- keys with digit d.  Thread i takes a contiguous chunk of the
+// row, so the row is read in one sweep and scanned once.
+__global__ void __launch_bounds__(kSortThreads) k_rts_scan(uint32_t *__restrict__ tcnt, int64_t tiles,
+                                                           uint32_t *__restrict__ rowtot,
+                                                           const int32_t *__restrict__ skip)
 {
     if (skip && skip[1]) return;
-    __shared__ uint32_t s_base[kRadix];               // where this tile's keys of each digit start
-    __shared__ uint32_t s_cnt[kRadix];                // this tile's count of each digit
+    __shared__ uint32_t lds[kSortThreads / 64];
+    const int d = blockIdx.x;
+    uint32_t *row = tcnt + (int64_t)d * tiles;
+    const int64_t chunk = (tiles + kSortThreads - 1) / kSortThreads;
+    const int64_t lo = (int64_t)threadIdx.x * chunk;
+    const int64_t hi = lo + chunk < tiles ? lo + chunk : tiles;
+    uint32_t sum = 0;
+    for (int64_t t = lo; t < hi; ++t) sum += row[t];
+    uint32_t total;
+    uint32_t run = block_scan_inclusive(sum, lds, &total) - sum;
+    for (int64_t t = lo; t < hi; ++t) {
+        const uint32_t c = row[t];
+        row[t] = run;
+        run += c;
+    }
+    if (threadIdx.x == 0) rowtot[d] = total;
+}
+
+// Stable scatter of every tile's keys (and values: vin, or the positions)
+// from the offsets of k_rts_scan, in rounds of 256 keys in position order.
+__global__ void __launch_bounds__(kSortThreads) k_rts_scatter(const uint32_t *__restrict__ kin,
+                                                              const int32_t *__restrict__ vin,
+                                                              uint32_t *__restrict__ kout, int32_t *__restrict__ vout,
+                                                              int64_t n, int pass, int64_t tiles,
+                                                              const uint32_t *__restrict__ tcnt,
+                                                              const uint32_t *__restrict__ rowtot,
+                                                              const int32_t *__restrict__ skip)
+{
+    if (skip && skip[1]) return;
+    __shared__ uint32_t s_base[kRadix];  // where this tile's next key of each digit goes
     __shared__ uint32_t wcnt[kSortThreads / 64][kRadix];
-    __shared__ uint32_t s_scan[kSortThreads / 64];
-    __shared__ int64_t s_tile;
+    __shared__ uint32_t lds[kSortThreads / 64];
     const int tid = threadIdx.x;
-    const int lane = tid & 63;
     const int wave = tid >> 6;
     const int shift = 8 * pass;
-    if (tid == 0) s_tile = (int64_t)atomicAdd(&tctr[pass], 1u);
-    s_cnt[tid] = 0;
+    const uint64_t lt = lanes_below();
     for (int w = 0; w < kSortThreads / 64; ++w) wcnt[w][tid] = 0;
-    // exclusive prefix of the digit counts over all keys
-    const uint32_t g = ghist[pass * kRadix + tid];
-    uint32_t incl = g;
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t t = __shfl_up(incl, off);
-        if (lane >= off) incl += t;
-    }
-    if (lane == 63) s_scan[wave] = incl;
-    __syncthreads();
-    uint32_t gexcl = incl - g;
-    for (int w = 0; w < wave; ++w) gexcl += s_scan[w];
-    const int64_t t = s_tile;
-    if (t >= tiles) return;  // more workgroups than tiles: never launched so
-    // the tile's keys, in registers
-    uint32_t k[kSortItems];
-    int32_t val[kSortItems];
-    const int64_t tile0 = t * kSortTile;
+    // keys of all smaller digits
+    const uint32_t g = rowtot[tid];
+    uint32_t total;
+    const uint32_t dbase = block_scan_inclusive(g, lds, &total) - g;
+    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        const int64_t tile0 = t * kSortTile;
+        uint32_t k[kSortItems];
+        int32_t val[kSortItems];
 #pragma unroll
-    for (int it = 0; it < kSortItems; ++it) {
-        const int64_t p = tile0 + (int64_t)it * kSortThreads + tid;
-        const bool valid = p < n;
-        k[it] = valid ? kin[p] : 0xffffffffu;
-        val[it] = valid ? (vin ? vin[p] : (int32_t)p) : 0;
-    }
-    // this tile's digit counts
+        for (int it = 0; it < kSortItems; ++it) {
+            const int64_t p = tile0 + (int64_t)it * kSortThreads + tid;
+            const bool valid = p < n;
+            k[it] = valid ? kin[p] : 0xffffffffu;
+            val[it] = valid ? (vin ? vin[p] : (int32_t)p) : 0;
+        }
+        s_base[tid] = dbase + tcnt[(int64_t)tid * tiles + t];
+        __syncthreads();
 #pragma unroll
-    for (int it = 0; it < kSortItems; ++it) {
-        const int64_t p = tile0 + (int64_t)it * kSortThreads + tid;
-        const bool valid = p < n;
-        const uint32_t d = (k[it] >> shift) & (kRadix - 1);
-        const uint64_t m = digit_mask(d, valid);
-        const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-        if (valid && (m & lt) == 0) atomicAdd(&s_cnt[d], (uint32_t)__popcll(m));
-    }
-    __syncthreads();
-    // publish, look back, publish the inclusive count
-    {
-        const uint32_t agg = s_cnt[tid];
-        uint64_t *fl = flags + (size_t)t * kRadix + tid;
-        uint32_t before = 0;
-        if (t == 0) {
-            __hip_atomic_store(fl, lb_word(epoch, 2u, agg), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            __hip_atomic_store(fl, lb_word(epoch, 1u, agg), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            int64_t j = t - 1;
-            uint32_t spins = 0;
-            while (j >= 0) {
-                const uint64_t w =
-                    __hip_atomic_load(flags + (size_t)j * kRadix + tid, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                const uint32_t st = (uint32_t)(w >> 32) & 3u;
-                if ((uint32_t)(w >> 34) != (epoch & 0x3fffffffu) || st == 0u) {
-                    if (++spins > kSpinLimit) {  // never expected: give up rather than hang
-                        raise_error(err, kErrSort, -2);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
+        for (int it = 0; it < kSortItems; ++it) {
+            const int64_t p = tile0 + (int64_t)it * kSortThreads + tid;
+            const bool valid = p < n;
+            const uint32_t d = (k[it] >> shift) & (kRadix - 1);
+            const uint64_t m = digit_mask(d, valid);
+            const uint32_t rank = (uint32_t)__popcll(m & lt);
+            if (valid && rank == 0) wcnt[wave][d] = (uint32_t)__popcll(m);
+            __syncthreads();
+            if (valid) {
+                uint32_t pos = s_base[d] + rank;
+                for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
+                if ((int64_t)pos < n) {
+                    kout[pos] = k[it];
+                    vout[pos] = val[it];
                 }
-                before += (uint32_t)w;
-                if (st == 2u) break;
-                --j;
             }
-            __hip_atomic_store(fl, lb_word(epoch, 2u, before + agg), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        s_base[tid] = gexcl + before;
-    }
-    __syncthreads();
-    // stable scatter, in rounds of 256 keys in position order
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-#pragma unroll
-    for (int it = 0; it < kSortItems; ++it) {
-        const int64_t p = tile0 + (int64_t)it * kSortThreads + tid;
-        const bool valid = p < n;
-        const uint32_t d = (k[it] >> shift) & (kRadix - 1);
-        const uint64_t m = digit_mask(d, valid);
-        const uint32_t rank = (uint32_t)__popcll(m & lt_mask);
-        if (valid && rank == 0) wcnt[wave][d] = (uint32_t)__popcll(m);
-        __syncthreads();
-        if (valid) {
-            uint32_t pos = s_base[d] + rank;
-            for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
-            if ((int64_t)pos < n) {
-                kout[pos] = k[it];
-                vout[pos] = val[it];
+            __syncthreads();
+            uint32_t add = 0;
+            for (int w = 0; w < kSortThreads / 64; ++w) {
+                add += wcnt[w][tid];
+                wcnt[w][tid] = 0;
             }
+            s_base[tid] += add;
+            __syncthreads();
         }
-        __syncthreads();
-        uint32_t add = 0;
-        for (int w = 0; w < kSortThreads / 64; ++w) {
-            add += wcnt[w][tid];
-            wcnt[w][tid] = 0;
-        }
-        s_base[tid] += add;
-        __syncthreads();
     }
 }
 
@@ -590,8 +564,7 @@ hipError_t launch_sort_cells(const DevParams &P, int64_t n, const double *x, uin
     const bool measure = nl && inc && !force && nl->thr2 > 0.0f;
     if (n > 0) {
         k_cell_keys<<<grid_for(n, 256), 256, 0, s>>>(P, n, x, key, err, pk, S.chg, S.ctl,
-                                                     measure ? nl->xref : nullptr, measure ? nl->dpart : nullptr,
-                                                     S.ghist);
+                                                     measure ? nl->xref : nullptr, measure ? nl->dpart : nullptr);
         if (inc) {
             k_chg_sort<<<1, 1024, 0, s>>>(n, pk, S.chg, S.ctl, S.chg_s, S.chg_p, skeys, order,
                                           nl ? nl->ctl : nullptr, measure ? 0 : 1, nl ? nl->thr2 : 0.0f,
@@ -600,24 +573,17 @@ hipError_t launch_sort_cells(const DevParams &P, int64_t n, const double *x, uin
         }
         // digit passes (skipped on the device when the incremental path sorted)
         const int64_t tiles = (n + kSortTile - 1) / kSortTile;
-        if ((++S.epoch & 0x3fffffffu) == 0u) {
-            // the 30-bit sort number wrapped: clear the words it tags
-            if (launch_fill_i64(reinterpret_cast<int64_t *>(S.flags), 4 * S.tiles_max * kRadix, s) != hipSuccess)
-                return hipGetLastError();
-            ++S.epoch;
-        }
-        unsigned hb = (unsigned)(tiles < 1024 ? tiles : 1024);
-        k_radix_hist_all<<<hb, kSortThreads, 0, s>>>(key, n, S.passes, S.ghist, skip);
+        const unsigned tg = (unsigned)(tiles < kRtsGrid ? tiles : kRtsGrid);
         const uint32_t *kin = key;
         const int32_t *vin = nullptr;
         for (int pass = 0; pass < S.passes; ++pass) {
             const bool last = pass == S.passes - 1;
             uint32_t *kout = last ? skeys : ((pass & 1) ? S.kB : S.kA);
             int32_t *vout = last ? order : ((pass & 1) ? S.vB : S.vA);
-            k_onesweep<<<(unsigned)tiles, kSortThreads, 0, s>>>(kin, vin, kout, vout, n, pass, S.ghist,
-                                                                 S.ghist + 4 * kRadix,
-                                                                 S.flags + (size_t)pass * S.tiles_max * kRadix,
-                                                                 tiles, S.epoch, skip, err);
+            k_rts_count<<<tg, kSortThreads, 0, s>>>(kin, n, pass, tiles, S.tcnt, skip);
+            k_rts_scan<<<kRadix, kSortThreads, 0, s>>>(S.tcnt, tiles, S.rowtot, skip);
+            k_rts_scatter<<<tg, kSortThreads, 0, s>>>(kin, vin, kout, vout, n, pass, tiles, S.tcnt, S.rowtot,
+                                                      skip);
             kin = kout;
             vin = vout;
         }
