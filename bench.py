@@ -244,34 +244,42 @@ WORKLOAD_TEXT = {
 
 def time_adjoint(reps=3):
     """Forward and backward of the differentiable rollout on the c4 workload
-    (65,536 bidisperse granules, 20 steps, checkpoint every 5), FP64."""
+    (65,536 bidisperse granules, 20 steps, checkpoint every 5), FP64: each
+    pass replayed as a recorded HIP graph (recorded in the untimed first
+    repetition), and run directly for comparison."""
     import torch
     from paper_2504_00745_amd import workloads as wl
     from paper_2504_00745_amd.rollout import GICRollout, Rollout
     d = wl.make("c4")
     cfg = d["params"]
-    sim = Rollout(cfg, d["r"], d["u"], 20, ckpt=5, r_max=float(d["r"].max()))
     x0 = torch.as_tensor(d["x"]).cuda()
     v0d = torch.as_tensor(d["v"]).cuda()
-    fw, bw = [], []
-    for it in range(reps + 1):
-        v0 = v0d.clone().requires_grad_(True)
-        mu = torch.tensor(cfg["mu"], dtype=torch.float64, requires_grad=True)
-        cd = torch.tensor(cfg["c_drag"], dtype=torch.float64, requires_grad=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        L = GICRollout.apply(x0, v0, mu, cd, sim)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        L.backward()
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        if it:
-            fw.append(t1 - t0)
-            bw.append(t2 - t1)
-    f, b = float(np.median(fw)), float(np.median(bw))
+
+    def timed(sim):
+        fw, bw = [], []
+        for it in range(reps + 1):
+            v0 = v0d.clone().requires_grad_(True)
+            mu = torch.tensor(cfg["mu"], dtype=torch.float64, requires_grad=True)
+            cd = torch.tensor(cfg["c_drag"], dtype=torch.float64, requires_grad=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            L = GICRollout.apply(x0, v0, mu, cd, sim)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            L.backward()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            if it:
+                fw.append(t1 - t0)
+                bw.append(t2 - t1)
+        return float(np.median(fw)) * 1e3, float(np.median(bw)) * 1e3
+
+    rm = float(d["r"].max())
+    f, b = timed(Rollout(cfg, d["r"], d["u"], 20, ckpt=5, r_max=rm, graph=True))
+    fd, bd = timed(Rollout(cfg, d["r"], d["u"], 20, ckpt=5, r_max=rm))
     return {"workload": "c4: 65,536 bidisperse granules, 64^3 grid, 20 steps, checkpoint every 5, FP64",
-            "forward_ms": f * 1e3, "backward_ms": b * 1e3, "ratio": b / f, "reps": reps}
+            "forward_ms": f, "backward_ms": b, "ratio": b / f, "reps": reps, "graph": True,
+            "direct": {"forward_ms": fd, "backward_ms": bd, "ratio": bd / fd}}
 
 
 COPY_BYTES = 1 << 30

@@ -767,9 +767,15 @@ __global__ void __launch_bounds__(kNbrThreads) k_nbr_build(DevParams P, int64_t 
 }
 
 // Contact forces from the neighbour list: one thread per granule in sorted
-// order (each XCD one contiguous eighth, so partners mostly share its L2);
-// the listed partners' double state is fetched kListBatch at a time so their
-// loads overlap, and each runs the exact test of Sec. 3.1 and, if touching,
+// order (each XCD one contiguous eighth, so partners mostly share its L2).
+// The workgroup first copies the double state of its own 256 granules into
+// LDS with coalesced loads; a listed partner among them (the granules of the
+// same few cells) is read from there, any other from global memory, two
+// partners' state fetched together so their loads overlap.  (Listed partners
+// of neighbouring lanes lie in different directions, so global partner reads
+// touch about one cache line per lane; a wider window of sorted positions in
+// LDS served more partners but lowered the waves per SIMD, which cost more.)
+// Each listed partner runs the exact test of Sec. 3.1 and, if touching,
 // Eq. (1); walls last.  A granule whose partners did not fit in its list
 // searches its cells in the same order.
 constexpr int kListBatch = 2;
@@ -784,13 +790,44 @@ __global__ void __launch_bounds__(256) k_contact_list(DevParams P, int64_t n, in
                                                       int32_t *__restrict__ ncont, int32_t *__restrict__ pairs,
                                                       int pair_cap, int64_t *err)
 {
+    __shared__ double sw[7][256];  // x0, x1, x2, v0, v1, v2, r of the workgroup's granules
     const int64_t lb = xcd_block(nblk);
     if (lb < 0) return;
-    const int64_t q = lb * 256 + threadIdx.x;
+    const int64_t wbeg = lb * 256;
+    const int32_t wlen = (int32_t)(n - wbeg < 256 ? n - wbeg : 256);
+    for (int32_t i = threadIdx.x; i < wlen; i += 256) {
+        const int64_t g = wbeg + i;
+        sw[0][i] = x[g];
+        sw[1][i] = x[n + g];
+        sw[2][i] = x[2 * n + g];
+        sw[3][i] = v[g];
+        sw[4][i] = v[n + g];
+        sw[5][i] = v[2 * n + g];
+        sw[6][i] = r[g];
+    }
+    __syncthreads();
+    // a partner's state from LDS, or from global memory
+    auto partner = [&](int32_t j) {
+        const uint32_t w = (uint32_t)((int64_t)j - wbeg);
+        if (w < (uint32_t)wlen) {
+            Partner p;
+            p.x[0] = sw[0][w];
+            p.x[1] = sw[1][w];
+            p.x[2] = sw[2][w];
+            p.v[0] = sw[3][w];
+            p.v[1] = sw[4][w];
+            p.v[2] = sw[5][w];
+            p.r = sw[6][w];
+            return p;
+        }
+        return fetch_partner(n, x, v, r, j);
+    };
+    const int64_t q = wbeg + threadIdx.x;
     if (q >= n) return;
-    const double xi[3] = {x[q], x[n + q], x[2 * n + q]};
-    const double vi[3] = {v[q], v[n + q], v[2 * n + q]};
-    const double ri = r[q];
+    const int32_t qw = (int32_t)(q - wbeg);
+    const double xi[3] = {sw[0][qw], sw[1][qw], sw[2][qw]};
+    const double vi[3] = {sw[3][qw], sw[4][qw], sw[5][qw]};
+    const double ri = sw[6][qw];
     const int32_t cnt = ncnt[q];
     if (ri > P.r_max) raise_error(err, kErrRange, q);
     const double mi = mass_of(P, ri);
@@ -813,7 +850,7 @@ __global__ void __launch_bounds__(256) k_contact_list(DevParams P, int64_t n, in
                 j[u] = (uint32_t)jj < (uint32_t)n ? jj : -1;  // a list entry outside [0, n) is skipped
             }
 #pragma unroll
-            for (int u = 0; u < kListBatch; ++u) p[u] = fetch_partner(n, x, v, r, j[u] >= 0 ? j[u] : (int32_t)q);
+            for (int u = 0; u < kListBatch; ++u) p[u] = partner(j[u] >= 0 ? j[u] : (int32_t)q);
 #pragma unroll
             for (int u = 0; u < kListBatch; ++u)
                 if (j[u] >= 0) take(j[u], p[u]);
@@ -823,7 +860,7 @@ __global__ void __launch_bounds__(256) k_contact_list(DevParams P, int64_t n, in
         int32_t lo[3], hi[3];
         for (int a = 0; a < 3; ++a) search_range(P, xi[a], Rs, P.nc[a], lo[a], hi[a]);
         for_each_run(P, n, lo, hi, cb, ce, [&](int32_t jb, int32_t je) {
-            for (int32_t jj = jb; jj < je; ++jj) take(jj, fetch_partner(n, x, v, r, jj));
+            for (int32_t jj = jb; jj < je; ++jj) take(jj, partner(jj));
         });
     }
     add_walls<T>(P, xi, vi, ri, mi, acc, nc);

@@ -23,7 +23,7 @@ struct gic_ctx {
     bool in_step;      // inside gic_step, which builds the brick list once
     int device;
     int64_t *fxs;      // device: 4 G int64, integer sums of the unquantised transfers
-    double *fxp;       // device: 4 x 1024 partial maxima (their scales)
+    double *fxp;       // device: 4 x 1024 partial maxima, then the 4 scales and their inverses
     NbrList nl;        // device: neighbour list of the stepping path
     // The list holds the stepping path's state when nl_n == n and the state
     // to step is the array that the last step wrote (nl_x): its sorted
@@ -368,7 +368,7 @@ gic_status gic_create(const gic_params *p, int64_t n_max, gic_ctx **out)
     ok &= hipMalloc(&c->bricks.count, sizeof(int32_t)) == hipSuccess;
     ok &= hipMalloc(&c->bricks.sums, sizeof(uint32_t) * 1024) == hipSuccess;
     ok &= hipMalloc(&c->fxs, sizeof(int64_t) * 4 * (size_t)(c->dp.G > 0 ? c->dp.G : 1)) == hipSuccess;
-    ok &= hipMalloc(&c->fxp, sizeof(double) * 4 * 1024) == hipSuccess;
+    ok &= hipMalloc(&c->fxp, sizeof(double) * (4 * 1024 + 8)) == hipSuccess;
     ok &= hipMalloc(&c->nl.nbr, sizeof(int32_t) * kNbrCap * nn) == hipSuccess;
     ok &= hipMalloc(&c->nl.cnt, sizeof(int32_t) * nn) == hipSuccess;
     ok &= hipMalloc(&c->nl.xref, sizeof(float) * 3 * nn) == hipSuccess;

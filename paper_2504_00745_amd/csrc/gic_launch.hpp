@@ -141,7 +141,7 @@ hipError_t launch_gather_g2p_drag(const DevParams &P, int64_t n, int64_t K, cons
                                   const int32_t *ce, const BrickList &B, T *Fd, T *uat, T *af, hipStream_t s);
 // Unquantised P2G (alpha G, momentum 3G doubles; = or += with acc),
 // summed deterministically as integers at a scale set by the largest
-// contribution; fx: 4 G int64 and part: 4 x 1024 doubles of scratch.
+// contribution; fx: 4 G int64 and part: 4 x 1024 + 8 doubles of scratch.
 hipError_t launch_p2g_real(const DevParams &P, int64_t n, int64_t K, const double *x, const double *v,
                            const double *r, const int32_t *cb, const int32_t *ce, const BrickList &B,
                            double *alpha, double *mom, int acc, int64_t *fx, double *part, hipStream_t s);

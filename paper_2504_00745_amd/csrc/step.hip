@@ -11,6 +11,51 @@ namespace gic {
 
 namespace {
 
+// Node tile entry of the drag gather: u and the clamped solid fraction of a
+// node, read with one LDS access.
+template <typename T>
+struct Node4;
+template <>
+struct Node4<float> {
+    using type = float4;
+};
+template <>
+struct Node4<double> {
+    using type = double4;
+};
+
+// g2p_sample_st for a stencil that lies inside the tile: the same weights,
+// products and summation order, the node read from the tile at
+// lz[cz] + ly[cy] + lx[cx].
+template <typename T, typename V4>
+__device__ inline void g2p_sample_tile(const Stencil &s, const V4 *__restrict__ tile, const int lx[3],
+                                       const int ly[3], const int lz[3], T uat[3], T &af)
+{
+    T acc[3] = {(T)0, (T)0, (T)0};
+    T as = (T)0;
+#pragma unroll
+    for (int cz = 0; cz < 3; ++cz) {
+        const double wz = s.w[2][cz];
+#pragma unroll
+        for (int cy = 0; cy < 3; ++cy) {
+            const double wyz = s.w[1][cy] * wz;
+#pragma unroll
+            for (int cx = 0; cx < 3; ++cx) {
+                const T w = (T)(s.w[0][cx] * wyz);
+                const V4 q = tile[lz[cz] + ly[cy] + lx[cx]];
+                acc[0] += w * q.x;
+                acc[1] += w * q.y;
+                acc[2] += w * q.z;
+                as += w * q.w;
+            }
+        }
+    }
+    uat[0] = acc[0];
+    uat[1] = acc[1];
+    uat[2] = acc[2];
+    af = (T)1 - as;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_gather_g2p_drag(DevParams P, int64_t n, const int32_t *__restrict__ bl,
                                                          const int32_t *__restrict__ bcnt,
@@ -23,6 +68,7 @@ __global__ void __launch_bounds__(256) k_gather_g2p_drag(DevParams P, int64_t n,
                                                          const int32_t *__restrict__ cb, const int32_t *__restrict__ ce,
                                                          T *__restrict__ Fd, T *__restrict__ uat, T *__restrict__ af)
 {
+    using V4 = typename Node4<T>::type;
     extern __shared__ double smem_d[];
     const int64_t b = brick_of_block(bl, bcnt);
     if (b < 0) return;
@@ -30,7 +76,7 @@ __global__ void __launch_bounds__(256) k_gather_g2p_drag(DevParams P, int64_t n,
     clip_range(n, gb, ge);
     if (ge <= gb) return;
     const int E = P.tile, E3 = E * E * E;
-    T *su = reinterpret_cast<T *>(smem_d);  // [4][E3]: u_x, u_y, u_z, clamped alpha
+    V4 *su = reinterpret_cast<V4 *>(smem_d);  // [E3]: u_x, u_y, u_z, clamped alpha
     int32_t o[3];
     tile_origin(P, b, o);
     const int64_t G = P.G;
@@ -38,10 +84,12 @@ __global__ void __launch_bounds__(256) k_gather_g2p_drag(DevParams P, int64_t n,
         const int32_t i = o[0] + k % E, j = o[1] + (k / E) % E, l = o[2] + k / (E * E);
         if (i < 0 || j < 0 || l < 0 || i >= P.n[0] || j >= P.n[1] || l >= P.n[2]) continue;  // never referenced
         const int64_t idx = node_index(P, i, j, l);
-        su[k] = u[idx];
-        su[E3 + k] = u[G + idx];
-        su[2 * E3 + k] = u[2 * G + idx];
-        su[3 * E3 + k] = (T)node_alpha(P, afx[idx]);
+        V4 q;
+        q.x = u[idx];
+        q.y = u[G + idx];
+        q.z = u[2 * G + idx];
+        q.w = (T)node_alpha(P, afx[idx]);
+        su[k] = q;
     }
     __syncthreads();
     for (int64_t q = gb + threadIdx.x; q < ge; q += 256) {
@@ -56,23 +104,41 @@ __global__ void __launch_bounds__(256) k_gather_g2p_drag(DevParams P, int64_t n,
         }
         ro[q] = rq;
         if (ido) ido[q] = id[s];
+        Stencil st;
+        stencil_of(P, xa, st);
+        // tile offsets of the stencil's nodes; every node inside the tile is
+        // the rule (a granule outside its brick's tile only if its cell is
+        // clamped)
+        int lx[3], ly[3], lz[3];
+        bool inside = true;
+        for (int k = 0; k < 3; ++k) {
+            const int ax = st.node[0][k] - o[0], ay = st.node[1][k] - o[1], az = st.node[2][k] - o[2];
+            inside &= ax >= 0 && ay >= 0 && az >= 0 && ax < E && ay < E && az < E;
+            lx[k] = ax;
+            ly[k] = ay * E;
+            lz[k] = az * E * E;
+        }
         T ua[3], a;
-        g2p_sample<T>(P, xa, [&](int32_t i, int32_t j, int32_t k, T uu[3], T &al) {
-            const int32_t li = i - o[0], lj = j - o[1], lk = k - o[2];
-            if (li >= 0 && lj >= 0 && lk >= 0 && li < E && lj < E && lk < E) {
-                const int t = (lk * E + lj) * E + li;
-                uu[0] = su[t];
-                uu[1] = su[E3 + t];
-                uu[2] = su[2 * E3 + t];
-                al = su[3 * E3 + t];
-            } else {  // a granule outside its brick's tile (only if its cell is clamped)
-                const int64_t idx = node_index(P, i, j, k);
-                uu[0] = u[idx];
-                uu[1] = u[G + idx];
-                uu[2] = u[2 * G + idx];
-                al = (T)node_alpha(P, afx[idx]);
-            }
-        }, ua, a);
+        if (inside) {
+            g2p_sample_tile<T>(st, su, lx, ly, lz, ua, a);
+        } else {
+            g2p_sample_st<T>(st, [&](int32_t i, int32_t j, int32_t k, T uu[3], T &al) {
+                const int32_t li = i - o[0], lj = j - o[1], lk = k - o[2];
+                if (li >= 0 && lj >= 0 && lk >= 0 && li < E && lj < E && lk < E) {
+                    const V4 t = su[(lk * E + lj) * E + li];
+                    uu[0] = t.x;
+                    uu[1] = t.y;
+                    uu[2] = t.z;
+                    al = t.w;
+                } else {
+                    const int64_t idx = node_index(P, i, j, k);
+                    uu[0] = u[idx];
+                    uu[1] = u[G + idx];
+                    uu[2] = u[2 * G + idx];
+                    al = (T)node_alpha(P, afx[idx]);
+                }
+            }, ua, a);
+        }
         T f[3];
         drag_one<T>(P, rq, va, ua, a, f);
         for (int c = 0; c < 3; ++c) Fd[c * n + q] = f[c];
@@ -236,7 +302,7 @@ hipError_t launch_gather_g2p_drag(const DevParams &P, int64_t n, int64_t K, cons
     if (n == 0) return hipSuccess;
     const int64_t bricks = K / kBrickCells;
     const int E = P.tile;
-    const size_t lds = sizeof(T) * 4 * (size_t)E * E * E;
+    const size_t lds = sizeof(typename Node4<T>::type) * (size_t)E * E * E;
     k_gather_g2p_drag<T><<<brick_grid(bricks), 256, lds, s>>>(P, n, B.list, B.count, order, x, v, r, id, xo, vo, ro,
                                                               ido, u, afx, cb, ce, Fd, uat, af);
     return hipGetLastError();

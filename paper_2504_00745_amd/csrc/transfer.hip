@@ -368,16 +368,34 @@ __global__ void __launch_bounds__(256) k_fix_prep(DevParams P, int64_t n, int64_
             fmax(fmax(wm[threadIdx.x][0], wm[threadIdx.x][1]), fmax(wm[threadIdx.x][2], wm[threadIdx.x][3]));
 }
 
-// 2^(50 - e) with 2^e the power of two above the largest of nb partial
-// maxima (1 when they are all zero): contributions times it stay below 2^50.
-__device__ inline double fix_scale(const double *__restrict__ part, int nb)
+// The scales of a call, after its nb partial maxima per channel:
+// part[kFixScale + c] = 2^(50 - e), 2^e the power of two above channel c's
+// largest bound (1 when all are zero), so contributions times it stay below
+// 2^50; part[kFixScale + 4 + c] = its inverse.  One workgroup, once per call.
+constexpr int kFixScale = 4 * kFixParts;
+
+__global__ void __launch_bounds__(256) k_fix_scale(double *__restrict__ part, int nb, int nch)
 {
-    double M = 0.0;
-    for (int b = 0; b < nb; ++b) M = fmax(M, part[b]);
-    if (!(M > 0.0)) return 1.0;
-    int e;
-    (void)frexp(M, &e);  // M = f 2^e, f in [0.5, 1)
-    return ldexp(1.0, 50 - e);
+    __shared__ double wm[4];
+    for (int c = 0; c < nch; ++c) {
+        double M = 0.0;
+        for (int b = threadIdx.x; b < nb; b += 256) M = fmax(M, part[c * kFixParts + b]);
+        for (int off = 32; off > 0; off >>= 1) M = fmax(M, __shfl_xor(M, off));
+        if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = M;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            M = fmax(fmax(wm[0], wm[1]), fmax(wm[2], wm[3]));
+            double sc = 1.0;
+            if (M > 0.0) {
+                int e;
+                (void)frexp(M, &e);  // M = f 2^e, f in [0.5, 1)
+                sc = ldexp(1.0, 50 - e);
+            }
+            part[kFixScale + c] = sc;
+            part[kFixScale + 4 + c] = 1.0 / sc;
+        }
+        __syncthreads();
+    }
 }
 
 __global__ void __launch_bounds__(kP2GThreads) k_p2g_real(DevParams P, int64_t n, const int32_t *__restrict__ bl,
@@ -387,7 +405,7 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g_real(DevParams P, int64_t n
                                                           const double *__restrict__ r,
                                                           const int32_t *__restrict__ cb,
                                                           const int32_t *__restrict__ ce,
-                                                          const double *__restrict__ part, int nb, int nch,
+                                                          const double *__restrict__ part, int nch,
                                                           unsigned long long *__restrict__ fx)
 {
     extern __shared__ unsigned long long itile[];
@@ -402,7 +420,7 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g_real(DevParams P, int64_t n
     const int32_t beg = s_range[0], end = s_range[1];
     if (end <= beg) return;
     double sc[4];
-    for (int c = 0; c < nch; ++c) sc[c] = fix_scale(part + c * kFixParts, nb);
+    for (int c = 0; c < nch; ++c) sc[c] = part[kFixScale + c];
     int32_t o[3];
     tile_origin(P, b, o);
     const int64_t G = P.G;
@@ -439,12 +457,12 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g_real(DevParams P, int64_t n
 }
 
 // out[c] (= or +=) the integer sums of channel c scaled back: fx / scale_c.
-__global__ void __launch_bounds__(256) k_fix_finish(int64_t G, int nch, const double *__restrict__ part, int nb,
+__global__ void __launch_bounds__(256) k_fix_finish(int64_t G, int nch, const double *__restrict__ part,
                                                     const int64_t *__restrict__ fx, double *__restrict__ out0,
                                                     double *__restrict__ out1, int acc)
 {
     __shared__ double inv[4];
-    if (threadIdx.x < nch) inv[threadIdx.x] = 1.0 / fix_scale(part + threadIdx.x * kFixParts, nb);
+    if (threadIdx.x < nch) inv[threadIdx.x] = part[kFixScale + 4 + threadIdx.x];
     __syncthreads();
     for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < nch * G; k += (int64_t)gridDim.x * 256) {
         const int c = (int)(k / G);
@@ -596,16 +614,17 @@ hipError_t launch_p2g_real(const DevParams &P, int64_t n, int64_t K, const doubl
     const int64_t per = n > 0 ? (n + kFixParts - 1) / kFixParts : 1;
     const int nb = (int)(n > 0 ? (n + per - 1) / per : 1);
     k_fix_prep<<<nb, 256, 0, s>>>(P, n, per, v, r, nullptr, fx, nch * G, part);
+    k_fix_scale<<<1, 256, 0, s>>>(part, nb, nch);
     if (n > 0) {
         const int64_t bricks = K / kBrickCells;
         const int E3 = P.tile * P.tile * P.tile;
         const size_t lds = sizeof(unsigned long long) * (size_t)nch * E3;
-        k_p2g_real<<<brick_grid(bricks), kP2GThreads, lds, s>>>(P, n, B.list, B.count, x, v, r, cb, ce, part, nb,
-                                                                 nch, reinterpret_cast<unsigned long long *>(fx));
+        k_p2g_real<<<brick_grid(bricks), kP2GThreads, lds, s>>>(P, n, B.list, B.count, x, v, r, cb, ce, part, nch,
+                                                                 reinterpret_cast<unsigned long long *>(fx));
     }
     unsigned g = grid_for(nch * G, 256);
     if (g > 4096) g = 4096;
-    k_fix_finish<<<g, 256, 0, s>>>(G, nch, part, nb, fx, alpha, mom, acc);
+    k_fix_finish<<<g, 256, 0, s>>>(G, nch, part, fx, alpha, mom, acc);
     return hipGetLastError();
 }
 
@@ -617,7 +636,7 @@ __global__ void __launch_bounds__(256) k_g2p_vjp_grid(DevParams P, int64_t n, co
                                                       const double *__restrict__ x, const double *__restrict__ A,
                                                       const double *__restrict__ gaf,
                                                       const int32_t *__restrict__ cb, const int32_t *__restrict__ ce,
-                                                      const double *__restrict__ part, int nb,
+                                                      const double *__restrict__ part,
                                                       unsigned long long *__restrict__ fx)
 {
     extern __shared__ unsigned long long itile[];
@@ -631,7 +650,7 @@ __global__ void __launch_bounds__(256) k_g2p_vjp_grid(DevParams P, int64_t n, co
     __syncthreads();
     const int32_t beg = s_range[0], end = s_range[1];
     if (end <= beg) return;
-    const double sc = fix_scale(part, nb);
+    const double sc = part[kFixScale];
     int32_t o[3];
     tile_origin(P, b, o);
     for (int64_t q = beg + (int64_t)threadIdx.x; q < end; q += 256) {
@@ -668,15 +687,16 @@ hipError_t launch_g2p_vjp_grid(const DevParams &P, int64_t n, int64_t K, const d
     const int64_t per = n > 0 ? (n + kFixParts - 1) / kFixParts : 1;
     const int nb = (int)(n > 0 ? (n + per - 1) / per : 1);
     k_fix_prep<<<nb, 256, 0, s>>>(P, n, per, nullptr, nullptr, gaf, fx, G, part);
+    k_fix_scale<<<1, 256, 0, s>>>(part, nb, 1);
     if (n > 0) {
         const int64_t bricks = K / kBrickCells;
         const size_t lds = sizeof(unsigned long long) * (size_t)P.tile * P.tile * P.tile;
-        k_g2p_vjp_grid<<<brick_grid(bricks), 256, lds, s>>>(P, n, B.list, B.count, x, A, gaf, cb, ce, part, nb,
+        k_g2p_vjp_grid<<<brick_grid(bricks), 256, lds, s>>>(P, n, B.list, B.count, x, A, gaf, cb, ce, part,
                                                             reinterpret_cast<unsigned long long *>(fx));
     }
     unsigned g = grid_for(G, 256);
     if (g > 4096) g = 4096;
-    k_fix_finish<<<g, 256, 0, s>>>(G, 1, part, nb, fx, gA, nullptr, 0);
+    k_fix_finish<<<g, 256, 0, s>>>(G, 1, part, fx, gA, nullptr, 0);
     return hipGetLastError();
 }
 

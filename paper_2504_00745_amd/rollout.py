@@ -15,6 +15,13 @@ scattered with the same permutations.  PyTorch provides device memory and
 the stream only: the loss cotangent is scaled on the device (gic_scale) and
 the parameters mu and c_drag, kernel arguments, are read from host tensors
 (or numbers), so neither pass reads the device back.
+
+With graph=True each pass is recorded once as a HIP graph (through
+torch.cuda.CUDAGraph: every launch of the pass, a few hundred, becomes one
+replay) and replayed with its inputs copied into the recorded buffers; it is
+recorded again when mu or c_drag change, since they are captured as kernel
+arguments.  The kernels are deterministic, so a replay gives the bits of the
+direct run.
 """
 import torch
 
@@ -24,7 +31,10 @@ from . import gic
 class Rollout:
     """Buffers and parameters of a differentiable rollout."""
 
-    def __init__(self, cfg, r, u, steps, ckpt=5, r_max=None):
+    def __init__(self, cfg, r, u, steps, ckpt=5, r_max=None, graph=False):
+        self.graph = bool(graph)
+        self._fwd = None  # (params, graph, static inputs, static outputs) of the recorded forward
+        self._bwd = None
         self.n = int(r.shape[-1])
         self.steps = int(steps)
         self.ckpt = int(ckpt)
@@ -44,9 +54,11 @@ class Rollout:
         self.gxs, self.gvs, self.gF = e(3 * n), e(3 * n), e(3 * n)
         self.guat, self.gaf, self.gmu_i, self.gcd_i = e(3 * n), e(n), e(n), e(n)
         self.scal = torch.zeros(4, dtype=f64, device=dev)  # L, dL/dmu, dL/dC_d, spare
+        self.params = (float(cfg["mu"]), float(cfg["c_drag"]))
 
     def set_params(self, mu, c_drag):
-        self.ctx.set_params(mu=float(mu), c_drag=float(c_drag))
+        self.params = (float(mu), float(c_drag))
+        self.ctx.set_params(mu=self.params[0], c_drag=self.params[1])
 
     # ---- forward pieces --------------------------------------------------
     def _sorted(self, x, v):
@@ -80,7 +92,36 @@ class Rollout:
         gic.gic_sum(c, self.P, self.scal[0:1], b=self.P)
 
     def forward(self, x0, v0):
-        """Runs the rollout; returns the loss tensor (1,) and checkpoints."""
+        """Runs the rollout; returns the loss tensor (1,), the checkpoints
+        and the final state (tensors of their own)."""
+        if not self.graph:
+            return self._forward(x0, v0)
+        x0, v0 = x0.detach().reshape(-1), v0.detach().reshape(-1)
+        if self._fwd is None or self._fwd[0] != self.params:
+            sx, sv = x0.clone(), v0.clone()
+            out = self._record(lambda: self._forward(sx, sv))
+            self._fwd = (self.params, out[0], (sx, sv), out[1])
+        _, g, (sx, sv), (L, ckpts, final) = self._fwd
+        sx.copy_(x0)
+        sv.copy_(v0)
+        g.replay()
+        return L.clone(), [(a.clone(), b.clone()) for a, b in ckpts], (final[0].clone(), final[1].clone())
+
+    @staticmethod
+    def _record(fn):
+        """fn run once directly (warm-up), then recorded as a graph; returns
+        (graph, fn's outputs in the graph's memory)."""
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            fn()
+        torch.cuda.current_stream().wait_stream(side)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            out = fn()
+        return g, out
+
+    def _forward(self, x0, v0):
         x, v = x0.contiguous().clone().view(-1), v0.contiguous().clone().view(-1)
         x2, v2 = torch.empty_like(x), torch.empty_like(v)
         ckpts = []
@@ -95,6 +136,26 @@ class Rollout:
     # ---- reverse pass ----------------------------------------------------
     def backward(self, ckpts, final, gL):
         """Gradients (dL/dv0 (3,n), dL/dmu, dL/dC_d) for cotangent gL of L."""
+        if not self.graph:
+            return self._backward(ckpts, final, gL)
+        gL = gL.detach().reshape(1).to(torch.float64)
+        if self._bwd is None or self._bwd[0] != self.params or len(self._bwd[2][0]) != len(ckpts):
+            sc = [(a.clone(), b.clone()) for a, b in ckpts]
+            sf = (final[0].clone(), final[1].clone())
+            sg = gL.clone()
+            out = self._record(lambda: self._backward(sc, sf, sg))
+            self._bwd = (self.params, out[0], (sc, sf, sg), out[1])
+        _, g, (sc, sf, sg), (gv, gmu, gcd) = self._bwd
+        for (a, b), (c, d) in zip(sc, ckpts):
+            a.copy_(c)
+            b.copy_(d)
+        sf[0].copy_(final[0])
+        sf[1].copy_(final[1])
+        sg.copy_(gL)
+        g.replay()
+        return gv.clone(), gmu.clone(), gcd.clone()
+
+    def _backward(self, ckpts, final, gL):
         c = self.ctx
         n = self.n
         x, v = final
