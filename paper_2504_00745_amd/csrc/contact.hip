@@ -768,7 +768,7 @@ __global__ void __launch_bounds__(kNbrThreads) k_nbr_build(DevParams P, int64_t 
 
 // Contact forces from the neighbour list: one thread per granule in sorted
 // order (each XCD one contiguous eighth, so partners mostly share its L2).
-// The workgroup first copies the double state of its own 256 granules into
+// The workgroup first copies the double state of its own granules into
 // LDS with coalesced loads; a listed partner among them (the granules of the
 // same few cells) is read from there, any other from global memory, two
 // partners' state fetched together so their loads overlap.  (Listed partners
@@ -779,9 +779,10 @@ __global__ void __launch_bounds__(kNbrThreads) k_nbr_build(DevParams P, int64_t 
 // Eq. (1); walls last.  A granule whose partners did not fit in its list
 // searches its cells in the same order.
 constexpr int kListBatch = 2;
+constexpr int kListThreads = 256;  // granules (threads) per workgroup
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_contact_list(DevParams P, int64_t n, int64_t nblk,
+__global__ void __launch_bounds__(kListThreads) k_contact_list(DevParams P, int64_t n, int64_t nblk,
                                                       const double *__restrict__ x, const double *__restrict__ v,
                                                       const double *__restrict__ r, const int32_t *__restrict__ cb,
                                                       const int32_t *__restrict__ ce,
@@ -790,12 +791,12 @@ __global__ void __launch_bounds__(256) k_contact_list(DevParams P, int64_t n, in
                                                       int32_t *__restrict__ ncont, int32_t *__restrict__ pairs,
                                                       int pair_cap, int64_t *err)
 {
-    __shared__ double sw[7][256];  // x0, x1, x2, v0, v1, v2, r of the workgroup's granules
+    __shared__ double sw[7][kListThreads];  // x0, x1, x2, v0, v1, v2, r of the workgroup's granules
     const int64_t lb = xcd_block(nblk);
     if (lb < 0) return;
-    const int64_t wbeg = lb * 256;
-    const int32_t wlen = (int32_t)(n - wbeg < 256 ? n - wbeg : 256);
-    for (int32_t i = threadIdx.x; i < wlen; i += 256) {
+    const int64_t wbeg = lb * kListThreads;
+    const int32_t wlen = (int32_t)(n - wbeg < kListThreads ? n - wbeg : kListThreads);
+    for (int32_t i = threadIdx.x; i < wlen; i += kListThreads) {
         const int64_t g = wbeg + i;
         sw[0][i] = x[g];
         sw[1][i] = x[n + g];
@@ -932,8 +933,8 @@ hipError_t launch_contact_list(const DevParams &P, int64_t n, const double *x, c
                                int32_t *pairs, int pair_cap, int64_t *err, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    const int64_t nblk = (n + 255) / 256;
-    k_contact_list<T><<<xcd_grid(nblk), 256, 0, s>>>(P, n, nblk, x, v, r, cb, ce, L.nbr, L.cnt, F, ncont, pairs,
+    const int64_t nblk = (n + kListThreads - 1) / kListThreads;
+    k_contact_list<T><<<xcd_grid(nblk), kListThreads, 0, s>>>(P, n, nblk, x, v, r, cb, ce, L.nbr, L.cnt, F, ncont, pairs,
                                                       pair_cap, err);
     return hipGetLastError();
 }
