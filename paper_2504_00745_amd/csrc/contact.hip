@@ -304,8 +304,10 @@ __device__ inline bool near_slot(float4 p, float mx, float my, float mz, float t
     return fmaf(mx, p.x, fmaf(my, p.y, fmaf(mz, p.z, p.w))) < thr;
 }
 
-// The bridge-force instantiation (the one launched) is held to four waves
-// per SIMD: it needs one register more than 128 and spills three.
+// The bridge-force instantiation is held to four waves per SIMD: it needs
+// one register more than 128 and spills three.  The dry instantiation
+// serves beds whose neighbour list could never be kept (no skin: cells of
+// exactly 2 r_max), where building a list every step costs more.
 template <typename T, bool CAP>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CAP ? 4 : 1)))
 k_contact_lds(DevParams P, int64_t n, const int32_t *__restrict__ bl,
@@ -892,10 +894,12 @@ hipError_t launch_contact(const DevParams &P, int64_t n, const double *x, const 
     if (n == 0) return hipSuccess;
     const int64_t nbricks = (int64_t)P.nb[0] * P.nb[1] * P.nb[2];
     const int cap = 1948;  // shell slots held in LDS: 40,908 bytes, four workgroups per CU
-    if (!sr) return hipErrorInvalidValue;  // the dry contact runs from the neighbour list
-    k_contact_lds<T, true><<<brick_grid(nbricks), 256, contact_lds_bytes(cap), s>>>(P, n, B.list, B.count, cap, x, v,
-                                                                                   r, cb, ce, sr, held, F, ncont,
-                                                                                   err);
+    if (sr)
+        k_contact_lds<T, true><<<brick_grid(nbricks), 256, contact_lds_bytes(cap), s>>>(
+            P, n, B.list, B.count, cap, x, v, r, cb, ce, sr, held, F, ncont, err);
+    else
+        k_contact_lds<T, false><<<brick_grid(nbricks), 256, contact_lds_bytes(cap), s>>>(
+            P, n, B.list, B.count, cap, x, v, r, cb, ce, nullptr, nullptr, F, ncont, err);
     return hipGetLastError();
 }
 

@@ -494,6 +494,16 @@ static gic_status contact_impl(gic_ctx *c, int64_t n, const double *x, const dou
                                const int32_t *cell_begin, const int32_t *cell_end, void *f_contact,
                                int32_t *n_contacts, int32_t *pair_ids, int32_t pair_cap, int force, hipStream_t s)
 {
+    if (!pair_ids && !(c->nl.thr2 > 0.0f)) {
+        // no skin (cells of exactly 2 r_max): a list would be rebuilt every
+        // step, so the forces come straight from the cells (same partner
+        // order, same bits)
+        if (fp32(c))
+            return hip_status(launch_contact<float>(c->dp, n, x, v, r, cell_begin, cell_end, c->bricks, nullptr,
+                                                    nullptr, (float *)f_contact, n_contacts, c->err, s));
+        return hip_status(launch_contact<double>(c->dp, n, x, v, r, cell_begin, cell_end, c->bricks, nullptr,
+                                                 nullptr, (double *)f_contact, n_contacts, c->err, s));
+    }
     if (launch_nbr_build(c->dp, n, x, r, cell_begin, cell_end, c->bricks, c->nl, force, c->err, s) != hipSuccess)
         return GIC_E_HIP;
     if (fp32(c))
