@@ -25,6 +25,12 @@ struct gic_ctx {
     int64_t *fxs;      // device: 4 G int64, integer sums of the unquantised transfers
     double *fxp;       // device: 4 x 1024 partial maxima, then the 4 scales and their inverses
     NbrList nl;        // device: neighbour list of the stepping path
+    // device: tiles and escape list of the stepping path's assembled P2G
+    // (tiles NULL: the grids are cleared and the tiles added with atomics);
+    // the escape counters alternate between consecutive steps
+    P2GStore p2gs;
+    uint32_t *esc_n2;
+    int esc_par;
     // The list holds the stepping path's state when nl_n == n and the state
     // to step is the array that the last step wrote (nl_x): its sorted
     // order is the one of the list's last build or check.
@@ -123,6 +129,18 @@ bool params_valid(const gic_params *p)
 // (the brick starts on a node boundary), one more otherwise.  Granules that
 // moved out of their cell since the sort reach outside the tile and take
 // the global path.
+// Whether a node lies in the tiles of at most two bricks per axis, which
+// k_p2g_assemble assumes: tile origins of bricks two apart differ by at
+// least the tile edge.  4 cell/dx an integer: cell/dx >= 1/2; otherwise
+// 4 cell/dx > 4.
+bool tiles_assemble(const gic_params *p)
+{
+    const double m4 = (double)kBrick * p->cell / p->dx;
+    const double r = floor(m4 + 0.5);
+    if (fabs(m4 - r) < 1e-9 * (r > 1.0 ? r : 1.0)) return r >= 2.0;
+    return m4 > 4.0;
+}
+
 int tile_edge(const gic_params *p)
 {
     const double m4 = (double)kBrick * p->cell / p->dx;
@@ -367,6 +385,32 @@ gic_status gic_create(const gic_params *p, int64_t n_max, gic_ctx **out)
     ok &= hipMalloc(&c->bricks.list, sizeof(int32_t) * (c->bricks.nbricks > 0 ? c->bricks.nbricks : 1)) == hipSuccess;
     ok &= hipMalloc(&c->bricks.count, sizeof(int32_t)) == hipSuccess;
     ok &= hipMalloc(&c->bricks.sums, sizeof(uint32_t) * 1024) == hipSuccess;
+    ok &= hipMalloc(&c->bricks.slot_of, sizeof(int32_t) * (c->bricks.nbricks > 0 ? c->bricks.nbricks : 1)) ==
+          hipSuccess;
+    ok &= hipMalloc(&c->p2gs.esc, sizeof(int32_t) * nn) == hipSuccess;
+    ok &= hipMalloc(&c->esc_n2, sizeof(uint32_t) * 2) == hipSuccess;
+    if (ok) ok = hipMemset(c->esc_n2, 0, sizeof(uint32_t) * 2) == hipSuccess;
+    if (ok && tiles_assemble(p)) {
+        // one 4-channel node tile per occupied brick (at most min(bricks, n));
+        // beyond 8 GiB the stepping path keeps the cleared grids and atomics
+        const int64_t E = c->dp.tile;
+        const int64_t slots = c->bricks.nbricks < nn ? c->bricks.nbricks : nn;
+        const size_t bytes = (size_t)(slots > 0 ? slots : 1) * 4 * E * E * E * sizeof(unsigned long long);
+        const size_t ncov = 4 * ((size_t)p->n[0] + p->n[1] + p->n[2]);
+        int32_t *cov = nullptr;
+        if (bytes <= ((size_t)8 << 30) && hipMalloc(&c->p2gs.tiles, bytes) == hipSuccess &&
+            hipMalloc(&cov, sizeof(int32_t) * ncov) == hipSuccess) {
+            int32_t *h = new int32_t[ncov];
+            p2g_cover_table(c->dp, h);
+            ok &= hipMemcpy(cov, h, sizeof(int32_t) * ncov, hipMemcpyHostToDevice) == hipSuccess;
+            delete[] h;
+            c->p2gs.cover = cov;
+        } else {
+            (void)hipFree(c->p2gs.tiles);
+            c->p2gs.tiles = nullptr;  // the fallback path needs neither
+            (void)hipGetLastError();
+        }
+    }
     ok &= hipMalloc(&c->fxs, sizeof(int64_t) * 4 * (size_t)(c->dp.G > 0 ? c->dp.G : 1)) == hipSuccess;
     ok &= hipMalloc(&c->fxp, sizeof(double) * (4 * 1024 + 8)) == hipSuccess;
     ok &= hipMalloc(&c->nl.nbr, sizeof(int32_t) * kNbrCap * nn) == hipSuccess;
@@ -423,6 +467,11 @@ gic_status gic_destroy(gic_ctx *c)
     (void)hipFree(c->bricks.list);
     (void)hipFree(c->bricks.count);
     (void)hipFree(c->bricks.sums);
+    (void)hipFree(c->bricks.slot_of);
+    (void)hipFree(c->p2gs.esc);
+    (void)hipFree(c->p2gs.tiles);
+    (void)hipFree(const_cast<int32_t *>(c->p2gs.cover));
+    (void)hipFree(c->esc_n2);
     if (c->tm_ev) {
         for (int i = 0; i < c->tm_cap * kStageEvents; ++i) (void)hipEventDestroy(c->tm_ev[i]);
         delete[] c->tm_ev;
@@ -690,6 +739,32 @@ gic_status gic_integrate_p2g_wet(gic_ctx *c, int64_t n, double *x, double *v, co
                               accumulate, stream);
 }
 
+// The stepping path's integrate + P2G into freshly written grids: stored
+// tiles assembled node by node (no clearing, no grid atomics) when the
+// context holds tile storage, else cleared grids and atomics.
+static gic_status step_integrate_p2g(gic_ctx *c, int64_t n, double *x, double *v, const double *r,
+                                     const void *f_contact, const void *f_force, const int32_t *cell_begin,
+                                     const int32_t *cell_end, int64_t *alpha_fx, int64_t *mom_fx, hipStream_t s)
+{
+    if (!c->p2gs.tiles || n == 0) {
+        if (launch_fill_i64(alpha_fx, c->dp.G, s) != hipSuccess || launch_fill_i64(mom_fx, 3 * c->dp.G, s) != hipSuccess)
+            return GIC_E_HIP;
+        return gic_integrate_p2g(c, n, x, v, r, f_contact, f_force, cell_begin, cell_end, alpha_fx, mom_fx, 1, s);
+    }
+    if (brick_list(c, cell_begin, cell_end, s) != hipSuccess) return GIC_E_HIP;
+    P2GStore st = c->p2gs;
+    st.esc_n = c->esc_n2 + c->esc_par;
+    uint32_t *next = c->esc_n2 + (c->esc_par ^ 1);
+    c->esc_par ^= 1;
+    if (fp32(c))
+        return hip_status(launch_integrate_p2g_assembled<float>(c->dp, n, c->K, x, v, r, (const float *)f_contact,
+                                                                (const float *)f_force, cell_begin, cell_end,
+                                                                c->bricks, alpha_fx, mom_fx, c->err, s, st, next));
+    return hip_status(launch_integrate_p2g_assembled<double>(c->dp, n, c->K, x, v, r, (const double *)f_contact,
+                                                             (const double *)f_force, cell_begin, cell_end, c->bricks,
+                                                             alpha_fx, mom_fx, c->err, s, st, next));
+}
+
 // Stage event k of the current timed step (no-op unless timing is on and
 // the event buffer has room).
 static void stage_mark(gic_ctx *c, int k, hipStream_t s)
@@ -772,13 +847,10 @@ gic_status gic_step(gic_ctx *c, int64_t n, const double *x_cur, const double *v_
         st = contact_impl(c, n, x_nxt, v_nxt, r_nxt, cell_begin, cell_end, f_contact, nullptr, nullptr, 0, force, s);
     stage_mark(c, 3, s);
     stage_mark(c, 4, s);  // no exchange deposit in this step
-    if (st == GIC_OK && (launch_fill_i64(alpha_fx, c->dp.G, s) != hipSuccess ||
-                         launch_fill_i64(mom_fx, 3 * c->dp.G, s) != hipSuccess))
-        st = GIC_E_HIP;
-    stage_mark(c, 5, s);
+    stage_mark(c, 5, s);  // the grids are written, not cleared and added to (step_integrate_p2g)
     if (st == GIC_OK)
-        st = gic_integrate_p2g(c, n, x_nxt, v_nxt, r_nxt, f_contact, f_drag, cell_begin, cell_end, alpha_fx, mom_fx, 1,
-                               stream);
+        st = step_integrate_p2g(c, n, x_nxt, v_nxt, r_nxt, f_contact, f_drag, cell_begin, cell_end, alpha_fx, mom_fx,
+                                s);
     stage_mark(c, 6, s);
     stage_done(c);
     c->in_step = false;
@@ -882,13 +954,9 @@ gic_status gic_sand_step(gic_ctx *c, int64_t n, double Dt, double *x_a, double *
             st = gic_exchange_p2g(c, n, xn, rn, f_contact, f_fluid, cell_begin, cell_end, weight, fs_fx, nullptr,
                                   stream);
         stage_mark(c, 4, s);
-        if (st == GIC_OK && (launch_fill_i64(alpha_fx, c->dp.G, s) != hipSuccess ||
-                             launch_fill_i64(mom_fx, 3 * c->dp.G, s) != hipSuccess))
-            st = GIC_E_HIP;
         stage_mark(c, 5, s);
         if (st == GIC_OK)
-            st = gic_integrate_p2g(c, n, xn, vn, rn, f_contact, f_fluid, cell_begin, cell_end, alpha_fx, mom_fx, 1,
-                                   stream);
+            st = step_integrate_p2g(c, n, xn, vn, rn, f_contact, f_fluid, cell_begin, cell_end, alpha_fx, mom_fx, s);
         stage_mark(c, 6, s);
         stage_done(c);
         c->in_step = false;

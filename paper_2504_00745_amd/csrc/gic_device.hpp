@@ -81,6 +81,18 @@ __device__ inline int64_t brick_at(const int32_t *__restrict__ list, const int32
     return j < per && l < nocc ? list[l] : -1;
 }
 
+// brick_of_block that also gives the brick's position in the list.
+__device__ inline int64_t brick_slot_of_block(const int32_t *__restrict__ list, const int32_t *__restrict__ count,
+                                              int64_t &slot)
+{
+    const int64_t nocc = *count;
+    const int64_t per = (nocc + kXcds - 1) / kXcds;
+    const int64_t b = blockIdx.x;
+    const int64_t j = b / kXcds;
+    slot = (b % kXcds) * per + j;
+    return j < per && slot < nocc ? list[slot] : -1;
+}
+
 // A range [b, e) of sorted positions read from caller-given cell ranges,
 // clipped to [0, n]: ranges that do not match the positions give wrong
 // results (and, where detected, a latched error) but never an access

@@ -36,9 +36,10 @@ struct SortScratch {
 // Occupied bricks of a set of cell ranges, in brick order (see
 // brick_of_block), built by launch_brick_list before the brick kernels.
 struct BrickList {
-    int32_t *list;    // [nbricks]
-    int32_t *count;   // [1]
-    uint32_t *sums;   // [<= 1024] block totals
+    int32_t *list;     // [nbricks]
+    int32_t *count;    // [1]
+    uint32_t *sums;    // [<= 1024] block totals
+    int32_t *slot_of;  // [nbricks] position of each brick in list, -1 if empty
     int64_t nbricks;
 };
 
@@ -111,6 +112,29 @@ hipError_t launch_drag(const DevParams &P, int64_t n, const double *r, const dou
 template <typename T>
 hipError_t launch_integrate(const DevParams &P, int64_t n, const double *r, const T *Fc, const T *Fd, double *x,
                             double *v, hipStream_t s);
+
+// Scratch of the assembled P2G of the stepping path: one node tile (4
+// channels) per occupied brick, and the list of granules whose stencil left
+// their brick's tile (at most n) with its counter.
+struct P2GStore {
+    unsigned long long *tiles;  // [occupied bricks][4][tile nodes]
+    int32_t *esc;               // [n]
+    uint32_t *esc_n;            // [1] granules listed
+    const int32_t *cover;       // per axis and node: (brick, node in its tile) twice, -1 for none
+};
+// The table P2GStore::cover for the parameters P (host; 4 (n0 + n1 + n2)
+// int32): for node i of axis a, at 4 (n0 + ... + n_{a-1} + i), the bricks
+// along the axis whose tile holds the node, with the node's offset in it.
+void p2g_cover_table(const DevParams &P, int32_t *out);
+// Integrate + P2G of the stepping path (dry, alpha and momentum): the tiles
+// are stored and the grids assembled from them (written, not added to:
+// alpha and mom need no clearing), then the listed granules deposited;
+// esc_next: the counter of the next call, cleared here.
+template <typename T>
+hipError_t launch_integrate_p2g_assembled(const DevParams &P, int64_t n, int64_t K, double *x, double *v,
+                                          const double *r, const T *Fc, const T *Fd, const int32_t *cb,
+                                          const int32_t *ce, const BrickList &B, int64_t *alpha, int64_t *mom,
+                                          int64_t *err, hipStream_t s, const P2GStore &st, uint32_t *esc_next);
 
 hipError_t launch_fill_i64(int64_t *a, int64_t len, hipStream_t s);
 hipError_t launch_fill_f64(double *a, int64_t len, hipStream_t s);

@@ -520,7 +520,7 @@ __global__ void __launch_bounds__(kScanThreads) k_brick_spine(uint32_t *sums, in
 __global__ void __launch_bounds__(256) k_brick_scatter(int64_t nbricks, int64_t per_block,
                                                        const int32_t *__restrict__ cb, const int32_t *__restrict__ ce,
                                                        const uint32_t *__restrict__ sums, int32_t *__restrict__ list,
-                                                       const int32_t *__restrict__ skip)
+                                                       int32_t *__restrict__ slot_of, const int32_t *__restrict__ skip)
 {
     if (skip && skip[2]) return;
     __shared__ uint32_t lds[4];
@@ -533,6 +533,7 @@ __global__ void __launch_bounds__(256) k_brick_scatter(int64_t nbricks, int64_t 
         uint32_t total;
         const uint32_t inc = block_scan_inclusive(f, lds, &total);
         if (f) list[base + inc - 1] = (int32_t)b;
+        if (b < hi) slot_of[b] = f ? (int32_t)(base + inc - 1) : -1;
         base += total;
     }
 }
@@ -614,7 +615,7 @@ hipError_t launch_brick_list(const int32_t *cb, const int32_t *ce, BrickList &B,
     const int blocks = (int)((nb + per - 1) / per);
     k_brick_count<<<blocks, 256, 0, s>>>(nb, per, cb, ce, B.sums, skip);
     k_brick_spine<<<1, kScanThreads, 0, s>>>(B.sums, blocks, B.count, skip);
-    k_brick_scatter<<<blocks, 256, 0, s>>>(nb, per, cb, ce, B.sums, B.list, skip);
+    k_brick_scatter<<<blocks, 256, 0, s>>>(nb, per, cb, ce, B.sums, B.list, B.slot_of, skip);
     return hipGetLastError();
 }
 

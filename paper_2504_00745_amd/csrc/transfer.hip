@@ -104,7 +104,7 @@ __device__ inline void tile_add(unsigned long long *tile, unsigned long long *gl
 // WET: granules hold water (held, per unit of their volume): the move takes
 // the wet mass of Eq. 19 (and the wet volume in the virtual mass), alpha
 // receives frac (1 + held) and momentum the wet mass's (Sec. 5.3).
-template <bool MOM, typename T, bool INTEG, bool EXCH = false, bool WET = false>
+template <bool MOM, typename T, bool INTEG, bool EXCH = false, bool WET = false, bool STORE = false>
 __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_eu(4))) k_p2g_fixed(DevParams P, int64_t n, const int32_t *__restrict__ bl,
                                                            const int32_t *__restrict__ bcnt, int batch,
                                                            double *x, double *v, const double *__restrict__ r,
@@ -113,20 +113,23 @@ __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_e
                                                            const int32_t *__restrict__ ce,
                                                            unsigned long long *__restrict__ alpha,
                                                            unsigned long long *__restrict__ mom, int64_t *err,
-                                                           double exsc, const double *__restrict__ held)
+                                                           double exsc, const double *__restrict__ held,
+                                                           P2GStore st)
 {
 #pragma clang fp contract(off)
     static_assert(!(EXCH && (MOM || INTEG)), "the exchange deposit is a kind of its own");
+    static_assert(!STORE || (MOM && !EXCH && !WET), "the stored tiles serve the dry alpha and momentum deposit");
     constexpr int NCH = EXCH ? 3 : (MOM ? 4 : 1);
     extern __shared__ unsigned long long tile[];
     __shared__ int32_t s_range[2];
     __shared__ int32_t s_wave[kP2GThreads / 64];
-    const int64_t b = brick_of_block(bl, bcnt);
+    int64_t slot;
+    const int64_t b = brick_slot_of_block(bl, bcnt, slot);
     if (b < 0) return;
     brick_range(n, b, cb, ce, s_range);
     __syncthreads();
     const int32_t beg = s_range[0], end = s_range[1];
-    if (end <= beg) return;
+    if (end <= beg && !STORE) return;  // (a stored tile is written even if empty)
     const int E = P.tile;
     const int E3 = E * E * E;
     const int bs = batch + 1;  // padded stride: the arrays start on different LDS banks
@@ -163,6 +166,7 @@ __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_e
                     v[a * n + q] = va[a];
                 }
             }
+            bool inside = true;  // all 27 stencil nodes (folded onto the edge) in the tile
             for (int a = 0; a < 3; ++a) {
                 const double t = xa[a] * P.inv_dx;
                 double fb = floor(t - 1.0);
@@ -170,6 +174,17 @@ __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_e
                 if (!(fb >= -2.0)) fb = -2.0;
                 if (fb > (double)P.n[a]) fb = (double)P.n[a];
                 sbase[a * bs + i] = (int16_t)fb;
+                if (STORE) {
+                    const int32_t lo = (int32_t)fb < 0 ? 0 : (int32_t)fb;
+                    const int32_t hi = (int32_t)fb + 2 > P.n[a] - 1 ? P.n[a] - 1 : (int32_t)fb + 2;
+                    inside &= lo - o[a] >= 0 && hi - o[a] < E;
+                }
+            }
+            if (STORE && !inside) {
+                // deposited after the assembly (k_p2g_escapes); a run of zeros here
+                const uint32_t k = atomicAdd(st.esc_n, 1u);
+                if (k < (uint32_t)n) st.esc[k] = (int32_t)q;
+                for (int a = 0; a < 3; ++a) sbase[a * bs + i] = (int16_t)(o[a] + 1);
             }
             double S[NCH];
             if constexpr (EXCH) {
@@ -214,7 +229,7 @@ __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_e
                 for (int c = 0; c < NCH; ++c) S[c] = 0.0;
             }
 #pragma unroll
-            for (int c = 0; c < NCH; ++c) sS[c * bs + i] = S[c];
+            for (int c = 0; c < NCH; ++c) sS[c * bs + i] = STORE && !inside ? 0.0 : S[c];
         }
         __syncthreads();
         // ---- runs of equal stencil base
@@ -300,19 +315,38 @@ __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_e
                 }
             }
             unsigned long long *tl = tile + c * E3;
+            if (STORE) {  // every node in the tile (phase 1 set aside the granules that were not)
 #pragma unroll
-            for (int cz = 0; cz < 3; ++cz)
+                for (int cz = 0; cz < 3; ++cz)
 #pragma unroll
-                for (int cy = 0; cy < 3; ++cy)
+                    for (int cy = 0; cy < 3; ++cy)
 #pragma unroll
-                    for (int cx = 0; cx < 3; ++cx) {
-                        const bool in = inb[0][cx] && inb[1][cy] && inb[2][cz];
-                        const int lidx = ((nd[2][cz] - o[2]) * E + (nd[1][cy] - o[1])) * E + (nd[0][cx] - o[0]);
-                        const int64_t gidx = node_index(P, nd[0][cx], nd[1][cy], nd[2][cz]);
-                        tile_add(tl, glob_of(c), in, lidx, gidx, (int64_t)acc[(cz * 3 + cy) * 3 + cx]);
-                    }
+                        for (int cx = 0; cx < 3; ++cx)
+                            __hip_atomic_fetch_add(
+                                &tl[((nd[2][cz] - o[2]) * E + (nd[1][cy] - o[1])) * E + (nd[0][cx] - o[0])],
+                                (unsigned long long)acc[(cz * 3 + cy) * 3 + cx], __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_WORKGROUP);
+            } else {
+#pragma unroll
+                for (int cz = 0; cz < 3; ++cz)
+#pragma unroll
+                    for (int cy = 0; cy < 3; ++cy)
+#pragma unroll
+                        for (int cx = 0; cx < 3; ++cx) {
+                            const bool in = inb[0][cx] && inb[1][cy] && inb[2][cz];
+                            const int lidx =
+                                ((nd[2][cz] - o[2]) * E + (nd[1][cy] - o[1])) * E + (nd[0][cx] - o[0]);
+                            const int64_t gidx = node_index(P, nd[0][cx], nd[1][cy], nd[2][cz]);
+                            tile_add(tl, glob_of(c), in, lidx, gidx, (int64_t)acc[(cz * 3 + cy) * 3 + cx]);
+                        }
+            }
         }
         __syncthreads();
+    }
+    if (STORE) {  // the whole tile, for k_p2g_assemble
+        unsigned long long *dst = st.tiles + slot * (int64_t)(NCH * E3);
+        for (int k = tid; k < NCH * E3; k += kP2GThreads) dst[k] = tile[k];
+        return;
     }
     for (int k = tid; k < NCH * E3; k += kP2GThreads) {
         const unsigned long long val = tile[k];
@@ -321,6 +355,121 @@ __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_e
         const int l = k - c * E3;
         const int32_t ni = o[0] + l % E, nj = o[1] + (l / E) % E, nk = o[2] + l / (E * E);
         atomicAdd(&glob_of(c)[node_index(P, ni, nj, nk)], val);
+    }
+}
+
+// Grid of the stored tiles (P2G in STORE mode): every node's alpha and
+// momentum is the sum of the tile entries of the occupied bricks whose tile
+// holds it (at most two bricks per axis, from the cover table), written
+// once, so the grids need no clearing and see no global atomics.  Nodes that
+// no occupied brick's tile holds get zero.  A workgroup takes x-rows of
+// nodes: the y and z bricks of a row are the same for all its threads.
+__global__ void __launch_bounds__(256) k_p2g_assemble(DevParams P, const unsigned long long *__restrict__ tiles,
+                                                      const int32_t *__restrict__ slot_of,
+                                                      const int32_t *__restrict__ cover,
+                                                      unsigned long long *__restrict__ alpha,
+                                                      unsigned long long *__restrict__ mom)
+{
+    const int E = P.tile, E3 = E * E * E;
+    const int64_t G = P.G;
+    const int64_t rows = (int64_t)P.n[1] * P.n[2];
+    const int32_t *cx = cover, *cy = cover + 4 * P.n[0], *cz = cover + 4 * (P.n[0] + P.n[1]);
+    for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+        const int32_t j = (int32_t)(row % P.n[1]), k = (int32_t)(row / P.n[1]);
+        const int32_t by[2] = {cy[4 * j], cy[4 * j + 2]}, ly[2] = {cy[4 * j + 1], cy[4 * j + 3]};
+        const int32_t bz[2] = {cz[4 * k], cz[4 * k + 2]}, lz[2] = {cz[4 * k + 1], cz[4 * k + 3]};
+        for (int32_t i = threadIdx.x; i < P.n[0]; i += 256) {
+            const int32_t bx[2] = {cx[4 * i], cx[4 * i + 2]}, lx[2] = {cx[4 * i + 1], cx[4 * i + 3]};
+            unsigned long long s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+            for (int iz = 0; iz < 2; ++iz) {
+                if (bz[iz] < 0) continue;
+                for (int iy = 0; iy < 2; ++iy) {
+                    if (by[iy] < 0) continue;
+                    const int64_t plane = ((int64_t)bz[iz] * P.nb[1] + by[iy]) * P.nb[0];
+                    const int off_yz = (lz[iz] * E + ly[iy]) * E;
+                    for (int ix = 0; ix < 2; ++ix) {
+                        if (bx[ix] < 0) continue;
+                        const int32_t sl = slot_of[plane + bx[ix]];
+                        if (sl < 0) continue;
+                        const unsigned long long *t = tiles + (int64_t)sl * (4 * E3) + off_yz + lx[ix];
+                        s0 += t[0];
+                        s1 += t[E3];
+                        s2 += t[2 * E3];
+                        s3 += t[3 * E3];
+                    }
+                }
+            }
+            const int64_t idx = row * P.n[0] + i;
+            alpha[idx] = s0;
+            mom[idx] = s1;
+            mom[G + idx] = s2;
+            mom[2 * G + idx] = s3;
+        }
+    }
+}
+
+// The granules whose stencil left their brick's tile (listed by the P2G in
+// STORE mode): each deposited straight to the assembled grids with the
+// rounding of the tile path, rint(w S) on the 26 outer nodes and rint(S)
+// minus their sum on the centre.  Also clears the other list counter, the
+// one the next step's P2G appends to.
+__global__ void __launch_bounds__(256) k_p2g_escapes(DevParams P, int64_t n, const int32_t *__restrict__ esc,
+                                                     const uint32_t *__restrict__ esc_n, uint32_t *__restrict__ next_n,
+                                                     const double *__restrict__ x, const double *__restrict__ v,
+                                                     const double *__restrict__ r,
+                                                     unsigned long long *__restrict__ alpha,
+                                                     unsigned long long *__restrict__ mom, int64_t *err)
+{
+#pragma clang fp contract(off)
+    if (blockIdx.x == 0 && threadIdx.x == 0) *next_n = 0u;
+    const uint32_t cnt = *esc_n < (uint32_t)n ? *esc_n : (uint32_t)n;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < cnt; e += (int64_t)gridDim.x * 256) {
+        const int64_t q = esc[e];
+        if ((uint64_t)q >= (uint64_t)n) continue;
+        double w[3][3];
+        int32_t nd[3][3];
+        for (int a = 0; a < 3; ++a) {
+            const double t = x[a * n + q] * P.inv_dx;
+            double fb = floor(t - 1.0);
+            const double f = (t - fb) - 0.5;
+            if (!(fb >= -2.0)) fb = -2.0;
+            if (fb > (double)P.n[a]) fb = (double)P.n[a];
+            const double c0 = 1.5 - f, c1 = f - 1.0, c2 = f - 0.5;
+            w[a][0] = 0.5 * (c0 * c0);
+            w[a][1] = 0.75 - c1 * c1;
+            w[a][2] = 0.5 * (c2 * c2);
+            for (int k = 0; k < 3; ++k) {
+                int32_t id = (int32_t)fb + k;
+                id = id < 0 ? 0 : id;
+                id = id > P.n[a] - 1 ? P.n[a] - 1 : id;
+                nd[a][k] = id;
+            }
+        }
+        const double frac = volume_of(r[q]) * P.inv_vcell;
+        double S[4] = {frac * GIC_TWO32, 0.0, 0.0, 0.0};
+        for (int c = 1; c < 4; ++c) S[c] = (frac * v[(c - 1) * n + q]) * GIC_TWO32;
+        bool ok = true;
+        for (int c = 0; c < 4; ++c) ok &= fabs(S[c]) < kFixLimit;
+        if (!ok) {
+            const double sum = ((S[0] + S[1]) + S[2]) + S[3];
+            raise_error(err, isfinite(sum) ? kErrRange : kErrNonFinite, q);
+            continue;
+        }
+        for (int c = 0; c < 4; ++c) {
+            unsigned long long *g = c == 0 ? alpha : mom + (int64_t)(c - 1) * P.G;
+            uint64_t outer = 0;
+            for (int cz = 0; cz < 3; ++cz)
+                for (int cy = 0; cy < 3; ++cy)
+                    for (int cx = 0; cx < 3; ++cx) {
+                        if (cx == 1 && cy == 1 && cz == 1) continue;
+                        const uint64_t val =
+                            rint_biased(((w[0][cx] * w[1][cy]) * w[2][cz]) * S[c]) - kRintBias;
+                        outer += val;
+                        if (val) atomicAdd(&g[node_index(P, nd[0][cx], nd[1][cy], nd[2][cz])], val);
+                    }
+            const uint64_t centre = (rint_biased(S[c]) - kRintBias) - outer;
+            if (centre) atomicAdd(&g[node_index(P, nd[0][1], nd[1][1], nd[2][1])], centre);
+        }
     }
 }
 
@@ -542,10 +691,10 @@ static hipError_t p2g_fixed_impl(const DevParams &P, int64_t n, int64_t K, doubl
     unsigned long long *M = reinterpret_cast<unsigned long long *>(mom);
     if (mom)
         k_p2g_fixed<true, T, INTEG, false, WET><<<brick_grid(bricks), kP2GThreads, lds, s>>>(
-            P, n, B.list, B.count, batch, x, v, r, Fc, Fd, cb, ce, A, M, err, 0.0, held);
+            P, n, B.list, B.count, batch, x, v, r, Fc, Fd, cb, ce, A, M, err, 0.0, held, P2GStore{});
     else
         k_p2g_fixed<false, T, INTEG, false, WET><<<brick_grid(bricks), kP2GThreads, lds, s>>>(
-            P, n, B.list, B.count, batch, x, v, r, Fc, Fd, cb, ce, A, nullptr, err, 0.0, held);
+            P, n, B.list, B.count, batch, x, v, r, Fc, Fd, cb, ce, A, nullptr, err, 0.0, held, P2GStore{});
     return hipGetLastError();
 }
 
@@ -564,7 +713,7 @@ hipError_t launch_exchange_p2g(const DevParams &P, int64_t n, int64_t K, const d
     // x is only read on this path
     k_p2g_fixed<false, T, false, true><<<brick_grid(bricks), kP2GThreads, lds, s>>>(
         P, n, B.list, B.count, batch, const_cast<double *>(x), nullptr, r, Fc, Ffl, cb, ce, F, F + P.G, err, exsc,
-        held);
+        held, P2GStore{});
     return hipGetLastError();
 }
 
@@ -594,6 +743,63 @@ hipError_t launch_integrate_p2g(const DevParams &P, int64_t n, int64_t K, double
     if (held)
         return p2g_fixed_impl<T, true, true>(P, n, K, x, v, r, Fc, Fd, cb, ce, B, alpha, mom, err, s, held);
     return p2g_fixed_impl<T, true>(P, n, K, x, v, r, Fc, Fd, cb, ce, B, alpha, mom, err, s);
+}
+
+template <typename T>
+hipError_t launch_integrate_p2g_assembled(const DevParams &P, int64_t n, int64_t K, double *x, double *v,
+                                          const double *r, const T *Fc, const T *Fd, const int32_t *cb,
+                                          const int32_t *ce, const BrickList &B, int64_t *alpha, int64_t *mom,
+                                          int64_t *err, hipStream_t s, const P2GStore &st, uint32_t *esc_next)
+{
+    const int64_t bricks = K / kBrickCells;
+    const int E3 = P.tile * P.tile * P.tile;
+    int batch = 512;
+    while (batch > 64 && p2g_lds(4, E3, batch) > 49152) batch /= 2;
+    const size_t lds = p2g_lds(4, E3, batch);
+    unsigned long long *A = reinterpret_cast<unsigned long long *>(alpha);
+    unsigned long long *M = reinterpret_cast<unsigned long long *>(mom);
+    if (n > 0)
+        k_p2g_fixed<true, T, true, false, false, true><<<brick_grid(bricks), kP2GThreads, lds, s>>>(
+            P, n, B.list, B.count, batch, x, v, r, Fc, Fd, cb, ce, A, M, err, 0.0, nullptr, st);
+    const int64_t rows = (int64_t)P.n[1] * P.n[2];
+    k_p2g_assemble<<<(unsigned)(rows < 16384 ? rows : 16384), 256, 0, s>>>(P, st.tiles, B.slot_of, st.cover, A, M);
+    k_p2g_escapes<<<256, 256, 0, s>>>(P, n, st.esc, st.esc_n, esc_next, x, v, r, A, M, err);
+    return hipGetLastError();
+}
+
+template hipError_t launch_integrate_p2g_assembled<float>(const DevParams &, int64_t, int64_t, double *, double *,
+                                                          const double *, const float *, const float *,
+                                                          const int32_t *, const int32_t *, const BrickList &,
+                                                          int64_t *, int64_t *, int64_t *, hipStream_t,
+                                                          const P2GStore &, uint32_t *);
+template hipError_t launch_integrate_p2g_assembled<double>(const DevParams &, int64_t, int64_t, double *, double *,
+                                                           const double *, const double *, const double *,
+                                                           const int32_t *, const int32_t *, const BrickList &,
+                                                           int64_t *, int64_t *, int64_t *, hipStream_t,
+                                                           const P2GStore &, uint32_t *);
+
+void p2g_cover_table(const DevParams &P, int32_t *out)
+{
+    int32_t *t = out;
+    for (int a = 0; a < 3; ++a) {
+        for (int32_t i = 0; i < P.n[a]; ++i, t += 4) {
+            t[0] = t[1] = t[2] = t[3] = -1;
+            int k = 0;
+            // tiles start about 4 cell/dx apart and reach about one node past
+            // their brick: the bricks near the node's own are the candidates
+            const int32_t bc = (int32_t)floor((double)(i + 1) / ((double)kBrick * P.cell * P.inv_dx));
+            const int32_t b0 = bc - 2 > 0 ? bc - 2 : 0;
+            for (int32_t bx = b0; bx <= bc + 2 && bx < P.nb[a] && k < 2; ++bx) {
+                // the tile origin of tile_origin
+                const int32_t o = (int32_t)floor((double)(bx * kBrick) * P.cell * P.inv_dx + 1e-7) - 1;
+                if (i >= o && i < o + P.tile) {
+                    t[2 * k] = bx;
+                    t[2 * k + 1] = i - o;
+                    ++k;
+                }
+            }
+        }
+    }
 }
 
 template hipError_t launch_integrate_p2g<float>(const DevParams &, int64_t, int64_t, double *, double *,
