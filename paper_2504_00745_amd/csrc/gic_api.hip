@@ -132,9 +132,10 @@ bool params_valid(const gic_params *p)
 // Whether a node lies in the tiles of at most two bricks per axis, which
 // k_p2g_assemble assumes: tile origins of bricks two apart differ by at
 // least the tile edge.  4 cell/dx an integer: cell/dx >= 1/2; otherwise
-// 4 cell/dx > 4.
+// 4 cell/dx > 4.  (And at most 2,048 bricks along x.)
 bool tiles_assemble(const gic_params *p)
 {
+    if ((p->nc[0] + kBrick - 1) / kBrick > 2048) return false;  // a row's bricks in 32 KiB of LDS
     const double m4 = (double)kBrick * p->cell / p->dx;
     const double r = floor(m4 + 0.5);
     if (fabs(m4 - r) < 1e-9 * (r > 1.0 ? r : 1.0)) return r >= 2.0;

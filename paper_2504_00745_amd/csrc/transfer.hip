@@ -370,26 +370,42 @@ __global__ void __launch_bounds__(256) k_p2g_assemble(DevParams P, const unsigne
                                                       unsigned long long *__restrict__ alpha,
                                                       unsigned long long *__restrict__ mom)
 {
+    extern __shared__ int32_t s_slot[];  // [4][nb0]: slots of the row's (z, y) brick pairs along x
+    __shared__ int32_t s_any;
     const int E = P.tile, E3 = E * E * E;
     const int64_t G = P.G;
     const int64_t rows = (int64_t)P.n[1] * P.n[2];
     const int32_t *cx = cover, *cy = cover + 4 * P.n[0], *cz = cover + 4 * (P.n[0] + P.n[1]);
+    const int32_t nbx = P.nb[0];
     for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
         const int32_t j = (int32_t)(row % P.n[1]), k = (int32_t)(row / P.n[1]);
         const int32_t by[2] = {cy[4 * j], cy[4 * j + 2]}, ly[2] = {cy[4 * j + 1], cy[4 * j + 3]};
         const int32_t bz[2] = {cz[4 * k], cz[4 * k + 2]}, lz[2] = {cz[4 * k + 1], cz[4 * k + 3]};
+        // the row's brick slots into LDS, and whether any is occupied
+        if (threadIdx.x == 0) s_any = 0;
+        __syncthreads();
+        int any = 0;
+        for (int t = threadIdx.x; t < 4 * nbx; t += 256) {
+            const int p = t / nbx, bx = t - p * nbx;
+            const int iz = p >> 1, iy = p & 1;
+            int32_t sl = -1;
+            if (bz[iz] >= 0 && by[iy] >= 0) sl = slot_of[((int64_t)bz[iz] * P.nb[1] + by[iy]) * nbx + bx];
+            s_slot[p * nbx + bx] = sl;
+            any |= sl >= 0;
+        }
+        if (any) s_any = 1;
+        __syncthreads();
+        const int occupied = s_any;
         for (int32_t i = threadIdx.x; i < P.n[0]; i += 256) {
-            const int32_t bx[2] = {cx[4 * i], cx[4 * i + 2]}, lx[2] = {cx[4 * i + 1], cx[4 * i + 3]};
             unsigned long long s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-            for (int iz = 0; iz < 2; ++iz) {
-                if (bz[iz] < 0) continue;
-                for (int iy = 0; iy < 2; ++iy) {
-                    if (by[iy] < 0) continue;
-                    const int64_t plane = ((int64_t)bz[iz] * P.nb[1] + by[iy]) * P.nb[0];
+            if (occupied) {
+                const int32_t bx[2] = {cx[4 * i], cx[4 * i + 2]}, lx[2] = {cx[4 * i + 1], cx[4 * i + 3]};
+                for (int p = 0; p < 4; ++p) {
+                    const int iz = p >> 1, iy = p & 1;
                     const int off_yz = (lz[iz] * E + ly[iy]) * E;
                     for (int ix = 0; ix < 2; ++ix) {
                         if (bx[ix] < 0) continue;
-                        const int32_t sl = slot_of[plane + bx[ix]];
+                        const int32_t sl = s_slot[p * nbx + bx[ix]];
                         if (sl < 0) continue;
                         const unsigned long long *t = tiles + (int64_t)sl * (4 * E3) + off_yz + lx[ix];
                         s0 += t[0];
@@ -405,6 +421,7 @@ __global__ void __launch_bounds__(256) k_p2g_assemble(DevParams P, const unsigne
             mom[G + idx] = s2;
             mom[2 * G + idx] = s3;
         }
+        __syncthreads();  // s_slot and s_any are rewritten for the next row
     }
 }
 
@@ -762,7 +779,8 @@ hipError_t launch_integrate_p2g_assembled(const DevParams &P, int64_t n, int64_t
         k_p2g_fixed<true, T, true, false, false, true><<<brick_grid(bricks), kP2GThreads, lds, s>>>(
             P, n, B.list, B.count, batch, x, v, r, Fc, Fd, cb, ce, A, M, err, 0.0, nullptr, st);
     const int64_t rows = (int64_t)P.n[1] * P.n[2];
-    k_p2g_assemble<<<(unsigned)(rows < 16384 ? rows : 16384), 256, 0, s>>>(P, st.tiles, B.slot_of, st.cover, A, M);
+    k_p2g_assemble<<<(unsigned)(rows < 16384 ? rows : 16384), 256, sizeof(int32_t) * 4 * P.nb[0], s>>>(
+        P, st.tiles, B.slot_of, st.cover, A, M);
     k_p2g_escapes<<<256, 256, 0, s>>>(P, n, st.esc, st.esc_n, esc_next, x, v, r, A, M, err);
     return hipGetLastError();
 }

@@ -229,22 +229,24 @@ def test_latched_errors(G, orc):
     assert out["err"][0] == 6
 
 
-@pytest.mark.parametrize("vscale", [1.0, 1e4])
-def test_whole_step_matches_stages(G, vscale):
+@pytest.mark.parametrize("name,vscale", [("c4s", 1.0), ("c4s", 1e4), ("c2s", 1.0), ("c1", 1.0)])
+def test_whole_step_matches_stages(G, name, vscale):
     """gic_step (grids assembled from stored brick tiles) runs the same
     arithmetic as the staged sequence (grids cleared, tiles added with
-    atomics): bit-identical state, grids and order.  With the velocities
-    scaled by 1e4 (up to two nodes per step) many granules leave their
-    brick's tile after the move and are deposited by the escape pass."""
+    atomics): bit-identical state, grids and order, for cells of 1.6, 2 and
+    1 node spacings.  With the velocities scaled by 1e4 (up to two nodes per
+    step) many granules leave their brick's tile after the move and are
+    deposited by the escape pass."""
     import torch
     from paper_2504_00745_amd import gic
-    G.say(f"[step] c4s fp32, v x {vscale}")
-    d = _make("c4s")
+    G.say(f"[step] {name} fp32, v x {vscale}")
+    d = _make(name)
     n = d["x"].shape[1]
     d["v"] = d["v"] * vscale
-    out = G.run_stages(d["params"], d["x"], d["v"], d["r"], d["u"], "fp32", r_max=0.006)
+    rm = _rmax(name, d["r"])
+    out = G.run_stages(d["params"], d["x"], d["v"], d["r"], d["u"], "fp32", r_max=rm)
     sim = gic.Simulator(d["params"], d["x"].reshape(3, n), d["v"].reshape(3, n), d["r"], d["u"].reshape(-1),
-                        "fp32", r_max=0.006)
+                        "fp32", r_max=rm)
     # the Simulator starts from its own sorted copy; feed the stage run the same
     # alpha grid and compare state by input index
     assert np.array_equal(sim.alpha.cpu().numpy(), out["alpha0"])
