@@ -111,6 +111,8 @@ def _declare(L):
         "orc_pair": (C.c_int, [_pp, _d, _d, _d, _d, C.c_double, C.c_double, _d, _i32]),
         "orc_stencil27": (None, [_pp, _d, _d, _i64, _d]),
         "orc_p2g_fixed": (None, [_pp, C.c_int64, _d, _d, _d, _i64, _i64]),
+        "orc_round_product_x": (C.c_int64, [C.c_double, C.c_double]),
+        "orc_p2g_totals_x": (None, [_pp, C.c_double, _d, _d]),
         "orc_p2g_real": (None, [_pp, C.c_int64, _d, _d, _d, _d, _d]),
         "orc_g2p": (None, [_pp, C.c_int64, _d, _d, _i64, _d, _d, _d]),
         "orc_drag": (None, [_pp, C.c_int64, _d, _d, _d, _d, _d]),
@@ -312,6 +314,20 @@ def p2g_fixed(cfg, x, v, r):
     lib().orc_p2g_fixed(C.byref(p), x.shape[1], _ptr(x, C.c_double), _ptr(v, C.c_double), _ptr(r, C.c_double),
                         _ptr(alpha, C.c_int64), _ptr(mom, C.c_int64))
     return alpha, mom
+
+
+def round_product(a, b):
+    """The integer a fixed-point contribution a b is rounded to: the exact
+    product, rounded once to the nearest integer (ties to even)."""
+    return int(lib().orc_round_product_x(float(a), float(b)))
+
+
+def p2g_totals(cfg, r, va):
+    """Scaled totals S (fraction, three momentum channels) of one dry
+    granule of radius r and velocity va (3,)."""
+    S = np.zeros(4)
+    lib().orc_p2g_totals_x(C.byref(params(cfg)), float(r), _ptr(_f64(va), C.c_double), _ptr(S, C.c_double))
+    return S
 
 
 def p2g_real(cfg, x, v, r):

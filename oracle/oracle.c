@@ -36,9 +36,10 @@
  *   - grid nodes at cell centres (i + 1/2) dx, quadratic B-spline kernel,
  *     out-of-range nodes folded onto the edge node;
  *   - alpha_s clamped at the nodes, then interpolated; alpha_f = 1 - alpha_s;
- *   - int64 fixed point, 2^-32 units, round half to even, the per-granule
- *     remainder goes to the centre node so each granule deposits exactly
- *     rint(frac * 2^32);
+ *   - int64 fixed point, 2^-32 units, round half to even (each outer
+ *     node's contribution w S rounded once, from the exact product), the
+ *     per-granule remainder goes to the centre node so each granule deposits
+ *     exactly rint(frac * 2^32);
  *   - coincident centres (d == 0) exert no force.
  *
  * Arrays are structure-of-arrays: x[0..n) = x-coordinates, x[n..2n) = y,
@@ -47,8 +48,10 @@
  * fields are three consecutive G-sized planes.
  *
  * Build: gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared (see build.py).
- * No fused multiply-add is allowed anywhere: every product and sum below is
- * rounded on its own, in the order written.
+ * No contracted multiply-add anywhere: every product and sum below is
+ * rounded on its own, in the order written.  The one fused operation is the
+ * explicit fma() of orc_round_product, which rounds a fixed-point
+ * contribution w S to an integer in a single step.
  */
 #include <math.h>
 #include <stdint.h>
@@ -594,11 +597,50 @@ void orc_stencil27(const orc_params *p, const double *xa, double *w27, int64_t *
 /* P2G: Eq. (7a) volume fraction and granule momentum                        */
 /* ------------------------------------------------------------------------ */
 
+/* Nearest integer (ties to even) to the exact product a b, for |a b| <
+ * 2^51: a b + M with M = 1.5 2^52 lies in [2^52, 2^53), where doubles are the
+ * integers, so the single rounding of the fused multiply-add rounds a b
+ * itself; subtracting M is exact.  (Rounding the double product a b first
+ * and then to an integer can differ by one where a b lies within half a
+ * double ulp of a half-integer.) */
+static int64_t orc_round_product(double a, double b)
+{
+    const double M = 6755399441055744.0; /* 1.5 * 2^52 */
+    return (int64_t)(fma(a, b, M) - M);
+}
+
+/* exposed for the rounding pin */
+int64_t orc_round_product_x(double a, double b) { return orc_round_product(a, b); }
+
 /* Fixed point.  alpha in units of 2^-32 cell volumes; momentum in units of
  * 2^-32 rho_s dx^3 (1 m/s).  Per granule and channel the target total is
  * Q = rint(S) with S = frac * 2^32 (alpha) or (frac * v_c) * 2^32 (momentum),
- * frac = V_i / dx^3.  The 26 outer nodes take rint(w * S); the centre node
- * takes Q minus their sum.  Adds into alpha (G) and mom (3G). */
+ * frac = V_i / dx^3.  The 26 outer nodes take w S rounded once to the
+ * nearest integer (orc_round_product, w the double weight of the node); the
+ * centre node takes Q minus their sum.  Adds into alpha (G) and mom (3G). */
+/* Scaled totals S of one granule: fraction, then the three momentum
+ * channels. */
+static void orc_p2g_totals(const orc_params *p, double inv_vcell, double rho_0, double r, double held, int wet,
+                           const double va[3], double S[4])
+{
+    double frac = orc_volume(r) * inv_vcell;
+    /* a wet granule's absorbed water counts as extra volume in alpha_s
+     * (Sec. 5.3): frac (1 + held) = frac + frac held (held = 0: frac) */
+    double fa = wet ? frac + frac * held : frac;
+    /* momentum in rho_s dx^3 units: a wet granule carries m_wet / (rho_s dx^3)
+     * = frac (rho_s + held rho_0) / rho_s = frac + frac held rho_0 / rho_s
+     * per unit velocity (Eq. 19), written so that held = 0 gives frac exactly */
+    double fm = wet ? frac + (frac * (held * rho_0)) / p->rho_s : frac;
+    S[0] = fa * ORC_TWO32;
+    for (int c = 0; c < 3; ++c) S[1 + c] = (fm * va[c]) * ORC_TWO32;
+}
+
+/* exposed for the rounding pin: the dry totals of one granule */
+void orc_p2g_totals_x(const orc_params *p, double r, const double *va, double *S)
+{
+    orc_p2g_totals(p, 1.0 / ((p->dx * p->dx) * p->dx), 0.0, r, 0.0, 0, va, S);
+}
+
 static void orc_p2g_fixed_held(const orc_params *p, double rho_0, int64_t n, const double *x, const double *v,
                                const double *r, const double *held, int64_t *alpha, int64_t *mom)
 {
@@ -610,16 +652,9 @@ static void orc_p2g_fixed_held(const orc_params *p, double rho_0, int64_t n, con
         orc_pos(n, x, i, xa);
         orc_stencil s;
         orc_stencil_of(p, inv_dx, xa, &s);
-        double frac = orc_volume(r[i]) * inv_vcell;
-        /* a wet granule's absorbed water counts as extra volume in alpha_s
-         * (Sec. 5.3): frac (1 + held) = frac + frac held (held = 0: frac) */
-        double fa = held ? frac + frac * held[i] : frac;
-        /* momentum in rho_s dx^3 units: a wet granule carries m_wet / (rho_s dx^3)
-         * = frac (rho_s + held rho_0) / rho_s = frac + frac held rho_0 / rho_s
-         * per unit velocity (Eq. 19), written so that held = 0 gives frac exactly */
-        double fm = held ? frac + (frac * (held[i] * rho_0)) / p->rho_s : frac;
-        double S[4] = {fa * ORC_TWO32, (fm * v[i]) * ORC_TWO32, (fm * v[n + i]) * ORC_TWO32,
-                       (fm * v[2 * n + i]) * ORC_TWO32};
+        const double va[3] = {v[i], v[n + i], v[2 * n + i]};
+        double S[4];
+        orc_p2g_totals(p, inv_vcell, rho_0, r[i], held ? held[i] : 0.0, held != NULL, va, S);
         for (int ch = 0; ch < 4; ++ch) {
             int64_t Q = llrint(S[ch]);
             int64_t rest = Q;
@@ -629,7 +664,7 @@ static void orc_p2g_fixed_held(const orc_params *p, double rho_0, int64_t n, con
                     for (int a = 0; a < 3; ++a) {
                         if (a == 1 && b == 1 && c == 1) continue;
                         double w = (s.w[0][a] * s.w[1][b]) * s.w[2][c];
-                        int64_t q = llrint(w * S[ch]);
+                        int64_t q = orc_round_product(w, S[ch]);
                         rest -= q;
                         dst[orc_node_index(p, &s, a, b, c)] += q;
                     }
@@ -1173,8 +1208,8 @@ double orc_rollout_vjp(const orc_params *p, int64_t n, const double *x0, const d
  *   - a sand step of length dt is cut into N = ceil(dt / dt'_max) equal
  *     sub-steps of dt / N, so each exchange weight dt'/dt is 1/N;
  *   - the exchange grid is int64 fixed point in units of 2^-32 f_unit,
- *     deposited like Eq. (7a): rint(w S) on the 26 outer nodes, the centre
- *     node takes rint(S) minus their sum.
+ *     deposited like Eq. (7a): w S rounded once on the 26 outer nodes, the
+ *     centre node takes rint(S) minus their sum.
  */
 
 typedef struct {
@@ -1307,7 +1342,8 @@ void orc_exchange_force(const orc_params *p, const orc_coupling *cp, int64_t n, 
 /* Exchange P2G of one sub-step: adds -weight * f_j N(x_j - x) to fs (3G,
  * int64, units of 2^-32 f_unit).  Per granule and component the target total
  * is Q = rint(S), S = (s f) * 2^32 with s = -weight / f_unit; the 26 outer
- * nodes take rint(w S), the centre node Q minus their sum. */
+ * nodes take w S rounded once (orc_round_product), the centre node Q minus
+ * their sum. */
 void orc_exchange_p2g(const orc_params *p, const orc_coupling *cp, int64_t n, const double *x, const double *r,
                       const double *held, const double *Fc, const double *Ffl, double weight, int64_t *fs)
 {
@@ -1331,7 +1367,7 @@ void orc_exchange_p2g(const orc_params *p, const orc_coupling *cp, int64_t n, co
                     for (int a = 0; a < 3; ++a) {
                         if (a == 1 && b == 1 && c == 1) continue;
                         double w = (s.w[0][a] * s.w[1][b]) * s.w[2][c];
-                        int64_t q = llrint(w * S);
+                        int64_t q = orc_round_product(w, S);
                         rest -= q;
                         dst[orc_node_index(p, &s, a, b, c)] += q;
                     }

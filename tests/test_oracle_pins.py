@@ -424,6 +424,67 @@ def test_p2g_conserves_volume_and_momentum_exactly(orc):
         assert abs(Qc * unit - m_tot) <= 1e-9 * np.abs(2500.0 * 4 / 3 * np.pi * r ** 3 * v[c]).sum() + r.size * unit
 
 
+def _round_exact(a, b):
+    """Nearest integer to the exact rational product a b, ties to even."""
+    from fractions import Fraction
+    q = Fraction(a) * Fraction(b)
+    f = math.floor(q)
+    d = q - f
+    if d > Fraction(1, 2) or (d == Fraction(1, 2) and f % 2 == 1):
+        f += 1
+    return int(f)
+
+
+def test_fixed_point_contribution_rounds_the_exact_product(orc):
+    """Reading of the int64 fixed point (Eq. 7a deposited in 2^-32 units): a
+    contribution w S is the exact product rounded once, ties to even.  Checked
+    against exact rational arithmetic on random products, on products whose
+    double rounding would land elsewhere (large S, where the double product's
+    ulp is a fraction of one) and on exact ties."""
+    rng = np.random.Generator(np.random.PCG64(21))
+    for _ in range(2000):
+        a = float(rng.uniform(0.0, 0.75))
+        b = float(rng.uniform(-2.0 ** 40, 2.0 ** 40))
+        assert orc.round_product(a, b) == _round_exact(a, b)
+    differ = 0
+    for _ in range(4000):
+        a = float(rng.uniform(0.0, 0.75))
+        b = float(rng.uniform(2.0 ** 49, 2.0 ** 50)) * (1.0 if rng.uniform() < 0.5 else -1.0)
+        exact = _round_exact(a, b)
+        differ += int(np.rint(a * b)) != exact
+        assert orc.round_product(a, b) == exact
+    assert differ > 100  # the cases where rounding the double product first would err
+    for k in (3, 4, 1 << 40, -7):  # exact ties: (k + 1/2) = 0.5 (2k + 1)
+        assert orc.round_product(0.5, 2.0 * k + 1.0) == _round_exact(0.5, 2.0 * k + 1.0)
+
+
+def test_p2g_nodes_take_the_rounded_contributions(orc):
+    """A lone granule's grids (Eq. 7a, int64 fixed point): each outer node
+    holds w S rounded once from the exact product, w the node's B-spline
+    weight and S the channel's scaled total; the centre holds rint(S) minus
+    their sum."""
+    cfg = small_cfg()
+    rng = np.random.Generator(np.random.PCG64(22))
+    for _ in range(12):
+        xa = rng.uniform(0.06, 0.26, 3)
+        va = rng.normal(0.0, 2.0, 3)
+        r0 = float(rng.uniform(0.002, 0.009))
+        a, m = orc.p2g_fixed(cfg, xa.reshape(3, 1), va.reshape(3, 1), np.array([r0]))
+        w27, node27, _ = orc.stencil27(cfg, xa)
+        S = orc.p2g_totals(cfg, r0, va)
+        grids = [a] + [m[c] for c in range(3)]
+        for ch in range(4):
+            outer = 0
+            for k in range(27):
+                if k == 13:
+                    continue
+                q = _round_exact(float(w27[k]), float(S[ch]))
+                assert int(grids[ch][node27[k]]) == q
+                outer += q
+            assert int(grids[ch][node27[13]]) == _round_exact(1.0, float(S[ch])) - outer
+            assert np.count_nonzero(grids[ch]) <= 27
+
+
 def test_stencil_folds_onto_edge_nodes(orc):
     """Reading of the boundary: a granule on the last node centre has weights
     (1/8, 3/4, 1/8) on nodes n-2, n-1, n; node n is outside the box and its
