@@ -60,15 +60,18 @@ def log(*a):
 # Algorithmic bytes per granule (and per touched grid node) of each kernel of
 # the step: the arrays the method itself must read and write once, neighbour
 # re-reads and scratch excluded.  B = size of the real type.
-def stage_bytes(stage, n, nodes, real_bytes):
+def stage_bytes(stage, n, nodes, real_bytes, G=0, assembled=False):
     B = real_bytes
+    if stage == "assemble":  # every grid node written once: alpha and three momentum components (int64)
+        return 32 * G
     per = {
         "sort": 24 + 4 + 4,                          # read x, write key, write order
         "gather_g2p_drag": 4 + 2 * (24 + 24 + 8 + 4) + 3 * B,  # order; gather + write x, v, r, id; write F_d
         "contact": 24 + 24 + 8 + 3 * B,              # read x, v, r; write F_c
         "integrate_p2g": 8 + 3 * B + 3 * B + 2 * (24 + 24),  # read r, F_c, F_d; read + write x, v
     }[stage]
-    grid = {"gather_g2p_drag": 3 * B + 8, "integrate_p2g": 8 + 24}.get(stage, 0)  # node reads / writes
+    # node reads / writes; with assembled grids the tile kernel writes no grid
+    grid = {"gather_g2p_drag": 3 * B + 8, "integrate_p2g": 0 if assembled else 8 + 24}.get(stage, 0)
     return per * n + grid * nodes
 
 
@@ -109,7 +112,7 @@ def time_steps(sim, steps, warmup):
 
 
 STAGE_KEYS = {"sort": "sort", "gather": "gather_g2p_drag", "contact": "contact", "exchange": "exchange_p2g",
-              "grid_clear": "grid_clear", "integrate_p2g": "integrate_p2g"}
+              "grid_clear": "grid_clear", "integrate_p2g": "integrate_p2g", "assemble": "assemble"}
 
 
 def time_stages(sim, steps, sand_dt=None, **sand):
@@ -136,23 +139,28 @@ def time_stages(sim, steps, sand_dt=None, **sand):
 
 # Kernels whose time is one launch of one kernel per (sub-)step (the sort is
 # a sequence of kernels; the contact stage is the neighbour-list kernel plus
-# the list build, which returns at once when the list is kept).
+# the list build, which returns at once when the list is kept; the assembly
+# of the grids from the brick tiles is followed by the small deposit of the
+# granules whose stencil left their tile, so it is priced beside them but
+# not taken as the dominant kernel).
 SINGLE_KERNEL_STAGES = ("gather_g2p_drag", "contact", "integrate_p2g")
 
 
-def dominant_roofline(stages, n, nodes, real_bytes, workload):
+def dominant_roofline(stages, n, nodes, real_bytes, workload, G):
     dom = max(SINGLE_KERNEL_STAGES, key=lambda k: stages[k])
-    abytes = stage_bytes(dom, n, nodes, real_bytes)
+    abytes = stage_bytes(dom, n, nodes, real_bytes, G, stages.get("assemble", 0.0) > 0.0)
     ach = abytes / stages[dom] / 1e9
     return {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": ach / HBM_PEAK_GBS, "traffic": stored_traffic(dom, workload), "algorithmic_bytes": abytes}
 
 
-def stage_rooflines(stages, n, nodes, real_bytes):
-    """Algorithmic GB/s and fraction of the HBM peak of each single-kernel stage."""
+def stage_rooflines(stages, n, nodes, real_bytes, G):
+    """Algorithmic GB/s and fraction of the HBM peak of each single-kernel
+    stage, and of the grid assembly when the step has one."""
     out = {}
-    for k in SINGLE_KERNEL_STAGES:
-        ab = stage_bytes(k, n, nodes, real_bytes)
+    assembled = stages.get("assemble", 0.0) > 0.0
+    for k in SINGLE_KERNEL_STAGES + (("assemble",) if assembled else ()):
+        ab = stage_bytes(k, n, nodes, real_bytes, G, assembled)
         out[k] = {"ms": round(stages[k] * 1e3, 4), "algorithmic_bytes": ab,
                   "GB_s": round(ab / stages[k] / 1e9, 1), "frac": round(ab / stages[k] / 1e9 / HBM_PEAK_GBS, 4)}
     return out
@@ -224,7 +232,8 @@ def run_leg(name, steps, warmup, with_fp64=False):
         B = 4 if prec == "fp32" else 8
         r = {"value": n * steps / t, "unit": "granule-steps/s", "ms_per_step": t / steps * 1e3,
              "neighbour_builds": builds, "stages_ms": {k_: round(v * 1e3, 4) for k_, v in stages.items()},
-             "stage_rooflines": stage_rooflines(stages, n, nodes, B), "error": [code, idx]}
+             "stage_rooflines": stage_rooflines(stages, n, nodes, B, int(np.prod(d["params"]["n"]))),
+             "error": [code, idx]}
         res[prec] = r
         del sim
         torch.cuda.empty_cache()
@@ -301,6 +310,7 @@ def copy_calibration():
 # Source files whose change invalidates a stored HBM traffic measurement.
 TRAFFIC_SOURCES = {
     "contact": ["contact.hip", "gic_device.hpp", "gic_launch.hpp"],
+    "assemble": ["transfer.hip", "gic_device.hpp", "gic_launch.hpp"],
     "integrate_p2g": ["transfer.hip", "gic_device.hpp", "gic_launch.hpp"],
     "gather_g2p_drag": ["step.hip", "gic_device.hpp", "gic_launch.hpp"],
     "gather_g2p_fluid": ["step.hip", "gic_device.hpp", "gic_launch.hpp"],
@@ -376,7 +386,8 @@ def time_coupled(d, wl_name, substeps=4, sand_steps=8):
     # per stage, from the events the library records between the stages of
     # each sub-step
     st, k = time_stages(sim, 4, sand_dt=Dt, grad_p=GP, acc_f=AF, fs=FS)
-    acc = {key: st[key] for key in ("sort", "gather_g2p_fluid", "contact", "exchange_p2g", "integrate_p2g")}
+    acc = {key: st[key] for key in ("sort", "gather_g2p_fluid", "contact", "exchange_p2g", "integrate_p2g",
+                                    "assemble")}
     nodes = touched_nodes(sim)
     xb = coupled_bytes("exchange_p2g", n, nodes, 4)
     ach = xb / acc["exchange_p2g"] / 1e9
@@ -650,8 +661,8 @@ def main():
                    "granules": n, "grid_nodes": G, "parallelism": "single GPU"},
         "stages_ms": {k: round(v * 1e3, 4) for k, v in st.items()},
         "neighbour_builds": r32["builds"],
-        "roofline": dominant_roofline(st, n, r32["nodes"], 4, a.workload),
-        "stage_rooflines": stage_rooflines(st, n, r32["nodes"], 4),
+        "roofline": dominant_roofline(st, n, r32["nodes"], 4, a.workload, G),
+        "stage_rooflines": stage_rooflines(st, n, r32["nodes"], 4, G),
     }
     if "fp64" in out:
         r64 = out["fp64"]

@@ -313,7 +313,8 @@ gic_status gic_integrate(gic_ctx *ctx, int64_t n, const double *r, const void *f
  * Fixed point: alpha in 2^-32 cell volumes, momentum in 2^-32 rho_s dx^3
  * (1 m/s) units.  Per granule and channel the total is Q = rint(S) with
  * S = frac 2^32 (alpha) or (frac v_c) 2^32 (momentum), frac = (4/3 pi r^3)
- * / dx^3; each of the 26 outer stencil nodes takes rint(w S) (round half to
+ * / dx^3; each of the 26 outer stencil nodes takes w S rounded once to the
+ * nearest integer (the exact product of the double weight w and S, ties to
  * even) and the centre node takes Q minus their sum, so every granule
  * deposits exactly Q.  Integer sums make the grid independent of the order
  * of accumulation.
@@ -403,7 +404,10 @@ gic_status gic_step(gic_ctx *ctx, int64_t n, const double *x_cur, const double *
  * ms[0] sort (keys, sort, cell ranges, brick list), ms[1] gather + G2P +
  * fluid force, ms[2] contact (neighbour-list build when needed, forces),
  * ms[3] exchange deposit (0 in gic_step), ms[4] grid clear, ms[5] integrate
- * + P2G; *steps receives their number. */
+ * + P2G (the brick-tile kernel, or the atomic deposit into cleared grids),
+ * ms[6] the grids assembled from the brick tiles, with the granules whose
+ * stencil left their tile (0 on the atomic path); ms holds 7 doubles;
+ * *steps receives their number. */
 gic_status gic_stage_timing(gic_ctx *ctx, int32_t max_steps);
 gic_status gic_stage_times(gic_ctx *ctx, void *stream, double *ms, int32_t *steps);
 
@@ -433,7 +437,7 @@ gic_status gic_gather_g2p_fluid(gic_ctx *ctx, int64_t n, const int32_t *order, c
  * params.vmass minus (rho_f V / 2) a_s with a_s = ((f_contact + f_fluid) +
  * m g) / (m + rho_f V / 2), the sub-step's acceleration.  Per granule and
  * component the deposit totals rint(S), S = (-weight / f_unit) f 2^32, the 26
- * outer nodes taking rint(w S) and the centre the rest (integer, so bit-exact
+ * outer nodes taking w S rounded once and the centre the rest (integer, so bit-exact
  * in any order).  x, r, f_contact, f_fluid in the sorted order of
  * cell_begin, cell_end (positions before the move).  held (n double,
  * sorted order, or NULL): wet granules take the wet mass V (rho_s + held
@@ -530,7 +534,8 @@ gic_status gic_sum_noalloc(int64_t n, const double *a, const double *b, double *
 gic_status gic_scale(gic_ctx *ctx, int64_t n, const double *a, const double *s, double factor, double *out,
                      void *stream);
 
-/* Permute comps (1..3) planes of n doubles: scatter = 0: out[c n + q] =
+/* Permute comps (1..6) planes of n doubles (six: positions and velocities
+ * held as one array, x then v): scatter = 0: out[c n + q] =
  * in[c n + order[q]];  scatter = 1: out[c n + order[q]] = in[c n + q]. */
 gic_status gic_permute(gic_ctx *ctx, int64_t n, int32_t comps, const int32_t *order, const double *in, double *out,
                        int32_t scatter, void *stream);

@@ -49,8 +49,9 @@ struct gic_ctx {
 
 // Events per timed (sub-)step: start, after the sort and brick list, after
 // the gather, after the contact, after the exchange deposit, after the grid
-// clear, after integrate + P2G.
-constexpr int kStageEvents = 7;
+// clear, after integrate + P2G (the tile kernel, or the atomic deposit),
+// after the assembly of the grids from the tiles.
+constexpr int kStageEvents = 8;
 
 namespace {
 
@@ -743,6 +744,12 @@ gic_status gic_integrate_p2g_wet(gic_ctx *c, int64_t n, double *x, double *v, co
 // The stepping path's integrate + P2G into freshly written grids: stored
 // tiles assembled node by node (no clearing, no grid atomics) when the
 // context holds tile storage, else cleared grids and atomics.
+static void stage_mark(gic_ctx *c, int k, hipStream_t s);
+
+// Integrate + P2G of the stepping paths, between the stage events 5
+// (integrate + P2G) and 7: with tiles, the tile kernel, event 6, then the
+// assembly of the grids; otherwise the grid fills, event 5, the atomic
+// deposit, event 6 (no assembly).
 static gic_status step_integrate_p2g(gic_ctx *c, int64_t n, double *x, double *v, const double *r,
                                      const void *f_contact, const void *f_force, const int32_t *cell_begin,
                                      const int32_t *cell_end, int64_t *alpha_fx, int64_t *mom_fx, hipStream_t s)
@@ -750,20 +757,29 @@ static gic_status step_integrate_p2g(gic_ctx *c, int64_t n, double *x, double *v
     if (!c->p2gs.tiles || n == 0) {
         if (launch_fill_i64(alpha_fx, c->dp.G, s) != hipSuccess || launch_fill_i64(mom_fx, 3 * c->dp.G, s) != hipSuccess)
             return GIC_E_HIP;
-        return gic_integrate_p2g(c, n, x, v, r, f_contact, f_force, cell_begin, cell_end, alpha_fx, mom_fx, 1, s);
+        stage_mark(c, 5, s);
+        const gic_status st =
+            gic_integrate_p2g(c, n, x, v, r, f_contact, f_force, cell_begin, cell_end, alpha_fx, mom_fx, 1, s);
+        stage_mark(c, 6, s);
+        return st;
     }
     if (brick_list(c, cell_begin, cell_end, s) != hipSuccess) return GIC_E_HIP;
+    stage_mark(c, 5, s);
     P2GStore st = c->p2gs;
     st.esc_n = c->esc_n2 + c->esc_par;
     uint32_t *next = c->esc_n2 + (c->esc_par ^ 1);
     c->esc_par ^= 1;
+    hipError_t e;
     if (fp32(c))
-        return hip_status(launch_integrate_p2g_assembled<float>(c->dp, n, c->K, x, v, r, (const float *)f_contact,
-                                                                (const float *)f_force, cell_begin, cell_end,
-                                                                c->bricks, alpha_fx, mom_fx, c->err, s, st, next));
-    return hip_status(launch_integrate_p2g_assembled<double>(c->dp, n, c->K, x, v, r, (const double *)f_contact,
-                                                             (const double *)f_force, cell_begin, cell_end, c->bricks,
-                                                             alpha_fx, mom_fx, c->err, s, st, next));
+        e = launch_integrate_p2g_store<float>(c->dp, n, c->K, x, v, r, (const float *)f_contact,
+                                              (const float *)f_force, cell_begin, cell_end, c->bricks, c->err, s, st);
+    else
+        e = launch_integrate_p2g_store<double>(c->dp, n, c->K, x, v, r, (const double *)f_contact,
+                                               (const double *)f_force, cell_begin, cell_end, c->bricks, c->err, s,
+                                               st);
+    if (e != hipSuccess) return hip_status(e);
+    stage_mark(c, 6, s);
+    return hip_status(launch_p2g_assemble(c->dp, n, x, v, r, c->bricks, alpha_fx, mom_fx, c->err, s, st, next));
 }
 
 // Stage event k of the current timed step (no-op unless timing is on and
@@ -848,11 +864,10 @@ gic_status gic_step(gic_ctx *c, int64_t n, const double *x_cur, const double *v_
         st = contact_impl(c, n, x_nxt, v_nxt, r_nxt, cell_begin, cell_end, f_contact, nullptr, nullptr, 0, force, s);
     stage_mark(c, 3, s);
     stage_mark(c, 4, s);  // no exchange deposit in this step
-    stage_mark(c, 5, s);  // the grids are written, not cleared and added to (step_integrate_p2g)
     if (st == GIC_OK)
         st = step_integrate_p2g(c, n, x_nxt, v_nxt, r_nxt, f_contact, f_drag, cell_begin, cell_end, alpha_fx, mom_fx,
                                 s);
-    stage_mark(c, 6, s);
+    stage_mark(c, 7, s);
     stage_done(c);
     c->in_step = false;
     if (st == GIC_OK) {
@@ -955,10 +970,9 @@ gic_status gic_sand_step(gic_ctx *c, int64_t n, double Dt, double *x_a, double *
             st = gic_exchange_p2g(c, n, xn, rn, f_contact, f_fluid, cell_begin, cell_end, weight, fs_fx, nullptr,
                                   stream);
         stage_mark(c, 4, s);
-        stage_mark(c, 5, s);
         if (st == GIC_OK)
             st = step_integrate_p2g(c, n, xn, vn, rn, f_contact, f_fluid, cell_begin, cell_end, alpha_fx, mom_fx, s);
-        stage_mark(c, 6, s);
+        stage_mark(c, 7, s);
         stage_done(c);
         c->in_step = false;
         if (st == GIC_OK) {
@@ -1082,7 +1096,7 @@ gic_status gic_scale(gic_ctx *c, int64_t n, const double *a, const double *s, do
 gic_status gic_permute(gic_ctx *c, int64_t n, int32_t comps, const int32_t *order, const double *in, double *out,
                        int32_t scatter, void *stream)
 {
-    if (!n_ok(c, n) || comps < 1 || comps > 3) return GIC_E_ARG;
+    if (!n_ok(c, n) || comps < 1 || comps > 6) return GIC_E_ARG;
     if (n > 0 && (!order || !in || !out || in == out)) return GIC_E_ARG;
     return hip_status(launch_permute(n, comps, order, in, out, scatter ? 1 : 0, (hipStream_t)stream));
 }

@@ -436,6 +436,15 @@ __device__ inline uint64_t rint_biased(double v)
     return (uint64_t)__double_as_longlong(v + M);
 }
 
+// Bit pattern of the nearest integer (ties to even) to the exact product
+// a b, plus kRintBias, for |a b| < 2^51: a b + 1.5 * 2^52 lies where the
+// doubles are the integers, so the one rounding of the fused multiply-add
+// rounds a b itself (a fixed-point contribution w S is rounded once).
+__device__ inline uint64_t rint_product_biased(double a, double b)
+{
+    return (uint64_t)__double_as_longlong(__builtin_fma(a, b, 6755399441055744.0));
+}
+
 constexpr double kFixLimit = 2251799813685248.0;  // 2^51
 
 // Pair (or wall) force of Eq. (1a)-(1c) with the dashpot reading, in real

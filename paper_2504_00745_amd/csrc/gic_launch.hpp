@@ -126,15 +126,20 @@ struct P2GStore {
 // int32): for node i of axis a, at 4 (n0 + ... + n_{a-1} + i), the bricks
 // along the axis whose tile holds the node, with the node's offset in it.
 void p2g_cover_table(const DevParams &P, int32_t *out);
-// Integrate + P2G of the stepping path (dry, alpha and momentum): the tiles
-// are stored and the grids assembled from them (written, not added to:
-// alpha and mom need no clearing), then the listed granules deposited;
-// esc_next: the counter of the next call, cleared here.
+// Integrate + P2G of the stepping path (dry, alpha and momentum) in two
+// launches: launch_integrate_p2g_store moves the granules and stores each
+// occupied brick's tile (listing the granules whose stencil left it);
+// launch_p2g_assemble then writes the grids from the tiles (written, not
+// added to: alpha and mom need no clearing) and deposits the listed
+// granules.  esc_next: the escape counter of the next call, cleared here.
 template <typename T>
-hipError_t launch_integrate_p2g_assembled(const DevParams &P, int64_t n, int64_t K, double *x, double *v,
-                                          const double *r, const T *Fc, const T *Fd, const int32_t *cb,
-                                          const int32_t *ce, const BrickList &B, int64_t *alpha, int64_t *mom,
-                                          int64_t *err, hipStream_t s, const P2GStore &st, uint32_t *esc_next);
+hipError_t launch_integrate_p2g_store(const DevParams &P, int64_t n, int64_t K, double *x, double *v,
+                                      const double *r, const T *Fc, const T *Fd, const int32_t *cb,
+                                      const int32_t *ce, const BrickList &B, int64_t *err, hipStream_t s,
+                                      const P2GStore &st);
+hipError_t launch_p2g_assemble(const DevParams &P, int64_t n, const double *x, const double *v, const double *r,
+                               const BrickList &B, int64_t *alpha, int64_t *mom, int64_t *err, hipStream_t s,
+                               const P2GStore &st, uint32_t *esc_next);
 
 hipError_t launch_fill_i64(int64_t *a, int64_t len, hipStream_t s);
 hipError_t launch_fill_f64(double *a, int64_t len, hipStream_t s);

@@ -45,21 +45,34 @@ __global__ void __launch_bounds__(256) k_cell_keys(DevParams P, int64_t n, const
         __syncthreads();
         if (threadIdx.x == 0) dpart[blockIdx.x] = fmaxf(fmaxf(s_d2[0], s_d2[1]), fmaxf(s_d2[2], s_d2[3]));
     }
-    if (i >= n) return;
-    double xa[3] = {x[i], x[n + i], x[2 * n + i]};
-    int32_t c[3];
-    bool bad = false, out = false;
-    for (int a = 0; a < 3; ++a) {
-        bad |= !isfinite(xa[a]);
-        out |= !(xa[a] >= 0.0 && xa[a] < P.L[a]);
-        c[a] = cell_coord(xa[a], P.inv_cell, P.nc[a]);
+    bool changed = false;
+    uint32_t k = 0;
+    if (i < n) {
+        double xa[3] = {x[i], x[n + i], x[2 * n + i]};
+        int32_t c[3];
+        bool bad = false, out = false;
+        for (int a = 0; a < 3; ++a) {
+            bad |= !isfinite(xa[a]);
+            out |= !(xa[a] >= 0.0 && xa[a] < P.L[a]);
+            c[a] = cell_coord(xa[a], P.inv_cell, P.nc[a]);
+        }
+        if (bad) raise_error(err, kErrNonFinite, i);
+        else if (out) raise_error(err, kErrDomain, i);
+        k = key_of_cell(P, c[0], c[1], c[2]);
+        key[i] = k;
+        changed = pk && pk[i] != k;
     }
-    if (bad) raise_error(err, kErrNonFinite, i);
-    else if (out) raise_error(err, kErrDomain, i);
-    const uint32_t k = key_of_cell(P, c[0], c[1], c[2]);
-    key[i] = k;
-    if (pk && pk[i] != k) {
-        const int32_t slot = atomicAdd(&ctl[0], 1);
+    if (!pk) return;
+    // changed keys appended with one counter atomic per wave (a moving bed
+    // changes many keys, and atomics on one address serialise)
+    const uint64_t mask = __ballot(changed);
+    if (mask == 0ull) return;
+    const int lane = threadIdx.x & 63;
+    int32_t base = 0;
+    if (lane == __ffsll((unsigned long long)mask) - 1) base = atomicAdd(&ctl[0], (int32_t)__popcll(mask));
+    base = __shfl(base, __ffsll((unsigned long long)mask) - 1);
+    if (changed) {
+        const int32_t slot = base + (int32_t)__popcll(mask & ((1ull << lane) - 1ull));
         if (slot < kChgCap) chg[slot] = ((uint64_t)k << 32) | (uint64_t)i;
     }
 }

@@ -82,7 +82,8 @@ __device__ inline void tile_add(unsigned long long *tile, unsigned long long *gl
 // scaled totals S of each channel in LDS.  Consecutive sorted granules with
 // the same stencil base form a run; they share all 27 nodes.  Phase 2 (a
 // thread per run and channel) walks the run's granules, rounds each outer
-// contribution rint(w S) and sums it in one of 26 register accumulators; the
+// contribution w S (once, from the exact product: one fused multiply-add)
+// and sums it in one of 26 register accumulators; the
 // centre node gets the run's sum of Q = rint(S) minus the 26 sums, which is
 // the sum over the run's granules of each granule's centre remainder (all
 // integer, so the regrouping is exact).  A run then costs 27 LDS atomics per
@@ -288,7 +289,7 @@ __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_e
                         for (int cx = 0; cx < 3; ++cx) {
                             if (cx == 1 && cy == 1 && cz == 1) continue;
                             const double ww = (w[0][cx] * w[1][cy]) * w[2][cz];
-                            acc[(cz * 3 + cy) * 3 + cx] += rint_biased(ww * S);
+                            acc[(cz * 3 + cy) * 3 + cx] += rint_product_biased(ww, S);
                         }
             }
             const uint64_t bias = (uint64_t)(g1 - g0) * kRintBias;
@@ -364,6 +365,9 @@ __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_e
 // once, so the grids need no clearing and see no global atomics.  Nodes that
 // no occupied brick's tile holds get zero.  A workgroup takes x-rows of
 // nodes: the y and z bricks of a row are the same for all its threads.
+// (Giving each XCD a contiguous eighth of the rows, so that the rows reading
+// one tile share an L2, was slower: a bed fills part of the box, so most
+// tile reads then fell to a few XCDs.)
 __global__ void __launch_bounds__(256) k_p2g_assemble(DevParams P, const unsigned long long *__restrict__ tiles,
                                                       const int32_t *__restrict__ slot_of,
                                                       const int32_t *__restrict__ cover,
@@ -427,7 +431,7 @@ __global__ void __launch_bounds__(256) k_p2g_assemble(DevParams P, const unsigne
 
 // The granules whose stencil left their brick's tile (listed by the P2G in
 // STORE mode): each deposited straight to the assembled grids with the
-// rounding of the tile path, rint(w S) on the 26 outer nodes and rint(S)
+// rounding of the tile path, w S rounded once on the 26 outer nodes and rint(S)
 // minus their sum on the centre.  Also clears the other list counter, the
 // one the next step's P2G appends to.
 __global__ void __launch_bounds__(256) k_p2g_escapes(DevParams P, int64_t n, const int32_t *__restrict__ esc,
@@ -480,7 +484,7 @@ __global__ void __launch_bounds__(256) k_p2g_escapes(DevParams P, int64_t n, con
                     for (int cx = 0; cx < 3; ++cx) {
                         if (cx == 1 && cy == 1 && cz == 1) continue;
                         const uint64_t val =
-                            rint_biased(((w[0][cx] * w[1][cy]) * w[2][cz]) * S[c]) - kRintBias;
+                            rint_product_biased((w[0][cx] * w[1][cy]) * w[2][cz], S[c]) - kRintBias;
                         outer += val;
                         if (val) atomicAdd(&g[node_index(P, nd[0][cx], nd[1][cy], nd[2][cz])], val);
                     }
@@ -763,38 +767,43 @@ hipError_t launch_integrate_p2g(const DevParams &P, int64_t n, int64_t K, double
 }
 
 template <typename T>
-hipError_t launch_integrate_p2g_assembled(const DevParams &P, int64_t n, int64_t K, double *x, double *v,
-                                          const double *r, const T *Fc, const T *Fd, const int32_t *cb,
-                                          const int32_t *ce, const BrickList &B, int64_t *alpha, int64_t *mom,
-                                          int64_t *err, hipStream_t s, const P2GStore &st, uint32_t *esc_next)
+hipError_t launch_integrate_p2g_store(const DevParams &P, int64_t n, int64_t K, double *x, double *v,
+                                      const double *r, const T *Fc, const T *Fd, const int32_t *cb,
+                                      const int32_t *ce, const BrickList &B, int64_t *err, hipStream_t s,
+                                      const P2GStore &st)
 {
     const int64_t bricks = K / kBrickCells;
     const int E3 = P.tile * P.tile * P.tile;
     int batch = 512;
     while (batch > 64 && p2g_lds(4, E3, batch) > 49152) batch /= 2;
     const size_t lds = p2g_lds(4, E3, batch);
-    unsigned long long *A = reinterpret_cast<unsigned long long *>(alpha);
-    unsigned long long *M = reinterpret_cast<unsigned long long *>(mom);
     if (n > 0)
         k_p2g_fixed<true, T, true, false, false, true><<<brick_grid(bricks), kP2GThreads, lds, s>>>(
-            P, n, B.list, B.count, batch, x, v, r, Fc, Fd, cb, ce, A, M, err, 0.0, nullptr, st);
+            P, n, B.list, B.count, batch, x, v, r, Fc, Fd, cb, ce, nullptr, nullptr, err, 0.0, nullptr, st);
+    return hipGetLastError();
+}
+
+template hipError_t launch_integrate_p2g_store<float>(const DevParams &, int64_t, int64_t, double *, double *,
+                                                      const double *, const float *, const float *,
+                                                      const int32_t *, const int32_t *, const BrickList &,
+                                                      int64_t *, hipStream_t, const P2GStore &);
+template hipError_t launch_integrate_p2g_store<double>(const DevParams &, int64_t, int64_t, double *, double *,
+                                                       const double *, const double *, const double *,
+                                                       const int32_t *, const int32_t *, const BrickList &,
+                                                       int64_t *, hipStream_t, const P2GStore &);
+
+hipError_t launch_p2g_assemble(const DevParams &P, int64_t n, const double *x, const double *v, const double *r,
+                               const BrickList &B, int64_t *alpha, int64_t *mom, int64_t *err, hipStream_t s,
+                               const P2GStore &st, uint32_t *esc_next)
+{
+    unsigned long long *A = reinterpret_cast<unsigned long long *>(alpha);
+    unsigned long long *M = reinterpret_cast<unsigned long long *>(mom);
     const int64_t rows = (int64_t)P.n[1] * P.n[2];
     k_p2g_assemble<<<(unsigned)(rows < 16384 ? rows : 16384), 256, sizeof(int32_t) * 4 * P.nb[0], s>>>(
         P, st.tiles, B.slot_of, st.cover, A, M);
     k_p2g_escapes<<<256, 256, 0, s>>>(P, n, st.esc, st.esc_n, esc_next, x, v, r, A, M, err);
     return hipGetLastError();
 }
-
-template hipError_t launch_integrate_p2g_assembled<float>(const DevParams &, int64_t, int64_t, double *, double *,
-                                                          const double *, const float *, const float *,
-                                                          const int32_t *, const int32_t *, const BrickList &,
-                                                          int64_t *, int64_t *, int64_t *, hipStream_t,
-                                                          const P2GStore &, uint32_t *);
-template hipError_t launch_integrate_p2g_assembled<double>(const DevParams &, int64_t, int64_t, double *, double *,
-                                                           const double *, const double *, const double *,
-                                                           const int32_t *, const int32_t *, const BrickList &,
-                                                           int64_t *, int64_t *, int64_t *, hipStream_t,
-                                                           const P2GStore &, uint32_t *);
 
 void p2g_cover_table(const DevParams &P, int32_t *out)
 {

@@ -194,7 +194,7 @@ class Context:
         _check(lib().gic_neighbour_builds(self.handle, _stream(), C.byref(b)), "gic_neighbour_builds")
         return int(b.value)
 
-    STAGES = ("sort", "gather", "contact", "exchange", "grid_clear", "integrate_p2g")
+    STAGES = ("sort", "gather", "contact", "exchange", "grid_clear", "integrate_p2g", "assemble")
 
     def stage_timing(self, max_steps):
         """Record stage events in the next max_steps (sub-)steps (0: off)."""
@@ -203,7 +203,7 @@ class Context:
     def stage_times(self):
         """(dict stage -> summed ms, number of steps) since the last call
         (synchronises)."""
-        ms = (C.c_double * 6)()
+        ms = (C.c_double * 7)()
         k = _I32()
         _check(lib().gic_stage_times(self.handle, _stream(), ms, C.byref(k)), "gic_stage_times")
         return dict(zip(self.STAGES, list(ms))), int(k.value)

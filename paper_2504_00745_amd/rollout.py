@@ -11,7 +11,9 @@ kernels of the C ABI (gic_*_vjp): states are checkpointed every `ckpt`
 steps in the forward, each segment is recomputed in the backward and walked
 in reverse.  The granule state is kept in input order; each step sorts, works
 on a sorted copy and scatters the result back, so adjoints are gathered and
-scattered with the same permutations.  PyTorch provides device memory and
+scattered with the same permutations.  Positions and velocities (and their
+adjoints) share one buffer, x then v (6n doubles), so each gather or scatter
+of both is one gic_permute of six components.  PyTorch provides device memory and
 the stream only: the loss cotangent is scaled on the device (gic_scale) and
 the parameters mu and c_drag, kernel arguments, are read from host tensors
 (or numbers), so neither pass reads the device back.
@@ -47,11 +49,13 @@ class Rollout:
         e = lambda *s, dt=f64: torch.empty(*s, dtype=dt, device=dev)
         self.key, self.order = e(n, dt=torch.int32), e(n, dt=torch.int32)
         self.cb, self.ce = e(K, dt=torch.int32), e(K, dt=torch.int32)
-        self.xs, self.vs, self.rs = e(3 * n), e(3 * n), e(n)
+        self.xvs, self.rs = e(6 * n), e(n)  # sorted x then v
+        self.xs, self.vs = self.xvs[:3 * n], self.xvs[3 * n:]
         self.A, self.gA = e(G), e(G)
         self.P = e(3 * G)
         self.uat, self.af, self.Fd, self.Fc = e(3 * n), e(n), e(3 * n), e(3 * n)
-        self.gxs, self.gvs, self.gF = e(3 * n), e(3 * n), e(3 * n)
+        self.gxvs, self.gF = e(6 * n), e(3 * n)  # sorted adjoints of x then v
+        self.gxs, self.gvs = self.gxvs[:3 * n], self.gxvs[3 * n:]
         self.guat, self.gaf, self.gmu_i, self.gcd_i = e(3 * n), e(n), e(n), e(n)
         self.scal = torch.zeros(4, dtype=f64, device=dev)  # L, dL/dmu, dL/dC_d, spare
         self.params = (float(cfg["mu"]), float(cfg["c_drag"]))
@@ -74,26 +78,29 @@ class Rollout:
         gic.gic_g2p(c, xs, self.u, None, self.A, self.uat, self.af)
         gic.gic_drag(c, self.rs, self.vs, self.uat, self.af, self.Fd)
 
-    def step(self, x, v, x_out, v_out):
-        """One step from (x, v) (input order) into (x_out, v_out)."""
+    def _split(self, xv):
+        return xv[:3 * self.n], xv[3 * self.n:]
+
+    def step(self, xv, xv_out):
+        """One step from the state xv = (x, v) (input order) into xv_out."""
         c = self.ctx
-        self._sorted(x, v)
+        self._sorted(*self._split(xv))
         self._forces()
         gic.gic_contact_forces(c, self.xs.view(3, -1), self.vs, self.rs, self.cb, self.ce, self.Fc)
         gic.gic_integrate(c, self.rs, self.Fc, self.Fd, self.xs, self.vs)
-        gic.gic_permute(c, self.order, self.xs, x_out, 3, True)
-        gic.gic_permute(c, self.order, self.vs, v_out, 3, True)
+        gic.gic_permute(c, self.order, self.xvs, xv_out, 6, True)
 
-    def loss(self, x, v):
-        """L = sum |P|^2 of the momentum grid of (x, v), into self.scal[0]."""
+    def loss(self, xv):
+        """L = sum |P|^2 of the momentum grid of the state xv, into self.scal[0]."""
         c = self.ctx
-        self._sorted(x, v)
+        self._sorted(*self._split(xv))
         gic.gic_p2g_real(c, self.xs.view(3, -1), self.vs, self.rs, self.cb, self.ce, None, self.P)
         gic.gic_sum(c, self.P, self.scal[0:1], b=self.P)
 
     def forward(self, x0, v0):
         """Runs the rollout; returns the loss tensor (1,), the checkpoints
-        and the final state (tensors of their own)."""
+        and the final state (states (x, v) as one tensor of 6n, of their
+        own)."""
         if not self.graph:
             return self._forward(x0, v0)
         x0, v0 = x0.detach().reshape(-1), v0.detach().reshape(-1)
@@ -105,7 +112,7 @@ class Rollout:
         sx.copy_(x0)
         sv.copy_(v0)
         g.replay()
-        return L.clone(), [(a.clone(), b.clone()) for a, b in ckpts], (final[0].clone(), final[1].clone())
+        return L.clone(), [a.clone() for a in ckpts], final.clone()
 
     @staticmethod
     def _record(fn):
@@ -122,16 +129,16 @@ class Rollout:
         return g, out
 
     def _forward(self, x0, v0):
-        x, v = x0.contiguous().clone().view(-1), v0.contiguous().clone().view(-1)
-        x2, v2 = torch.empty_like(x), torch.empty_like(v)
+        xv = torch.cat([x0.reshape(-1), v0.reshape(-1)])
+        xv2 = torch.empty_like(xv)
         ckpts = []
         for s in range(self.steps):
             if s % self.ckpt == 0:
-                ckpts.append((x.clone(), v.clone()))
-            self.step(x, v, x2, v2)
-            x, x2, v, v2 = x2, x, v2, v
-        self.loss(x, v)
-        return self.scal[0:1].clone(), ckpts, (x, v)
+                ckpts.append(xv.clone())
+            self.step(xv, xv2)
+            xv, xv2 = xv2, xv
+        self.loss(xv)
+        return self.scal[0:1].clone(), ckpts, xv
 
     # ---- reverse pass ----------------------------------------------------
     def backward(self, ckpts, final, gL):
@@ -140,17 +147,15 @@ class Rollout:
             return self._backward(ckpts, final, gL)
         gL = gL.detach().reshape(1).to(torch.float64)
         if self._bwd is None or self._bwd[0] != self.params or len(self._bwd[2][0]) != len(ckpts):
-            sc = [(a.clone(), b.clone()) for a, b in ckpts]
-            sf = (final[0].clone(), final[1].clone())
+            sc = [a.clone() for a in ckpts]
+            sf = final.clone()
             sg = gL.clone()
             out = self._record(lambda: self._backward(sc, sf, sg))
             self._bwd = (self.params, out[0], (sc, sf, sg), out[1])
         _, g, (sc, sf, sg), (gv, gmu, gcd) = self._bwd
-        for (a, b), (c, d) in zip(sc, ckpts):
+        for a, c in zip(sc, ckpts):
             a.copy_(c)
-            b.copy_(d)
-        sf[0].copy_(final[0])
-        sf[1].copy_(final[1])
+        sf.copy_(final)
         sg.copy_(gL)
         g.replay()
         return gv.clone(), gmu.clone(), gcd.clone()
@@ -158,36 +163,30 @@ class Rollout:
     def _backward(self, ckpts, final, gL):
         c = self.ctx
         n = self.n
-        x, v = final
-        gx = torch.zeros(3 * n, dtype=torch.float64, device="cuda")
-        gv = torch.zeros_like(gx)
+        gxv = torch.zeros(6 * n, dtype=torch.float64, device="cuda")  # adjoint of (x, v), input order
         self.scal[1:3].zero_()
         # L = sum P^2  ->  dL/dP = 2 gL P, gL a device scalar
-        self.loss(x, v)
+        self.loss(final)
         gP = torch.empty_like(self.P)
         gic.gic_scale(c, self.P, gL.reshape(1).to(torch.float64), 2.0, gP)
-        self.gxs.zero_()
-        self.gvs.zero_()
+        self.gxvs.zero_()
         gic.gic_p2g_vjp(c, self.xs.view(3, -1), self.vs, self.rs, None, gP, self.gxs, self.gvs)
-        gic.gic_permute(c, self.order, self.gxs, gx, 3, True)
-        gic.gic_permute(c, self.order, self.gvs, gv, 3, True)
+        gic.gic_permute(c, self.order, self.gxvs, gxv, 6, True)
         nseg = len(ckpts)
         for seg in reversed(range(nseg)):
             s0 = seg * self.ckpt
             s1 = min(s0 + self.ckpt, self.steps)
             xs_list = [ckpts[seg]]
-            xa, va = ckpts[seg][0].clone(), ckpts[seg][1].clone()
+            xa = ckpts[seg].clone()
             for s in range(s0, s1 - 1):
-                xb, vb = torch.empty_like(xa), torch.empty_like(va)
-                self.step(xa, va, xb, vb)
-                xs_list.append((xb, vb))
-                xa, va = xb, vb
+                xb = torch.empty_like(xa)
+                self.step(xa, xb)
+                xs_list.append(xb)
+                xa = xb
             for s in reversed(range(s0, s1)):
-                xn, vn = xs_list[s - s0]
-                self._sorted(xn, vn)
+                self._sorted(*self._split(xs_list[s - s0]))
                 self._forces()
-                gic.gic_permute(c, self.order, gx, self.gxs, 3, False)
-                gic.gic_permute(c, self.order, gv, self.gvs, 3, False)
+                gic.gic_permute(c, self.order, gxv, self.gxvs, 6, False)
                 xs = self.xs.view(3, -1)
                 gic.gic_integrate_vjp(c, self.rs, self.gxs, self.gvs, self.gF)
                 gic.gic_contact_forces_vjp(c, xs, self.vs, self.rs, self.cb, self.ce, self.gF, self.gxs, self.gvs,
@@ -198,9 +197,8 @@ class Rollout:
                 gic.gic_sum(c, self.gcd_i, self.scal[2:3], accumulate=True)
                 gic.gic_g2p_vjp(c, xs, self.u, self.A, self.guat, self.gaf, self.cb, self.ce, self.gxs, self.gA)
                 gic.gic_p2g_vjp(c, xs, self.vs, self.rs, self.gA, None, self.gxs, self.gvs)
-                gic.gic_permute(c, self.order, self.gxs, gx, 3, True)
-                gic.gic_permute(c, self.order, self.gvs, gv, 3, True)
-        return gv.view(3, n), self.scal[1:2].clone(), self.scal[2:3].clone()
+                gic.gic_permute(c, self.order, self.gxvs, gxv, 6, True)
+        return gxv[3 * n:].view(3, n), self.scal[1:2].clone(), self.scal[2:3].clone()
 
 
 class GICRollout(torch.autograd.Function):
