@@ -208,6 +208,15 @@ gic_status gic_get_error(gic_ctx *ctx, void *stream, int32_t *code, int64_t *ind
 gic_status gic_sort_cells(gic_ctx *ctx, int64_t n, const double *x, uint32_t *key, int32_t *order,
                           int32_t *cell_begin, int32_t *cell_end, void *stream);
 
+/* Build the context's list of occupied bricks (the schedule of the brick
+ * kernels) for the cell tables cell_begin, cell_end (K each, from
+ * gic_sort_cells), and keep it: the calls that follow and are given these
+ * same tables use it instead of building their own, until the next
+ * gic_sort_cells, stepping call or gic_brick_list.  The caller must not
+ * change the tables' contents meanwhile.  Without this call every brick
+ * kernel call builds the list (three small kernels) itself. */
+gic_status gic_brick_list(gic_ctx *ctx, const int32_t *cell_begin, const int32_t *cell_end, void *stream);
+
 /* Gather granule arrays into sorted order: out[q] = in[order[q]] for x, v
  * (3n each) and r, id (n each).  id / id_out may both be NULL.  Outputs must
  * not alias inputs. */
@@ -227,9 +236,11 @@ gic_status gic_reorder(gic_ctx *ctx, int64_t n, const int32_t *order, const doub
  * form); the pair force arithmetic and the per-granule sum are in the
  * form's real type, over the touching partners in the order of their cells
  * (z, then y, then x) and of their sorted positions inside a cell, then the
- * walls.  The call builds the context's neighbour list (every granule closer
- * than r_i + r_j + skin, in that order; see gic_step) and evaluates the
- * forces from it.
+ * walls.  Without pair_ids the forces come straight from the cells (the
+ * brick's 6x6x6-cell shell in LDS); with pair_ids the call builds the
+ * context's neighbour list (every granule closer than r_i + r_j + skin, in
+ * that order; see gic_step) and evaluates the forces from it.  Both give
+ * the same bits.
  *   x, v, r     sorted order (see Conventions).
  *   f_contact   out, 3n real: force per granule [N].
  *   n_contacts  out (optional, NULL = skip), n: touching partners + walls.

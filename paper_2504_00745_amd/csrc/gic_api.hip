@@ -41,6 +41,11 @@ struct gic_ctx {
     // cleared by any other call that sorts or builds a brick list).
     bool rng_ok;
     const int32_t *rng_cb, *rng_ce;
+    // gic_brick_list: the brick list built for the cell tables bl_cb, bl_ce,
+    // reused by the calls given those tables until the next sort, stepping
+    // call or brick list build
+    bool bl_pin;
+    const int32_t *bl_cb, *bl_ce;
     // stage timing of gic_step / gic_sand_step (gic_stage_timing): events
     // recorded on the step's stream between its stages, kStageEvents per step
     int tm_cap, tm_used;
@@ -217,6 +222,8 @@ constexpr int64_t kSumNoallocMax = (int64_t)kSumParts << 20;
 hipError_t brick_list(gic_ctx *c, const int32_t *cb, const int32_t *ce, hipStream_t s)
 {
     if (c->in_step) return hipSuccess;
+    if (c->bl_pin && c->bl_cb == cb && c->bl_ce == ce) return hipSuccess;  // kept by gic_brick_list
+    c->bl_pin = false;
     c->rng_ok = false;  // the brick list is now that of these tables
     return launch_brick_list(cb, ce, c->bricks, s);
 }
@@ -229,6 +236,7 @@ hipError_t step_sort(gic_ctx *c, int64_t n, const double *x, uint32_t *key, int3
 {
     const int keep = c->rng_ok && c->rng_cb == cb && c->rng_ce == ce && c->sort.last_n == n ? 1 : 0;
     c->rng_ok = false;
+    c->bl_pin = false;
     hipError_t e = launch_sort_cells(c->dp, n, x, key, order, cb, ce, c->K, c->sort, c->err, s, &c->nl, force, keep);
     if (e == hipSuccess && n > 0) e = launch_brick_list(cb, ce, c->bricks, s, keep ? c->sort.ctl : nullptr);
     if (e == hipSuccess) {
@@ -524,8 +532,23 @@ gic_status gic_sort_cells(gic_ctx *c, int64_t n, const double *x, uint32_t *key,
     if (!n_ok(c, n) || !cell_begin || !cell_end || (n > 0 && (!x || !key || !order))) return GIC_E_ARG;
     c->nl_n = -1;  // the next gic_step cannot rely on this sort's keys for its neighbour list
     c->rng_ok = false;
+    c->bl_pin = false;
     return hip_status(launch_sort_cells(c->dp, n, x, key, order, cell_begin, cell_end, c->K, c->sort, c->err,
                                         (hipStream_t)stream));
+}
+
+gic_status gic_brick_list(gic_ctx *c, const int32_t *cell_begin, const int32_t *cell_end, void *stream)
+{
+    if (!c || !cell_begin || !cell_end) return GIC_E_ARG;
+    c->bl_pin = false;
+    const hipError_t e = brick_list(c, cell_begin, cell_end, (hipStream_t)stream);
+    if (e != hipSuccess) return GIC_E_HIP;
+    if (!c->in_step) {
+        c->bl_pin = true;
+        c->bl_cb = cell_begin;
+        c->bl_ce = cell_end;
+    }
+    return GIC_OK;
 }
 
 gic_status gic_reorder(gic_ctx *c, int64_t n, const int32_t *order, const double *x, const double *v,
@@ -545,10 +568,11 @@ static gic_status contact_impl(gic_ctx *c, int64_t n, const double *x, const dou
                                const int32_t *cell_begin, const int32_t *cell_end, void *f_contact,
                                int32_t *n_contacts, int32_t *pair_ids, int32_t pair_cap, int force, hipStream_t s)
 {
-    if (!pair_ids && !(c->nl.thr2 > 0.0f)) {
-        // no skin (cells of exactly 2 r_max): a list would be rebuilt every
-        // step, so the forces come straight from the cells (same partner
-        // order, same bits)
+    if (!pair_ids && (!c->in_step || !(c->nl.thr2 > 0.0f))) {
+        // a list that would serve this call only (a stage call outside the
+        // stepping path, or no skin: cells of exactly 2 r_max, so the
+        // stepping path would rebuild it every step): the forces come
+        // straight from the cells (same partner order, same bits)
         if (fp32(c))
             return hip_status(launch_contact<float>(c->dp, n, x, v, r, cell_begin, cell_end, c->bricks, nullptr,
                                                     nullptr, (float *)f_contact, n_contacts, c->err, s));

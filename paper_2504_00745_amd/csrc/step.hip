@@ -80,6 +80,23 @@ __global__ void __launch_bounds__(256) k_gather_g2p_drag(DevParams P, int64_t n,
     int32_t o[3];
     tile_origin(P, b, o);
     const int64_t G = P.G;
+    // the first granule's state is fetched before the tile, so the two
+    // loads' latencies overlap
+    int64_t s = -1;
+    double xa[3] = {0.0, 0.0, 0.0}, va[3] = {0.0, 0.0, 0.0}, rq = 0.0;
+    int32_t idq = 0;
+    auto fetch = [&](int64_t q) {
+        s = order[q];
+        if ((uint64_t)s >= (uint64_t)n) return;
+        for (int a = 0; a < 3; ++a) {
+            xa[a] = x[a * n + s];
+            va[a] = v[a * n + s];
+        }
+        rq = r[s];
+        if (ido) idq = id[s];
+    };
+    const int64_t q0 = gb + threadIdx.x;
+    if (q0 < ge) fetch(q0);
     for (int k = threadIdx.x; k < E3; k += 256) {
         const int32_t i = o[0] + k % E, j = o[1] + (k / E) % E, l = o[2] + k / (E * E);
         if (i < 0 || j < 0 || l < 0 || i >= P.n[0] || j >= P.n[1] || l >= P.n[2]) continue;  // never referenced
@@ -92,18 +109,15 @@ __global__ void __launch_bounds__(256) k_gather_g2p_drag(DevParams P, int64_t n,
         su[k] = q;
     }
     __syncthreads();
-    for (int64_t q = gb + threadIdx.x; q < ge; q += 256) {
-        const int64_t s = order[q];
+    for (int64_t q = q0; q < ge; q += 256) {
+        if (q != q0) fetch(q);
         if ((uint64_t)s >= (uint64_t)n) continue;  // not a permutation of [0, n): position q left untouched
-        const double xa[3] = {x[s], x[n + s], x[2 * n + s]};
-        const double va[3] = {v[s], v[n + s], v[2 * n + s]};
-        const double rq = r[s];
         for (int a = 0; a < 3; ++a) {
             xo[a * n + q] = xa[a];
             vo[a * n + q] = va[a];
         }
         ro[q] = rq;
-        if (ido) ido[q] = id[s];
+        if (ido) ido[q] = idq;
         Stencil st;
         stencil_of(P, xa, st);
         // tile offsets of the stencil's nodes; every node inside the tile is

@@ -64,6 +64,7 @@ def lib():
             "gic_stage_timing": (C.c_int, [_V, _I32]),
             "gic_stage_times": (C.c_int, [_V, _V, C.POINTER(C.c_double), C.POINTER(_I32)]),
             "gic_sort_cells": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V]),
+            "gic_brick_list": (C.c_int, [_V, _V, _V, _V]),
             "gic_reorder": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V, _V, _V, _V]),
             "gic_contact_forces": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V, _V, _I32, _V]),
             "gic_contact_capillary_forces": (C.c_int, [_V, _I64, _V, _V, _V, _V, _V, _V, _V, _V, _V, _V]),
@@ -225,6 +226,13 @@ def gic_sort_cells(ctx, x, key, order, cell_begin, cell_end):
     _check(lib().gic_sort_cells(ctx.handle, n, _ptr(x, torch.float64, 3 * n, "x"), _ptr(key, torch.int32, n, "key"),
                                 _ptr(order, torch.int32, n, "order"), _ptr(cell_begin, torch.int32, ctx.K, "cell_begin"),
                                 _ptr(cell_end, torch.int32, ctx.K, "cell_end"), _stream()), "gic_sort_cells")
+
+
+def gic_brick_list(ctx, cell_begin, cell_end):
+    """Build and keep the brick schedule of these cell tables for the calls
+    that follow (until the next sort or stepping call)."""
+    _check(lib().gic_brick_list(ctx.handle, _ptr(cell_begin, torch.int32, ctx.K, "cell_begin"),
+                                _ptr(cell_end, torch.int32, ctx.K, "cell_end"), _stream()), "gic_brick_list")
 
 
 def gic_reorder(ctx, order, x, v, r, id_, x_out, v_out, r_out, id_out):

@@ -69,6 +69,7 @@ class Rollout:
         """Sort by cell, gather x, v, r into sorted order (one kernel)."""
         c = self.ctx
         gic.gic_sort_cells(c, x.view(3, -1), self.key, self.order, self.cb, self.ce)
+        gic.gic_brick_list(c, self.cb, self.ce)  # one brick schedule for the step's brick kernels
         gic.gic_reorder(c, self.order, x.view(3, -1), v, self.r, None, self.xs, self.vs, self.rs, None)
 
     def _forces(self):

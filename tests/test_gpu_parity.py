@@ -395,3 +395,68 @@ def test_sort_incremental_path(G, orc, moved):
     other = wl.make("c2", n_override=30001, seed=77)["x"]
     sort_and_check(other)
     assert ctx.error() == (0, -1)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_kept_brick_list_gives_the_same_bits(G, prec):
+    """gic_brick_list: brick kernels that reuse the kept schedule (fixed and
+    unquantised P2G, contact with and without the pair output, the fused
+    gather) give the bits of the same calls building their own, on a
+    polydisperse bed with a ragged tail; a new sort drops the kept list."""
+    import torch
+    from paper_2504_00745_amd import gic
+    G.say(f"[kept brick list] c2s {prec}")
+    d = _make("c2s")
+    cfg, x, v, r, u = d["params"], d["x"], d["v"], d["r"], d["u"]
+    n = x.shape[1]
+    X, V, R = G.dev(x.reshape(-1)), G.dev(v.reshape(-1)), G.dev(r)
+    ID = torch.arange(n, dtype=torch.int32, device="cuda")
+
+    def run(keep):
+        ctx = gic.Context(cfg, n, prec, float(r.max()))
+        real = ctx.real
+        key = torch.empty(n, dtype=torch.int32, device="cuda")
+        order = torch.empty(n, dtype=torch.int32, device="cuda")
+        cb = torch.empty(ctx.K, dtype=torch.int32, device="cuda")
+        ce = torch.empty(ctx.K, dtype=torch.int32, device="cuda")
+        gic.gic_sort_cells(ctx, X.view(3, n), key, order, cb, ce)
+        if keep:
+            gic.gic_brick_list(ctx, cb, ce)
+        e = lambda like: torch.empty_like(like)
+        Xs, Vs, Rs, IDs = e(X), e(V), e(R), e(ID)
+        gic.gic_reorder(ctx, order, X.view(3, n), V, R, ID, Xs, Vs, Rs, IDs)
+        A = torch.zeros(ctx.G, dtype=torch.int64, device="cuda")
+        M = torch.zeros(3 * ctx.G, dtype=torch.int64, device="cuda")
+        gic.gic_p2g(ctx, Xs.view(3, n), Vs, Rs, cb, ce, A, M)
+        Fc = torch.empty(3 * n, dtype=real, device="cuda")
+        gic.gic_contact_forces(ctx, Xs.view(3, n), Vs, Rs, cb, ce, Fc)
+        Fc2 = torch.empty(3 * n, dtype=real, device="cuda")
+        P = torch.empty(8 * n, dtype=torch.int32, device="cuda")
+        gic.gic_contact_forces(ctx, Xs.view(3, n), Vs, Rs, cb, ce, Fc2, pair_ids=P)
+        U = G.dev(u.reshape(-1), real)
+        X2, V2, R2, ID2 = e(X), e(V), e(R), e(ID)
+        Fd = torch.empty(3 * n, dtype=real, device="cuda")
+        gic.gic_gather_g2p_drag(ctx, order, X.view(3, n), V, R, ID, X2, V2, R2, ID2, U, A, cb, ce, Fd)
+        out = [A, M, Fc, Fc2, P, Fd, X2]
+        if prec == "fp64":
+            Ar = torch.empty(ctx.G, dtype=torch.float64, device="cuda")
+            Mr = torch.empty(3 * ctx.G, dtype=torch.float64, device="cuda")
+            gic.gic_p2g_real(ctx, Xs.view(3, n), Vs, Rs, cb, ce, Ar, Mr)
+            out += [Ar, Mr]
+        # a new sort of other positions drops the kept list: these calls
+        # then build the list of the new tables
+        Xb = X.clone()
+        Xb.view(3, n)[0] += 0.37 * cfg["cell"]
+        Xb.view(3, n)[0].clamp_(max=cfg["n"][0] * cfg["dx"] * 0.999)
+        gic.gic_sort_cells(ctx, Xb.view(3, n), key, order, cb, ce)
+        Xbs, Vbs, Rbs = e(X), e(V), e(R)
+        gic.gic_reorder(ctx, order, Xb.view(3, n), V, R, None, Xbs, Vbs, Rbs, None)
+        Ab = torch.zeros(ctx.G, dtype=torch.int64, device="cuda")
+        gic.gic_p2g(ctx, Xbs.view(3, n), Vbs, Rbs, cb, ce, Ab, None)
+        out.append(Ab)
+        torch.cuda.synchronize()
+        assert ctx.error() == (0, -1)
+        return out
+
+    for a, b in zip(run(True), run(False)):
+        assert torch.equal(a, b)
