@@ -234,9 +234,9 @@ gic_status gic_reorder(gic_ctx *ctx, int64_t n, const int32_t *order, const doub
  * overlap is R - d in double (plain form) or (R^2 - d^2) / (R + d) with the
  * cancelling difference R^2 - d^2 in double and the quotient in float (FP32
  * form); the pair force arithmetic and the per-granule sum are in the
- * form's real type, over the touching partners in the order of their cells
- * (z, then y, then x) and of their sorted positions inside a cell, then the
- * walls.  Without pair_ids the forces come straight from the cells (the
+ * form's real type, over the touching partners in canonical order (by
+ * distance |j - q| in sorted order from the granule q, the lower position j
+ * first at equal distance), then the walls.  Without pair_ids the forces come straight from the cells (the
  * brick's 6x6x6-cell shell in LDS); with pair_ids the call builds the
  * context's neighbour list (every granule closer than r_i + r_j + skin, in
  * that order; see gic_step) and evaluates the forces from it.  Both give
@@ -395,7 +395,7 @@ gic_status gic_integrate_p2g_wet(gic_ctx *ctx, int64_t n, double *x, double *v, 
  * granule has moved by skin / 2 since the list was built (measured on the
  * device from the positions of the build); otherwise the step rebuilds it.
  * The exact contact test runs on every listed pair every step, and a
- * granule's forces are summed over its touching partners in cell order
+ * granule's forces are summed over its touching partners in canonical order
  * either way, so f_contact is the same bits as gic_contact_forces on the
  * sorted state.  Calls of gic_sort_cells or gic_contact_forces on the
  * context, gic_set_params, or radii changed by the caller between steps:

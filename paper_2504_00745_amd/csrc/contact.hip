@@ -8,8 +8,9 @@
 // which runs the exact double test of Sec. 3.1 on every listed partner each
 // step.  The stepping path builds the list only when the sorted order
 // changed or a granule moved by skin / 2 since the last build; a granule's
-// force sum runs over its touching partners in cell order either way, so the
-// forces do not depend on when the list was built.  The capillary
+// force sum runs over its touching partners in one canonical order
+// (canon_before: by distance in sorted order) either way, so the forces do
+// not depend on when the list was built, nor on which kernel summed them.  The capillary
 // instantiation of k_contact_lds (candidates and forces in one brick kernel)
 // serves wet beds.
 //
@@ -67,6 +68,84 @@ __device__ inline void for_each_run(const DevParams &P, int64_t n, const int32_t
                 cx = cend + 1;
             }
         }
+}
+
+// Canonical order of a granule's partners, in which every kernel sums its
+// pair forces: by distance in sorted order from the granule, |j - q|, the
+// lower position first at equal distance.  It depends on the sorted order
+// only, so lists built at different steps of one order give the same sums;
+// and in a regular packing the partners at one place of neighbouring
+// granules' lists lie in the same direction, so their state loads coalesce
+// and the in-workgroup partners come first.
+__device__ inline bool canon_before(int64_t a, int64_t b, int64_t q)
+{
+    const int64_t da = a > q ? a - q : q - a, db = b > q ? b - q : q - b;
+    return da < db || (da == db && a < b);
+}
+
+// Insertion sort into canonical order of the m entries of granule q at
+// a[0], a[stride], ... (an LDS column or a list column); j_of maps an entry
+// to its sorted position.
+template <typename E, typename J>
+__device__ inline void canon_sort(E *a, int64_t stride, int m, int64_t q, J &&j_of)
+{
+    for (int i = 1; i < m; ++i) {
+        const E e = a[i * stride];
+        const int64_t je = j_of(e);
+        int k = i - 1;
+        while (k >= 0) {
+            const E f = a[k * stride];
+            if (!canon_before(je, j_of(f), q)) break;
+            a[(k + 1) * stride] = f;
+            --k;
+        }
+        a[(k + 1) * stride] = e;
+    }
+}
+
+// Every granule in the cell runs of q's search box (cells lo..hi), q
+// itself excepted, visited once in canonical order.  For the rare granules
+// whose partners overflow a list: each step rescans the runs, taking in
+// each run the nearest position beyond the last distance.
+template <typename F>
+__device__ inline void for_each_canonical(const DevParams &P, int64_t n, int64_t q, const int32_t lo[3],
+                                          const int32_t hi[3], const int32_t *__restrict__ cb,
+                                          const int32_t *__restrict__ ce, F &&f)
+{
+    int64_t d = 0;      // distance of the last granule visited (q itself at 0)
+    bool upper = true;  // q + d already considered
+    for (;;) {
+        if (!upper) {  // q - d was visited: q + d next, if it is a candidate
+            upper = true;
+            const int64_t j = q + d;
+            bool cand = false;
+            for_each_run(P, n, lo, hi, cb, ce, [&](int32_t jb, int32_t je) { cand |= j >= jb && j < je; });
+            if (cand) {
+                f((int32_t)j);
+                continue;
+            }
+        }
+        // the least distance beyond d with a candidate, the lower side first
+        int64_t best = INT64_MAX;
+        bool low = false;
+        for_each_run(P, n, lo, hi, cb, ce, [&](int32_t jb, int32_t je) {
+            if (je <= jb) return;
+            const int64_t jl = (int64_t)je - 1 < q - d - 1 ? (int64_t)je - 1 : q - d - 1;
+            if (jl >= jb && (q - jl < best || (q - jl == best && !low))) {
+                best = q - jl;
+                low = true;
+            }
+            const int64_t ju = (int64_t)jb > q + d + 1 ? (int64_t)jb : q + d + 1;
+            if (ju < je && ju - q < best) {
+                best = ju - q;
+                low = false;
+            }
+        });
+        if (best == INT64_MAX) return;
+        d = best;
+        upper = !low;
+        f((int32_t)(low ? q - d : q + d));
+    }
 }
 
 constexpr int kUnroll = 4;
@@ -198,10 +277,11 @@ __device__ inline int exact_pair(const DevParams &P, const double xi[3], const d
 // Contact force on granule q reading its candidates from global memory, in
 // two passes: the candidate pass runs only the double contact test and lists
 // touching partners in `plist` (kMaxPartners x 256 ints in LDS, column tid);
-// the force pass then evaluates the pair law for the listed partners.  Lanes
-// of a wave touch partners at different candidate positions, so evaluating
-// forces inside the candidate loop would run the expensive branch for almost
-// every candidate.
+// the force pass then evaluates the pair law for the listed partners in
+// canonical order.  Lanes of a wave touch partners at different candidate
+// positions, so evaluating forces inside the candidate loop would run the
+// expensive branch for almost every candidate.  A granule with more
+// partners than the list holds walks its candidates in canonical order.
 template <typename T, bool CAP>
 __device__ inline void contact_global(const DevParams &P, int64_t n, const double *__restrict__ x,
                                       const double *__restrict__ v, const double *__restrict__ r,
@@ -240,18 +320,21 @@ __device__ inline void contact_global(const DevParams &P, int64_t n, const doubl
                 double d2;
                 if (!touching(xi[0] - cx[u], xi[1] - cy[u], xi[2] - cz[u], ri + cr[u] + reach, d2) || d2 == 0.0)
                     continue;
-                if (cnt < kMaxPartners)
-                    plist[cnt * 256 + tid] = j;
-                else  // rare: long partner list
-                    nc += exact_pair<T, CAP>(P, xi, vi, ri, mi, q, j, fetch_partner(n, x, v, r, j), sri, sr, held, acc);
+                if (cnt < kMaxPartners) plist[cnt * 256 + tid] = j;
                 ++cnt;
             }
         }
     });
-    const int listed = cnt < kMaxPartners ? cnt : kMaxPartners;
-    for (int k = 0; k < listed; ++k) {
-        const int32_t j = plist[k * 256 + tid];
-        nc += exact_pair<T, CAP>(P, xi, vi, ri, mi, q, j, fetch_partner(n, x, v, r, j), sri, sr, held, acc);
+    if (cnt <= kMaxPartners) {
+        canon_sort(plist + tid, 256, cnt, q, [](int32_t j) { return (int64_t)j; });
+        for (int k = 0; k < cnt; ++k) {
+            const int32_t j = plist[k * 256 + tid];
+            nc += exact_pair<T, CAP>(P, xi, vi, ri, mi, q, j, fetch_partner(n, x, v, r, j), sri, sr, held, acc);
+        }
+    } else {  // rare: more partners than the list holds
+        for_each_canonical(P, n, q, lo, hi, cb, ce, [&](int32_t j) {
+            nc += exact_pair<T, CAP>(P, xi, vi, ri, mi, q, j, fetch_partner(n, x, v, r, j), sri, sr, held, acc);
+        });
     }
     add_walls<T>(P, xi, vi, ri, mi, acc, nc);
     F[q] = acc[0];
@@ -296,6 +379,69 @@ constexpr int kLdsPartners = 10;
 constexpr int kCand = 4;  // candidates read from LDS before they are tested
 constexpr int kPad = 1;   // empty slots after each cell
 constexpr int kCopyRounds = 8;  // shell copy rounds of 256 slots: covers every cap <= 2047
+
+// Fixed compare-exchange networks sorting 4, 6, 8 and 10 entries (5, 12,
+// 19 and 29 comparators, the least known for those sizes).
+constexpr int kNet4[5][2] = {{0, 2}, {1, 3}, {0, 1}, {2, 3}, {1, 2}};
+constexpr int kNet6[12][2] = {{0, 5}, {1, 3}, {2, 4}, {1, 2}, {3, 4}, {0, 3},
+                              {2, 5}, {0, 1}, {2, 3}, {4, 5}, {1, 2}, {3, 4}};
+constexpr int kNet8[19][2] = {{0, 2}, {1, 3}, {4, 6}, {5, 7}, {0, 4}, {1, 5}, {2, 6}, {3, 7}, {0, 1}, {2, 3},
+                              {4, 5}, {6, 7}, {2, 4}, {3, 5}, {1, 4}, {3, 6}, {1, 2}, {3, 4}, {5, 6}};
+constexpr int kNet10[29][2] = {{0, 8}, {1, 9}, {2, 7}, {3, 5}, {4, 6}, {0, 2}, {1, 4}, {5, 8}, {7, 9}, {0, 3},
+                               {2, 4}, {5, 7}, {6, 9}, {0, 1}, {3, 6}, {8, 9}, {1, 5}, {2, 3}, {4, 8}, {6, 7},
+                               {1, 2}, {3, 5}, {4, 6}, {7, 8}, {2, 3}, {4, 5}, {6, 7}, {3, 4}, {5, 6}};
+
+template <int C>
+__device__ inline void run_net(const int (&net)[C][2], uint32_t key[], uint32_t sl[])
+{
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int a = net[c][0], b = net[c][1];
+        const bool sw = key[b] < key[a];
+        const uint32_t ka = sw ? key[b] : key[a], kb = sw ? key[a] : key[b];
+        const uint32_t sa = sw ? sl[b] : sl[a], sb = sw ? sl[a] : sl[b];
+        key[a] = ka;
+        key[b] = kb;
+        sl[a] = sa;
+        sl[b] = sb;
+    }
+}
+
+// The listed slots of granule q (plist column, m <= kLdsPartners entries)
+// into canonical order: a 32-bit key per entry, 2 |j - q| plus 1 above q
+// (a distance holds at most the two positions q - d and q + d, so the key
+// orders by distance, the lower position first), sorted in registers by the
+// smallest network that covers the longest list in the wave (none when no
+// list has two entries), written back.
+template <typename J>
+__device__ inline void lds_list_canonical(uint16_t *col, int m, int64_t q, J &&j_of)
+{
+    static_assert(kLdsPartners == 10, "the networks sort up to ten entries");
+    if (__ballot(m >= 2) == 0ull) return;
+    uint32_t key[kLdsPartners];
+    uint32_t sl[kLdsPartners];
+#pragma unroll
+    for (int i = 0; i < kLdsPartners; ++i) {
+        key[i] = 0xFFFFFFFFu;  // past the last entry: sorts last
+        sl[i] = 0;
+        if (i < m) {
+            sl[i] = col[i * 256];
+            const int64_t j = j_of((int)sl[i]);
+            key[i] = j > q ? (uint32_t)(2 * (j - q) + 1) : (uint32_t)(2 * (q - j));
+        }
+    }
+    if (__ballot(m > 8) != 0ull)
+        run_net(kNet10, key, sl);
+    else if (__ballot(m > 6) != 0ull)
+        run_net(kNet8, key, sl);
+    else if (__ballot(m > 4) != 0ull)
+        run_net(kNet6, key, sl);
+    else
+        run_net(kNet4, key, sl);
+#pragma unroll
+    for (int i = 0; i < kLdsPartners; ++i)
+        if (i < m) col[i * 256] = (uint16_t)sl[i];
+}
 
 // Candidate test of the LDS pass (see above): p = (p, Q) of a slot,
 // m = -2 a, thr = M - b_i.
@@ -426,10 +572,9 @@ k_contact_lds(DevParams P, int64_t n, const int32_t *__restrict__ bl,
     }
     __syncthreads();
     const float M = (float)(P.cell * P.cell * (1.0 / 4096.0));
-    // ---- granules of the brick, one thread each: partners are taken in
-    // slot order (cells z, y, x; positions inside a cell), the order of the
-    // dry contact's neighbour list, so a bed without bridges gives the dry
-    // contact's bits
+    // ---- granules of the brick, one thread each: the listed partners are
+    // evaluated in canonical order, the order of the dry contact's
+    // neighbour list, so a bed without bridges gives the dry contact's bits
     constexpr int L = 1;
     constexpr int sub = 0;
     for (int64_t qb = gb; qb < ge; qb += 256) {  // same trip count in every lane
@@ -498,35 +643,35 @@ k_contact_lds(DevParams P, int64_t n, const int32_t *__restrict__ bl,
                         }
                     }
                 });
+                auto global_of = [&](int k) { const int c = scell[k]; return (int64_t)cgb[c] + (k - clo[c]); };
+                if (cnt <= kLdsPartners) lds_list_canonical(plist + tid, cnt, q, global_of);
                 vi[0] = v[q];
                 vi[1] = v[n + q];
                 vi[2] = v[2 * n + q];
                 mi = (CAP && held) ? wet_mass(P, ri, held[q]) : mass_of(P, ri);
                 const T sri = CAP ? sr[q] : (T)0;
-                const int listed = cnt < kLdsPartners ? cnt : kLdsPartners;
-                auto global_of = [&](int k) { const int c = scell[k]; return cgb[c] + (k - clo[c]); };
-                for (int i = 0; i < listed; i += 2) {
-                    // two partners per round, their loads in flight together
-                    const bool two = i + 1 < listed;
-                    const int32_t j0 = global_of(plist[i * 256 + tid]);
-                    const int32_t j1 = two ? global_of(plist[(i + 1) * 256 + tid]) : j0;
-                    const Partner p0 = fetch_partner(n, x, v, r, j0);
-                    const Partner p1 = fetch_partner(n, x, v, r, j1);
-                    nc += exact_pair<T, CAP>(P, xi, vi, ri, mi, q, j0, p0, sri, sr, held, acc);
-                    if (two) nc += exact_pair<T, CAP>(P, xi, vi, ri, mi, q, j1, p1, sri, sr, held, acc);
-                }
-                if (cnt > kLdsPartners) {
-                    // more candidates than listed: walk this lane's rows again for the rest
-                    int32_t seen = 0;
-                    for_rows([&](int c) {
-                        const int k1 = clo[c + hi[0]] + cnum[c + hi[0]];
-                        for (int k = clo[c + lo[0]]; k < k1; ++k) {
-                            if (k == kself || !near_slot(spos[k], mx, my, mz, thr)) continue;
-                            if (seen++ < kLdsPartners) continue;
-                            const int32_t j = global_of(k);
-                            nc += exact_pair<T, CAP>(P, xi, vi, ri, mi, q, j, fetch_partner(n, x, v, r, j), sri, sr,
-                                                     held, acc);
-                        }
+                if (cnt <= kLdsPartners) {
+                    for (int i = 0; i < cnt; i += 2) {
+                        // two partners per round, their loads in flight together
+                        const bool two = i + 1 < cnt;
+                        const int32_t j0 = (int32_t)global_of(plist[i * 256 + tid]);
+                        const int32_t j1 = two ? (int32_t)global_of(plist[(i + 1) * 256 + tid]) : j0;
+                        const Partner p0 = fetch_partner(n, x, v, r, j0);
+                        const Partner p1 = fetch_partner(n, x, v, r, j1);
+                        nc += exact_pair<T, CAP>(P, xi, vi, ri, mi, q, j0, p0, sri, sr, held, acc);
+                        if (two) nc += exact_pair<T, CAP>(P, xi, vi, ri, mi, q, j1, p1, sri, sr, held, acc);
+                    }
+                } else {
+                    // more candidates than listed (rare): every granule of the
+                    // search box in canonical order, from global memory
+                    int32_t glo[3], ghi[3];
+                    for (int a = 0; a < 3; ++a) {
+                        glo[a] = lo[a] + c0[a];
+                        ghi[a] = hi[a] + c0[a];
+                    }
+                    for_each_canonical(P, n, q, glo, ghi, cb, ce, [&](int32_t j) {
+                        nc += exact_pair<T, CAP>(P, xi, vi, ri, mi, q, j, fetch_partner(n, x, v, r, j), sri, sr,
+                                                 held, acc);
                     });
                 }
             }
@@ -543,15 +688,14 @@ k_contact_lds(DevParams P, int64_t n, const int32_t *__restrict__ bl,
 
 // ---------------------------------------------------------------------------
 // Neighbour list.  The list build stages the brick's shell in LDS like the
-// contact kernel above, with every radius grown by skin / 2, and keeps, in
-// slot order (cells z, y, x; positions inside a cell), every shell granule
-// that passes the three-FMA test and then a single-precision distance test
-// d^2 < (r_i + r_j + skin)^2 + M (same margin M: the float evaluation errs
-// by less than M / 8), so the list holds every pair closer than
-// r_i + r_j + skin.  One thread per granule, so the order is canonical: the
-// touching pairs of two lists built from the same sorted order (whatever the
-// positions) come in the same order, and the forces summed over them are the
-// same bits.
+// contact kernel above, with every radius grown by skin / 2, and keeps every
+// shell granule that passes the three-FMA test and then a single-precision
+// distance test d^2 < (r_i + r_j + skin)^2 + M (same margin M: the float
+// evaluation errs by less than M / 8), so the list holds every pair closer
+// than r_i + r_j + skin, in canonical order (canon_before): the touching
+// pairs of two lists built from the same sorted order (whatever the
+// positions) come in the same order, and the forces summed over them are
+// the same bits.
 constexpr int kNbrThreads = 256;
 
 // Partners of granule q by a search of its cells in global memory (shells
@@ -574,6 +718,7 @@ __device__ inline int nbr_global(const DevParams &P, int64_t n, const double *__
             ++cnt;
         }
     });
+    canon_sort(nbr + q, n, cnt < kNbrCap ? cnt : kNbrCap, q, [](int32_t j) { return (int64_t)j; });
     return cnt;
 }
 
@@ -737,11 +882,9 @@ __device__ inline void nbr_build_brick(const DevParams &P, int64_t n, int64_t b,
             }
         ncnt[q] = cnt;
         const int listed = cnt < kNbrCap ? cnt : kNbrCap;
-        for (int k = 0; k < listed; ++k) {
-            const int slot = plist[k * kNbrThreads + tid];
-            const int c = scell[slot];
-            nbr[(int64_t)k * n + q] = cgb[c] + (slot - clo[c]);
-        }
+        auto j_of = [&](int slot) { const int c = scell[slot]; return (int64_t)cgb[c] + (slot - clo[c]); };
+        canon_sort(plist + tid, kNbrThreads, listed, q, j_of);
+        for (int k = 0; k < listed; ++k) nbr[(int64_t)k * n + q] = (int32_t)j_of(plist[k * kNbrThreads + tid]);
     }
 }
 
@@ -773,13 +916,15 @@ __global__ void __launch_bounds__(kNbrThreads) k_nbr_build(DevParams P, int64_t 
 // The workgroup first copies the double state of its own granules into
 // LDS with coalesced loads; a listed partner among them (the granules of the
 // same few cells) is read from there, any other from global memory, two
-// partners' state fetched together so their loads overlap.  (Listed partners
-// of neighbouring lanes lie in different directions, so global partner reads
-// touch about one cache line per lane; a wider window of sorted positions in
-// LDS served more partners but lowered the waves per SIMD, which cost more.)
-// Each listed partner runs the exact test of Sec. 3.1 and, if touching,
-// Eq. (1); walls last.  A granule whose partners did not fit in its list
-// searches its cells in the same order.
+// partners' state fetched together so their loads overlap.  The list's
+// canonical order puts each granule's nearest sorted positions first, which
+// lie in the workgroup, so the global partners of a wave gather in the
+// last few list places and in like directions: fewer load instructions
+// issue, and they touch fewer cache lines.  (A wider window of sorted
+// positions in LDS served more partners but lowered the waves per SIMD,
+// which cost more.)  Each listed partner runs the exact test of Sec. 3.1
+// and, if touching, Eq. (1); walls last.  A granule whose partners did not
+// fit in its list walks its cells' granules in the same order.
 constexpr int kListBatch = 2;
 constexpr int kListThreads = 256;  // granules (threads) per workgroup
 
@@ -862,9 +1007,7 @@ __global__ void __launch_bounds__(kListThreads) k_contact_list(DevParams P, int6
         const double Rs = (ri + P.r_max) * P.search_scale;
         int32_t lo[3], hi[3];
         for (int a = 0; a < 3; ++a) search_range(P, xi[a], Rs, P.nc[a], lo[a], hi[a]);
-        for_each_run(P, n, lo, hi, cb, ce, [&](int32_t jb, int32_t je) {
-            for (int32_t jj = jb; jj < je; ++jj) take(jj, partner(jj));
-        });
+        for_each_canonical(P, n, q, lo, hi, cb, ce, [&](int32_t jj) { take(jj, partner(jj)); });
     }
     add_walls<T>(P, xi, vi, ri, mi, acc, nc);
     F[q] = acc[0];
