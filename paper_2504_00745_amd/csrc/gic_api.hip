@@ -141,7 +141,7 @@ bool params_valid(const gic_params *p)
 // 4 cell/dx > 4.  (And at most 2,048 bricks along x.)
 bool tiles_assemble(const gic_params *p)
 {
-    if ((p->nc[0] + kBrick - 1) / kBrick > 2048) return false;  // a row's bricks in 32 KiB of LDS
+    if ((p->nc[0] + kBrick - 1) / kBrick > 512) return false;  // four rows' bricks in 32 KiB of LDS
     const double m4 = (double)kBrick * p->cell / p->dx;
     const double r = floor(m4 + 0.5);
     if (fabs(m4 - r) < 1e-9 * (r > 1.0 ? r : 1.0)) return r >= 2.0;

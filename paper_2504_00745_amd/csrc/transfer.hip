@@ -368,64 +368,75 @@ __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_e
 // (Giving each XCD a contiguous eighth of the rows, so that the rows reading
 // one tile share an L2, was slower: a bed fills part of the box, so most
 // tile reads then fell to a few XCDs.)
+constexpr int kAsmRows = 4;  // node rows per workgroup pass, one per wave
+
 __global__ void __launch_bounds__(256) k_p2g_assemble(DevParams P, const unsigned long long *__restrict__ tiles,
                                                       const int32_t *__restrict__ slot_of,
                                                       const int32_t *__restrict__ cover,
                                                       unsigned long long *__restrict__ alpha,
                                                       unsigned long long *__restrict__ mom)
 {
-    extern __shared__ int32_t s_slot[];  // [4][nb0]: slots of the row's (z, y) brick pairs along x
-    __shared__ int32_t s_any;
+    extern __shared__ int32_t s_slot[];  // [kAsmRows][4][nb0]: slots of each row's (z, y) brick pairs along x
+    __shared__ int32_t s_any[kAsmRows];
     const int E = P.tile, E3 = E * E * E;
     const int64_t G = P.G;
     const int64_t rows = (int64_t)P.n[1] * P.n[2];
     const int32_t *cx = cover, *cy = cover + 4 * P.n[0], *cz = cover + 4 * (P.n[0] + P.n[1]);
     const int32_t nbx = P.nb[0];
-    for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
-        const int32_t j = (int32_t)(row % P.n[1]), k = (int32_t)(row / P.n[1]);
-        const int32_t by[2] = {cy[4 * j], cy[4 * j + 2]}, ly[2] = {cy[4 * j + 1], cy[4 * j + 3]};
-        const int32_t bz[2] = {cz[4 * k], cz[4 * k + 2]}, lz[2] = {cz[4 * k + 1], cz[4 * k + 3]};
-        // the row's brick slots into LDS, and whether any is occupied
-        if (threadIdx.x == 0) s_any = 0;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int64_t r0 = (int64_t)blockIdx.x * kAsmRows; r0 < rows; r0 += (int64_t)gridDim.x * kAsmRows) {
+        // the brick slots of the pass's rows into LDS (all loads in flight
+        // together), and whether any is occupied
+        if (threadIdx.x < kAsmRows) s_any[threadIdx.x] = 0;
         __syncthreads();
-        int any = 0;
-        for (int t = threadIdx.x; t < 4 * nbx; t += 256) {
-            const int p = t / nbx, bx = t - p * nbx;
-            const int iz = p >> 1, iy = p & 1;
+        for (int t = threadIdx.x; t < kAsmRows * 4 * nbx; t += 256) {
+            const int rr = t / (4 * nbx), rem = t - rr * (4 * nbx);
+            const int p = rem / nbx, bx = rem - p * nbx;
+            const int64_t row = r0 + rr;
             int32_t sl = -1;
-            if (bz[iz] >= 0 && by[iy] >= 0) sl = slot_of[((int64_t)bz[iz] * P.nb[1] + by[iy]) * nbx + bx];
-            s_slot[p * nbx + bx] = sl;
-            any |= sl >= 0;
+            if (row < rows) {
+                const int32_t j = (int32_t)(row % P.n[1]), k = (int32_t)(row / P.n[1]);
+                const int32_t by = cy[4 * j + 2 * (p & 1)], bz = cz[4 * k + 2 * (p >> 1)];
+                if (bz >= 0 && by >= 0) sl = slot_of[((int64_t)bz * P.nb[1] + by) * nbx + bx];
+            }
+            s_slot[t] = sl;
+            if (sl >= 0) s_any[rr] = 1;
         }
-        if (any) s_any = 1;
         __syncthreads();
-        const int occupied = s_any;
-        for (int32_t i = threadIdx.x; i < P.n[0]; i += 256) {
-            unsigned long long s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-            if (occupied) {
-                const int32_t bx[2] = {cx[4 * i], cx[4 * i + 2]}, lx[2] = {cx[4 * i + 1], cx[4 * i + 3]};
-                for (int p = 0; p < 4; ++p) {
-                    const int iz = p >> 1, iy = p & 1;
-                    const int off_yz = (lz[iz] * E + ly[iy]) * E;
-                    for (int ix = 0; ix < 2; ++ix) {
-                        if (bx[ix] < 0) continue;
-                        const int32_t sl = s_slot[p * nbx + bx[ix]];
-                        if (sl < 0) continue;
-                        const unsigned long long *t = tiles + (int64_t)sl * (4 * E3) + off_yz + lx[ix];
-                        s0 += t[0];
-                        s1 += t[E3];
-                        s2 += t[2 * E3];
-                        s3 += t[3 * E3];
+        const int64_t row = r0 + wave;  // each wave writes one row
+        if (row < rows) {
+            const int32_t j = (int32_t)(row % P.n[1]), k = (int32_t)(row / P.n[1]);
+            const int32_t ly[2] = {cy[4 * j + 1], cy[4 * j + 3]};
+            const int32_t lz[2] = {cz[4 * k + 1], cz[4 * k + 3]};
+            const int occupied = s_any[wave];
+            const int32_t *rs = s_slot + wave * 4 * nbx;
+#pragma unroll 2
+            for (int32_t i = lane; i < P.n[0]; i += 64) {
+                unsigned long long s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+                if (occupied) {
+                    const int32_t bx[2] = {cx[4 * i], cx[4 * i + 2]}, lx[2] = {cx[4 * i + 1], cx[4 * i + 3]};
+                    for (int p = 0; p < 4; ++p) {
+                        const int off_yz = (lz[p >> 1] * E + ly[p & 1]) * E;
+                        for (int ix = 0; ix < 2; ++ix) {
+                            if (bx[ix] < 0) continue;
+                            const int32_t sl = rs[p * nbx + bx[ix]];
+                            if (sl < 0) continue;
+                            const unsigned long long *t = tiles + (int64_t)sl * (4 * E3) + off_yz + lx[ix];
+                            s0 += t[0];
+                            s1 += t[E3];
+                            s2 += t[2 * E3];
+                            s3 += t[3 * E3];
+                        }
                     }
                 }
+                const int64_t idx = row * P.n[0] + i;
+                alpha[idx] = s0;
+                mom[idx] = s1;
+                mom[G + idx] = s2;
+                mom[2 * G + idx] = s3;
             }
-            const int64_t idx = row * P.n[0] + i;
-            alpha[idx] = s0;
-            mom[idx] = s1;
-            mom[G + idx] = s2;
-            mom[2 * G + idx] = s3;
         }
-        __syncthreads();  // s_slot and s_any are rewritten for the next row
+        __syncthreads();  // s_slot and s_any are rewritten by the next pass
     }
 }
 
@@ -798,8 +809,9 @@ hipError_t launch_p2g_assemble(const DevParams &P, int64_t n, const double *x, c
 {
     unsigned long long *A = reinterpret_cast<unsigned long long *>(alpha);
     unsigned long long *M = reinterpret_cast<unsigned long long *>(mom);
-    const int64_t rows = (int64_t)P.n[1] * P.n[2];
-    k_p2g_assemble<<<(unsigned)(rows < 16384 ? rows : 16384), 256, sizeof(int32_t) * 4 * P.nb[0], s>>>(
+    const int64_t passes = ((int64_t)P.n[1] * P.n[2] + kAsmRows - 1) / kAsmRows;
+    k_p2g_assemble<<<(unsigned)(passes < 16384 ? passes : 16384), 256, sizeof(int32_t) * kAsmRows * 4 * P.nb[0],
+                     s>>>(
         P, st.tiles, B.slot_of, st.cover, A, M);
     k_p2g_escapes<<<256, 256, 0, s>>>(P, n, st.esc, st.esc_n, esc_next, x, v, r, A, M, err);
     return hipGetLastError();
