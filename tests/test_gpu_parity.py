@@ -460,3 +460,37 @@ def test_kept_brick_list_gives_the_same_bits(G, prec):
 
     for a, b in zip(run(True), run(False)):
         assert torch.equal(a, b)
+
+
+def test_stage_times_cover_the_step(G):
+    """gic_stage_timing / gic_stage_times: seven stages per step (sort,
+    gather, contact, exchange, grid clear, integrate + P2G, assembly) over
+    the steps asked for; on a bed whose grids are assembled from brick tiles
+    the assembly takes time, while the exchange deposit (none in gic_step)
+    and the grid clear (none when the grids are assembled) are only the gap
+    between two adjacent events (a few microseconds); the stages sum to at
+    most the steps' own elapsed time."""
+    import torch
+    from paper_2504_00745_amd import gic
+    G.say("[stage times] c4s fp32")
+    d = _make("c4s")
+    n = d["x"].shape[1]
+    sim = gic.Simulator(d["params"], d["x"].reshape(3, n), d["v"].reshape(3, n), d["r"], d["u"].reshape(-1),
+                        "fp32", r_max=_rmax("c4s", d["r"]))
+    sim.step()
+    torch.cuda.synchronize()
+    sim.ctx.stage_timing(8)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(4):
+        sim.step()
+    e1.record()
+    ms, k = sim.ctx.stage_times()
+    sim.ctx.stage_timing(0)
+    assert k == 4
+    assert list(ms) == list(gic.Context.STAGES) and len(ms) == 7
+    assert all(v >= 0.0 for v in ms.values())
+    assert ms["assemble"] > 0.0 and ms["integrate_p2g"] > 0.0 and ms["sort"] > 0.0
+    assert ms["exchange"] / k < 0.010 and ms["grid_clear"] / k < 0.010  # ms per step
+    assert sum(ms.values()) <= 1.05 * e0.elapsed_time(e1)
+    assert sim.ctx.error() == (0, -1)
