@@ -367,7 +367,7 @@ gic_status gic_create(const gic_params *p, int64_t n_max, gic_ctx **out)
         return GIC_E_HIP;
     }
     const int64_t nn = n_max > 0 ? n_max : 1;
-    const int64_t tiles = (nn + kSortTile - 1) / kSortTile;
+    const int64_t tiles = sort_tiles_max(nn);
     c->sort.tiles_max = tiles;
     c->sort.passes = sort_passes(c->K);
     bool ok = true;

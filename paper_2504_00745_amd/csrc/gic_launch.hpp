@@ -71,6 +71,18 @@ struct NbrList {
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 8;
 constexpr int kSortTile = kSortThreads * kSortItems;
+// Up to this many keys the digit passes take tiles of one key per thread,
+// so a small sort still spreads over many workgroups.
+constexpr int64_t kSmallSort = (int64_t)1 << 18;
+inline int sort_items(int64_t n) { return n <= kSmallSort ? 1 : kSortItems; }
+// Tiles of the digit passes for up to n_max keys (the larger of the two tilings).
+inline int64_t sort_tiles_max(int64_t n_max)
+{
+    const int64_t big = (n_max + kSortTile - 1) / kSortTile;
+    const int64_t m = n_max < kSmallSort ? n_max : kSmallSort;
+    const int64_t small = (m + kSortThreads - 1) / kSortThreads;
+    return big > small ? big : small;
+}
 
 // nl: the neighbour list of the stepping path, or NULL.  With nl, the key
 // kernel also measures every granule's displacement since the list's build

@@ -158,10 +158,12 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_spine(uint32_t *sums, int
 // ---- digit passes (reduce, scan, scatter) --------------------------------
 //
 // Each 8-bit digit pass is three kernels with no waits between workgroups:
-// every tile of kSortTile keys counts its digits (k_rts_count, into
-// tcnt[digit][tile]); one workgroup per digit turns its row into the
-// exclusive prefix over the tiles and records the row's total (k_rts_scan);
-// every tile then scatters its keys stably (k_rts_scatter) from the prefix
+// every tile of 2,048 keys (256 for sorts of at most 2^18 keys, so that a
+// small sort still spreads over many workgroups) counts its digits
+// (k_rts_count, into tcnt[digit][tile]); one workgroup per digit turns its
+// row into the exclusive prefix over the tiles and records the row's total
+// (k_rts_scan); every tile then scatters its keys stably (k_rts_scatter)
+// from the prefix
 // of its tile plus the keys of all smaller digits (a scan of the 256 row
 // totals).  The tile loops stride over the grid, so a launch needs no more
 // workgroups than it has tiles.
@@ -187,7 +189,8 @@ __device__ inline uint64_t lanes_below()
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-// Digit counts of every tile: tcnt[d * tiles + t].
+// Digit counts of every tile of ITEMS x 256 keys: tcnt[d * tiles + t].
+template <int ITEMS>
 __global__ void __launch_bounds__(kSortThreads) k_rts_count(const uint32_t *__restrict__ kin, int64_t n, int pass,
                                                             int64_t tiles, uint32_t *__restrict__ tcnt,
                                                             const int32_t *__restrict__ skip)
@@ -200,9 +203,9 @@ __global__ void __launch_bounds__(kSortThreads) k_rts_count(const uint32_t *__re
     for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
         s_cnt[tid] = 0;
         __syncthreads();
-        const int64_t tile0 = t * kSortTile;
+        const int64_t tile0 = t * (kSortThreads * ITEMS);
 #pragma unroll
-        for (int it = 0; it < kSortItems; ++it) {
+        for (int it = 0; it < ITEMS; ++it) {
             const int64_t p = tile0 + (int64_t)it * kSortThreads + tid;
             const bool valid = p < n;
             const uint32_t d = valid ? (kin[p] >> shift) & (kRadix - 1) : 0u;
@@ -243,6 +246,7 @@ __global__ void __launch_bounds__(kSortThreads) k_rts_scan(uint32_t *__restrict_
 
 // Stable scatter of every tile's keys (and values: vin, or the positions)
 // from the offsets of k_rts_scan, in rounds of 256 keys in position order.
+template <int ITEMS>
 __global__ void __launch_bounds__(kSortThreads) k_rts_scatter(const uint32_t *__restrict__ kin,
                                                               const int32_t *__restrict__ vin,
                                                               uint32_t *__restrict__ kout, int32_t *__restrict__ vout,
@@ -265,11 +269,11 @@ __global__ void __launch_bounds__(kSortThreads) k_rts_scatter(const uint32_t *__
     uint32_t total;
     const uint32_t dbase = block_scan_inclusive(g, lds, &total) - g;
     for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
-        const int64_t tile0 = t * kSortTile;
-        uint32_t k[kSortItems];
-        int32_t val[kSortItems];
+        const int64_t tile0 = t * (kSortThreads * ITEMS);
+        uint32_t k[ITEMS];
+        int32_t val[ITEMS];
 #pragma unroll
-        for (int it = 0; it < kSortItems; ++it) {
+        for (int it = 0; it < ITEMS; ++it) {
             const int64_t p = tile0 + (int64_t)it * kSortThreads + tid;
             const bool valid = p < n;
             k[it] = valid ? kin[p] : 0xffffffffu;
@@ -278,7 +282,7 @@ __global__ void __launch_bounds__(kSortThreads) k_rts_scatter(const uint32_t *__
         s_base[tid] = dbase + tcnt[(int64_t)tid * tiles + t];
         __syncthreads();
 #pragma unroll
-        for (int it = 0; it < kSortItems; ++it) {
+        for (int it = 0; it < ITEMS; ++it) {
             const int64_t p = tile0 + (int64_t)it * kSortThreads + tid;
             const bool valid = p < n;
             const uint32_t d = (k[it] >> shift) & (kRadix - 1);
@@ -592,7 +596,8 @@ hipError_t launch_sort_cells(const DevParams &P, int64_t n, const double *x, uin
             k_merge<<<grid_for(n, 256), 256, 0, s>>>(n, key, pk, S.ctl, S.chg_s, S.chg_p, skeys, order);
         }
         // digit passes (skipped on the device when the incremental path sorted)
-        const int64_t tiles = (n + kSortTile - 1) / kSortTile;
+        const int items = sort_items(n);
+        const int64_t tiles = (n + kSortThreads * items - 1) / (kSortThreads * items);
         const unsigned tg = (unsigned)(tiles < kRtsGrid ? tiles : kRtsGrid);
         const uint32_t *kin = key;
         const int32_t *vin = nullptr;
@@ -600,10 +605,17 @@ hipError_t launch_sort_cells(const DevParams &P, int64_t n, const double *x, uin
             const bool last = pass == S.passes - 1;
             uint32_t *kout = last ? skeys : ((pass & 1) ? S.kB : S.kA);
             int32_t *vout = last ? order : ((pass & 1) ? S.vB : S.vA);
-            k_rts_count<<<tg, kSortThreads, 0, s>>>(kin, n, pass, tiles, S.tcnt, skip);
+            if (items == 1)
+                k_rts_count<1><<<tg, kSortThreads, 0, s>>>(kin, n, pass, tiles, S.tcnt, skip);
+            else
+                k_rts_count<kSortItems><<<tg, kSortThreads, 0, s>>>(kin, n, pass, tiles, S.tcnt, skip);
             k_rts_scan<<<kRadix, kSortThreads, 0, s>>>(S.tcnt, tiles, S.rowtot, skip);
-            k_rts_scatter<<<tg, kSortThreads, 0, s>>>(kin, vin, kout, vout, n, pass, tiles, S.tcnt, S.rowtot,
-                                                      skip);
+            if (items == 1)
+                k_rts_scatter<1><<<tg, kSortThreads, 0, s>>>(kin, vin, kout, vout, n, pass, tiles, S.tcnt,
+                                                             S.rowtot, skip);
+            else
+                k_rts_scatter<kSortItems><<<tg, kSortThreads, 0, s>>>(kin, vin, kout, vout, n, pass, tiles, S.tcnt,
+                                                                      S.rowtot, skip);
             kin = kout;
             vin = vout;
         }
