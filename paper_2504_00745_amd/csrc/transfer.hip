@@ -265,10 +265,13 @@ __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_e
             const int rr = task / NCH;
             const int c = task - rr * NCH;
             const int g0 = srun[rr], g1 = srun[rr + 1];
-            uint64_t acc[27];  // sums of rint_biased patterns (mod 2^64)
+            // sums of rint_biased patterns (mod 2^64), started at minus the
+            // run's bias so that they end as sums of rint values
+            const uint64_t nbias = 0ull - (uint64_t)(g1 - g0) * kRintBias;
+            uint64_t acc[27];
 #pragma unroll
-            for (int k = 0; k < 27; ++k) acc[k] = 0;
-            uint64_t qsum = 0;
+            for (int k = 0; k < 27; ++k) acc[k] = nbias;
+            uint64_t qsum = nbias;
             for (int g = g0; g < g1; ++g) {
                 const double S = sS[c * bs + g];
                 double w[3][3];
@@ -292,15 +295,11 @@ __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_e
                             acc[(cz * 3 + cy) * 3 + cx] += rint_product_biased(ww, S);
                         }
             }
-            const uint64_t bias = (uint64_t)(g1 - g0) * kRintBias;
             uint64_t outer = 0;
 #pragma unroll
-            for (int k = 0; k < 27; ++k) {
-                if (k == 13) continue;
-                acc[k] -= bias;
-                outer += acc[k];
-            }
-            acc[13] = (qsum - bias) - outer;
+            for (int k = 0; k < 27; ++k)
+                if (k != 13) outer += acc[k];
+            acc[13] = qsum - outer;
             // nodes of the run's stencil, folded onto the edge
             int32_t nd[3][3];
             bool inb[3][3];
