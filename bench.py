@@ -60,10 +60,13 @@ def log(*a):
 # Algorithmic bytes per granule (and per touched grid node) of each kernel of
 # the step: the arrays the method itself must read and write once, neighbour
 # re-reads and scratch excluded.  B = size of the real type.
-def stage_bytes(stage, n, nodes, real_bytes, G=0, assembled=False):
+def stage_bytes(stage, n, nodes, real_bytes, G=0, assembled=False, tile_bytes=0):
     B = real_bytes
-    if stage == "assemble":  # every grid node written once: alpha and three momentum components (int64)
-        return 32 * G
+    if stage == "assemble":
+        # the stored tiles read once, and each node that holds a value written
+        # once (four int64 channels); the zeros elsewhere stay from the step
+        # before
+        return tile_bytes + 32 * nodes
     per = {
         "sort": 24 + 4 + 4,                          # read x, write key, write order
         "gather_g2p_drag": 4 + 2 * (24 + 24 + 8 + 4) + 3 * B,  # order; gather + write x, v, r, id; write F_d
@@ -154,13 +157,29 @@ def dominant_roofline(stages, n, nodes, real_bytes, workload, G):
             "frac": ach / HBM_PEAK_GBS, "traffic": stored_traffic(dom, workload), "algorithmic_bytes": abytes}
 
 
-def stage_rooflines(stages, n, nodes, real_bytes, G):
+def stored_tile_bytes(d):
+    """Bytes of the stored P2G tiles of the bed d (its initial positions):
+    one tile of four int64 channels per occupied brick of 4x4x4 cells, E
+    nodes an edge (4 cell / dx + 2 when that is an integer, else its ceiling
+    + 3)."""
+    p = d["params"]
+    m4 = 4.0 * p["cell"] / p["dx"]
+    E = int(round(m4)) + 2 if abs(m4 - round(m4)) < 1e-9 * max(round(m4), 1.0) else int(np.ceil(m4)) + 3
+    nc = np.array(p["nc"], dtype=np.int64)
+    c = np.clip(np.floor(d["x"] / p["cell"]).astype(np.int64), 0, (nc - 1)[:, None])
+    b = c // 4
+    nb = (nc + 3) // 4
+    occupied = np.unique((b[2] * nb[1] + b[1]) * nb[0] + b[0]).size
+    return occupied * 4 * E ** 3 * 8
+
+
+def stage_rooflines(stages, n, nodes, real_bytes, G, tile_bytes=0):
     """Algorithmic GB/s and fraction of the HBM peak of each single-kernel
     stage, and of the grid assembly when the step has one."""
     out = {}
     assembled = stages.get("assemble", 0.0) > 0.0
     for k in SINGLE_KERNEL_STAGES + (("assemble",) if assembled else ()):
-        ab = stage_bytes(k, n, nodes, real_bytes, G, assembled)
+        ab = stage_bytes(k, n, nodes, real_bytes, G, assembled, tile_bytes)
         out[k] = {"ms": round(stages[k] * 1e3, 4), "algorithmic_bytes": ab,
                   "GB_s": round(ab / stages[k] / 1e9, 1), "frac": round(ab / stages[k] / 1e9 / HBM_PEAK_GBS, 4)}
     return out
@@ -232,7 +251,8 @@ def run_leg(name, steps, warmup, with_fp64=False):
         B = 4 if prec == "fp32" else 8
         r = {"value": n * steps / t, "unit": "granule-steps/s", "ms_per_step": t / steps * 1e3,
              "neighbour_builds": builds, "stages_ms": {k_: round(v * 1e3, 4) for k_, v in stages.items()},
-             "stage_rooflines": stage_rooflines(stages, n, nodes, B, int(np.prod(d["params"]["n"]))),
+             "stage_rooflines": stage_rooflines(stages, n, nodes, B, int(np.prod(d["params"]["n"])),
+                                               stored_tile_bytes(d)),
              "error": [code, idx]}
         res[prec] = r
         del sim
@@ -662,7 +682,7 @@ def main():
         "stages_ms": {k: round(v * 1e3, 4) for k, v in st.items()},
         "neighbour_builds": r32["builds"],
         "roofline": dominant_roofline(st, n, r32["nodes"], 4, a.workload, G),
-        "stage_rooflines": stage_rooflines(st, n, r32["nodes"], 4, G),
+        "stage_rooflines": stage_rooflines(st, n, r32["nodes"], 4, G, stored_tile_bytes(d)),
     }
     if "fp64" in out:
         r64 = out["fp64"]

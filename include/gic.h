@@ -182,7 +182,9 @@ int64_t gic_key_space(const gic_params *p);
 gic_status gic_create(const gic_params *p, int64_t n_max, gic_ctx **out);
 
 /* Replace the parameters (same grid, cells and precision; e.g. mu, c_drag,
- * dt).  Returns GIC_E_ARG if the grid, cells or precision change. */
+ * dt).  Returns GIC_E_ARG if the grid, cells or precision change.  The next
+ * gic_step or gic_sand_step builds its neighbour list afresh and writes its
+ * grids whole. */
 gic_status gic_set_params(gic_ctx *ctx, const gic_params *p);
 
 /* Synchronise the device and free the context's scratch. */
@@ -383,7 +385,13 @@ gic_status gic_integrate_p2g_wet(gic_ctx *ctx, int64_t n, double *x, double *v, 
  * read from the `cur` arrays and written, advanced and in the new sorted
  * order, to the `nxt` arrays (same sizes); the caller swaps them.  alpha_fx
  * is read, then overwritten with the fraction at the new positions; mom_fx
- * receives the new momentum.  Scratch arrays (caller-owned): key, order (n
+ * receives the new momentum.  Both are complete after every step; when they
+ * are the arrays of the previous step on this context, the step rewrites
+ * only the 4-node x-segments that a granule's stencil reaches now or reached
+ * then (the rest hold that step's zeros and are left as they are), so a
+ * caller that writes into them between steps passes other arrays or calls
+ * gic_set_params first (calls on the context that write grids into them
+ * are noticed).  Scratch arrays (caller-owned): key, order (n
  * int32), cell_begin, cell_end (K int32), f_contact, f_drag (3n real; they
  * hold the step's forces afterwards); u_at (3n real) and alpha_f (n real)
  * receive the sampled fluid velocity and fraction, or are skipped when
@@ -465,8 +473,10 @@ gic_status gic_exchange_p2g(gic_ctx *ctx, int64_t n, const double *x, const doub
  * gic_integrate_p2g.  The state ping-pongs between the a and b arrays,
  * starting in a; *which = 0 if it ends in a, 1 if in b; *nsub = N.  fs_fx
  * accumulates (clear it before the first sand step of a fluid step);
- * alpha_fx, mom_fx hold the P2G of the final state.  Scratch as for
- * gic_step; f_contact, f_fluid hold the last sub-step's forces. */
+ * alpha_fx, mom_fx hold the P2G of the final state (rewritten as by
+ * gic_step: only where a stencil reaches now or did at the last write of the
+ * same arrays).  Scratch as for gic_step; f_contact, f_fluid hold the last
+ * sub-step's forces. */
 gic_status gic_sand_step(gic_ctx *ctx, int64_t n, double Dt, double *x_a, double *v_a, double *r_a, int32_t *id_a,
                          double *x_b, double *v_b, double *r_b, int32_t *id_b, const void *u, const void *grad_p,
                          const void *acc_f, int64_t *alpha_fx, int64_t *mom_fx, int64_t *fs_fx, uint32_t *key,

@@ -31,6 +31,11 @@ struct gic_ctx {
     P2GStore p2gs;
     uint32_t *esc_n2;
     int esc_par;
+    // The live flags of p2gs describe the grids live_a, live_m (alpha and
+    // momentum) when live_ok: the last write to them was the stepping path's
+    // assembly, and no call on the context has written to them since.
+    bool live_ok;
+    const int64_t *live_a, *live_m;
     // The list holds the stepping path's state when nl_n == n and the state
     // to step is the array that the last step wrote (nl_x): its sorted
     // order is the one of the list's last build or check.
@@ -415,6 +420,13 @@ gic_status gic_create(const gic_params *p, int64_t n_max, gic_ctx **out)
             ok &= hipMemcpy(cov, h, sizeof(int32_t) * ncov, hipMemcpyHostToDevice) == hipSuccess;
             delete[] h;
             c->p2gs.cover = cov;
+            // live flags: without them every assembly writes every node
+            const size_t nlive = (size_t)p->n[1] * p->n[2] * (((size_t)p->n[0] + 3) / 4);
+            if (hipMalloc(&c->p2gs.live, nlive) != hipSuccess || hipMemset(c->p2gs.live, 0, nlive) != hipSuccess) {
+                (void)hipFree(c->p2gs.live);
+                c->p2gs.live = nullptr;
+                (void)hipGetLastError();
+            }
         } else {
             (void)hipFree(c->p2gs.tiles);
             c->p2gs.tiles = nullptr;  // the fallback path needs neither
@@ -451,6 +463,7 @@ gic_status gic_set_params(gic_ctx *c, const gic_params *p)
     c->dp = derive(p);
     nbr_reach(p, c->nl);
     c->nl_n = -1;  // radii or r_max may differ: the next step builds its list afresh
+    c->live_ok = false;  // and writes its grids whole
     return GIC_OK;
 }
 
@@ -481,6 +494,7 @@ gic_status gic_destroy(gic_ctx *c)
     (void)hipFree(c->p2gs.esc);
     (void)hipFree(c->p2gs.tiles);
     (void)hipFree(const_cast<int32_t *>(c->p2gs.cover));
+    (void)hipFree(c->p2gs.live);
     (void)hipFree(c->esc_n2);
     if (c->tm_ev) {
         for (int i = 0; i < c->tm_cap * kStageEvents; ++i) (void)hipEventDestroy(c->tm_ev[i]);
@@ -670,6 +684,16 @@ gic_status gic_integrate(gic_ctx *c, int64_t n, const double *r, const void *f_c
         launch_integrate<double>(c->dp, n, r, (const double *)f_contact, (const double *)f_drag, x, v, s));
 }
 
+// A call writes len int64 from p: the live flags no longer describe the
+// stepping path's grids if p overlaps them.
+static void grids_written(gic_ctx *c, const int64_t *p, int64_t len)
+{
+    if (!c->live_ok || !p) return;
+    const int64_t G = c->dp.G;
+    auto overlaps = [&](const int64_t *q, int64_t m) { return p < q + m && q < p + len; };
+    if (overlaps(c->live_a, G) || overlaps(c->live_m, 3 * G)) c->live_ok = false;
+}
+
 gic_status gic_p2g(gic_ctx *c, int64_t n, const double *x, const double *v, const double *r,
                    const int32_t *cell_begin, const int32_t *cell_end, int64_t *alpha_fx, int64_t *mom_fx,
                    int32_t accumulate, void *stream)
@@ -678,6 +702,8 @@ gic_status gic_p2g(gic_ctx *c, int64_t n, const double *x, const double *v, cons
     if (n > 0 && (!x || !r || !cell_begin || !cell_end || (mom_fx && !v))) return GIC_E_ARG;
     hipStream_t s = (hipStream_t)stream;
     const int64_t G = c->dp.G;
+    grids_written(c, alpha_fx, G);
+    grids_written(c, mom_fx, 3 * G);
     if (!accumulate) {
         hipError_t e = launch_fill_i64(alpha_fx, G, s);
         if (e == hipSuccess && mom_fx) e = launch_fill_i64(mom_fx, 3 * G, s);
@@ -731,6 +757,8 @@ static gic_status integrate_p2g_impl(gic_ctx *c, int64_t n, double *x, double *v
     if (!n_ok(c, n) || !alpha_fx || !mom_fx || !cell_begin || !cell_end) return GIC_E_ARG;
     if (n > 0 && (!x || !v || !r || !f_contact || !f_drag)) return GIC_E_ARG;
     hipStream_t s = (hipStream_t)stream;
+    grids_written(c, alpha_fx, c->dp.G);
+    grids_written(c, mom_fx, 3 * c->dp.G);
     if (!accumulate) {
         hipError_t e = launch_fill_i64(alpha_fx, c->dp.G, s);
         if (e == hipSuccess) e = launch_fill_i64(mom_fx, 3 * c->dp.G, s);
@@ -779,6 +807,7 @@ static gic_status step_integrate_p2g(gic_ctx *c, int64_t n, double *x, double *v
                                      const int32_t *cell_end, int64_t *alpha_fx, int64_t *mom_fx, hipStream_t s)
 {
     if (!c->p2gs.tiles || n == 0) {
+        c->live_ok = false;
         if (launch_fill_i64(alpha_fx, c->dp.G, s) != hipSuccess || launch_fill_i64(mom_fx, 3 * c->dp.G, s) != hipSuccess)
             return GIC_E_HIP;
         stage_mark(c, 5, s);
@@ -790,6 +819,7 @@ static gic_status step_integrate_p2g(gic_ctx *c, int64_t n, double *x, double *v
     if (brick_list(c, cell_begin, cell_end, s) != hipSuccess) return GIC_E_HIP;
     stage_mark(c, 5, s);
     P2GStore st = c->p2gs;
+    st.full = c->live_ok && c->live_a == alpha_fx && c->live_m == mom_fx ? 0 : 1;
     st.esc_n = c->esc_n2 + c->esc_par;
     uint32_t *next = c->esc_n2 + (c->esc_par ^ 1);
     c->esc_par ^= 1;
@@ -803,7 +833,11 @@ static gic_status step_integrate_p2g(gic_ctx *c, int64_t n, double *x, double *v
                                                st);
     if (e != hipSuccess) return hip_status(e);
     stage_mark(c, 6, s);
-    return hip_status(launch_p2g_assemble(c->dp, n, x, v, r, c->bricks, alpha_fx, mom_fx, c->err, s, st, next));
+    e = launch_p2g_assemble(c->dp, n, x, v, r, c->bricks, alpha_fx, mom_fx, c->err, s, st, next);
+    c->live_ok = e == hipSuccess && st.live;
+    c->live_a = alpha_fx;
+    c->live_m = mom_fx;
+    return hip_status(e);
 }
 
 // Stage event k of the current timed step (no-op unless timing is on and
@@ -937,6 +971,7 @@ gic_status gic_exchange_p2g(gic_ctx *c, int64_t n, const double *x, const double
     if (n > 0 && (!x || !r || !f_contact || !f_fluid)) return GIC_E_ARG;
     if (!(c->p.f_unit > 0.0) || !isfinite(weight)) return GIC_E_ARG;
     hipStream_t s = (hipStream_t)stream;
+    grids_written(c, fs_fx, 3 * c->dp.G);
     if (n == 0) return GIC_OK;
     if (brick_list(c, cell_begin, cell_end, s) != hipSuccess) return GIC_E_HIP;
     const double exsc = -weight / c->p.f_unit;

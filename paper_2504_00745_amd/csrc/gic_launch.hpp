@@ -133,6 +133,12 @@ struct P2GStore {
     int32_t *esc;               // [n]
     uint32_t *esc_n;            // [1] granules listed
     const int32_t *cover;       // per axis and node: (brick, node in its tile) twice, -1 for none
+    // per node row (j, k) and segment of 4 nodes along x (row-major, (n0 + 3) / 4
+    // segments a row): 1 where the grids may hold a nonzero value, i.e. a
+    // tile reached the segment at the last assembly or a listed granule was
+    // deposited there since; NULL: every node is written
+    uint8_t *live;
+    int full;  // 1: write every node (the grids hold no earlier assembly's values)
 };
 // The table P2GStore::cover for the parameters P (host; 4 (n0 + n1 + n2)
 // int32): for node i of axis a, at 4 (n0 + ... + n_{a-1} + i), the bricks
@@ -144,6 +150,9 @@ void p2g_cover_table(const DevParams &P, int32_t *out);
 // launch_p2g_assemble then writes the grids from the tiles (written, not
 // added to: alpha and mom need no clearing) and deposits the listed
 // granules.  esc_next: the escape counter of the next call, cleared here.
+// With st.live and !st.full the grids hold the previous assembly's result
+// (and its deposits): segments that no tile reaches now and that were not
+// live are zero already and are not written again.
 template <typename T>
 hipError_t launch_integrate_p2g_store(const DevParams &P, int64_t n, int64_t K, double *x, double *v,
                                       const double *r, const T *Fc, const T *Fd, const int32_t *cb,

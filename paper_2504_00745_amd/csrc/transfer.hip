@@ -364,6 +364,10 @@ __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_e
 // once, so the grids need no clearing and see no global atomics.  Nodes that
 // no occupied brick's tile holds get zero.  A workgroup takes x-rows of
 // nodes: the y and z bricks of a row are the same for all its threads.
+// With live flags (4-node segments of a row) and !full, a segment that no
+// tile holds now and that was not live holds zeros from an earlier
+// assembly and is left as it is: a bed that fills part of the box writes
+// its own region (and the region it left) instead of the whole grids.
 // (Giving each XCD a contiguous eighth of the rows, so that the rows reading
 // one tile share an L2, was slower: a bed fills part of the box, so most
 // tile reads then fell to a few XCDs.)
@@ -373,7 +377,8 @@ __global__ void __launch_bounds__(256) k_p2g_assemble(DevParams P, const unsigne
                                                       const int32_t *__restrict__ slot_of,
                                                       const int32_t *__restrict__ cover,
                                                       unsigned long long *__restrict__ alpha,
-                                                      unsigned long long *__restrict__ mom)
+                                                      unsigned long long *__restrict__ mom,
+                                                      uint8_t *__restrict__ live, int full)
 {
     extern __shared__ int32_t s_slot[];  // [kAsmRows][4][nb0]: slots of each row's (z, y) brick pairs along x
     __shared__ int32_t s_any[kAsmRows];
@@ -409,9 +414,11 @@ __global__ void __launch_bounds__(256) k_p2g_assemble(DevParams P, const unsigne
             const int32_t lz[2] = {cz[4 * k + 1], cz[4 * k + 3]};
             const int occupied = s_any[wave];
             const int32_t *rs = s_slot + wave * 4 * nbx;
+            uint8_t *lrow = live ? live + row * ((P.n[0] + 3) >> 2) : nullptr;
 #pragma unroll 2
             for (int32_t i = lane; i < P.n[0]; i += 64) {
                 unsigned long long s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+                bool has = false;  // a tile holds the node
                 if (occupied) {
                     const int32_t bx[2] = {cx[4 * i], cx[4 * i + 2]}, lx[2] = {cx[4 * i + 1], cx[4 * i + 3]};
                     for (int p = 0; p < 4; ++p) {
@@ -420,6 +427,7 @@ __global__ void __launch_bounds__(256) k_p2g_assemble(DevParams P, const unsigne
                             if (bx[ix] < 0) continue;
                             const int32_t sl = rs[p * nbx + bx[ix]];
                             if (sl < 0) continue;
+                            has = true;
                             const unsigned long long *t = tiles + (int64_t)sl * (4 * E3) + off_yz + lx[ix];
                             s0 += t[0];
                             s1 += t[E3];
@@ -428,11 +436,23 @@ __global__ void __launch_bounds__(256) k_p2g_assemble(DevParams P, const unsigne
                         }
                     }
                 }
-                const int64_t idx = row * P.n[0] + i;
-                alpha[idx] = s0;
-                mom[idx] = s1;
-                mom[G + idx] = s2;
-                mom[2 * G + idx] = s3;
+                bool put = true;
+                if (lrow) {
+                    // segment i / 4 (lanes 4 (lane / 4) .. + 3 of this round):
+                    // written when a tile holds one of its nodes now or when
+                    // it was live; its flag becomes the former
+                    const bool now = ((__ballot(has) >> (lane & ~3)) & 0xFull) != 0ull;
+                    const uint8_t was = lrow[i >> 2];
+                    put = full || now || was != 0;
+                    if ((lane & 3) == 0 && was != (uint8_t)now) lrow[i >> 2] = (uint8_t)now;
+                }
+                if (put) {
+                    const int64_t idx = row * P.n[0] + i;
+                    alpha[idx] = s0;
+                    mom[idx] = s1;
+                    mom[G + idx] = s2;
+                    mom[2 * G + idx] = s3;
+                }
             }
         }
         __syncthreads();  // s_slot and s_any are rewritten by the next pass
@@ -449,7 +469,8 @@ __global__ void __launch_bounds__(256) k_p2g_escapes(DevParams P, int64_t n, con
                                                      const double *__restrict__ x, const double *__restrict__ v,
                                                      const double *__restrict__ r,
                                                      unsigned long long *__restrict__ alpha,
-                                                     unsigned long long *__restrict__ mom, int64_t *err)
+                                                     unsigned long long *__restrict__ mom,
+                                                     uint8_t *__restrict__ live, int64_t *err)
 {
 #pragma clang fp contract(off)
     if (blockIdx.x == 0 && threadIdx.x == 0) *next_n = 0u;
@@ -485,6 +506,14 @@ __global__ void __launch_bounds__(256) k_p2g_escapes(DevParams P, int64_t n, con
             const double sum = ((S[0] + S[1]) + S[2]) + S[3];
             raise_error(err, isfinite(sum) ? kErrRange : kErrNonFinite, q);
             continue;
+        }
+        if (live) {  // the segments of the stencil's nodes are live from now on
+            const int64_t nseg = (P.n[0] + 3) >> 2;
+            for (int cz = 0; cz < 3; ++cz)
+                for (int cy = 0; cy < 3; ++cy) {
+                    uint8_t *lr = live + ((int64_t)nd[2][cz] * P.n[1] + nd[1][cy]) * nseg;
+                    for (int cx = 0; cx < 3; ++cx) lr[nd[0][cx] >> 2] = 1;
+                }
         }
         for (int c = 0; c < 4; ++c) {
             unsigned long long *g = c == 0 ? alpha : mom + (int64_t)(c - 1) * P.G;
@@ -811,8 +840,8 @@ hipError_t launch_p2g_assemble(const DevParams &P, int64_t n, const double *x, c
     const int64_t passes = ((int64_t)P.n[1] * P.n[2] + kAsmRows - 1) / kAsmRows;
     k_p2g_assemble<<<(unsigned)(passes < 16384 ? passes : 16384), 256, sizeof(int32_t) * kAsmRows * 4 * P.nb[0],
                      s>>>(
-        P, st.tiles, B.slot_of, st.cover, A, M);
-    k_p2g_escapes<<<256, 256, 0, s>>>(P, n, st.esc, st.esc_n, esc_next, x, v, r, A, M, err);
+        P, st.tiles, B.slot_of, st.cover, A, M, st.live, st.live ? st.full : 1);
+    k_p2g_escapes<<<256, 256, 0, s>>>(P, n, st.esc, st.esc_n, esc_next, x, v, r, A, M, st.live, err);
     return hipGetLastError();
 }
 
