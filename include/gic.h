@@ -36,9 +36,11 @@
  * Conventions
  *   Memory.   Every array argument is a DEVICE pointer owned by the caller.
  *             The library never frees or keeps it beyond the work the call
- *             enqueues.  The context owns only its scratch (sort buffers,
- *             error word), allocated by gic_create for n_max granules; no
- *             stage call allocates.
+ *             enqueues (gic_step and gic_sand_step remember the addresses of
+ *             the grids their last call wrote, only to compare them with the
+ *             next call's).  The context owns only its scratch (sort
+ *             buffers, tiles, error word), allocated by gic_create for n_max
+ *             granules; no stage call allocates.
  *   Streams.  `stream` is a hipStream_t passed as void* (NULL = the null
  *             stream).  Stage calls only enqueue work on it and never
  *             synchronise; gic_get_error and gic_destroy do.
