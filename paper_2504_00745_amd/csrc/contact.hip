@@ -462,7 +462,8 @@ k_contact_lds(DevParams P, int64_t n, const int32_t *__restrict__ bl,
                                                      const double *__restrict__ r, const int32_t *__restrict__ cb,
                                                      const int32_t *__restrict__ ce, const T *__restrict__ sr,
                                                      const double *__restrict__ held, T *__restrict__ F,
-                                                     int32_t *__restrict__ ncont, int64_t *err)
+                                                     int32_t *__restrict__ ncont, int64_t *err,
+                                                     int32_t *__restrict__ hmax, int32_t *__restrict__ hclr)
 {
     extern __shared__ float4 smem4[];
     float4 *spos = smem4;                                        // [cap + kCand] (p, Q), see above
@@ -473,6 +474,7 @@ k_contact_lds(DevParams P, int64_t n, const int32_t *__restrict__ bl,
     int32_t *s_wave = cgb + kHaloCells;                                    // [4]
     uint8_t *scell = reinterpret_cast<uint8_t *>(s_wave + 4);              // [cap] shell cell of each slot
     const int tid = threadIdx.x;
+    if (hclr && blockIdx.x == 0 && tid == 0) *hclr = 0;  // the next call's record
     const int64_t b = brick_of_block(bl, bcnt);
     if (b < 0) return;
     const int32_t bc[3] = {(int32_t)(b % P.nb[0]), (int32_t)((b / P.nb[0]) % P.nb[1]),
@@ -516,6 +518,9 @@ k_contact_lds(DevParams P, int64_t n, const int32_t *__restrict__ bl,
         }
     }
     const int32_t H = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+    // the largest shell so far (an atomic only when this one is larger)
+    if (hmax && tid == 0 && H > __hip_atomic_load(hmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        atomicMax(hmax, H);
     if (H > cap) {  // shell too large for LDS: global candidate path for this brick
         __syncthreads();  // every thread has read s_wave
         int32_t *glist = reinterpret_cast<int32_t *>(smem4);  // the slot arrays are unused on this path
@@ -1029,31 +1034,53 @@ static size_t contact_lds_bytes(int cap)
     return b > fallback ? b : fallback;
 }
 
+// Shell slots held in LDS: at most 1,948 (40,908 bytes, four workgroups per
+// CU); with a record of the largest shell met, an eighth and 64 slots more
+// than it, in steps of 64 (a sparser bed: smaller workgroups, more of them
+// per CU; c5's shells took the kernel from 2.96 to about 1.7 ms).
+constexpr int kShellCapMax = 1948;
+
+static int shell_cap(const ShellSize *ss)
+{
+    if (!ss || !ss->host) return kShellCapMax;
+    const int32_t seen = *(volatile const int32_t *)ss->host;  // an earlier call's record, or 0
+    if (seen <= 0) return kShellCapMax;
+    const int64_t want = ((int64_t)seen + seen / 8 + 64 + 63) / 64 * 64;
+    return want < kShellCapMax ? (int)want : kShellCapMax;
+}
+
 template <typename T>
 hipError_t launch_contact(const DevParams &P, int64_t n, const double *x, const double *v, const double *r,
                           const int32_t *cb, const int32_t *ce, const BrickList &B, const T *sr, const double *held,
-                          T *F, int32_t *ncont, int64_t *err, hipStream_t s)
+                          T *F, int32_t *ncont, int64_t *err, hipStream_t s, ShellSize *ss)
 {
     if (n == 0) return hipSuccess;
     const int64_t nbricks = (int64_t)P.nb[0] * P.nb[1] * P.nb[2];
-    const int cap = 1948;  // shell slots held in LDS: 40,908 bytes, four workgroups per CU
+    const int cap = shell_cap(ss);
+    int32_t *hm = ss ? ss->dev + ss->par : nullptr;
+    int32_t *hc = ss ? ss->dev + (ss->par ^ 1) : nullptr;
     if (sr)
         k_contact_lds<T, true><<<brick_grid(nbricks), 256, contact_lds_bytes(cap), s>>>(
-            P, n, B.list, B.count, cap, x, v, r, cb, ce, sr, held, F, ncont, err);
+            P, n, B.list, B.count, cap, x, v, r, cb, ce, sr, held, F, ncont, err, hm, hc);
     else
         k_contact_lds<T, false><<<brick_grid(nbricks), 256, contact_lds_bytes(cap), s>>>(
-            P, n, B.list, B.count, cap, x, v, r, cb, ce, nullptr, nullptr, F, ncont, err);
-    return hipGetLastError();
+            P, n, B.list, B.count, cap, x, v, r, cb, ce, nullptr, nullptr, F, ncont, err, hm, hc);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && ss && ss->host) {
+        e = hipMemcpyAsync(ss->host, hm, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        ss->par ^= 1;
+    }
+    return e;
 }
 
 template hipError_t launch_contact<float>(const DevParams &, int64_t, const double *, const double *,
                                           const double *, const int32_t *, const int32_t *, const BrickList &,
                                           const float *, const double *, float *, int32_t *, int64_t *,
-                                          hipStream_t);
+                                          hipStream_t, ShellSize *);
 template hipError_t launch_contact<double>(const DevParams &, int64_t, const double *, const double *,
                                            const double *, const int32_t *, const int32_t *, const BrickList &,
                                            const double *, const double *, double *, int32_t *, int64_t *,
-                                           hipStream_t);
+                                           hipStream_t, ShellSize *);
 
 // LDS bytes of the neighbour-list build for a shell capacity of cap granules.
 static size_t nbr_lds_bytes(int cap)

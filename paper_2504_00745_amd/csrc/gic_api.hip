@@ -36,6 +36,9 @@ struct gic_ctx {
     // assembly, and no call on the context has written to them since.
     bool live_ok;
     const int64_t *live_a, *live_m;
+    // the largest brick shell of the direct contact kernel, for the size of
+    // its shell array (device record and its pinned host copy)
+    ShellSize shell;
     // The list holds the stepping path's state when nl_n == n and the state
     // to step is the array that the last step wrote (nl_x): its sorted
     // order is the one of the list's last build or check.
@@ -405,6 +408,10 @@ gic_status gic_create(const gic_params *p, int64_t n_max, gic_ctx **out)
     ok &= hipMalloc(&c->p2gs.esc, sizeof(int32_t) * nn) == hipSuccess;
     ok &= hipMalloc(&c->esc_n2, sizeof(uint32_t) * 2) == hipSuccess;
     if (ok) ok = hipMemset(c->esc_n2, 0, sizeof(uint32_t) * 2) == hipSuccess;
+    ok &= hipMalloc(&c->shell.dev, sizeof(int32_t) * 2) == hipSuccess;
+    if (ok) ok = hipMemset(c->shell.dev, 0, sizeof(int32_t) * 2) == hipSuccess;
+    ok &= hipHostMalloc(&c->shell.host, sizeof(int32_t), hipHostMallocDefault) == hipSuccess;
+    if (ok) *c->shell.host = 0;  // no record yet: the largest shell array
     if (ok && tiles_assemble(p)) {
         // one 4-channel node tile per occupied brick (at most min(bricks, n));
         // beyond 8 GiB the stepping path keeps the cleared grids and atomics
@@ -496,6 +503,8 @@ gic_status gic_destroy(gic_ctx *c)
     (void)hipFree(const_cast<int32_t *>(c->p2gs.cover));
     (void)hipFree(c->p2gs.live);
     (void)hipFree(c->esc_n2);
+    (void)hipFree(c->shell.dev);
+    (void)hipHostFree(c->shell.host);
     if (c->tm_ev) {
         for (int i = 0; i < c->tm_cap * kStageEvents; ++i) (void)hipEventDestroy(c->tm_ev[i]);
         delete[] c->tm_ev;
@@ -589,9 +598,9 @@ static gic_status contact_impl(gic_ctx *c, int64_t n, const double *x, const dou
         // straight from the cells (same partner order, same bits)
         if (fp32(c))
             return hip_status(launch_contact<float>(c->dp, n, x, v, r, cell_begin, cell_end, c->bricks, nullptr,
-                                                    nullptr, (float *)f_contact, n_contacts, c->err, s));
+                                                    nullptr, (float *)f_contact, n_contacts, c->err, s, &c->shell));
         return hip_status(launch_contact<double>(c->dp, n, x, v, r, cell_begin, cell_end, c->bricks, nullptr,
-                                                 nullptr, (double *)f_contact, n_contacts, c->err, s));
+                                                 nullptr, (double *)f_contact, n_contacts, c->err, s, &c->shell));
     }
     if (launch_nbr_build(c->dp, n, x, r, cell_begin, cell_end, c->bricks, c->nl, force, c->err, s) != hipSuccess)
         return GIC_E_HIP;
@@ -629,9 +638,10 @@ gic_status gic_contact_capillary_forces(gic_ctx *c, int64_t n, const double *x, 
     if (fp32(c))
         return hip_status(launch_contact<float>(c->dp, n, x, v, r, cell_begin, cell_end, c->bricks,
                                                 (const float *)sr, held, (float *)f_contact, n_contacts, c->err,
-                                                s));
+                                                s, &c->shell));
     return hip_status(launch_contact<double>(c->dp, n, x, v, r, cell_begin, cell_end, c->bricks,
-                                             (const double *)sr, held, (double *)f_contact, n_contacts, c->err, s));
+                                             (const double *)sr, held, (double *)f_contact, n_contacts, c->err, s,
+                                             &c->shell));
 }
 
 gic_status gic_moisture_ratio(gic_ctx *c, int64_t n, const double *held, const void *alpha_f, void *sr,

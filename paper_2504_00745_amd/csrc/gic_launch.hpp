@@ -97,10 +97,22 @@ hipError_t launch_sort_cells(const DevParams &P, int64_t n, const double *x, uin
 hipError_t launch_reorder(int64_t n, const int32_t *order, const double *x, const double *v, const double *r,
                           const int32_t *id, double *xo, double *vo, double *ro, int32_t *ido, hipStream_t s);
 
+// The largest brick shell (granule slots, pads included) that the direct
+// contact kernel met: dev[2] (device, alternating between calls: one call
+// records into dev[par] and clears dev[par ^ 1]), host (pinned: a copy of
+// the last recorded value, read by a later call without waiting; 0 until the
+// first copy lands).  The kernel's shell array is sized from it; a shell
+// beyond the size takes the global candidate path (same bits, slower), and
+// the calls after size for it.
+struct ShellSize {
+    int32_t *dev;
+    int32_t *host;
+    int par;
+};
 template <typename T>
 hipError_t launch_contact(const DevParams &P, int64_t n, const double *x, const double *v, const double *r,
                           const int32_t *cb, const int32_t *ce, const BrickList &B, const T *sr, const double *held,
-                          T *F, int32_t *ncont, int64_t *err, hipStream_t s);
+                          T *F, int32_t *ncont, int64_t *err, hipStream_t s, ShellSize *ss = nullptr);
 // Neighbour-list build (only when force is set or the sort asked for it)
 // and the contact forces from the list (Sec. 3.1, Eq. 1a-1c, walls).
 // pairs (optional, pair_cap x n, column-major): the partners that touch, in

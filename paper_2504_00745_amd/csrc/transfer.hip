@@ -415,7 +415,6 @@ __global__ void __launch_bounds__(256) k_p2g_assemble(DevParams P, const unsigne
             const int occupied = s_any[wave];
             const int32_t *rs = s_slot + wave * 4 * nbx;
             uint8_t *lrow = live ? live + row * ((P.n[0] + 3) >> 2) : nullptr;
-#pragma unroll 2
             for (int32_t i = lane; i < P.n[0]; i += 64) {
                 unsigned long long s0 = 0, s1 = 0, s2 = 0, s3 = 0;
                 bool has = false;  // a tile holds the node

@@ -494,3 +494,65 @@ def test_stage_times_cover_the_step(G):
     assert ms["exchange"] / k < 0.010 and ms["grid_clear"] / k < 0.010  # ms per step
     assert sum(ms.values()) <= 1.05 * e0.elapsed_time(e1)
     assert sim.ctx.error() == (0, -1)
+
+
+def _contact_direct(gic, ctx, x, v, r):
+    """Sort, reorder and the direct contact kernel (no pair output) on ctx;
+    forces and counts in input order."""
+    import torch
+    n = x.shape[1]
+    X, V, R = G_dev(x.reshape(-1)), G_dev(v.reshape(-1)), G_dev(r)
+    ID = torch.arange(n, dtype=torch.int32, device="cuda")
+    key = torch.empty(n, dtype=torch.int32, device="cuda")
+    order = torch.empty(n, dtype=torch.int32, device="cuda")
+    cb = torch.empty(ctx.K, dtype=torch.int32, device="cuda")
+    ce = torch.empty(ctx.K, dtype=torch.int32, device="cuda")
+    gic.gic_sort_cells(ctx, X.view(3, n), key, order, cb, ce)
+    Xs, Vs, Rs, IDs = torch.empty_like(X), torch.empty_like(V), torch.empty_like(R), torch.empty_like(ID)
+    gic.gic_reorder(ctx, order, X.view(3, n), V, R, ID, Xs, Vs, Rs, IDs)
+    F = torch.empty(3 * n, dtype=ctx.real, device="cuda")
+    nc = torch.empty(n, dtype=torch.int32, device="cuda")
+    gic.gic_contact_forces(ctx, Xs.view(3, n), Vs, Rs, cb, ce, F, nc)
+    torch.cuda.synchronize()  # (the context's record of the largest shell has landed too)
+    ids = IDs.cpu().numpy()
+    Fi = np.empty((3, n))
+    Fi[:, ids] = F.view(3, n).cpu().numpy()
+    nci = np.empty(n, dtype=np.int32)
+    nci[ids] = nc.cpu().numpy()
+    return Fi, nci
+
+
+def G_dev(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a)).to("cuda", torch.float64).contiguous()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_contact_shell_array_sized_from_earlier_calls(G, prec):
+    """The direct contact kernel sizes its LDS shell array from the largest
+    brick shell an earlier call on the context met.  After calls on a sparse
+    bed (a small array), a bed with one dense brick (its shell beyond that
+    array, within the largest) takes the global candidate path for that
+    brick and gives the bits of a fresh context (largest array, LDS path);
+    the call after sizes for it and gives them again."""
+    from paper_2504_00745_amd import gic
+    G.say(f"[contact shell size] {prec}")
+    d = wl.make("c2", n_override=20000)
+    cfg = d["params"]
+    rng = np.random.Generator(np.random.PCG64(33))
+    # 700 small granules in a 0.04 m cube inside one 0.08 m brick (cell 0.02)
+    xs = rng.uniform(0.42, 0.46, (3, 700))
+    x = np.concatenate([d["x"], xs], 1)
+    r = np.concatenate([d["r"], np.full(700, 0.0018)])
+    v = np.concatenate([d["v"], rng.normal(0, 0.05, (3, 700))], 1)
+    rm = float(d["r"].max())
+    ctx = gic.Context(cfg, x.shape[1], prec, rm)
+    for _ in range(3):  # the sparse bed: the record settles on its shells
+        _contact_direct(gic, ctx, d["x"], d["v"], d["r"])
+    ref = _contact_direct(gic, gic.Context(cfg, x.shape[1], prec, rm), x, v, r)
+    for k in range(2):
+        F, nc = _contact_direct(gic, ctx, x, v, r)
+        assert np.array_equal(F, ref[0]), k
+        assert np.array_equal(nc, ref[1]), k
+    assert ref[1][-700:].sum() > 700  # the dense brick's granules touch
+    assert ctx.error() == (0, -1)
