@@ -1037,7 +1037,7 @@ static size_t contact_lds_bytes(int cap)
 // Shell slots held in LDS: at most 1,948 (40,908 bytes, four workgroups per
 // CU); with a record of the largest shell met, an eighth and 64 slots more
 // than it, in steps of 64 (a sparser bed: smaller workgroups, more of them
-// per CU; c5's shells took the kernel from 2.96 to about 1.7 ms).
+// per CU; the shells of the c5 bed took the kernel from 2.96 to 1.61 ms).
 constexpr int kShellCapMax = 1948;
 
 static int shell_cap(const ShellSize *ss)
