@@ -474,7 +474,7 @@ k_contact_lds(DevParams P, int64_t n, const int32_t *__restrict__ bl,
     int32_t *s_wave = cgb + kHaloCells;                                    // [4]
     uint8_t *scell = reinterpret_cast<uint8_t *>(s_wave + 4);              // [cap] shell cell of each slot
     const int tid = threadIdx.x;
-    if (hclr && blockIdx.x == 0 && tid == 0) *hclr = 0;  // the next call's record
+    if (hclr && blockIdx.x == 0 && tid == 0) *hclr = 0;  // the next recording call's record
     const int64_t b = brick_of_block(bl, bcnt);
     if (b < 0) return;
     const int32_t bc[3] = {(int32_t)(b % P.nb[0]), (int32_t)((b / P.nb[0]) % P.nb[1]),
@@ -518,7 +518,7 @@ k_contact_lds(DevParams P, int64_t n, const int32_t *__restrict__ bl,
         }
     }
     const int32_t H = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
-    // the largest shell so far (an atomic only when this one is larger)
+    // the largest shell (an atomic only when this one is larger than the record)
     if (hmax && tid == 0 && H > __hip_atomic_load(hmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
         atomicMax(hmax, H);
     if (H > cap) {  // shell too large for LDS: global candidate path for this brick
@@ -1040,10 +1040,10 @@ static size_t contact_lds_bytes(int cap)
 // per CU; the shells of the c5 bed took the kernel from 2.96 to 1.61 ms).
 constexpr int kShellCapMax = 1948;
 
-static int shell_cap(const ShellSize *ss)
+static int shell_cap(const SizeRecord *ss)
 {
-    if (!ss || !ss->host) return kShellCapMax;
-    const int32_t seen = *(volatile const int32_t *)ss->host;  // an earlier call's record, or 0
+    // an earlier call's record (the largest shell, in the first word), or 0
+    const int32_t seen = ss && ss->host ? *(volatile const int32_t *)ss->host : 0;
     if (seen <= 0) return kShellCapMax;
     const int64_t want = ((int64_t)seen + seen / 8 + 64 + 63) / 64 * 64;
     return want < kShellCapMax ? (int)want : kShellCapMax;
@@ -1052,13 +1052,14 @@ static int shell_cap(const ShellSize *ss)
 template <typename T>
 hipError_t launch_contact(const DevParams &P, int64_t n, const double *x, const double *v, const double *r,
                           const int32_t *cb, const int32_t *ce, const BrickList &B, const T *sr, const double *held,
-                          T *F, int32_t *ncont, int64_t *err, hipStream_t s, ShellSize *ss)
+                          T *F, int32_t *ncont, int64_t *err, hipStream_t s, SizeRecord *ss)
 {
     if (n == 0) return hipSuccess;
     const int64_t nbricks = (int64_t)P.nb[0] * P.nb[1] * P.nb[2];
     const int cap = shell_cap(ss);
-    int32_t *hm = ss ? ss->dev + ss->par : nullptr;
-    int32_t *hc = ss ? ss->dev + (ss->par ^ 1) : nullptr;
+    const bool copy = record_copy(ss);  // only these calls record (the stores contend)
+    int32_t *hm = copy ? ss->dev + ss->par * kRecSlots : nullptr;
+    int32_t *hc = copy ? ss->dev + (ss->par ^ 1) * kRecSlots : nullptr;
     if (sr)
         k_contact_lds<T, true><<<brick_grid(nbricks), 256, contact_lds_bytes(cap), s>>>(
             P, n, B.list, B.count, cap, x, v, r, cb, ce, sr, held, F, ncont, err, hm, hc);
@@ -1066,9 +1067,9 @@ hipError_t launch_contact(const DevParams &P, int64_t n, const double *x, const 
         k_contact_lds<T, false><<<brick_grid(nbricks), 256, contact_lds_bytes(cap), s>>>(
             P, n, B.list, B.count, cap, x, v, r, cb, ce, nullptr, nullptr, F, ncont, err, hm, hc);
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess && ss && ss->host) {
-        e = hipMemcpyAsync(ss->host, hm, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (copy) {
         ss->par ^= 1;
+        if (e == hipSuccess) e = hipMemcpyAsync(ss->host, hm, sizeof(int32_t), hipMemcpyDeviceToHost, s);
     }
     return e;
 }
@@ -1076,11 +1077,11 @@ hipError_t launch_contact(const DevParams &P, int64_t n, const double *x, const 
 template hipError_t launch_contact<float>(const DevParams &, int64_t, const double *, const double *,
                                           const double *, const int32_t *, const int32_t *, const BrickList &,
                                           const float *, const double *, float *, int32_t *, int64_t *,
-                                          hipStream_t, ShellSize *);
+                                          hipStream_t, SizeRecord *);
 template hipError_t launch_contact<double>(const DevParams &, int64_t, const double *, const double *,
                                            const double *, const int32_t *, const int32_t *, const BrickList &,
                                            const double *, const double *, double *, int32_t *, int64_t *,
-                                           hipStream_t, ShellSize *);
+                                           hipStream_t, SizeRecord *);
 
 // LDS bytes of the neighbour-list build for a shell capacity of cap granules.
 static size_t nbr_lds_bytes(int cap)

@@ -37,8 +37,9 @@ struct gic_ctx {
     bool live_ok;
     const int64_t *live_a, *live_m;
     // the largest brick shell of the direct contact kernel, for the size of
-    // its shell array (device record and its pinned host copy)
-    ShellSize shell;
+    // its shell array, and the most granules in a brick of the P2G tile
+    // kernel, for its workgroup size (device records, pinned host copies)
+    SizeRecord shell, brick_n;
     // The list holds the stepping path's state when nl_n == n and the state
     // to step is the array that the last step wrote (nl_x): its sorted
     // order is the one of the list's last build or check.
@@ -408,10 +409,16 @@ gic_status gic_create(const gic_params *p, int64_t n_max, gic_ctx **out)
     ok &= hipMalloc(&c->p2gs.esc, sizeof(int32_t) * nn) == hipSuccess;
     ok &= hipMalloc(&c->esc_n2, sizeof(uint32_t) * 2) == hipSuccess;
     if (ok) ok = hipMemset(c->esc_n2, 0, sizeof(uint32_t) * 2) == hipSuccess;
-    ok &= hipMalloc(&c->shell.dev, sizeof(int32_t) * 2) == hipSuccess;
-    if (ok) ok = hipMemset(c->shell.dev, 0, sizeof(int32_t) * 2) == hipSuccess;
-    ok &= hipHostMalloc(&c->shell.host, sizeof(int32_t), hipHostMallocDefault) == hipSuccess;
-    if (ok) *c->shell.host = 0;  // no record yet: the largest shell array
+    ok &= hipMalloc(&c->shell.dev, sizeof(int32_t) * 2 * kRecSlots) == hipSuccess;
+    if (ok) ok = hipMemset(c->shell.dev, 0, sizeof(int32_t) * 2 * kRecSlots) == hipSuccess;
+    ok &= hipHostMalloc(&c->shell.host, sizeof(int32_t) * kRecSlots, hipHostMallocDefault) == hipSuccess;
+    if (ok)
+        for (int i = 0; i < kRecSlots; ++i) c->shell.host[i] = 0;  // no record yet: the largest shell array
+    ok &= hipMalloc(&c->brick_n.dev, sizeof(int32_t) * 2 * kRecSlots) == hipSuccess;
+    if (ok) ok = hipMemset(c->brick_n.dev, 0, sizeof(int32_t) * 2 * kRecSlots) == hipSuccess;
+    ok &= hipHostMalloc(&c->brick_n.host, sizeof(int32_t) * kRecSlots, hipHostMallocDefault) == hipSuccess;
+    if (ok)
+        for (int i = 0; i < kRecSlots; ++i) c->brick_n.host[i] = 0;  // no record yet: workgroups of 256
     if (ok && tiles_assemble(p)) {
         // one 4-channel node tile per occupied brick (at most min(bricks, n));
         // beyond 8 GiB the stepping path keeps the cleared grids and atomics
@@ -505,6 +512,8 @@ gic_status gic_destroy(gic_ctx *c)
     (void)hipFree(c->esc_n2);
     (void)hipFree(c->shell.dev);
     (void)hipHostFree(c->shell.host);
+    (void)hipFree(c->brick_n.dev);
+    (void)hipHostFree(c->brick_n.host);
     if (c->tm_ev) {
         for (int i = 0; i < c->tm_cap * kStageEvents; ++i) (void)hipEventDestroy(c->tm_ev[i]);
         delete[] c->tm_ev;
@@ -836,11 +845,12 @@ static gic_status step_integrate_p2g(gic_ctx *c, int64_t n, double *x, double *v
     hipError_t e;
     if (fp32(c))
         e = launch_integrate_p2g_store<float>(c->dp, n, c->K, x, v, r, (const float *)f_contact,
-                                              (const float *)f_force, cell_begin, cell_end, c->bricks, c->err, s, st);
+                                              (const float *)f_force, cell_begin, cell_end, c->bricks, c->err, s, st,
+                                              &c->brick_n);
     else
         e = launch_integrate_p2g_store<double>(c->dp, n, c->K, x, v, r, (const double *)f_contact,
                                                (const double *)f_force, cell_begin, cell_end, c->bricks, c->err, s,
-                                               st);
+                                               st, &c->brick_n);
     if (e != hipSuccess) return hip_status(e);
     stage_mark(c, 6, s);
     e = launch_p2g_assemble(c->dp, n, x, v, r, c->bricks, alpha_fx, mom_fx, c->err, s, st, next);

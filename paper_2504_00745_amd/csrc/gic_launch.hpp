@@ -97,22 +97,50 @@ hipError_t launch_sort_cells(const DevParams &P, int64_t n, const double *x, uin
 hipError_t launch_reorder(int64_t n, const int32_t *order, const double *x, const double *v, const double *r,
                           const int32_t *id, double *xo, double *vo, double *ro, int32_t *ido, hipStream_t s);
 
-// The largest brick shell (granule slots, pads included) that the direct
-// contact kernel met: dev[2] (device, alternating between calls: one call
-// records into dev[par] and clears dev[par ^ 1]), host (pinned: a copy of
-// the last recorded value, read by a later call without waiting; 0 until the
-// first copy lands).  The kernel's shell array is sized from it; a shell
-// beyond the size takes the global candidate path (same bits, slower), and
-// the calls after size for it.
-struct ShellSize {
+// The largest size a brick kernel met: dev[2][kRecSlots] (device,
+// alternating between recording calls: one records into dev[par] and clears
+// dev[par ^ 1]), host[kRecSlots] (pinned: a copy of the record, read by
+// later calls without waiting; zeros until the first copy lands).  Only
+// every 16th call records and copies (a copy costs a few microseconds of
+// the stream).  The direct contact kernel keeps the largest brick shell
+// (granule slots, pads included) in the first word (an atomic maximum,
+// taken only when the word is smaller); the P2G tile kernel keeps flags of
+// the granules of its bricks by steps of 64 (a brick of v granules sets
+// flag ceil(v / 64) with a plain store).  The next launches are shaped from
+// the record; a brick beyond the shape takes a slower path with the same
+// bits, and the calls after adapt.
+constexpr int kRecSlots = 64;  // flags of sizes up to 64 (kRecSlots - 1)
+struct SizeRecord {
     int32_t *dev;
     int32_t *host;
     int par;
+    unsigned calls;
 };
+// Whether this call copies its record to the host.
+inline bool record_copy(SizeRecord *r)
+{
+    return r && r->host && (r->calls++ & 15u) == 0u;
+}
+// An upper bound (a multiple of 64) of the largest size in the last copy
+// that reached the host (0: none yet).
+inline int32_t record_seen(const SizeRecord *r)
+{
+    if (!r || !r->host) return 0;
+    int32_t m = 0;
+    for (int i = 0; i < kRecSlots; ++i)
+        if (((volatile const int32_t *)r->host)[i]) m = 64 * i;
+    return m;
+}
+// The flag of size v (the last flag for sizes beyond the table).
+__host__ __device__ inline int record_flag(int32_t v)
+{
+    const int32_t f = (v + 63) / 64;
+    return f < kRecSlots - 1 ? (f > 0 ? f : 0) : kRecSlots - 1;
+}
 template <typename T>
 hipError_t launch_contact(const DevParams &P, int64_t n, const double *x, const double *v, const double *r,
                           const int32_t *cb, const int32_t *ce, const BrickList &B, const T *sr, const double *held,
-                          T *F, int32_t *ncont, int64_t *err, hipStream_t s, ShellSize *ss = nullptr);
+                          T *F, int32_t *ncont, int64_t *err, hipStream_t s, SizeRecord *ss = nullptr);
 // Neighbour-list build (only when force is set or the sort asked for it)
 // and the contact forces from the list (Sec. 3.1, Eq. 1a-1c, walls).
 // pairs (optional, pair_cap x n, column-major): the partners that touch, in
@@ -151,6 +179,9 @@ struct P2GStore {
     // deposited there since; NULL: every node is written
     uint8_t *live;
     int full;  // 1: write every node (the grids hold no earlier assembly's values)
+    // the tile kernel's record of the most granules in a brick (max into
+    // nrec, clear nclr for the next call); NULL: none
+    int32_t *nrec, *nclr;
 };
 // The table P2GStore::cover for the parameters P (host; 4 (n0 + n1 + n2)
 // int32): for node i of axis a, at 4 (n0 + ... + n_{a-1} + i), the bricks
@@ -169,7 +200,7 @@ template <typename T>
 hipError_t launch_integrate_p2g_store(const DevParams &P, int64_t n, int64_t K, double *x, double *v,
                                       const double *r, const T *Fc, const T *Fd, const int32_t *cb,
                                       const int32_t *ce, const BrickList &B, int64_t *err, hipStream_t s,
-                                      const P2GStore &st);
+                                      const P2GStore &st, SizeRecord *rec = nullptr);
 hipError_t launch_p2g_assemble(const DevParams &P, int64_t n, const double *x, const double *v, const double *r,
                                const BrickList &B, int64_t *alpha, int64_t *mom, int64_t *err, hipStream_t s,
                                const P2GStore &st, uint32_t *esc_next);

@@ -105,8 +105,10 @@ __device__ inline void tile_add(unsigned long long *tile, unsigned long long *gl
 // WET: granules hold water (held, per unit of their volume): the move takes
 // the wet mass of Eq. 19 (and the wet volume in the virtual mass), alpha
 // receives frac (1 + held) and momentum the wet mass's (Sec. 5.3).
-template <bool MOM, typename T, bool INTEG, bool EXCH = false, bool WET = false, bool STORE = false>
-__global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_eu(4))) k_p2g_fixed(DevParams P, int64_t n, const int32_t *__restrict__ bl,
+// NT: threads per workgroup (128 serves beds whose bricks hold few granules).
+template <bool MOM, typename T, bool INTEG, bool EXCH = false, bool WET = false, bool STORE = false,
+          int NT = kP2GThreads>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_p2g_fixed(DevParams P, int64_t n, const int32_t *__restrict__ bl,
                                                            const int32_t *__restrict__ bcnt, int batch,
                                                            double *x, double *v, const double *__restrict__ r,
                                                            const T *__restrict__ Fc, const T *__restrict__ Fd,
@@ -123,13 +125,15 @@ __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_e
     constexpr int NCH = EXCH ? 3 : (MOM ? 4 : 1);
     extern __shared__ unsigned long long tile[];
     __shared__ int32_t s_range[2];
-    __shared__ int32_t s_wave[kP2GThreads / 64];
+    __shared__ int32_t s_wave[NT / 64];
     int64_t slot;
+    if (STORE && st.nclr && blockIdx.x == 0 && threadIdx.x < kRecSlots) st.nclr[threadIdx.x] = 0;  // the next call's record
     const int64_t b = brick_slot_of_block(bl, bcnt, slot);
     if (b < 0) return;
     brick_range(n, b, cb, ce, s_range);
     __syncthreads();
     const int32_t beg = s_range[0], end = s_range[1];
+    if (STORE && st.nrec && threadIdx.x == 0) st.nrec[record_flag(end - beg)] = 1;  // the brick's granules
     if (end <= beg && !STORE) return;  // (a stored tile is written even if empty)
     const int E = P.tile;
     const int E3 = E * E * E;
@@ -139,7 +143,7 @@ __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_e
     int32_t *srun = reinterpret_cast<int32_t *>(sS + NCH * bs);   // [bs] run starts
     int16_t *sbase = reinterpret_cast<int16_t *>(srun + bs);      // [3][bs] stencil base (grid edges < 2^15 nodes)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int k = tid; k < NCH * E3; k += kP2GThreads) tile[k] = 0ull;
+    for (int k = tid; k < NCH * E3; k += NT) tile[k] = 0ull;
     int32_t o[3];
     tile_origin(P, b, o);
     // grid plane of channel c (computed, not an array indexed by c, which
@@ -149,7 +153,7 @@ __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_e
     for (int64_t b0 = beg; b0 < end; b0 += batch) {
         const int m = (int)(end - b0 < batch ? end - b0 : batch);
         // ---- phase 1: per granule
-        for (int i = tid; i < m; i += kP2GThreads) {
+        for (int i = tid; i < m; i += NT) {
             const int64_t q = b0 + i;
             double xa[3] = {x[q], x[n + q], x[2 * n + q]};
             double va[3] = {0.0, 0.0, 0.0};
@@ -235,7 +239,7 @@ __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_e
         __syncthreads();
         // ---- runs of equal stencil base
         int nruns = 0;
-        for (int i0 = 0; i0 < m; i0 += kP2GThreads) {
+        for (int i0 = 0; i0 < m; i0 += NT) {
             const int i = i0 + tid;
             bool start = false;
             if (i < m) {
@@ -247,7 +251,7 @@ __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_e
             if (lane == 0) s_wave[wave] = (int32_t)__popcll(smask);
             __syncthreads();
             int off = nruns, tot = nruns;
-            for (int w = 0; w < kP2GThreads / 64; ++w) {
+            for (int w = 0; w < NT / 64; ++w) {
                 off += w < wave ? s_wave[w] : 0;
                 tot += s_wave[w];
             }
@@ -261,7 +265,7 @@ __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_e
         if (tid == 0) srun[nruns] = m;
         __syncthreads();
         // ---- phase 2: per run and channel
-        for (int task = tid; task < nruns * NCH; task += kP2GThreads) {
+        for (int task = tid; task < nruns * NCH; task += NT) {
             const int rr = task / NCH;
             const int c = task - rr * NCH;
             const int g0 = srun[rr], g1 = srun[rr + 1];
@@ -345,10 +349,10 @@ __global__ void __launch_bounds__(kP2GThreads) __attribute__((amdgpu_waves_per_e
     }
     if (STORE) {  // the whole tile, for k_p2g_assemble
         unsigned long long *dst = st.tiles + slot * (int64_t)(NCH * E3);
-        for (int k = tid; k < NCH * E3; k += kP2GThreads) dst[k] = tile[k];
+        for (int k = tid; k < NCH * E3; k += NT) dst[k] = tile[k];
         return;
     }
-    for (int k = tid; k < NCH * E3; k += kP2GThreads) {
+    for (int k = tid; k < NCH * E3; k += NT) {
         const unsigned long long val = tile[k];
         if (val == 0ull) continue;
         const int c = k / E3;
@@ -808,27 +812,45 @@ template <typename T>
 hipError_t launch_integrate_p2g_store(const DevParams &P, int64_t n, int64_t K, double *x, double *v,
                                       const double *r, const T *Fc, const T *Fd, const int32_t *cb,
                                       const int32_t *ce, const BrickList &B, int64_t *err, hipStream_t s,
-                                      const P2GStore &st)
+                                      const P2GStore &st, SizeRecord *rec)
 {
     const int64_t bricks = K / kBrickCells;
     const int E3 = P.tile * P.tile * P.tile;
     int batch = 512;
     while (batch > 64 && p2g_lds(4, E3, batch) > 49152) batch /= 2;
+    // bricks of at most 128 granules at the last record: workgroups of 128
+    // threads and batches of 128 (less LDS, twice the workgroups per CU); a
+    // denser brick loops over batches, and the calls after take 256
+    const int32_t seen = record_seen(rec);
+    const bool small = seen > 0 && seen <= 128 && batch >= 128;
+    if (small) batch = 128;
     const size_t lds = p2g_lds(4, E3, batch);
-    if (n > 0)
+    P2GStore sr = st;
+    const bool copy = n > 0 && record_copy(rec);  // only these calls record (the stores contend)
+    sr.nrec = copy ? rec->dev + rec->par * kRecSlots : nullptr;
+    sr.nclr = copy ? rec->dev + (rec->par ^ 1) * kRecSlots : nullptr;
+    if (n > 0 && small)
+        k_p2g_fixed<true, T, true, false, false, true, 128><<<brick_grid(bricks), 128, lds, s>>>(
+            P, n, B.list, B.count, batch, x, v, r, Fc, Fd, cb, ce, nullptr, nullptr, err, 0.0, nullptr, sr);
+    else if (n > 0)
         k_p2g_fixed<true, T, true, false, false, true><<<brick_grid(bricks), kP2GThreads, lds, s>>>(
-            P, n, B.list, B.count, batch, x, v, r, Fc, Fd, cb, ce, nullptr, nullptr, err, 0.0, nullptr, st);
-    return hipGetLastError();
+            P, n, B.list, B.count, batch, x, v, r, Fc, Fd, cb, ce, nullptr, nullptr, err, 0.0, nullptr, sr);
+    hipError_t e = hipGetLastError();
+    if (copy) {
+        rec->par ^= 1;
+        if (e == hipSuccess) e = hipMemcpyAsync(rec->host, sr.nrec, sizeof(int32_t) * kRecSlots, hipMemcpyDeviceToHost, s);
+    }
+    return e;
 }
 
 template hipError_t launch_integrate_p2g_store<float>(const DevParams &, int64_t, int64_t, double *, double *,
                                                       const double *, const float *, const float *,
                                                       const int32_t *, const int32_t *, const BrickList &,
-                                                      int64_t *, hipStream_t, const P2GStore &);
+                                                      int64_t *, hipStream_t, const P2GStore &, SizeRecord *);
 template hipError_t launch_integrate_p2g_store<double>(const DevParams &, int64_t, int64_t, double *, double *,
                                                        const double *, const double *, const double *,
                                                        const int32_t *, const int32_t *, const BrickList &,
-                                                       int64_t *, hipStream_t, const P2GStore &);
+                                                       int64_t *, hipStream_t, const P2GStore &, SizeRecord *);
 
 hipError_t launch_p2g_assemble(const DevParams &P, int64_t n, const double *x, const double *v, const double *r,
                                const BrickList &B, int64_t *alpha, int64_t *mom, int64_t *err, hipStream_t s,

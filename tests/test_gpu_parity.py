@@ -530,11 +530,13 @@ def G_dev(a):
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_contact_shell_array_sized_from_earlier_calls(G, prec):
     """The direct contact kernel sizes its LDS shell array from the largest
-    brick shell an earlier call on the context met.  After calls on a sparse
-    bed (a small array), a bed with one dense brick (its shell beyond that
-    array, within the largest) takes the global candidate path for that
-    brick and gives the bits of a fresh context (largest array, LDS path);
-    the call after sizes for it and gives them again."""
+    brick shell that an earlier call on the context recorded (the record of
+    every 16th call reaches the host).  After calls on a sparse bed (a small
+    array), a bed with one dense brick (its shell beyond that array, within
+    the largest) takes the global candidate path for that brick and gives
+    the bits of a fresh context (largest array, LDS path); once the dense
+    bed's record has reached the host (the 17th call on the context), the
+    calls size for it and give the same bits again."""
     from paper_2504_00745_amd import gic
     G.say(f"[contact shell size] {prec}")
     d = wl.make("c2", n_override=20000)
@@ -550,7 +552,7 @@ def test_contact_shell_array_sized_from_earlier_calls(G, prec):
     for _ in range(3):  # the sparse bed: the record settles on its shells
         _contact_direct(gic, ctx, d["x"], d["v"], d["r"])
     ref = _contact_direct(gic, gic.Context(cfg, x.shape[1], prec, rm), x, v, r)
-    for k in range(2):
+    for k in range(17):  # calls 3 .. 19 on ctx: call 16 copies the dense record
         F, nc = _contact_direct(gic, ctx, x, v, r)
         assert np.array_equal(F, ref[0]), k
         assert np.array_equal(nc, ref[1]), k
